@@ -1,0 +1,1050 @@
+// Oracle for the block-structured geometric-multigrid Poisson path.
+//
+// TEST INFRASTRUCTURE ONLY. Plain, slow, single-threaded, obviously-correct
+// CPU implementation in FP64 (plus a float emulation of the FP32 inner
+// V-cycle).  Only the test suite, the smoke check and the benchmark's
+// CPU-baseline leg may load it.  It shares no code with the HIP library.
+// Build: g++ -O2 -std=c++17 -ffp-contract=off (no FMA contraction, no
+// -march=native), so every floating-point operation below is one IEEE RNE op.
+//
+// Data model (paper Section 2): a Box is an inclusive integer index range
+// [lo, hi] in a global index space whose bounds may be negative; a FArrayBox
+// holds the data of one box grown by ng ghost cells in Fortran order (x
+// fastest); a MultiFab is the collection of FArrayBoxes over a BoxArray.
+// Ghost cells covered by the valid region of some box (after a periodic shift)
+// are filled by FillBoundary (Section 2: ghost cell exchange).
+//
+// The paper names the solver family only ("linear solvers for cell-centered
+// data", Section 2).  The multigrid steps below are the textbook cell-centred
+// V-cycle; every point the paper leaves open is a documented reading:
+//   operator   : div(beta grad u) = f, 7-point, cubic cells of width h
+//   Dirichlet  : homogeneous, ghost = -(mirror cell), one sign per outside dim
+//   smoother   : red-black Gauss-Seidel, red = (i+j+k) even (global indices),
+//                ghosts refreshed before every colour
+//   restriction: average of the 8 children
+//   prolongation: trilinear cell-centred (27/9/3/1 over 64) or piecewise const
+//   coarsening : by 2 while every domain edge is even and >= 4; boxes are
+//                coarsened one by one while every box edge is even and >= 4
+//                and its lower corner even, else the coarse level is one box
+//   bottom     : FP64 conjugate gradients, rel. L2 residual 1e-12,
+//                at most 4*cells iterations; periodic: mean-zero projection
+//   stop test  : ||f - L u||_inf <= rel_tol * ||f||_inf (or <= abs_tol)
+//   var coef   : fine faces = harmonic mean of the two cells (beta ghosts by
+//                even reflection at Dirichlet faces, wrap at periodic ones);
+//                coarse face = mean of the 4 fine faces it covers
+//   mixed      : FP64 iterative refinement around one FP32 V(nu1,nu2) from zero
+//                per outer step, FP64 bottom inside it.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+namespace orc {
+
+struct Box {
+    int lo[3], hi[3];
+    int n(int d) const { return hi[d] - lo[d] + 1; }
+    long cells() const { return (long)n(0) * n(1) * n(2); }
+    bool has(int i, int j, int k) const {
+        return i >= lo[0] && i <= hi[0] && j >= lo[1] && j <= hi[1] && k >= lo[2] && k <= hi[2];
+    }
+};
+
+static int fdiv2(int a) { return (a >= 0) ? a / 2 : -((1 - a) / 2); }  // floor(a/2)
+static int pmod(int a, int n) { int r = a % n; return r < 0 ? r + n : r; }
+static int parity(int i, int j, int k) { return (i + j + k) & 1; }
+
+struct Geom {
+    Box dom;
+    int per[3];
+    double h;  // cell width (cubic cells)
+    bool all_periodic() const { return per[0] && per[1] && per[2]; }
+};
+
+// One FArrayBox: box grown by ng, F-order.
+template <class T>
+struct Fab {
+    Box bx;
+    int ng;
+    int sy, sz;
+    std::vector<T> v;
+    void define(const Box& b, int g) {
+        bx = b; ng = g;
+        sy = b.n(0) + 2 * g;
+        sz = sy * (b.n(1) + 2 * g);
+        v.assign((size_t)sz * (b.n(2) + 2 * g), T(0));
+    }
+    size_t idx(int i, int j, int k) const {
+        return (size_t)(i - bx.lo[0] + ng) + (size_t)(j - bx.lo[1] + ng) * sy + (size_t)(k - bx.lo[2] + ng) * sz;
+    }
+    T& operator()(int i, int j, int k) { return v[idx(i, j, k)]; }
+    T operator()(int i, int j, int k) const { return v[idx(i, j, k)]; }
+    bool in_grown(int i, int j, int k) const {
+        return i >= bx.lo[0] - ng && i <= bx.hi[0] + ng && j >= bx.lo[1] - ng && j <= bx.hi[1] + ng &&
+               k >= bx.lo[2] - ng && k <= bx.hi[2] + ng;
+    }
+};
+
+template <class T>
+struct MF {
+    std::vector<Fab<T>> f;
+    void define(const std::vector<Box>& bs, int ng) {
+        f.resize(bs.size());
+        for (size_t b = 0; b < bs.size(); ++b) f[b].define(bs[b], ng);
+    }
+    void zero() { for (auto& fb : f) std::fill(fb.v.begin(), fb.v.end(), T(0)); }
+};
+
+// Face coefficients of one level, global arrays: bx over faces i in [lo, hi+1]
+// (face i sits between cells i-1 and i), likewise by, bz.
+template <class T>
+struct FacesT {
+    Box dom;
+    std::vector<T> c[3];
+    size_t idx(int d, int i, int j, int k) const {
+        int nx = dom.n(0) + (d == 0), ny = dom.n(1) + (d == 1);
+        return (size_t)(i - dom.lo[0]) + (size_t)nx * ((size_t)(j - dom.lo[1]) + (size_t)ny * (k - dom.lo[2]));
+    }
+    T at(int d, int i, int j, int k) const { return c[d][idx(d, i, j, k)]; }
+};
+using Faces = FacesT<double>;
+
+// ---------------------------------------------------------------- BoxArray
+// Chop a domain edge of length n into pieces: blocking factor bf = largest
+// power of two dividing n, capped at max_box; pieces of floor(max_box/bf)*bf
+// and one remainder (a multiple of bf).
+static std::vector<std::pair<int, int>> chop1(int lo, int n, int max_box) {
+    int bf = 1;
+    while (n % (bf * 2) == 0 && bf * 2 <= max_box) bf *= 2;
+    int piece = (max_box / bf) * bf;
+    std::vector<std::pair<int, int>> out;
+    int s = 0;
+    while (s < n) {
+        int len = std::min(piece, n - s);
+        out.push_back({lo + s, lo + s + len - 1});
+        s += len;
+    }
+    return out;
+}
+
+static std::vector<Box> chop(const Box& dom, int max_box) {
+    std::vector<std::pair<int, int>> p[3];
+    for (int d = 0; d < 3; ++d) p[d] = chop1(dom.lo[d], dom.n(d), max_box);
+    std::vector<Box> out;
+    for (auto& z : p[2])
+        for (auto& y : p[1])
+            for (auto& x : p[0]) out.push_back(Box{{x.first, y.first, z.first}, {x.second, y.second, z.second}});
+    return out;
+}
+
+static Box coarsen(const Box& b) {
+    Box c;
+    for (int d = 0; d < 3; ++d) { c.lo[d] = fdiv2(b.lo[d]); c.hi[d] = fdiv2(b.hi[d]); }
+    return c;
+}
+
+static bool can_coarsen_domain(const Box& dom) {
+    for (int d = 0; d < 3; ++d)
+        if (dom.n(d) % 2 != 0 || dom.n(d) < 4 || (dom.lo[d] & 1)) return false;
+    return true;
+}
+
+static bool can_coarsen_boxes(const std::vector<Box>& bs) {
+    for (auto& b : bs)
+        for (int d = 0; d < 3; ++d)
+            if (b.n(d) % 2 != 0 || b.n(d) < 4 || (b.lo[d] & 1)) return false;
+    return true;
+}
+
+struct Level {
+    Geom g;
+    std::vector<Box> boxes;
+};
+
+static std::vector<Level> hierarchy(const Geom& g0, const std::vector<Box>& b0) {
+    std::vector<Level> L;
+    L.push_back(Level{g0, b0});
+    while (can_coarsen_domain(L.back().g.dom)) {
+        Level c;
+        c.g = L.back().g;
+        c.g.dom = coarsen(L.back().g.dom);
+        c.g.h = L.back().g.h * 2.0;
+        if (can_coarsen_boxes(L.back().boxes)) {
+            for (auto& b : L.back().boxes) c.boxes.push_back(coarsen(b));
+        } else {
+            c.boxes.push_back(c.g.dom);
+        }
+        L.push_back(c);
+    }
+    return L;
+}
+
+// ----------------------------------------------------- ghost cell exchange
+// Owner map: for every domain cell, the box whose valid region holds it.
+static std::vector<int> owner_map(const Geom& g, const std::vector<Box>& bs) {
+    const Box& D = g.dom;
+    std::vector<int> own((size_t)D.cells(), -1);
+    for (size_t b = 0; b < bs.size(); ++b)
+        for (int k = bs[b].lo[2]; k <= bs[b].hi[2]; ++k)
+            for (int j = bs[b].lo[1]; j <= bs[b].hi[1]; ++j)
+                for (int i = bs[b].lo[0]; i <= bs[b].hi[0]; ++i) {
+                    size_t q = (size_t)(i - D.lo[0]) + (size_t)D.n(0) * ((size_t)(j - D.lo[1]) + (size_t)D.n(1) * (k - D.lo[2]));
+                    own[q] = (int)b;
+                }
+    return own;
+}
+
+// FillBoundary: every ghost cell that (after wrapping periodic directions) is
+// a valid cell of some box takes that cell's value; all other ghosts are left
+// untouched.  Faces, edges and corners.
+template <class T>
+static void fill_boundary(const Geom& g, MF<T>& mf, int ncomp_stride_unused = 0) {
+    (void)ncomp_stride_unused;
+    std::vector<Box> bs;
+    for (auto& fb : mf.f) bs.push_back(fb.bx);
+    std::vector<int> own = owner_map(g, bs);
+    const Box& D = g.dom;
+    for (size_t b = 0; b < mf.f.size(); ++b) {
+        Fab<T>& F = mf.f[b];
+        const Box& B = F.bx;
+        for (int k = B.lo[2] - F.ng; k <= B.hi[2] + F.ng; ++k)
+            for (int j = B.lo[1] - F.ng; j <= B.hi[1] + F.ng; ++j)
+                for (int i = B.lo[0] - F.ng; i <= B.hi[0] + F.ng; ++i) {
+                    if (B.has(i, j, k)) continue;
+                    int c[3] = {i, j, k};
+                    bool inside = true;
+                    for (int d = 0; d < 3; ++d) {
+                        if (c[d] < D.lo[d] || c[d] > D.hi[d]) {
+                            if (g.per[d]) c[d] = D.lo[d] + pmod(c[d] - D.lo[d], D.n(d));
+                            else inside = false;
+                        }
+                    }
+                    if (!inside) continue;
+                    size_t q = (size_t)(c[0] - D.lo[0]) + (size_t)D.n(0) * ((size_t)(c[1] - D.lo[1]) + (size_t)D.n(1) * (c[2] - D.lo[2]));
+                    int o = own[q];
+                    if (o < 0) continue;
+                    F(i, j, k) = mf.f[o](c[0], c[1], c[2]);
+                }
+    }
+}
+
+// Physical boundary: ghost cells outside a non-periodic domain face take
+// sign * (mirror cell), mirror reflected across every such face; sign = -1
+// per reflected direction for the homogeneous Dirichlet condition (odd), +1
+// for the even reflection used for cell coefficients.  Call after
+// fill_boundary (the mirror may be a ghost that fill_boundary set).
+template <class T>
+static void apply_bc(const Geom& g, MF<T>& mf, bool odd) {
+    const Box& D = g.dom;
+    for (auto& F : mf.f) {
+        const Box& B = F.bx;
+        for (int k = B.lo[2] - F.ng; k <= B.hi[2] + F.ng; ++k)
+            for (int j = B.lo[1] - F.ng; j <= B.hi[1] + F.ng; ++j)
+                for (int i = B.lo[0] - F.ng; i <= B.hi[0] + F.ng; ++i) {
+                    int m[3] = {i, j, k};
+                    int flips = 0;
+                    for (int d = 0; d < 3; ++d) {
+                        if (g.per[d]) continue;
+                        if (m[d] < D.lo[d]) { m[d] = 2 * D.lo[d] - 1 - m[d]; ++flips; }
+                        else if (m[d] > D.hi[d]) { m[d] = 2 * D.hi[d] + 1 - m[d]; ++flips; }
+                    }
+                    if (flips == 0) continue;
+                    T v = F(m[0], m[1], m[2]);
+                    F(i, j, k) = (odd && (flips & 1)) ? -v : v;
+                }
+    }
+}
+
+template <class T>
+static void fill_and_bc(const Geom& g, MF<T>& mf) {
+    fill_boundary(g, mf);
+    apply_bc(g, mf, true);
+}
+
+// ------------------------------------------------------- coefficients
+// Level-0 faces from a global cell-centred beta (F-order over the domain),
+// computed in T from beta rounded to T.
+template <class T>
+static FacesT<T> faces_from_beta(const Geom& g, const double* beta) {
+    const Box& D = g.dom;
+    FacesT<T> F;
+    F.dom = D;
+    auto B = [&](int i, int j, int k) -> T {
+        int c[3] = {i, j, k};
+        for (int d = 0; d < 3; ++d) {
+            if (c[d] < D.lo[d] || c[d] > D.hi[d]) {
+                if (g.per[d]) c[d] = D.lo[d] + pmod(c[d] - D.lo[d], D.n(d));
+                else c[d] = (c[d] < D.lo[d]) ? 2 * D.lo[d] - 1 - c[d] : 2 * D.hi[d] + 1 - c[d];  // even reflection
+            }
+        }
+        return (T)beta[(size_t)(c[0] - D.lo[0]) + (size_t)D.n(0) * ((size_t)(c[1] - D.lo[1]) + (size_t)D.n(1) * (c[2] - D.lo[2]))];
+    };
+    for (int d = 0; d < 3; ++d) {
+        int nx = D.n(0) + (d == 0), ny = D.n(1) + (d == 1), nz = D.n(2) + (d == 2);
+        F.c[d].assign((size_t)nx * ny * nz, T(0));
+        for (int k = D.lo[2]; k < D.lo[2] + nz; ++k)
+            for (int j = D.lo[1]; j < D.lo[1] + ny; ++j)
+                for (int i = D.lo[0]; i < D.lo[0] + nx; ++i) {
+                    int e[3] = {0, 0, 0};
+                    e[d] = 1;
+                    T bl = B(i - e[0], j - e[1], k - e[2]);
+                    T br = B(i, j, k);
+                    F.c[d][F.idx(d, i, j, k)] = (bl * br) * T(2) / (bl + br);  // harmonic mean
+                }
+    }
+    return F;
+}
+
+// Coarse faces: mean of the four fine faces that make up each coarse face.
+template <class T>
+static FacesT<T> coarsen_faces(const FacesT<T>& Ff, const Box& cdom) {
+    FacesT<T> C;
+    C.dom = cdom;
+    for (int d = 0; d < 3; ++d) {
+        int nx = cdom.n(0) + (d == 0), ny = cdom.n(1) + (d == 1), nz = cdom.n(2) + (d == 2);
+        C.c[d].assign((size_t)nx * ny * nz, T(0));
+        int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;  // the two tangential directions
+        for (int K = cdom.lo[2]; K < cdom.lo[2] + nz; ++K)
+            for (int J = cdom.lo[1]; J < cdom.lo[1] + ny; ++J)
+                for (int I = cdom.lo[0]; I < cdom.lo[0] + nx; ++I) {
+                    int f0[3] = {2 * I, 2 * J, 2 * K};
+                    T a[2][2];
+                    for (int q = 0; q < 2; ++q)
+                        for (int p = 0; p < 2; ++p) {
+                            int c[3] = {f0[0], f0[1], f0[2]};
+                            c[t1] += p;
+                            c[t2] += q;
+                            a[q][p] = Ff.at(d, c[0], c[1], c[2]);
+                        }
+                    C.c[d][C.idx(d, I, J, K)] = ((a[0][0] + a[0][1]) + (a[1][0] + a[1][1])) * T(0.25);
+                }
+    }
+    return C;
+}
+
+// ------------------------------------------------------------ operators
+// 7-point operator, constant coefficient:
+//   s = ((u[i-1]+u[i+1]) + (u[j-1]+u[j+1])) + (u[k-1]+u[k+1])
+//   (L u) = (s - 6 u) / h^2,   GS: u = (s - h^2 f) / 6
+// variable coefficient (face coefficients b):
+//   sb = ((bxm+bxp) + (bym+byp)) + (bzm+bzp)
+//   su = ((bxm u[i-1] + bxp u[i+1]) + (bym u[j-1] + byp u[j+1])) + (bzm u[k-1] + bzp u[k+1])
+//   (L u) = (su - sb u) / h^2, GS: u = (su - h^2 f) / sb
+template <class T>
+static inline void stencil(const Fab<T>& U, const FacesT<T>* fc, int i, int j, int k, T& su, T& sb) {
+    if (!fc) {
+        su = ((U(i - 1, j, k) + U(i + 1, j, k)) + (U(i, j - 1, k) + U(i, j + 1, k))) + (U(i, j, k - 1) + U(i, j, k + 1));
+        sb = T(6);
+        return;
+    }
+    // periodic: the face at hi+1 and the face at lo hold the same value
+    auto F = [&](int d, int a, int b, int c) -> T { return fc->at(d, a, b, c); };
+    T bxm = F(0, i, j, k), bxp = F(0, i + 1, j, k);
+    T bym = F(1, i, j, k), byp = F(1, i, j + 1, k);
+    T bzm = F(2, i, j, k), bzp = F(2, i, j, k + 1);
+    sb = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
+    su = ((bxm * U(i - 1, j, k) + bxp * U(i + 1, j, k)) + (bym * U(i, j - 1, k) + byp * U(i, j + 1, k))) +
+         (bzm * U(i, j, k - 1) + bzp * U(i, j, k + 1));
+}
+
+// One colour of red-black Gauss-Seidel (ghosts of u must be current).
+template <class T>
+static void gs_colour(const Geom& g, MF<T>& u, const MF<T>& f, const FacesT<T>* fc, int colour) {
+    const T h2 = (T)(g.h * g.h);
+    for (size_t b = 0; b < u.f.size(); ++b) {
+        Fab<T>& U = u.f[b];
+        const Fab<T>& Fb = f.f[b];
+        const Box& B = U.bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) {
+                    if (parity(i, j, k) != colour) continue;
+                    T su, sb;
+                    stencil(U, fc, i, j, k, su, sb);
+                    U(i, j, k) = (su - h2 * Fb(i, j, k)) / sb;
+                }
+    }
+}
+
+// r = f - L u on valid cells (ghosts of u must be current).  Returns the
+// max-norm and the sum of squares (in box, k, j, i order).
+template <class T>
+static void residual(const Geom& g, const MF<T>& u, const MF<T>& f, const FacesT<T>* fc, MF<T>& r, double* rinf,
+                     double* rl2sq) {
+    const T ih2 = (T)(1.0 / (g.h * g.h));
+    double mx = 0.0, s2 = 0.0;
+    bool bad = false;
+    for (size_t b = 0; b < u.f.size(); ++b) {
+        const Fab<T>& U = u.f[b];
+        const Box& B = U.bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) {
+                    T su, sb;
+                    stencil(U, fc, i, j, k, su, sb);
+                    T Lu = (su - sb * U(i, j, k)) * ih2;
+                    T rv = f.f[b](i, j, k) - Lu;
+                    r.f[b](i, j, k) = rv;
+                    double a = std::fabs((double)rv);
+                    if (std::isnan(a)) bad = true;
+                    else if (a > mx) mx = a;
+                    s2 += (double)rv * (double)rv;
+                }
+    }
+    if (bad) mx = std::nan("");
+    if (rinf) *rinf = mx;
+    if (rl2sq) *rl2sq = s2;
+}
+
+// Index of the coarse box that contains the coarsened fine box.
+static int coarse_owner(const std::vector<Box>& cb, const Box& fine) {
+    Box c = coarsen(fine);
+    for (size_t q = 0; q < cb.size(); ++q)
+        if (cb[q].has(c.lo[0], c.lo[1], c.lo[2]) && cb[q].has(c.hi[0], c.hi[1], c.hi[2])) return (int)q;
+    return -1;
+}
+
+// f_c(I) = (1/8) * sum of the 8 children of I.
+template <class T>
+static void restrict_avg(const MF<T>& rf, MF<T>& fc) {
+    std::vector<Box> cbs;
+    for (auto& F : fc.f) cbs.push_back(F.bx);
+    for (size_t b = 0; b < rf.f.size(); ++b) {
+        const Fab<T>& R = rf.f[b];
+        Box c = coarsen(R.bx);
+        Fab<T>& C = fc.f[coarse_owner(cbs, R.bx)];
+        for (int K = c.lo[2]; K <= c.hi[2]; ++K)
+            for (int J = c.lo[1]; J <= c.hi[1]; ++J)
+                for (int I = c.lo[0]; I <= c.hi[0]; ++I) {
+                    int i = 2 * I, j = 2 * J, k = 2 * K;
+                    T s = ((R(i, j, k) + R(i + 1, j, k)) + (R(i, j + 1, k) + R(i + 1, j + 1, k))) +
+                          ((R(i, j, k + 1) + R(i + 1, j, k + 1)) + (R(i, j + 1, k + 1) + R(i + 1, j + 1, k + 1)));
+                    C(I, J, K) = s * T(0.125);
+                }
+    }
+}
+
+// u_f += P e_c.  Trilinear (order 2): per direction the parent P = floor(i/2)
+// weighs 3/4 and its neighbour P+s (s = +1 for odd i, -1 for even i) 1/4, so
+//   e = (((27 c000 + 9 ((c100 + c010) + c001)) + 3 ((c110 + c101) + c011)) + c111) / 64.
+// Piecewise constant (order 1): e = c000.  Ghosts of e_c must be current.
+template <class T>
+static void prolong_add(const MF<T>& ec, MF<T>& uf, int order) {
+    std::vector<Box> cbs;
+    for (auto& F : ec.f) cbs.push_back(F.bx);
+    for (size_t b = 0; b < uf.f.size(); ++b) {
+        Fab<T>& U = uf.f[b];
+        const Fab<T>& E = ec.f[coarse_owner(cbs, U.bx)];
+        const Box& B = U.bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) {
+                    int I = fdiv2(i), J = fdiv2(j), K = fdiv2(k);
+                    T e;
+                    if (order == 1) {
+                        e = E(I, J, K);
+                    } else {
+                        int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+                        T c000 = E(I, J, K);
+                        T c100 = E(I + si, J, K), c010 = E(I, J + sj, K), c001 = E(I, J, K + sk);
+                        T c110 = E(I + si, J + sj, K), c101 = E(I + si, J, K + sk), c011 = E(I, J + sj, K + sk);
+                        T c111 = E(I + si, J + sj, K + sk);
+                        e = (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
+                            T(0.015625);
+                    }
+                    U(i, j, k) = U(i, j, k) + e;
+                }
+    }
+}
+
+// ------------------------------------------------------------- bottom
+// FP64 conjugate gradients for L x = rhs on one level (any box layout).
+// The operator is negative definite (Dirichlet) or negative semidefinite
+// with the constants as null space (fully periodic); CG applies unchanged.
+struct CGStats { int iters = 0; double rel = 0.0; };
+
+static double dot(const MF<double>& a, const MF<double>& b) {
+    double s = 0.0;
+    for (size_t q = 0; q < a.f.size(); ++q) {
+        const Box& B = a.f[q].bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) s += a.f[q](i, j, k) * b.f[q](i, j, k);
+    }
+    return s;
+}
+
+static double mean_valid(const MF<double>& a) {
+    double s = 0.0;
+    long n = 0;
+    for (auto& F : a.f) {
+        const Box& B = F.bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) { s += F(i, j, k); ++n; }
+    }
+    return s / (double)n;
+}
+
+static void add_const_valid(MF<double>& a, double c) {
+    for (auto& F : a.f) {
+        const Box& B = F.bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) F(i, j, k) -= c;
+    }
+}
+
+static void apply_op(const Geom& g, MF<double>& p, const Faces* fc, MF<double>& Ap) {
+    fill_and_bc(g, p);
+    const double ih2 = 1.0 / (g.h * g.h);
+    for (size_t b = 0; b < p.f.size(); ++b) {
+        const Box& B = p.f[b].bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) {
+                    double su, sb;
+                    stencil(p.f[b], fc, i, j, k, su, sb);
+                    Ap.f[b](i, j, k) = (su - sb * p.f[b](i, j, k)) * ih2;
+                }
+    }
+}
+
+static CGStats bottom_cg(const Geom& g, const std::vector<Box>& bs, const MF<double>& rhs_in, const Faces* fc,
+                         MF<double>& x, double rtol) {
+    CGStats st;
+    MF<double> r, p, Ap;
+    r.define(bs, 0);
+    p.define(bs, 1);
+    Ap.define(bs, 0);
+    x.zero();
+    for (size_t b = 0; b < bs.size(); ++b) {
+        const Box& B = bs[b];
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) r.f[b](i, j, k) = rhs_in.f[b](i, j, k);
+    }
+    const bool sing = g.all_periodic();
+    if (sing) add_const_valid(r, mean_valid(r));
+    for (size_t b = 0; b < bs.size(); ++b) {
+        const Box& B = bs[b];
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) p.f[b](i, j, k) = r.f[b](i, j, k);
+    }
+    double rs = dot(r, r);
+    const double rs0 = rs;
+    if (rs0 == 0.0) return st;
+    long ncell = 0;
+    for (auto& B : bs) ncell += B.cells();
+    const long maxit = 4 * ncell;
+    for (long it = 0; it < maxit; ++it) {
+        apply_op(g, p, fc, Ap);
+        double pAp = dot(p, Ap);
+        double alpha = rs / pAp;
+        for (size_t b = 0; b < bs.size(); ++b) {
+            const Box& B = bs[b];
+            for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+                for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                    for (int i = B.lo[0]; i <= B.hi[0]; ++i) {
+                        x.f[b](i, j, k) += alpha * p.f[b](i, j, k);
+                        r.f[b](i, j, k) -= alpha * Ap.f[b](i, j, k);
+                    }
+        }
+        double rsn = dot(r, r);
+        st.iters = (int)(it + 1);
+        st.rel = std::sqrt(rsn / rs0);
+        if (std::sqrt(rsn) <= rtol * std::sqrt(rs0)) break;
+        double beta = rsn / rs;
+        for (size_t b = 0; b < bs.size(); ++b) {
+            const Box& B = bs[b];
+            for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+                for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                    for (int i = B.lo[0]; i <= B.hi[0]; ++i)
+                        p.f[b](i, j, k) = r.f[b](i, j, k) + beta * p.f[b](i, j, k);
+        }
+        rs = rsn;
+    }
+    if (sing) add_const_valid(x, mean_valid(x));
+    return st;
+}
+
+// ------------------------------------------------------------ V-cycle
+struct Params {
+    int nu1 = 2, nu2 = 2, max_cycles = 200, precision = 0, prolong = 2, fixed_cycles = 0;
+    double rel_tol = 1e-10, abs_tol = 0.0, h = 0.0, bottom_rtol = 1e-12;
+};
+
+// Multigrid hierarchy of storage type T: per level u, f, r and (variable
+// coefficient) the face coefficients in T, plus the bottom level's faces in
+// FP64 for the FP64 bottom solve.
+template <class T>
+struct Hier {
+    std::vector<Level> L;
+    std::vector<FacesT<T>> faces;  // empty: constant coefficient
+    Faces bottom_faces;
+    std::vector<MF<T>> u, f, r;
+    const FacesT<T>* fc(size_t l) const { return faces.empty() ? nullptr : &faces[l]; }
+    const Faces* bfc() const { return faces.empty() ? nullptr : &bottom_faces; }
+    void define(const std::vector<Level>& lv, const double* beta);
+};
+
+template <class T>
+static std::vector<FacesT<T>> build_faces(const std::vector<Level>& L, const double* beta) {
+    std::vector<FacesT<T>> out;
+    if (!beta) return out;
+    out.push_back(faces_from_beta<T>(L[0].g, beta));
+    for (size_t l = 1; l < L.size(); ++l) out.push_back(coarsen_faces(out[l - 1], L[l].g.dom));
+    return out;
+}
+
+template <class T>
+void Hier<T>::define(const std::vector<Level>& lv, const double* beta) {
+    L = lv;
+    u.resize(L.size()); f.resize(L.size()); r.resize(L.size());
+    for (size_t l = 0; l < L.size(); ++l) {
+        u[l].define(L[l].boxes, 1);
+        f[l].define(L[l].boxes, 1);
+        r[l].define(L[l].boxes, 1);
+    }
+    faces = build_faces<T>(L, beta);
+    if (!faces.empty()) {
+        const FacesT<T>& fb = faces.back();
+        bottom_faces.dom = fb.dom;
+        for (int d = 0; d < 3; ++d) bottom_faces.c[d].assign(fb.c[d].begin(), fb.c[d].end());
+    }
+}
+
+template <class T>
+static void copy_valid(const MF<T>& a, MF<double>& b) {
+    for (size_t q = 0; q < a.f.size(); ++q) {
+        const Box& B = a.f[q].bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) b.f[q](i, j, k) = (double)a.f[q](i, j, k);
+    }
+}
+
+template <class T>
+static void copy_valid_back(const MF<double>& a, MF<T>& b) {
+    for (size_t q = 0; q < a.f.size(); ++q) {
+        const Box& B = a.f[q].bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) b.f[q](i, j, k) = (T)a.f[q](i, j, k);
+    }
+}
+
+template <class T>
+static void smooth(Hier<T>& H, size_t l, int nsweeps) {
+    const Geom& g = H.L[l].g;
+    for (int s = 0; s < nsweeps; ++s)
+        for (int c = 0; c < 2; ++c) {
+            fill_and_bc(g, H.u[l]);
+            gs_colour(g, H.u[l], H.f[l], H.fc(l), c);
+        }
+}
+
+// V(nu1, nu2) from level l down: pre-smooth, residual, restrict, zero the
+// coarse guess, recurse, prolong-correct, post-smooth; FP64 CG at the bottom.
+template <class T>
+static void vcycle(Hier<T>& H, const Params& P, size_t l, std::vector<CGStats>* cgs) {
+    const size_t last = H.L.size() - 1;
+    if (l == last) {
+        MF<double> rhs, x;
+        rhs.define(H.L[l].boxes, 0);
+        x.define(H.L[l].boxes, 1);
+        copy_valid(H.f[l], rhs);
+        CGStats st = bottom_cg(H.L[l].g, H.L[l].boxes, rhs, H.bfc(), x, P.bottom_rtol);
+        if (cgs) cgs->push_back(st);
+        copy_valid_back(x, H.u[l]);
+        return;
+    }
+    smooth(H, l, P.nu1);
+    fill_and_bc(H.L[l].g, H.u[l]);
+    residual(H.L[l].g, H.u[l], H.f[l], H.fc(l), H.r[l], nullptr, nullptr);
+    restrict_avg(H.r[l], H.f[l + 1]);
+    H.u[l + 1].zero();
+    vcycle(H, P, l + 1, cgs);
+    fill_and_bc(H.L[l + 1].g, H.u[l + 1]);
+    prolong_add(H.u[l + 1], H.u[l], P.prolong);
+    smooth(H, l, P.nu2);
+}
+
+struct Info {
+    int status, cycles, nhist, levels;
+    double rel_inf, rel_l2, f_inf;
+    double hist[256];
+    double hist_l2[256];
+    int cg_iters_max;
+};
+
+static void scatter_global(const Box& D, const double* glob, MF<double>& mf) {
+    for (auto& F : mf.f) {
+        const Box& B = F.bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i)
+                    F(i, j, k) = glob[(size_t)(i - D.lo[0]) + (size_t)D.n(0) * ((size_t)(j - D.lo[1]) + (size_t)D.n(1) * (k - D.lo[2]))];
+    }
+}
+
+static void gather_global(const Box& D, const MF<double>& mf, double* glob) {
+    for (auto& F : mf.f) {
+        const Box& B = F.bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i)
+                    glob[(size_t)(i - D.lo[0]) + (size_t)D.n(0) * ((size_t)(j - D.lo[1]) + (size_t)D.n(1) * (k - D.lo[2]))] = F(i, j, k);
+    }
+}
+
+static double max_abs_valid(const MF<double>& a) {
+    double m = 0.0;
+    bool bad = false;
+    for (auto& F : a.f) {
+        const Box& B = F.bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) {
+                    double v = std::fabs(F(i, j, k));
+                    if (std::isnan(v)) bad = true;
+                    else if (v > m) m = v;
+                }
+    }
+    return bad ? std::nan("") : m;
+}
+
+// Driver.  u starts at zero; each cycle: ghosts, residual and its norms, stop
+// test, then one V-cycle (FP64) or one refinement step around an FP32
+// V-cycle.  Status codes: 0 ok, -4 not converged, -5 non-finite.
+static int solve(const Params& P, const Geom& g0, const std::vector<Box>& b0, const double* fglob, const double* beta,
+                 double* uglob, Info* info) {
+    std::vector<Level> L = hierarchy(g0, b0);
+    std::memset(info, 0, sizeof(Info));
+    info->levels = (int)L.size();
+
+    Hier<double> H64;
+    Hier<float> H32;
+    MF<double> u_ir, f_ir, r_ir;
+    std::vector<Faces> faces64;
+    MF<double>* u;
+    MF<double>* f;
+    MF<double>* r;
+    const Faces* fc0;
+    if (P.precision == 0) {
+        H64.define(L, beta);
+        u = &H64.u[0]; f = &H64.f[0]; r = &H64.r[0];
+        fc0 = H64.fc(0);
+    } else {
+        H32.define(L, beta);
+        u_ir.define(b0, 1); f_ir.define(b0, 1); r_ir.define(b0, 1);
+        u = &u_ir; f = &f_ir; r = &r_ir;
+        if (beta) faces64.push_back(faces_from_beta<double>(g0, beta));
+        fc0 = beta ? &faces64[0] : nullptr;
+    }
+    scatter_global(g0.dom, fglob, *f);
+    const double fnorm = max_abs_valid(*f);
+    info->f_inf = fnorm;
+    std::vector<CGStats> cgs;
+
+    int status = 0;
+    if (!(fnorm > 0.0)) {
+        if (std::isnan(fnorm)) status = -5;
+        gather_global(g0.dom, *u, uglob);
+        info->status = status;
+        return status;
+    }
+    int cyc = 0;
+    for (;; ++cyc) {
+        fill_and_bc(g0, *u);
+        double rinf, rl2;
+        residual(g0, *u, *f, fc0, *r, &rinf, &rl2);
+        if (cyc < 256) { info->hist[cyc] = rinf / fnorm; info->hist_l2[cyc] = std::sqrt(rl2); info->nhist = cyc + 1; }
+        info->rel_inf = rinf / fnorm;
+        info->rel_l2 = std::sqrt(rl2);
+        if (!std::isfinite(rinf)) { status = -5; break; }
+        if (P.fixed_cycles > 0) {
+            if (cyc == P.fixed_cycles) break;
+        } else {
+            if (rinf <= P.rel_tol * fnorm || rinf <= P.abs_tol) break;
+            if (cyc == P.max_cycles) { status = -4; break; }
+        }
+        if (P.precision == 0) {
+            vcycle(H64, P, 0, &cgs);
+        } else {
+            for (size_t q = 0; q < u->f.size(); ++q) {
+                const Box& B = u->f[q].bx;
+                for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+                    for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                        for (int i = B.lo[0]; i <= B.hi[0]; ++i) H32.f[0].f[q](i, j, k) = (float)r->f[q](i, j, k);
+            }
+            H32.u[0].zero();
+            vcycle(H32, P, 0, &cgs);
+            for (size_t q = 0; q < u->f.size(); ++q) {
+                const Box& B = u->f[q].bx;
+                for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+                    for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                        for (int i = B.lo[0]; i <= B.hi[0]; ++i) u->f[q](i, j, k) += (double)H32.u[0].f[q](i, j, k);
+            }
+        }
+    }
+    info->cycles = cyc;
+    for (auto& s : cgs) info->cg_iters_max = std::max(info->cg_iters_max, s.iters);
+    gather_global(g0.dom, *u, uglob);
+    if (g0.all_periodic()) {
+        // mean-zero representative; the mean is summed in global F-order so
+        // that it does not depend on the box decomposition
+        const size_t N = (size_t)g0.dom.cells();
+        double s = 0.0;
+        for (size_t q = 0; q < N; ++q) s += uglob[q];
+        const double m = s / (double)N;
+        for (size_t q = 0; q < N; ++q) uglob[q] -= m;
+    }
+    info->status = status;
+    return status;
+}
+
+}  // namespace orc
+
+// ====================================================================== C API
+// Multi-box arrays cross this interface "packed": the grown boxes (ng ghost
+// cells) of a level, one after another in box order, each in F-order with
+// the component index slowest.  Global arrays are domain-sized, F-order.
+using namespace orc;
+
+static Box box6(const int* p) { return Box{{p[0], p[1], p[2]}, {p[3], p[4], p[5]}}; }
+static std::vector<Box> boxes_of(int nb, const int* lohi) {
+    std::vector<Box> v;
+    for (int b = 0; b < nb; ++b) v.push_back(box6(lohi + 6 * b));
+    return v;
+}
+static Geom geom_of(const int* dom6, const int* per, double h) {
+    Geom g;
+    g.dom = box6(dom6);
+    for (int d = 0; d < 3; ++d) g.per[d] = per[d] ? 1 : 0;
+    g.h = h;
+    return g;
+}
+template <class T>
+static void unpack(MF<T>& mf, const T* data, int comp, int ncomp) {
+    size_t off = 0;
+    for (auto& F : mf.f) {
+        size_t n = F.v.size();
+        std::memcpy(F.v.data(), data + off + (size_t)comp * n, n * sizeof(T));
+        off += n * ncomp;
+    }
+}
+template <class T>
+static void pack(const MF<T>& mf, T* data, int comp, int ncomp) {
+    size_t off = 0;
+    for (auto& F : mf.f) {
+        size_t n = F.v.size();
+        std::memcpy(data + off + (size_t)comp * n, F.v.data(), n * sizeof(T));
+        off += n * ncomp;
+    }
+}
+
+extern "C" {
+
+int orc_chop(const int* dom6, int max_box, int cap, int* out_lohi) {
+    std::vector<Box> bs = chop(box6(dom6), max_box);
+    if ((int)bs.size() > cap) return -(int)bs.size();
+    for (size_t b = 0; b < bs.size(); ++b)
+        for (int d = 0; d < 3; ++d) { out_lohi[6 * b + d] = bs[b].lo[d]; out_lohi[6 * b + 3 + d] = bs[b].hi[d]; }
+    return (int)bs.size();
+}
+
+// Hierarchy of levels: per level the domain and the boxes.  Returns the
+// number of levels, or a negative count if the caps are too small.
+int orc_hierarchy(const int* dom6, int nb, const int* lohi, int cap_levels, int cap_boxes, int* lev_nb,
+                  int* lev_dom6, int* lev_lohi) {
+    const int noper[3] = {0, 0, 0};
+    Geom g = geom_of(dom6, noper, 1.0);
+    std::vector<Level> L = hierarchy(g, boxes_of(nb, lohi));
+    int tot = 0;
+    for (auto& l : L) tot += (int)l.boxes.size();
+    if ((int)L.size() > cap_levels || tot > cap_boxes) return -1;
+    int o = 0;
+    for (size_t l = 0; l < L.size(); ++l) {
+        lev_nb[l] = (int)L[l].boxes.size();
+        for (int d = 0; d < 3; ++d) { lev_dom6[6 * l + d] = L[l].g.dom.lo[d]; lev_dom6[6 * l + 3 + d] = L[l].g.dom.hi[d]; }
+        for (auto& b : L[l].boxes) {
+            for (int d = 0; d < 3; ++d) { lev_lohi[6 * o + d] = b.lo[d]; lev_lohi[6 * o + 3 + d] = b.hi[d]; }
+            ++o;
+        }
+    }
+    return (int)L.size();
+}
+
+void orc_fill_boundary(const int* dom6, const int* per, int nb, const int* lohi, int ng, int ncomp, double* data) {
+    MF<double> mf;
+    mf.define(boxes_of(nb, lohi), ng);
+    Geom g = geom_of(dom6, per, 1.0);
+    for (int c = 0; c < ncomp; ++c) {
+        unpack(mf, data, c, ncomp);
+        fill_boundary(g, mf);
+        pack(mf, data, c, ncomp);
+    }
+}
+
+void orc_apply_bc(const int* dom6, const int* per, int nb, const int* lohi, int ng, int ncomp, int odd, double* data) {
+    MF<double> mf;
+    mf.define(boxes_of(nb, lohi), ng);
+    Geom g = geom_of(dom6, per, 1.0);
+    for (int c = 0; c < ncomp; ++c) {
+        unpack(mf, data, c, ncomp);
+        apply_bc(g, mf, odd != 0);
+        pack(mf, data, c, ncomp);
+    }
+}
+
+void orc_fill_boundary_f32(const int* dom6, const int* per, int nb, const int* lohi, int ng, float* data) {
+    MF<float> mf;
+    mf.define(boxes_of(nb, lohi), ng);
+    Geom g = geom_of(dom6, per, 1.0);
+    unpack(mf, data, 0, 1);
+    fill_boundary(g, mf);
+    pack(mf, data, 0, 1);
+}
+
+// One red-black colour on a level (ng = 1, ghosts must be current).
+// beta_glob: NULL for constant coefficient, else the level's cell beta as a
+// global array (only valid for a level-0 call: faces from the cell field).
+static void gs_impl(const int* dom6, const int* per, int nb, const int* lohi, double h, int colour, double* u,
+                    const double* f, const double* beta_glob) {
+    Geom g = geom_of(dom6, per, h);
+    MF<double> U, F;
+    U.define(boxes_of(nb, lohi), 1);
+    F.define(boxes_of(nb, lohi), 1);
+    unpack(U, u, 0, 1);
+    unpack(F, f, 0, 1);
+    Faces fc;
+    if (beta_glob) fc = faces_from_beta<double>(g, beta_glob);
+    gs_colour(g, U, F, beta_glob ? &fc : nullptr, colour);
+    pack(U, u, 0, 1);
+}
+
+void orc_gs(const int* dom6, const int* per, int nb, const int* lohi, double h, int colour, double* u,
+            const double* f, const double* beta_glob) {
+    gs_impl(dom6, per, nb, lohi, h, colour, u, f, beta_glob);
+}
+
+void orc_gs_f32(const int* dom6, const int* per, int nb, const int* lohi, double h, int colour, float* u,
+                const float* f) {
+    Geom g = geom_of(dom6, per, h);
+    MF<float> U, F;
+    U.define(boxes_of(nb, lohi), 1);
+    F.define(boxes_of(nb, lohi), 1);
+    unpack(U, u, 0, 1);
+    unpack(F, f, 0, 1);
+    gs_colour<float>(g, U, F, nullptr, colour);
+    pack(U, u, 0, 1);
+}
+
+void orc_residual(const int* dom6, const int* per, int nb, const int* lohi, double h, const double* u,
+                  const double* f, const double* beta_glob, double* r, double* norms) {
+    Geom g = geom_of(dom6, per, h);
+    MF<double> U, F, R;
+    U.define(boxes_of(nb, lohi), 1);
+    F.define(boxes_of(nb, lohi), 1);
+    R.define(boxes_of(nb, lohi), 1);
+    unpack(U, u, 0, 1);
+    unpack(F, f, 0, 1);
+    unpack(R, r, 0, 1);
+    Faces fc;
+    if (beta_glob) fc = faces_from_beta<double>(g, beta_glob);
+    residual(g, U, F, beta_glob ? &fc : nullptr, R, &norms[0], &norms[1]);
+    pack(R, r, 0, 1);
+}
+
+// Restriction from a fine level (ng_f) to a coarse level (ng_c).
+void orc_restrict(int nbf, const int* lohif, int ngf, int nbc, const int* lohic, int ngc, const double* rf,
+                  double* fc) {
+    MF<double> R, C;
+    R.define(boxes_of(nbf, lohif), ngf);
+    C.define(boxes_of(nbc, lohic), ngc);
+    unpack(R, rf, 0, 1);
+    unpack(C, fc, 0, 1);
+    restrict_avg(R, C);
+    pack(C, fc, 0, 1);
+}
+
+void orc_prolong(int nbf, const int* lohif, int ngf, int nbc, const int* lohic, int ngc, int order, const double* ec,
+                 double* uf) {
+    MF<double> U, E;
+    U.define(boxes_of(nbf, lohif), ngf);
+    E.define(boxes_of(nbc, lohic), ngc);
+    unpack(U, uf, 0, 1);
+    unpack(E, ec, 0, 1);
+    prolong_add(E, U, order);
+    pack(U, uf, 0, 1);
+}
+
+// Face coefficients of every level from a global cell beta.  out receives,
+// level by level, the x, y and z face arrays (global, F-order, sized
+// (nx+1)*ny*nz, nx*(ny+1)*nz, nx*ny*(nz+1)).  Returns the number of doubles.
+long orc_faces(const int* dom6, const int* per, int nb, const int* lohi, const double* beta, double* out, long cap) {
+    Geom g = geom_of(dom6, per, 1.0);
+    std::vector<Level> L = hierarchy(g, boxes_of(nb, lohi));
+    std::vector<Faces> F = build_faces<double>(L, beta);
+    long n = 0;
+    for (auto& fl : F)
+        for (int d = 0; d < 3; ++d) n += (long)fl.c[d].size();
+    if (n > cap) return -n;
+    long o = 0;
+    for (auto& fl : F)
+        for (int d = 0; d < 3; ++d) { std::memcpy(out + o, fl.c[d].data(), fl.c[d].size() * sizeof(double)); o += (long)fl.c[d].size(); }
+    return n;
+}
+
+// L u for a global array u (one box covering the domain), FP64.
+void orc_apply_op(const int* dom6, const int* per, double h, const double* u_glob, const double* beta_glob,
+                  double* Lu_glob) {
+    Geom g = geom_of(dom6, per, h);
+    std::vector<Box> one{g.dom};
+    MF<double> U, A;
+    U.define(one, 1);
+    A.define(one, 0);
+    scatter_global(g.dom, u_glob, U);
+    Faces fc;
+    if (beta_glob) fc = faces_from_beta<double>(g, beta_glob);
+    apply_op(g, U, beta_glob ? &fc : nullptr, A);
+    gather_global(g.dom, A, Lu_glob);
+}
+
+typedef struct {
+    int nu1, nu2, max_cycles, precision, prolong, fixed_cycles;
+    double rel_tol, abs_tol, h, bottom_rtol;
+} orc_params;
+
+int orc_solve(const orc_params* p, const int* dom6, const int* per, int nb, const int* lohi, const double* f_glob,
+              const double* beta_glob, double* u_glob, Info* info) {
+    Params P;
+    P.nu1 = p->nu1; P.nu2 = p->nu2; P.max_cycles = p->max_cycles; P.precision = p->precision;
+    P.prolong = p->prolong; P.fixed_cycles = p->fixed_cycles;
+    P.rel_tol = p->rel_tol; P.abs_tol = p->abs_tol; P.h = p->h; P.bottom_rtol = p->bottom_rtol;
+    Geom g = geom_of(dom6, per, p->h);
+    return solve(P, g, boxes_of(nb, lohi), f_glob, beta_glob, u_glob, info);
+}
+
+// Bottom solve on its own (global arrays, one box): for tests of the CG stage.
+int orc_bottom(const int* dom6, const int* per, double h, const double* f_glob, const double* beta_glob,
+               double rtol, double* u_glob, int* iters) {
+    Geom g = geom_of(dom6, per, h);
+    std::vector<Box> one{g.dom};
+    std::vector<Level> L{Level{g, one}};
+    std::vector<Faces> F = build_faces<double>(L, beta_glob);
+    MF<double> rhs, x;
+    rhs.define(one, 0);
+    x.define(one, 1);
+    scatter_global(g.dom, f_glob, rhs);
+    CGStats st = bottom_cg(g, one, rhs, F.empty() ? nullptr : &F[0], x, rtol);
+    gather_global(g.dom, x, u_glob);
+    if (iters) *iters = st.iters;
+    return 0;
+}
+
+}  // extern "C"

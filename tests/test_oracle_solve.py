@@ -1,0 +1,184 @@
+"""Oracle pins for the whole multigrid solve.
+
+* Closed-form discrete solution: with f = -3 k^2 sin(kx)sin(ky)sin(kz) the
+  discrete solution is C(h) * sin-product, C(h) = (k h/2)^2 / sin^2(k h/2)
+  (k = 2 pi periodic, k = pi homogeneous Dirichlet).
+* Second-order convergence: ||u_h - s||_inf = (C(h) - 1) ||s||_inf, ratio -> 4;
+  and for a smooth variable coefficient against a manufactured solution.
+* Dense direct solves on 8^3 (numpy.linalg.solve / lstsq on the matrix
+  assembled column by column from the operator).
+* Per-cycle contraction (frozen bound) and its independence of h.
+* Decomposition independence: the same problem on 1, 8 or 64 boxes gives the
+  same bits after a fixed number of cycles.
+* Mixed precision: FP64 iterative refinement around an FP32 V-cycle reaches
+  the FP64 tolerance (residual recomputed with the FP64 operator).
+* Status codes: non-finite input, cycle cap, zero right-hand side.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from test_oracle_operator import assemble
+
+FROZEN_MAX_CONTRACTION = 0.125  # measured 0.104-0.110 on n = 32, 64 (+10% margin, rounded)
+
+
+def C_of(n, periodic):
+    k = 2 * np.pi if periodic else np.pi
+    x = k / n / 2
+    return x * x / np.sin(x) ** 2
+
+
+def cube(n):
+    return (0, 0, 0), (n - 1, n - 1, n - 1)
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_closed_form_discrete_solution(orc, periodic):
+    n = 32
+    f, s = W.sine_rhs(n, periodic)
+    lo, hi = cube(n)
+    per = (1, 1, 1) if periodic else (0, 0, 0)
+    u, info = orc.solve(lo, hi, per, orc.chop(lo, hi, 16), f)
+    assert info["status"] == 0 and info["rel_inf"] <= 1e-10
+    C = C_of(n, periodic)
+    assert np.max(np.abs(u - C * s)) <= 1e-8
+    if periodic:
+        assert abs(C - 1.0032189644400795) < 1e-15
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_second_order_convergence(orc, periodic):
+    errs = []
+    for n in (16, 32, 64):
+        f, s = W.sine_rhs(n, periodic)
+        lo, hi = cube(n)
+        per = (1, 1, 1) if periodic else (0, 0, 0)
+        u, info = orc.solve(lo, hi, per, orc.chop(lo, hi, 32), f)
+        e = np.max(np.abs(u - s))
+        exp = (C_of(n, periodic) - 1.0) * np.max(np.abs(s))
+        assert abs(e - exp) <= 1e-6 * exp
+        errs.append(e)
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.8 < r1 < 4.2 and 3.9 < r2 < 4.1
+
+
+def test_varcoef_manufactured_second_order(orc):
+    # u = sin(pi x) sin(pi y) sin(pi z), beta = 1 + cos(pi x)cos(pi y)cos(pi z)/2
+    # (zero normal derivative on the walls), f = div(beta grad u).
+    errs = []
+    for n in (16, 32, 64):
+        x = (np.arange(n) + 0.5) / n
+        X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+        S = np.sin(np.pi * X) * np.sin(np.pi * Y) * np.sin(np.pi * Z)
+        Cc = np.cos(np.pi * X) * np.cos(np.pi * Y) * np.cos(np.pi * Z)
+        beta = 1.0 + 0.5 * Cc
+        sc = np.sin(np.pi * X) * np.cos(np.pi * X) * np.sin(np.pi * Y) * np.cos(np.pi * Y) * np.sin(np.pi * Z) * np.cos(np.pi * Z)
+        f = -3 * np.pi ** 2 * beta * S - 1.5 * np.pi ** 2 * sc
+        lo, hi = cube(n)
+        u, info = orc.solve(lo, hi, (0, 0, 0), orc.chop(lo, hi, 32), np.asfortranarray(f), np.asfortranarray(beta))
+        assert info["status"] == 0
+        errs.append(np.max(np.abs(u - S)))
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.7 < errs[1] / errs[2] < 4.3
+
+
+@pytest.mark.parametrize("case", ["dir_const", "dir_var", "per_const", "mixed_var", "dir_const_8boxes"])
+def test_dense_direct_8cubed(orc, case):
+    n = 8
+    lo, hi = cube(n)
+    shape = (n, n, n)
+    per = {"dir_const": (0, 0, 0), "dir_var": (0, 0, 0), "per_const": (1, 1, 1), "mixed_var": (1, 0, 0),
+           "dir_const_8boxes": (0, 0, 0)}[case]
+    beta = W.smooth_gaussian_beta(shape, 31) if "var" in case else None
+    f = W.uniform_rhs(shape, 30, mean_zero=(per == (1, 1, 1)))
+    boxes = orc.chop(lo, hi, 4 if "8boxes" in case else 8)
+    u, info = orc.solve(lo, hi, per, boxes, f, beta, rel_tol=1e-12)
+    assert info["status"] == 0
+    A = assemble(orc, shape, per, 1.0 / n, beta)
+    fv = f.ravel(order="F")
+    if per == (1, 1, 1):
+        ud = np.linalg.lstsq(A, fv, rcond=None)[0]  # minimum norm = mean-zero solution
+    else:
+        ud = np.linalg.solve(A, fv)
+    ud = ud.reshape(shape, order="F")
+    assert np.max(np.abs(u - ud)) <= 1e-9 * np.max(np.abs(ud))
+
+
+def contraction(hist):
+    h = np.asarray(hist)
+    return h[1:] / h[:-1]
+
+
+def test_contraction_frozen_and_h_independent(orc):
+    worst = []
+    for n in (16, 32, 64):
+        lo, hi = cube(n)
+        f = W.uniform_rhs((n, n, n), 2)
+        u, info = orc.solve(lo, hi, (0, 0, 0), orc.chop(lo, hi, 32), f, fixed_cycles=9)
+        rho = contraction(info["hist"])
+        assert rho.max() <= FROZEN_MAX_CONTRACTION
+        worst.append(rho[2:8].max())
+    assert max(worst) / min(worst) <= 1.5
+
+
+@pytest.mark.parametrize("periodic", [(0, 0, 0), (1, 1, 1)])
+def test_decomposition_independence_bitwise(orc, periodic):
+    n = 32
+    lo, hi = cube(n)
+    f = W.uniform_rhs((n, n, n), 9, mean_zero=periodic == (1, 1, 1))
+    ref = None
+    for mb in (32, 16, 8, 12):
+        boxes = orc.chop(lo, hi, mb)
+        u, info = orc.solve(lo, hi, periodic, boxes, f, fixed_cycles=4)
+        if ref is None:
+            ref, rinfo = u, info
+        else:
+            assert np.array_equal(u, ref), mb
+            assert info["hist"] == rinfo["hist"]
+
+
+@pytest.mark.parametrize("var", [False, True])
+def test_mixed_precision_reaches_fp64_tolerance(orc, var):
+    n = 32
+    lo, hi = cube(n)
+    shape = (n, n, n)
+    f = W.uniform_rhs(shape, 3)
+    beta = W.smooth_gaussian_beta(shape, 33) if var else None
+    boxes = orc.chop(lo, hi, 16)
+    u64, i64 = orc.solve(lo, hi, (0, 0, 0), boxes, f, beta)
+    u32, i32 = orc.solve(lo, hi, (0, 0, 0), boxes, f, beta, precision=1)
+    assert i32["status"] == 0 and i32["rel_inf"] <= 1e-10
+    r = f - orc.apply_op(lo, hi, (0, 0, 0), 1.0 / n, u32, beta)
+    assert np.max(np.abs(r)) <= 1e-10 * np.max(np.abs(f))
+    # error bound: kappa * 2 * tol with kappa_2 ~ 0.405 n^2 (Dirichlet)
+    kappa = 0.405 * n * n * (np.max(beta) / np.min(beta) if var else 1.0)
+    assert np.max(np.abs(u32 - u64)) <= kappa * 2e-10 * np.max(np.abs(u64))
+    assert i32["cycles"] <= i64["cycles"] + 4
+
+
+def test_bottom_cg_vs_dense(orc):
+    for shape, per in [((5, 5, 5), (0, 0, 0)), ((3, 3, 3), (1, 1, 1)), ((2, 2, 2), (0, 0, 0)), ((7, 5, 3), (1, 0, 1))]:
+        lo, hi = (0, 0, 0), tuple(x - 1 for x in shape)
+        f = W.uniform_rhs(shape, 4, mean_zero=(per == (1, 1, 1)))
+        for beta in (None, W.smooth_gaussian_beta(shape, 40, passes=0)):
+            u, it = orc.bottom(lo, hi, per, 0.5, f, beta)
+            A = assemble(orc, shape, per, 0.5, beta)
+            fv = f.ravel(order="F")
+            ud = np.linalg.lstsq(A, fv, rcond=None)[0] if per == (1, 1, 1) else np.linalg.solve(A, fv)
+            assert np.max(np.abs(u.ravel(order="F") - ud)) <= 1e-10 * np.max(np.abs(ud))
+            assert it <= 2 * int(np.prod(shape))  # exact arithmetic: <= N; rounding costs a few more
+
+
+def test_status_codes(orc):
+    n = 16
+    lo, hi = cube(n)
+    boxes = orc.chop(lo, hi, 16)
+    f = W.uniform_rhs((n, n, n), 1)
+    bad = f.copy()
+    bad[3, 4, 5] = np.nan
+    _, info = orc.solve(lo, hi, (0, 0, 0), boxes, bad)
+    assert info["status"] == -5
+    _, info = orc.solve(lo, hi, (0, 0, 0), boxes, f, max_cycles=1, rel_tol=1e-14)
+    assert info["status"] == -4 and info["cycles"] == 1
+    u, info = orc.solve(lo, hi, (0, 0, 0), boxes, np.zeros((n, n, n), order="F"))
+    assert info["status"] == 0 and info["cycles"] == 0 and not u.any()

@@ -1,0 +1,85 @@
+"""Seeded synthetic inputs shaped like the multigrid workloads.
+
+This module holds input generation only (random fields, manufactured
+right-hand sides, size draws): none of the solver's arithmetic.  Both the HIP
+path's tests/benchmark and the oracle consume it.  All draws use numpy's
+PCG64 ``default_rng(seed)``; fields are generated over the global domain in
+F-order (x fastest) so they do not depend on the box decomposition.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def cell_centres(n, lo=0, h=None):
+    h = 1.0 / n if h is None else h
+    return (np.arange(lo, lo + n) + 0.5) * h
+
+
+def sine_rhs(n, periodic=True):
+    """Manufactured RHS on the unit cube with cubic cells h = 1/n.
+
+    periodic : f = -3 (2 pi)^2 sin(2 pi x) sin(2 pi y) sin(2 pi z)
+    Dirichlet: f = -3 pi^2     sin(pi x)   sin(pi y)   sin(pi z)
+    Returns (f, s) with s the sine product at the cell centres.
+    """
+    x = cell_centres(n)
+    k = 2.0 * np.pi if periodic else np.pi
+    sx = np.sin(k * x)
+    s = sx[:, None, None] * sx[None, :, None] * sx[None, None, :]
+    return np.asfortranarray(-3.0 * k * k * s), np.asfortranarray(s)
+
+
+def uniform_rhs(shape, seed, mean_zero=False):
+    """i.i.d. uniform[-1, 1] over the global domain (F-order draw order)."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    f = rng.uniform(-1.0, 1.0, size=n).reshape(shape, order="F")
+    if mean_zero:
+        f = f - f.mean()
+    return np.asfortranarray(f)
+
+
+def smooth_gaussian_beta(shape, seed, passes=3):
+    """beta = exp(g): g0 ~ N(0,1) i.i.d., `passes` periodic 3x3x3 box-filter
+    passes, then standardised to mean 0 and (population) std 1."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    g = rng.standard_normal(n).reshape(shape, order="F")
+    for _ in range(passes):
+        acc = np.zeros_like(g)
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    acc += np.roll(g, (dx, dy, dz), axis=(0, 1, 2))
+        g = acc / 27.0
+    g = (g - g.mean()) / g.std()
+    return np.asfortranarray(np.exp(g))
+
+
+def dyadic_codes(shape, seed=0, scale=1.0 / 64):
+    """Exactly representable small codes: integers in [-64, 64] times `scale`
+    (a power of two), so sums of up to 64 of them with weights k/64 are exact
+    in FP64 and FP32."""
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(rng.integers(-64, 65, size=shape).astype(np.float64) * scale)
+
+
+def batch_edges(nprob, seed, choices=(32, 48, 64, 96, 128)):
+    """Cube edges of a batch of independent problems, uniform over choices."""
+    rng = np.random.default_rng(seed)
+    return [int(x) for x in rng.choice(np.asarray(choices), size=nprob)]
+
+
+def serving_trace(nreq, seed, rate=200.0, lo=32, hi=256, step=16):
+    """Open-loop request trace: exponential inter-arrivals (mean 1/rate s),
+    edge = clamp(step*round(exp(U(ln lo, ln hi))/step), lo, hi), tolerance
+    10^U(-10, -8), coefficient kind Bernoulli(1/2) (0 constant, 1 lognormal)."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=nreq))
+    e = np.exp(rng.uniform(np.log(lo), np.log(hi), size=nreq))
+    edges = np.clip(step * np.round(e / step), lo, hi).astype(int)
+    tols = 10.0 ** rng.uniform(-10.0, -8.0, size=nreq)
+    kinds = rng.integers(0, 2, size=nreq)
+    return [dict(t=float(t[q]), edge=int(edges[q]), tol=float(tols[q]), kind=int(kinds[q]), seed=5000 + q)
+            for q in range(nreq)]
