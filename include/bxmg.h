@@ -1,0 +1,220 @@
+/*
+ * bxmg -- block-structured geometric multigrid for one MI355X (gfx950).
+ *
+ * C ABI of the library libbxmg.so.  Plain pointers and sizes only; no C++ or
+ * PyTorch types cross this boundary, and no exception escapes it.
+ *
+ * Data model (paper, Section 2): a Box is an inclusive integer index range
+ * [lo, hi] (cell centred) in a global index space whose bounds may be
+ * negative; a BoxArray is a set of disjoint boxes inside a problem domain; a
+ * MultiFab holds, for every box, its data grown by `nghost` ghost cells, in
+ * Fortran order (x fastest, then y, z, component), as one device slab.
+ * Ghost cells covered by the valid region of some box (after periodic
+ * shifts) are filled by FillBoundary, the paper's cached ghost cell exchange
+ * (Section 2; fused pack/unpack, Section 3.5).  The multigrid solve is the
+ * cell-centred linear solver the paper lists among the framework's functions
+ * (Section 2), realised as a red-black Gauss-Seidel V-cycle.
+ *
+ * Conventions
+ *  - Every function returns bxmg_status (0 = BXMG_OK, < 0 = error) unless
+ *    stated otherwise; on error bxmg_last_error() gives a message (thread
+ *    local, valid until the next failing call of the same thread).
+ *  - Handles are owned by the caller and released with the matching
+ *    *_release / *_destroy call.  A MultiFab keeps its BoxArray alive.
+ *  - Device work is enqueued on the HIP stream passed in (NULL = the
+ *    context's stream).  bxmg_mlmg_solve returns after its work completed.
+ *  - A caller-provided device buffer stays owned by the caller and must
+ *    outlive the MultiFab built on it.
+ */
+#ifndef BXMG_H
+#define BXMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bxmg_ctx_s* bxmg_ctx;
+typedef struct bxmg_ba_s* bxmg_boxarray;
+typedef struct bxmg_mf_s* bxmg_multifab;
+
+typedef enum {
+    BXMG_OK = 0,
+    BXMG_EINVAL = -1,     /* invalid argument or geometry                     */
+    BXMG_ENOMEM = -2,     /* device or host allocation failed                 */
+    BXMG_EDEVICE = -3,    /* a HIP runtime call failed                        */
+    BXMG_ENOCONV = -4,    /* max_cycles reached before the tolerance           */
+    BXMG_ENONFINITE = -5, /* NaN or Inf seen in the residual or right-hand side */
+    BXMG_EBUSY = -6       /* not admitted now (batch memory budget)            */
+} bxmg_status;
+
+typedef enum { BXMG_F64 = 0, BXMG_F32 = 1 } bxmg_dtype;
+typedef enum { BXMG_PERIODIC = 0, BXMG_DIRICHLET0 = 1 } bxmg_bc;
+
+/* Library version (major*10000 + minor*100 + patch).  Never fails. */
+int bxmg_version(void);
+
+/* Message describing the last failure of the calling thread ("" if none). */
+const char* bxmg_last_error(void);
+
+/* ------------------------------------------------------------ context ---- */
+/* Binds a HIP device and a default stream (NULL = the null stream).  The
+ * context owns the multigrid hierarchies it builds (cached per BoxArray and
+ * mode) and frees them in bxmg_ctx_destroy, after its stream has drained. */
+bxmg_status bxmg_ctx_create(int device, void* hip_stream, bxmg_ctx* out);
+void bxmg_ctx_destroy(bxmg_ctx ctx);
+
+/* ----------------------------------------------------------- BoxArray ---- */
+/* Host-only calls: no device is needed.
+ *
+ * bxmg_define_boxarray: chops the domain [dom_lo, dom_hi] (inclusive) into
+ * boxes of edge <= max_box_size.  Per direction the blocking factor bf is the
+ * largest power of two dividing the domain edge (capped at max_box_size);
+ * pieces are floor(max_box_size/bf)*bf long, plus one remainder that is a
+ * multiple of bf (e.g. 48 -> 32+16, 240 -> 7x32+16).  bc[d] is a bxmg_bc per
+ * direction.  EINVAL for an empty domain or max_box_size < 1. */
+bxmg_status bxmg_define_boxarray(const int32_t dom_lo[3], const int32_t dom_hi[3], const int32_t bc[3],
+                                 int32_t max_box_size, bxmg_boxarray* out);
+
+/* Explicit box list: lohi is [nboxes][6] = {lo.x, lo.y, lo.z, hi.x, hi.y,
+ * hi.z}.  EINVAL if a box is empty, leaves the domain or overlaps another.
+ * The boxes need not cover the domain (FillBoundary then leaves the ghosts
+ * over the holes untouched); a solve requires full coverage. */
+bxmg_status bxmg_define_boxarray_list(const int32_t dom_lo[3], const int32_t dom_hi[3], const int32_t bc[3],
+                                      int32_t nboxes, const int32_t* lohi, bxmg_boxarray* out);
+
+/* Number of boxes and (if lohi_out != NULL, room for nboxes*6) their bounds. */
+bxmg_status bxmg_boxarray_get(bxmg_boxarray ba, int32_t* nboxes, int32_t* lohi_out);
+
+/* Multigrid level hierarchy the solver builds for this BoxArray: the domain
+ * halves while every domain edge is even and >= 4; boxes halve one by one
+ * while every box edge is even and >= 4 with an even lower corner, otherwise
+ * the coarser level is one box covering its domain.  Writes up to cap_levels
+ * levels: lev_nboxes[l], lev_dom[6*l..], and all levels' boxes concatenated
+ * in lev_lohi (room for cap_boxes boxes).  EINVAL if a cap is too small. */
+bxmg_status bxmg_boxarray_hierarchy(bxmg_boxarray ba, int32_t cap_levels, int32_t* nlevels, int32_t* lev_nboxes,
+                                    int32_t* lev_dom, int32_t cap_boxes, int32_t* lev_lohi);
+void bxmg_boxarray_release(bxmg_boxarray ba);
+
+/* ----------------------------------------------------------- MultiFab ---- */
+/* Bytes of device memory a MultiFab over ba needs: every box's grown data
+ * (ncomp * prod(n_d + 2*nghost) elements) starting on a 256-byte boundary. */
+size_t bxmg_multifab_bytes(bxmg_boxarray ba, int32_t ncomp, int32_t nghost, bxmg_dtype dtype);
+
+/* Allocates (device_buf == NULL: from the library, freed on release) or
+ * adopts (device_buf != NULL: caller-owned device memory of at least
+ * bxmg_multifab_bytes bytes, 256-byte aligned) a MultiFab.  Contents are not
+ * initialised.  EINVAL for ncomp < 1, nghost < 0 or a misaligned buffer. */
+bxmg_status bxmg_alloc_multifab(bxmg_ctx ctx, bxmg_boxarray ba, int32_t ncomp, int32_t nghost, bxmg_dtype dtype,
+                                void* device_buf, bxmg_multifab* out);
+
+/* Zero-copy view of box `box` (paper, Section 4.1): device pointer to the
+ * first grown cell, grown bounds lo/hi (global indices) and element strides
+ * {x, y, z, component}.  EINVAL for a box index out of range. */
+bxmg_status bxmg_multifab_box_view(bxmg_multifab mf, int32_t box, void** dptr, int32_t lo[3], int32_t hi[3],
+                                   int64_t strides[4]);
+
+/* Slab base pointer and size in bytes, plus ncomp / nghost / dtype. */
+bxmg_status bxmg_multifab_info(bxmg_multifab mf, void** base, size_t* bytes, int32_t* ncomp, int32_t* nghost,
+                               int32_t* dtype);
+
+/* Releases the handle.  Library-owned memory is freed after the work already
+ * queued on the context's stream has completed (stream-ordered free). */
+void bxmg_multifab_release(bxmg_multifab mf);
+
+/* FillBoundary (paper, Section 2 and Section 3.5): for components
+ * [scomp, scomp+ncomp), every ghost cell that -- after wrapping periodic
+ * directions -- is a valid cell of some box takes that cell's value; faces,
+ * edges and corners (cross == 0) or faces only (cross != 0).  Ghosts outside
+ * a non-periodic domain face, and ghosts over uncovered cells, are left
+ * untouched.  One fused launch over a cached copy plan.  Asynchronous on
+ * `hip_stream`. */
+bxmg_status bxmg_fill_boundary(bxmg_multifab mf, int32_t scomp, int32_t ncomp, int32_t cross, void* hip_stream);
+
+/* Physical boundary ghosts (homogeneous Dirichlet): every ghost cell outside
+ * a non-periodic domain face takes s * (mirror cell), the mirror reflected
+ * across every such face (index -1-t -> t below, n+t -> n-1-t above); s = -1
+ * per reflected direction when odd != 0, s = +1 otherwise.  Reads the box's
+ * own grown data, so call it after bxmg_fill_boundary.  Asynchronous. */
+bxmg_status bxmg_apply_domain_bc(bxmg_multifab mf, int32_t scomp, int32_t ncomp, int32_t odd, void* hip_stream);
+
+/* -------------------------------------------------------------- solve ---- */
+typedef struct {
+    int32_t nu1, nu2;       /* pre/post red-black sweeps per level (2, 2)            */
+    int32_t max_cycles;     /* cap on V-cycles (200)                                  */
+    int32_t precision;      /* 0: FP64 V-cycle; 1: FP32 V-cycle inside FP64 refinement */
+    int32_t prolong;        /* 2: trilinear (default); 1: piecewise constant          */
+    int32_t fixed_cycles;   /* > 0: run exactly this many cycles, no tolerance stop   */
+    double rel_tol;         /* stop when ||f - L u||_inf <= rel_tol * ||f||_inf        */
+    double abs_tol;         /*  ... or when ||f - L u||_inf <= abs_tol                 */
+    double dx;              /* cell width h (cubic cells); <= 0: 1 / (x-edge of domain) */
+    double bottom_rtol;     /* bottom CG relative L2 tolerance (1e-12)                 */
+} bxmg_solve_params;
+
+typedef struct {
+    int32_t status;         /* bxmg_status of the solve                               */
+    int32_t cycles;         /* V-cycles (or refinement steps) performed               */
+    int32_t levels;         /* multigrid levels                                       */
+    int32_t nhist;          /* entries in hist / hist_l2                              */
+    double rel_resid_inf;   /* final ||r||_inf / ||f||_inf                             */
+    double resid_l2;        /* final ||r||_2                                          */
+    double f_inf;           /* ||f||_inf                                              */
+    double seconds;         /* wall time of the solve                                 */
+    double hist[256];       /* ||r_k||_inf / ||f||_inf before cycle k                  */
+    double hist_l2[256];    /* ||r_k||_2                                              */
+} bxmg_solve_info;
+
+/* Fills *p with the defaults above. */
+void bxmg_solve_params_default(bxmg_solve_params* p);
+
+/* Solves div(beta grad phi) = rhs on the BoxArray's domain (7-point,
+ * cell-centred, h = dx; beta == NULL: beta = 1) with homogeneous Dirichlet
+ * (odd-reflection ghosts) or periodic boundaries as the BoxArray's bc says.
+ * phi, rhs and beta (if any) must be FP64 MultiFabs over the same BoxArray
+ * with nghost >= 1; component 0 is used.  phi's valid cells hold the initial
+ * guess on entry (the solver starts from them) and the solution on return;
+ * a fully periodic problem returns the mean-zero solution and needs a
+ * mean-zero rhs.  The solve is synchronous on the context's stream.
+ * Returns info->status: OK, ENOCONV (info filled), ENONFINITE, EINVAL (bad
+ * arguments; bottom level above 4096 cells), ENOMEM or EDEVICE. */
+bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi, bxmg_multifab rhs,
+                            bxmg_multifab beta, bxmg_solve_info* info);
+
+/* ------------------------------------------------- single level stages --- */
+/* The solver's own stage kernels applied once to caller MultiFabs (FP64,
+ * nghost >= 1, component 0), each bracketed by the same layout conversion
+ * the solver performs on entry and exit.  Synchronous.  h: cell width of
+ * the level.  beta may be NULL (constant coefficient).
+ *
+ * bxmg_gs_colour: ghost exchange + physical ghosts of the other colour, then
+ * one red-black colour (colour 0: (i+j+k) even) of Gauss-Seidel,
+ * u = (sum_faces beta u_nb - h^2 f) / sum_faces beta, on phi's valid cells. */
+bxmg_status bxmg_gs_colour(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab rhs, bxmg_multifab beta, double h,
+                           int32_t colour);
+
+/* r = rhs - L phi on valid cells (ghost exchange + physical ghosts first);
+ * norms[0] = max |r|, norms[1] = sum r^2 (non-finite: norms[0] = NaN). */
+bxmg_status bxmg_residual(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab rhs, bxmg_multifab beta, double h,
+                          bxmg_multifab r, double norms[2]);
+
+/* coarse(I) = (1/8) sum of the 8 children of I; the coarse BoxArray must be
+ * the next level of the fine one's hierarchy (or its boxes' coarsening). */
+bxmg_status bxmg_restrict(bxmg_ctx ctx, bxmg_multifab fine, bxmg_multifab coarse);
+
+/* fine += P coarse after ghost exchange + physical ghosts of coarse;
+ * order 2: trilinear (27/9/3/1 over 64), order 1: piecewise constant. */
+bxmg_status bxmg_prolong_add(bxmg_ctx ctx, bxmg_multifab coarse, bxmg_multifab fine, int32_t order);
+
+/* FP64 conjugate-gradient bottom solve on a BoxArray of at most 4096 cells:
+ * L phi = rhs from phi = 0, stop at relative L2 residual <= rtol or 4 * cells
+ * iterations (fully periodic: rhs projected to mean zero, mean-zero result).
+ * *iters receives the iteration count. */
+bxmg_status bxmg_bottom_solve(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab rhs, bxmg_multifab beta, double h,
+                              double rtol, int32_t* iters);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BXMG_H */

@@ -1,0 +1,915 @@
+// HIP kernels of the multigrid path, written for gfx950 (wave64, 256 CUs).
+//
+// Every stage is one fused launch over all boxes of a level (the fused
+// multi-box launch of the paper, Section 3.2): a thread's global index is
+// mapped to (box, cell) through a flattened work list, so 512 boxes of 32^3
+// run as one grid, like one 256^3 box.  The level data uses a colour-split
+// ("red-black") layout: the cells of one colour of a box row are contiguous,
+// so a half-sweep streams only the colour it reads (the other one) plus the
+// right-hand side of the colour it writes -- 1.5 arrays per half-sweep.
+// All stages are bandwidth-bound (<= 0.5 flop per byte): no matrix cores.
+//
+// Floating point: built with -ffp-contract=off; every expression below
+// fixes its operation order, so results are reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "bxmg_internal.h"
+
+namespace bxmg {
+
+// ----------------------------------------------------------------- helpers
+__device__ __forceinline__ int find_work(const WorkBox* __restrict__ w, int n, long long g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (w[mid].cstart <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int find_tag(const Tag* __restrict__ t, int n, long long g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (t[mid].prefix <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ long long rb_row(const RBox& b, int c, int j, int k) {
+    return b.base + (long long)c * b.cstride + ((long long)(k - b.glo[2]) * b.G[1] + (j - b.glo[1])) * b.H;
+}
+
+__device__ __forceinline__ long long rb_idx(const RBox& b, int i, int j, int k) {
+    return rb_row(b, (i + j + k) & 1, j, k) + ((i - b.glo[0]) >> 1);
+}
+
+__device__ __forceinline__ long long fab_idx(const FBox& b, int i, int j, int k) {
+    return b.base + (long long)(i - b.glo[0]) + (long long)b.G[0] * ((long long)(j - b.glo[1]) + (long long)b.G[1] * (k - b.glo[2]));
+}
+
+template <class T>
+__device__ __forceinline__ T harm(T a, T b) {
+    return (a * b) * T(2) / (a + b);
+}
+
+// Colour-cell decode: g -> (box, i, j, k) of colour c; false if padding.
+struct Cell {
+    int box, i, j, k;
+};
+
+__device__ __forceinline__ bool decode_colour(const WorkBox* __restrict__ work, int nwork, const RBox* __restrict__ boxes,
+                                              long long g, int c, Cell& out, RBox& B) {
+    const int w = find_work(work, nwork, g);
+    const WorkBox wb = work[w];
+    const long long loc = g - wb.cstart;
+    const int t = (int)(loc % wb.tn);
+    const long long rem = loc / wb.tn;
+    B = boxes[wb.box];
+    const int j = B.lo[1] + (int)(rem % wb.ny);
+    const int k = B.lo[2] + (int)(rem / wb.ny);
+    const int i = B.lo[0] + 2 * t + ((c - B.lo[0] - j - k) & 1);
+    out = Cell{wb.box, i, j, k};
+    return i <= B.hi[0];
+}
+
+// Coarse-cell decode for the transfer kernels: g -> (fine box, coarse cell).
+__device__ __forceinline__ void decode_coarse(const WorkBox* __restrict__ work, int nwork, long long g, WorkBox& wb,
+                                              int& I, int& J, int& K) {
+    const int w = find_work(work, nwork, g);
+    wb = work[w];
+    const long long loc = g - wb.cstart;
+    I = (int)(loc % wb.tn);
+    const long long rem = loc / wb.tn;
+    J = (int)(rem % wb.ny);
+    K = (int)(rem / wb.ny);
+}
+
+// Stencil sums of one cell: su = sum_faces beta*u_nb, sb = sum_faces beta,
+// in the fixed order ((x- + x+) + (y- + y+)) + (z- + z+).
+//   MODE 0: constant coefficient; 1: level 0, faces = harmonic means of the
+//   cell beta (same layout as u); 2: coarse level, global face arrays.
+template <class T, int MODE>
+__device__ __forceinline__ void stencil(const T* __restrict__ u, const T* __restrict__ beta, const FaceArrays<T>& fa,
+                                        const RBox& B, int i, int j, int k, T& su, T& sb, T& uc) {
+    const int c = (i + j + k) & 1;
+    const long long rc = rb_row(B, c, j, k);
+    const long long ro = rb_row(B, c ^ 1, j, k);
+    const long long Hy = B.H, Hz = (long long)B.H * B.G[1];
+    const int m = (i - B.glo[0]) >> 1;
+    const int mxm = (i - 1 - B.glo[0]) >> 1, mxp = (i + 1 - B.glo[0]) >> 1;
+    const T uxm = u[ro + mxm], uxp = u[ro + mxp];
+    const T uym = u[ro - Hy + m], uyp = u[ro + Hy + m];
+    const T uzm = u[ro - Hz + m], uzp = u[ro + Hz + m];
+    uc = u[rc + m];
+    if constexpr (MODE == 0) {
+        su = ((uxm + uxp) + (uym + uyp)) + (uzm + uzp);
+        sb = T(6);
+    } else {
+        T bxm, bxp, bym, byp, bzm, bzp;
+        if constexpr (MODE == 1) {
+            const T bc = beta[rc + m];
+            bxm = harm(beta[ro + mxm], bc);
+            bxp = harm(bc, beta[ro + mxp]);
+            bym = harm(beta[ro - Hy + m], bc);
+            byp = harm(bc, beta[ro + Hy + m]);
+            bzm = harm(beta[ro - Hz + m], bc);
+            bzp = harm(bc, beta[ro + Hz + m]);
+        } else {
+            const int x = i - fa.dlo[0], y = j - fa.dlo[1], z = k - fa.dlo[2];
+            const int nx = fa.n[0], ny = fa.n[1];
+            const long long ix = (long long)x + (long long)(nx + 1) * ((long long)y + (long long)ny * z);
+            const long long iy = (long long)x + (long long)nx * ((long long)y + (long long)(ny + 1) * z);
+            const long long iz = (long long)x + (long long)nx * ((long long)y + (long long)ny * z);
+            bxm = fa.c[0][ix];
+            bxp = fa.c[0][ix + 1];
+            bym = fa.c[1][iy];
+            byp = fa.c[1][iy + nx];
+            bzm = fa.c[2][iz];
+            bzp = fa.c[2][iz + (long long)nx * ny];
+        }
+        sb = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
+        su = ((bxm * uxm + bxp * uxp) + (bym * uym + byp * uyp)) + (bzm * uzm + bzp * uzp);
+    }
+}
+
+// -------------------------------------------------------------- ghost fill
+// One thread per destination cell of the flattened tag list.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fill_rb(T* __restrict__ data, const RBox* __restrict__ boxes,
+                                                   const Tag* __restrict__ tags, int ntags, long long ncells, int cmask) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    const Tag t = tags[find_tag(tags, ntags, g)];
+    const long long loc = g - t.prefix;
+    const int x = (int)(loc % t.n[0]);
+    const int y = (int)((loc / t.n[0]) % t.n[1]);
+    const int z = (int)(loc / ((long long)t.n[0] * t.n[1]));
+    const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
+    if (!((cmask >> ((di + dj + dk) & 1)) & 1)) return;
+    const int si = t.sgn[0] * di + t.soff[0], sj = t.sgn[1] * dj + t.soff[1], sk = t.sgn[2] * dk + t.soff[2];
+    T v = data[rb_idx(boxes[t.sbox], si, sj, sk)];
+    if (t.neg) v = -v;
+    data[rb_idx(boxes[t.dbox], di, dj, dk)] = v;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fill_fab(T* __restrict__ data, const FBox* __restrict__ boxes,
+                                                    const Tag* __restrict__ tags, int ntags, long long ncells,
+                                                    int comp0, int ncomp) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    const Tag t = tags[find_tag(tags, ntags, g)];
+    const long long loc = g - t.prefix;
+    const int x = (int)(loc % t.n[0]);
+    const int y = (int)((loc / t.n[0]) % t.n[1]);
+    const int z = (int)(loc / ((long long)t.n[0] * t.n[1]));
+    const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
+    const int si = t.sgn[0] * di + t.soff[0], sj = t.sgn[1] * dj + t.soff[1], sk = t.sgn[2] * dk + t.soff[2];
+    const FBox sb = boxes[t.sbox], db = boxes[t.dbox];
+    const long long s0 = fab_idx(sb, si, sj, sk), d0 = fab_idx(db, di, dj, dk);
+    for (int n = comp0; n < comp0 + ncomp; ++n) {
+        T v = data[s0 + n * sb.cs];
+        if (t.neg) v = -v;
+        data[d0 + n * db.cs] = v;
+    }
+}
+
+// ---------------------------------------------------- red-black smoothing
+// One colour: u_c = (su - h^2 f) / sb.  Reads only the other colour of u.
+template <class T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_gs(T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ beta,
+                                              FaceArrays<T> fa, const RBox* __restrict__ boxes,
+                                              const WorkBox* __restrict__ work, int nwork, long long ncells, T h2,
+                                              int colour) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    Cell q;
+    RBox B;
+    if (!decode_colour(work, nwork, boxes, g, colour, q, B)) return;
+    T su, sb, uc;
+    stencil<T, MODE>(u, beta, fa, B, q.i, q.j, q.k, su, sb, uc);
+    const long long idx = rb_idx(B, q.i, q.j, q.k);
+    u[idx] = (su - h2 * f[idx]) / sb;
+}
+
+// ---------------------------------------------------------------- residual
+// Block reduction of (max |r|, sum r^2, non-finite count) with a fixed tree.
+__device__ __forceinline__ void block_reduce3(double& mx, double& s2, double& bad, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const double a = __shfl_xor(mx, o), b = __shfl_xor(s2, o), c = __shfl_xor(bad, o);
+        mx = fmax(mx, a);
+        s2 = s2 + b;
+        bad = bad + c;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { sh[3 * wid] = mx; sh[3 * wid + 1] = s2; sh[3 * wid + 2] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        mx = sh[0]; s2 = sh[1]; bad = sh[2];
+        for (int w = 1; w < nw; ++w) { mx = fmax(mx, sh[3 * w]); s2 = s2 + sh[3 * w + 1]; bad = bad + sh[3 * w + 2]; }
+    }
+}
+
+__device__ __forceinline__ void acc_norm(double rv, double& mx, double& s2, double& bad) {
+    const double a = fabs(rv);
+    if (!(a <= 1.7976931348623157e308)) bad += 1.0;  // NaN or Inf
+    else mx = fmax(mx, a);
+    s2 = s2 + rv * rv;
+}
+
+// r = f - (su - sb u) / h^2 on both colours; optional store of r (same type
+// and layout) or of float(r) (mixed precision); fused norms per block.
+template <class T, int MODE, class R>
+__global__ void __launch_bounds__(kBlock) k_resid(const T* __restrict__ u, const T* __restrict__ f,
+                                                 const T* __restrict__ beta, FaceArrays<T> fa,
+                                                 const RBox* __restrict__ boxes, const WorkBox* __restrict__ work,
+                                                 int nwork, long long ncells, T ih2, R* __restrict__ r,
+                                                 double* __restrict__ partials) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < ncells; g += stride) {
+        for (int c = 0; c < 2; ++c) {
+            Cell q;
+            RBox B;
+            if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
+            T su, sb, uc;
+            stencil<T, MODE>(u, beta, fa, B, q.i, q.j, q.k, su, sb, uc);
+            const long long idx = rb_idx(B, q.i, q.j, q.k);
+            const T rv = f[idx] - (su - sb * uc) * ih2;
+            if (r) r[idx] = (R)rv;
+            acc_norm((double)rv, mx, s2, bad);
+        }
+    }
+    block_reduce3(mx, s2, bad, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = mx;
+        partials[3 * blockIdx.x + 1] = s2;
+        partials[3 * blockIdx.x + 2] = bad;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_norm_final(const double* __restrict__ partials, int n,
+                                                      double* __restrict__ out) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        mx = fmax(mx, partials[3 * q]);
+        s2 = s2 + partials[3 * q + 1];
+        bad = bad + partials[3 * q + 2];
+    }
+    block_reduce3(mx, s2, bad, sh);
+    if (threadIdx.x == 0) { out[0] = mx; out[1] = s2; out[2] = bad; }
+}
+
+// ------------------------------------------------------ restriction (fused)
+// One thread per coarse cell: the residual at its 8 children, averaged
+// as ((r000 + r100) + (r010 + r110)) + ((r001 + r101) + (r011 + r111)), * 1/8.
+template <class T, int MODE>
+__device__ __forceinline__ T resid_at(const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ beta,
+                                      const FaceArrays<T>& fa, const RBox& B, int i, int j, int k, T ih2) {
+    T su, sb, uc;
+    stencil<T, MODE>(u, beta, fa, B, i, j, k, su, sb, uc);
+    return f[rb_idx(B, i, j, k)] - (su - sb * uc) * ih2;
+}
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_resid_restrict(const T* __restrict__ u, const T* __restrict__ f,
+                                                          const T* __restrict__ beta, FaceArrays<T> fa,
+                                                          const RBox* __restrict__ fboxes,
+                                                          const RBox* __restrict__ cboxes,
+                                                          const WorkBox* __restrict__ work, int nwork,
+                                                          long long ncells, T ih2, T* __restrict__ fc) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    WorkBox wb;
+    int I, J, K;
+    decode_coarse(work, nwork, g, wb, I, J, K);
+    const RBox B = fboxes[wb.box];
+    I += B.lo[0] >> 1; J += B.lo[1] >> 1; K += B.lo[2] >> 1;
+    const int i = 2 * I, j = 2 * J, k = 2 * K;
+    const T r000 = resid_at<T, MODE>(u, f, beta, fa, B, i, j, k, ih2);
+    const T r100 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j, k, ih2);
+    const T r010 = resid_at<T, MODE>(u, f, beta, fa, B, i, j + 1, k, ih2);
+    const T r110 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j + 1, k, ih2);
+    const T r001 = resid_at<T, MODE>(u, f, beta, fa, B, i, j, k + 1, ih2);
+    const T r101 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j, k + 1, ih2);
+    const T r011 = resid_at<T, MODE>(u, f, beta, fa, B, i, j + 1, k + 1, ih2);
+    const T r111 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j + 1, k + 1, ih2);
+    const T s = ((r000 + r100) + (r010 + r110)) + ((r001 + r101) + (r011 + r111));
+    fc[rb_idx(cboxes[wb.cbox], I, J, K)] = s * T(0.125);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_restrict_plain(const T* __restrict__ rf, T* __restrict__ fc,
+                                                          const RBox* __restrict__ fboxes,
+                                                          const RBox* __restrict__ cboxes,
+                                                          const WorkBox* __restrict__ work, int nwork,
+                                                          long long ncells) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    WorkBox wb;
+    int I, J, K;
+    decode_coarse(work, nwork, g, wb, I, J, K);
+    const RBox B = fboxes[wb.box];
+    I += B.lo[0] >> 1; J += B.lo[1] >> 1; K += B.lo[2] >> 1;
+    const int i = 2 * I, j = 2 * J, k = 2 * K;
+    const T s = ((rf[rb_idx(B, i, j, k)] + rf[rb_idx(B, i + 1, j, k)]) +
+                 (rf[rb_idx(B, i, j + 1, k)] + rf[rb_idx(B, i + 1, j + 1, k)])) +
+                ((rf[rb_idx(B, i, j, k + 1)] + rf[rb_idx(B, i + 1, j, k + 1)]) +
+                 (rf[rb_idx(B, i, j + 1, k + 1)] + rf[rb_idx(B, i + 1, j + 1, k + 1)]));
+    fc[rb_idx(cboxes[wb.cbox], I, J, K)] = s * T(0.125);
+}
+
+// ---------------------------------------------------- prolongation + add
+// One thread per coarse cell: its 8 children get
+//   e = (((27 c000 + 9 ((c100 + c010) + c001)) + 3 ((c110 + c101) + c011)) + c111) / 64
+// where c_abc is the coarse value at the parent shifted by a*sx, b*sy, c*sz
+// and s = +1 for an odd child index, -1 for an even one (trilinear), or
+// e = c000 (piecewise constant).  Coarse ghosts must be current.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_prolong(const T* __restrict__ ec, T* __restrict__ uf,
+                                                   const RBox* __restrict__ fboxes, const RBox* __restrict__ cboxes,
+                                                   const WorkBox* __restrict__ work, int nwork, long long ncells,
+                                                   int order) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    WorkBox wb;
+    int I, J, K;
+    decode_coarse(work, nwork, g, wb, I, J, K);
+    const RBox B = fboxes[wb.box];
+    const RBox C = cboxes[wb.cbox];
+    I += B.lo[0] >> 1; J += B.lo[1] >> 1; K += B.lo[2] >> 1;
+    T v[3][3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) v[c][b][a] = (order == 1 && (a != 1 || b != 1 || c != 1)) ? T(0) : ec[rb_idx(C, I + a - 1, J + b - 1, K + c - 1)];
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                const int sx = cx ? 2 : 0, sy = cy ? 2 : 0, sz = cz ? 2 : 0;  // neighbour slot: parent 1 +- 1
+                T e;
+                if (order == 1) {
+                    e = v[1][1][1];
+                } else {
+                    const T c000 = v[1][1][1];
+                    const T c100 = v[1][1][sx], c010 = v[1][sy][1], c001 = v[sz][1][1];
+                    const T c110 = v[1][sy][sx], c101 = v[sz][1][sx], c011 = v[sz][sy][1];
+                    const T c111 = v[sz][sy][sx];
+                    e = (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
+                        T(0.015625);
+                }
+                const long long idx = rb_idx(B, 2 * I + cx, 2 * J + cy, 2 * K + cz);
+                uf[idx] = uf[idx] + e;
+            }
+}
+
+// -------------------------------------------------------------- utilities
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_zero(T* __restrict__ p, long long n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = T(0);
+}
+
+__global__ void __launch_bounds__(kBlock) k_cast_f32(const double* __restrict__ s, float* __restrict__ d, long long n) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) d[q] = (float)s[q];
+}
+
+// F-order FP64 caller MultiFab (component 0) -> RB level, valid cells.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fab_to_rb(const double* __restrict__ fab, const FBox* __restrict__ fb,
+                                                     T* __restrict__ rb, const RBox* __restrict__ boxes,
+                                                     const WorkBox* __restrict__ work, int nwork, long long ncells) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    for (int c = 0; c < 2; ++c) {
+        Cell q;
+        RBox B;
+        if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
+        rb[rb_idx(B, q.i, q.j, q.k)] = (T)fab[fab_idx(fb[q.box], q.i, q.j, q.k)];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_rb_to_fab(const double* __restrict__ rb, const RBox* __restrict__ boxes,
+                                                     double* __restrict__ fab, const FBox* __restrict__ fb,
+                                                     const WorkBox* __restrict__ work, int nwork, long long ncells) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    for (int c = 0; c < 2; ++c) {
+        Cell q;
+        RBox B;
+        if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
+        fab[fab_idx(fb[q.box], q.i, q.j, q.k)] = rb[rb_idx(B, q.i, q.j, q.k)];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_add_f32(double* __restrict__ u, const float* __restrict__ e,
+                                                   const RBox* __restrict__ boxes, const WorkBox* __restrict__ work,
+                                                   int nwork, long long ncells) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    for (int c = 0; c < 2; ++c) {
+        Cell q;
+        RBox B;
+        if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
+        const long long idx = rb_idx(B, q.i, q.j, q.k);
+        u[idx] = u[idx] + (double)e[idx];
+    }
+}
+
+// Norms of a field's valid cells (the right-hand side's max norm).
+__global__ void __launch_bounds__(kBlock) k_field_norm(const double* __restrict__ x, const RBox* __restrict__ boxes,
+                                                      const WorkBox* __restrict__ work, int nwork, long long ncells,
+                                                      double* __restrict__ partials) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < ncells; g += stride)
+        for (int c = 0; c < 2; ++c) {
+            Cell q;
+            RBox B;
+            if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
+            acc_norm(x[rb_idx(B, q.i, q.j, q.k)], mx, s2, bad);
+        }
+    block_reduce3(mx, s2, bad, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = mx;
+        partials[3 * blockIdx.x + 1] = s2;
+        partials[3 * blockIdx.x + 2] = bad;
+    }
+}
+
+// Sum of valid cells (periodic mean projection), then subtraction.
+__global__ void __launch_bounds__(kBlock) k_sum_valid(const double* __restrict__ u, const RBox* __restrict__ boxes,
+                                                     const WorkBox* __restrict__ work, int nwork, long long ncells,
+                                                     double* __restrict__ partials) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    double mx = 0.0, s = 0.0, cnt = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < ncells; g += stride)
+        for (int c = 0; c < 2; ++c) {
+            Cell q;
+            RBox B;
+            if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
+            s = s + u[rb_idx(B, q.i, q.j, q.k)];
+            cnt += 1.0;
+        }
+    block_reduce3(mx, s, cnt, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = 0.0;
+        partials[3 * blockIdx.x + 1] = s;
+        partials[3 * blockIdx.x + 2] = cnt;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sub_mean(double* __restrict__ u, const double* __restrict__ tot,
+                                                    const RBox* __restrict__ boxes, const WorkBox* __restrict__ work,
+                                                    int nwork, long long ncells) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    const double m = tot[1] / tot[2];
+    for (int c = 0; c < 2; ++c) {
+        Cell q;
+        RBox B;
+        if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
+        const long long idx = rb_idx(B, q.i, q.j, q.k);
+        u[idx] = u[idx] - m;
+    }
+}
+
+// ------------------------------------------------------ coefficient setup
+// Level-1 faces from the level-0 cell beta (ghosts filled by the exchange
+// and the even reflection): each fine face is the harmonic mean of its two
+// cells, each coarse face the mean of its 4 fine faces,
+//   ((a(t1,t2) + a(t1+1,t2)) + (a(t1,t2+1) + a(t1+1,t2+1))) * 1/4.
+// Work: per fine box, coarse faces of direction d anchored in it.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_faces_from_cells(const T* __restrict__ beta,
+                                                            const RBox* __restrict__ fboxes,
+                                                            const WorkBox* __restrict__ work, int nwork,
+                                                            long long ncells, int d, FaceArrays<T> out,
+                                                            T* __restrict__ dst) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    WorkBox wb;
+    int I, J, K;
+    decode_coarse(work, nwork, g, wb, I, J, K);
+    const RBox B = fboxes[wb.box];
+    I += B.lo[0] >> 1; J += B.lo[1] >> 1; K += B.lo[2] >> 1;
+    const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    int f0[3] = {2 * I, 2 * J, 2 * K};
+    T a[2][2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            int cc[3] = {f0[0], f0[1], f0[2]};
+            cc[t1] += p;
+            cc[t2] += q;
+            int lc[3] = {cc[0], cc[1], cc[2]};
+            lc[d] -= 1;
+            a[q][p] = harm(beta[rb_idx(B, lc[0], lc[1], lc[2])], beta[rb_idx(B, cc[0], cc[1], cc[2])]);
+        }
+    const T v = ((a[0][0] + a[0][1]) + (a[1][0] + a[1][1])) * T(0.25);
+    const int x = I - out.dlo[0], y = J - out.dlo[1], z = K - out.dlo[2];
+    const int nx = out.n[0] + (d == 0), ny = out.n[1] + (d == 1);
+    dst[(long long)x + (long long)nx * ((long long)y + (long long)ny * z)] = v;
+}
+
+// Level l+1 faces from level l faces (global arrays).
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_faces_coarsen(FaceArrays<T> fine, FaceArrays<T> coarse, int d,
+                                                         T* __restrict__ dst) {
+    const int nxc = coarse.n[0] + (d == 0), nyc = coarse.n[1] + (d == 1), nzc = coarse.n[2] + (d == 2);
+    const long long total = (long long)nxc * nyc * nzc;
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const int x = (int)(g % nxc), y = (int)((g / nxc) % nyc), z = (int)(g / ((long long)nxc * nyc));
+    const int nxf = fine.n[0] + (d == 0), nyf = fine.n[1] + (d == 1);
+    const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    const int f0[3] = {2 * x, 2 * y, 2 * z};
+    T a[2][2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            int cc[3] = {f0[0], f0[1], f0[2]};
+            cc[t1] += p;
+            cc[t2] += q;
+            a[q][p] = fine.c[d][(long long)cc[0] + (long long)nxf * ((long long)cc[1] + (long long)nyf * cc[2])];
+        }
+    dst[g] = ((a[0][0] + a[0][1]) + (a[1][0] + a[1][1])) * T(0.25);
+}
+
+// ---------------------------------------------------------------- bottom
+// FP64 conjugate gradients on the coarsest level by one workgroup, vectors
+// in LDS over the level domain (natural order, p with a ghost layer).
+constexpr int kBotThreads = 1024;
+constexpr int kBotGrown = 6144;
+
+struct BottomGeom {
+    int dlo[3], n[3];
+    int per[3];
+    int nboxes;
+};
+
+__device__ __forceinline__ double bot_reduce(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = sh[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s = s + sh[w];
+        sh[32] = s;
+    }
+    __syncthreads();
+    return sh[32];
+}
+
+template <class T, bool VAR>
+__global__ void __launch_bounds__(kBotThreads) k_bottom(T* __restrict__ u, const T* __restrict__ f, FaceArrays<T> fa,
+                                                       const RBox* __restrict__ boxes, BottomGeom G, double h,
+                                                       double rtol, int* __restrict__ iters_out) {
+    __shared__ double p[kBotGrown];
+    __shared__ double x[kMaxBottomCells], r[kMaxBottomCells], q[kMaxBottomCells];
+    __shared__ double sh[40];
+    const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+    const int N = nx * ny * nz;
+    const int gx = nx + 2, gy = ny + 2;
+    const double ih2 = 1.0 / (h * h);
+    auto pidx = [&](int a, int b, int c) { return (a + 1) + gx * ((b + 1) + gy * (c + 1)); };
+    // gather rhs
+    for (int bi = 0; bi < G.nboxes; ++bi) {
+        const RBox B = boxes[bi];
+        const int bx = B.hi[0] - B.lo[0] + 1, by = B.hi[1] - B.lo[1] + 1, bz = B.hi[2] - B.lo[2] + 1;
+        for (int qq = threadIdx.x; qq < bx * by * bz; qq += blockDim.x) {
+            const int i = B.lo[0] + qq % bx, j = B.lo[1] + (qq / bx) % by, k = B.lo[2] + qq / (bx * by);
+            const int n = (i - G.dlo[0]) + nx * ((j - G.dlo[1]) + ny * (k - G.dlo[2]));
+            r[n] = (double)f[rb_idx(B, i, j, k)];
+        }
+    }
+    __syncthreads();
+    const bool sing = G.per[0] && G.per[1] && G.per[2];
+    if (sing) {
+        double s = 0.0;
+        for (int n = threadIdx.x; n < N; n += blockDim.x) s = s + r[n];
+        const double mean = bot_reduce(s, sh) / (double)N;
+        for (int n = threadIdx.x; n < N; n += blockDim.x) r[n] = r[n] - mean;
+        __syncthreads();
+    }
+    double rs = 0.0;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        x[n] = 0.0;
+        const int a = n % nx, b = (n / nx) % ny, c = n / (nx * ny);
+        p[pidx(a, b, c)] = r[n];
+        rs = rs + r[n] * r[n];
+    }
+    rs = bot_reduce(rs, sh);
+    const double rs0 = rs;
+    int it = 0;
+    if (rs0 != 0.0) {
+        const int maxit = 4 * N;
+        for (it = 0; it < maxit;) {
+            // ghosts of p: face ghosts only (7-point stencil)
+            const int nfx = ny * nz, nfy = nx * nz, nfz = nx * ny;
+            for (int t = threadIdx.x; t < 2 * (nfx + nfy + nfz); t += blockDim.x) {
+                int d, side, a, b;
+                int tt = t;
+                if (tt < 2 * nfx) { d = 0; side = tt / nfx; tt %= nfx; a = tt % ny; b = tt / ny; }
+                else if ((tt -= 2 * nfx) < 2 * nfy) { d = 1; side = tt / nfy; tt %= nfy; a = tt % nx; b = tt / nx; }
+                else { tt -= 2 * nfy; d = 2; side = tt / nfz; tt %= nfz; a = tt % nx; b = tt / nx; }
+                int gc[3], sc[3];
+                if (d == 0) { gc[1] = sc[1] = a; gc[2] = sc[2] = b; }
+                else if (d == 1) { gc[0] = sc[0] = a; gc[2] = sc[2] = b; }
+                else { gc[0] = sc[0] = a; gc[1] = sc[1] = b; }
+                const int nd = G.n[d];
+                gc[d] = side ? nd : -1;
+                double sgn = 1.0;
+                if (G.per[d]) sc[d] = side ? 0 : nd - 1;
+                else { sc[d] = side ? nd - 1 : 0; sgn = -1.0; }
+                p[pidx(gc[0], gc[1], gc[2])] = sgn * p[pidx(sc[0], sc[1], sc[2])];
+            }
+            __syncthreads();
+            double pAp = 0.0;
+            for (int n = threadIdx.x; n < N; n += blockDim.x) {
+                const int a = n % nx, b = (n / nx) % ny, c = n / (nx * ny);
+                const int pc = pidx(a, b, c);
+                double su, sb;
+                const double pxm = p[pc - 1], pxp = p[pc + 1], pym = p[pc - gx], pyp = p[pc + gx];
+                const double pzm = p[pc - gx * gy], pzp = p[pc + gx * gy];
+                if constexpr (!VAR) {
+                    su = ((pxm + pxp) + (pym + pyp)) + (pzm + pzp);
+                    sb = 6.0;
+                } else {
+                    const long long ix = (long long)a + (long long)(nx + 1) * ((long long)b + (long long)ny * c);
+                    const long long iy = (long long)a + (long long)nx * ((long long)b + (long long)(ny + 1) * c);
+                    const long long iz = (long long)a + (long long)nx * ((long long)b + (long long)ny * c);
+                    const double bxm = (double)fa.c[0][ix], bxp = (double)fa.c[0][ix + 1];
+                    const double bym = (double)fa.c[1][iy], byp = (double)fa.c[1][iy + nx];
+                    const double bzm = (double)fa.c[2][iz], bzp = (double)fa.c[2][iz + (long long)nx * ny];
+                    sb = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
+                    su = ((bxm * pxm + bxp * pxp) + (bym * pym + byp * pyp)) + (bzm * pzm + bzp * pzp);
+                }
+                const double qv = (su - sb * p[pc]) * ih2;
+                q[n] = qv;
+                pAp = pAp + p[pc] * qv;
+            }
+            pAp = bot_reduce(pAp, sh);
+            const double alpha = rs / pAp;
+            double rsn = 0.0;
+            for (int n = threadIdx.x; n < N; n += blockDim.x) {
+                const int a = n % nx, b = (n / nx) % ny, c = n / (nx * ny);
+                x[n] = x[n] + alpha * p[pidx(a, b, c)];
+                const double rn = r[n] - alpha * q[n];
+                r[n] = rn;
+                rsn = rsn + rn * rn;
+            }
+            rsn = bot_reduce(rsn, sh);
+            ++it;
+            if (sqrt(rsn) <= rtol * sqrt(rs0)) break;
+            const double beta = rsn / rs;
+            for (int n = threadIdx.x; n < N; n += blockDim.x) {
+                const int a = n % nx, b = (n / nx) % ny, c = n / (nx * ny);
+                const int pc = pidx(a, b, c);
+                p[pc] = r[n] + beta * p[pc];
+            }
+            rs = rsn;
+            __syncthreads();
+        }
+        if (sing) {
+            double s = 0.0;
+            for (int n = threadIdx.x; n < N; n += blockDim.x) s = s + x[n];
+            const double mean = bot_reduce(s, sh) / (double)N;
+            for (int n = threadIdx.x; n < N; n += blockDim.x) x[n] = x[n] - mean;
+        }
+    }
+    __syncthreads();
+    for (int bi = 0; bi < G.nboxes; ++bi) {
+        const RBox B = boxes[bi];
+        const int bx = B.hi[0] - B.lo[0] + 1, by = B.hi[1] - B.lo[1] + 1, bz = B.hi[2] - B.lo[2] + 1;
+        for (int qq = threadIdx.x; qq < bx * by * bz; qq += blockDim.x) {
+            const int i = B.lo[0] + qq % bx, j = B.lo[1] + (qq / bx) % by, k = B.lo[2] + qq / (bx * by);
+            const int n = (i - G.dlo[0]) + nx * ((j - G.dlo[1]) + ny * (k - G.dlo[2]));
+            u[rb_idx(B, i, j, k)] = (T)x[n];
+        }
+    }
+    if (threadIdx.x == 0 && iters_out) *iters_out = it;
+}
+
+// ================================================================ launchers
+static inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const RBox* boxes, const Tag* tags, int ntags,
+                          long long ncells, int cmask) {
+    if (ncells <= 0) return hipSuccess;
+    if (f32) hipLaunchKernelGGL(k_fill_rb<float>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (float*)data, boxes, tags, ntags, ncells, cmask);
+    else hipLaunchKernelGGL(k_fill_rb<double>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (double*)data, boxes, tags, ntags, ncells, cmask);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_fab(hipStream_t s, void* data, bool f32, const FBox* boxes, const Tag* tags, int ntags,
+                           long long ncells, int comp0, int ncomp) {
+    if (ncells <= 0) return hipSuccess;
+    if (f32) hipLaunchKernelGGL(k_fill_fab<float>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (float*)data, boxes, tags, ntags, ncells, comp0, ncomp);
+    else hipLaunchKernelGGL(k_fill_fab<double>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (double*)data, boxes, tags, ntags, ncells, comp0, ncomp);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_gs(hipStream_t s, T* u, const T* f, const T* beta, FaceArrays<T> fa, const RBox* boxes,
+                     const WorkBox* work, int nwork, long long ncells, T h2, int colour) {
+    if (ncells <= 0) return hipSuccess;
+    if (beta) hipLaunchKernelGGL((k_gs<T, 1>), dim3(nblk(ncells)), dim3(kBlock), 0, s, u, f, beta, fa, boxes, work, nwork, ncells, h2, colour);
+    else if (fa.c[0]) hipLaunchKernelGGL((k_gs<T, 2>), dim3(nblk(ncells)), dim3(kBlock), 0, s, u, f, beta, fa, boxes, work, nwork, ncells, h2, colour);
+    else hipLaunchKernelGGL((k_gs<T, 0>), dim3(nblk(ncells)), dim3(kBlock), 0, s, u, f, beta, fa, boxes, work, nwork, ncells, h2, colour);
+    return hipGetLastError();
+}
+template hipError_t launch_gs<double>(hipStream_t, double*, const double*, const double*, FaceArrays<double>,
+                                      const RBox*, const WorkBox*, int, long long, double, int);
+template hipError_t launch_gs<float>(hipStream_t, float*, const float*, const float*, FaceArrays<float>, const RBox*,
+                                     const WorkBox*, int, long long, float, int);
+
+template <class T, class R>
+static hipError_t resid_dispatch(hipStream_t s, const T* u, const T* f, const T* beta, FaceArrays<T> fa,
+                                 const RBox* boxes, const WorkBox* work, int nwork, long long ncells, T ih2, R* r,
+                                 double* partials, int nblocks) {
+    if (beta) hipLaunchKernelGGL((k_resid<T, 1, R>), dim3(nblocks), dim3(kBlock), 0, s, u, f, beta, fa, boxes, work, nwork, ncells, ih2, r, partials);
+    else if (fa.c[0]) hipLaunchKernelGGL((k_resid<T, 2, R>), dim3(nblocks), dim3(kBlock), 0, s, u, f, beta, fa, boxes, work, nwork, ncells, ih2, r, partials);
+    else hipLaunchKernelGGL((k_resid<T, 0, R>), dim3(nblocks), dim3(kBlock), 0, s, u, f, beta, fa, boxes, work, nwork, ncells, ih2, r, partials);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_resid_norm(hipStream_t s, const T* u, const T* f, const T* beta, FaceArrays<T> fa,
+                             const RBox* boxes, const WorkBox* work, int nwork, long long ncells, T ih2, T* r,
+                             double* partials, int nblocks) {
+    return resid_dispatch<T, T>(s, u, f, beta, fa, boxes, work, nwork, ncells, ih2, r, partials, nblocks);
+}
+template hipError_t launch_resid_norm<double>(hipStream_t, const double*, const double*, const double*,
+                                              FaceArrays<double>, const RBox*, const WorkBox*, int, long long,
+                                              double, double*, double*, int);
+template hipError_t launch_resid_norm<float>(hipStream_t, const float*, const float*, const float*, FaceArrays<float>,
+                                             const RBox*, const WorkBox*, int, long long, float, float*, double*,
+                                             int);
+
+hipError_t launch_resid_cast(hipStream_t s, const double* u, const double* f, const double* beta,
+                             FaceArrays<double> fa, const RBox* boxes, const WorkBox* work, int nwork,
+                             long long ncells, double ih2, float* r32, double* partials, int nblocks) {
+    return resid_dispatch<double, float>(s, u, f, beta, fa, boxes, work, nwork, ncells, ih2, r32, partials, nblocks);
+}
+
+hipError_t launch_norm_final(hipStream_t s, const double* partials, int nblocks, double* out3) {
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, s, partials, nblocks, out3);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_resid_restrict(hipStream_t s, const T* u, const T* f, const T* beta, FaceArrays<T> fa,
+                                 const RBox* fboxes, const RBox* cboxes, const WorkBox* work, int nwork,
+                                 long long ncells, T ih2, T* fc) {
+    if (ncells <= 0) return hipSuccess;
+    if (beta) hipLaunchKernelGGL((k_resid_restrict<T, 1>), dim3(nblk(ncells)), dim3(kBlock), 0, s, u, f, beta, fa, fboxes, cboxes, work, nwork, ncells, ih2, fc);
+    else if (fa.c[0]) hipLaunchKernelGGL((k_resid_restrict<T, 2>), dim3(nblk(ncells)), dim3(kBlock), 0, s, u, f, beta, fa, fboxes, cboxes, work, nwork, ncells, ih2, fc);
+    else hipLaunchKernelGGL((k_resid_restrict<T, 0>), dim3(nblk(ncells)), dim3(kBlock), 0, s, u, f, beta, fa, fboxes, cboxes, work, nwork, ncells, ih2, fc);
+    return hipGetLastError();
+}
+template hipError_t launch_resid_restrict<double>(hipStream_t, const double*, const double*, const double*,
+                                                  FaceArrays<double>, const RBox*, const RBox*, const WorkBox*, int,
+                                                  long long, double, double*);
+template hipError_t launch_resid_restrict<float>(hipStream_t, const float*, const float*, const float*,
+                                                 FaceArrays<float>, const RBox*, const RBox*, const WorkBox*, int,
+                                                 long long, float, float*);
+
+template <class T>
+hipError_t launch_restrict_plain(hipStream_t s, const T* rf, T* fc, const RBox* fboxes, const RBox* cboxes,
+                                 const WorkBox* work, int nwork, long long ncells) {
+    if (ncells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restrict_plain<T>, dim3(nblk(ncells)), dim3(kBlock), 0, s, rf, fc, fboxes, cboxes, work, nwork, ncells);
+    return hipGetLastError();
+}
+template hipError_t launch_restrict_plain<double>(hipStream_t, const double*, double*, const RBox*, const RBox*,
+                                                  const WorkBox*, int, long long);
+
+template <class T>
+hipError_t launch_prolong(hipStream_t s, const T* ec, T* uf, const RBox* fboxes, const RBox* cboxes,
+                          const WorkBox* work, int nwork, long long ncells, int order) {
+    if (ncells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prolong<T>, dim3(nblk(ncells)), dim3(kBlock), 0, s, ec, uf, fboxes, cboxes, work, nwork, ncells, order);
+    return hipGetLastError();
+}
+template hipError_t launch_prolong<double>(hipStream_t, const double*, double*, const RBox*, const RBox*,
+                                           const WorkBox*, int, long long, int);
+template hipError_t launch_prolong<float>(hipStream_t, const float*, float*, const RBox*, const RBox*,
+                                          const WorkBox*, int, long long, int);
+
+template <class T>
+hipError_t launch_zero(hipStream_t s, T* p, long long n) {
+    if (n <= 0) return hipSuccess;
+    const long long nb = std::min<long long>(nblk(n), 4096);
+    hipLaunchKernelGGL(k_zero<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+template hipError_t launch_zero<double>(hipStream_t, double*, long long);
+template hipError_t launch_zero<float>(hipStream_t, float*, long long);
+
+hipError_t launch_cast_f32(hipStream_t s, const double* src, float* dst, long long n) {
+    if (n <= 0) return hipSuccess;
+    const long long nb = std::min<long long>(nblk(n), 4096);
+    hipLaunchKernelGGL(k_cast_f32, dim3((unsigned)nb), dim3(kBlock), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fab_to_rb(hipStream_t s, const double* fab, const FBox* fb, void* rb, bool f32, const RBox* rbx,
+                            const WorkBox* work, int nwork, long long ncells) {
+    if (ncells <= 0) return hipSuccess;
+    if (f32) hipLaunchKernelGGL(k_fab_to_rb<float>, dim3(nblk(ncells)), dim3(kBlock), 0, s, fab, fb, (float*)rb, rbx, work, nwork, ncells);
+    else hipLaunchKernelGGL(k_fab_to_rb<double>, dim3(nblk(ncells)), dim3(kBlock), 0, s, fab, fb, (double*)rb, rbx, work, nwork, ncells);
+    return hipGetLastError();
+}
+
+hipError_t launch_rb_to_fab(hipStream_t s, const double* rb, const RBox* rbx, double* fab, const FBox* fb,
+                            const WorkBox* work, int nwork, long long ncells) {
+    if (ncells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rb_to_fab, dim3(nblk(ncells)), dim3(kBlock), 0, s, rb, rbx, fab, fb, work, nwork, ncells);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_f32(hipStream_t s, double* u, const float* e, const RBox* boxes, const WorkBox* work,
+                          int nwork, long long ncells) {
+    if (ncells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_f32, dim3(nblk(ncells)), dim3(kBlock), 0, s, u, e, boxes, work, nwork, ncells);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_norm(hipStream_t s, const double* x, const RBox* boxes, const WorkBox* work, int nwork,
+                             long long ncells, double* partials, int nblocks) {
+    hipLaunchKernelGGL(k_field_norm, dim3(nblocks), dim3(kBlock), 0, s, x, boxes, work, nwork, ncells, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_mean_sub(hipStream_t s, double* u, const RBox* boxes, const WorkBox* work, int nwork,
+                           long long ncells, double* scratch, int nblocks) {
+    if (ncells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_valid, dim3(nblocks), dim3(kBlock), 0, s, u, boxes, work, nwork, ncells, scratch);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, s, scratch, nblocks, scratch + 3 * nblocks);
+    hipLaunchKernelGGL(k_sub_mean, dim3(nblk(ncells)), dim3(kBlock), 0, s, u, scratch + 3 * nblocks, boxes, work, nwork, ncells);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_faces_from_cells(hipStream_t s, const T* beta, const RBox* fboxes, const WorkBox* work, int nwork,
+                                   long long ncells, int d, FaceArrays<T> out, T* dst) {
+    if (ncells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_faces_from_cells<T>, dim3(nblk(ncells)), dim3(kBlock), 0, s, beta, fboxes, work, nwork, ncells, d, out, dst);
+    return hipGetLastError();
+}
+template hipError_t launch_faces_from_cells<double>(hipStream_t, const double*, const RBox*, const WorkBox*, int,
+                                                    long long, int, FaceArrays<double>, double*);
+template hipError_t launch_faces_from_cells<float>(hipStream_t, const float*, const RBox*, const WorkBox*, int,
+                                                   long long, int, FaceArrays<float>, float*);
+
+template <class T>
+hipError_t launch_faces_coarsen(hipStream_t s, FaceArrays<T> fine, FaceArrays<T> coarse, int d, T* dst) {
+    const long long total = (long long)(coarse.n[0] + (d == 0)) * (coarse.n[1] + (d == 1)) * (coarse.n[2] + (d == 2));
+    hipLaunchKernelGGL(k_faces_coarsen<T>, dim3(nblk(total)), dim3(kBlock), 0, s, fine, coarse, d, dst);
+    return hipGetLastError();
+}
+template hipError_t launch_faces_coarsen<double>(hipStream_t, FaceArrays<double>, FaceArrays<double>, int, double*);
+template hipError_t launch_faces_coarsen<float>(hipStream_t, FaceArrays<float>, FaceArrays<float>, int, float*);
+
+template <class T>
+hipError_t launch_bottom(hipStream_t s, T* u, const T* f, FaceArrays<T> fa, bool var, const RBox* boxes, int nboxes,
+                         const int* dom_lo, const int* dom_hi, const int* periodic, double h, double rtol,
+                         int* iters_out) {
+    BottomGeom G;
+    for (int d = 0; d < 3; ++d) {
+        G.dlo[d] = dom_lo[d];
+        G.n[d] = dom_hi[d] - dom_lo[d] + 1;
+        G.per[d] = periodic[d];
+    }
+    G.nboxes = nboxes;
+    if (var) hipLaunchKernelGGL((k_bottom<T, true>), dim3(1), dim3(kBotThreads), 0, s, u, f, fa, boxes, G, h, rtol, iters_out);
+    else hipLaunchKernelGGL((k_bottom<T, false>), dim3(1), dim3(kBotThreads), 0, s, u, f, fa, boxes, G, h, rtol, iters_out);
+    return hipGetLastError();
+}
+template hipError_t launch_bottom<double>(hipStream_t, double*, const double*, FaceArrays<double>, bool, const RBox*,
+                                          int, const int*, const int*, const int*, double, double, int*);
+template hipError_t launch_bottom<float>(hipStream_t, float*, const float*, FaceArrays<float>, bool, const RBox*, int,
+                                         const int*, const int*, const int*, double, double, int*);
+
+}  // namespace bxmg

@@ -1,0 +1,181 @@
+"""GPU parity of whole multigrid solves against the oracle, through the C ABI.
+
+Tolerances: the FP64 solve must reach the oracle's stopping test (relative
+max-norm residual 1e-10, recomputed here with the oracle's FP64 operator) and
+agree with the oracle's solution to within the error bound of that residual
+(kappa * 2 * tol, kappa_2 ~ 0.405 n^2 for the Dirichlet Laplacian).  The
+per-cycle residual history must match the oracle's to 1e-6 relative while the
+residual is above 1e-6 ||f|| (below that, rounding noise in f - L u of order
+1e-12 ||f|| dominates); the stages are bitwise equal, the bottom CG's
+reductions sum in another order, which is where the two iterates part.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bx():
+    import paper_2403_12179_amd as bx
+    return bx
+
+
+def setup(bx, dlo, dhi, mb, per, f, beta=None):
+    bc = tuple(bx.PERIODIC if p else bx.DIRICHLET0 for p in per)
+    ba = bx.BoxArray.chop(dlo, dhi, mb, bc=bc)
+    phi = bx.MultiFab(ba).set_val(0.0)
+    rhs = bx.MultiFab(ba).set_val(0.0).from_global(f)
+    bmf = bx.MultiFab(ba).set_val(1.0).from_global(beta) if beta is not None else None
+    return ba, phi, rhs, bmf
+
+
+def hist_match(h_gpu, h_orc, floor=1e-6):
+    n = min(len(h_gpu), len(h_orc))
+    for k in range(n):
+        a, b = h_gpu[k], h_orc[k]
+        if b >= floor:
+            assert abs(a - b) <= 1e-6 * b, (k, a, b)
+        else:
+            assert abs(a - b) <= 1e-10, (k, a, b)
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_sine_closed_form_32(bx, orc, periodic):
+    n = 32
+    f, s = W.sine_rhs(n, periodic)
+    per = (1, 1, 1) if periodic else (0, 0, 0)
+    ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 32, per, f)
+    res = bx.mlmg_solve(phi, rhs)
+    assert res.ok and res.rel_resid_inf <= 1e-10
+    u = phi.to_global()
+    k = 2 * np.pi if periodic else np.pi
+    C = (k / n / 2) ** 2 / np.sin(k / n / 2) ** 2
+    assert np.max(np.abs(u - C * s)) <= 1e-8
+    uo, io = orc.solve((0, 0, 0), (n - 1,) * 3, per, orc.chop((0, 0, 0), (n - 1,) * 3, 32), f)
+    assert res.cycles == io["cycles"]
+    hist_match(res.hist, io["hist"])
+    assert np.max(np.abs(u - uo)) <= 1e-9 * np.max(np.abs(uo))
+
+
+CASES = [
+    # (dom_lo, dom_hi, max_box, periodic, var)
+    ((0, 0, 0), (63, 63, 63), 32, (0, 0, 0), False),
+    ((0, 0, 0), (63, 63, 63), 16, (1, 1, 1), False),
+    ((-16, -16, -16), (15, 15, 15), 16, (1, 0, 1), False),
+    ((0, 0, 0), (47, 47, 47), 32, (1, 1, 1), False),      # 32 + 16 boxes, bottom 3^3
+    ((0, 0, 0), (63, 31, 47), 16, (0, 0, 0), False),      # non-cubic, bottom 4x2x3
+    ((0, 0, 0), (63, 63, 63), 32, (0, 0, 0), True),
+    ((0, 0, 0), (31, 31, 31), 8, (1, 0, 0), True),
+    ((0, 0, 0), (79, 79, 79), 32, (0, 0, 0), False),      # bottom 5^3
+]
+
+
+@pytest.mark.parametrize("dlo,dhi,mb,per,var", CASES)
+def test_fp64_solve_parity(bx, orc, dlo, dhi, mb, per, var):
+    shape = tuple(dhi[d] - dlo[d] + 1 for d in range(3))
+    f = W.uniform_rhs(shape, 21, mean_zero=(per == (1, 1, 1)))
+    beta = W.smooth_gaussian_beta(shape, 22) if var else None
+    ba, phi, rhs, bmf = setup(bx, dlo, dhi, mb, per, f, beta)
+    h = 1.0 / shape[0]
+    res = bx.mlmg_solve(phi, rhs, bmf)
+    assert res.ok, res
+    u = phi.to_global()
+    r = f - orc.apply_op(dlo, dhi, per, h, u, beta)
+    assert np.max(np.abs(r)) <= 1e-10 * np.max(np.abs(f))
+    uo, io = orc.solve(dlo, dhi, per, [(b.small, b.big) for b in ba.boxes], f, beta, h=h)
+    assert abs(res.cycles - io["cycles"]) <= 1
+    hist_match(res.hist, io["hist"])
+    kappa = 0.405 * max(shape) ** 2 * ((beta.max() / beta.min()) if var else 1.0)
+    assert np.max(np.abs(u - uo)) <= kappa * 2e-10 * np.max(np.abs(uo))
+
+
+def test_fixed_cycles_iterates_match(bx, orc):
+    n = 64
+    f = W.uniform_rhs((n, n, n), 23)
+    ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 16, (0, 0, 0), f)
+    res = bx.mlmg_solve(phi, rhs, fixed_cycles=3)
+    uo, io = orc.solve((0, 0, 0), (n - 1,) * 3, (0, 0, 0), [(b.small, b.big) for b in ba.boxes], f, fixed_cycles=3)
+    assert res.cycles == 3 and io["cycles"] == 3
+    u = phi.to_global()
+    assert np.max(np.abs(u - uo)) <= 1e-12 * np.max(np.abs(uo))
+    # zero cycles: the residual of u = 0 is f itself
+    phi.set_val(0.0)
+    res0 = bx.mlmg_solve(phi, rhs, max_cycles=0, rel_tol=0.0)
+    assert res0.status == -4 and res0.cycles == 0 and res0.hist[0] == 1.0
+
+
+def test_decomposition_independence_and_repeatability(bx):
+    n = 64
+    f = W.uniform_rhs((n, n, n), 24)
+    out = []
+    for mb in (64, 32, 16):
+        ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, mb, (0, 0, 0), f)
+        res = bx.mlmg_solve(phi, rhs, fixed_cycles=4)
+        out.append((phi.to_global(), res.hist))
+    for u, h in out[1:]:
+        assert np.array_equal(u, out[0][0])
+        assert h == out[0][1]
+    ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 16, (0, 0, 0), f)
+    bx.mlmg_solve(phi, rhs, fixed_cycles=4)
+    assert np.array_equal(phi.to_global(), out[2][0])
+
+
+@pytest.mark.parametrize("var", [False, True])
+def test_mixed_precision_reaches_fp64_tolerance(bx, orc, var):
+    n = 64
+    shape = (n, n, n)
+    f = W.uniform_rhs(shape, 25)
+    beta = W.smooth_gaussian_beta(shape, 26) if var else None
+    ba, phi, rhs, bmf = setup(bx, (0, 0, 0), (n - 1,) * 3, 32, (0, 0, 0), f, beta)
+    res = bx.mlmg_solve(phi, rhs, bmf, precision=1)
+    assert res.ok and res.rel_resid_inf <= 1e-10
+    u = phi.to_global()
+    r = f - orc.apply_op((0, 0, 0), (n - 1,) * 3, (0, 0, 0), 1.0 / n, u, beta)
+    assert np.max(np.abs(r)) <= 1e-10 * np.max(np.abs(f))
+    uo, io = orc.solve((0, 0, 0), (n - 1,) * 3, (0, 0, 0), [(b.small, b.big) for b in ba.boxes], f, beta)
+    kappa = 0.405 * n * n * ((beta.max() / beta.min()) if var else 1.0)
+    err = np.max(np.abs(u - uo)) / np.max(np.abs(uo))
+    assert err <= kappa * 2e-10
+    uo32, io32 = orc.solve((0, 0, 0), (n - 1,) * 3, (0, 0, 0), [(b.small, b.big) for b in ba.boxes], f, beta,
+                           precision=1)
+    assert abs(res.cycles - io32["cycles"]) <= 1
+
+
+def test_status_codes(bx):
+    n = 16
+    f = W.uniform_rhs((n, n, n), 1)
+    ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 8, (0, 0, 0), f)
+    res = bx.mlmg_solve(phi, rhs, max_cycles=1, rel_tol=1e-14)
+    assert res.status == -4 and res.cycles == 1
+    bad = f.copy()
+    bad[1, 2, 3] = np.nan
+    rhs.from_global(bad)
+    phi.set_val(0.0)
+    res = bx.mlmg_solve(phi, rhs)
+    assert res.status == -5
+    rhs.set_val(0.0)
+    phi.set_val(0.0)
+    res = bx.mlmg_solve(phi, rhs)
+    assert res.ok and res.cycles == 0 and not np.any(phi.to_global())
+
+
+def test_full_size_256_in_512_boxes(bx, orc):
+    """The 256^3 / 512 x 32^3 Dirichlet workload at full size: the FP64
+    solve reaches 1e-10 as recomputed by the oracle's operator, and two
+    cycles agree with two oracle cycles."""
+    n = 256
+    f = W.uniform_rhs((n, n, n), 2)
+    ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 32, (0, 0, 0), f)
+    assert len(ba) == 512
+    res = bx.mlmg_solve(phi, rhs)
+    assert res.ok and res.levels == 8
+    u = phi.to_global()
+    r = f - orc.apply_op((0, 0, 0), (n - 1,) * 3, (0, 0, 0), 1.0 / n, u)
+    assert np.max(np.abs(r)) <= 1e-10 * np.max(np.abs(f))
+    phi.set_val(0.0)
+    bx.mlmg_solve(phi, rhs, fixed_cycles=2)
+    uo, io = orc.solve((0, 0, 0), (n - 1,) * 3, (0, 0, 0), [(b.small, b.big) for b in ba.boxes], f, fixed_cycles=2)
+    assert np.max(np.abs(phi.to_global() - uo)) <= 1e-12 * np.max(np.abs(uo))
