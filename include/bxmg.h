@@ -182,6 +182,20 @@ void bxmg_solve_params_default(bxmg_solve_params* p);
 bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi, bxmg_multifab rhs,
                             bxmg_multifab beta, bxmg_solve_info* info);
 
+/* ---------------------------------------------------------- profiling --- */
+/* Kernel timing with HIP events recorded on the context's stream around
+ * every launch of one stage on the finest level (level 0) during solves:
+ *   0 red-black Gauss-Seidel colour, 1 convergence residual + norms,
+ *   2 residual + restriction, 3 prolongation + correction,
+ *   4 ghost fills of the solution; -1 switches timing off (default).
+ * Times accumulate until read; the events add a few microseconds per timed
+ * launch to the stream. */
+bxmg_status bxmg_profile_stage(bxmg_ctx ctx, int32_t stage);
+
+/* Launches timed and their summed duration in milliseconds since the last
+ * reset; reset != 0 clears the totals after reading. */
+bxmg_status bxmg_profile_read(bxmg_ctx ctx, int64_t* launches, double* total_ms, int32_t reset);
+
 /* ------------------------------------------------- single level stages --- */
 /* The solver's own stage kernels applied once to caller MultiFabs (FP64,
  * nghost >= 1, component 0), each bracketed by the same layout conversion

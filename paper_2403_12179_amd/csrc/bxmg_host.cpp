@@ -340,9 +340,40 @@ static void ba_release(bxmg_ba_s* ba) {
 
 struct Hier;
 
+// Event pairs around the level-0 launches of one stage (bxmg_profile_stage).
+struct Profiler {
+    int stage = -1;
+    std::vector<hipEvent_t> ev;
+    size_t n = 0;
+    long long launches = 0;
+    double ms = 0.0;
+    void mark(hipStream_t s) {
+        if (n >= ev.size()) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        HIPCHK(hipEventRecord(ev[n++], s));
+    }
+    // after the stream has drained
+    void harvest() {
+        for (size_t i = 0; i + 1 < n; i += 2) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+            ms += t;
+            ++launches;
+        }
+        n = 0;
+    }
+    ~Profiler() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+};
+
 struct bxmg_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
+    Profiler prof;
     std::map<std::string, std::unique_ptr<Hier>> cache;
     double* h_norm = nullptr;  // pinned
     std::mutex mu;
@@ -557,7 +588,13 @@ struct Run {
     hipStream_t s;
     int nu1, nu2, prolong;
     double bottom_rtol;
+    Profiler* prof = nullptr;
+    // event brackets around level-0 launches of the profiled stage
+    void pre(size_t l, int stage) { if (prof && prof->stage == stage && l == 0) prof->mark(s); }
+    void post(size_t l, int stage) { if (prof && prof->stage == stage && l == 0) prof->mark(s); }
 };
+
+enum { kStageGS = 0, kStageResid = 1, kStageRestrict = 2, kStageProlong = 3, kStageFill = 4 };
 
 template <class T>
 T* lvl_u(Hier* H, size_t l);
@@ -595,7 +632,9 @@ FaceArrays<float> lvl_faces<float>(Hier* H, size_t l) {
 template <class T>
 void fill(Run& R, size_t l, T* data, const Plan& p, int cmask) {
     const Level& L = *R.H->L[l];
+    R.pre(l, kStageFill);
     HIPCHK(launch_fill_rb(R.s, data, sizeof(T) == 4, L.d_rb.p, p.tags.p, p.ntags, p.cells, cmask));
+    R.post(l, kStageFill);
 }
 
 template <class T>
@@ -608,8 +647,10 @@ void smooth(Run& R, size_t l, int nsweeps) {
     for (int s = 0; s < nsweeps; ++s)
         for (int c = 0; c < 2; ++c) {
             fill<T>(R, l, u, L.faces_odd, 1 << (c ^ 1));
+            R.pre(l, kStageGS);
             HIPCHK(launch_gs<T>(R.s, u, f, lvl_beta<T>(H, l), lvl_faces<T>(H, l), L.d_rb.p, L.wcol.p, L.nwcol, L.ncol,
                                 h2, c));
+            R.post(l, kStageGS);
         }
 }
 
@@ -635,12 +676,16 @@ void vcycle(Run& R, size_t l) {
     smooth<T>(R, l, R.nu1);
     fill<T>(R, l, u, L.faces_odd, 3);
     const T ih2 = (T)(1.0 / (L.h * L.h));
+    R.pre(l, kStageRestrict);
     HIPCHK(launch_resid_restrict<T>(R.s, u, lvl_f<T>(H, l), lvl_beta<T>(H, l), lvl_faces<T>(H, l), L.d_rb.p, C.d_rb.p,
                                     L.wdown.p, L.nwdown, L.ndown, ih2, lvl_f<T>(H, l + 1)));
+    R.post(l, kStageRestrict);
     HIPCHK(launch_zero<T>(R.s, lvl_u<T>(H, l + 1), C.nelem));
     vcycle<T>(R, l + 1);
     fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full_odd, 3);
+    R.pre(l, kStageProlong);
     HIPCHK(launch_prolong<T>(R.s, lvl_u<T>(H, l + 1), u, L.d_rb.p, C.d_rb.p, L.wdown.p, L.nwdown, L.ndown, R.prolong));
+    R.post(l, kStageProlong);
     smooth<T>(R, l, R.nu2);
 }
 
@@ -981,6 +1026,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         if (!H) return set_status(info, st);
         info->levels = (int)H->L.size();
         Run R{H, ctx->stream, P.nu1, P.nu2, P.prolong, P.bottom_rtol};
+        R.prof = &ctx->prof;
         const Level& L0 = *H->L[0];
         double* u = H->u64[0]->p;
         double* f = H->f64[0]->p;
@@ -1013,6 +1059,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         if (fnorm > 0.0) {
             for (;; ++cyc) {
                 fill<double>(R, 0, u, L0.faces_odd, 3);
+                R.pre(0, kStageResid);
                 if (P.precision == 0) {
                     HIPCHK(launch_resid_norm<double>(R.s, u, f, beta ? H->beta64.p : nullptr, nf, L0.d_rb.p, L0.wcol.p,
                                                      L0.nwcol, L0.ncol, ih2, nullptr, H->partials.p, kNormBlocks));
@@ -1020,6 +1067,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
                     HIPCHK(launch_resid_cast(R.s, u, f, beta ? H->beta64.p : nullptr, nf, L0.d_rb.p, L0.wcol.p,
                                              L0.nwcol, L0.ncol, ih2, H->f32[0]->p, H->partials.p, kNormBlocks));
                 }
+                R.post(0, kStageResid);
                 HIPCHK(launch_norm_final(R.s, H->partials.p, kNormBlocks, H->fnorm.p));
                 norm_readback(R, ctx->h_norm, H->fnorm.p);
                 const double rinf = ctx->h_norm[2] > 0 ? NAN : ctx->h_norm[0];
@@ -1051,6 +1099,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
             HIPCHK(launch_mean_sub(R.s, u, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol, H->partials.p, kNormBlocks));
         HIPCHK(launch_rb_to_fab(R.s, u, L0.d_rb.p, (double*)phi->data, phi->d_fboxes.p, L0.wcol.p, L0.nwcol, L0.ncol));
         HIPCHK(hipStreamSynchronize(R.s));
+        ctx->prof.harvest();
         info->status = status;
         if (status == BXMG_ENOCONV) fail(BXMG_ENOCONV, "solve: max_cycles reached");
         if (status == BXMG_ENONFINITE) fail(BXMG_ENONFINITE, "solve: non-finite residual");
@@ -1061,6 +1110,24 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
     return (bxmg_status)info->status;
 }
 
+
+bxmg_status bxmg_profile_stage(bxmg_ctx ctx, int32_t stage) {
+    if (!ctx) return fail(BXMG_EINVAL, "profile_stage: NULL context");
+    if (stage < -1 || stage > kStageFill) return fail(BXMG_EINVAL, "profile_stage: unknown stage");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->prof.stage = stage;
+    ctx->prof.n = 0;
+    return BXMG_OK;
+}
+
+bxmg_status bxmg_profile_read(bxmg_ctx ctx, int64_t* launches, double* total_ms, int32_t reset) {
+    if (!ctx) return fail(BXMG_EINVAL, "profile_read: NULL context");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (launches) *launches = ctx->prof.launches;
+    if (total_ms) *total_ms = ctx->prof.ms;
+    if (reset) { ctx->prof.launches = 0; ctx->prof.ms = 0.0; }
+    return BXMG_OK;
+}
 
 // ----------------------------------------------------- single-level stages
 // Each stage runs the solver's own kernels on the hierarchy cached for the
