@@ -23,9 +23,10 @@
 //                ghosts refreshed before every colour
 //   restriction: average of the 8 children
 //   prolongation: trilinear cell-centred (27/9/3/1 over 64) or piecewise const
-//   coarsening : by 2 while every domain edge is even and >= 4; boxes are
-//                coarsened one by one while every box edge is even and >= 4
-//                and its lower corner even, else the coarse level is one box
+//   coarsening : by 2 while every domain edge is even and >= 4 and every box
+//                holds whole cell pairs (even lower corner and edges); boxes
+//                are coarsened one by one while every box edge is also >= 4,
+//                else the coarse level is one box
 //   bottom     : FP64 conjugate gradients, rel. L2 residual 1e-12,
 //                at most 4*cells iterations; periodic: mean-zero projection
 //   stop test  : ||f - L u||_inf <= rel_tol * ||f||_inf (or <= abs_tol)
@@ -151,6 +152,15 @@ static bool can_coarsen_domain(const Box& dom) {
     return true;
 }
 
+// Every box holds whole pairs of cells (even lower corner, even edges), so
+// each coarse cell's 8 children lie in one box.
+static bool pair_aligned(const std::vector<Box>& bs) {
+    for (auto& b : bs)
+        for (int d = 0; d < 3; ++d)
+            if (b.n(d) % 2 != 0 || (b.lo[d] & 1)) return false;
+    return true;
+}
+
 static bool can_coarsen_boxes(const std::vector<Box>& bs) {
     for (auto& b : bs)
         for (int d = 0; d < 3; ++d)
@@ -166,7 +176,7 @@ struct Level {
 static std::vector<Level> hierarchy(const Geom& g0, const std::vector<Box>& b0) {
     std::vector<Level> L;
     L.push_back(Level{g0, b0});
-    while (can_coarsen_domain(L.back().g.dom)) {
+    while (can_coarsen_domain(L.back().g.dom) && pair_aligned(L.back().boxes)) {
         Level c;
         c.g = L.back().g;
         c.g.dom = coarsen(L.back().g.dom);

@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
+#include <stdexcept>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -32,10 +34,10 @@ struct HipError {
     const char* where;
 };
 
-#define HIPCHK(x)                                          \
-    do {                                                   \
-        hipError_t e_ = (x);                               \
-        if (e_ != hipSuccess) throw HipError{e_, #x};      \
+#define HIPCHK(...)                                                   \
+    do {                                                              \
+        hipError_t e_ = (__VA_ARGS__);                                \
+        if (e_ != hipSuccess) throw HipError{e_, #__VA_ARGS__};       \
     } while (0)
 
 // -------------------------------------------------------------- box algebra
@@ -82,6 +84,15 @@ bool domain_coarsenable(const Box& dom) {
     return true;
 }
 
+// Every box holds whole pairs of cells (even lower corner, even edges), so
+// each coarse cell's 8 children lie in one box.
+bool boxes_pair_aligned(const std::vector<Box>& bs) {
+    for (auto& b : bs)
+        for (int d = 0; d < 3; ++d)
+            if (b.n(d) % 2 || (b.lo[d] & 1)) return false;
+    return true;
+}
+
 bool boxes_coarsenable(const std::vector<Box>& bs) {
     for (auto& b : bs)
         for (int d = 0; d < 3; ++d)
@@ -96,7 +107,7 @@ struct LevelBoxes {
 
 std::vector<LevelBoxes> make_hierarchy(const Box& dom, const std::vector<Box>& b0) {
     std::vector<LevelBoxes> L{LevelBoxes{dom, b0}};
-    while (domain_coarsenable(L.back().dom)) {
+    while (domain_coarsenable(L.back().dom) && boxes_pair_aligned(L.back().boxes)) {
         LevelBoxes c;
         c.dom = coarsen(L.back().dom);
         if (boxes_coarsenable(L.back().boxes))
@@ -217,51 +228,68 @@ long long tag_cells(const std::vector<Tag>& t) {
     return t.back().prefix + (long long)t.back().n[0] * t.back().n[1] * t.back().n[2];
 }
 
-// Colour-cell work list: per box ceil(nx/2) x ny x nz threads.
-std::vector<WorkBox> colour_work(const std::vector<Box>& boxes, long long* total) {
-    std::vector<WorkBox> w;
-    long long s = 0;
-    for (size_t b = 0; b < boxes.size(); ++b) {
-        WorkBox x;
-        x.cstart = s;
-        x.tn = (boxes[b].n(0) + 1) / 2;
-        x.ny = boxes[b].n(1);
-        x.nz = boxes[b].n(2);
-        x.box = (int)b;
-        x.cbox = -1;
-        x.pad = 0;
-        s += (long long)x.tn * x.ny * x.nz;
-        w.push_back(x);
-    }
-    *total = s;
-    return w;
+// Tiles: one block of kBlock threads per tile, TX x TY x TZ threads with
+// TX = 2^lx covering x, TY = 2^ly covering y, TZ = 2^lz planes walked zc
+// times.  ext[b] = per-box thread extents (x, y, z).  Tiles run box-major,
+// then z, y, x, so consecutive tiles share halo planes.
+struct TileSet {
+    std::vector<Tile> tiles;
+    TileShape sh;
+};
+
+int ilog2ceil(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
 }
 
-// Coarse-cell work list of a fine level: per fine box its coarsened cells,
-// with the index of the coarse box that contains them.  extra_d adds the
-// high-boundary face layer in direction d for boxes touching dom.hi.
-std::vector<WorkBox> coarse_work(const std::vector<Box>& fine, const std::vector<Box>& coarse, const Box& fdom,
-                                 int extra_d, long long* total) {
-    std::vector<WorkBox> w;
-    long long s = 0;
-    for (size_t b = 0; b < fine.size(); ++b) {
-        const Box c = coarsen(fine[b]);
-        int owner = -1;
-        for (size_t q = 0; q < coarse.size(); ++q)
-            if (coarse[q].contains(c)) { owner = (int)q; break; }
-        WorkBox x;
-        x.cstart = s;
-        x.tn = c.n(0) + (extra_d == 0 && fine[b].hi[0] == fdom.hi[0]);
-        x.ny = c.n(1) + (extra_d == 1 && fine[b].hi[1] == fdom.hi[1]);
-        x.nz = c.n(2) + (extra_d == 2 && fine[b].hi[2] == fdom.hi[2]);
-        x.box = (int)b;
-        x.cbox = owner;
-        x.pad = 0;
-        s += (long long)x.tn * x.ny * x.nz;
-        w.push_back(x);
+TileSet make_tiles(const std::vector<std::array<int, 3>>& ext, int zc_target) {
+    int mx = 1, my = 1, mz = 1;
+    for (auto& e : ext) { mx = std::max(mx, e[0]); my = std::max(my, e[1]); mz = std::max(mz, e[2]); }
+    TileSet t;
+    t.sh.lx = std::min(ilog2ceil(mx), 6);
+    t.sh.ly = std::min(ilog2ceil(my), 8 - t.sh.lx);
+    t.sh.lz = 8 - t.sh.lx - t.sh.ly;
+    const int TX = 1 << t.sh.lx, TY = 1 << t.sh.ly, TZ = 1 << t.sh.lz;
+    t.sh.zc = std::max(1, std::min(zc_target, (mz + TZ - 1) / TZ));
+    const int KZ = TZ * t.sh.zc;
+    for (size_t b = 0; b < ext.size(); ++b)
+        for (int z0 = 0; z0 < ext[b][2]; z0 += KZ)
+            for (int y0 = 0; y0 < ext[b][1]; y0 += TY)
+                for (int x0 = 0; x0 < ext[b][0]; x0 += TX) t.tiles.push_back(Tile{(int)b, x0, y0, z0});
+    return t;
+}
+
+// Colour-cell extents: ceil(nx/2) cells of one colour per row.
+std::vector<std::array<int, 3>> colour_extents(const std::vector<Box>& boxes) {
+    std::vector<std::array<int, 3>> e;
+    for (auto& b : boxes) e.push_back({(b.n(0) + 1) / 2, b.n(1), b.n(2)});
+    return e;
+}
+
+// Coarse-cell extents of every fine box; extra_d >= 0 adds the high face
+// layer in direction d for boxes touching the fine domain's upper end.
+std::vector<std::array<int, 3>> coarse_extents(const std::vector<Box>& fine, const Box& fdom, int extra_d) {
+    std::vector<std::array<int, 3>> e;
+    for (auto& b : fine) {
+        std::array<int, 3> x{b.n(0) / 2, b.n(1) / 2, b.n(2) / 2};
+        if (extra_d >= 0 && b.hi[extra_d] == fdom.hi[extra_d]) x[extra_d] += 1;
+        e.push_back(x);
     }
-    *total = s;
-    return w;
+    return e;
+}
+
+std::vector<int> coarse_owner(const std::vector<Box>& fine, const std::vector<Box>& coarse) {
+    std::vector<int> own;
+    for (auto& b : fine) {
+        const Box c = coarsen(b);
+        int o = -1;
+        for (size_t q = 0; q < coarse.size(); ++q)
+            if (coarse[q].contains(c)) { o = (int)q; break; }
+        if (o < 0) throw std::runtime_error("a coarsened box lies in no coarse box");
+        own.push_back(o);
+    }
+    return own;
 }
 
 // RB layout of a level: per box two colour blocks, each 64-element aligned.
@@ -278,6 +306,7 @@ std::vector<RBox> rb_layout(const std::vector<Box>& boxes, int ng, long long* ne
         }
         r.H = (r.G[0] + 1) / 2;
         r.pid = 0;
+        for (int q = 0; q < 6; ++q) { r.nb[q] = -2; r.shift[q] = 0; }
         const long long half = (long long)r.H * r.G[1] * r.G[2];
         const long long padded = (half + 63) / 64 * 64;
         r.base = off;
@@ -287,6 +316,63 @@ std::vector<RBox> rb_layout(const std::vector<Box>& boxes, int ng, long long* ne
     }
     *nelem = off;
     return v;
+}
+
+// Face neighbours of every box of a level (RBox::nb / shift).  Returns true
+// when each face is resolvable: the 1-cell slab beyond it lies in one box
+// (after a periodic shift) or outside a Dirichlet domain face.
+bool face_neighbours(const Box& dom, const int per[3], const std::vector<Box>& boxes, std::vector<RBox>& rb) {
+    bool all = true;
+    for (size_t b = 0; b < boxes.size(); ++b)
+        for (int d = 0; d < 3; ++d)
+            for (int side = 0; side < 2; ++side) {
+                const int q = 2 * d + side;
+                Box S = boxes[b];
+                S.lo[d] = S.hi[d] = side ? boxes[b].hi[d] + 1 : boxes[b].lo[d] - 1;
+                int shift = 0;
+                if (S.lo[d] < dom.lo[d] || S.lo[d] > dom.hi[d]) {
+                    if (!per[d]) {
+                        rb[b].nb[q] = -1;
+                        rb[b].shift[q] = 0;
+                        continue;
+                    }
+                    shift = side ? -dom.n(d) : dom.n(d);
+                    S.lo[d] += shift;
+                    S.hi[d] += shift;
+                }
+                int found = -2;
+                for (size_t o = 0; o < boxes.size(); ++o)
+                    if (boxes[o].contains(S)) { found = (int)o; break; }
+                rb[b].nb[q] = found;
+                rb[b].shift[q] = shift;
+                if (found == -2) all = false;
+            }
+    return all;
+}
+
+long long rb_index(const RBox& b, int i, int j, int k) {
+    return b.base + (long long)((i + j + k) & 1) * b.cstride +
+           ((long long)(k - b.glo[2]) * b.G[1] + (j - b.glo[1])) * b.H + ((i - b.glo[0]) >> 1);
+}
+
+// Expand region tags into per-cell (dst, src) element pairs of an RB level,
+// keeping the destinations whose colour is in cmask.
+std::vector<GhostCopy> ghost_list(const std::vector<Tag>& tags, const std::vector<RBox>& rb, int cmask) {
+    std::vector<GhostCopy> out;
+    for (auto& t : tags)
+        for (int z = 0; z < t.n[2]; ++z)
+            for (int y = 0; y < t.n[1]; ++y)
+                for (int x = 0; x < t.n[0]; ++x) {
+                    const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
+                    if (!((cmask >> ((di + dj + dk) & 1)) & 1)) continue;
+                    const int si = t.sgn[0] * di + t.soff[0], sj = t.sgn[1] * dj + t.soff[1],
+                              sk = t.sgn[2] * dk + t.soff[2];
+                    const long long d = rb_index(rb[t.dbox], di, dj, dk), sr = rb_index(rb[t.sbox], si, sj, sk);
+                    if (d < 0 || sr < 0 || d > 0x7fffffffLL || sr > 0x7fffffffLL)
+                        throw std::runtime_error("level storage exceeds 2^31 elements");
+                    out.push_back(GhostCopy{(uint32_t)d, (uint32_t)sr | (t.neg ? 0x80000000u : 0u)});
+                }
+    return out;
 }
 
 // ----------------------------------------------------------- device buffers
@@ -429,8 +515,6 @@ static Plan* mf_plan(bxmg_mf_s* mf, int mode, bool cross, bool odd) {
 // ================================================================ hierarchy
 namespace {
 
-constexpr int kNormBlocks = 1024;
-
 template <class T>
 struct FaceSet {
     DevBuf<T> c[3];
@@ -448,6 +532,15 @@ FaceArrays<T> no_faces() {
     return f;
 }
 
+struct GhostList {
+    DevBuf<GhostCopy> list;
+    long long n = 0;
+    void set(const std::vector<GhostCopy>& v) {
+        list.upload(v);
+        n = (long long)v.size();
+    }
+};
+
 struct Level {
     Box dom;
     double h;
@@ -455,17 +548,24 @@ struct Level {
     std::vector<RBox> rb;
     DevBuf<RBox> d_rb;
     long long nelem = 0;
-    DevBuf<WorkBox> wcol;   // colour cells
-    int nwcol = 0;
-    long long ncol = 0;
-    DevBuf<WorkBox> wdown;  // coarse cells of this level's boxes (to level+1)
-    int nwdown = 0;
-    long long ndown = 0;
-    DevBuf<WorkBox> wface[3];  // coarse faces anchored in this level's boxes
-    long long nface[3] = {0, 0, 0};
-    Plan faces_odd;  // face ghosts, exchange + Dirichlet
-    Plan full_odd;   // all ghosts, exchange + Dirichlet
-    Plan full_even;  // all ghosts, exchange + even reflection (cell beta)
+    // colour-cell tiles (valid cells, one colour per thread per plane)
+    DevBuf<Tile> tcol;
+    int ntcol = 0;
+    TileShape shcol{};
+    // transfer tiles to level + 1 (coarse cells of every box)
+    DevBuf<Tile> tdown;
+    int ntdown = 0;
+    TileShape shdown{};
+    DevBuf<int> cbox;
+    // coefficient setup tiles (coarse faces anchored in every box), level 0
+    DevBuf<Tile> tface[3];
+    int ntface[3] = {0, 0, 0};
+    TileShape shface[3]{};
+    GhostList face[2];  // face ghosts of colour c: exchange + Dirichlet
+    GhostList full;     // every ghost: exchange + Dirichlet
+    GhostList full_even;  // every ghost: exchange + even reflection (cell beta)
+    bool push = false;    // producers refresh the face ghosts they mirror
+    Grid grid() const { return Grid{d_rb.p, tcol.p, ntcol, shcol, push ? 1 : 0}; }
 };
 
 }  // namespace
@@ -482,11 +582,29 @@ struct Hier {
     DevBuf<float> beta32;
     std::vector<std::unique_ptr<FaceSet<double>>> faces64;  // index = level (0 unused)
     std::vector<std::unique_ptr<FaceSet<float>>> faces32;
-    DevBuf<double> partials;  // 3*kNormBlocks + 3
+    DevBuf<double> partials;  // 3 per tile of the largest tiled launch, + 3
     DevBuf<double> fnorm;     // 3
     DevBuf<int> iters;
     size_t bytes = 0;
+    XGrid xgrid(size_t l) const {
+        const Level& F = *L[l];
+        const Level& C = *L[l + 1];
+        return XGrid{F.d_rb.p, C.d_rb.p, F.cbox.p, F.tdown.p, F.ntdown, F.shdown, F.push ? 1 : 0};
+    }
+    XGrid face_grid(int d) const {
+        const Level& F = *L[0];
+        const Level& C = *L[1];
+        return XGrid{F.d_rb.p, C.d_rb.p, F.cbox.p, F.tface[d].p, F.ntface[d], F.shface[d], 0};
+    }
 };
+
+constexpr int kZc = 4;  // planes per thread in the cell kernels
+
+static void upload_tiles(const TileSet& t, DevBuf<Tile>& buf, int& n, TileShape& sh) {
+    buf.upload(t.tiles);
+    n = (int)t.tiles.size();
+    sh = t.sh;
+}
 
 static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool var, double h0) {
     auto H = std::make_unique<Hier>();
@@ -495,6 +613,7 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
     H->var = var;
     std::vector<LevelBoxes> lb = make_hierarchy(ba->dom, ba->boxes);
     double h = h0;
+    long long max_tiles = 1;
     for (size_t l = 0; l < lb.size(); ++l) {
         auto lv = std::make_unique<Level>();
         lv->dom = lb[l].dom;
@@ -502,27 +621,23 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
         h *= 2.0;
         lv->boxes = lb[l].boxes;
         lv->rb = rb_layout(lv->boxes, 1, &lv->nelem);
+        lv->push = face_neighbours(lv->dom, H->per, lv->boxes, lv->rb);
         lv->d_rb.upload(lv->rb);
-        long long tot;
-        auto wc = colour_work(lv->boxes, &tot);
-        lv->wcol.upload(wc);
-        lv->nwcol = (int)wc.size();
-        lv->ncol = tot;
+        upload_tiles(make_tiles(colour_extents(lv->boxes), kZc), lv->tcol, lv->ntcol, lv->shcol);
+        max_tiles = std::max<long long>(max_tiles, lv->ntcol);
         if (l + 1 < lb.size()) {
-            auto wd = coarse_work(lv->boxes, lb[l + 1].boxes, lv->dom, -1, &tot);
-            lv->wdown.upload(wd);
-            lv->nwdown = (int)wd.size();
-            lv->ndown = tot;
-            if (var)
-                for (int d = 0; d < 3; ++d) {
-                    auto wf = coarse_work(lv->boxes, lb[l + 1].boxes, lv->dom, d, &tot);
-                    lv->wface[d].upload(wf);
-                    lv->nface[d] = tot;
-                }
+            upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, -1), kZc), lv->tdown, lv->ntdown, lv->shdown);
+            lv->cbox.upload(coarse_owner(lv->boxes, lb[l + 1].boxes));
+            if (var && l == 0)
+                for (int d = 0; d < 3; ++d)
+                    upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, d), kZc), lv->tface[d], lv->ntface[d],
+                                 lv->shface[d]);
         }
-        lv->faces_odd.set(build_tags(lv->dom, H->per, lv->boxes, 1, true, 2, true));
-        lv->full_odd.set(build_tags(lv->dom, H->per, lv->boxes, 1, false, 2, true));
-        if (l == 0 && var) lv->full_even.set(build_tags(lv->dom, H->per, lv->boxes, 1, false, 2, false));
+        const std::vector<Tag> faces = build_tags(lv->dom, H->per, lv->boxes, 1, true, 2, true);
+        lv->face[0].set(ghost_list(faces, lv->rb, 1));
+        lv->face[1].set(ghost_list(faces, lv->rb, 2));
+        lv->full.set(ghost_list(build_tags(lv->dom, H->per, lv->boxes, 1, false, 2, true), lv->rb, 3));
+        if (l == 0 && var) lv->full_even.set(ghost_list(build_tags(lv->dom, H->per, lv->boxes, 1, false, 2, false), lv->rb, 3));
         H->L.push_back(std::move(lv));
     }
     const size_t nl = H->L.size();
@@ -574,7 +689,7 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
             }
         }
     }
-    H->partials.alloc(3 * kNormBlocks + 8);
+    H->partials.alloc(3 * max_tiles + 8);
     H->fnorm.alloc(4);
     H->iters.alloc(1);
     return H;
@@ -582,19 +697,6 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
 
 // ================================================================== driver
 namespace {
-
-struct Run {
-    Hier* H;
-    hipStream_t s;
-    int nu1, nu2, prolong;
-    double bottom_rtol;
-    Profiler* prof = nullptr;
-    // event brackets around level-0 launches of the profiled stage
-    void pre(size_t l, int stage) { if (prof && prof->stage == stage && l == 0) prof->mark(s); }
-    void post(size_t l, int stage) { if (prof && prof->stage == stage && l == 0) prof->mark(s); }
-};
-
-enum { kStageGS = 0, kStageResid = 1, kStageRestrict = 2, kStageProlong = 3, kStageFill = 4 };
 
 template <class T>
 T* lvl_u(Hier* H, size_t l);
@@ -629,12 +731,32 @@ FaceArrays<float> lvl_faces<float>(Hier* H, size_t l) {
     return H->faces32[l]->view(H->L[l]->dom);
 }
 
+struct Run {
+    Hier* H;
+    hipStream_t s;
+    int nu1, nu2, prolong;
+    double bottom_rtol;
+    Profiler* prof = nullptr;
+    // event brackets around level-0 launches of the profiled stage
+    void pre(size_t l, int stage) { if (prof && prof->stage == stage && l == 0) prof->mark(s); }
+    void post(size_t l, int stage) { if (prof && prof->stage == stage && l == 0) prof->mark(s); }
+};
+
+enum { kStageGS = 0, kStageResid = 1, kStageRestrict = 2, kStageProlong = 3, kStageFill = 4 };
+
 template <class T>
-void fill(Run& R, size_t l, T* data, const Plan& p, int cmask) {
-    const Level& L = *R.H->L[l];
+void fill(Run& R, size_t l, T* data, const GhostList& g) {
     R.pre(l, kStageFill);
-    HIPCHK(launch_fill_rb(R.s, data, sizeof(T) == 4, L.d_rb.p, p.tags.p, p.ntags, p.cells, cmask));
+    HIPCHK(launch_fill_rb(R.s, data, sizeof(T) == 4, g.list.p, g.n));
     R.post(l, kStageFill);
+}
+
+// both colours' face ghosts: two lists (the solver refreshes them per colour)
+template <class T>
+void fill_faces(Run& R, size_t l, T* data) {
+    const Level& L = *R.H->L[l];
+    fill<T>(R, l, data, L.face[0]);
+    fill<T>(R, l, data, L.face[1]);
 }
 
 template <class T>
@@ -646,10 +768,9 @@ void smooth(Run& R, size_t l, int nsweeps) {
     const T h2 = (T)(L.h * L.h);
     for (int s = 0; s < nsweeps; ++s)
         for (int c = 0; c < 2; ++c) {
-            fill<T>(R, l, u, L.faces_odd, 1 << (c ^ 1));
+            if (!L.push) fill<T>(R, l, u, L.face[c ^ 1]);
             R.pre(l, kStageGS);
-            HIPCHK(launch_gs<T>(R.s, u, f, lvl_beta<T>(H, l), lvl_faces<T>(H, l), L.d_rb.p, L.wcol.p, L.nwcol, L.ncol,
-                                h2, c));
+            HIPCHK(launch_gs<T>(R.s, L.grid(), u, f, lvl_beta<T>(H, l), lvl_faces<T>(H, l), h2, c));
             R.post(l, kStageGS);
         }
 }
@@ -674,17 +795,17 @@ void vcycle(Run& R, size_t l) {
     const Level& C = *H->L[l + 1];
     T* u = lvl_u<T>(H, l);
     smooth<T>(R, l, R.nu1);
-    fill<T>(R, l, u, L.faces_odd, 3);
+    if (!L.push) fill_faces<T>(R, l, u);
     const T ih2 = (T)(1.0 / (L.h * L.h));
     R.pre(l, kStageRestrict);
-    HIPCHK(launch_resid_restrict<T>(R.s, u, lvl_f<T>(H, l), lvl_beta<T>(H, l), lvl_faces<T>(H, l), L.d_rb.p, C.d_rb.p,
-                                    L.wdown.p, L.nwdown, L.ndown, ih2, lvl_f<T>(H, l + 1)));
+    HIPCHK(launch_resid_restrict<T>(R.s, H->xgrid(l), u, lvl_f<T>(H, l), lvl_beta<T>(H, l), lvl_faces<T>(H, l), ih2,
+                                    lvl_f<T>(H, l + 1)));
     R.post(l, kStageRestrict);
     HIPCHK(launch_zero<T>(R.s, lvl_u<T>(H, l + 1), C.nelem));
     vcycle<T>(R, l + 1);
-    fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full_odd, 3);
+    fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full);
     R.pre(l, kStageProlong);
-    HIPCHK(launch_prolong<T>(R.s, lvl_u<T>(H, l + 1), u, L.d_rb.p, C.d_rb.p, L.wdown.p, L.nwdown, L.ndown, R.prolong));
+    HIPCHK(launch_prolong<T>(R.s, H->xgrid(l), lvl_u<T>(H, l + 1), u, R.prolong));
     R.post(l, kStageProlong);
     smooth<T>(R, l, R.nu2);
 }
@@ -695,17 +816,13 @@ template <class T>
 void setup_faces(Run& R, T* beta0) {
     Hier* H = R.H;
     const Level& L0 = *H->L[0];
-    fill<T>(R, 0, beta0, L0.full_even, 3);
+    fill<T>(R, 0, beta0, L0.full_even);
     for (size_t l = 1; l < H->L.size(); ++l) {
         FaceArrays<T> out = lvl_faces<T>(H, l);
         for (int d = 0; d < 3; ++d) {
             T* dst = const_cast<T*>(out.c[d]);
-            if (l == 1) {
-                HIPCHK(launch_faces_from_cells<T>(R.s, beta0, L0.d_rb.p, L0.wface[d].p, (int)L0.boxes.size(),
-                                                  L0.nface[d], d, out, dst));
-            } else {
-                HIPCHK(launch_faces_coarsen<T>(R.s, lvl_faces<T>(H, l - 1), out, d, dst));
-            }
+            if (l == 1) HIPCHK(launch_faces_from_cells<T>(R.s, H->face_grid(d), beta0, d, out, dst));
+            else HIPCHK(launch_faces_coarsen<T>(R.s, lvl_faces<T>(H, l - 1), out, d, dst));
         }
     }
 }
@@ -976,7 +1093,6 @@ static bool covers_domain(const bxmg_ba_s* ba) {
 
 // The bottom kernel keeps the level's vectors in LDS: at most kMaxBottomCells
 // cells and kBottomGrown cells including the ghost layer.
-constexpr long long kBottomGrown = 6144;
 static bool bottom_fits(const Box& dom) {
     const long long grown = (long long)(dom.n(0) + 2) * (dom.n(1) + 2) * (dom.n(2) + 2);
     return dom.cells() <= kMaxBottomCells && grown <= kBottomGrown;
@@ -994,7 +1110,17 @@ static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var
                                     " cells (at most 4096, and 6144 with its ghost layer)");
         return nullptr;
     }
-    auto H = build_hier(ba, precision, var, h);
+    std::unique_ptr<Hier> H;
+    try {
+        H = build_hier(ba, precision, var, h);
+    } catch (HipError& e) {
+        *st = fail(e.e == hipErrorOutOfMemory ? BXMG_ENOMEM : BXMG_EDEVICE,
+                   std::string("solve: hierarchy setup: ") + e.where + ": " + hipGetErrorString(e.e));
+        return nullptr;
+    } catch (std::exception& e) {
+        *st = fail(BXMG_EINVAL, std::string("solve: hierarchy setup: ") + e.what());
+        return nullptr;
+    }
     Hier* raw = H.get();
     ctx->cache[key] = std::move(H);
     return raw;
@@ -1031,22 +1157,25 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         double* u = H->u64[0]->p;
         double* f = H->f64[0]->p;
         // caller layout -> colour-split level 0
-        HIPCHK(launch_fab_to_rb(R.s, (const double*)phi->data, phi->d_fboxes.p, u, false, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol));
-        HIPCHK(launch_fab_to_rb(R.s, (const double*)rhs->data, rhs->d_fboxes.p, f, false, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol));
+        HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)phi->data, phi->d_fboxes.p, u, false));
+        HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)rhs->data, rhs->d_fboxes.p, f, false));
         if (beta) {
-            HIPCHK(launch_fab_to_rb(R.s, (const double*)beta->data, beta->d_fboxes.p, H->beta64.p, false, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol));
+            HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)beta->data, beta->d_fboxes.p, H->beta64.p, false));
             if (P.precision == 0) {
                 setup_faces<double>(R, H->beta64.p);
             } else {
-                fill<double>(R, 0, H->beta64.p, L0.full_even, 3);
+                fill<double>(R, 0, H->beta64.p, L0.full_even);
                 HIPCHK(launch_cast_f32(R.s, H->beta64.p, H->beta32.p, L0.nelem));
                 setup_faces<float>(R, H->beta32.p);
             }
         }
+        // ghost cells of the converted guess; from here on every producer of
+        // level-0 values refreshes the face ghosts it mirrors (push levels)
+        fill_faces<double>(R, 0, u);
         const double ih2 = 1.0 / (L0.h * L0.h);
         const FaceArrays<double> nf = no_faces<double>();
-        HIPCHK(launch_field_norm(R.s, f, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol, H->partials.p, kNormBlocks));
-        HIPCHK(launch_norm_final(R.s, H->partials.p, kNormBlocks, H->fnorm.p));
+        HIPCHK(launch_field_norm(R.s, L0.grid(), f, H->partials.p));
+        HIPCHK(launch_norm_final(R.s, H->partials.p, L0.ntcol, H->fnorm.p));
         norm_readback(R, ctx->h_norm, H->fnorm.p);
         const double fnorm = ctx->h_norm[0];
         info->f_inf = fnorm;
@@ -1058,17 +1187,17 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         int cyc = 0;
         if (fnorm > 0.0) {
             for (;; ++cyc) {
-                fill<double>(R, 0, u, L0.faces_odd, 3);
+                if (!L0.push) fill_faces<double>(R, 0, u);
                 R.pre(0, kStageResid);
                 if (P.precision == 0) {
-                    HIPCHK(launch_resid_norm<double>(R.s, u, f, beta ? H->beta64.p : nullptr, nf, L0.d_rb.p, L0.wcol.p,
-                                                     L0.nwcol, L0.ncol, ih2, nullptr, H->partials.p, kNormBlocks));
+                    HIPCHK(launch_resid<double, double>(R.s, L0.grid(), u, f, beta ? H->beta64.p : nullptr, nf, ih2,
+                                                        (double*)nullptr, H->partials.p));
                 } else {
-                    HIPCHK(launch_resid_cast(R.s, u, f, beta ? H->beta64.p : nullptr, nf, L0.d_rb.p, L0.wcol.p,
-                                             L0.nwcol, L0.ncol, ih2, H->f32[0]->p, H->partials.p, kNormBlocks));
+                    HIPCHK(launch_resid<double, float>(R.s, L0.grid(), u, f, beta ? H->beta64.p : nullptr, nf, ih2,
+                                                       H->f32[0]->p, H->partials.p));
                 }
                 R.post(0, kStageResid);
-                HIPCHK(launch_norm_final(R.s, H->partials.p, kNormBlocks, H->fnorm.p));
+                HIPCHK(launch_norm_final(R.s, H->partials.p, L0.ntcol, H->fnorm.p));
                 norm_readback(R, ctx->h_norm, H->fnorm.p);
                 const double rinf = ctx->h_norm[2] > 0 ? NAN : ctx->h_norm[0];
                 if (cyc < 256) {
@@ -1090,14 +1219,14 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
                 } else {
                     HIPCHK(launch_zero<float>(R.s, H->u32[0]->p, L0.nelem));
                     vcycle<float>(R, 0);
-                    HIPCHK(launch_add_f32(R.s, u, H->u32[0]->p, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol));
+                    HIPCHK(launch_add_f32(R.s, L0.grid(), u, H->u32[0]->p));
                 }
             }
         }
         info->cycles = cyc;
         if (ba->per[0] && ba->per[1] && ba->per[2])
-            HIPCHK(launch_mean_sub(R.s, u, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol, H->partials.p, kNormBlocks));
-        HIPCHK(launch_rb_to_fab(R.s, u, L0.d_rb.p, (double*)phi->data, phi->d_fboxes.p, L0.wcol.p, L0.nwcol, L0.ncol));
+            HIPCHK(launch_mean_sub(R.s, L0.grid(), u, H->partials.p));
+        HIPCHK(launch_rb_to_fab(R.s, L0.grid(), u, (double*)phi->data, phi->d_fboxes.p));
         HIPCHK(hipStreamSynchronize(R.s));
         ctx->prof.harvest();
         info->status = status;
@@ -1150,10 +1279,10 @@ static bxmg_status stage_prepare(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab 
 
 static void stage_load(Run& R, Hier* H, bxmg_multifab phi, bxmg_multifab rhs, bxmg_multifab beta) {
     const Level& L0 = *H->L[0];
-    HIPCHK(launch_fab_to_rb(R.s, (const double*)phi->data, phi->d_fboxes.p, H->u64[0]->p, false, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol));
-    if (rhs) HIPCHK(launch_fab_to_rb(R.s, (const double*)rhs->data, rhs->d_fboxes.p, H->f64[0]->p, false, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol));
+    HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)phi->data, phi->d_fboxes.p, H->u64[0]->p, false));
+    if (rhs) HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)rhs->data, rhs->d_fboxes.p, H->f64[0]->p, false));
     if (beta) {
-        HIPCHK(launch_fab_to_rb(R.s, (const double*)beta->data, beta->d_fboxes.p, H->beta64.p, false, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol));
+        HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)beta->data, beta->d_fboxes.p, H->beta64.p, false));
         setup_faces<double>(R, H->beta64.p);
     }
 }
@@ -1171,10 +1300,10 @@ bxmg_status bxmg_gs_colour(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab rhs, b
         Run R{H, ctx->stream, 0, 0, 2, 1e-12};
         stage_load(R, H, phi, rhs, beta);
         const Level& L0 = *H->L[0];
-        fill<double>(R, 0, H->u64[0]->p, L0.faces_odd, 1 << (colour ^ 1));
-        HIPCHK(launch_gs<double>(R.s, H->u64[0]->p, H->f64[0]->p, beta ? H->beta64.p : nullptr, no_faces<double>(),
-                                 L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol, L0.h * L0.h, colour));
-        HIPCHK(launch_rb_to_fab(R.s, H->u64[0]->p, L0.d_rb.p, (double*)phi->data, phi->d_fboxes.p, L0.wcol.p, L0.nwcol, L0.ncol));
+        fill<double>(R, 0, H->u64[0]->p, L0.face[colour ^ 1]);
+        HIPCHK(launch_gs<double>(R.s, L0.grid(), H->u64[0]->p, H->f64[0]->p, beta ? H->beta64.p : nullptr,
+                                 no_faces<double>(), L0.h * L0.h, colour));
+        HIPCHK(launch_rb_to_fab(R.s, L0.grid(), H->u64[0]->p, (double*)phi->data, phi->d_fboxes.p));
         HIPCHK(hipStreamSynchronize(R.s));
     } catch (HipError& e) {
         return fail(BXMG_EDEVICE, std::string("gs_colour: ") + e.where + ": " + hipGetErrorString(e.e));
@@ -1196,13 +1325,12 @@ bxmg_status bxmg_residual(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab rhs, bx
         Run R{H, ctx->stream, 0, 0, 2, 1e-12};
         stage_load(R, H, phi, rhs, beta);
         const Level& L0 = *H->L[0];
-        fill<double>(R, 0, H->u64[0]->p, L0.faces_odd, 3);
+        fill_faces<double>(R, 0, H->u64[0]->p);
         // r overwrites f in place (each cell reads its own f, then stores r)
-        HIPCHK(launch_resid_norm<double>(R.s, H->u64[0]->p, H->f64[0]->p, beta ? H->beta64.p : nullptr,
-                                         no_faces<double>(), L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol,
-                                         1.0 / (L0.h * L0.h), H->f64[0]->p, H->partials.p, kNormBlocks));
-        HIPCHK(launch_norm_final(R.s, H->partials.p, kNormBlocks, H->fnorm.p));
-        HIPCHK(launch_rb_to_fab(R.s, H->f64[0]->p, L0.d_rb.p, (double*)r->data, r->d_fboxes.p, L0.wcol.p, L0.nwcol, L0.ncol));
+        HIPCHK(launch_resid<double, double>(R.s, L0.grid(), H->u64[0]->p, H->f64[0]->p, beta ? H->beta64.p : nullptr,
+                                            no_faces<double>(), 1.0 / (L0.h * L0.h), H->f64[0]->p, H->partials.p));
+        HIPCHK(launch_norm_final(R.s, H->partials.p, L0.ntcol, H->fnorm.p));
+        HIPCHK(launch_rb_to_fab(R.s, L0.grid(), H->f64[0]->p, (double*)r->data, r->d_fboxes.p));
         norm_readback(R, ctx->h_norm, H->fnorm.p);
         if (norms) {
             norms[0] = ctx->h_norm[2] > 0 ? NAN : ctx->h_norm[0];
@@ -1232,9 +1360,9 @@ bxmg_status bxmg_restrict(bxmg_ctx ctx, bxmg_multifab fine, bxmg_multifab coarse
         Run R{H, ctx->stream, 0, 0, 2, 1e-12};
         const Level& L0 = *H->L[0];
         const Level& L1 = *H->L[1];
-        HIPCHK(launch_fab_to_rb(R.s, (const double*)fine->data, fine->d_fboxes.p, H->u64[0]->p, false, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol));
-        HIPCHK(launch_restrict_plain<double>(R.s, H->u64[0]->p, H->f64[1]->p, L0.d_rb.p, L1.d_rb.p, L0.wdown.p, L0.nwdown, L0.ndown));
-        HIPCHK(launch_rb_to_fab(R.s, H->f64[1]->p, L1.d_rb.p, (double*)coarse->data, coarse->d_fboxes.p, L1.wcol.p, L1.nwcol, L1.ncol));
+        HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)fine->data, fine->d_fboxes.p, H->u64[0]->p, false));
+        HIPCHK(launch_restrict_plain<double>(R.s, H->xgrid(0), H->u64[0]->p, H->f64[1]->p));
+        HIPCHK(launch_rb_to_fab(R.s, L1.grid(), H->f64[1]->p, (double*)coarse->data, coarse->d_fboxes.p));
         HIPCHK(hipStreamSynchronize(R.s));
     } catch (HipError& e) {
         return fail(BXMG_EDEVICE, std::string("restrict: ") + e.where + ": " + hipGetErrorString(e.e));
@@ -1257,11 +1385,11 @@ bxmg_status bxmg_prolong_add(bxmg_ctx ctx, bxmg_multifab coarse, bxmg_multifab f
         Run R{H, ctx->stream, 0, 0, order, 1e-12};
         const Level& L0 = *H->L[0];
         const Level& L1 = *H->L[1];
-        HIPCHK(launch_fab_to_rb(R.s, (const double*)fine->data, fine->d_fboxes.p, H->u64[0]->p, false, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol));
-        HIPCHK(launch_fab_to_rb(R.s, (const double*)coarse->data, coarse->d_fboxes.p, H->u64[1]->p, false, L1.d_rb.p, L1.wcol.p, L1.nwcol, L1.ncol));
-        fill<double>(R, 1, H->u64[1]->p, L1.full_odd, 3);
-        HIPCHK(launch_prolong<double>(R.s, H->u64[1]->p, H->u64[0]->p, L0.d_rb.p, L1.d_rb.p, L0.wdown.p, L0.nwdown, L0.ndown, order));
-        HIPCHK(launch_rb_to_fab(R.s, H->u64[0]->p, L0.d_rb.p, (double*)fine->data, fine->d_fboxes.p, L0.wcol.p, L0.nwcol, L0.ncol));
+        HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)fine->data, fine->d_fboxes.p, H->u64[0]->p, false));
+        HIPCHK(launch_fab_to_rb(R.s, L1.grid(), (const double*)coarse->data, coarse->d_fboxes.p, H->u64[1]->p, false));
+        fill<double>(R, 1, H->u64[1]->p, L1.full);
+        HIPCHK(launch_prolong<double>(R.s, H->xgrid(0), H->u64[1]->p, H->u64[0]->p, order));
+        HIPCHK(launch_rb_to_fab(R.s, L0.grid(), H->u64[0]->p, (double*)fine->data, fine->d_fboxes.p));
         HIPCHK(hipStreamSynchronize(R.s));
     } catch (HipError& e) {
         return fail(BXMG_EDEVICE, std::string("prolong_add: ") + e.where + ": " + hipGetErrorString(e.e));
@@ -1284,10 +1412,10 @@ bxmg_status bxmg_bottom_solve(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab rhs
         if (st != BXMG_OK) return st;
         Run R{H, ctx->stream, 0, 0, 2, rtol};
         const Level& L0 = *H->L[0];
-        HIPCHK(launch_fab_to_rb(R.s, (const double*)rhs->data, rhs->d_fboxes.p, H->f64[0]->p, false, L0.d_rb.p, L0.wcol.p, L0.nwcol, L0.ncol));
+        HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)rhs->data, rhs->d_fboxes.p, H->f64[0]->p, false));
         HIPCHK(launch_bottom<double>(R.s, H->u64[0]->p, H->f64[0]->p, no_faces<double>(), false, L0.d_rb.p,
                                      (int)L0.boxes.size(), L0.dom.lo, L0.dom.hi, H->per, L0.h, rtol, H->iters.p));
-        HIPCHK(launch_rb_to_fab(R.s, H->u64[0]->p, L0.d_rb.p, (double*)phi->data, phi->d_fboxes.p, L0.wcol.p, L0.nwcol, L0.ncol));
+        HIPCHK(launch_rb_to_fab(R.s, L0.grid(), H->u64[0]->p, (double*)phi->data, phi->d_fboxes.p));
         int it = 0;
         HIPCHK(hipMemcpyAsync(&it, H->iters.p, sizeof(int), hipMemcpyDeviceToHost, R.s));
         HIPCHK(hipStreamSynchronize(R.s));

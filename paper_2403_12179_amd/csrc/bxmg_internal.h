@@ -8,6 +8,7 @@
 namespace bxmg {
 
 constexpr int kMaxBottomCells = 4096;  // bottom level: one workgroup, vectors in LDS
+constexpr int kBottomGrown = 6144;     // ... and at most this many cells with its ghost layer
 constexpr int kBlock = 256;            // threads per block of the cell kernels
 
 // Box of a level in the multigrid hierarchy, colour-split storage ("RB").
@@ -15,6 +16,13 @@ constexpr int kBlock = 256;            // threads per block of the cell kernels
 // rows: element (i,j,k) sits at
 //   base + c*cstride + ((k-glo.z)*G.y + (j-glo.y))*H + ((i-glo.x)>>1).
 // Both colours of a row share the half-row index m = (i-glo.x)>>1.
+//
+// Face neighbours: for direction q = 2*d + (0 low side, 1 high side), the
+// 1-cell slab just outside the box across that face lies in box nb[q] once
+// coordinate d is shifted by shift[q] (a periodic image), or, when
+// nb[q] == -1, outside a homogeneous-Dirichlet domain face.  Conversely a
+// cell of this box on face q is the ghost cell (coordinate d + shift[q]) of
+// box nb[q].  nb[q] == -2: not resolvable through one box.
 struct RBox {
     int lo[3], hi[3];  // valid cells, global
     int glo[3];        // lo - ng
@@ -23,6 +31,8 @@ struct RBox {
     int pid;           // problem id (batches); 0 for a single problem
     long long base;    // element offset of colour 0
     long long cstride; // elements between colour 0 and colour 1
+    int nb[6];
+    int shift[6];
 };
 
 // Box of a caller MultiFab (F-order): element (i,j,k,n) at
@@ -35,9 +45,9 @@ struct FBox {
     long long cs;  // component stride
 };
 
-// One rectangular ghost-copy region: destination cells dlo + (x,y,z),
-// 0 <= x < n[0] ..., of box dbox take neg ? -v : v, v = the cell
-// s_d = sgn_d * dst_d + soff_d of box sbox.  prefix = cells before it.
+// One rectangular ghost-copy region (caller MultiFabs): destination cells
+// dlo + (x,y,z), 0 <= x < n[0] ..., of box dbox take neg ? -v : v, v = the
+// cell s_d = sgn_d * dst_d + soff_d of box sbox.  prefix = cells before it.
 struct Tag {
     int dbox, sbox;
     int dlo[3];
@@ -49,16 +59,24 @@ struct Tag {
     long long prefix;
 };
 
-// Work decomposition of a level's valid cells of one colour (or of the
-// coarse cells of every fine box) flattened over boxes: cell g of the
-// launch belongs to box b with cstart[b] <= g < cstart[b+1]; within the box
-// it is (t, j, k) with t fastest, t < tn[b] (= half-row cells or coarse x).
-struct WorkBox {
-    long long cstart;
-    int tn, ny, nz;
-    int box;  // box index in the level
-    int cbox; // coarse box owning coarsen(box) (transfer kernels), else -1
-    int pad;
+// One ghost cell of a level (RB storage): data[dst] = +-data[src & 0x7fffffff],
+// negated when bit 31 of src is set.
+struct GhostCopy {
+    uint32_t dst, src;
+};
+
+// A tile is the work of one block: threads (tx, ty, tz) of a TX x TY x TZ
+// block cover x-index x0 + tx, y-index y0 + ty and z-indices
+// z0 + tz + z*TZ for z < ZC, relative to the box's lower corner; x counts
+// half-row cells (colour kernels) or coarse cells (transfer kernels).
+struct Tile {
+    int box;
+    int x0, y0, z0;
+};
+
+struct TileShape {
+    int lx, ly, lz;  // log2 of TX, TY, TZ (TX*TY*TZ = kBlock)
+    int zc;          // z iterations per thread
 };
 
 // Face coefficients of a level >= 1: global arrays over the level domain,
@@ -70,55 +88,71 @@ struct FaceArrays {
     int n[3];  // domain extents
 };
 
+// Tiled launch of one level: its boxes, tiles and tile shape.  push != 0:
+// every box face is resolvable (RBox::nb), and the kernels that write the
+// level's values also write them into the face ghost cells that mirror
+// them, so no separate face-ghost refresh is needed.
+struct Grid {
+    const RBox* boxes;
+    const Tile* tiles;
+    int ntiles;
+    TileShape sh;
+    int push;
+};
+
+// Transfer launch fine <-> coarse: tiles over the coarse cells of every fine
+// box; cbox[b] = coarse box holding the coarsened fine box b.
+struct XGrid {
+    const RBox* fboxes;
+    const RBox* cboxes;
+    const int* cbox;
+    const Tile* tiles;
+    int ntiles;
+    TileShape sh;
+    int push;  // as Grid::push, for the fine level
+};
+
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `s` and return hipSuccess or the launch error.
-hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const RBox* boxes, const Tag* tags, int ntags,
-                          long long ncells, int cmask);
+hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* list, long long n);
 hipError_t launch_fill_fab(hipStream_t s, void* data, bool f32, const FBox* boxes, const Tag* tags, int ntags,
                            long long ncells, int comp0, int ncomp);
 
 template <class T>
-hipError_t launch_gs(hipStream_t s, T* u, const T* f, const T* beta, FaceArrays<T> fa, const RBox* boxes,
-                     const WorkBox* work, int nwork, long long ncells, T h2, int colour);
+hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* beta, FaceArrays<T> fa, T h2,
+                     int colour);
+
+// r = f - L u on both colours, optional store of r (R = T, or float for the
+// mixed-precision cast), per-tile partial norms (max|r|, sum r^2, bad count)
+template <class T, class R>
+hipError_t launch_resid(hipStream_t s, const Grid& g, const T* u, const T* f, const T* beta, FaceArrays<T> fa,
+                        T ih2, R* r, double* partials);
+hipError_t launch_norm_final(hipStream_t s, const double* partials, int n, double* out3);
+hipError_t launch_field_norm(hipStream_t s, const Grid& g, const double* x, double* partials);
 
 template <class T>
-hipError_t launch_resid_norm(hipStream_t s, const T* u, const T* f, const T* beta, FaceArrays<T> fa,
-                             const RBox* boxes, const WorkBox* work, int nwork, long long ncells, T ih2, T* r,
-                             double* partials, int nblocks);
-hipError_t launch_norm_final(hipStream_t s, const double* partials, int nblocks, double* out3);
-
+hipError_t launch_resid_restrict(hipStream_t s, const XGrid& x, const T* u, const T* f, const T* beta,
+                                 FaceArrays<T> fa, T ih2, T* fc);
 template <class T>
-hipError_t launch_resid_restrict(hipStream_t s, const T* u, const T* f, const T* beta, FaceArrays<T> fa,
-                                 const RBox* fboxes, const RBox* cboxes, const WorkBox* work, int nwork,
-                                 long long ncells, T ih2, T* fc);
+hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* fc);
 template <class T>
-hipError_t launch_prolong(hipStream_t s, const T* ec, T* uf, const RBox* fboxes, const RBox* cboxes,
-                          const WorkBox* work, int nwork, long long ncells, int order);
-template <class T>
-hipError_t launch_restrict_plain(hipStream_t s, const T* rf, T* fc, const RBox* fboxes, const RBox* cboxes,
-                                 const WorkBox* work, int nwork, long long ncells);
+hipError_t launch_prolong(hipStream_t s, const XGrid& x, const T* ec, T* uf, int order);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n);
+hipError_t launch_cast_f32(hipStream_t s, const double* src, float* dst, long long n);
 
 // layout conversions: F-order caller MultiFab (FP64, comp 0) <-> RB level
-hipError_t launch_fab_to_rb(hipStream_t s, const double* fab, const FBox* fb, void* rb, bool f32, const RBox* rbx,
-                            const WorkBox* work, int nwork, long long ncells);
-hipError_t launch_rb_to_fab(hipStream_t s, const double* rb, const RBox* rbx, double* fab, const FBox* fb,
-                            const WorkBox* work, int nwork, long long ncells);
+hipError_t launch_fab_to_rb(hipStream_t s, const Grid& g, const double* fab, const FBox* fb, void* rb, bool f32);
+hipError_t launch_rb_to_fab(hipStream_t s, const Grid& g, const double* rb, double* fab, const FBox* fb);
+hipError_t launch_add_f32(hipStream_t s, const Grid& g, double* u, const float* e);
 
-// mixed precision: r32 = float(f - L u) with fused norms; u64 += e32
-hipError_t launch_resid_cast(hipStream_t s, const double* u, const double* f, const double* beta,
-                             FaceArrays<double> fa, const RBox* boxes, const WorkBox* work, int nwork,
-                             long long ncells, double ih2, float* r32, double* partials, int nblocks);
-hipError_t launch_add_f32(hipStream_t s, double* u, const float* e, const RBox* boxes, const WorkBox* work,
-                          int nwork, long long ncells);
-hipError_t launch_cast_f32(hipStream_t s, const double* src, float* dst, long long n);
+// periodic projection: subtract the mean of the valid cells
+hipError_t launch_mean_sub(hipStream_t s, const Grid& g, double* u, double* scratch);
 
 // variable coefficient setup
 template <class T>
-hipError_t launch_faces_from_cells(hipStream_t s, const T* beta, const RBox* fboxes, const WorkBox* work, int nwork,
-                                   long long ncells, int d, FaceArrays<T> out, T* dst);
+hipError_t launch_faces_from_cells(hipStream_t s, const XGrid& x, const T* beta, int d, FaceArrays<T> out, T* dst);
 template <class T>
 hipError_t launch_faces_coarsen(hipStream_t s, FaceArrays<T> fine, FaceArrays<T> coarse, int d, T* dst);
 
@@ -127,13 +161,5 @@ template <class T>
 hipError_t launch_bottom(hipStream_t s, T* u, const T* f, FaceArrays<T> fa, bool var, const RBox* boxes, int nboxes,
                          const int* dom_lo, const int* dom_hi, const int* periodic, double h, double rtol,
                          int* iters_out);
-
-// max |x|, sum x^2, non-finite count of an RB field's valid cells -> partials
-hipError_t launch_field_norm(hipStream_t s, const double* x, const RBox* boxes, const WorkBox* work, int nwork,
-                             long long ncells, double* partials, int nblocks);
-
-// periodic projection of a level-0 RB field: subtract the mean of valid cells
-hipError_t launch_mean_sub(hipStream_t s, double* u, const RBox* boxes, const WorkBox* work, int nwork,
-                           long long ncells, double* scratch, int nblocks);
 
 }  // namespace bxmg

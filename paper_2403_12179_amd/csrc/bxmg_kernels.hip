@@ -1,13 +1,20 @@
-// HIP kernels of the multigrid path, written for gfx950 (wave64, 256 CUs).
+// HIP kernels of the multigrid path, written for gfx950 (wave64, 256 CUs in
+// 8 XCDs).
 //
 // Every stage is one fused launch over all boxes of a level (the fused
-// multi-box launch of the paper, Section 3.2): a thread's global index is
-// mapped to (box, cell) through a flattened work list, so 512 boxes of 32^3
-// run as one grid, like one 256^3 box.  The level data uses a colour-split
-// ("red-black") layout: the cells of one colour of a box row are contiguous,
-// so a half-sweep streams only the colour it reads (the other one) plus the
-// right-hand side of the colour it writes -- 1.5 arrays per half-sweep.
-// All stages are bandwidth-bound (<= 0.5 flop per byte): no matrix cores.
+// multi-box launch of the paper, Section 3.2): the host cuts each box into
+// tiles and one block works one tile, so 512 boxes of 32^3 run as one grid,
+// like one 256^3 box.  A block reads its tile descriptor once; threads find
+// their cells with shifts and masks only, and walk ZC planes in z.  Blocks
+// are dispatched round-robin over the 8 XCDs, so the block -> tile map gives
+// each XCD a contiguous run of tiles: neighbouring tiles then share that
+// XCD's L2 for their halo rows.
+//
+// Level data uses a colour-split ("red-black") layout: the cells of one
+// colour of a box row are contiguous, so a half-sweep streams only the colour
+// it reads (the other one) plus the right-hand side of the colour it writes,
+// 1.5 arrays per half-sweep.  All stages are bandwidth-bound (<= 0.5 flop per
+// byte): no matrix cores.
 //
 // Floating point: built with -ffp-contract=off; every expression below
 // fixes its operation order, so results are reproducible run to run.
@@ -20,16 +27,6 @@
 namespace bxmg {
 
 // ----------------------------------------------------------------- helpers
-__device__ __forceinline__ int find_work(const WorkBox* __restrict__ w, int n, long long g) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (w[mid].cstart <= g) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ int find_tag(const Tag* __restrict__ t, int n, long long g) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -57,45 +54,40 @@ __device__ __forceinline__ T harm(T a, T b) {
     return (a * b) * T(2) / (a + b);
 }
 
-// Colour-cell decode: g -> (box, i, j, k) of colour c; false if padding.
-struct Cell {
-    int box, i, j, k;
-};
-
-__device__ __forceinline__ bool decode_colour(const WorkBox* __restrict__ work, int nwork, const RBox* __restrict__ boxes,
-                                              long long g, int c, Cell& out, RBox& B) {
-    const int w = find_work(work, nwork, g);
-    const WorkBox wb = work[w];
-    const long long loc = g - wb.cstart;
-    const int t = (int)(loc % wb.tn);
-    const long long rem = loc / wb.tn;
-    B = boxes[wb.box];
-    const int j = B.lo[1] + (int)(rem % wb.ny);
-    const int k = B.lo[2] + (int)(rem / wb.ny);
-    const int i = B.lo[0] + 2 * t + ((c - B.lo[0] - j - k) & 1);
-    out = Cell{wb.box, i, j, k};
-    return i <= B.hi[0];
+// Block -> tile: XCD x (= block % 8) receives tiles [x*n/8, (x+1)*n/8).
+__device__ __forceinline__ int tile_index() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    if ((nb & 7) == 0) return (b & 7) * (nb >> 3) + (b >> 3);
+    return b;
 }
 
-// Coarse-cell decode for the transfer kernels: g -> (fine box, coarse cell).
-__device__ __forceinline__ void decode_coarse(const WorkBox* __restrict__ work, int nwork, long long g, WorkBox& wb,
-                                              int& I, int& J, int& K) {
-    const int w = find_work(work, nwork, g);
-    wb = work[w];
-    const long long loc = g - wb.cstart;
-    I = (int)(loc % wb.tn);
-    const long long rem = loc / wb.tn;
-    J = (int)(rem % wb.ny);
-    K = (int)(rem / wb.ny);
+struct TileThread {
+    int x, y, z0, dz;  // box-relative x and y, first z and z step
+};
+
+__device__ __forceinline__ TileThread tile_thread(const Tile& tl, const TileShape& sh) {
+    const int tid = threadIdx.x;
+    TileThread r;
+    r.x = tl.x0 + (tid & ((1 << sh.lx) - 1));
+    r.y = tl.y0 + ((tid >> sh.lx) & ((1 << sh.ly) - 1));
+    r.z0 = tl.z0 + (tid >> (sh.lx + sh.ly));
+    r.dz = 1 << sh.lz;
+    return r;
+}
+
+// x index of the colour-c cell number t of row (j, k) of box B
+__device__ __forceinline__ int colour_i(const RBox& B, int t, int j, int k, int c) {
+    return B.lo[0] + 2 * t + ((c - B.lo[0] - j - k) & 1);
 }
 
 // Stencil sums of one cell: su = sum_faces beta*u_nb, sb = sum_faces beta,
-// in the fixed order ((x- + x+) + (y- + y+)) + (z- + z+).
+// in the fixed order ((x- + x+) + (y- + y+)) + (z- + z+).  Neighbours across
+// a box face are read from the box's ghost cells.
 //   MODE 0: constant coefficient; 1: level 0, faces = harmonic means of the
 //   cell beta (same layout as u); 2: coarse level, global face arrays.
 template <class T, int MODE>
 __device__ __forceinline__ void stencil(const T* __restrict__ u, const T* __restrict__ beta, const FaceArrays<T>& fa,
-                                        const RBox& B, int i, int j, int k, T& su, T& sb, T& uc) {
+                                        const RBox& B, int i, int j, int k, T& su, T& sb, T& uc, long long& idx) {
     const int c = (i + j + k) & 1;
     const long long rc = rb_row(B, c, j, k);
     const long long ro = rb_row(B, c ^ 1, j, k);
@@ -105,14 +97,15 @@ __device__ __forceinline__ void stencil(const T* __restrict__ u, const T* __rest
     const T uxm = u[ro + mxm], uxp = u[ro + mxp];
     const T uym = u[ro - Hy + m], uyp = u[ro + Hy + m];
     const T uzm = u[ro - Hz + m], uzp = u[ro + Hz + m];
-    uc = u[rc + m];
+    idx = rc + m;
+    uc = u[idx];
     if constexpr (MODE == 0) {
         su = ((uxm + uxp) + (uym + uyp)) + (uzm + uzp);
         sb = T(6);
     } else {
         T bxm, bxp, bym, byp, bzm, bzp;
         if constexpr (MODE == 1) {
-            const T bc = beta[rc + m];
+            const T bc = beta[idx];
             bxm = harm(beta[ro + mxm], bc);
             bxp = harm(bc, beta[ro + mxp]);
             bym = harm(beta[ro - Hy + m], bc);
@@ -137,68 +130,35 @@ __device__ __forceinline__ void stencil(const T* __restrict__ u, const T* __rest
     }
 }
 
-// -------------------------------------------------------------- ghost fill
-// One thread per destination cell of the flattened tag list.
+// Ghost exchange fused into a producer: cell (i,j,k) of box B just took value
+// v; write v into every face ghost cell that mirrors it -- the ghost of the
+// neighbouring box across each face the cell lies on (periodic images
+// included) and, across a homogeneous-Dirichlet domain face, -v into the
+// box's own ghost beyond it.  Exactly the values a ghost refresh would copy.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_fill_rb(T* __restrict__ data, const RBox* __restrict__ boxes,
-                                                   const Tag* __restrict__ tags, int ntags, long long ncells, int cmask) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncells) return;
-    const Tag t = tags[find_tag(tags, ntags, g)];
-    const long long loc = g - t.prefix;
-    const int x = (int)(loc % t.n[0]);
-    const int y = (int)((loc / t.n[0]) % t.n[1]);
-    const int z = (int)(loc / ((long long)t.n[0] * t.n[1]));
-    const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
-    if (!((cmask >> ((di + dj + dk) & 1)) & 1)) return;
-    const int si = t.sgn[0] * di + t.soff[0], sj = t.sgn[1] * dj + t.soff[1], sk = t.sgn[2] * dk + t.soff[2];
-    T v = data[rb_idx(boxes[t.sbox], si, sj, sk)];
-    if (t.neg) v = -v;
-    data[rb_idx(boxes[t.dbox], di, dj, dk)] = v;
+__device__ __forceinline__ void push_ghosts(T* __restrict__ u, const RBox* __restrict__ boxes, const RBox& B, int i,
+                                            int j, int k, T v) {
+    const int c[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            if (c[d] != (side ? B.hi[d] : B.lo[d])) continue;
+            const int q = 2 * d + side;
+            const int nb = B.nb[q];
+            int t[3] = {i, j, k};
+            if (nb >= 0) {
+                t[d] += B.shift[q];
+                u[rb_idx(boxes[nb], t[0], t[1], t[2])] = v;
+            } else {
+                t[d] += side ? 1 : -1;
+                u[rb_idx(B, t[0], t[1], t[2])] = -v;
+            }
+        }
 }
 
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_fill_fab(T* __restrict__ data, const FBox* __restrict__ boxes,
-                                                    const Tag* __restrict__ tags, int ntags, long long ncells,
-                                                    int comp0, int ncomp) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncells) return;
-    const Tag t = tags[find_tag(tags, ntags, g)];
-    const long long loc = g - t.prefix;
-    const int x = (int)(loc % t.n[0]);
-    const int y = (int)((loc / t.n[0]) % t.n[1]);
-    const int z = (int)(loc / ((long long)t.n[0] * t.n[1]));
-    const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
-    const int si = t.sgn[0] * di + t.soff[0], sj = t.sgn[1] * dj + t.soff[1], sk = t.sgn[2] * dk + t.soff[2];
-    const FBox sb = boxes[t.sbox], db = boxes[t.dbox];
-    const long long s0 = fab_idx(sb, si, sj, sk), d0 = fab_idx(db, di, dj, dk);
-    for (int n = comp0; n < comp0 + ncomp; ++n) {
-        T v = data[s0 + n * sb.cs];
-        if (t.neg) v = -v;
-        data[d0 + n * db.cs] = v;
-    }
-}
-
-// ---------------------------------------------------- red-black smoothing
-// One colour: u_c = (su - h^2 f) / sb.  Reads only the other colour of u.
-template <class T, int MODE>
-__global__ void __launch_bounds__(kBlock) k_gs(T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ beta,
-                                              FaceArrays<T> fa, const RBox* __restrict__ boxes,
-                                              const WorkBox* __restrict__ work, int nwork, long long ncells, T h2,
-                                              int colour) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncells) return;
-    Cell q;
-    RBox B;
-    if (!decode_colour(work, nwork, boxes, g, colour, q, B)) return;
-    T su, sb, uc;
-    stencil<T, MODE>(u, beta, fa, B, q.i, q.j, q.k, su, sb, uc);
-    const long long idx = rb_idx(B, q.i, q.j, q.k);
-    u[idx] = (su - h2 * f[idx]) / sb;
-}
-
-// ---------------------------------------------------------------- residual
-// Block reduction of (max |r|, sum r^2, non-finite count) with a fixed tree.
+// Fixed-tree block reduction of (max, sum, sum): wave64 butterflies, then
+// the 4 wave results in order.  The result is valid in thread 0.
 __device__ __forceinline__ void block_reduce3(double& mx, double& s2, double& bad, double* sh) {
     for (int o = 32; o > 0; o >>= 1) {
         const double a = __shfl_xor(mx, o), b = __shfl_xor(s2, o), c = __shfl_xor(bad, o);
@@ -223,28 +183,91 @@ __device__ __forceinline__ void acc_norm(double rv, double& mx, double& s2, doub
     s2 = s2 + rv * rv;
 }
 
+// -------------------------------------------------------------- ghost fill
+// Level ghost cells: one precomputed (dst, src) pair per cell.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fill_rb(T* __restrict__ data, const GhostCopy* __restrict__ list, long long n) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const GhostCopy p = list[g];
+    const T v = data[p.src & 0x7fffffffu];
+    data[p.dst] = (p.src >> 31) ? -v : v;
+}
+
+// Caller MultiFabs (F-order, several components): region tags.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fill_fab(T* __restrict__ data, const FBox* __restrict__ boxes,
+                                                    const Tag* __restrict__ tags, int ntags, long long ncells,
+                                                    int comp0, int ncomp) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    const Tag t = tags[find_tag(tags, ntags, g)];
+    const long long loc = g - t.prefix;
+    const int x = (int)(loc % t.n[0]);
+    const int y = (int)((loc / t.n[0]) % t.n[1]);
+    const int z = (int)(loc / ((long long)t.n[0] * t.n[1]));
+    const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
+    const int si = t.sgn[0] * di + t.soff[0], sj = t.sgn[1] * dj + t.soff[1], sk = t.sgn[2] * dk + t.soff[2];
+    const FBox sb = boxes[t.sbox], db = boxes[t.dbox];
+    const long long s0 = fab_idx(sb, si, sj, sk), d0 = fab_idx(db, di, dj, dk);
+    for (int n = comp0; n < comp0 + ncomp; ++n) {
+        T v = data[s0 + n * sb.cs];
+        if (t.neg) v = -v;
+        data[d0 + n * db.cs] = v;
+    }
+}
+
+// ---------------------------------------------------- red-black smoothing
+// One colour: u_c = (su - h^2 f) / sb.  Reads only the other colour of u.
+template <class T, int MODE, bool PUSH>
+__global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const T* __restrict__ f,
+                                              const T* __restrict__ beta, FaceArrays<T> fa, T h2, int colour) {
+    const Tile tl = g.tiles[tile_index()];
+    const RBox B = g.boxes[tl.box];
+    const TileThread th = tile_thread(tl, g.sh);
+    const int j = B.lo[1] + th.y;
+    if (j > B.hi[1]) return;
+    for (int z = 0; z < g.sh.zc; ++z) {
+        const int k = B.lo[2] + th.z0 + z * th.dz;
+        if (k > B.hi[2]) break;
+        const int i = colour_i(B, th.x, j, k, colour);
+        if (i > B.hi[0]) continue;
+        T su, sb, uc;
+        long long idx;
+        stencil<T, MODE>(u, beta, fa, B, i, j, k, su, sb, uc, idx);
+        const T v = (su - h2 * f[idx]) / sb;
+        u[idx] = v;
+        if constexpr (PUSH) push_ghosts(u, g.boxes, B, i, j, k, v);
+    }
+}
+
+// ---------------------------------------------------------------- residual
 // r = f - (su - sb u) / h^2 on both colours; optional store of r (same type
 // and layout) or of float(r) (mixed precision); fused norms per block.
 template <class T, int MODE, class R>
-__global__ void __launch_bounds__(kBlock) k_resid(const T* __restrict__ u, const T* __restrict__ f,
-                                                 const T* __restrict__ beta, FaceArrays<T> fa,
-                                                 const RBox* __restrict__ boxes, const WorkBox* __restrict__ work,
-                                                 int nwork, long long ncells, T ih2, R* __restrict__ r,
-                                                 double* __restrict__ partials) {
+__global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ u, const T* __restrict__ f,
+                                                 const T* __restrict__ beta, FaceArrays<T> fa, T ih2,
+                                                 R* __restrict__ r, double* __restrict__ partials) {
     __shared__ double sh[3 * (kBlock / 64)];
     double mx = 0.0, s2 = 0.0, bad = 0.0;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < ncells; g += stride) {
-        for (int c = 0; c < 2; ++c) {
-            Cell q;
-            RBox B;
-            if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
-            T su, sb, uc;
-            stencil<T, MODE>(u, beta, fa, B, q.i, q.j, q.k, su, sb, uc);
-            const long long idx = rb_idx(B, q.i, q.j, q.k);
-            const T rv = f[idx] - (su - sb * uc) * ih2;
-            if (r) r[idx] = (R)rv;
-            acc_norm((double)rv, mx, s2, bad);
+    const Tile tl = g.tiles[tile_index()];
+    const RBox B = g.boxes[tl.box];
+    const TileThread th = tile_thread(tl, g.sh);
+    const int j = B.lo[1] + th.y;
+    if (j <= B.hi[1]) {
+        for (int z = 0; z < g.sh.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            if (k > B.hi[2]) break;
+            for (int c = 0; c < 2; ++c) {
+                const int i = colour_i(B, th.x, j, k, c);
+                if (i > B.hi[0]) continue;
+                T su, sb, uc;
+                long long idx;
+                stencil<T, MODE>(u, beta, fa, B, i, j, k, su, sb, uc, idx);
+                const T rv = f[idx] - (su - sb * uc) * ih2;
+                if (r) r[idx] = (R)rv;
+                acc_norm((double)rv, mx, s2, bad);
+            }
         }
     }
     block_reduce3(mx, s2, bad, sh);
@@ -268,6 +291,38 @@ __global__ void __launch_bounds__(kBlock) k_norm_final(const double* __restrict_
     if (threadIdx.x == 0) { out[0] = mx; out[1] = s2; out[2] = bad; }
 }
 
+// Norms of a field's valid cells (the right-hand side's max norm).
+__global__ void __launch_bounds__(kBlock) k_field_norm(Grid g, const double* __restrict__ x,
+                                                      double* __restrict__ partials) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    const Tile tl = g.tiles[tile_index()];
+    const RBox B = g.boxes[tl.box];
+    const TileThread th = tile_thread(tl, g.sh);
+    const int j = B.lo[1] + th.y;
+    if (j <= B.hi[1])
+        for (int z = 0; z < g.sh.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            if (k > B.hi[2]) break;
+            for (int c = 0; c < 2; ++c) {
+                const int i = colour_i(B, th.x, j, k, c);
+                if (i <= B.hi[0]) acc_norm(x[rb_idx(B, i, j, k)], mx, s2, bad);
+            }
+        }
+    block_reduce3(mx, s2, bad, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = mx;
+        partials[3 * blockIdx.x + 1] = s2;
+        partials[3 * blockIdx.x + 2] = bad;
+    }
+}
+
+// ---------------------------------------------------------- fine <-> coarse
+// Coarse cell (I, J, K) of the tile's fine box, or false past its end.
+struct CoarseCell {
+    int I, J, K;
+};
+
 // ------------------------------------------------------ restriction (fused)
 // One thread per coarse cell: the residual at its 8 children, averaged
 // as ((r000 + r100) + (r010 + r110)) + ((r001 + r101) + (r011 + r111)), * 1/8.
@@ -275,56 +330,56 @@ template <class T, int MODE>
 __device__ __forceinline__ T resid_at(const T* __restrict__ u, const T* __restrict__ f, const T* __restrict__ beta,
                                       const FaceArrays<T>& fa, const RBox& B, int i, int j, int k, T ih2) {
     T su, sb, uc;
-    stencil<T, MODE>(u, beta, fa, B, i, j, k, su, sb, uc);
-    return f[rb_idx(B, i, j, k)] - (su - sb * uc) * ih2;
+    long long idx;
+    stencil<T, MODE>(u, beta, fa, B, i, j, k, su, sb, uc, idx);
+    return f[idx] - (su - sb * uc) * ih2;
 }
 
 template <class T, int MODE>
-__global__ void __launch_bounds__(kBlock) k_resid_restrict(const T* __restrict__ u, const T* __restrict__ f,
-                                                          const T* __restrict__ beta, FaceArrays<T> fa,
-                                                          const RBox* __restrict__ fboxes,
-                                                          const RBox* __restrict__ cboxes,
-                                                          const WorkBox* __restrict__ work, int nwork,
-                                                          long long ncells, T ih2, T* __restrict__ fc) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncells) return;
-    WorkBox wb;
-    int I, J, K;
-    decode_coarse(work, nwork, g, wb, I, J, K);
-    const RBox B = fboxes[wb.box];
-    I += B.lo[0] >> 1; J += B.lo[1] >> 1; K += B.lo[2] >> 1;
-    const int i = 2 * I, j = 2 * J, k = 2 * K;
-    const T r000 = resid_at<T, MODE>(u, f, beta, fa, B, i, j, k, ih2);
-    const T r100 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j, k, ih2);
-    const T r010 = resid_at<T, MODE>(u, f, beta, fa, B, i, j + 1, k, ih2);
-    const T r110 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j + 1, k, ih2);
-    const T r001 = resid_at<T, MODE>(u, f, beta, fa, B, i, j, k + 1, ih2);
-    const T r101 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j, k + 1, ih2);
-    const T r011 = resid_at<T, MODE>(u, f, beta, fa, B, i, j + 1, k + 1, ih2);
-    const T r111 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j + 1, k + 1, ih2);
-    const T s = ((r000 + r100) + (r010 + r110)) + ((r001 + r101) + (r011 + r111));
-    fc[rb_idx(cboxes[wb.cbox], I, J, K)] = s * T(0.125);
+__global__ void __launch_bounds__(kBlock) k_resid_restrict(XGrid x, const T* __restrict__ u, const T* __restrict__ f,
+                                                          const T* __restrict__ beta, FaceArrays<T> fa, T ih2,
+                                                          T* __restrict__ fc) {
+    const Tile tl = x.tiles[tile_index()];
+    const RBox B = x.fboxes[tl.box];
+    const RBox C = x.cboxes[x.cbox[tl.box]];
+    const TileThread th = tile_thread(tl, x.sh);
+    const int I = (B.lo[0] >> 1) + th.x, J = (B.lo[1] >> 1) + th.y;
+    if (I > (B.hi[0] >> 1) || J > (B.hi[1] >> 1)) return;
+    for (int z = 0; z < x.sh.zc; ++z) {
+        const int K = (B.lo[2] >> 1) + th.z0 + z * th.dz;
+        if (K > (B.hi[2] >> 1)) break;
+        const int i = 2 * I, j = 2 * J, k = 2 * K;
+        const T r000 = resid_at<T, MODE>(u, f, beta, fa, B, i, j, k, ih2);
+        const T r100 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j, k, ih2);
+        const T r010 = resid_at<T, MODE>(u, f, beta, fa, B, i, j + 1, k, ih2);
+        const T r110 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j + 1, k, ih2);
+        const T r001 = resid_at<T, MODE>(u, f, beta, fa, B, i, j, k + 1, ih2);
+        const T r101 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j, k + 1, ih2);
+        const T r011 = resid_at<T, MODE>(u, f, beta, fa, B, i, j + 1, k + 1, ih2);
+        const T r111 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j + 1, k + 1, ih2);
+        const T s = ((r000 + r100) + (r010 + r110)) + ((r001 + r101) + (r011 + r111));
+        fc[rb_idx(C, I, J, K)] = s * T(0.125);
+    }
 }
 
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_restrict_plain(const T* __restrict__ rf, T* __restrict__ fc,
-                                                          const RBox* __restrict__ fboxes,
-                                                          const RBox* __restrict__ cboxes,
-                                                          const WorkBox* __restrict__ work, int nwork,
-                                                          long long ncells) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncells) return;
-    WorkBox wb;
-    int I, J, K;
-    decode_coarse(work, nwork, g, wb, I, J, K);
-    const RBox B = fboxes[wb.box];
-    I += B.lo[0] >> 1; J += B.lo[1] >> 1; K += B.lo[2] >> 1;
-    const int i = 2 * I, j = 2 * J, k = 2 * K;
-    const T s = ((rf[rb_idx(B, i, j, k)] + rf[rb_idx(B, i + 1, j, k)]) +
-                 (rf[rb_idx(B, i, j + 1, k)] + rf[rb_idx(B, i + 1, j + 1, k)])) +
-                ((rf[rb_idx(B, i, j, k + 1)] + rf[rb_idx(B, i + 1, j, k + 1)]) +
-                 (rf[rb_idx(B, i, j + 1, k + 1)] + rf[rb_idx(B, i + 1, j + 1, k + 1)]));
-    fc[rb_idx(cboxes[wb.cbox], I, J, K)] = s * T(0.125);
+__global__ void __launch_bounds__(kBlock) k_restrict_plain(XGrid x, const T* __restrict__ rf, T* __restrict__ fc) {
+    const Tile tl = x.tiles[tile_index()];
+    const RBox B = x.fboxes[tl.box];
+    const RBox C = x.cboxes[x.cbox[tl.box]];
+    const TileThread th = tile_thread(tl, x.sh);
+    const int I = (B.lo[0] >> 1) + th.x, J = (B.lo[1] >> 1) + th.y;
+    if (I > (B.hi[0] >> 1) || J > (B.hi[1] >> 1)) return;
+    for (int z = 0; z < x.sh.zc; ++z) {
+        const int K = (B.lo[2] >> 1) + th.z0 + z * th.dz;
+        if (K > (B.hi[2] >> 1)) break;
+        const int i = 2 * I, j = 2 * J, k = 2 * K;
+        const T s = ((rf[rb_idx(B, i, j, k)] + rf[rb_idx(B, i + 1, j, k)]) +
+                     (rf[rb_idx(B, i, j + 1, k)] + rf[rb_idx(B, i + 1, j + 1, k)])) +
+                    ((rf[rb_idx(B, i, j, k + 1)] + rf[rb_idx(B, i + 1, j, k + 1)]) +
+                     (rf[rb_idx(B, i, j + 1, k + 1)] + rf[rb_idx(B, i + 1, j + 1, k + 1)]));
+        fc[rb_idx(C, I, J, K)] = s * T(0.125);
+    }
 }
 
 // ---------------------------------------------------- prolongation + add
@@ -333,47 +388,50 @@ __global__ void __launch_bounds__(kBlock) k_restrict_plain(const T* __restrict__
 // where c_abc is the coarse value at the parent shifted by a*sx, b*sy, c*sz
 // and s = +1 for an odd child index, -1 for an even one (trilinear), or
 // e = c000 (piecewise constant).  Coarse ghosts must be current.
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_prolong(const T* __restrict__ ec, T* __restrict__ uf,
-                                                   const RBox* __restrict__ fboxes, const RBox* __restrict__ cboxes,
-                                                   const WorkBox* __restrict__ work, int nwork, long long ncells,
-                                                   int order) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncells) return;
-    WorkBox wb;
-    int I, J, K;
-    decode_coarse(work, nwork, g, wb, I, J, K);
-    const RBox B = fboxes[wb.box];
-    const RBox C = cboxes[wb.cbox];
-    I += B.lo[0] >> 1; J += B.lo[1] >> 1; K += B.lo[2] >> 1;
-    T v[3][3][3];
+template <class T, bool PUSH>
+__global__ void __launch_bounds__(kBlock) k_prolong(XGrid x, const T* __restrict__ ec, T* __restrict__ uf, int order) {
+    const Tile tl = x.tiles[tile_index()];
+    const RBox B = x.fboxes[tl.box];
+    const RBox C = x.cboxes[x.cbox[tl.box]];
+    const TileThread th = tile_thread(tl, x.sh);
+    const int I = (B.lo[0] >> 1) + th.x, J = (B.lo[1] >> 1) + th.y;
+    if (I > (B.hi[0] >> 1) || J > (B.hi[1] >> 1)) return;
+    for (int z = 0; z < x.sh.zc; ++z) {
+        const int K = (B.lo[2] >> 1) + th.z0 + z * th.dz;
+        if (K > (B.hi[2] >> 1)) break;
+        T v[3][3][3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
+            for (int b = 0; b < 3; ++b)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) v[c][b][a] = (order == 1 && (a != 1 || b != 1 || c != 1)) ? T(0) : ec[rb_idx(C, I + a - 1, J + b - 1, K + c - 1)];
+                for (int a = 0; a < 3; ++a)
+                    v[c][b][a] = (order == 1 && (a != 1 || b != 1 || c != 1)) ? T(0)
+                                                                              : ec[rb_idx(C, I + a - 1, J + b - 1, K + c - 1)];
 #pragma unroll
-    for (int cz = 0; cz < 2; ++cz)
+        for (int cz = 0; cz < 2; ++cz)
 #pragma unroll
-        for (int cy = 0; cy < 2; ++cy)
+            for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
-            for (int cx = 0; cx < 2; ++cx) {
-                const int sx = cx ? 2 : 0, sy = cy ? 2 : 0, sz = cz ? 2 : 0;  // neighbour slot: parent 1 +- 1
-                T e;
-                if (order == 1) {
-                    e = v[1][1][1];
-                } else {
-                    const T c000 = v[1][1][1];
-                    const T c100 = v[1][1][sx], c010 = v[1][sy][1], c001 = v[sz][1][1];
-                    const T c110 = v[1][sy][sx], c101 = v[sz][1][sx], c011 = v[sz][sy][1];
-                    const T c111 = v[sz][sy][sx];
-                    e = (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
-                        T(0.015625);
+                for (int cx = 0; cx < 2; ++cx) {
+                    const int sx = cx ? 2 : 0, sy = cy ? 2 : 0, sz = cz ? 2 : 0;  // neighbour slot: parent 1 -+ 1
+                    T e;
+                    if (order == 1) {
+                        e = v[1][1][1];
+                    } else {
+                        const T c000 = v[1][1][1];
+                        const T c100 = v[1][1][sx], c010 = v[1][sy][1], c001 = v[sz][1][1];
+                        const T c110 = v[1][sy][sx], c101 = v[sz][1][sx], c011 = v[sz][sy][1];
+                        const T c111 = v[sz][sy][sx];
+                        e = (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
+                            T(0.015625);
+                    }
+                    const long long idx = rb_idx(B, 2 * I + cx, 2 * J + cy, 2 * K + cz);
+                    const T v = uf[idx] + e;
+                    uf[idx] = v;
+                    if constexpr (PUSH) push_ghosts(uf, x.fboxes, B, 2 * I + cx, 2 * J + cy, 2 * K + cz, v);
                 }
-                const long long idx = rb_idx(B, 2 * I + cx, 2 * J + cy, 2 * K + cz);
-                uf[idx] = uf[idx] + e;
-            }
+    }
 }
 
 // -------------------------------------------------------------- utilities
@@ -388,84 +446,60 @@ __global__ void __launch_bounds__(kBlock) k_cast_f32(const double* __restrict__ 
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) d[q] = (float)s[q];
 }
 
+// Per-cell maps over both colours of the valid cells, tiled like the
+// smoother; OP(B, i, j, k) does the work.
+#define BXMG_FOR_VALID_CELLS(g, OP)                                          \
+    const Tile tl = (g).tiles[tile_index()];                                 \
+    const RBox B = (g).boxes[tl.box];                                        \
+    const TileThread th = tile_thread(tl, (g).sh);                           \
+    const int j = B.lo[1] + th.y;                                            \
+    if (j > B.hi[1]) return;                                                 \
+    for (int z = 0; z < (g).sh.zc; ++z) {                                    \
+        const int k = B.lo[2] + th.z0 + z * th.dz;                           \
+        if (k > B.hi[2]) break;                                              \
+        for (int c = 0; c < 2; ++c) {                                        \
+            const int i = colour_i(B, th.x, j, k, c);                        \
+            if (i > B.hi[0]) continue;                                       \
+            OP;                                                              \
+        }                                                                    \
+    }
+
 // F-order FP64 caller MultiFab (component 0) -> RB level, valid cells.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_fab_to_rb(const double* __restrict__ fab, const FBox* __restrict__ fb,
-                                                     T* __restrict__ rb, const RBox* __restrict__ boxes,
-                                                     const WorkBox* __restrict__ work, int nwork, long long ncells) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncells) return;
-    for (int c = 0; c < 2; ++c) {
-        Cell q;
-        RBox B;
-        if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
-        rb[rb_idx(B, q.i, q.j, q.k)] = (T)fab[fab_idx(fb[q.box], q.i, q.j, q.k)];
-    }
+__global__ void __launch_bounds__(kBlock) k_fab_to_rb(Grid g, const double* __restrict__ fab, const FBox* __restrict__ fb,
+                                                     T* __restrict__ rb) {
+    BXMG_FOR_VALID_CELLS(g, rb[rb_idx(B, i, j, k)] = (T)fab[fab_idx(fb[tl.box], i, j, k)])
 }
 
-__global__ void __launch_bounds__(kBlock) k_rb_to_fab(const double* __restrict__ rb, const RBox* __restrict__ boxes,
-                                                     double* __restrict__ fab, const FBox* __restrict__ fb,
-                                                     const WorkBox* __restrict__ work, int nwork, long long ncells) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncells) return;
-    for (int c = 0; c < 2; ++c) {
-        Cell q;
-        RBox B;
-        if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
-        fab[fab_idx(fb[q.box], q.i, q.j, q.k)] = rb[rb_idx(B, q.i, q.j, q.k)];
-    }
+__global__ void __launch_bounds__(kBlock) k_rb_to_fab(Grid g, const double* __restrict__ rb, double* __restrict__ fab,
+                                                     const FBox* __restrict__ fb) {
+    BXMG_FOR_VALID_CELLS(g, fab[fab_idx(fb[tl.box], i, j, k)] = rb[rb_idx(B, i, j, k)])
 }
 
-__global__ void __launch_bounds__(kBlock) k_add_f32(double* __restrict__ u, const float* __restrict__ e,
-                                                   const RBox* __restrict__ boxes, const WorkBox* __restrict__ work,
-                                                   int nwork, long long ncells) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncells) return;
-    for (int c = 0; c < 2; ++c) {
-        Cell q;
-        RBox B;
-        if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
-        const long long idx = rb_idx(B, q.i, q.j, q.k);
-        u[idx] = u[idx] + (double)e[idx];
-    }
-}
-
-// Norms of a field's valid cells (the right-hand side's max norm).
-__global__ void __launch_bounds__(kBlock) k_field_norm(const double* __restrict__ x, const RBox* __restrict__ boxes,
-                                                      const WorkBox* __restrict__ work, int nwork, long long ncells,
-                                                      double* __restrict__ partials) {
-    __shared__ double sh[3 * (kBlock / 64)];
-    double mx = 0.0, s2 = 0.0, bad = 0.0;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < ncells; g += stride)
-        for (int c = 0; c < 2; ++c) {
-            Cell q;
-            RBox B;
-            if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
-            acc_norm(x[rb_idx(B, q.i, q.j, q.k)], mx, s2, bad);
-        }
-    block_reduce3(mx, s2, bad, sh);
-    if (threadIdx.x == 0) {
-        partials[3 * blockIdx.x] = mx;
-        partials[3 * blockIdx.x + 1] = s2;
-        partials[3 * blockIdx.x + 2] = bad;
-    }
+__global__ void __launch_bounds__(kBlock) k_add_f32(Grid g, double* __restrict__ u, const float* __restrict__ e) {
+    BXMG_FOR_VALID_CELLS(g, const long long idx = rb_idx(B, i, j, k); const double v = u[idx] + (double)e[idx];
+                         u[idx] = v; if (g.push) push_ghosts(u, g.boxes, B, i, j, k, v))
 }
 
 // Sum of valid cells (periodic mean projection), then subtraction.
-__global__ void __launch_bounds__(kBlock) k_sum_valid(const double* __restrict__ u, const RBox* __restrict__ boxes,
-                                                     const WorkBox* __restrict__ work, int nwork, long long ncells,
+__global__ void __launch_bounds__(kBlock) k_sum_valid(Grid g, const double* __restrict__ u,
                                                      double* __restrict__ partials) {
     __shared__ double sh[3 * (kBlock / 64)];
     double mx = 0.0, s = 0.0, cnt = 0.0;
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < ncells; g += stride)
-        for (int c = 0; c < 2; ++c) {
-            Cell q;
-            RBox B;
-            if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
-            s = s + u[rb_idx(B, q.i, q.j, q.k)];
-            cnt += 1.0;
+    const Tile tl = g.tiles[tile_index()];
+    const RBox B = g.boxes[tl.box];
+    const TileThread th = tile_thread(tl, g.sh);
+    const int j = B.lo[1] + th.y;
+    if (j <= B.hi[1])
+        for (int z = 0; z < g.sh.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            if (k > B.hi[2]) break;
+            for (int c = 0; c < 2; ++c) {
+                const int i = colour_i(B, th.x, j, k, c);
+                if (i > B.hi[0]) continue;
+                s = s + u[rb_idx(B, i, j, k)];
+                cnt += 1.0;
+            }
         }
     block_reduce3(mx, s, cnt, sh);
     if (threadIdx.x == 0) {
@@ -475,19 +509,9 @@ __global__ void __launch_bounds__(kBlock) k_sum_valid(const double* __restrict__
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_sub_mean(double* __restrict__ u, const double* __restrict__ tot,
-                                                    const RBox* __restrict__ boxes, const WorkBox* __restrict__ work,
-                                                    int nwork, long long ncells) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncells) return;
-    const double m = tot[1] / tot[2];
-    for (int c = 0; c < 2; ++c) {
-        Cell q;
-        RBox B;
-        if (!decode_colour(work, nwork, boxes, g, c, q, B)) continue;
-        const long long idx = rb_idx(B, q.i, q.j, q.k);
-        u[idx] = u[idx] - m;
-    }
+__global__ void __launch_bounds__(kBlock) k_sub_mean(Grid g, double* __restrict__ u, const double* __restrict__ tot) {
+    const double mean = tot[1] / tot[2];
+    BXMG_FOR_VALID_CELLS(g, const long long idx = rb_idx(B, i, j, k); u[idx] = u[idx] - mean)
 }
 
 // ------------------------------------------------------ coefficient setup
@@ -495,38 +519,41 @@ __global__ void __launch_bounds__(kBlock) k_sub_mean(double* __restrict__ u, con
 // and the even reflection): each fine face is the harmonic mean of its two
 // cells, each coarse face the mean of its 4 fine faces,
 //   ((a(t1,t2) + a(t1+1,t2)) + (a(t1,t2+1) + a(t1+1,t2+1))) * 1/4.
-// Work: per fine box, coarse faces of direction d anchored in it.
+// Tiles cover the coarse faces of direction d anchored in each fine box:
+// the low face of every coarse cell, plus the high face of the last cell
+// when the box touches the domain's upper end in d (index range one larger).
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_faces_from_cells(const T* __restrict__ beta,
-                                                            const RBox* __restrict__ fboxes,
-                                                            const WorkBox* __restrict__ work, int nwork,
-                                                            long long ncells, int d, FaceArrays<T> out,
-                                                            T* __restrict__ dst) {
-    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncells) return;
-    WorkBox wb;
-    int I, J, K;
-    decode_coarse(work, nwork, g, wb, I, J, K);
-    const RBox B = fboxes[wb.box];
-    I += B.lo[0] >> 1; J += B.lo[1] >> 1; K += B.lo[2] >> 1;
+__global__ void __launch_bounds__(kBlock) k_faces_from_cells(XGrid x, const T* __restrict__ beta, int d, int fdom_hi,
+                                                            FaceArrays<T> out, T* __restrict__ dst) {
+    const Tile tl = x.tiles[tile_index()];
+    const RBox B = x.fboxes[tl.box];
+    const TileThread th = tile_thread(tl, x.sh);
+    int chi[3] = {B.hi[0] >> 1, B.hi[1] >> 1, B.hi[2] >> 1};
+    if (B.hi[d] == fdom_hi) chi[d] += 1;
+    const int I = (B.lo[0] >> 1) + th.x, J = (B.lo[1] >> 1) + th.y;
+    if (I > chi[0] || J > chi[1]) return;
     const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-    int f0[3] = {2 * I, 2 * J, 2 * K};
-    T a[2][2];
+    for (int z = 0; z < x.sh.zc; ++z) {
+        const int K = (B.lo[2] >> 1) + th.z0 + z * th.dz;
+        if (K > chi[2]) break;
+        const int f0[3] = {2 * I, 2 * J, 2 * K};
+        T a[2][2];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            int cc[3] = {f0[0], f0[1], f0[2]};
-            cc[t1] += p;
-            cc[t2] += q;
-            int lc[3] = {cc[0], cc[1], cc[2]};
-            lc[d] -= 1;
-            a[q][p] = harm(beta[rb_idx(B, lc[0], lc[1], lc[2])], beta[rb_idx(B, cc[0], cc[1], cc[2])]);
-        }
-    const T v = ((a[0][0] + a[0][1]) + (a[1][0] + a[1][1])) * T(0.25);
-    const int x = I - out.dlo[0], y = J - out.dlo[1], z = K - out.dlo[2];
-    const int nx = out.n[0] + (d == 0), ny = out.n[1] + (d == 1);
-    dst[(long long)x + (long long)nx * ((long long)y + (long long)ny * z)] = v;
+            for (int p = 0; p < 2; ++p) {
+                int cc[3] = {f0[0], f0[1], f0[2]};
+                cc[t1] += p;
+                cc[t2] += q;
+                int lc[3] = {cc[0], cc[1], cc[2]};
+                lc[d] -= 1;
+                a[q][p] = harm(beta[rb_idx(B, lc[0], lc[1], lc[2])], beta[rb_idx(B, cc[0], cc[1], cc[2])]);
+            }
+        const T v = ((a[0][0] + a[0][1]) + (a[1][0] + a[1][1])) * T(0.25);
+        const int xx = I - out.dlo[0], yy = J - out.dlo[1], zz = K - out.dlo[2];
+        const int nx = out.n[0] + (d == 0), ny = out.n[1] + (d == 1);
+        dst[(long long)xx + (long long)nx * ((long long)yy + (long long)ny * zz)] = v;
+    }
 }
 
 // Level l+1 faces from level l faces (global arrays).
@@ -558,7 +585,7 @@ __global__ void __launch_bounds__(kBlock) k_faces_coarsen(FaceArrays<T> fine, Fa
 // FP64 conjugate gradients on the coarsest level by one workgroup, vectors
 // in LDS over the level domain (natural order, p with a ghost layer).
 constexpr int kBotThreads = 1024;
-constexpr int kBotGrown = 6144;
+constexpr int kBotGrown = kBottomGrown;
 
 struct BottomGeom {
     int dlo[3], n[3];
@@ -714,11 +741,10 @@ __global__ void __launch_bounds__(kBotThreads) k_bottom(T* __restrict__ u, const
 // ================================================================ launchers
 static inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const RBox* boxes, const Tag* tags, int ntags,
-                          long long ncells, int cmask) {
-    if (ncells <= 0) return hipSuccess;
-    if (f32) hipLaunchKernelGGL(k_fill_rb<float>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (float*)data, boxes, tags, ntags, ncells, cmask);
-    else hipLaunchKernelGGL(k_fill_rb<double>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (double*)data, boxes, tags, ntags, ncells, cmask);
+hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* list, long long n) {
+    if (n <= 0) return hipSuccess;
+    if (f32) hipLaunchKernelGGL(k_fill_rb<float>, dim3(nblk(n)), dim3(kBlock), 0, s, (float*)data, list, n);
+    else hipLaunchKernelGGL(k_fill_rb<double>, dim3(nblk(n)), dim3(kBlock), 0, s, (double*)data, list, n);
     return hipGetLastError();
 }
 
@@ -731,96 +757,89 @@ hipError_t launch_fill_fab(hipStream_t s, void* data, bool f32, const FBox* boxe
 }
 
 template <class T>
-hipError_t launch_gs(hipStream_t s, T* u, const T* f, const T* beta, FaceArrays<T> fa, const RBox* boxes,
-                     const WorkBox* work, int nwork, long long ncells, T h2, int colour) {
-    if (ncells <= 0) return hipSuccess;
-    if (beta) hipLaunchKernelGGL((k_gs<T, 1>), dim3(nblk(ncells)), dim3(kBlock), 0, s, u, f, beta, fa, boxes, work, nwork, ncells, h2, colour);
-    else if (fa.c[0]) hipLaunchKernelGGL((k_gs<T, 2>), dim3(nblk(ncells)), dim3(kBlock), 0, s, u, f, beta, fa, boxes, work, nwork, ncells, h2, colour);
-    else hipLaunchKernelGGL((k_gs<T, 0>), dim3(nblk(ncells)), dim3(kBlock), 0, s, u, f, beta, fa, boxes, work, nwork, ncells, h2, colour);
+hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* beta, FaceArrays<T> fa, T h2,
+                     int colour) {
+    if (g.ntiles <= 0) return hipSuccess;
+    const dim3 G(g.ntiles), B(kBlock);
+#define BXMG_GS(MODE, PUSH) hipLaunchKernelGGL((k_gs<T, MODE, PUSH>), G, B, 0, s, g, u, f, beta, fa, h2, colour)
+    if (g.push) {
+        if (beta) BXMG_GS(1, true); else if (fa.c[0]) BXMG_GS(2, true); else BXMG_GS(0, true);
+    } else {
+        if (beta) BXMG_GS(1, false); else if (fa.c[0]) BXMG_GS(2, false); else BXMG_GS(0, false);
+    }
+#undef BXMG_GS
     return hipGetLastError();
 }
-template hipError_t launch_gs<double>(hipStream_t, double*, const double*, const double*, FaceArrays<double>,
-                                      const RBox*, const WorkBox*, int, long long, double, int);
-template hipError_t launch_gs<float>(hipStream_t, float*, const float*, const float*, FaceArrays<float>, const RBox*,
-                                     const WorkBox*, int, long long, float, int);
+template hipError_t launch_gs<double>(hipStream_t, const Grid&, double*, const double*, const double*,
+                                      FaceArrays<double>, double, int);
+template hipError_t launch_gs<float>(hipStream_t, const Grid&, float*, const float*, const float*, FaceArrays<float>,
+                                     float, int);
 
 template <class T, class R>
-static hipError_t resid_dispatch(hipStream_t s, const T* u, const T* f, const T* beta, FaceArrays<T> fa,
-                                 const RBox* boxes, const WorkBox* work, int nwork, long long ncells, T ih2, R* r,
-                                 double* partials, int nblocks) {
-    if (beta) hipLaunchKernelGGL((k_resid<T, 1, R>), dim3(nblocks), dim3(kBlock), 0, s, u, f, beta, fa, boxes, work, nwork, ncells, ih2, r, partials);
-    else if (fa.c[0]) hipLaunchKernelGGL((k_resid<T, 2, R>), dim3(nblocks), dim3(kBlock), 0, s, u, f, beta, fa, boxes, work, nwork, ncells, ih2, r, partials);
-    else hipLaunchKernelGGL((k_resid<T, 0, R>), dim3(nblocks), dim3(kBlock), 0, s, u, f, beta, fa, boxes, work, nwork, ncells, ih2, r, partials);
+hipError_t launch_resid(hipStream_t s, const Grid& g, const T* u, const T* f, const T* beta, FaceArrays<T> fa,
+                        T ih2, R* r, double* partials) {
+    if (g.ntiles <= 0) return hipSuccess;
+    const dim3 G(g.ntiles), B(kBlock);
+    if (beta) hipLaunchKernelGGL((k_resid<T, 1, R>), G, B, 0, s, g, u, f, beta, fa, ih2, r, partials);
+    else if (fa.c[0]) hipLaunchKernelGGL((k_resid<T, 2, R>), G, B, 0, s, g, u, f, beta, fa, ih2, r, partials);
+    else hipLaunchKernelGGL((k_resid<T, 0, R>), G, B, 0, s, g, u, f, beta, fa, ih2, r, partials);
+    return hipGetLastError();
+}
+template hipError_t launch_resid<double, double>(hipStream_t, const Grid&, const double*, const double*, const double*,
+                                                 FaceArrays<double>, double, double*, double*);
+template hipError_t launch_resid<double, float>(hipStream_t, const Grid&, const double*, const double*, const double*,
+                                                FaceArrays<double>, double, float*, double*);
+template hipError_t launch_resid<float, float>(hipStream_t, const Grid&, const float*, const float*, const float*,
+                                               FaceArrays<float>, float, float*, double*);
+
+hipError_t launch_norm_final(hipStream_t s, const double* partials, int n, double* out3) {
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, s, partials, n, out3);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_norm(hipStream_t s, const Grid& g, const double* x, double* partials) {
+    if (g.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_field_norm, dim3(g.ntiles), dim3(kBlock), 0, s, g, x, partials);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_resid_norm(hipStream_t s, const T* u, const T* f, const T* beta, FaceArrays<T> fa,
-                             const RBox* boxes, const WorkBox* work, int nwork, long long ncells, T ih2, T* r,
-                             double* partials, int nblocks) {
-    return resid_dispatch<T, T>(s, u, f, beta, fa, boxes, work, nwork, ncells, ih2, r, partials, nblocks);
-}
-template hipError_t launch_resid_norm<double>(hipStream_t, const double*, const double*, const double*,
-                                              FaceArrays<double>, const RBox*, const WorkBox*, int, long long,
-                                              double, double*, double*, int);
-template hipError_t launch_resid_norm<float>(hipStream_t, const float*, const float*, const float*, FaceArrays<float>,
-                                             const RBox*, const WorkBox*, int, long long, float, float*, double*,
-                                             int);
-
-hipError_t launch_resid_cast(hipStream_t s, const double* u, const double* f, const double* beta,
-                             FaceArrays<double> fa, const RBox* boxes, const WorkBox* work, int nwork,
-                             long long ncells, double ih2, float* r32, double* partials, int nblocks) {
-    return resid_dispatch<double, float>(s, u, f, beta, fa, boxes, work, nwork, ncells, ih2, r32, partials, nblocks);
-}
-
-hipError_t launch_norm_final(hipStream_t s, const double* partials, int nblocks, double* out3) {
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, s, partials, nblocks, out3);
+hipError_t launch_resid_restrict(hipStream_t s, const XGrid& x, const T* u, const T* f, const T* beta,
+                                 FaceArrays<T> fa, T ih2, T* fc) {
+    if (x.ntiles <= 0) return hipSuccess;
+    const dim3 G(x.ntiles), B(kBlock);
+    if (beta) hipLaunchKernelGGL((k_resid_restrict<T, 1>), G, B, 0, s, x, u, f, beta, fa, ih2, fc);
+    else if (fa.c[0]) hipLaunchKernelGGL((k_resid_restrict<T, 2>), G, B, 0, s, x, u, f, beta, fa, ih2, fc);
+    else hipLaunchKernelGGL((k_resid_restrict<T, 0>), G, B, 0, s, x, u, f, beta, fa, ih2, fc);
     return hipGetLastError();
 }
+template hipError_t launch_resid_restrict<double>(hipStream_t, const XGrid&, const double*, const double*,
+                                                  const double*, FaceArrays<double>, double, double*);
+template hipError_t launch_resid_restrict<float>(hipStream_t, const XGrid&, const float*, const float*, const float*,
+                                                 FaceArrays<float>, float, float*);
 
 template <class T>
-hipError_t launch_resid_restrict(hipStream_t s, const T* u, const T* f, const T* beta, FaceArrays<T> fa,
-                                 const RBox* fboxes, const RBox* cboxes, const WorkBox* work, int nwork,
-                                 long long ncells, T ih2, T* fc) {
-    if (ncells <= 0) return hipSuccess;
-    if (beta) hipLaunchKernelGGL((k_resid_restrict<T, 1>), dim3(nblk(ncells)), dim3(kBlock), 0, s, u, f, beta, fa, fboxes, cboxes, work, nwork, ncells, ih2, fc);
-    else if (fa.c[0]) hipLaunchKernelGGL((k_resid_restrict<T, 2>), dim3(nblk(ncells)), dim3(kBlock), 0, s, u, f, beta, fa, fboxes, cboxes, work, nwork, ncells, ih2, fc);
-    else hipLaunchKernelGGL((k_resid_restrict<T, 0>), dim3(nblk(ncells)), dim3(kBlock), 0, s, u, f, beta, fa, fboxes, cboxes, work, nwork, ncells, ih2, fc);
+hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* fc) {
+    if (x.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restrict_plain<T>, dim3(x.ntiles), dim3(kBlock), 0, s, x, rf, fc);
     return hipGetLastError();
 }
-template hipError_t launch_resid_restrict<double>(hipStream_t, const double*, const double*, const double*,
-                                                  FaceArrays<double>, const RBox*, const RBox*, const WorkBox*, int,
-                                                  long long, double, double*);
-template hipError_t launch_resid_restrict<float>(hipStream_t, const float*, const float*, const float*,
-                                                 FaceArrays<float>, const RBox*, const RBox*, const WorkBox*, int,
-                                                 long long, float, float*);
+template hipError_t launch_restrict_plain<double>(hipStream_t, const XGrid&, const double*, double*);
 
 template <class T>
-hipError_t launch_restrict_plain(hipStream_t s, const T* rf, T* fc, const RBox* fboxes, const RBox* cboxes,
-                                 const WorkBox* work, int nwork, long long ncells) {
-    if (ncells <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_restrict_plain<T>, dim3(nblk(ncells)), dim3(kBlock), 0, s, rf, fc, fboxes, cboxes, work, nwork, ncells);
+hipError_t launch_prolong(hipStream_t s, const XGrid& x, const T* ec, T* uf, int order) {
+    if (x.ntiles <= 0) return hipSuccess;
+    if (x.push) hipLaunchKernelGGL((k_prolong<T, true>), dim3(x.ntiles), dim3(kBlock), 0, s, x, ec, uf, order);
+    else hipLaunchKernelGGL((k_prolong<T, false>), dim3(x.ntiles), dim3(kBlock), 0, s, x, ec, uf, order);
     return hipGetLastError();
 }
-template hipError_t launch_restrict_plain<double>(hipStream_t, const double*, double*, const RBox*, const RBox*,
-                                                  const WorkBox*, int, long long);
-
-template <class T>
-hipError_t launch_prolong(hipStream_t s, const T* ec, T* uf, const RBox* fboxes, const RBox* cboxes,
-                          const WorkBox* work, int nwork, long long ncells, int order) {
-    if (ncells <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prolong<T>, dim3(nblk(ncells)), dim3(kBlock), 0, s, ec, uf, fboxes, cboxes, work, nwork, ncells, order);
-    return hipGetLastError();
-}
-template hipError_t launch_prolong<double>(hipStream_t, const double*, double*, const RBox*, const RBox*,
-                                           const WorkBox*, int, long long, int);
-template hipError_t launch_prolong<float>(hipStream_t, const float*, float*, const RBox*, const RBox*,
-                                          const WorkBox*, int, long long, int);
+template hipError_t launch_prolong<double>(hipStream_t, const XGrid&, const double*, double*, int);
+template hipError_t launch_prolong<float>(hipStream_t, const XGrid&, const float*, float*, int);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n) {
     if (n <= 0) return hipSuccess;
-    const long long nb = std::min<long long>(nblk(n), 4096);
+    const long long nb = std::min<long long>(nblk(n), 8192);
     hipLaunchKernelGGL(k_zero<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, p, n);
     return hipGetLastError();
 }
@@ -829,59 +848,50 @@ template hipError_t launch_zero<float>(hipStream_t, float*, long long);
 
 hipError_t launch_cast_f32(hipStream_t s, const double* src, float* dst, long long n) {
     if (n <= 0) return hipSuccess;
-    const long long nb = std::min<long long>(nblk(n), 4096);
+    const long long nb = std::min<long long>(nblk(n), 8192);
     hipLaunchKernelGGL(k_cast_f32, dim3((unsigned)nb), dim3(kBlock), 0, s, src, dst, n);
     return hipGetLastError();
 }
 
-hipError_t launch_fab_to_rb(hipStream_t s, const double* fab, const FBox* fb, void* rb, bool f32, const RBox* rbx,
-                            const WorkBox* work, int nwork, long long ncells) {
-    if (ncells <= 0) return hipSuccess;
-    if (f32) hipLaunchKernelGGL(k_fab_to_rb<float>, dim3(nblk(ncells)), dim3(kBlock), 0, s, fab, fb, (float*)rb, rbx, work, nwork, ncells);
-    else hipLaunchKernelGGL(k_fab_to_rb<double>, dim3(nblk(ncells)), dim3(kBlock), 0, s, fab, fb, (double*)rb, rbx, work, nwork, ncells);
+hipError_t launch_fab_to_rb(hipStream_t s, const Grid& g, const double* fab, const FBox* fb, void* rb, bool f32) {
+    if (g.ntiles <= 0) return hipSuccess;
+    if (f32) hipLaunchKernelGGL(k_fab_to_rb<float>, dim3(g.ntiles), dim3(kBlock), 0, s, g, fab, fb, (float*)rb);
+    else hipLaunchKernelGGL(k_fab_to_rb<double>, dim3(g.ntiles), dim3(kBlock), 0, s, g, fab, fb, (double*)rb);
     return hipGetLastError();
 }
 
-hipError_t launch_rb_to_fab(hipStream_t s, const double* rb, const RBox* rbx, double* fab, const FBox* fb,
-                            const WorkBox* work, int nwork, long long ncells) {
-    if (ncells <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rb_to_fab, dim3(nblk(ncells)), dim3(kBlock), 0, s, rb, rbx, fab, fb, work, nwork, ncells);
+hipError_t launch_rb_to_fab(hipStream_t s, const Grid& g, const double* rb, double* fab, const FBox* fb) {
+    if (g.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rb_to_fab, dim3(g.ntiles), dim3(kBlock), 0, s, g, rb, fab, fb);
     return hipGetLastError();
 }
 
-hipError_t launch_add_f32(hipStream_t s, double* u, const float* e, const RBox* boxes, const WorkBox* work,
-                          int nwork, long long ncells) {
-    if (ncells <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_add_f32, dim3(nblk(ncells)), dim3(kBlock), 0, s, u, e, boxes, work, nwork, ncells);
+hipError_t launch_add_f32(hipStream_t s, const Grid& g, double* u, const float* e) {
+    if (g.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_f32, dim3(g.ntiles), dim3(kBlock), 0, s, g, u, e);
     return hipGetLastError();
 }
 
-hipError_t launch_field_norm(hipStream_t s, const double* x, const RBox* boxes, const WorkBox* work, int nwork,
-                             long long ncells, double* partials, int nblocks) {
-    hipLaunchKernelGGL(k_field_norm, dim3(nblocks), dim3(kBlock), 0, s, x, boxes, work, nwork, ncells, partials);
-    return hipGetLastError();
-}
-
-hipError_t launch_mean_sub(hipStream_t s, double* u, const RBox* boxes, const WorkBox* work, int nwork,
-                           long long ncells, double* scratch, int nblocks) {
-    if (ncells <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sum_valid, dim3(nblocks), dim3(kBlock), 0, s, u, boxes, work, nwork, ncells, scratch);
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, s, scratch, nblocks, scratch + 3 * nblocks);
-    hipLaunchKernelGGL(k_sub_mean, dim3(nblk(ncells)), dim3(kBlock), 0, s, u, scratch + 3 * nblocks, boxes, work, nwork, ncells);
+hipError_t launch_mean_sub(hipStream_t s, const Grid& g, double* u, double* scratch) {
+    if (g.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_valid, dim3(g.ntiles), dim3(kBlock), 0, s, g, u, scratch);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, s, scratch, g.ntiles, scratch + 3 * (long long)g.ntiles);
+    hipLaunchKernelGGL(k_sub_mean, dim3(g.ntiles), dim3(kBlock), 0, s, g, u, scratch + 3 * (long long)g.ntiles);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_faces_from_cells(hipStream_t s, const T* beta, const RBox* fboxes, const WorkBox* work, int nwork,
-                                   long long ncells, int d, FaceArrays<T> out, T* dst) {
-    if (ncells <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_faces_from_cells<T>, dim3(nblk(ncells)), dim3(kBlock), 0, s, beta, fboxes, work, nwork, ncells, d, out, dst);
+hipError_t launch_faces_from_cells(hipStream_t s, const XGrid& x, const T* beta, int d, FaceArrays<T> out, T* dst) {
+    if (x.ntiles <= 0) return hipSuccess;
+    // fine domain upper end in d = 2 * (coarse upper end) + 1
+    const int fdom_hi = 2 * (out.dlo[d] + out.n[d] - 1) + 1;
+    hipLaunchKernelGGL(k_faces_from_cells<T>, dim3(x.ntiles), dim3(kBlock), 0, s, x, beta, d, fdom_hi, out, dst);
     return hipGetLastError();
 }
-template hipError_t launch_faces_from_cells<double>(hipStream_t, const double*, const RBox*, const WorkBox*, int,
-                                                    long long, int, FaceArrays<double>, double*);
-template hipError_t launch_faces_from_cells<float>(hipStream_t, const float*, const RBox*, const WorkBox*, int,
-                                                   long long, int, FaceArrays<float>, float*);
+template hipError_t launch_faces_from_cells<double>(hipStream_t, const XGrid&, const double*, int, FaceArrays<double>,
+                                                    double*);
+template hipError_t launch_faces_from_cells<float>(hipStream_t, const XGrid&, const float*, int, FaceArrays<float>,
+                                                   float*);
 
 template <class T>
 hipError_t launch_faces_coarsen(hipStream_t s, FaceArrays<T> fine, FaceArrays<T> coarse, int d, T* dst) {

@@ -115,3 +115,14 @@ def test_workloads_are_deterministic():
     tr = W.serving_trace(100, 5)
     assert all(32 <= r["edge"] <= 256 and r["edge"] % 16 == 0 for r in tr)
     assert all(1e-10 <= r["tol"] <= 1e-8 for r in tr)
+
+
+@pytest.mark.parametrize("boxes", [[((0, 0, 0), (2, 7, 7)), ((3, 0, 0), (7, 7, 7))],
+                                   [((0, 0, 0), (1, 7, 7)), ((2, 0, 0), (7, 7, 7))],
+                                   [((-4, 0, 0), (-1, 7, 7)), ((0, 0, 0), (3, 7, 7))]])
+def test_hierarchy_of_box_lists_matches_oracle(bx, orc, boxes):
+    dlo = (min(b[0][0] for b in boxes), 0, 0)
+    dhi = (max(b[1][0] for b in boxes), 7, 7)
+    ba = bx.BoxArray.from_boxes(dlo, dhi, boxes)
+    mine = [(d.small, d.big, [(b.small, b.big) for b in bl]) for d, bl in ba.hierarchy()]
+    assert mine == orc.hierarchy(dlo, dhi, boxes)

@@ -85,3 +85,14 @@ def test_hierarchy_odd_bottoms(orc, n, bottom):
     for dlo, dhi, bl in lv:
         ncell = sum(int(np.prod([hi[d] - lo[d] + 1 for d in range(3)])) for lo, hi in bl)
         assert ncell == int(np.prod([dhi[d] - dlo[d] + 1 for d in range(3)]))
+
+
+def test_hierarchy_stops_on_boxes_without_whole_pairs(orc):
+    # a box with an odd lower corner cannot hand whole 2x2x2 blocks to a coarse
+    # cell, so the level is the bottom even though the domain could halve
+    boxes = [((0, 0, 0), (2, 7, 7)), ((3, 0, 0), (7, 7, 7))]
+    lv = orc.hierarchy((0, 0, 0), (7, 7, 7), boxes)
+    assert len(lv) == 1
+    boxes = [((0, 0, 0), (1, 7, 7)), ((2, 0, 0), (7, 7, 7))]  # whole pairs, box of width 2
+    lv = orc.hierarchy((0, 0, 0), (7, 7, 7), boxes)
+    assert [l[1][0] + 1 for l in lv] == [8, 4, 2] and len(lv[1][2]) == 1
