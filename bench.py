@@ -106,44 +106,40 @@ def traffic_from_counters():
 
 def summarize_counters(d):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the level-0 GS launches
-    and of the 1 GiB copy, from rocprofv3 --pmc outputs under d/fetch and
-    d/write; writes the committed summary."""
-    import csv
+    and of the 1 GiB elementwise calibration kernel, from the rocprofv3 --pmc
+    databases under d/fetch and d/write; writes the committed summary."""
+    import sqlite3
 
-    def rows(sub):
-        files = glob.glob(os.path.join(d, sub, "**", "*counter_collection.csv"), recursive=True)
-        if not files:
-            raise SystemExit("no counter_collection.csv under %s" % os.path.join(d, sub))
+    def rows(sub, counter):
+        dbs = glob.glob(os.path.join(d, sub, "**", "*.db"), recursive=True)
+        if not dbs:
+            raise SystemExit("no rocprofv3 database under %s" % os.path.join(d, sub))
         out = []
-        for fn in files:
-            with open(fn) as fh:
-                out += list(csv.DictReader(fh))
+        for db in dbs:
+            con = sqlite3.connect(db)
+            out += list(con.execute("select dispatch_id, kernel_name, grid_size, value from counters_collection "
+                                    "where counter_name = ?", (counter,)))
         return out
 
-    def per_dispatch(rs, counter, match, min_grid):
+    def per_dispatch(rs, match, min_grid):
         vals = {}
-        for r in rs:
-            if r.get("Counter_Name") != counter or match not in r.get("Kernel_Name", ""):
-                continue
-            grid = int(r.get("Grid_Size", r.get("Grid_Size_X", "0")) or 0)
-            if grid < min_grid:
-                continue
-            key = r.get("Dispatch_Id")
-            vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+        for disp, name, grid, value in rs:
+            if match in name and grid >= min_grid:
+                vals[disp] = vals.get(disp, 0.0) + float(value)
         return list(vals.values())
 
-    level0_threads = (N ** 3) // 2  # one colour of level 0
+    level0_threads = (N ** 3) // 2 // 4  # one colour of level 0, >= 1 cell per thread
     out = {"kernel": GS_KERNEL, "workload": "256^3 in 512 boxes of 32^3, FP64", "kernel_src_sha": src_sha()}
     for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
-        rs = rows(sub)
-        gs = per_dispatch(rs, counter, "k_gs", level0_threads)
-        cp = per_dispatch(rs, counter, "elementwise", 0)
+        rs = rows(sub, counter)
+        gs = per_dispatch(rs, "k_gs", level0_threads)
+        cp = per_dispatch(rs, "MulFunctor", 0)
         if not gs or not cp:
             raise SystemExit("missing dispatches for %s (gs %d, copy %d)" % (counter, len(gs), len(cp)))
         out[counter.lower() + "_kib_per_launch"] = sum(gs) / len(gs)
         out[counter.lower() + "_copy_kib"] = max(cp)
         out[counter.lower() + "_launches"] = len(gs)
-    # a 1 GiB copy reads 1 GiB and writes 1 GiB
+    # the calibration kernel reads 1 GiB and writes 1 GiB
     fscale = (COPY_BYTES / 1024.0) / out["fetch_size_copy_kib"]
     wscale = (COPY_BYTES / 1024.0) / out["write_size_copy_kib"]
     out["fetch_scale"], out["write_scale"] = fscale, wscale

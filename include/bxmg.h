@@ -89,9 +89,9 @@ bxmg_status bxmg_define_boxarray_list(const int32_t dom_lo[3], const int32_t dom
 bxmg_status bxmg_boxarray_get(bxmg_boxarray ba, int32_t* nboxes, int32_t* lohi_out);
 
 /* Multigrid level hierarchy the solver builds for this BoxArray: the domain
- * halves while every domain edge is even and >= 4; boxes halve one by one
- * while every box edge is even and >= 4 with an even lower corner, otherwise
- * the coarser level is one box covering its domain.  Writes up to cap_levels
+ * halves while every domain edge is even and >= 4 and every box has an even
+ * lower corner and even edges; boxes halve one by one while every box edge is
+ * also >= 32, otherwise the coarser level is one box covering its domain.  Writes up to cap_levels
  * levels: lev_nboxes[l], lev_dom[6*l..], and all levels' boxes concatenated
  * in lev_lohi (room for cap_boxes boxes).  EINVAL if a cap is too small. */
 bxmg_status bxmg_boxarray_hierarchy(bxmg_boxarray ba, int32_t cap_levels, int32_t* nlevels, int32_t* lev_nboxes,
@@ -181,6 +181,14 @@ void bxmg_solve_params_default(bxmg_solve_params* p);
  * arguments; bottom level above 4096 cells), ENOMEM or EDEVICE. */
 bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi, bxmg_multifab rhs,
                             bxmg_multifab beta, bxmg_solve_info* info);
+
+/* -------------------------------------------------------------- tuning --- */
+/* Launch-shape knobs for hierarchies built after the call (hierarchies are
+ * cached per knob setting): param 0 = planes each thread walks in the cell
+ * kernels (default 4); param 1 = the same for levels whose tiles span whole
+ * box planes (default 4).  value in [1, 64], else EINVAL.  Results do not
+ * depend on the knobs; only the work decomposition does. */
+bxmg_status bxmg_ctx_tune(bxmg_ctx ctx, int32_t param, int32_t value);
 
 /* ---------------------------------------------------------- profiling --- */
 /* Kernel timing with HIP events recorded on the context's stream around

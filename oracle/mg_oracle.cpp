@@ -25,8 +25,8 @@
 //   prolongation: trilinear cell-centred (27/9/3/1 over 64) or piecewise const
 //   coarsening : by 2 while every domain edge is even and >= 4 and every box
 //                holds whole cell pairs (even lower corner and edges); boxes
-//                are coarsened one by one while every box edge is also >= 4,
-//                else the coarse level is one box
+//                are coarsened one by one while every box edge is also >= 32,
+//                else the coarse level is one box covering the domain
 //   bottom     : FP64 conjugate gradients, rel. L2 residual 1e-12,
 //                at most 4*cells iterations; periodic: mean-zero projection
 //   stop test  : ||f - L u||_inf <= rel_tol * ||f||_inf (or <= abs_tol)
@@ -161,10 +161,13 @@ static bool pair_aligned(const std::vector<Box>& bs) {
     return true;
 }
 
+// Boxes are coarsened one by one while every box edge is at least 32 (and
+// they hold whole cell pairs); smaller boxes are merged: the coarser level is
+// one box covering its domain.
 static bool can_coarsen_boxes(const std::vector<Box>& bs) {
     for (auto& b : bs)
         for (int d = 0; d < 3; ++d)
-            if (b.n(d) % 2 != 0 || b.n(d) < 4 || (b.lo[d] & 1)) return false;
+            if (b.n(d) % 2 != 0 || b.n(d) < 32 || (b.lo[d] & 1)) return false;
     return true;
 }
 

@@ -14,6 +14,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/bxmg.h"
@@ -93,10 +94,16 @@ bool boxes_pair_aligned(const std::vector<Box>& bs) {
     return true;
 }
 
+// Boxes are coarsened one by one while every box edge is at least
+// kMinBoxCoarsen; smaller boxes are merged into one box per level (fewer,
+// larger boxes on the coarse levels: less ghost overhead, and the small
+// single-box levels can run as one fused coarse cycle).
+constexpr int kMinBoxCoarsen = 32;
+
 bool boxes_coarsenable(const std::vector<Box>& bs) {
     for (auto& b : bs)
         for (int d = 0; d < 3; ++d)
-            if (b.n(d) % 2 || b.n(d) < 4 || (b.lo[d] & 1)) return false;
+            if (b.n(d) % 2 || b.n(d) < kMinBoxCoarsen || (b.lo[d] & 1)) return false;
     return true;
 }
 
@@ -456,10 +463,12 @@ struct Profiler {
     }
 };
 
+
 struct bxmg_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
     Profiler prof;
+    int zc = 4, zc_planes = 4;  // tile depths for hierarchies built from now on
     std::map<std::string, std::unique_ptr<Hier>> cache;
     double* h_norm = nullptr;  // pinned
     std::mutex mu;
@@ -582,6 +591,11 @@ struct Hier {
     DevBuf<float> beta32;
     std::vector<std::unique_ptr<FaceSet<double>>> faces64;  // index = level (0 unused)
     std::vector<std::unique_ptr<FaceSet<float>>> faces32;
+    int coarse_start = -1;    // first level of the fused coarse cycle (-1: none)
+    DevBuf<CoarseCycle<double>> cc64;  // device copies of the descriptors ...
+    DevBuf<CoarseCycle<float>> cc32;
+    CoarseCycle<double> cc64_host{};   // ... and what they hold
+    CoarseCycle<float> cc32_host{};
     DevBuf<double> partials;  // 3 per tile of the largest tiled launch, + 3
     DevBuf<double> fnorm;     // 3
     DevBuf<int> iters;
@@ -598,7 +612,12 @@ struct Hier {
     }
 };
 
-constexpr int kZc = 4;  // planes per thread in the cell kernels
+// Tile depth: planes walked per thread in the cell kernels (a tuning knob,
+// bxmg_ctx_tune), separately for tiles that span whole box planes.
+struct Tuning {
+    int zc = 4;
+    int zc_planes = 4;
+};
 
 static void upload_tiles(const TileSet& t, DevBuf<Tile>& buf, int& n, TileShape& sh) {
     buf.upload(t.tiles);
@@ -606,7 +625,7 @@ static void upload_tiles(const TileSet& t, DevBuf<Tile>& buf, int& n, TileShape&
     sh = t.sh;
 }
 
-static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool var, double h0) {
+static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool var, double h0, const Tuning& tune) {
     auto H = std::make_unique<Hier>();
     for (int d = 0; d < 3; ++d) H->per[d] = ba->per[d];
     H->precision = precision;
@@ -623,14 +642,18 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
         lv->rb = rb_layout(lv->boxes, 1, &lv->nelem);
         lv->push = face_neighbours(lv->dom, H->per, lv->boxes, lv->rb);
         lv->d_rb.upload(lv->rb);
-        upload_tiles(make_tiles(colour_extents(lv->boxes), kZc), lv->tcol, lv->ntcol, lv->shcol);
+        {
+            TileSet ts = make_tiles(colour_extents(lv->boxes), tune.zc);
+            if (ts.sh.lz == 0) ts = make_tiles(colour_extents(lv->boxes), tune.zc_planes);
+            upload_tiles(ts, lv->tcol, lv->ntcol, lv->shcol);
+        }
         max_tiles = std::max<long long>(max_tiles, lv->ntcol);
         if (l + 1 < lb.size()) {
-            upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, -1), kZc), lv->tdown, lv->ntdown, lv->shdown);
+            upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, -1), tune.zc), lv->tdown, lv->ntdown, lv->shdown);
             lv->cbox.upload(coarse_owner(lv->boxes, lb[l + 1].boxes));
             if (var && l == 0)
                 for (int d = 0; d < 3; ++d)
-                    upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, d), kZc), lv->tface[d], lv->ntface[d],
+                    upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, d), tune.zc), lv->tface[d], lv->ntface[d],
                                  lv->shface[d]);
         }
         const std::vector<Tag> faces = build_tags(lv->dom, H->per, lv->boxes, 1, true, 2, true);
@@ -692,8 +715,20 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
     H->partials.alloc(3 * max_tiles + 8);
     H->fnorm.alloc(4);
     H->iters.alloc(1);
+    // fused coarse cycle: from the first level l >= 1 below which every level
+    // is one box of at most kMaxBottomCells cells
+    for (size_t l = 1; l < nl; ++l) {
+        bool ok = nl - l <= (size_t)kMaxCoarseLevels;
+        for (size_t m = l; m < nl && ok; ++m)
+            ok = H->L[m]->boxes.size() == 1 && H->L[m]->dom.cells() <= kMaxBottomCells;
+        if (ok) { H->coarse_start = (int)l; break; }
+    }
     return H;
 }
+
+// Device descriptor of the fused coarse cycle for storage type T.
+template <class T>
+static CoarseCycle<T> coarse_desc(Hier* H, int nu1, int nu2, int prolong, double rtol);
 
 // ================================================================== driver
 namespace {
@@ -730,6 +765,39 @@ FaceArrays<float> lvl_faces<float>(Hier* H, size_t l) {
     if (!H->var || l == 0) return no_faces<float>();
     return H->faces32[l]->view(H->L[l]->dom);
 }
+
+}  // namespace
+
+template <class T>
+static CoarseCycle<T> coarse_desc(Hier* H, int nu1, int nu2, int prolong, double rtol) {
+    CoarseCycle<T> cc;
+    std::memset(&cc, 0, sizeof cc);
+    const size_t l0 = (size_t)H->coarse_start;
+    cc.nlev = (int)(H->L.size() - l0);
+    cc.nu1 = nu1;
+    cc.nu2 = nu2;
+    cc.prolong = prolong;
+    for (int d = 0; d < 3; ++d) cc.per[d] = H->per[d];
+    cc.rtol = rtol;
+    cc.iters = H->iters.p;
+    for (int m = 0; m < cc.nlev; ++m) {
+        const Level& L = *H->L[l0 + m];
+        CoarseLevel<T>& c = cc.L[m];
+        c.box = L.rb[0];
+        c.u = lvl_u<T>(H, l0 + m);
+        c.f = lvl_f<T>(H, l0 + m);
+        for (int q = 0; q < 2; ++q) { c.face[q] = L.face[q].list.p; c.nface[q] = L.face[q].n; }
+        c.full = L.full.list.p;
+        c.nfull = L.full.n;
+        c.nelem = L.nelem;
+        c.h = L.h;
+        c.fa = lvl_faces<T>(H, l0 + m);
+        c.push = L.push ? 1 : 0;
+    }
+    return cc;
+}
+
+namespace {
 
 struct Run {
     Hier* H;
@@ -784,9 +852,42 @@ void bottom(Run& R, size_t l) {
 }
 
 template <class T>
+DevBuf<CoarseCycle<T>>& cc_buf(Hier* H);
+template <>
+DevBuf<CoarseCycle<double>>& cc_buf<double>(Hier* H) { return H->cc64; }
+template <>
+DevBuf<CoarseCycle<float>>& cc_buf<float>(Hier* H) { return H->cc32; }
+template <class T>
+CoarseCycle<T>& cc_host(Hier* H);
+template <>
+CoarseCycle<double>& cc_host<double>(Hier* H) { return H->cc64_host; }
+template <>
+CoarseCycle<float>& cc_host<float>(Hier* H) { return H->cc32_host; }
+
+// the fused coarse cycle; its descriptor is uploaded when the settings change
+template <class T>
+void coarse_cycle(Run& R) {
+    Hier* H = R.H;
+    static_assert(std::is_trivially_copyable<CoarseCycle<T>>::value, "descriptor must be plain data");
+    DevBuf<CoarseCycle<T>>& buf = cc_buf<T>(H);
+    CoarseCycle<T>& host = cc_host<T>(H);
+    const CoarseCycle<T> cc = coarse_desc<T>(H, R.nu1, R.nu2, R.prolong, R.bottom_rtol);
+    if (!buf.p || std::memcmp(&cc, &host, sizeof cc) != 0) {
+        if (!buf.p) buf.alloc(1);
+        host = cc;  // lives as long as the hierarchy: safe source for the async copy
+        HIPCHK(hipMemcpyAsync(buf.p, &host, sizeof host, hipMemcpyHostToDevice, R.s));
+    }
+    HIPCHK(launch_coarse_cycle<T>(R.s, buf.p, H->var));
+}
+
+template <class T>
 void vcycle(Run& R, size_t l) {
     Hier* H = R.H;
     const size_t last = H->L.size() - 1;
+    if ((int)l == H->coarse_start) {
+        coarse_cycle<T>(R);
+        return;
+    }
     if (l == last) {
         bottom<T>(R, l);
         return;
@@ -805,7 +906,7 @@ void vcycle(Run& R, size_t l) {
     vcycle<T>(R, l + 1);
     fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full);
     R.pre(l, kStageProlong);
-    HIPCHK(launch_prolong<T>(R.s, H->xgrid(l), lvl_u<T>(H, l + 1), u, R.prolong));
+    HIPCHK(launch_prolong<T>(R.s, L.grid(), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong));
     R.post(l, kStageProlong);
     smooth<T>(R, l, R.nu2);
 }
@@ -1100,7 +1201,8 @@ static bool bottom_fits(const Box& dom) {
 
 static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var, double h, bxmg_status* st) {
     char key[128];
-    std::snprintf(key, sizeof key, "%llu/%d/%d/%.17g", (unsigned long long)ba->id, precision, (int)var, h);
+    std::snprintf(key, sizeof key, "%llu/%d/%d/%.17g/%d/%d", (unsigned long long)ba->id, precision, (int)var, h,
+                  ctx->zc, ctx->zc_planes);
     auto it = ctx->cache.find(key);
     if (it != ctx->cache.end()) return it->second.get();
     auto lb = make_hierarchy(ba->dom, ba->boxes);
@@ -1112,7 +1214,10 @@ static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var
     }
     std::unique_ptr<Hier> H;
     try {
-        H = build_hier(ba, precision, var, h);
+        Tuning tune;
+        tune.zc = ctx->zc;
+        tune.zc_planes = ctx->zc_planes;
+        H = build_hier(ba, precision, var, h, tune);
     } catch (HipError& e) {
         *st = fail(e.e == hipErrorOutOfMemory ? BXMG_ENOMEM : BXMG_EDEVICE,
                    std::string("solve: hierarchy setup: ") + e.where + ": " + hipGetErrorString(e.e));
@@ -1239,6 +1344,16 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
     return (bxmg_status)info->status;
 }
 
+
+bxmg_status bxmg_ctx_tune(bxmg_ctx ctx, int32_t param, int32_t value) {
+    if (!ctx) return fail(BXMG_EINVAL, "ctx_tune: NULL context");
+    if (value < 1 || value > 64) return fail(BXMG_EINVAL, "ctx_tune: value out of range [1, 64]");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (param == 0) ctx->zc = value;
+    else if (param == 1) ctx->zc_planes = value;
+    else return fail(BXMG_EINVAL, "ctx_tune: unknown parameter");
+    return BXMG_OK;
+}
 
 bxmg_status bxmg_profile_stage(bxmg_ctx ctx, int32_t stage) {
     if (!ctx) return fail(BXMG_EINVAL, "profile_stage: NULL context");
@@ -1388,7 +1503,7 @@ bxmg_status bxmg_prolong_add(bxmg_ctx ctx, bxmg_multifab coarse, bxmg_multifab f
         HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)fine->data, fine->d_fboxes.p, H->u64[0]->p, false));
         HIPCHK(launch_fab_to_rb(R.s, L1.grid(), (const double*)coarse->data, coarse->d_fboxes.p, H->u64[1]->p, false));
         fill<double>(R, 1, H->u64[1]->p, L1.full);
-        HIPCHK(launch_prolong<double>(R.s, H->xgrid(0), H->u64[1]->p, H->u64[0]->p, order));
+        HIPCHK(launch_prolong<double>(R.s, L0.grid(), L1.d_rb.p, L0.cbox.p, H->u64[1]->p, H->u64[0]->p, order));
         HIPCHK(launch_rb_to_fab(R.s, L0.grid(), H->u64[0]->p, (double*)fine->data, fine->d_fboxes.p));
         HIPCHK(hipStreamSynchronize(R.s));
     } catch (HipError& e) {

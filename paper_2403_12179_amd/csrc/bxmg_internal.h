@@ -112,6 +112,35 @@ struct XGrid {
     int push;  // as Grid::push, for the fine level
 };
 
+// One level of the fused coarse V-cycle: a single box in RB storage.
+template <class T>
+struct CoarseLevel {
+    RBox box;  // box.nb[q] == 0: the box itself (periodic), -1: Dirichlet face
+    T* u;
+    T* f;
+    const GhostCopy* face[2];
+    long long nface[2];
+    const GhostCopy* full;
+    long long nfull;
+    long long nelem;
+    double h;
+    FaceArrays<T> fa;  // coefficient faces (c[0] == nullptr: constant coefficient)
+    int push;
+};
+
+constexpr int kMaxCoarseLevels = 8;
+
+// The levels of the fused coarse cycle, finest first; the last is the bottom.
+template <class T>
+struct CoarseCycle {
+    int nlev;
+    int nu1, nu2, prolong;
+    int per[3];
+    double rtol;
+    int* iters;
+    CoarseLevel<T> L[kMaxCoarseLevels];
+};
+
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `s` and return hipSuccess or the launch error.
 hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* list, long long n);
@@ -135,8 +164,11 @@ hipError_t launch_resid_restrict(hipStream_t s, const XGrid& x, const T* u, cons
                                  FaceArrays<T> fa, T ih2, T* fc);
 template <class T>
 hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* fc);
+// fine += P coarse: one thread per fine cell over the fine level's colour
+// tiles; cbox[b] = coarse box holding the coarsened fine box b
 template <class T>
-hipError_t launch_prolong(hipStream_t s, const XGrid& x, const T* ec, T* uf, int order);
+hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
+                          int order);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n);
@@ -161,5 +193,9 @@ template <class T>
 hipError_t launch_bottom(hipStream_t s, T* u, const T* f, FaceArrays<T> fa, bool var, const RBox* boxes, int nboxes,
                          const int* dom_lo, const int* dom_hi, const int* periodic, double h, double rtol,
                          int* iters_out);
+
+// the fused coarse V-cycle (one workgroup); cc lives in device memory
+template <class T>
+hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, bool var);
 
 }  // namespace bxmg

@@ -383,54 +383,48 @@ __global__ void __launch_bounds__(kBlock) k_restrict_plain(XGrid x, const T* __r
 }
 
 // ---------------------------------------------------- prolongation + add
-// One thread per coarse cell: its 8 children get
+// One thread per fine cell (both colours of a colour-tile slot): the parent
+// is P = floor(i/2) per direction and the neighbour on the child's side is
+// P + s, s = +1 for an odd index, -1 for an even one; with c_abc the coarse
+// value at P shifted by a*sx, b*sy, c*sz,
 //   e = (((27 c000 + 9 ((c100 + c010) + c001)) + 3 ((c110 + c101) + c011)) + c111) / 64
-// where c_abc is the coarse value at the parent shifted by a*sx, b*sy, c*sz
-// and s = +1 for an odd child index, -1 for an even one (trilinear), or
-// e = c000 (piecewise constant).  Coarse ghosts must be current.
+// (trilinear) or e = c000 (piecewise constant).  Coarse ghosts must be current.
 template <class T, bool PUSH>
-__global__ void __launch_bounds__(kBlock) k_prolong(XGrid x, const T* __restrict__ ec, T* __restrict__ uf, int order) {
-    const Tile tl = x.tiles[tile_index()];
-    const RBox B = x.fboxes[tl.box];
-    const RBox C = x.cboxes[x.cbox[tl.box]];
-    const TileThread th = tile_thread(tl, x.sh);
-    const int I = (B.lo[0] >> 1) + th.x, J = (B.lo[1] >> 1) + th.y;
-    if (I > (B.hi[0] >> 1) || J > (B.hi[1] >> 1)) return;
-    for (int z = 0; z < x.sh.zc; ++z) {
-        const int K = (B.lo[2] >> 1) + th.z0 + z * th.dz;
-        if (K > (B.hi[2] >> 1)) break;
-        T v[3][3][3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    v[c][b][a] = (order == 1 && (a != 1 || b != 1 || c != 1)) ? T(0)
-                                                                              : ec[rb_idx(C, I + a - 1, J + b - 1, K + c - 1)];
-#pragma unroll
-        for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-            for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-                for (int cx = 0; cx < 2; ++cx) {
-                    const int sx = cx ? 2 : 0, sy = cy ? 2 : 0, sz = cz ? 2 : 0;  // neighbour slot: parent 1 -+ 1
-                    T e;
-                    if (order == 1) {
-                        e = v[1][1][1];
-                    } else {
-                        const T c000 = v[1][1][1];
-                        const T c100 = v[1][1][sx], c010 = v[1][sy][1], c001 = v[sz][1][1];
-                        const T c110 = v[1][sy][sx], c101 = v[sz][1][sx], c011 = v[sz][sy][1];
-                        const T c111 = v[sz][sy][sx];
-                        e = (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
-                            T(0.015625);
-                    }
-                    const long long idx = rb_idx(B, 2 * I + cx, 2 * J + cy, 2 * K + cz);
-                    const T v = uf[idx] + e;
-                    uf[idx] = v;
-                    if constexpr (PUSH) push_ghosts(uf, x.fboxes, B, 2 * I + cx, 2 * J + cy, 2 * K + cz, v);
-                }
+__global__ void __launch_bounds__(kBlock) k_prolong(Grid g, const RBox* __restrict__ cboxes, const int* __restrict__ cbox,
+                                                   const T* __restrict__ ec, T* __restrict__ uf, int order) {
+    const Tile tl = g.tiles[tile_index()];
+    const RBox B = g.boxes[tl.box];
+    const RBox C = cboxes[cbox[tl.box]];
+    const TileThread th = tile_thread(tl, g.sh);
+    const int j = B.lo[1] + th.y;
+    if (j > B.hi[1]) return;
+    const int J = j >> 1, sj = (j & 1) ? 1 : -1;
+    for (int z = 0; z < g.sh.zc; ++z) {
+        const int k = B.lo[2] + th.z0 + z * th.dz;
+        if (k > B.hi[2]) break;
+        const int K = k >> 1, sk = (k & 1) ? 1 : -1;
+        for (int c = 0; c < 2; ++c) {
+            const int i = colour_i(B, th.x, j, k, c);
+            if (i > B.hi[0]) continue;
+            const int I = i >> 1, si = (i & 1) ? 1 : -1;
+            T e;
+            const T c000 = ec[rb_idx(C, I, J, K)];
+            if (order == 1) {
+                e = c000;
+            } else {
+                const T c100 = ec[rb_idx(C, I + si, J, K)], c010 = ec[rb_idx(C, I, J + sj, K)];
+                const T c001 = ec[rb_idx(C, I, J, K + sk)];
+                const T c110 = ec[rb_idx(C, I + si, J + sj, K)], c101 = ec[rb_idx(C, I + si, J, K + sk)];
+                const T c011 = ec[rb_idx(C, I, J + sj, K + sk)];
+                const T c111 = ec[rb_idx(C, I + si, J + sj, K + sk)];
+                e = (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
+                    T(0.015625);
+            }
+            const long long idx = rb_idx(B, i, j, k);
+            const T v = uf[idx] + e;
+            uf[idx] = v;
+            if constexpr (PUSH) push_ghosts(uf, g.boxes, B, i, j, k, v);
+        }
     }
 }
 
@@ -608,13 +602,22 @@ __device__ __forceinline__ double bot_reduce(double v, double* sh) {
     return sh[32];
 }
 
+struct BottomLds {
+    double p[kBotGrown];
+    double x[kMaxBottomCells], r[kMaxBottomCells], q[kMaxBottomCells];
+    double sh[40];
+};
+
+// The whole CG, executed by one workgroup (any block size, multiple of 64).
 template <class T, bool VAR>
-__global__ void __launch_bounds__(kBotThreads) k_bottom(T* __restrict__ u, const T* __restrict__ f, FaceArrays<T> fa,
-                                                       const RBox* __restrict__ boxes, BottomGeom G, double h,
-                                                       double rtol, int* __restrict__ iters_out) {
-    __shared__ double p[kBotGrown];
-    __shared__ double x[kMaxBottomCells], r[kMaxBottomCells], q[kMaxBottomCells];
-    __shared__ double sh[40];
+__device__ void bottom_cg(T* __restrict__ u, const T* __restrict__ f, const FaceArrays<T>& fa,
+                          const RBox* __restrict__ boxes, const BottomGeom& G, double h, double rtol,
+                          int* __restrict__ iters_out, BottomLds& S) {
+    double* p = S.p;
+    double* x = S.x;
+    double* r = S.r;
+    double* q = S.q;
+    double* sh = S.sh;
     const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
     const int N = nx * ny * nz;
     const int gx = nx + 2, gy = ny + 2;
@@ -738,6 +741,176 @@ __global__ void __launch_bounds__(kBotThreads) k_bottom(T* __restrict__ u, const
     if (threadIdx.x == 0 && iters_out) *iters_out = it;
 }
 
+template <class T, bool VAR>
+__global__ void __launch_bounds__(kBotThreads) k_bottom(T* __restrict__ u, const T* __restrict__ f, FaceArrays<T> fa,
+                                                       const RBox* __restrict__ boxes, BottomGeom G, double h,
+                                                       double rtol, int* __restrict__ iters_out) {
+    __shared__ BottomLds S;
+    bottom_cg<T, VAR>(u, f, fa, boxes, G, h, rtol, iters_out, S);
+}
+
+// --------------------------------------------------- fused coarse V-cycle
+// The V-cycle below a level whose remaining levels are single boxes of at
+// most kMaxBottomCells cells runs as one workgroup in one launch: the same
+// stages in the same order as the level-by-level launches (pre-smoothing,
+// residual + restriction, zero coarse guess, ..., CG bottom, ..., ghost fill
+// of the coarse level, prolongation, post-smoothing), each a block-strided
+// loop closed by a barrier.  Launch latency, not bandwidth, bounds these
+// levels, so one launch replaces some 20 per level.
+template <class T>
+__device__ void blk_fill(T* __restrict__ data, const GhostCopy* __restrict__ list, long long n) {
+    for (long long g = threadIdx.x; g < n; g += blockDim.x) {
+        const GhostCopy pc = list[g];
+        const T v = data[pc.src & 0x7fffffffu];
+        data[pc.dst] = (pc.src >> 31) ? -v : v;
+    }
+    __syncthreads();
+}
+
+// colour cell g of a single box: (i, j, k) or false
+__device__ __forceinline__ bool box_colour_cell(const RBox& B, long long g, int c, int& i, int& j, int& k) {
+    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1;
+    const int tn = (nx + 1) >> 1;
+    const int t = (int)(g % tn);
+    const long long r = g / tn;
+    j = B.lo[1] + (int)(r % ny);
+    k = B.lo[2] + (int)(r / ny);
+    i = colour_i(B, t, j, k, c);
+    return i <= B.hi[0];
+}
+
+__device__ __forceinline__ long long box_colour_cells(const RBox& B) {
+    const long long nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1, nz = B.hi[2] - B.lo[2] + 1;
+    return ((nx + 1) >> 1) * ny * nz;
+}
+
+template <class T, int MODE>
+__device__ void blk_gs(const CoarseLevel<T>& L, int colour) {
+    const RBox& B = L.box;
+    const long long n = box_colour_cells(B);
+    const T h2 = (T)(L.h * L.h);
+    for (long long g = threadIdx.x; g < n; g += blockDim.x) {
+        int i, j, k;
+        if (!box_colour_cell(B, g, colour, i, j, k)) continue;
+        T su, sb, uc;
+        long long idx;
+        stencil<T, MODE>(L.u, (const T*)nullptr, L.fa, B, i, j, k, su, sb, uc, idx);
+        const T v = (su - h2 * L.f[idx]) / sb;
+        L.u[idx] = v;
+        if (L.push) push_ghosts(L.u, &L.box, B, i, j, k, v);
+    }
+    __syncthreads();
+}
+
+template <class T, int MODE>
+__device__ void blk_smooth(const CoarseLevel<T>& L, int nsweeps) {
+    for (int s = 0; s < nsweeps; ++s)
+        for (int c = 0; c < 2; ++c) {
+            if (!L.push) blk_fill(L.u, L.face[c ^ 1], L.nface[c ^ 1]);
+            blk_gs<T, MODE>(L, c);
+        }
+}
+
+template <class T, int MODE>
+__device__ void blk_resid_restrict(const CoarseLevel<T>& F, const CoarseLevel<T>& C) {
+    const RBox& B = F.box;
+    const int cnx = (B.hi[0] - B.lo[0] + 1) >> 1, cny = (B.hi[1] - B.lo[1] + 1) >> 1, cnz = (B.hi[2] - B.lo[2] + 1) >> 1;
+    const long long n = (long long)cnx * cny * cnz;
+    const T ih2 = (T)(1.0 / (F.h * F.h));
+    for (long long g = threadIdx.x; g < n; g += blockDim.x) {
+        const int I = (B.lo[0] >> 1) + (int)(g % cnx);
+        const int J = (B.lo[1] >> 1) + (int)((g / cnx) % cny);
+        const int K = (B.lo[2] >> 1) + (int)(g / ((long long)cnx * cny));
+        const int i = 2 * I, j = 2 * J, k = 2 * K;
+        auto ra = [&](int a, int b, int c) {
+            T su, sb, uc;
+            long long idx;
+            stencil<T, MODE>(F.u, (const T*)nullptr, F.fa, B, a, b, c, su, sb, uc, idx);
+            return F.f[idx] - (su - sb * uc) * ih2;
+        };
+        const T r000 = ra(i, j, k), r100 = ra(i + 1, j, k), r010 = ra(i, j + 1, k), r110 = ra(i + 1, j + 1, k);
+        const T r001 = ra(i, j, k + 1), r101 = ra(i + 1, j, k + 1), r011 = ra(i, j + 1, k + 1);
+        const T r111 = ra(i + 1, j + 1, k + 1);
+        const T s = ((r000 + r100) + (r010 + r110)) + ((r001 + r101) + (r011 + r111));
+        C.f[rb_idx(C.box, I, J, K)] = s * T(0.125);
+    }
+    __syncthreads();
+}
+
+template <class T>
+__device__ void blk_zero(const CoarseLevel<T>& L) {
+    for (long long g = threadIdx.x; g < L.nelem; g += blockDim.x) L.u[g] = T(0);
+    __syncthreads();
+}
+
+template <class T>
+__device__ void blk_prolong(const CoarseLevel<T>& C, const CoarseLevel<T>& F, int order) {
+    const RBox& B = F.box;
+    const long long n = box_colour_cells(B);
+    for (long long g = threadIdx.x; g < n; g += blockDim.x)
+        for (int c = 0; c < 2; ++c) {
+            int i, j, k;
+            if (!box_colour_cell(B, g, c, i, j, k)) continue;
+            const int I = i >> 1, J = j >> 1, K = k >> 1;
+            const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+            const RBox& Q = C.box;
+            const T c000 = C.u[rb_idx(Q, I, J, K)];
+            T e;
+            if (order == 1) {
+                e = c000;
+            } else {
+                const T c100 = C.u[rb_idx(Q, I + si, J, K)], c010 = C.u[rb_idx(Q, I, J + sj, K)];
+                const T c001 = C.u[rb_idx(Q, I, J, K + sk)];
+                const T c110 = C.u[rb_idx(Q, I + si, J + sj, K)], c101 = C.u[rb_idx(Q, I + si, J, K + sk)];
+                const T c011 = C.u[rb_idx(Q, I, J + sj, K + sk)];
+                const T c111 = C.u[rb_idx(Q, I + si, J + sj, K + sk)];
+                e = (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
+                    T(0.015625);
+            }
+            const long long idx = rb_idx(B, i, j, k);
+            const T v = F.u[idx] + e;
+            F.u[idx] = v;
+            if (F.push) push_ghosts(F.u, &F.box, B, i, j, k, v);
+        }
+    __syncthreads();
+}
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(kBotThreads) k_coarse_cycle(const CoarseCycle<T>* __restrict__ ccp) {
+    __shared__ BottomLds S;
+    const CoarseCycle<T>& cc = *ccp;
+    const int nl = cc.nlev;
+    for (int l = 0; l + 1 < nl; ++l) {
+        const CoarseLevel<T>& F = cc.L[l];
+        blk_smooth<T, MODE>(F, cc.nu1);
+        if (!F.push) {
+            blk_fill(F.u, F.face[0], F.nface[0]);
+            blk_fill(F.u, F.face[1], F.nface[1]);
+        }
+        blk_resid_restrict<T, MODE>(F, cc.L[l + 1]);
+        blk_zero(cc.L[l + 1]);
+    }
+    {
+        const CoarseLevel<T>& Lb = cc.L[nl - 1];
+        BottomGeom G;
+        for (int d = 0; d < 3; ++d) {
+            G.dlo[d] = Lb.box.lo[d];
+            G.n[d] = Lb.box.hi[d] - Lb.box.lo[d] + 1;
+            G.per[d] = cc.per[d];
+        }
+        G.nboxes = 1;
+        bottom_cg<T, MODE == 2>(Lb.u, Lb.f, Lb.fa, &Lb.box, G, Lb.h, cc.rtol, cc.iters, S);
+        __syncthreads();
+    }
+    for (int l = nl - 2; l >= 0; --l) {
+        const CoarseLevel<T>& F = cc.L[l];
+        const CoarseLevel<T>& C = cc.L[l + 1];
+        blk_fill(C.u, C.full, C.nfull);
+        blk_prolong(C, F, cc.prolong);
+        blk_smooth<T, MODE>(F, cc.nu2);
+    }
+}
+
 // ================================================================ launchers
 static inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -827,14 +1000,16 @@ hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* 
 template hipError_t launch_restrict_plain<double>(hipStream_t, const XGrid&, const double*, double*);
 
 template <class T>
-hipError_t launch_prolong(hipStream_t s, const XGrid& x, const T* ec, T* uf, int order) {
-    if (x.ntiles <= 0) return hipSuccess;
-    if (x.push) hipLaunchKernelGGL((k_prolong<T, true>), dim3(x.ntiles), dim3(kBlock), 0, s, x, ec, uf, order);
-    else hipLaunchKernelGGL((k_prolong<T, false>), dim3(x.ntiles), dim3(kBlock), 0, s, x, ec, uf, order);
+hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
+                          int order) {
+    if (fine.ntiles <= 0) return hipSuccess;
+    if (fine.push) hipLaunchKernelGGL((k_prolong<T, true>), dim3(fine.ntiles), dim3(kBlock), 0, s, fine, cboxes, cbox, ec, uf, order);
+    else hipLaunchKernelGGL((k_prolong<T, false>), dim3(fine.ntiles), dim3(kBlock), 0, s, fine, cboxes, cbox, ec, uf, order);
     return hipGetLastError();
 }
-template hipError_t launch_prolong<double>(hipStream_t, const XGrid&, const double*, double*, int);
-template hipError_t launch_prolong<float>(hipStream_t, const XGrid&, const float*, float*, int);
+template hipError_t launch_prolong<double>(hipStream_t, const Grid&, const RBox*, const int*, const double*, double*,
+                                           int);
+template hipError_t launch_prolong<float>(hipStream_t, const Grid&, const RBox*, const int*, const float*, float*, int);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n) {
@@ -921,5 +1096,14 @@ template hipError_t launch_bottom<double>(hipStream_t, double*, const double*, F
                                           int, const int*, const int*, const int*, double, double, int*);
 template hipError_t launch_bottom<float>(hipStream_t, float*, const float*, FaceArrays<float>, bool, const RBox*, int,
                                          const int*, const int*, const int*, double, double, int*);
+
+template <class T>
+hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, bool var) {
+    if (var) hipLaunchKernelGGL((k_coarse_cycle<T, 2>), dim3(1), dim3(kBotThreads), 0, s, cc);
+    else hipLaunchKernelGGL((k_coarse_cycle<T, 0>), dim3(1), dim3(kBotThreads), 0, s, cc);
+    return hipGetLastError();
+}
+template hipError_t launch_coarse_cycle<double>(hipStream_t, const CoarseCycle<double>*, bool);
+template hipError_t launch_coarse_cycle<float>(hipStream_t, const CoarseCycle<float>*, bool);
 
 }  // namespace bxmg

@@ -62,17 +62,18 @@ def test_hierarchy_256_in_512_boxes(orc):
     boxes = orc.chop((0, 0, 0), (255, 255, 255), 32)
     lv = orc.hierarchy((0, 0, 0), (255, 255, 255), boxes)
     assert [l[1][0] + 1 for l in lv] == [256, 128, 64, 32, 16, 8, 4, 2]
-    assert [len(l[2]) for l in lv] == [512, 512, 512, 512, 512, 1, 1, 1]
+    assert [len(l[2]) for l in lv] == [512, 512, 1, 1, 1, 1, 1, 1]
     # boxes coarsen one by one with floor division
     for (lo, hi), (clo, chi) in zip(lv[0][2], lv[1][2]):
         assert clo == tuple(x // 2 for x in lo) and chi == tuple(x // 2 for x in hi)
 
 
 def test_hierarchy_negative_lower_corner(orc):
-    boxes = orc.chop((-16, -16, -16), (15, 15, 15), 16)
-    lv = orc.hierarchy((-16, -16, -16), (15, 15, 15), boxes)
-    assert lv[1][0] == (-8, -8, -8) and lv[1][1] == (7, 7, 7)
+    boxes = orc.chop((-64, -64, -64), (63, 63, 63), 32)
+    lv = orc.hierarchy((-64, -64, -64), (63, 63, 63), boxes)
+    assert lv[1][0] == (-32, -32, -32) and lv[1][1] == (31, 31, 31)
     assert sorted(lv[1][2]) == sorted(((tuple(x // 2 for x in lo), tuple(x // 2 for x in hi)) for lo, hi in boxes))
+    assert lv[2][2] == [((-16, -16, -16), (15, 15, 15))]  # 16-cell boxes are merged
 
 
 @pytest.mark.parametrize("n,bottom", [(48, 3), (96, 3), (64, 2), (80, 5), (112, 7), (240, 15)])
