@@ -19,6 +19,14 @@ The JSON line also carries
   cpu_baseline : the FP64 oracle on the machine's host, one thread, on a bounded
                  sample (two V-cycles of the same problem).
 
+After the headline the same line carries, unless --sections says otherwise:
+  mixed_precision : 512^3 variable coefficient in 512 boxes of 64^3, FP64
+                    V-cycles vs FP32 V-cycles inside FP64 refinement
+  batched         : 256 periodic problems of edges 32..128, batch engine vs
+                    plain FP64 solves one at a time
+  serving         : an open-loop request trace (200/s), continuous batching
+                    vs plain FP64 first-come-first-served, p50/p99 latency
+
 Other modes (not the benchmark line):
   --calibrate-copy          also run one elementwise kernel that reads and
                             writes 1 GiB (scales the counters)
@@ -151,6 +159,198 @@ def summarize_counters(d):
     print(json.dumps(out, indent=1))
 
 
+# ------------------------------------------------------------ other rows
+def section_mixed(bx, W, reps=3):
+    """512^3 in 512 boxes of 64^3, Dirichlet, beta = exp(g) (g: 3 box-filter
+    passes, std 1), f ~ U[-1,1]: FP64 V-cycles vs FP32 V-cycles inside FP64
+    refinement, both to 1e-10; error of the mixed solution against the FP64
+    one.  Fields drawn on the device (seeds 3 and 33)."""
+    import torch
+    n = 512
+    ba = bx.BoxArray.chop((0, 0, 0), (n - 1,) * 3, 64, bc=(bx.DIRICHLET0,) * 3)
+    f = W.uniform_rhs_device((n, n, n), 3)
+    beta = W.smooth_gaussian_beta_device((n, n, n), 33)
+    rhs = bx.MultiFab(ba).set_val(0.0).from_tensor(f)
+    bmf = bx.MultiFab(ba).set_val(1.0).from_tensor(beta)
+    del f, beta
+    phi = bx.MultiFab(ba)
+    out = {"workload": "poisson_varcoef_512c_512x64c_dirichlet_tol1e-10", "boxes": len(ba)}
+    sols = {}
+    for prec in (0, 1):
+        times, res = [], None
+        for r in range(reps + 1):
+            phi.set_val(0.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = bx.mlmg_solve(phi, rhs, bmf, rel_tol=TOL, precision=prec)
+            torch.cuda.synchronize()
+            if r > 0:
+                times.append(time.perf_counter() - t0)
+            if not res.ok:
+                raise SystemExit("mixed-precision section: solve failed: %s" % res)
+        key = "fp64" if prec == 0 else "fp32_in_fp64_ir"
+        ms = 1000.0 * min(times)
+        out[key] = {"ms_per_solve": ms, "solves_per_s": 1000.0 / ms, "cycles": res.cycles,
+                    "final_rel_resid_inf": res.rel_resid_inf}
+        sols[prec] = phi.slab.clone()
+    d = (sols[1] - sols[0]).abs().max().item() / sols[0].abs().max().item()
+    out["mixed_vs_fp64_rel_max_diff"] = d
+    out["speedup_mixed_over_fp64"] = out["fp64"]["ms_per_solve"] / out["fp32_in_fp64_ir"]["ms_per_solve"]
+    del sols, phi, rhs, bmf
+    torch.cuda.empty_cache()
+    return out
+
+
+def make_batch_problems(bx, W, nprob=256, seed=4):
+    edges = W.batch_edges(nprob, seed)
+    probs = []
+    for p, e in enumerate(edges):
+        ba = bx.BoxArray.chop((0, 0, 0), (e - 1,) * 3, 32, bc=(bx.PERIODIC,) * 3)
+        f = W.uniform_rhs_device((e, e, e), 4000 + p, mean_zero=True)
+        probs.append(dict(e=e, ba=ba, phi=bx.MultiFab(ba).set_val(0.0), rhs=bx.MultiFab(ba).set_val(0.0).from_tensor(f)))
+    return probs
+
+
+def section_batched(bx, W):
+    """256 periodic problems, edges uniform over {32,48,64,96,128} (seed 4),
+    max box 32, f ~ U[-1,1] minus its mean (seed 4000+p): the batch engine
+    (FP32 V-cycles inside FP64 refinement, one launch per stage over all
+    problems, hipGraph) vs plain FP64 solves one at a time, both to 1e-10."""
+    import torch
+    probs = make_batch_problems(bx, W)
+    cells = sum(p["e"] ** 3 for p in probs)
+    ctx = probs[0]["phi"].ctx
+    out = {"workload": "batch_256_periodic_edges_32-128_maxbox32_tol1e-10", "problems": len(probs),
+           "cells": cells, "boxes": sum(len(p["ba"]) for p in probs)}
+    # warm-up of both paths on a few problems (builds, graph capture)
+    b = bx.Batch(ctx, 12 << 30, 512, precision=1)
+    for p in probs[:4]:
+        b.add(p["phi"], p["rhs"], rel_tol=TOL)
+    b.run(2)
+    for p in probs[:4]:
+        p["phi"].set_val(0.0)
+        bx.mlmg_solve(p["phi"], p["rhs"], rel_tol=TOL)
+    for p in probs:
+        p["phi"].set_val(0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in probs:
+        if b.add(p["phi"], p["rhs"], rel_tol=TOL) is None:
+            raise SystemExit("batched section: arena too small")
+    t_add = time.perf_counter() - t0
+    done = b.run(2)
+    t_batch = time.perf_counter() - t0
+    ok = all(r.ok for _, r in done) and len(done) == len(probs)
+    cyc = [r.cycles for _, r in done]
+    worst = max(r.rel_resid_inf for _, r in done)
+    b.close()
+    # plain FP64, one problem after another
+    t0 = time.perf_counter()
+    cyc64 = []
+    for p in probs:
+        p["phi"].set_val(0.0)
+        r = bx.mlmg_solve(p["phi"], p["rhs"], rel_tol=TOL)
+        cyc64.append(r.cycles)
+        ok = ok and r.ok
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    out.update({"ok": ok, "batched_solves_per_s": len(probs) / t_batch, "batched_seconds": t_batch,
+                "batched_admission_seconds": t_add, "batched_cycles_mean": sum(cyc) / len(cyc),
+                "batched_worst_rel_resid_inf": worst,
+                "fp64_one_at_a_time_solves_per_s": len(probs) / t_one, "fp64_one_at_a_time_seconds": t_one,
+                "fp64_cycles_mean": sum(cyc64) / len(cyc64),
+                "speedup_batched_over_fp64": t_one / t_batch,
+                "batched_cell_updates_per_s": sum(p["e"] ** 3 * c for p, c in zip(probs, cyc)) / t_batch})
+    del probs
+    torch.cuda.empty_cache()
+    return out
+
+
+def stage_requests(bx, W, trace):
+    reqs = []
+    for q in trace:
+        e = q["edge"]
+        ba = bx.BoxArray.chop((0, 0, 0), (e - 1,) * 3, 32, bc=(bx.DIRICHLET0,) * 3)
+        f = W.uniform_rhs_device((e, e, e), q["seed"])
+        rhs = bx.MultiFab(ba).set_val(0.0).from_tensor(f)
+        bmf = None
+        if q["kind"]:
+            bmf = bx.MultiFab(ba).set_val(1.0).from_tensor(W.smooth_gaussian_beta_device((e, e, e), q["seed"] + 1))
+        reqs.append(dict(q=q, ba=ba, phi=bx.MultiFab(ba).set_val(0.0), rhs=rhs, beta=bmf))
+    return reqs
+
+
+def latency_stats(lat, t_first, t_last):
+    import numpy as np
+    a = np.asarray(lat)
+    return {"p50_ms": 1000.0 * float(np.percentile(a, 50)), "p99_ms": 1000.0 * float(np.percentile(a, 99)),
+            "mean_ms": 1000.0 * float(a.mean()), "solves_per_s": len(a) / (t_last - t_first)}
+
+
+def section_serving(bx, W, nreq):
+    """Open-loop trace: exponential inter-arrivals of mean 5 ms (seed 5),
+    edge = clamp(16 round(exp(U(ln 32, ln 256)) / 16), 32, 256), Dirichlet,
+    beta constant or lognormal (1/2 each), tol 10^U(-10,-8), f ~ U[-1,1]
+    (seed 5000+q); inputs staged in HBM before the clock starts.  Served:
+    continuous batching (FP32 V-cycles inside FP64 refinement, admission by
+    footprint, one cycle per pump); baseline: plain FP64 solves one at a
+    time in arrival order.  Latency = completion - arrival."""
+    import torch
+    trace = W.serving_trace(nreq, 5)
+    reqs = stage_requests(bx, W, trace)
+    ctx = reqs[0]["phi"].ctx
+    torch.cuda.synchronize()
+    out = {"workload": "serving_trace_%d_req_200per_s_edges_32-256_dirichlet_tol1e-8..1e-10" % nreq,
+           "requests": nreq, "mean_cells": sum(r["q"]["edge"] ** 3 for r in reqs) / nreq,
+           "lognormal_share": sum(r["q"]["kind"] for r in reqs) / nreq}
+    srv = bx.Server(ctx, 24 << 30, max_problems=512, chunk=1, precision=1)
+    # warm-up: one request of each kind through the server
+    for r in reqs[:2]:
+        srv.submit(-1, r["phi"], r["rhs"], r["beta"], r["q"]["tol"])
+    while not srv.idle():
+        srv.pump()
+    for r in reqs:
+        r["phi"].set_val(0.0)
+    torch.cuda.synchronize()
+    lat, ok, nxt = {}, True, 0
+    t0 = time.perf_counter()
+    while len(lat) + len(srv.rejected) < nreq:
+        now = time.perf_counter() - t0
+        while nxt < nreq and reqs[nxt]["q"]["t"] <= now:
+            r = reqs[nxt]
+            srv.submit(nxt, r["phi"], r["rhs"], r["beta"], r["q"]["tol"])
+            nxt += 1
+        if srv.idle():
+            continue
+        for tag, res, t_done in srv.pump():
+            lat[tag] = (t_done - t0) - reqs[tag]["q"]["t"]
+            ok = ok and res.ok and res.rel_resid_inf <= reqs[tag]["q"]["tol"]
+    t_end = max(lat[k] + reqs[k]["q"]["t"] for k in lat)
+    out["served"] = latency_stats(list(lat.values()), reqs[0]["q"]["t"], t_end)
+    out["served"]["ok"] = ok and not srv.rejected
+    srv.close()
+    # baseline: FP64 solves one at a time, first come first served
+    for r in reqs:
+        r["phi"].set_val(0.0)
+    torch.cuda.synchronize()
+    lat1 = []
+    ok1 = True
+    t0 = time.perf_counter()
+    for r in reqs:
+        while time.perf_counter() - t0 < r["q"]["t"]:
+            pass
+        res = bx.mlmg_solve(r["phi"], r["rhs"], r["beta"], rel_tol=r["q"]["tol"])
+        lat1.append(time.perf_counter() - t0 - r["q"]["t"])
+        ok1 = ok1 and res.ok
+    t_end1 = max(l + r["q"]["t"] for l, r in zip(lat1, reqs))
+    out["fp64_fcfs"] = latency_stats(lat1, reqs[0]["q"]["t"], t_end1)
+    out["fp64_fcfs"]["ok"] = ok1
+    out["p99_ratio_fcfs_over_served"] = out["fp64_fcfs"]["p99_ms"] / out["served"]["p99_ms"]
+    del reqs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +359,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--summarize-counters", metavar="DIR")
+    ap.add_argument("--sections", default="mixed,batched,serving",
+                    help="other rows to measure after the headline (comma list; '' for none)")
+    ap.add_argument("--serving-requests", type=int, default=400)
     args = ap.parse_args()
 
     if args.summarize_counters:
@@ -238,6 +441,19 @@ def main():
                      "algorithmic_bytes_per_launch": gs_bytes, "avg_launch_ms": gs_avg_ms,
                      "launches_timed": launches.value},
     }
+    del phi, rhs
+    torch.cuda.empty_cache()
+    secs = [x for x in args.sections.split(",") if x]
+    for name in secs:
+        print("bench: section %s" % name, file=sys.stderr, flush=True)
+        if name == "mixed":
+            line["mixed_precision"] = section_mixed(bx, W)
+        elif name == "batched":
+            line["batched"] = section_batched(bx, W)
+        elif name == "serving":
+            line["serving"] = section_serving(bx, W, args.serving_requests)
+        else:
+            raise SystemExit("unknown section %r" % name)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(f)
         cb.pop("seconds", None)

@@ -186,8 +186,10 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
 /* Launch-shape knobs for hierarchies built after the call (hierarchies are
  * cached per knob setting): param 0 = planes each thread walks in the cell
  * kernels (default 4); param 1 = the same for levels whose tiles span whole
- * box planes (default 4).  value in [1, 64], else EINVAL.  Results do not
- * depend on the knobs; only the work decomposition does. */
+ * box planes (default 4); value in [1, 64].  param 2 = address box data with
+ * 32-bit buffer offsets where every box allows it (1, default) or with
+ * 64-bit addresses (0).  Other values: EINVAL.  Results do not depend on the
+ * knobs; only the work decomposition and instruction selection do. */
 bxmg_status bxmg_ctx_tune(bxmg_ctx ctx, int32_t param, int32_t value);
 
 /* ---------------------------------------------------------- profiling --- */
@@ -235,6 +237,84 @@ bxmg_status bxmg_prolong_add(bxmg_ctx ctx, bxmg_multifab coarse, bxmg_multifab f
  * *iters receives the iteration count. */
 bxmg_status bxmg_bottom_solve(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab rhs, bxmg_multifab beta, double h,
                               double rtol, int32_t* iters);
+
+/* ------------------------------------------------------------ batches --- */
+/* Many independent problems solved together (the fused multi-box launch of
+ * the paper, Section 3.2, taken across problems).  Every stage of the
+ * V-cycle is one launch over all boxes of that level of every running
+ * problem; the trailing single-box levels of each problem run as one
+ * workgroup of one shared launch.  Per cycle: FP64 residual and norms of
+ * every problem, a stop test on the device (each problem with its own
+ * tolerance), then the V-cycle of those still running; a problem that has
+ * stopped costs nothing more.  The cycle is captured once as a hipGraph and
+ * replayed (rebuilt whenever problems join or leave).
+ *
+ * Memory: level storage of all problems lives in one arena sized by the
+ * budget given at creation (the arena is the budget; nothing else grows
+ * with the number of problems except small per-problem tables).  A problem
+ * is admitted only if its levels fit in the free part of the arena (the
+ * admission by HBM footprint the serving loop needs); problems keep their
+ * storage on the device until they finish.
+ *
+ * Every problem's result is the one bxmg_mlmg_solve gives for it alone with
+ * the batch's parameters: the same kernels in the same order per problem,
+ * and stop tests on exact max-norms.  */
+typedef struct bxmg_batch_s* bxmg_batch;
+
+/* params: shared by all problems (NULL = defaults; precision 1 = FP32
+ * V-cycle inside FP64 refinement); var != 0: every problem brings a beta
+ * MultiFab, var == 0: none does.  max_problems: slots (1..4096).
+ * hbm_budget_bytes: arena plus coefficient storage (at most 2^31 elements
+ * per arena array).  Each call takes the context's lock. */
+bxmg_status bxmg_batch_create(bxmg_ctx ctx, size_t hbm_budget_bytes, int32_t max_problems, int32_t var,
+                              const bxmg_solve_params* params, bxmg_batch* out);
+void bxmg_batch_destroy(bxmg_batch b);
+
+/* Device bytes problem `ba` would take in batch b (0 if it cannot run in a
+ * batch: a domain whose trailing levels are not single boxes of at most 4096
+ * cells, or level storage beyond 2^31 elements). */
+size_t bxmg_batch_footprint(bxmg_batch b, bxmg_boxarray ba);
+
+/* Admits a problem: converts phi (initial guess) and rhs (and beta) into
+ * the arena on the batch's stream and computes ||rhs||_inf (one host sync).
+ * rel_tol <= 0: the batch's rel_tol.  The MultiFabs (FP64, nghost >= 1,
+ * one BoxArray) must stay alive until the result is polled: phi receives
+ * the solution.  BXMG_EBUSY: the footprint does not fit now or every slot
+ * is taken (nothing changed); EINVAL: bad arguments or a domain a batch
+ * cannot run.  *id identifies the problem in poll / remove. */
+bxmg_status bxmg_batch_add(bxmg_batch b, bxmg_multifab phi, bxmg_multifab rhs, bxmg_multifab beta, double rel_tol,
+                           int64_t* id);
+
+/* Runs ncycles (>= 1) batch cycles, then synchronises once, writes the
+ * solutions of the problems that stopped into their phi and queues their
+ * results for poll.  *nrunning (may be NULL): problems still running. */
+bxmg_status bxmg_batch_step(bxmg_batch b, int32_t ncycles, int32_t* nrunning);
+
+/* bxmg_batch_step in two halves, so that the cycles of several batches
+ * (each on its own stream) overlap on the device: launch enqueues ncycles
+ * cycles and returns at once (EBUSY if an earlier launch is not collected);
+ * collect waits for them and does the rest of a step.  add, remove and set
+ * are refused (EINVAL) between the two. */
+bxmg_status bxmg_batch_launch(bxmg_batch b, int32_t ncycles);
+bxmg_status bxmg_batch_collect(bxmg_batch b, int32_t* nrunning);
+
+/* Up to max finished problems, oldest first: ids[i] and infos[i] (status,
+ * cycles, history; seconds = time from add to the end of its last step).
+ * *ndone receives the number returned. */
+bxmg_status bxmg_batch_poll(bxmg_batch b, int32_t max, int64_t* ids, bxmg_solve_info* infos, int32_t* ndone);
+
+/* Cancels a running problem (its phi keeps whatever it held) or drops a
+ * finished one from the poll queue.  EINVAL for an unknown id. */
+bxmg_status bxmg_batch_remove(bxmg_batch b, int64_t id);
+
+/* Occupancy: device bytes in use by problems, the budget, running problems,
+ * finished problems waiting in the poll queue (any pointer may be NULL). */
+bxmg_status bxmg_batch_stats(bxmg_batch b, size_t* bytes_used, size_t* bytes_budget, int32_t* nrunning,
+                             int32_t* nqueued);
+
+/* Knobs: param 0 = capture the cycle as a hipGraph (value 1, default) or
+ * launch it stage by stage (0).  Results do not depend on it. */
+bxmg_status bxmg_batch_set(bxmg_batch b, int32_t param, int32_t value);
 
 #ifdef __cplusplus
 }

@@ -73,6 +73,17 @@ def _declare(lib):
         "bxmg_restrict": (C.c_int, [H, H, H]),
         "bxmg_prolong_add": (C.c_int, [H, H, H, C.c_int32]),
         "bxmg_bottom_solve": (C.c_int, [H, H, H, H, C.c_double, C.c_double, I32P]),
+        "bxmg_batch_create": (C.c_int, [H, C.c_size_t, C.c_int32, C.c_int32, C.POINTER(SolveParams), C.POINTER(H)]),
+        "bxmg_batch_destroy": (None, [H]),
+        "bxmg_batch_footprint": (C.c_size_t, [H, H]),
+        "bxmg_batch_add": (C.c_int, [H, H, H, H, C.c_double, I64P]),
+        "bxmg_batch_step": (C.c_int, [H, C.c_int32, I32P]),
+        "bxmg_batch_launch": (C.c_int, [H, C.c_int32]),
+        "bxmg_batch_collect": (C.c_int, [H, I32P]),
+        "bxmg_batch_poll": (C.c_int, [H, C.c_int32, I64P, C.POINTER(SolveInfo), I32P]),
+        "bxmg_batch_remove": (C.c_int, [H, C.c_int64]),
+        "bxmg_batch_stats": (C.c_int, [H, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), I32P, I32P]),
+        "bxmg_batch_set": (C.c_int, [H, C.c_int32, C.c_int32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -249,6 +249,20 @@ class MultiFab:
         self.slab.copy_(torch.from_numpy(host))
         return self
 
+    def from_tensor(self, t, comp=0):
+        """Set valid cells of component comp from a domain-sized device tensor
+        indexed [i, j, k] (box by box, on the device)."""
+        D = self.ba.domain
+        ng = self.nghost
+        for b in range(len(self.ba)):
+            g = self.grown_box(b)
+            v = self.array(b)
+            if self.ncomp > 1:
+                v = v[..., comp]
+            src = t[tuple(slice(g.small[d] + ng - D.small[d], g.big[d] - ng - D.small[d] + 1) for d in range(3))]
+            v[ng:v.shape[0] - ng, ng:v.shape[1] - ng, ng:v.shape[2] - ng].copy_(src)
+        return self
+
     def from_packed(self, packed):
         """Set all cells (valid + ghost) from the oracle's packed layout."""
         import torch

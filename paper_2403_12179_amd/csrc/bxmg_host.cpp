@@ -19,507 +19,10 @@
 
 #include "../../include/bxmg.h"
 #include "bxmg_internal.h"
+#include "bxmg_host.h"
 
-using namespace bxmg;
-
-// ------------------------------------------------------------------ errors
-static thread_local std::string g_err;
-
-static bxmg_status fail(bxmg_status st, const std::string& msg) {
-    g_err = msg;
-    return st;
-}
-
-struct HipError {
-    hipError_t e;
-    const char* where;
-};
-
-#define HIPCHK(...)                                                   \
-    do {                                                              \
-        hipError_t e_ = (__VA_ARGS__);                                \
-        if (e_ != hipSuccess) throw HipError{e_, #__VA_ARGS__};       \
-    } while (0)
-
-// -------------------------------------------------------------- box algebra
-namespace {
-
-struct Box {
-    int lo[3], hi[3];
-    int n(int d) const { return hi[d] - lo[d] + 1; }
-    long long cells() const { return (long long)n(0) * n(1) * n(2); }
-    bool ok() const { return lo[0] <= hi[0] && lo[1] <= hi[1] && lo[2] <= hi[2]; }
-    bool contains(const Box& b) const {
-        for (int d = 0; d < 3; ++d)
-            if (b.lo[d] < lo[d] || b.hi[d] > hi[d]) return false;
-        return true;
-    }
-};
-
-Box intersect(const Box& a, const Box& b) {
-    Box c;
-    for (int d = 0; d < 3; ++d) { c.lo[d] = std::max(a.lo[d], b.lo[d]); c.hi[d] = std::min(a.hi[d], b.hi[d]); }
-    return c;
-}
-
-int floor2(int a) { return a >> 1; }  // arithmetic shift: floor(a/2)
-
-Box coarsen(const Box& b) {
-    Box c;
-    for (int d = 0; d < 3; ++d) { c.lo[d] = floor2(b.lo[d]); c.hi[d] = floor2(b.hi[d]); }
-    return c;
-}
-
-std::vector<std::pair<int, int>> chop1(int lo, int n, int max_box) {
-    int bf = 1;
-    while (n % (bf * 2) == 0 && bf * 2 <= max_box) bf *= 2;
-    const int piece = (max_box / bf) * bf;
-    std::vector<std::pair<int, int>> out;
-    for (int s = 0; s < n; s += piece) out.push_back({lo + s, lo + std::min(s + piece, n) - 1});
-    return out;
-}
-
-bool domain_coarsenable(const Box& dom) {
-    for (int d = 0; d < 3; ++d)
-        if (dom.n(d) % 2 || dom.n(d) < 4 || (dom.lo[d] & 1)) return false;
-    return true;
-}
-
-// Every box holds whole pairs of cells (even lower corner, even edges), so
-// each coarse cell's 8 children lie in one box.
-bool boxes_pair_aligned(const std::vector<Box>& bs) {
-    for (auto& b : bs)
-        for (int d = 0; d < 3; ++d)
-            if (b.n(d) % 2 || (b.lo[d] & 1)) return false;
-    return true;
-}
-
-// Boxes are coarsened one by one while every box edge is at least
-// kMinBoxCoarsen; smaller boxes are merged into one box per level (fewer,
-// larger boxes on the coarse levels: less ghost overhead, and the small
-// single-box levels can run as one fused coarse cycle).
-constexpr int kMinBoxCoarsen = 32;
-
-bool boxes_coarsenable(const std::vector<Box>& bs) {
-    for (auto& b : bs)
-        for (int d = 0; d < 3; ++d)
-            if (b.n(d) % 2 || b.n(d) < kMinBoxCoarsen || (b.lo[d] & 1)) return false;
-    return true;
-}
-
-struct LevelBoxes {
-    Box dom;
-    std::vector<Box> boxes;
-};
-
-std::vector<LevelBoxes> make_hierarchy(const Box& dom, const std::vector<Box>& b0) {
-    std::vector<LevelBoxes> L{LevelBoxes{dom, b0}};
-    while (domain_coarsenable(L.back().dom) && boxes_pair_aligned(L.back().boxes)) {
-        LevelBoxes c;
-        c.dom = coarsen(L.back().dom);
-        if (boxes_coarsenable(L.back().boxes))
-            for (auto& b : L.back().boxes) c.boxes.push_back(coarsen(b));
-        else
-            c.boxes.push_back(c.dom);
-        L.push_back(c);
-    }
-    return L;
-}
-
-// --------------------------------------------------------- ghost-copy plans
-// Region tags for the ghost cells of every box grown by ng.
-// mode 0: FillBoundary (periodic shifts; ghosts outside a non-periodic face
-//         are skipped);  mode 1: physical ghosts only (reflection into the
-//         box's own grown data);  mode 2: FillBoundary and physical ghosts in
-//         one plan (reflection + shift, read straight from the owning box).
-// odd: sign -1 per reflected direction (homogeneous Dirichlet) or +1.
-std::vector<Tag> build_tags(const Box& dom, const int per[3], const std::vector<Box>& boxes, int ng, bool cross,
-                            int mode, bool odd) {
-    std::vector<Tag> tags;
-    long long prefix = 0;
-    for (size_t b = 0; b < boxes.size(); ++b) {
-        const Box& B = boxes[b];
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int dir[3] = {dx, dy, dz};
-                    const int nnz = (dx != 0) + (dy != 0) + (dz != 0);
-                    if (nnz == 0 || (cross && nnz != 1)) continue;
-                    Box slab;
-                    for (int d = 0; d < 3; ++d) {
-                        if (dir[d] < 0) { slab.lo[d] = B.lo[d] - ng; slab.hi[d] = B.lo[d] - 1; }
-                        else if (dir[d] > 0) { slab.lo[d] = B.hi[d] + 1; slab.hi[d] = B.hi[d] + ng; }
-                        else { slab.lo[d] = B.lo[d]; slab.hi[d] = B.hi[d]; }
-                    }
-                    // split the slab per direction into below / inside / above the domain
-                    std::vector<std::pair<int, int>> seg[3];
-                    std::vector<int> kind[3];  // -1 below, 0 inside, +1 above
-                    for (int d = 0; d < 3; ++d) {
-                        const int a = slab.lo[d], z = slab.hi[d];
-                        if (a < dom.lo[d]) { seg[d].push_back({a, std::min(z, dom.lo[d] - 1)}); kind[d].push_back(-1); }
-                        if (std::max(a, dom.lo[d]) <= std::min(z, dom.hi[d])) {
-                            seg[d].push_back({std::max(a, dom.lo[d]), std::min(z, dom.hi[d])});
-                            kind[d].push_back(0);
-                        }
-                        if (z > dom.hi[d]) { seg[d].push_back({std::max(a, dom.hi[d] + 1), z}); kind[d].push_back(1); }
-                    }
-                    for (size_t s0 = 0; s0 < seg[0].size(); ++s0)
-                        for (size_t s1 = 0; s1 < seg[1].size(); ++s1)
-                            for (size_t s2 = 0; s2 < seg[2].size(); ++s2) {
-                                const size_t si[3] = {s0, s1, s2};
-                                Box piece;
-                                int sgn[3], off[3], k[3];
-                                int flips = 0, outside_nonper = 0;
-                                bool skip = false;
-                                for (int d = 0; d < 3; ++d) {
-                                    piece.lo[d] = seg[d][si[d]].first;
-                                    piece.hi[d] = seg[d][si[d]].second;
-                                    k[d] = kind[d][si[d]];
-                                    sgn[d] = 1;
-                                    off[d] = 0;
-                                    if (k[d] == 0) continue;
-                                    if (per[d]) {
-                                        if (mode == 1) continue;  // read own (already exchanged) ghost
-                                        off[d] = (k[d] < 0) ? dom.n(d) : -dom.n(d);
-                                    } else {
-                                        ++outside_nonper;
-                                        if (mode == 0) { skip = true; break; }
-                                        sgn[d] = -1;
-                                        off[d] = (k[d] < 0) ? 2 * dom.lo[d] - 1 : 2 * dom.hi[d] + 1;
-                                        ++flips;
-                                    }
-                                }
-                                if (skip) continue;
-                                if (mode == 1 && outside_nonper == 0) continue;
-                                // image of the piece
-                                Box img;
-                                for (int d = 0; d < 3; ++d) {
-                                    const int a = sgn[d] * piece.lo[d] + off[d], z = sgn[d] * piece.hi[d] + off[d];
-                                    img.lo[d] = std::min(a, z);
-                                    img.hi[d] = std::max(a, z);
-                                }
-                                auto emit = [&](int sbox, const Box& I) {
-                                    Tag t;
-                                    t.dbox = (int)b;
-                                    t.sbox = sbox;
-                                    for (int d = 0; d < 3; ++d) {
-                                        // preimage of I under s = sgn*x + off
-                                        const int a = sgn[d] * (I.lo[d] - off[d]), z = sgn[d] * (I.hi[d] - off[d]);
-                                        t.dlo[d] = std::min(a, z);
-                                        t.n[d] = std::abs(z - a) + 1;
-                                        t.sgn[d] = sgn[d];
-                                        t.soff[d] = off[d];
-                                    }
-                                    t.neg = (odd && (flips & 1)) ? 1 : 0;
-                                    t.pad = 0;
-                                    t.prefix = prefix;
-                                    prefix += (long long)t.n[0] * t.n[1] * t.n[2];
-                                    tags.push_back(t);
-                                };
-                                if (mode == 1) {
-                                    emit((int)b, img);  // mirror lies in the box's own grown region
-                                } else {
-                                    for (size_t q = 0; q < boxes.size(); ++q) {
-                                        Box I = intersect(img, boxes[q]);
-                                        if (I.ok()) emit((int)q, I);
-                                    }
-                                }
-                            }
-                }
-    }
-    return tags;
-}
-
-long long tag_cells(const std::vector<Tag>& t) {
-    if (t.empty()) return 0;
-    return t.back().prefix + (long long)t.back().n[0] * t.back().n[1] * t.back().n[2];
-}
-
-// Tiles: one block of kBlock threads per tile, TX x TY x TZ threads with
-// TX = 2^lx covering x, TY = 2^ly covering y, TZ = 2^lz planes walked zc
-// times.  ext[b] = per-box thread extents (x, y, z).  Tiles run box-major,
-// then z, y, x, so consecutive tiles share halo planes.
-struct TileSet {
-    std::vector<Tile> tiles;
-    TileShape sh;
-};
-
-int ilog2ceil(int n) {
-    int l = 0;
-    while ((1 << l) < n) ++l;
-    return l;
-}
-
-TileSet make_tiles(const std::vector<std::array<int, 3>>& ext, int zc_target) {
-    int mx = 1, my = 1, mz = 1;
-    for (auto& e : ext) { mx = std::max(mx, e[0]); my = std::max(my, e[1]); mz = std::max(mz, e[2]); }
-    TileSet t;
-    t.sh.lx = std::min(ilog2ceil(mx), 6);
-    t.sh.ly = std::min(ilog2ceil(my), 8 - t.sh.lx);
-    t.sh.lz = 8 - t.sh.lx - t.sh.ly;
-    const int TX = 1 << t.sh.lx, TY = 1 << t.sh.ly, TZ = 1 << t.sh.lz;
-    t.sh.zc = std::max(1, std::min(zc_target, (mz + TZ - 1) / TZ));
-    const int KZ = TZ * t.sh.zc;
-    for (size_t b = 0; b < ext.size(); ++b)
-        for (int z0 = 0; z0 < ext[b][2]; z0 += KZ)
-            for (int y0 = 0; y0 < ext[b][1]; y0 += TY)
-                for (int x0 = 0; x0 < ext[b][0]; x0 += TX) t.tiles.push_back(Tile{(int)b, x0, y0, z0});
-    return t;
-}
-
-// Colour-cell extents: ceil(nx/2) cells of one colour per row.
-std::vector<std::array<int, 3>> colour_extents(const std::vector<Box>& boxes) {
-    std::vector<std::array<int, 3>> e;
-    for (auto& b : boxes) e.push_back({(b.n(0) + 1) / 2, b.n(1), b.n(2)});
-    return e;
-}
-
-// Coarse-cell extents of every fine box; extra_d >= 0 adds the high face
-// layer in direction d for boxes touching the fine domain's upper end.
-std::vector<std::array<int, 3>> coarse_extents(const std::vector<Box>& fine, const Box& fdom, int extra_d) {
-    std::vector<std::array<int, 3>> e;
-    for (auto& b : fine) {
-        std::array<int, 3> x{b.n(0) / 2, b.n(1) / 2, b.n(2) / 2};
-        if (extra_d >= 0 && b.hi[extra_d] == fdom.hi[extra_d]) x[extra_d] += 1;
-        e.push_back(x);
-    }
-    return e;
-}
-
-std::vector<int> coarse_owner(const std::vector<Box>& fine, const std::vector<Box>& coarse) {
-    std::vector<int> own;
-    for (auto& b : fine) {
-        const Box c = coarsen(b);
-        int o = -1;
-        for (size_t q = 0; q < coarse.size(); ++q)
-            if (coarse[q].contains(c)) { o = (int)q; break; }
-        if (o < 0) throw std::runtime_error("a coarsened box lies in no coarse box");
-        own.push_back(o);
-    }
-    return own;
-}
-
-// RB layout of a level: per box two colour blocks, each 64-element aligned.
-std::vector<RBox> rb_layout(const std::vector<Box>& boxes, int ng, long long* nelem) {
-    std::vector<RBox> v;
-    long long off = 0;
-    for (auto& b : boxes) {
-        RBox r;
-        for (int d = 0; d < 3; ++d) {
-            r.lo[d] = b.lo[d];
-            r.hi[d] = b.hi[d];
-            r.glo[d] = b.lo[d] - ng;
-            r.G[d] = b.n(d) + 2 * ng;
-        }
-        r.H = (r.G[0] + 1) / 2;
-        r.pid = 0;
-        for (int q = 0; q < 6; ++q) { r.nb[q] = -2; r.shift[q] = 0; }
-        const long long half = (long long)r.H * r.G[1] * r.G[2];
-        const long long padded = (half + 63) / 64 * 64;
-        r.base = off;
-        r.cstride = padded;
-        off += 2 * padded;
-        v.push_back(r);
-    }
-    *nelem = off;
-    return v;
-}
-
-// Face neighbours of every box of a level (RBox::nb / shift).  Returns true
-// when each face is resolvable: the 1-cell slab beyond it lies in one box
-// (after a periodic shift) or outside a Dirichlet domain face.
-bool face_neighbours(const Box& dom, const int per[3], const std::vector<Box>& boxes, std::vector<RBox>& rb) {
-    bool all = true;
-    for (size_t b = 0; b < boxes.size(); ++b)
-        for (int d = 0; d < 3; ++d)
-            for (int side = 0; side < 2; ++side) {
-                const int q = 2 * d + side;
-                Box S = boxes[b];
-                S.lo[d] = S.hi[d] = side ? boxes[b].hi[d] + 1 : boxes[b].lo[d] - 1;
-                int shift = 0;
-                if (S.lo[d] < dom.lo[d] || S.lo[d] > dom.hi[d]) {
-                    if (!per[d]) {
-                        rb[b].nb[q] = -1;
-                        rb[b].shift[q] = 0;
-                        continue;
-                    }
-                    shift = side ? -dom.n(d) : dom.n(d);
-                    S.lo[d] += shift;
-                    S.hi[d] += shift;
-                }
-                int found = -2;
-                for (size_t o = 0; o < boxes.size(); ++o)
-                    if (boxes[o].contains(S)) { found = (int)o; break; }
-                rb[b].nb[q] = found;
-                rb[b].shift[q] = shift;
-                if (found == -2) all = false;
-            }
-    return all;
-}
-
-long long rb_index(const RBox& b, int i, int j, int k) {
-    return b.base + (long long)((i + j + k) & 1) * b.cstride +
-           ((long long)(k - b.glo[2]) * b.G[1] + (j - b.glo[1])) * b.H + ((i - b.glo[0]) >> 1);
-}
-
-// Expand region tags into per-cell (dst, src) element pairs of an RB level,
-// keeping the destinations whose colour is in cmask.
-std::vector<GhostCopy> ghost_list(const std::vector<Tag>& tags, const std::vector<RBox>& rb, int cmask) {
-    std::vector<GhostCopy> out;
-    for (auto& t : tags)
-        for (int z = 0; z < t.n[2]; ++z)
-            for (int y = 0; y < t.n[1]; ++y)
-                for (int x = 0; x < t.n[0]; ++x) {
-                    const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
-                    if (!((cmask >> ((di + dj + dk) & 1)) & 1)) continue;
-                    const int si = t.sgn[0] * di + t.soff[0], sj = t.sgn[1] * dj + t.soff[1],
-                              sk = t.sgn[2] * dk + t.soff[2];
-                    const long long d = rb_index(rb[t.dbox], di, dj, dk), sr = rb_index(rb[t.sbox], si, sj, sk);
-                    if (d < 0 || sr < 0 || d > 0x7fffffffLL || sr > 0x7fffffffLL)
-                        throw std::runtime_error("level storage exceeds 2^31 elements");
-                    out.push_back(GhostCopy{(uint32_t)d, (uint32_t)sr | (t.neg ? 0x80000000u : 0u)});
-                }
-    return out;
-}
-
-// ----------------------------------------------------------- device buffers
-template <class T>
-struct DevBuf {
-    T* p = nullptr;
-    size_t n = 0;
-    DevBuf() = default;
-    DevBuf(const DevBuf&) = delete;
-    DevBuf& operator=(const DevBuf&) = delete;
-    ~DevBuf() { if (p) (void)hipFree(p); }
-    void alloc(size_t count) {
-        if (p) { (void)hipFree(p); p = nullptr; }
-        n = count;
-        if (count) HIPCHK(hipMalloc((void**)&p, count * sizeof(T)));
-    }
-    void upload(const std::vector<T>& v) {
-        alloc(v.size());
-        if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-    }
-};
-
-struct Plan {
-    DevBuf<Tag> tags;
-    int ntags = 0;
-    long long cells = 0;
-    void set(const std::vector<Tag>& t) {
-        tags.upload(t);
-        ntags = (int)t.size();
-        cells = tag_cells(t);
-    }
-};
-
-}  // namespace
-
-// ============================================================ public handles
-struct bxmg_ba_s {
-    Box dom;
-    int bc[3];
-    int per[3];
-    std::vector<Box> boxes;
-    std::atomic<int> refs{1};
-    uint64_t id;
-};
-
-static std::atomic<uint64_t> g_next_id{1};
-
-static void ba_release(bxmg_ba_s* ba) {
-    if (ba && --ba->refs == 0) delete ba;
-}
-
-struct Hier;
-
-// Event pairs around the level-0 launches of one stage (bxmg_profile_stage).
-struct Profiler {
-    int stage = -1;
-    std::vector<hipEvent_t> ev;
-    size_t n = 0;
-    long long launches = 0;
-    double ms = 0.0;
-    void mark(hipStream_t s) {
-        if (n >= ev.size()) {
-            hipEvent_t e;
-            HIPCHK(hipEventCreate(&e));
-            ev.push_back(e);
-        }
-        HIPCHK(hipEventRecord(ev[n++], s));
-    }
-    // after the stream has drained
-    void harvest() {
-        for (size_t i = 0; i + 1 < n; i += 2) {
-            float t = 0.f;
-            HIPCHK(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
-            ms += t;
-            ++launches;
-        }
-        n = 0;
-    }
-    ~Profiler() {
-        for (auto e : ev) (void)hipEventDestroy(e);
-    }
-};
-
-
-struct bxmg_ctx_s {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    Profiler prof;
-    int zc = 4, zc_planes = 4;  // tile depths for hierarchies built from now on
-    std::map<std::string, std::unique_ptr<Hier>> cache;
-    double* h_norm = nullptr;  // pinned
-    std::mutex mu;
-};
-
-struct bxmg_mf_s {
-    bxmg_ctx ctx;
-    bxmg_ba_s* ba;
-    int ncomp, ng;
-    bxmg_dtype dtype;
-    void* data = nullptr;
-    size_t bytes = 0;
-    bool owned = false;
-    std::vector<FBox> fboxes;
-    DevBuf<FBox> d_fboxes;
-    std::map<int, std::unique_ptr<Plan>> plans;  // key: mode*4 + cross*2 + odd
-};
-
-static size_t mf_layout(const bxmg_ba_s* ba, int ncomp, int ng, bxmg_dtype dt, std::vector<FBox>* out) {
-    const size_t es = (dt == BXMG_F64) ? 8 : 4;
-    const size_t align = 256 / es;
-    size_t off = 0;
-    for (auto& b : ba->boxes) {
-        FBox f;
-        long long n = 1;
-        for (int d = 0; d < 3; ++d) {
-            f.lo[d] = b.lo[d];
-            f.hi[d] = b.hi[d];
-            f.glo[d] = b.lo[d] - ng;
-            f.G[d] = b.n(d) + 2 * ng;
-            n *= f.G[d];
-        }
-        f.base = (long long)off;
-        f.cs = n;
-        if (out) out->push_back(f);
-        off += (size_t)n * ncomp;
-        off = (off + align - 1) / align * align;
-    }
-    return off * es;
-}
-
-static Plan* mf_plan(bxmg_mf_s* mf, int mode, bool cross, bool odd) {
-    const int key = mode * 4 + (cross ? 2 : 0) + (odd ? 1 : 0);
-    auto it = mf->plans.find(key);
-    if (it != mf->plans.end()) return it->second.get();
-    auto p = std::make_unique<Plan>();
-    p->set(build_tags(mf->ba->dom, mf->ba->per, mf->ba->boxes, mf->ng, cross, mode, odd));
-    Plan* raw = p.get();
-    mf->plans[key] = std::move(p);
-    return raw;
-}
+thread_local std::string g_err;
+std::atomic<uint64_t> g_next_id{1};
 
 // ================================================================ hierarchy
 namespace {
@@ -527,6 +30,7 @@ namespace {
 template <class T>
 struct FaceSet {
     DevBuf<T> c[3];
+    DevBuf<FaceArrays<T>> table;  // one entry (problem slot 0): the view below
     FaceArrays<T> view(const Box& dom) const {
         FaceArrays<T> f;
         for (int d = 0; d < 3; ++d) { f.c[d] = c[d].p; f.dlo[d] = dom.lo[d]; f.n[d] = dom.n(d); }
@@ -574,7 +78,16 @@ struct Level {
     GhostList full;     // every ghost: exchange + Dirichlet
     GhostList full_even;  // every ghost: exchange + even reflection (cell beta)
     bool push = false;    // producers refresh the face ghosts they mirror
-    Grid grid() const { return Grid{d_rb.p, tcol.p, ntcol, shcol, push ? 1 : 0}; }
+    mutable int flip = 0; // direction of the next sweep over the level's tiles
+    bool res = false;     // 32-bit buffer addressing of the boxes
+    Grid grid() const { return Grid{d_rb.p, tcol.p, ntcol, shcol, push ? 1 : 0, nullptr, 0, res ? 1 : 0}; }
+    // grid of the next sweep in the alternating order (see tile_index)
+    Grid walk() const {
+        Grid g = grid();
+        g.rev = flip;
+        flip ^= 1;
+        return g;
+    }
 };
 
 }  // namespace
@@ -603,12 +116,18 @@ struct Hier {
     XGrid xgrid(size_t l) const {
         const Level& F = *L[l];
         const Level& C = *L[l + 1];
-        return XGrid{F.d_rb.p, C.d_rb.p, F.cbox.p, F.tdown.p, F.ntdown, F.shdown, F.push ? 1 : 0};
+        return XGrid{F.d_rb.p, C.d_rb.p, F.cbox.p, F.tdown.p, F.ntdown, F.shdown, F.push ? 1 : 0, nullptr, 0};
+    }
+    XGrid xwalk(size_t l) const {
+        XGrid x = xgrid(l);
+        x.rev = L[l]->flip;
+        L[l]->flip ^= 1;
+        return x;
     }
     XGrid face_grid(int d) const {
         const Level& F = *L[0];
         const Level& C = *L[1];
-        return XGrid{F.d_rb.p, C.d_rb.p, F.cbox.p, F.tface[d].p, F.ntface[d], F.shface[d], 0};
+        return XGrid{F.d_rb.p, C.d_rb.p, F.cbox.p, F.tface[d].p, F.ntface[d], F.shface[d], 0, nullptr, 0};
     }
 };
 
@@ -617,6 +136,7 @@ struct Hier {
 struct Tuning {
     int zc = 4;
     int zc_planes = 4;
+    int res = 1;
 };
 
 static void upload_tiles(const TileSet& t, DevBuf<Tile>& buf, int& n, TileShape& sh) {
@@ -639,8 +159,9 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
         lv->h = h;
         h *= 2.0;
         lv->boxes = lb[l].boxes;
-        lv->rb = rb_layout(lv->boxes, 1, &lv->nelem);
+        lv->rb = rb_layout(lv->boxes, 1, lv->h, &lv->nelem);
         lv->push = face_neighbours(lv->dom, H->per, lv->boxes, lv->rb);
+        lv->res = tune.res && boxes_fit_res(lv->rb);
         lv->d_rb.upload(lv->rb);
         {
             TileSet ts = make_tiles(colour_extents(lv->boxes), tune.zc);
@@ -710,6 +231,8 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
                     H->faces32[l]->c[d].alloc(nf);
                 }
             }
+            if (precision == 0) H->faces64[l]->table.upload({H->faces64[l]->view(D)});
+            else H->faces32[l]->table.upload({H->faces32[l]->view(D)});
         }
     }
     H->partials.alloc(3 * max_tiles + 8);
@@ -764,6 +287,18 @@ template <>
 FaceArrays<float> lvl_faces<float>(Hier* H, size_t l) {
     if (!H->var || l == 0) return no_faces<float>();
     return H->faces32[l]->view(H->L[l]->dom);
+}
+
+// device table of the level's face arrays (MODE 2 stencils), or nullptr
+template <class T>
+const FaceArrays<T>* lvl_fat(Hier* H, size_t l);
+template <>
+const FaceArrays<double>* lvl_fat<double>(Hier* H, size_t l) {
+    return (!H->var || l == 0) ? nullptr : H->faces64[l]->table.p;
+}
+template <>
+const FaceArrays<float>* lvl_fat<float>(Hier* H, size_t l) {
+    return (!H->var || l == 0) ? nullptr : H->faces32[l]->table.p;
 }
 
 }  // namespace
@@ -833,12 +368,11 @@ void smooth(Run& R, size_t l, int nsweeps) {
     const Level& L = *H->L[l];
     T* u = lvl_u<T>(H, l);
     const T* f = lvl_f<T>(H, l);
-    const T h2 = (T)(L.h * L.h);
     for (int s = 0; s < nsweeps; ++s)
         for (int c = 0; c < 2; ++c) {
             if (!L.push) fill<T>(R, l, u, L.face[c ^ 1]);
             R.pre(l, kStageGS);
-            HIPCHK(launch_gs<T>(R.s, L.grid(), u, f, lvl_beta<T>(H, l), lvl_faces<T>(H, l), h2, c));
+            HIPCHK(launch_gs<T>(R.s, L.walk(), u, f, lvl_beta<T>(H, l), lvl_fat<T>(H, l), c));
             R.post(l, kStageGS);
         }
 }
@@ -877,7 +411,7 @@ void coarse_cycle(Run& R) {
         host = cc;  // lives as long as the hierarchy: safe source for the async copy
         HIPCHK(hipMemcpyAsync(buf.p, &host, sizeof host, hipMemcpyHostToDevice, R.s));
     }
-    HIPCHK(launch_coarse_cycle<T>(R.s, buf.p, H->var));
+    HIPCHK(launch_coarse_cycle<T>(R.s, buf.p, 1, nullptr, H->var));
 }
 
 template <class T>
@@ -897,16 +431,15 @@ void vcycle(Run& R, size_t l) {
     T* u = lvl_u<T>(H, l);
     smooth<T>(R, l, R.nu1);
     if (!L.push) fill_faces<T>(R, l, u);
-    const T ih2 = (T)(1.0 / (L.h * L.h));
     R.pre(l, kStageRestrict);
-    HIPCHK(launch_resid_restrict<T>(R.s, H->xgrid(l), u, lvl_f<T>(H, l), lvl_beta<T>(H, l), lvl_faces<T>(H, l), ih2,
+    HIPCHK(launch_resid_restrict<T>(R.s, H->xwalk(l), u, lvl_f<T>(H, l), lvl_beta<T>(H, l), lvl_fat<T>(H, l),
                                     lvl_f<T>(H, l + 1)));
     R.post(l, kStageRestrict);
     HIPCHK(launch_zero<T>(R.s, lvl_u<T>(H, l + 1), C.nelem));
     vcycle<T>(R, l + 1);
     fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full);
     R.pre(l, kStageProlong);
-    HIPCHK(launch_prolong<T>(R.s, L.grid(), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong));
+    HIPCHK(launch_prolong<T>(R.s, L.walk(), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong));
     R.post(l, kStageProlong);
     smooth<T>(R, l, R.nu2);
 }
@@ -1176,33 +709,10 @@ static bxmg_status set_status(bxmg_solve_info* info, bxmg_status st) {
     return st;
 }
 
-static bxmg_status check_solve_mf(bxmg_multifab m, const bxmg_ba_s* ba, const char* name) {
-    if (!m) return fail(BXMG_EINVAL, std::string("solve: ") + name + " is NULL");
-    if (m->ba != ba && (m->ba->boxes.size() != ba->boxes.size() ||
-                        std::memcmp(m->ba->boxes.data(), ba->boxes.data(), ba->boxes.size() * sizeof(Box)) != 0))
-        return fail(BXMG_EINVAL, std::string("solve: ") + name + " is on a different BoxArray");
-    if (m->dtype != BXMG_F64) return fail(BXMG_EINVAL, std::string("solve: ") + name + " must be FP64");
-    if (m->ng < 1) return fail(BXMG_EINVAL, std::string("solve: ") + name + " needs nghost >= 1");
-    return BXMG_OK;
-}
-
-static bool covers_domain(const bxmg_ba_s* ba) {
-    long long n = 0;
-    for (auto& b : ba->boxes) n += b.cells();
-    return n == ba->dom.cells();  // boxes are disjoint and inside the domain
-}
-
-// The bottom kernel keeps the level's vectors in LDS: at most kMaxBottomCells
-// cells and kBottomGrown cells including the ghost layer.
-static bool bottom_fits(const Box& dom) {
-    const long long grown = (long long)(dom.n(0) + 2) * (dom.n(1) + 2) * (dom.n(2) + 2);
-    return dom.cells() <= kMaxBottomCells && grown <= kBottomGrown;
-}
-
 static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var, double h, bxmg_status* st) {
     char key[128];
-    std::snprintf(key, sizeof key, "%llu/%d/%d/%.17g/%d/%d", (unsigned long long)ba->id, precision, (int)var, h,
-                  ctx->zc, ctx->zc_planes);
+    std::snprintf(key, sizeof key, "%llu/%d/%d/%.17g/%d/%d/%d", (unsigned long long)ba->id, precision, (int)var, h,
+                  ctx->zc, ctx->zc_planes, ctx->res);
     auto it = ctx->cache.find(key);
     if (it != ctx->cache.end()) return it->second.get();
     auto lb = make_hierarchy(ba->dom, ba->boxes);
@@ -1217,6 +727,7 @@ static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var
         Tuning tune;
         tune.zc = ctx->zc;
         tune.zc_planes = ctx->zc_planes;
+        tune.res = ctx->res;
         H = build_hier(ba, precision, var, h, tune);
     } catch (HipError& e) {
         *st = fail(e.e == hipErrorOutOfMemory ? BXMG_ENOMEM : BXMG_EDEVICE,
@@ -1277,8 +788,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         // ghost cells of the converted guess; from here on every producer of
         // level-0 values refreshes the face ghosts it mirrors (push levels)
         fill_faces<double>(R, 0, u);
-        const double ih2 = 1.0 / (L0.h * L0.h);
-        const FaceArrays<double> nf = no_faces<double>();
+        const FaceArrays<double>* nf = nullptr;
         HIPCHK(launch_field_norm(R.s, L0.grid(), f, H->partials.p));
         HIPCHK(launch_norm_final(R.s, H->partials.p, L0.ntcol, H->fnorm.p));
         norm_readback(R, ctx->h_norm, H->fnorm.p);
@@ -1295,10 +805,10 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
                 if (!L0.push) fill_faces<double>(R, 0, u);
                 R.pre(0, kStageResid);
                 if (P.precision == 0) {
-                    HIPCHK(launch_resid<double, double>(R.s, L0.grid(), u, f, beta ? H->beta64.p : nullptr, nf, ih2,
+                    HIPCHK(launch_resid<double, double>(R.s, L0.walk(), u, f, beta ? H->beta64.p : nullptr, nf,
                                                         (double*)nullptr, H->partials.p));
                 } else {
-                    HIPCHK(launch_resid<double, float>(R.s, L0.grid(), u, f, beta ? H->beta64.p : nullptr, nf, ih2,
+                    HIPCHK(launch_resid<double, float>(R.s, L0.walk(), u, f, beta ? H->beta64.p : nullptr, nf,
                                                        H->f32[0]->p, H->partials.p));
                 }
                 R.post(0, kStageResid);
@@ -1324,7 +834,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
                 } else {
                     HIPCHK(launch_zero<float>(R.s, H->u32[0]->p, L0.nelem));
                     vcycle<float>(R, 0);
-                    HIPCHK(launch_add_f32(R.s, L0.grid(), u, H->u32[0]->p));
+                    HIPCHK(launch_add_f32(R.s, L0.walk(), u, H->u32[0]->p));
                 }
             }
         }
@@ -1347,11 +857,13 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
 
 bxmg_status bxmg_ctx_tune(bxmg_ctx ctx, int32_t param, int32_t value) {
     if (!ctx) return fail(BXMG_EINVAL, "ctx_tune: NULL context");
-    if (value < 1 || value > 64) return fail(BXMG_EINVAL, "ctx_tune: value out of range [1, 64]");
+    if (param < 0 || param > 2) return fail(BXMG_EINVAL, "ctx_tune: unknown parameter");
+    if (param <= 1 && (value < 1 || value > 64)) return fail(BXMG_EINVAL, "ctx_tune: value out of range [1, 64]");
+    if (param == 2 && value != 0 && value != 1) return fail(BXMG_EINVAL, "ctx_tune: value must be 0 or 1");
     std::lock_guard<std::mutex> lock(ctx->mu);
     if (param == 0) ctx->zc = value;
     else if (param == 1) ctx->zc_planes = value;
-    else return fail(BXMG_EINVAL, "ctx_tune: unknown parameter");
+    else ctx->res = value;
     return BXMG_OK;
 }
 
@@ -1417,7 +929,7 @@ bxmg_status bxmg_gs_colour(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab rhs, b
         const Level& L0 = *H->L[0];
         fill<double>(R, 0, H->u64[0]->p, L0.face[colour ^ 1]);
         HIPCHK(launch_gs<double>(R.s, L0.grid(), H->u64[0]->p, H->f64[0]->p, beta ? H->beta64.p : nullptr,
-                                 no_faces<double>(), L0.h * L0.h, colour));
+                                 nullptr, colour));
         HIPCHK(launch_rb_to_fab(R.s, L0.grid(), H->u64[0]->p, (double*)phi->data, phi->d_fboxes.p));
         HIPCHK(hipStreamSynchronize(R.s));
     } catch (HipError& e) {
@@ -1443,7 +955,7 @@ bxmg_status bxmg_residual(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab rhs, bx
         fill_faces<double>(R, 0, H->u64[0]->p);
         // r overwrites f in place (each cell reads its own f, then stores r)
         HIPCHK(launch_resid<double, double>(R.s, L0.grid(), H->u64[0]->p, H->f64[0]->p, beta ? H->beta64.p : nullptr,
-                                            no_faces<double>(), 1.0 / (L0.h * L0.h), H->f64[0]->p, H->partials.p));
+                                            nullptr, H->f64[0]->p, H->partials.p));
         HIPCHK(launch_norm_final(R.s, H->partials.p, L0.ntcol, H->fnorm.p));
         HIPCHK(launch_rb_to_fab(R.s, L0.grid(), H->f64[0]->p, (double*)r->data, r->d_fboxes.p));
         norm_readback(R, ctx->h_norm, H->fnorm.p);

@@ -28,9 +28,10 @@ struct RBox {
     int glo[3];        // lo - ng
     int G[3];          // grown extents
     int H;             // half-row pitch = (G.x + 1) / 2
-    int pid;           // problem id (batches); 0 for a single problem
+    int pid;           // problem slot (batches); 0 for a single problem
     long long base;    // element offset of colour 0
     long long cstride; // elements between colour 0 and colour 1
+    double h;          // grid spacing of the box's level
     int nb[6];
     int shift[6];
 };
@@ -92,12 +93,18 @@ struct FaceArrays {
 // every box face is resolvable (RBox::nb), and the kernels that write the
 // level's values also write them into the face ghost cells that mirror
 // them, so no separate face-ghost refresh is needed.
+//
+// active != nullptr (batches): a block whose box belongs to a problem slot p
+// with active[p] == 0 does nothing.
 struct Grid {
     const RBox* boxes;
     const Tile* tiles;
     int ntiles;
     TileShape sh;
     int push;
+    const int* active;
+    int rev;  // walk the tiles in reverse order (see tile_index)
+    int res;  // every box's colour blocks span < 2^31 bytes: 32-bit buffer addressing
 };
 
 // Transfer launch fine <-> coarse: tiles over the coarse cells of every fine
@@ -110,6 +117,8 @@ struct XGrid {
     int ntiles;
     TileShape sh;
     int push;  // as Grid::push, for the fine level
+    const int* active;
+    int rev;
 };
 
 // One level of the fused coarse V-cycle: a single box in RB storage.
@@ -136,10 +145,24 @@ struct CoarseCycle {
     int nlev;
     int nu1, nu2, prolong;
     int per[3];
+    int pid;  // problem slot (checked against the active flags of a batch)
     double rtol;
     int* iters;
     CoarseLevel<T> L[kMaxCoarseLevels];
 };
+
+// Per-problem state of a batch, one entry per slot, in device memory.
+struct BatchSlot {
+    double fnorm;     // max |f| over the valid cells
+    double rel_tol, abs_tol;
+    int max_cycles;   // ENOCONV past this many cycles
+    int fixed_cycles; // > 0: run exactly this many cycles
+    int cycles;       // V-cycles done
+    int status;       // 0 running / OK, else a bxmg_status
+    int nhist;
+    int pad;
+};
+constexpr int kHist = 256;
 
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `s` and return hipSuccess or the launch error.
@@ -147,21 +170,25 @@ hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* 
 hipError_t launch_fill_fab(hipStream_t s, void* data, bool f32, const FBox* boxes, const Tag* tags, int ntags,
                            long long ncells, int comp0, int ncomp);
 
+// Coefficient modes of the stencil kernels: beta != nullptr -> cell beta of
+// the level (same layout as u); fat != nullptr -> face arrays fat[pid] of the
+// box's problem; both null -> constant coefficient.  Grid spacing: RBox::h.
 template <class T>
-hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* beta, FaceArrays<T> fa, T h2,
+hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* beta, const FaceArrays<T>* fat,
                      int colour);
 
 // r = f - L u on both colours, optional store of r (R = T, or float for the
-// mixed-precision cast), per-tile partial norms (max|r|, sum r^2, bad count)
+// mixed-precision cast), partial norms (max|r|, sum r^2, bad count) at
+// 3 * (tile index)
 template <class T, class R>
-hipError_t launch_resid(hipStream_t s, const Grid& g, const T* u, const T* f, const T* beta, FaceArrays<T> fa,
-                        T ih2, R* r, double* partials);
+hipError_t launch_resid(hipStream_t s, const Grid& g, const T* u, const T* f, const T* beta,
+                        const FaceArrays<T>* fat, R* r, double* partials);
 hipError_t launch_norm_final(hipStream_t s, const double* partials, int n, double* out3);
 hipError_t launch_field_norm(hipStream_t s, const Grid& g, const double* x, double* partials);
 
 template <class T>
 hipError_t launch_resid_restrict(hipStream_t s, const XGrid& x, const T* u, const T* f, const T* beta,
-                                 FaceArrays<T> fa, T ih2, T* fc);
+                                 const FaceArrays<T>* fat, T* fc);
 template <class T>
 hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* fc);
 // fine += P coarse: one thread per fine cell over the fine level's colour
@@ -194,8 +221,29 @@ hipError_t launch_bottom(hipStream_t s, T* u, const T* f, FaceArrays<T> fa, bool
                          const int* dom_lo, const int* dom_hi, const int* periodic, double h, double rtol,
                          int* iters_out);
 
-// the fused coarse V-cycle (one workgroup); cc lives in device memory
+// the fused coarse V-cycle, one workgroup per descriptor cc[0..n); with
+// active != nullptr a descriptor whose problem slot is inactive is skipped
 template <class T>
-hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, bool var);
+hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, int n, const int* active, bool var);
+
+// ---------------------------------------------------------------- batches
+constexpr int kStatusNoConv = -4;     // = BXMG_ENOCONV
+constexpr int kStatusNonFinite = -5;  // = BXMG_ENONFINITE
+
+// Per-problem norms: segment q covers partials of tiles [tstart[q],
+// tstart[q+1]) and belongs to slot seg_slot[q]; active slots only.
+hipError_t launch_norm_seg(hipStream_t s, const double* partials, const int* tstart, const int* seg_slot, int nseg,
+                           const int* active, double* norms);
+// Stop test of every active member slot (see BatchSlot): records the
+// history, retires finished problems, counts the rest into *nactive.
+hipError_t launch_batch_check(hipStream_t s, const int* slots, int n, const double* norms, BatchSlot* st,
+                              int* active, double* hist, double* hist_l2, int* nactive);
+// Zero element ranges [start, start + len) of the problems still active.
+struct ZeroRange {
+    long long start, len;
+    int pid, pad;
+};
+template <class T>
+hipError_t launch_zero_ranges(hipStream_t s, T* p, const ZeroRange* r, int n, long long max_len, const int* active);
 
 }  // namespace bxmg

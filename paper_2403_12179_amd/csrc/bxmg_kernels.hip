@@ -54,11 +54,17 @@ __device__ __forceinline__ T harm(T a, T b) {
     return (a * b) * T(2) / (a + b);
 }
 
-// Block -> tile: XCD x (= block % 8) receives tiles [x*n/8, (x+1)*n/8).
-__device__ __forceinline__ int tile_index() {
+// Block -> tile: XCD x (= block % 8) receives tiles [x*n/8, (x+1)*n/8),
+// walked upwards, or downwards when rev != 0.  Consecutive launches over a
+// level alternate the direction, so each starts on the data the previous
+// one touched last, while it is still in the memory-side cache.
+__device__ __forceinline__ int tile_index(int rev) {
     const int nb = gridDim.x, b = blockIdx.x;
-    if ((nb & 7) == 0) return (b & 7) * (nb >> 3) + (b >> 3);
-    return b;
+    if ((nb & 7) == 0) {
+        const int per = nb >> 3, q = b >> 3;
+        return (b & 7) * per + (rev ? per - 1 - q : q);
+    }
+    return rev ? nb - 1 - b : b;
 }
 
 struct TileThread {
@@ -85,50 +91,187 @@ __device__ __forceinline__ int colour_i(const RBox& B, int t, int j, int k, int 
 // a box face are read from the box's ghost cells.
 //   MODE 0: constant coefficient; 1: level 0, faces = harmonic means of the
 //   cell beta (same layout as u); 2: coarse level, global face arrays.
-template <class T, int MODE>
-__device__ __forceinline__ void stencil(const T* __restrict__ u, const T* __restrict__ beta, const FaceArrays<T>& fa,
-                                        const RBox& B, int i, int j, int k, T& su, T& sb, T& uc, long long& idx) {
+// The stencil is split into gather (every load of one cell) and sums (the
+// arithmetic), so kernels can issue the loads of several cells before any
+// arithmetic or store: more memory requests in flight per thread.
+template <class T>
+struct Nbr {
+    T xm, xp, ym, yp, zm, zp;        // u at the 6 face neighbours
+    T c;                             // u at the cell (if gathered)
+    T bxm, bxp, bym, byp, bzm, bzp;  // MODE 1: beta at the neighbours; MODE 2: face coefficients
+    T bc;                            // MODE 1: beta at the cell
+};
+
+// Loads of cell (i,j,k); returns its element index.  CENTRE: also u there.
+template <class T, int MODE, bool CENTRE>
+__device__ __forceinline__ long long gather(const T* __restrict__ u, const T* __restrict__ beta,
+                                            const FaceArrays<T>& fa, const RBox& B, int i, int j, int k, Nbr<T>& n) {
     const int c = (i + j + k) & 1;
     const long long rc = rb_row(B, c, j, k);
     const long long ro = rb_row(B, c ^ 1, j, k);
     const long long Hy = B.H, Hz = (long long)B.H * B.G[1];
     const int m = (i - B.glo[0]) >> 1;
     const int mxm = (i - 1 - B.glo[0]) >> 1, mxp = (i + 1 - B.glo[0]) >> 1;
-    const T uxm = u[ro + mxm], uxp = u[ro + mxp];
-    const T uym = u[ro - Hy + m], uyp = u[ro + Hy + m];
-    const T uzm = u[ro - Hz + m], uzp = u[ro + Hz + m];
-    idx = rc + m;
-    uc = u[idx];
+    const long long idx = rc + m;
+    n.xm = u[ro + mxm];
+    n.xp = u[ro + mxp];
+    n.ym = u[ro - Hy + m];
+    n.yp = u[ro + Hy + m];
+    n.zm = u[ro - Hz + m];
+    n.zp = u[ro + Hz + m];
+    if constexpr (CENTRE) n.c = u[idx];
+    if constexpr (MODE == 1) {
+        n.bc = beta[idx];
+        n.bxm = beta[ro + mxm];
+        n.bxp = beta[ro + mxp];
+        n.bym = beta[ro - Hy + m];
+        n.byp = beta[ro + Hy + m];
+        n.bzm = beta[ro - Hz + m];
+        n.bzp = beta[ro + Hz + m];
+    } else if constexpr (MODE == 2) {
+        const int x = i - fa.dlo[0], y = j - fa.dlo[1], z = k - fa.dlo[2];
+        const int nx = fa.n[0], ny = fa.n[1];
+        const long long ix = (long long)x + (long long)(nx + 1) * ((long long)y + (long long)ny * z);
+        const long long iy = (long long)x + (long long)nx * ((long long)y + (long long)(ny + 1) * z);
+        const long long iz = (long long)x + (long long)nx * ((long long)y + (long long)ny * z);
+        n.bxm = fa.c[0][ix];
+        n.bxp = fa.c[0][ix + 1];
+        n.bym = fa.c[1][iy];
+        n.byp = fa.c[1][iy + nx];
+        n.bzm = fa.c[2][iz];
+        n.bzp = fa.c[2][iz + (long long)nx * ny];
+    }
+    return idx;
+}
+
+// su = sum_faces beta*u_nb, sb = sum_faces beta, each in the fixed order
+// ((x- + x+) + (y- + y+)) + (z- + z+).
+//   MODE 0: constant coefficient; 1: level 0, faces = harmonic means of the
+//   cell beta (same layout as u); 2: coarse level, global face arrays.
+template <class T, int MODE>
+__device__ __forceinline__ void sums(const Nbr<T>& n, T& su, T& sb) {
     if constexpr (MODE == 0) {
-        su = ((uxm + uxp) + (uym + uyp)) + (uzm + uzp);
+        su = ((n.xm + n.xp) + (n.ym + n.yp)) + (n.zm + n.zp);
         sb = T(6);
     } else {
         T bxm, bxp, bym, byp, bzm, bzp;
         if constexpr (MODE == 1) {
-            const T bc = beta[idx];
-            bxm = harm(beta[ro + mxm], bc);
-            bxp = harm(bc, beta[ro + mxp]);
-            bym = harm(beta[ro - Hy + m], bc);
-            byp = harm(bc, beta[ro + Hy + m]);
-            bzm = harm(beta[ro - Hz + m], bc);
-            bzp = harm(bc, beta[ro + Hz + m]);
+            bxm = harm(n.bxm, n.bc);
+            bxp = harm(n.bc, n.bxp);
+            bym = harm(n.bym, n.bc);
+            byp = harm(n.bc, n.byp);
+            bzm = harm(n.bzm, n.bc);
+            bzp = harm(n.bc, n.bzp);
         } else {
-            const int x = i - fa.dlo[0], y = j - fa.dlo[1], z = k - fa.dlo[2];
-            const int nx = fa.n[0], ny = fa.n[1];
-            const long long ix = (long long)x + (long long)(nx + 1) * ((long long)y + (long long)ny * z);
-            const long long iy = (long long)x + (long long)nx * ((long long)y + (long long)(ny + 1) * z);
-            const long long iz = (long long)x + (long long)nx * ((long long)y + (long long)ny * z);
-            bxm = fa.c[0][ix];
-            bxp = fa.c[0][ix + 1];
-            bym = fa.c[1][iy];
-            byp = fa.c[1][iy + nx];
-            bzm = fa.c[2][iz];
-            bzp = fa.c[2][iz + (long long)nx * ny];
+            bxm = n.bxm;
+            bxp = n.bxp;
+            bym = n.bym;
+            byp = n.byp;
+            bzm = n.bzm;
+            bzp = n.bzp;
         }
         sb = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
-        su = ((bxm * uxm + bxp * uxp) + (bym * uym + byp * uyp)) + (bzm * uzm + bzp * uzp);
+        su = ((bxm * n.xm + bxp * n.xp) + (bym * n.ym + byp * n.yp)) + (bzm * n.zm + bzp * n.zp);
     }
 }
+
+// Stencil sums of one cell: neighbours across a box face are read from the
+// box's ghost cells.
+template <class T, int MODE>
+__device__ __forceinline__ void stencil(const T* __restrict__ u, const T* __restrict__ beta, const FaceArrays<T>& fa,
+                                        const RBox& B, int i, int j, int k, T& su, T& sb, T& uc, long long& idx) {
+    Nbr<T> n;
+    idx = gather<T, MODE, true>(u, beta, fa, B, i, j, k, n);
+    uc = n.c;
+    sums<T, MODE>(n, su, sb);
+}
+
+// Raw-buffer access to the colour blocks of one box: a resource descriptor
+// (box start, size) in scalar registers and 32-bit offsets per lane, instead
+// of 64-bit addresses.  The hardware bounds-checks every access against the
+// box: a read past its end returns 0 and a write there is dropped.
+constexpr int kBufferDword3 = 0x00020000;  // raw buffer, gfx9 data format
+
+template <class T>
+struct BoxRes;
+
+template <>
+struct BoxRes<double> {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ BoxRes(const double* base, long long nelem)
+        : r(__builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(nelem * 8), kBufferDword3)) {}
+    __device__ __forceinline__ double ld(int e) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, e * 8, 0, 0));
+    }
+    __device__ __forceinline__ void st(int e, double v) const {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, e * 8, 0, 0);
+    }
+};
+
+template <>
+struct BoxRes<float> {
+    __amdgpu_buffer_rsrc_t r;
+    __device__ __forceinline__ BoxRes(const float* base, long long nelem)
+        : r(__builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(nelem * 4), kBufferDword3)) {}
+    __device__ __forceinline__ float ld(int e) const {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, e * 4, 0, 0));
+    }
+    __device__ __forceinline__ void st(int e, float v) const {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, e * 4, 0, 0);
+    }
+};
+
+// gather() through box resources; offsets relative to the box start
+template <class T, int MODE, bool CENTRE>
+__device__ __forceinline__ int gather_res(const BoxRes<T>& U, const BoxRes<T>& Bt, const FaceArrays<T>& fa,
+                                          const RBox& B, int i, int j, int k, Nbr<T>& n) {
+    const int c = (i + j + k) & 1;
+    const int row = ((k - B.glo[2]) * B.G[1] + (j - B.glo[1])) * B.H;
+    const int cs = (int)B.cstride;
+    const int rc = c * cs + row, ro = (c ^ 1) * cs + row;
+    const int Hy = B.H, Hz = B.H * B.G[1];
+    const int m = (i - B.glo[0]) >> 1;
+    const int mxm = (i - 1 - B.glo[0]) >> 1, mxp = (i + 1 - B.glo[0]) >> 1;
+    const int idx = rc + m;
+    n.xm = U.ld(ro + mxm);
+    n.xp = U.ld(ro + mxp);
+    n.ym = U.ld(ro - Hy + m);
+    n.yp = U.ld(ro + Hy + m);
+    n.zm = U.ld(ro - Hz + m);
+    n.zp = U.ld(ro + Hz + m);
+    if constexpr (CENTRE) n.c = U.ld(idx);
+    if constexpr (MODE == 1) {
+        n.bc = Bt.ld(idx);
+        n.bxm = Bt.ld(ro + mxm);
+        n.bxp = Bt.ld(ro + mxp);
+        n.bym = Bt.ld(ro - Hy + m);
+        n.byp = Bt.ld(ro + Hy + m);
+        n.bzm = Bt.ld(ro - Hz + m);
+        n.bzp = Bt.ld(ro + Hz + m);
+    } else if constexpr (MODE == 2) {
+        const int x = i - fa.dlo[0], y = j - fa.dlo[1], z = k - fa.dlo[2];
+        const int nx = fa.n[0], ny = fa.n[1];
+        const long long ix = (long long)x + (long long)(nx + 1) * ((long long)y + (long long)ny * z);
+        const long long iy = (long long)x + (long long)nx * ((long long)y + (long long)(ny + 1) * z);
+        const long long iz = (long long)x + (long long)nx * ((long long)y + (long long)ny * z);
+        n.bxm = fa.c[0][ix];
+        n.bxp = fa.c[0][ix + 1];
+        n.bym = fa.c[1][iy];
+        n.byp = fa.c[1][iy + nx];
+        n.bzm = fa.c[2][iz];
+        n.bzp = fa.c[2][iz + (long long)nx * ny];
+    }
+    return idx;
+}
+
+// Cells whose loads a thread issues together: the z planes it walks, in
+// groups of kZB (constant coefficient) or kZBVar (coefficient loads too).
+#ifndef BXMG_ZB
+#define BXMG_ZB 2
+#endif
+constexpr int kZB = BXMG_ZB;
+constexpr int kZBVar = 1;
 
 // Ghost exchange fused into a producer: cell (i,j,k) of box B just took value
 // v; write v into every face ghost cell that mirrors it -- the ghost of the
@@ -219,62 +362,125 @@ __global__ void __launch_bounds__(kBlock) k_fill_fab(T* __restrict__ data, const
 
 // ---------------------------------------------------- red-black smoothing
 // One colour: u_c = (su - h^2 f) / sb.  Reads only the other colour of u.
-template <class T, int MODE, bool PUSH>
+template <class T, int MODE, bool PUSH, bool RES>
 __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const T* __restrict__ f,
-                                              const T* __restrict__ beta, FaceArrays<T> fa, T h2, int colour) {
-    const Tile tl = g.tiles[tile_index()];
+                                              const T* __restrict__ beta, const FaceArrays<T>* __restrict__ fat,
+                                              int colour) {
+    const Tile tl = g.tiles[tile_index(g.rev)];
     const RBox B = g.boxes[tl.box];
+    if (g.active && !g.active[B.pid]) return;
+    FaceArrays<T> fa;
+    if constexpr (MODE == 2) fa = fat[B.pid];
+    const T h2 = (T)(B.h * B.h);
     const TileThread th = tile_thread(tl, g.sh);
     const int j = B.lo[1] + th.y;
     if (j > B.hi[1]) return;
-    for (int z = 0; z < g.sh.zc; ++z) {
-        const int k = B.lo[2] + th.z0 + z * th.dz;
-        if (k > B.hi[2]) break;
-        const int i = colour_i(B, th.x, j, k, colour);
-        if (i > B.hi[0]) continue;
-        T su, sb, uc;
-        long long idx;
-        stencil<T, MODE>(u, beta, fa, B, i, j, k, su, sb, uc, idx);
-        const T v = (su - h2 * f[idx]) / sb;
-        u[idx] = v;
-        if constexpr (PUSH) push_ghosts(u, g.boxes, B, i, j, k, v);
+    const long long ne = 2 * B.cstride;
+    const BoxRes<T> U(u + B.base, ne), F(f + B.base, ne), Bt((MODE == 1 ? beta : f) + B.base, ne);
+    constexpr int ZB = (MODE == 0) ? kZB : kZBVar;
+    for (int z0 = 0; z0 < g.sh.zc; z0 += ZB) {
+        Nbr<T> nb[ZB];
+        T fv[ZB];
+        long long idx[ZB];
+        int ii[ZB], kk[ZB];
+        bool ok[ZB];
+#pragma unroll
+        for (int q = 0; q < ZB; ++q) {
+            const int k = B.lo[2] + th.z0 + (z0 + q) * th.dz;
+            const int i = colour_i(B, th.x, j, k, colour);
+            ii[q] = i;
+            kk[q] = k;
+            ok[q] = (z0 + q < g.sh.zc) && k <= B.hi[2] && i <= B.hi[0];
+            if (ok[q]) {
+                if constexpr (RES) {
+                    idx[q] = gather_res<T, MODE, false>(U, Bt, fa, B, i, j, k, nb[q]);
+                    fv[q] = F.ld((int)idx[q]);
+                } else {
+                    idx[q] = gather<T, MODE, false>(u, beta, fa, B, i, j, k, nb[q]);
+                    fv[q] = f[idx[q]];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < ZB; ++q) {
+            if (!ok[q]) continue;
+            T su, sb;
+            sums<T, MODE>(nb[q], su, sb);
+            const T v = (su - h2 * fv[q]) / sb;
+            if constexpr (RES) U.st((int)idx[q], v);
+            else u[idx[q]] = v;
+            if constexpr (PUSH) push_ghosts(u, g.boxes, B, ii[q], j, kk[q], v);
+        }
     }
 }
 
 // ---------------------------------------------------------------- residual
 // r = f - (su - sb u) / h^2 on both colours; optional store of r (same type
 // and layout) or of float(r) (mixed precision); fused norms per block.
-template <class T, int MODE, class R>
+template <class T, int MODE, class R, bool RES>
 __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ u, const T* __restrict__ f,
-                                                 const T* __restrict__ beta, FaceArrays<T> fa, T ih2,
+                                                 const T* __restrict__ beta, const FaceArrays<T>* __restrict__ fat,
                                                  R* __restrict__ r, double* __restrict__ partials) {
     __shared__ double sh[3 * (kBlock / 64)];
     double mx = 0.0, s2 = 0.0, bad = 0.0;
-    const Tile tl = g.tiles[tile_index()];
+    const int tix = tile_index(g.rev);
+    const Tile tl = g.tiles[tix];
     const RBox B = g.boxes[tl.box];
+    if (g.active && !g.active[B.pid]) return;
+    FaceArrays<T> fa;
+    if constexpr (MODE == 2) fa = fat[B.pid];
+    const T ih2 = (T)(1.0 / (B.h * B.h));
     const TileThread th = tile_thread(tl, g.sh);
     const int j = B.lo[1] + th.y;
+    const long long ne = 2 * B.cstride;
+    const BoxRes<T> U(u + B.base, ne), F(f + B.base, ne), Bt((MODE == 1 ? beta : f) + B.base, ne);
+    const BoxRes<R> Rr(r ? r + B.base : (R*)nullptr, r ? ne : 0);
     if (j <= B.hi[1]) {
-        for (int z = 0; z < g.sh.zc; ++z) {
-            const int k = B.lo[2] + th.z0 + z * th.dz;
-            if (k > B.hi[2]) break;
-            for (int c = 0; c < 2; ++c) {
-                const int i = colour_i(B, th.x, j, k, c);
-                if (i > B.hi[0]) continue;
-                T su, sb, uc;
-                long long idx;
-                stencil<T, MODE>(u, beta, fa, B, i, j, k, su, sb, uc, idx);
-                const T rv = f[idx] - (su - sb * uc) * ih2;
-                if (r) r[idx] = (R)rv;
-                acc_norm((double)rv, mx, s2, bad);
+        constexpr int ZB = (MODE == 0) ? kZB : kZBVar;
+        for (int z0 = 0; z0 < g.sh.zc; z0 += ZB) {
+            Nbr<T> nb[ZB][2];
+            T fv[ZB][2];
+            long long idx[ZB][2];
+            bool ok[ZB][2];
+#pragma unroll
+            for (int q = 0; q < ZB; ++q) {
+                const int k = B.lo[2] + th.z0 + (z0 + q) * th.dz;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int i = colour_i(B, th.x, j, k, c);
+                    ok[q][c] = (z0 + q < g.sh.zc) && k <= B.hi[2] && i <= B.hi[0];
+                    if (ok[q][c]) {
+                        if constexpr (RES) {
+                            idx[q][c] = gather_res<T, MODE, true>(U, Bt, fa, B, i, j, k, nb[q][c]);
+                            fv[q][c] = F.ld((int)idx[q][c]);
+                        } else {
+                            idx[q][c] = gather<T, MODE, true>(u, beta, fa, B, i, j, k, nb[q][c]);
+                            fv[q][c] = f[idx[q][c]];
+                        }
+                    }
+                }
             }
+#pragma unroll
+            for (int q = 0; q < ZB; ++q)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    if (!ok[q][c]) continue;
+                    T su, sb;
+                    sums<T, MODE>(nb[q][c], su, sb);
+                    const T rv = fv[q][c] - (su - sb * nb[q][c].c) * ih2;
+                    if (r) {
+                        if constexpr (RES) Rr.st((int)idx[q][c], (R)rv);
+                        else r[idx[q][c]] = (R)rv;
+                    }
+                    acc_norm((double)rv, mx, s2, bad);
+                }
         }
     }
     block_reduce3(mx, s2, bad, sh);
     if (threadIdx.x == 0) {
-        partials[3 * blockIdx.x] = mx;
-        partials[3 * blockIdx.x + 1] = s2;
-        partials[3 * blockIdx.x + 2] = bad;
+        partials[3 * tix] = mx;
+        partials[3 * tix + 1] = s2;
+        partials[3 * tix + 2] = bad;
     }
 }
 
@@ -296,7 +502,7 @@ __global__ void __launch_bounds__(kBlock) k_field_norm(Grid g, const double* __r
                                                       double* __restrict__ partials) {
     __shared__ double sh[3 * (kBlock / 64)];
     double mx = 0.0, s2 = 0.0, bad = 0.0;
-    const Tile tl = g.tiles[tile_index()];
+    const Tile tl = g.tiles[tile_index(g.rev)];
     const RBox B = g.boxes[tl.box];
     const TileThread th = tile_thread(tl, g.sh);
     const int j = B.lo[1] + th.y;
@@ -337,10 +543,14 @@ __device__ __forceinline__ T resid_at(const T* __restrict__ u, const T* __restri
 
 template <class T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_resid_restrict(XGrid x, const T* __restrict__ u, const T* __restrict__ f,
-                                                          const T* __restrict__ beta, FaceArrays<T> fa, T ih2,
-                                                          T* __restrict__ fc) {
-    const Tile tl = x.tiles[tile_index()];
+                                                          const T* __restrict__ beta,
+                                                          const FaceArrays<T>* __restrict__ fat, T* __restrict__ fc) {
+    const Tile tl = x.tiles[tile_index(x.rev)];
     const RBox B = x.fboxes[tl.box];
+    if (x.active && !x.active[B.pid]) return;
+    FaceArrays<T> fa;
+    if constexpr (MODE == 2) fa = fat[B.pid];
+    const T ih2 = (T)(1.0 / (B.h * B.h));
     const RBox C = x.cboxes[x.cbox[tl.box]];
     const TileThread th = tile_thread(tl, x.sh);
     const int I = (B.lo[0] >> 1) + th.x, J = (B.lo[1] >> 1) + th.y;
@@ -364,7 +574,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(XGrid x, const T* __r
 
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_restrict_plain(XGrid x, const T* __restrict__ rf, T* __restrict__ fc) {
-    const Tile tl = x.tiles[tile_index()];
+    const Tile tl = x.tiles[tile_index(x.rev)];
     const RBox B = x.fboxes[tl.box];
     const RBox C = x.cboxes[x.cbox[tl.box]];
     const TileThread th = tile_thread(tl, x.sh);
@@ -392,8 +602,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict_plain(XGrid x, const T* __r
 template <class T, bool PUSH>
 __global__ void __launch_bounds__(kBlock) k_prolong(Grid g, const RBox* __restrict__ cboxes, const int* __restrict__ cbox,
                                                    const T* __restrict__ ec, T* __restrict__ uf, int order) {
-    const Tile tl = g.tiles[tile_index()];
+    const Tile tl = g.tiles[tile_index(g.rev)];
     const RBox B = g.boxes[tl.box];
+    if (g.active && !g.active[B.pid]) return;
     const RBox C = cboxes[cbox[tl.box]];
     const TileThread th = tile_thread(tl, g.sh);
     const int j = B.lo[1] + th.y;
@@ -443,8 +654,9 @@ __global__ void __launch_bounds__(kBlock) k_cast_f32(const double* __restrict__ 
 // Per-cell maps over both colours of the valid cells, tiled like the
 // smoother; OP(B, i, j, k) does the work.
 #define BXMG_FOR_VALID_CELLS(g, OP)                                          \
-    const Tile tl = (g).tiles[tile_index()];                                 \
+    const Tile tl = (g).tiles[tile_index((g).rev)];                                 \
     const RBox B = (g).boxes[tl.box];                                        \
+    if ((g).active && !(g).active[B.pid]) return;                            \
     const TileThread th = tile_thread(tl, (g).sh);                           \
     const int j = B.lo[1] + th.y;                                            \
     if (j > B.hi[1]) return;                                                 \
@@ -480,7 +692,7 @@ __global__ void __launch_bounds__(kBlock) k_sum_valid(Grid g, const double* __re
                                                      double* __restrict__ partials) {
     __shared__ double sh[3 * (kBlock / 64)];
     double mx = 0.0, s = 0.0, cnt = 0.0;
-    const Tile tl = g.tiles[tile_index()];
+    const Tile tl = g.tiles[tile_index(g.rev)];
     const RBox B = g.boxes[tl.box];
     const TileThread th = tile_thread(tl, g.sh);
     const int j = B.lo[1] + th.y;
@@ -519,7 +731,7 @@ __global__ void __launch_bounds__(kBlock) k_sub_mean(Grid g, double* __restrict_
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_faces_from_cells(XGrid x, const T* __restrict__ beta, int d, int fdom_hi,
                                                             FaceArrays<T> out, T* __restrict__ dst) {
-    const Tile tl = x.tiles[tile_index()];
+    const Tile tl = x.tiles[tile_index(x.rev)];
     const RBox B = x.fboxes[tl.box];
     const TileThread th = tile_thread(tl, x.sh);
     int chi[3] = {B.hi[0] >> 1, B.hi[1] >> 1, B.hi[2] >> 1};
@@ -876,9 +1088,11 @@ __device__ void blk_prolong(const CoarseLevel<T>& C, const CoarseLevel<T>& F, in
 }
 
 template <class T, int MODE>
-__global__ void __launch_bounds__(kBotThreads) k_coarse_cycle(const CoarseCycle<T>* __restrict__ ccp) {
+__global__ void __launch_bounds__(kBotThreads) k_coarse_cycle(const CoarseCycle<T>* __restrict__ ccs,
+                                                             const int* __restrict__ active) {
     __shared__ BottomLds S;
-    const CoarseCycle<T>& cc = *ccp;
+    const CoarseCycle<T>& cc = ccs[blockIdx.x];
+    if (active && !active[cc.pid]) return;
     const int nl = cc.nlev;
     for (int l = 0; l + 1 < nl; ++l) {
         const CoarseLevel<T>& F = cc.L[l];
@@ -930,40 +1144,47 @@ hipError_t launch_fill_fab(hipStream_t s, void* data, bool f32, const FBox* boxe
 }
 
 template <class T>
-hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* beta, FaceArrays<T> fa, T h2,
+hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* beta, const FaceArrays<T>* fat,
                      int colour) {
     if (g.ntiles <= 0) return hipSuccess;
     const dim3 G(g.ntiles), B(kBlock);
-#define BXMG_GS(MODE, PUSH) hipLaunchKernelGGL((k_gs<T, MODE, PUSH>), G, B, 0, s, g, u, f, beta, fa, h2, colour)
+#define BXMG_GS(MODE, PUSH, RES) hipLaunchKernelGGL((k_gs<T, MODE, PUSH, RES>), G, B, 0, s, g, u, f, beta, fat, colour)
+#define BXMG_GS_MODES(PUSH, RES) \
+    if (beta) BXMG_GS(1, PUSH, RES); else if (fat) BXMG_GS(2, PUSH, RES); else BXMG_GS(0, PUSH, RES)
     if (g.push) {
-        if (beta) BXMG_GS(1, true); else if (fa.c[0]) BXMG_GS(2, true); else BXMG_GS(0, true);
+        if (g.res) { BXMG_GS_MODES(true, true); } else { BXMG_GS_MODES(true, false); }
     } else {
-        if (beta) BXMG_GS(1, false); else if (fa.c[0]) BXMG_GS(2, false); else BXMG_GS(0, false);
+        if (g.res) { BXMG_GS_MODES(false, true); } else { BXMG_GS_MODES(false, false); }
     }
+#undef BXMG_GS_MODES
 #undef BXMG_GS
     return hipGetLastError();
 }
 template hipError_t launch_gs<double>(hipStream_t, const Grid&, double*, const double*, const double*,
-                                      FaceArrays<double>, double, int);
-template hipError_t launch_gs<float>(hipStream_t, const Grid&, float*, const float*, const float*, FaceArrays<float>,
-                                     float, int);
+                                      const FaceArrays<double>*, int);
+template hipError_t launch_gs<float>(hipStream_t, const Grid&, float*, const float*, const float*,
+                                     const FaceArrays<float>*, int);
 
 template <class T, class R>
-hipError_t launch_resid(hipStream_t s, const Grid& g, const T* u, const T* f, const T* beta, FaceArrays<T> fa,
-                        T ih2, R* r, double* partials) {
+hipError_t launch_resid(hipStream_t s, const Grid& g, const T* u, const T* f, const T* beta,
+                        const FaceArrays<T>* fat, R* r, double* partials) {
     if (g.ntiles <= 0) return hipSuccess;
     const dim3 G(g.ntiles), B(kBlock);
-    if (beta) hipLaunchKernelGGL((k_resid<T, 1, R>), G, B, 0, s, g, u, f, beta, fa, ih2, r, partials);
-    else if (fa.c[0]) hipLaunchKernelGGL((k_resid<T, 2, R>), G, B, 0, s, g, u, f, beta, fa, ih2, r, partials);
-    else hipLaunchKernelGGL((k_resid<T, 0, R>), G, B, 0, s, g, u, f, beta, fa, ih2, r, partials);
+#define BXMG_RS(MODE, RES) hipLaunchKernelGGL((k_resid<T, MODE, R, RES>), G, B, 0, s, g, u, f, beta, fat, r, partials)
+    if (g.res) {
+        if (beta) BXMG_RS(1, true); else if (fat) BXMG_RS(2, true); else BXMG_RS(0, true);
+    } else {
+        if (beta) BXMG_RS(1, false); else if (fat) BXMG_RS(2, false); else BXMG_RS(0, false);
+    }
+#undef BXMG_RS
     return hipGetLastError();
 }
 template hipError_t launch_resid<double, double>(hipStream_t, const Grid&, const double*, const double*, const double*,
-                                                 FaceArrays<double>, double, double*, double*);
+                                                 const FaceArrays<double>*, double*, double*);
 template hipError_t launch_resid<double, float>(hipStream_t, const Grid&, const double*, const double*, const double*,
-                                                FaceArrays<double>, double, float*, double*);
+                                                const FaceArrays<double>*, float*, double*);
 template hipError_t launch_resid<float, float>(hipStream_t, const Grid&, const float*, const float*, const float*,
-                                               FaceArrays<float>, float, float*, double*);
+                                               const FaceArrays<float>*, float*, double*);
 
 hipError_t launch_norm_final(hipStream_t s, const double* partials, int n, double* out3) {
     hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, s, partials, n, out3);
@@ -978,18 +1199,18 @@ hipError_t launch_field_norm(hipStream_t s, const Grid& g, const double* x, doub
 
 template <class T>
 hipError_t launch_resid_restrict(hipStream_t s, const XGrid& x, const T* u, const T* f, const T* beta,
-                                 FaceArrays<T> fa, T ih2, T* fc) {
+                                 const FaceArrays<T>* fat, T* fc) {
     if (x.ntiles <= 0) return hipSuccess;
     const dim3 G(x.ntiles), B(kBlock);
-    if (beta) hipLaunchKernelGGL((k_resid_restrict<T, 1>), G, B, 0, s, x, u, f, beta, fa, ih2, fc);
-    else if (fa.c[0]) hipLaunchKernelGGL((k_resid_restrict<T, 2>), G, B, 0, s, x, u, f, beta, fa, ih2, fc);
-    else hipLaunchKernelGGL((k_resid_restrict<T, 0>), G, B, 0, s, x, u, f, beta, fa, ih2, fc);
+    if (beta) hipLaunchKernelGGL((k_resid_restrict<T, 1>), G, B, 0, s, x, u, f, beta, fat, fc);
+    else if (fat) hipLaunchKernelGGL((k_resid_restrict<T, 2>), G, B, 0, s, x, u, f, beta, fat, fc);
+    else hipLaunchKernelGGL((k_resid_restrict<T, 0>), G, B, 0, s, x, u, f, beta, fat, fc);
     return hipGetLastError();
 }
 template hipError_t launch_resid_restrict<double>(hipStream_t, const XGrid&, const double*, const double*,
-                                                  const double*, FaceArrays<double>, double, double*);
+                                                  const double*, const FaceArrays<double>*, double*);
 template hipError_t launch_resid_restrict<float>(hipStream_t, const XGrid&, const float*, const float*, const float*,
-                                                 FaceArrays<float>, float, float*);
+                                                 const FaceArrays<float>*, float*);
 
 template <class T>
 hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* fc) {
@@ -1098,12 +1319,106 @@ template hipError_t launch_bottom<float>(hipStream_t, float*, const float*, Face
                                          const int*, const int*, const int*, double, double, int*);
 
 template <class T>
-hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, bool var) {
-    if (var) hipLaunchKernelGGL((k_coarse_cycle<T, 2>), dim3(1), dim3(kBotThreads), 0, s, cc);
-    else hipLaunchKernelGGL((k_coarse_cycle<T, 0>), dim3(1), dim3(kBotThreads), 0, s, cc);
+hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, int n, const int* active, bool var) {
+    if (n <= 0) return hipSuccess;
+    if (var) hipLaunchKernelGGL((k_coarse_cycle<T, 2>), dim3(n), dim3(kBotThreads), 0, s, cc, active);
+    else hipLaunchKernelGGL((k_coarse_cycle<T, 0>), dim3(n), dim3(kBotThreads), 0, s, cc, active);
     return hipGetLastError();
 }
-template hipError_t launch_coarse_cycle<double>(hipStream_t, const CoarseCycle<double>*, bool);
-template hipError_t launch_coarse_cycle<float>(hipStream_t, const CoarseCycle<float>*, bool);
+template hipError_t launch_coarse_cycle<double>(hipStream_t, const CoarseCycle<double>*, int, const int*, bool);
+template hipError_t launch_coarse_cycle<float>(hipStream_t, const CoarseCycle<float>*, int, const int*, bool);
+
+// ------------------------------------------------------------ batch kernels
+// One block per segment: the fixed-tree reduction of k_norm_final over the
+// segment's tiles, in tile order.
+__global__ void __launch_bounds__(kBlock) k_norm_seg(const double* __restrict__ partials, const int* __restrict__ tstart,
+                                                    const int* __restrict__ seg_slot, const int* __restrict__ active,
+                                                    double* __restrict__ norms) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    const int q = blockIdx.x, p = seg_slot[q];
+    if (!active[p]) return;
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    for (int t = tstart[q] + (int)threadIdx.x; t < tstart[q + 1]; t += blockDim.x) {
+        mx = fmax(mx, partials[3 * t]);
+        s2 = s2 + partials[3 * t + 1];
+        bad = bad + partials[3 * t + 2];
+    }
+    block_reduce3(mx, s2, bad, sh);
+    if (threadIdx.x == 0) { norms[3 * p] = mx; norms[3 * p + 1] = s2; norms[3 * p + 2] = bad; }
+}
+
+// One thread per member slot, one block: the same stop test as the
+// single-problem driver (history entry, then stop or count one more cycle).
+__global__ void __launch_bounds__(1024) k_batch_check(const int* __restrict__ slots, int n,
+                                                     const double* __restrict__ norms, BatchSlot* __restrict__ st,
+                                                     int* __restrict__ active, double* __restrict__ hist,
+                                                     double* __restrict__ hist_l2, int* __restrict__ nactive) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int p = slots[q];
+        if (!active[p]) continue;
+        BatchSlot S = st[p];
+        const double rinf = norms[3 * p + 2] > 0.0 ? (double)NAN : norms[3 * p];
+        const int c = S.cycles;
+        if (c < kHist) {
+            hist[(long long)p * kHist + c] = rinf / S.fnorm;
+            hist_l2[(long long)p * kHist + c] = sqrt(norms[3 * p + 1]);
+            S.nhist = c + 1;
+        }
+        bool done = false;
+        if (!(fabs(rinf) <= 1.7976931348623157e308)) {
+            S.status = kStatusNonFinite;
+            done = true;
+        } else if (S.fixed_cycles > 0) {
+            done = (c == S.fixed_cycles);
+        } else if (rinf <= S.rel_tol * S.fnorm || rinf <= S.abs_tol) {
+            done = true;
+        } else if (c == S.max_cycles) {
+            S.status = kStatusNoConv;
+            done = true;
+        }
+        if (done) active[p] = 0;
+        else { S.cycles = c + 1; ++mine; }
+        st[p] = S;
+    }
+    if (mine) atomicAdd(&cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) *nactive = cnt;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_zero_ranges(T* __restrict__ p, const ZeroRange* __restrict__ r,
+                                                       const int* __restrict__ active) {
+    const ZeroRange R = r[blockIdx.y];
+    if (active && !active[R.pid]) return;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < R.len; q += stride) p[R.start + q] = T(0);
+}
+
+hipError_t launch_norm_seg(hipStream_t s, const double* partials, const int* tstart, const int* seg_slot, int nseg,
+                           const int* active, double* norms) {
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_norm_seg, dim3(nseg), dim3(kBlock), 0, s, partials, tstart, seg_slot, active, norms);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_check(hipStream_t s, const int* slots, int n, const double* norms, BatchSlot* st,
+                              int* active, double* hist, double* hist_l2, int* nactive) {
+    hipLaunchKernelGGL(k_batch_check, dim3(1), dim3(1024), 0, s, slots, n, norms, st, active, hist, hist_l2, nactive);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_zero_ranges(hipStream_t s, T* p, const ZeroRange* r, int n, long long max_len, const int* active) {
+    if (n <= 0 || max_len <= 0) return hipSuccess;
+    const long long nb = std::min<long long>(nblk(max_len), 1024);
+    hipLaunchKernelGGL(k_zero_ranges<T>, dim3((unsigned)nb, (unsigned)n), dim3(kBlock), 0, s, p, r, active);
+    return hipGetLastError();
+}
+template hipError_t launch_zero_ranges<double>(hipStream_t, double*, const ZeroRange*, int, long long, const int*);
+template hipError_t launch_zero_ranges<float>(hipStream_t, float*, const ZeroRange*, int, long long, const int*);
 
 }  // namespace bxmg

@@ -35,6 +35,11 @@ def solve_params(**kw):
     return p
 
 
+def _result(info):
+    return SolveResult(info.status, info.cycles, info.levels, info.rel_resid_inf, info.resid_l2, info.f_inf,
+                       info.seconds, list(info.hist[:info.nhist]), list(info.hist_l2[:info.nhist]))
+
+
 def mlmg_solve(phi: MultiFab, rhs: MultiFab, beta: MultiFab | None = None, raise_on_error=True, **params):
     """Solve div(beta grad phi) = rhs (beta=None: Poisson) in place on phi.
 
@@ -45,8 +50,7 @@ def mlmg_solve(phi: MultiFab, rhs: MultiFab, beta: MultiFab | None = None, raise
     info = L.SolveInfo()
     st = L.lib().bxmg_mlmg_solve(phi.ctx._h, C.byref(p), phi._h, rhs._h, beta._h if beta is not None else None,
                                  C.byref(info))
-    res = SolveResult(info.status, info.cycles, info.levels, info.rel_resid_inf, info.resid_l2, info.f_inf,
-                      info.seconds, list(info.hist[:info.nhist]), list(info.hist_l2[:info.nhist]))
+    res = _result(info)
     if raise_on_error and st not in (0, -4, -5):
         L.check(st)
     return res
@@ -76,3 +80,89 @@ def bottom_solve(phi, rhs, h, rtol=1e-12):
     it = C.c_int32()
     L.check(L.lib().bxmg_bottom_solve(phi.ctx._h, phi._h, rhs._h, None, float(h), float(rtol), C.byref(it)))
     return it.value
+
+
+class Batch:
+    """Many independent solves in flight together (bxmg_batch_*).
+
+    Batch(ctx, budget_bytes, max_problems, var=False, **params); add() admits a
+    problem (None when it does not fit now), step() runs cycles and returns
+    the number still running, poll() returns finished (id, SolveResult)."""
+
+    def __init__(self, ctx, budget_bytes, max_problems, var=False, graph=True, **params):
+        self.ctx = ctx
+        p = solve_params(**params)
+        h = C.c_void_p()
+        L.check(L.lib().bxmg_batch_create(ctx._h, int(budget_bytes), int(max_problems), 1 if var else 0,
+                                          C.byref(p), C.byref(h)))
+        self._h = h
+        if not graph:
+            self.set_graph(False)
+
+    def close(self):
+        if self._h:
+            L.lib().bxmg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_graph(self, on):
+        L.check(L.lib().bxmg_batch_set(self._h, 0, 1 if on else 0))
+
+    def footprint(self, ba):
+        return int(L.lib().bxmg_batch_footprint(self._h, ba._h))
+
+    def add(self, phi, rhs, beta=None, rel_tol=0.0):
+        """Problem id, or None if it does not fit now (EBUSY)."""
+        pid = C.c_int64()
+        st = L.lib().bxmg_batch_add(self._h, phi._h, rhs._h, beta._h if beta is not None else None, float(rel_tol),
+                                    C.byref(pid))
+        if st == -6:
+            return None
+        L.check(st)
+        return pid.value
+
+    def step(self, ncycles=1):
+        n = C.c_int32()
+        L.check(L.lib().bxmg_batch_step(self._h, int(ncycles), C.byref(n)))
+        return n.value
+
+    def launch(self, ncycles=1):
+        """Enqueue ncycles cycles without waiting (pair with collect())."""
+        L.check(L.lib().bxmg_batch_launch(self._h, int(ncycles)))
+
+    def collect(self):
+        """Wait for the launched cycles; returns the number still running."""
+        n = C.c_int32()
+        L.check(L.lib().bxmg_batch_collect(self._h, C.byref(n)))
+        return n.value
+
+    def poll(self, max_results=64):
+        ids = (C.c_int64 * max_results)()
+        infos = (L.SolveInfo * max_results)()
+        n = C.c_int32()
+        L.check(L.lib().bxmg_batch_poll(self._h, int(max_results), ids, infos, C.byref(n)))
+        return [(ids[i], _result(infos[i])) for i in range(n.value)]
+
+    def remove(self, pid):
+        L.check(L.lib().bxmg_batch_remove(self._h, int(pid)))
+
+    def stats(self):
+        used, budget = C.c_size_t(), C.c_size_t()
+        run, q = C.c_int32(), C.c_int32()
+        L.check(L.lib().bxmg_batch_stats(self._h, C.byref(used), C.byref(budget), C.byref(run), C.byref(q)))
+        return {"bytes_used": used.value, "bytes_budget": budget.value, "running": run.value, "queued": q.value}
+
+    def run(self, chunk=2):
+        """Steps until nothing runs; returns every finished (id, SolveResult)."""
+        out = []
+        while True:
+            n = self.step(chunk)
+            out += self.poll(1 << 16)
+            if n == 0:
+                out += self.poll(1 << 16)
+                return out

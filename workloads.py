@@ -57,6 +57,40 @@ def smooth_gaussian_beta(shape, seed, passes=3):
     return np.asfortranarray(np.exp(g))
 
 
+# ------------------------------------------------------------------------
+# Device-side draws of the same distributions (torch's Philox generator on
+# the GPU, seeded per field), for workloads too large to draw and copy from
+# the host in a benchmark: the recipes are those of uniform_rhs and
+# smooth_gaussian_beta, the random streams are not.  Tensors are indexed
+# [i, j, k] like the numpy fields.
+
+
+def uniform_rhs_device(shape, seed, mean_zero=False, device="cuda"):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f = torch.rand(tuple(shape), generator=g, device=device, dtype=torch.float64) * 2.0 - 1.0
+    if mean_zero:
+        f = f - f.mean()
+    return f
+
+
+def smooth_gaussian_beta_device(shape, seed, passes=3, device="cuda"):
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    x = torch.randn(tuple(shape), generator=g, device=device, dtype=torch.float64)
+    for _ in range(passes):
+        acc = torch.zeros_like(x)
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    acc += torch.roll(x, (dx, dy, dz), dims=(0, 1, 2))
+        x = acc / 27.0
+    x = (x - x.mean()) / x.std(unbiased=False)
+    return torch.exp(x)
+
+
 def dyadic_codes(shape, seed=0, scale=1.0 / 64):
     """Exactly representable small codes: integers in [-64, 64] times `scale`
     (a power of two), so sums of up to 64 of them with weights k/64 are exact
