@@ -351,6 +351,22 @@ def section_serving(bx, W, nreq):
     return out
 
 
+def summarize_trace(csv_path, out_path, command):
+    """The rocprofv3 --stats kernel table (csv) as a short text summary."""
+    import csv
+    rows = list(csv.DictReader(open(csv_path)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = ["# rocprofv3 --kernel-trace --stats summary", "# command: " + command,
+             "# %d kernels, %.3f ms total GPU time" % (len(rows), tot / 1e6),
+             "%-90s %8s %12s %12s %7s" % ("kernel", "calls", "total_us", "avg_us", "pct")]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name = r["Name"] if len(r["Name"]) <= 90 else r["Name"][:87] + "..."
+        lines.append("%-90s %8d %12.1f %12.2f %7.2f" % (name, int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
+                                                        float(r["AverageNs"]) / 1e3, 100.0 * float(r["TotalDurationNs"]) / tot))
+    open(out_path, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines[:25]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,10 +378,17 @@ def main():
     ap.add_argument("--sections", default="mixed,batched,serving",
                     help="other rows to measure after the headline (comma list; '' for none)")
     ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("CSV", "OUT", "COMMAND"),
+                    help="write a text summary of a rocprofv3 kernel_stats.csv")
+    ap.add_argument("--knobs", metavar="Z,R,L", help="planes per thread, buffer addressing (0/1), log2 tile-row cap")
     args = ap.parse_args()
 
     if args.summarize_counters:
         summarize_counters(args.summarize_counters)
+        return 0
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
         return 0
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported (the batched and served forms "
@@ -379,6 +402,17 @@ def main():
     ba, f, phi, rhs = make_problem(bx, W)
     ctx = phi.ctx
     lib = bx.lib()
+    tuned = None
+    if args.knobs:
+        # launch shapes given explicitly (e.g. the autotuner's choice of an
+        # earlier run, so that a profiled run times exactly those launches)
+        z, r, ly = (int(x) for x in args.knobs.split(","))
+        for param, value in ((0, z), (1, z), (2, r), (3, ly)):
+            bx._lib.check(lib.bxmg_ctx_tune(ctx._h, param, value))
+        tuned = {"planes_per_thread": z, "buffer_addressing": r, "tile_rows_log2_cap": ly, "source": "--knobs"}
+    elif not args.no_autotune:
+        # the project autotuner picks the launch shapes on this workload
+        tuned = bx.autotune(bx.MultiFab(ba), rhs, cycles=2)
     for _ in range(args.warmup):
         phi.set_val(0.0)
         res = bx.mlmg_solve(phi, rhs, rel_tol=TOL)
@@ -435,6 +469,7 @@ def main():
         "vcycle_effective_GBps": BYTES_PER_CELL_CYCLE * N ** 3 * mean_cycles / (ms_per_step / 1000.0) / 1e9,
         "vcycle_model_bytes_per_cell": BYTES_PER_CELL_CYCLE,
         "solves_per_s": 1000.0 / ms_per_step,
+        "autotuned_launch_shape": tuned,
         "final_rel_resid_inf": res.rel_resid_inf,
         "roofline": {"bound": "hbm", "kernel": GS_KERNEL + " (level 0, one colour)", "achieved": achieved,
                      "peak": PEAK_GBPS, "unit": "GB/s", "frac": achieved / PEAK_GBPS, "traffic": traffic,

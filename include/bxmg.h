@@ -189,8 +189,21 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
  * box planes (default 4); value in [1, 64].  param 2 = address box data with
  * 32-bit buffer offsets where every box allows it (1, default) or with
  * 64-bit addresses (0).  Other values: EINVAL.  Results do not depend on the
- * knobs; only the work decomposition and instruction selection do. */
+ * knobs; only the work decomposition and instruction selection do.
+ * param 3 = at most 2^value threads of a tile along y (0..8, default 8). */
 bxmg_status bxmg_ctx_tune(bxmg_ctx ctx, int32_t param, int32_t value);
+
+/* Launch-shape autotuner: solves the given problem for `cycles` V-cycles
+ * (fixed count, params otherwise as given) under every candidate setting of
+ * the knobs above -- planes per thread {1, 2, 4, 8} (params 0 and 1), tile
+ * rows 2^{2, 3, 8} (param 3), buffer addressing on/off (param 2) -- timing
+ * each twice after one warm-up solve, and leaves the fastest set on the
+ * context (hierarchies and batches built afterwards use it).  best receives
+ * {param 0, param 1, param 2, param 3}, *best_ms the time per V-cycle,
+ * *ntried the candidates timed.  phi is overwritten (pass a scratch guess).
+ * Synchronous. */
+bxmg_status bxmg_autotune(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi, bxmg_multifab rhs,
+                          bxmg_multifab beta, int32_t cycles, int32_t best[4], double* best_ms, int32_t* ntried);
 
 /* ---------------------------------------------------------- profiling --- */
 /* Kernel timing with HIP events recorded on the context's stream around
@@ -246,8 +259,10 @@ bxmg_status bxmg_bottom_solve(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab rhs
  * workgroup of one shared launch.  Per cycle: FP64 residual and norms of
  * every problem, a stop test on the device (each problem with its own
  * tolerance), then the V-cycle of those still running; a problem that has
- * stopped costs nothing more.  The cycle is captured once as a hipGraph and
- * replayed (rebuilt whenever problems join or leave).
+ * stopped costs nothing more.  The cycle is captured as a hipGraph and
+ * replayed once the set of running problems has stayed the same for one
+ * launch; while problems join or leave every step, its stages are launched
+ * one by one instead.
  *
  * Memory: level storage of all problems lives in one arena sized by the
  * budget given at creation (the arena is the budget; nothing else grows
@@ -275,9 +290,10 @@ void bxmg_batch_destroy(bxmg_batch b);
  * cells, or level storage beyond 2^31 elements). */
 size_t bxmg_batch_footprint(bxmg_batch b, bxmg_boxarray ba);
 
-/* Admits a problem: converts phi (initial guess) and rhs (and beta) into
- * the arena on the batch's stream and computes ||rhs||_inf (one host sync).
- * rel_tol <= 0: the batch's rel_tol.  The MultiFabs (FP64, nghost >= 1,
+/* Admits a problem: enqueues the conversion of phi (initial guess), rhs
+ * (and beta) into the arena and the computation of ||rhs||_inf on the
+ * batch's stream, without waiting for them (a zero or non-finite rhs
+ * retires the problem at the next step).  rel_tol <= 0: the batch's rel_tol.  The MultiFabs (FP64, nghost >= 1,
  * one BoxArray) must stay alive until the result is polled: phi receives
  * the solution.  BXMG_EBUSY: the footprint does not fit now or every slot
  * is taken (nothing changed); EINVAL: bad arguments or a domain a batch

@@ -66,6 +66,7 @@ def _declare(lib):
         "bxmg_solve_params_default": (None, [C.POINTER(SolveParams)]),
         "bxmg_mlmg_solve": (C.c_int, [H, C.POINTER(SolveParams), H, H, H, C.POINTER(SolveInfo)]),
         "bxmg_ctx_tune": (C.c_int, [H, C.c_int32, C.c_int32]),
+        "bxmg_autotune": (C.c_int, [H, C.POINTER(SolveParams), H, H, H, C.c_int32, I32P, DP, I32P]),
         "bxmg_profile_stage": (C.c_int, [H, C.c_int32]),
         "bxmg_profile_read": (C.c_int, [H, I64P, DP, C.c_int32]),
         "bxmg_gs_colour": (C.c_int, [H, H, H, H, C.c_double, C.c_int32]),

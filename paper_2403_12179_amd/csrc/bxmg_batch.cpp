@@ -4,14 +4,21 @@
 // in FP32 for the mixed form).  A problem owns one contiguous element range
 // of that arena, laid out level by level in the colour-split format of the
 // single-problem driver, so its level data sit at the same offsets in every
-// kind.  For each level index l the batch concatenates the boxes of every
-// running problem that has a level l, and the stage kernels run once per
-// level over all of them (boxes carry their problem slot and grid spacing).
-// The trailing single-box levels of every problem run in one launch of the
-// fused coarse cycle, one workgroup per problem.  A cycle's residual norms
-// are reduced per problem and a device-side stop test retires the problems
-// that are done; later launches skip their boxes.  The whole cycle is
-// captured as a hipGraph and replayed until the host looks again.
+// kind.  Everything that depends only on a problem's geometry (hierarchy,
+// box layouts, ghost lists, tiles) is built once per geometry as a GeoPlan
+// whose offsets are relative to the problem start, and shared by every
+// problem of that shape; a problem itself is an arena offset and a slot.
+//
+// For each level index l the batch concatenates the boxes of every running
+// problem that has a level l, and the stage kernels run once per level over
+// all of them (boxes carry their problem slot and grid spacing).  The
+// trailing single-box levels of every problem run in one launch of the fused
+// coarse cycle, one workgroup per problem.  A cycle's residual norms are
+// reduced per problem and a device-side stop test retires the problems that
+// are done; later launches skip their boxes.  The whole cycle is captured as
+// a hipGraph and replayed until the host looks again.  Admission and
+// retirement enqueue their conversions without waiting; a step synchronises
+// once.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -36,6 +43,7 @@ struct Ranges {
         if (cap > 0) free[0] = cap;
     }
     long long take(long long n) {
+        if (n <= 0) return 0;
         for (auto it = free.begin(); it != free.end(); ++it)
             if (it->second >= n) {
                 const long long s = it->first, len = it->second;
@@ -46,6 +54,7 @@ struct Ranges {
         return -1;
     }
     void give(long long s, long long n) {
+        if (n <= 0) return;
         auto it = free.emplace(s, n).first;
         auto nx = std::next(it);
         if (nx != free.end() && it->first + it->second == nx->first) {
@@ -60,82 +69,198 @@ struct Ranges {
             }
         }
     }
+    long long free_total() const {
+        long long t = 0;
+        for (auto& r : free) t += r.second;
+        return t;
+    }
 };
 
-// One level of one problem; RBox bases are absolute arena offsets, face
-// neighbours index the problem's own box list of the level.
-struct PLevel {
+// ------------------------------------------------------------------- plans
+// One level of a geometry; element offsets relative to the problem start.
+struct PlanLevel {
     Box dom;
     double h = 0;
     std::vector<Box> boxes;
     std::vector<RBox> rb;
-    long long off = 0, nelem = 0;  // absolute element range of the level
+    long long off = 0, nelem = 0;
     bool push = false;
-    std::vector<GhostCopy> face[2], full;  // absolute element indices
-    std::vector<int> cbox;                 // coarse owner (level l+1, local index)
+    std::vector<int> cbox;  // coarse owner (level l+1, local index)
+    std::vector<std::array<int, 3>> ecol, edown;
+    std::vector<Tile> tcol, tdown;  // tiles of the level alone (box = local index)
+    DevBuf<GhostCopy> face[2], full;    // indices relative to the problem start
+    DevBuf<GhostCopy> cface[2], cfull;  // relative to the level start (coarse-cycle levels)
+    long long fface[3] = {0, 0, 0};     // face-array offsets (variable coefficient)
 };
 
-template <class T>
-struct PFaces {
-    DevBuf<T> c[3];
-    FaceArrays<T> view{};
-};
-
-// Device copies of a level's coarse-cycle ghost lists, indices relative to
-// the level's first element.
-struct CList {
-    DevBuf<GhostCopy> face[2], full;
-};
-
-struct Problem {
-    int64_t id = 0;
-    int slot = -1;
-    bxmg_multifab phi = nullptr, rhs = nullptr, beta = nullptr;
+struct GeoPlan {
     Box dom;
     int per[3] = {0, 0, 0};
-    std::vector<PLevel> L;
+    std::vector<PlanLevel> L;
     int cs = -1;  // first level of the fused coarse cycle
-    long long off = 0, len = 0;
-    double rel_tol = 0, f_inf = 0;
-    Clock::time_point t_add;
-    // level 0 (and level 1 for the coefficient setup) of this problem alone
+    long long len = 0, face_len = 0;
+    // level 0 (and 1, for the coefficient setup) of one problem alone
     DevBuf<RBox> rb0, rb1;
     DevBuf<Tile> t0;
     int nt0 = 0;
-    TileShape sh0{};
-    DevBuf<GhostCopy> face0[2], full_even0;
+    int res0 = 0;
+    DevBuf<GhostCopy> full_even0;
     DevBuf<int> cbox0;
     DevBuf<Tile> tface[3];
     int ntface[3] = {0, 0, 0};
-    TileShape shface[3]{};
-    std::vector<std::unique_ptr<PFaces<double>>> f64;  // index = level (0 unused)
-    std::vector<std::unique_ptr<PFaces<float>>> f32;
-    size_t face_bytes = 0;
-    std::vector<std::unique_ptr<CList>> clist;  // index = level - cs
-    int res0 = 0;
-    Grid grid0() const { return Grid{rb0.p, t0.p, nt0, sh0, L[0].push ? 1 : 0, nullptr, 0, res0}; }
+    Grid grid0() const { return Grid{rb0.p, t0.p, nt0, L[0].push ? 1 : 0, nullptr, 0, res0}; }
     XGrid face_grid(int d) const {
-        return XGrid{rb0.p, rb1.p, cbox0.p, tface[d].p, ntface[d], shface[d], 0, nullptr, 0};
+        return XGrid{rb0.p, rb1.p, cbox0.p, tface[d].p, ntface[d], 0, nullptr, 0, 0};
     }
+};
+
+// Geometry only (no device work): hierarchy, coarse-cycle start, layout.
+// False (with a reason) if the problem cannot run in a batch.
+bool plan_geometry(const bxmg_ba_s* ba, double h0, GeoPlan& P, std::string* why) {
+    P.dom = ba->dom;
+    for (int d = 0; d < 3; ++d) P.per[d] = ba->per[d];
+    const std::vector<LevelBoxes> lb = make_hierarchy(ba->dom, ba->boxes);
+    if (!bottom_fits(lb.back().dom)) {
+        if (why) *why = "bottom level above 4096 cells";
+        return false;
+    }
+    const size_t nl = lb.size();
+    P.cs = -1;
+    for (size_t l = 1; l < nl; ++l) {
+        bool ok = nl - l <= (size_t)kMaxCoarseLevels;
+        for (size_t m = l; m < nl && ok; ++m) ok = lb[m].boxes.size() == 1 && lb[m].dom.cells() <= kMaxBottomCells;
+        if (ok) { P.cs = (int)l; break; }
+    }
+    if (P.cs < 0) {
+        if (why) *why = "the trailing levels are not single boxes of at most 4096 cells";
+        return false;
+    }
+    P.L.clear();
+    P.L.resize(nl);
+    long long off = 0, foff = 0;
+    double h = h0;
+    for (size_t l = 0; l < nl; ++l) {
+        PlanLevel& v = P.L[l];
+        v.dom = lb[l].dom;
+        v.h = h;
+        h *= 2.0;
+        v.boxes = lb[l].boxes;
+        v.rb = rb_layout(v.boxes, 1, v.h, &v.nelem);
+        v.push = face_neighbours(v.dom, P.per, v.boxes, v.rb);
+        v.off = off;
+        for (auto& r : v.rb) r.base += off;
+        off += v.nelem;
+        if (l + 1 < nl) v.cbox = coarse_owner(v.boxes, lb[l + 1].boxes);
+        v.ecol = colour_extents(v.boxes);
+        if (l + 1 < nl) v.edown = coarse_extents(v.boxes, v.dom, -1);
+        if (l >= 1)
+            for (int d = 0; d < 3; ++d) {
+                v.fface[d] = foff;
+                foff += (long long)(v.dom.n(0) + (d == 0)) * (v.dom.n(1) + (d == 1)) * (v.dom.n(2) + (d == 2));
+            }
+    }
+    P.len = (off + 63) / 64 * 64;
+    P.face_len = (foff + 63) / 64 * 64;
+    if (P.len > 0x7fffffffLL) {
+        if (why) *why = "level storage beyond 2^31 elements";
+        return false;
+    }
+    return true;
+}
+
+// Ghost lists and device structures of a planned geometry.
+void plan_device(GeoPlan& P, const bxmg_ctx_s* ctx, bool var) {
+    for (size_t l = 0; l < P.L.size(); ++l) {
+        PlanLevel& v = P.L[l];
+        if ((int)l < P.cs) {
+            TileSet tc = make_tiles(v.ecol, ctx->zc, ctx->ly_cap);
+            if (tc.sh.lz == 0) tc = make_tiles(v.ecol, ctx->zc_planes, ctx->ly_cap);
+            v.tcol = tc.tiles;
+            v.tdown = make_tiles(v.edown, ctx->zc, ctx->ly_cap).tiles;
+        }
+        const std::vector<Tag> faces = build_tags(v.dom, P.per, v.boxes, 1, true, 2, true);
+        const std::vector<GhostCopy> f0 = ghost_list(faces, v.rb, 1), f1 = ghost_list(faces, v.rb, 2);
+        const std::vector<GhostCopy> full = ghost_list(build_tags(v.dom, P.per, v.boxes, 1, false, 2, true), v.rb, 3);
+        if ((int)l < P.cs) {
+            v.face[0].upload(f0);
+            v.face[1].upload(f1);
+        }
+        if (l >= 1 && (int)l <= P.cs) v.full.upload(full);
+        if ((int)l >= P.cs) {
+            auto rel = [&](const std::vector<GhostCopy>& a) {
+                std::vector<GhostCopy> o(a);
+                for (auto& g : o) {
+                    g.dst -= (uint32_t)v.off;
+                    g.src = ((g.src & 0x7fffffffu) - (uint32_t)v.off) | (g.src & 0x80000000u);
+                }
+                return o;
+            };
+            v.cface[0].upload(rel(f0));
+            v.cface[1].upload(rel(f1));
+            v.cfull.upload(rel(full));
+        }
+    }
+    const PlanLevel& L0 = P.L[0];
+    P.rb0.upload(L0.rb);
+    P.rb1.upload(P.L[1].rb);
+    P.cbox0.upload(L0.cbox);
+    P.res0 = (ctx->res && boxes_fit_res(L0.rb)) ? 1 : 0;
+    P.t0.upload(L0.tcol);
+    P.nt0 = (int)L0.tcol.size();
+    if (var) {
+        P.full_even0.upload(ghost_list(build_tags(L0.dom, P.per, L0.boxes, 1, false, 2, false), L0.rb, 3));
+        for (int d = 0; d < 3; ++d) {
+            TileSet tf = make_tiles(coarse_extents(L0.boxes, L0.dom, d), ctx->zc);
+            P.tface[d].upload(tf.tiles);
+            P.ntface[d] = (int)tf.tiles.size();
+        }
+    }
+}
+
+std::string plan_key(const bxmg_ba_s* ba, double h, const bxmg_ctx_s* ctx) {
+    std::string k;
+    auto put = [&](long long x) { k.append((const char*)&x, sizeof x); };
+    for (int d = 0; d < 3; ++d) { put(ba->dom.lo[d]); put(ba->dom.hi[d]); put(ba->per[d]); }
+    put(ctx->zc);
+    put(ctx->zc_planes);
+    put(ctx->res);
+    put(ctx->ly_cap);
+    long long hb;
+    std::memcpy(&hb, &h, sizeof hb);
+    put(hb);
+    for (auto& b : ba->boxes)
+        for (int d = 0; d < 3; ++d) { put(b.lo[d]); put(b.hi[d]); }
+    return k;
+}
+
+// ------------------------------------------------------------- problems
+struct Problem {
+    int64_t id = 0;
+    int slot = -1;
+    bxmg_multifab phi = nullptr;
+    std::shared_ptr<GeoPlan> plan;
+    long long off = 0, foff = 0;  // arena ranges
+    double rel_tol = 0;
+    Clock::time_point t_add;
 };
 
 // Launch structures of one level index over the running problems.
 struct BLevel {
-    DevBuf<RBox> rb;
-    DevBuf<Tile> tcol, tdown;
+    DevVec<RBox> rb;
+    DevVec<Tile> tcol, tdown;
     int ntcol = 0, ntdown = 0;
-    TileShape shcol{}, shdown{};
-    DevBuf<int> cbox;
+    DevVec<int> cbox;
     bool push = true;
-    DevBuf<GhostCopy> face[2], fullc;  // face ghosts of l; every ghost of l + 1
-    long long nface[2] = {0, 0}, nfullc = 0;
-    DevBuf<ZeroRange> zr;  // level l + 1 of the problems tiled at l
+    int res = 1;
+    DevVec<GhostSet> face[2], fullc;  // face ghosts of l; every ghost of l + 1
+    int nface = 0, nfullc = 0;
+    long long mface = 0, mfullc = 0;
+    DevVec<ZeroRange> zr;  // level l + 1 of the problems tiled at l
     int nzr = 0;
     long long zmax = 0;
-    DevBuf<FaceArrays<double>> fat64;  // by slot
-    DevBuf<FaceArrays<float>> fat32;
+    DevVec<FaceArrays<double>> fat64;  // by slot
+    DevVec<FaceArrays<float>> fat32;
     int flip = 0;
-    int res = 1;
 };
 
 struct Done {
@@ -151,226 +276,138 @@ struct bxmg_batch_s {
     bool var = false;
     int prec = 0;
     int max_slots = 0;
-    size_t budget = 0, arena_bytes = 0, face_budget = 0, face_used = 0;
-    long long cap = 0;  // arena elements
-    Ranges ranges;
-    DevBuf<double> u64, f64, b64;
-    DevBuf<float> u32, f32, b32;
+    size_t budget = 0;
+    long long cap = 0, fcap = 0;  // arena elements, face-arena elements
+    Ranges ranges, franges;
+    DevBuf<double> u64, f64, b64, fa64;
+    DevBuf<float> u32, f32, b32, fa32;
     // per slot
     DevBuf<int> active, nactive;
     DevBuf<BatchSlot> st;
-    DevBuf<double> norms, hist, hist_l2;
+    DevBuf<double> norms, hist, hist_l2, fn3;
     int* h_active = nullptr;
-    int* h_nactive = nullptr;
     BatchSlot* h_st = nullptr;
+    double* h_hist = nullptr;  // 2 * kHist per slot (history, then L2 history)
     std::vector<std::unique_ptr<Problem>> slots;
     std::deque<int> free_slots;
     int64_t next_id = 1;
     std::deque<Done> done;
+    std::map<std::string, std::shared_ptr<GeoPlan>> plans;
+    std::deque<std::string> plan_lru;
     // launch structures of the running set
     bool dirty = true;
     std::vector<int> members;
-    DevBuf<int> d_members;
+    DevVec<int> d_members;
     std::vector<BLevel> lev;
     int lmax = 0;
-    DevBuf<int> tstart, segslot;
+    DevVec<int> tstart, segslot;
     int nseg = 0;
-    DevBuf<double> partials, scratch;
-    DevBuf<ZeroRange> z0;
+    DevVec<double> partials, scratch;
+    DevVec<ZeroRange> z0;
     int nz0 = 0;
     long long z0max = 0;
-    DevBuf<CoarseCycle<double>> cc64;
-    DevBuf<CoarseCycle<float>> cc32;
-    std::vector<CoarseCycle<double>> cc64_host;
-    std::vector<CoarseCycle<float>> cc32_host;
+    DevVec<CoarseCycle<double>> cc64;
+    DevVec<CoarseCycle<float>> cc32;
     int ncc = 0;
     bool use_graph = true;
+    int stable = 0;         // launches since the running set last changed
     bool inflight = false;  // cycles launched and not yet collected
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     // the batch's own stream (default priority): graphs cannot be captured on
     // the legacy default stream a context may use
     hipStream_t stream = nullptr;
+    hipEvent_t caller_ready = nullptr;
     ~bxmg_batch_s() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (caller_ready) (void)hipEventDestroy(caller_ready);
         if (stream) (void)hipStreamDestroy(stream);
         if (h_active) (void)hipHostFree(h_active);
-        if (h_nactive) (void)hipHostFree(h_nactive);
         if (h_st) (void)hipHostFree(h_st);
+        if (h_hist) (void)hipHostFree(h_hist);
     }
 };
 
 namespace {
 
-// ------------------------------------------------------- problem layout
-// The problem's hierarchy, its coarse-cycle start, and its element count;
-// false if it cannot run in a batch.
-bool plan_problem(const bxmg_ba_s* ba, double h0, Problem& p, long long* len, std::string* why) {
-    p.dom = ba->dom;
-    for (int d = 0; d < 3; ++d) p.per[d] = ba->per[d];
-    const std::vector<LevelBoxes> lb = make_hierarchy(ba->dom, ba->boxes);
-    if (!bottom_fits(lb.back().dom)) {
-        if (why) *why = "bottom level above 4096 cells";
-        return false;
-    }
-    const size_t nl = lb.size();
-    p.cs = -1;
-    for (size_t l = 1; l < nl; ++l) {
-        bool ok = nl - l <= (size_t)kMaxCoarseLevels;
-        for (size_t m = l; m < nl && ok; ++m) ok = lb[m].boxes.size() == 1 && lb[m].dom.cells() <= kMaxBottomCells;
-        if (ok) { p.cs = (int)l; break; }
-    }
-    if (p.cs < 0) {
-        if (why) *why = "the trailing levels are not single boxes of at most 4096 cells";
-        return false;
-    }
-    p.L.clear();
-    long long off = 0;
-    double h = h0;
-    for (size_t l = 0; l < nl; ++l) {
-        PLevel v;
-        v.dom = lb[l].dom;
-        v.h = h;
-        h *= 2.0;
-        v.boxes = lb[l].boxes;
-        v.rb = rb_layout(v.boxes, 1, v.h, &v.nelem);
-        v.push = face_neighbours(v.dom, p.per, v.boxes, v.rb);
-        v.off = off;
-        off += v.nelem;
-        if (l + 1 < nl) v.cbox = coarse_owner(v.boxes, lb[l + 1].boxes);
-        p.L.push_back(std::move(v));
-    }
-    *len = (off + 63) / 64 * 64;
-    return true;
+size_t arena_bytes_per_elem(int prec, bool var) {
+    size_t e = 16;                // u, f FP64
+    if (prec == 1) e += 8;        // u, f FP32
+    if (var) e += prec ? 12 : 8;  // beta FP64 (+ FP32)
+    return e;
 }
 
-size_t face_bytes_of(const Problem& p, int es) {
-    size_t n = 0;
-    for (size_t l = 1; l < p.L.size(); ++l) {
-        const Box& D = p.L[l].dom;
-        for (int d = 0; d < 3; ++d) n += (size_t)(D.n(0) + (d == 0)) * (D.n(1) + (d == 1)) * (D.n(2) + (d == 2));
+// The plan of a geometry (built on first use; the last 64 are kept).
+std::shared_ptr<GeoPlan> get_plan(bxmg_batch_s* b, const bxmg_ba_s* ba, double h, std::string* why) {
+    const std::string key = plan_key(ba, h, b->ctx);
+    auto it = b->plans.find(key);
+    if (it != b->plans.end()) return it->second;
+    auto P = std::make_shared<GeoPlan>();
+    if (!plan_geometry(ba, h, *P, why)) return nullptr;
+    plan_device(*P, b->ctx, b->var);
+    b->plans[key] = P;
+    b->plan_lru.push_back(key);
+    if (b->plan_lru.size() > 64) {
+        b->plans.erase(b->plan_lru.front());
+        b->plan_lru.pop_front();
     }
-    return n * es;
-}
-
-// Places the problem at arena offset `base`: absolute box bases, ghost lists.
-void place_problem(Problem& p, long long base, bool var) {
-    p.off = base;
-    for (size_t l = 0; l < p.L.size(); ++l) {
-        PLevel& v = p.L[l];
-        v.off += base;
-        for (auto& r : v.rb) r.base += v.off;
-        const std::vector<Tag> faces = build_tags(v.dom, p.per, v.boxes, 1, true, 2, true);
-        v.face[0] = ghost_list(faces, v.rb, 1);
-        v.face[1] = ghost_list(faces, v.rb, 2);
-        v.full = ghost_list(build_tags(v.dom, p.per, v.boxes, 1, false, 2, true), v.rb, 3);
-    }
-    // coarse-cycle levels: lists relative to the level start
-    p.clist.clear();
-    for (size_t l = (size_t)p.cs; l < p.L.size(); ++l) {
-        PLevel& v = p.L[l];
-        auto rel = [&](const std::vector<GhostCopy>& a) {
-            std::vector<GhostCopy> o(a);
-            for (auto& g : o) {
-                g.dst -= (uint32_t)v.off;
-                g.src = ((g.src & 0x7fffffffu) - (uint32_t)v.off) | (g.src & 0x80000000u);
-            }
-            return o;
-        };
-        auto c = std::make_unique<CList>();
-        c->face[0].upload(rel(v.face[0]));
-        c->face[1].upload(rel(v.face[1]));
-        c->full.upload(rel(v.full));
-        p.clist.push_back(std::move(c));
-    }
-    // level 0 alone: setup, norms of f, final conversion
-    p.rb0.upload(p.L[0].rb);
-    p.rb1.upload(p.L[1].rb);
-    p.face0[0].upload(p.L[0].face[0]);
-    p.face0[1].upload(p.L[0].face[1]);
-    p.cbox0.upload(p.L[0].cbox);
-    if (var) {
-        std::vector<RBox> rb = p.L[0].rb;
-        p.full_even0.upload(ghost_list(build_tags(p.L[0].dom, p.per, p.L[0].boxes, 1, false, 2, false), rb, 3));
-    }
-}
-
-void problem_tiles(Problem& p, int zc, int zc_planes, int res, bool var) {
-    p.res0 = (res && boxes_fit_res(p.L[0].rb)) ? 1 : 0;
-    TileSet ts = make_tiles(colour_extents(p.L[0].boxes), zc);
-    if (ts.sh.lz == 0) ts = make_tiles(colour_extents(p.L[0].boxes), zc_planes);
-    p.t0.upload(ts.tiles);
-    p.nt0 = (int)ts.tiles.size();
-    p.sh0 = ts.sh;
-    if (var)
-        for (int d = 0; d < 3; ++d) {
-            TileSet tf = make_tiles(coarse_extents(p.L[0].boxes, p.L[0].dom, d), zc);
-            p.tface[d].upload(tf.tiles);
-            p.ntface[d] = (int)tf.tiles.size();
-            p.shface[d] = tf.sh;
-        }
+    return P;
 }
 
 template <class T>
-void alloc_faces(Problem& p, std::vector<std::unique_ptr<PFaces<T>>>& F) {
-    F.clear();
-    F.resize(p.L.size());
-    for (size_t l = 1; l < p.L.size(); ++l) {
-        F[l] = std::make_unique<PFaces<T>>();
-        const Box& D = p.L[l].dom;
-        for (int d = 0; d < 3; ++d) {
-            F[l]->c[d].alloc((size_t)(D.n(0) + (d == 0)) * (D.n(1) + (d == 1)) * (D.n(2) + (d == 2)));
-            F[l]->view.c[d] = F[l]->c[d].p;
-            F[l]->view.dlo[d] = D.lo[d];
-            F[l]->view.n[d] = D.n(d);
-        }
+FaceArrays<T> face_view(const Problem& p, const T* arena, size_t l) {
+    FaceArrays<T> f;
+    const PlanLevel& v = p.plan->L[l];
+    for (int d = 0; d < 3; ++d) {
+        f.c[d] = (l >= 1 && arena) ? arena + p.foff + v.fface[d] : nullptr;
+        f.dlo[d] = v.dom.lo[d];
+        f.n[d] = v.dom.n(d);
     }
+    return f;
 }
 
 // face arrays of levels >= 1 from the level-0 cell beta (as the single-problem setup)
 template <class T>
-void setup_faces(hipStream_t s, Problem& p, std::vector<std::unique_ptr<PFaces<T>>>& F, T* beta_arena) {
-    HIPCHK(launch_fill_rb(s, beta_arena, sizeof(T) == 4, p.full_even0.p, (long long)p.full_even0.n));
-    for (size_t l = 1; l < p.L.size(); ++l)
+void setup_faces(hipStream_t s, const Problem& p, T* beta0, const T* arena) {
+    const GeoPlan& P = *p.plan;
+    HIPCHK(launch_fill_rb(s, beta0, sizeof(T) == 4, P.full_even0.p, (long long)P.full_even0.n));
+    for (size_t l = 1; l < P.L.size(); ++l) {
+        const FaceArrays<T> out = face_view<T>(p, arena, l);
         for (int d = 0; d < 3; ++d) {
-            T* dst = F[l]->c[d].p;
-            if (l == 1) HIPCHK(launch_faces_from_cells<T>(s, p.face_grid(d), beta_arena, d, F[l]->view, dst));
-            else HIPCHK(launch_faces_coarsen<T>(s, F[l - 1]->view, F[l]->view, d, dst));
+            T* dst = const_cast<T*>(out.c[d]);
+            if (l == 1) HIPCHK(launch_faces_from_cells<T>(s, P.face_grid(d), beta0, d, out, dst));
+            else HIPCHK(launch_faces_coarsen<T>(s, face_view<T>(p, arena, l - 1), out, d, dst));
         }
+    }
 }
 
 template <class T>
-CoarseCycle<T> coarse_desc(const bxmg_batch_s* b, const Problem& p, T* u, T* f,
-                           const std::vector<std::unique_ptr<PFaces<T>>>* F) {
+CoarseCycle<T> coarse_desc(const bxmg_batch_s* b, const Problem& p, T* u, T* f, const T* faces) {
+    const GeoPlan& P = *p.plan;
     CoarseCycle<T> cc;
     std::memset(&cc, 0, sizeof cc);
-    cc.nlev = (int)p.L.size() - p.cs;
+    cc.nlev = (int)P.L.size() - P.cs;
     cc.nu1 = b->P.nu1;
     cc.nu2 = b->P.nu2;
     cc.prolong = b->P.prolong;
-    for (int d = 0; d < 3; ++d) cc.per[d] = p.per[d];
+    for (int d = 0; d < 3; ++d) cc.per[d] = P.per[d];
     cc.pid = p.slot;
     cc.rtol = b->P.bottom_rtol;
     cc.iters = nullptr;
     for (int m = 0; m < cc.nlev; ++m) {
-        const PLevel& v = p.L[p.cs + m];
+        const PlanLevel& v = P.L[P.cs + m];
         CoarseLevel<T>& c = cc.L[m];
         c.box = v.rb[0];
         c.box.base -= v.off;
-        c.u = u + v.off;
-        c.f = f + v.off;
-        const CList& cl = *p.clist[m];
-        for (int q = 0; q < 2; ++q) { c.face[q] = cl.face[q].p; c.nface[q] = (long long)cl.face[q].n; }
-        c.full = cl.full.p;
-        c.nfull = (long long)cl.full.n;
+        c.u = u + p.off + v.off;
+        c.f = f + p.off + v.off;
+        for (int q = 0; q < 2; ++q) { c.face[q] = v.cface[q].p; c.nface[q] = (long long)v.cface[q].n; }
+        c.full = v.cfull.p;
+        c.nfull = (long long)v.cfull.n;
         c.nelem = v.nelem;
         c.h = v.h;
-        if (F && p.cs + m >= 1) {
-            c.fa = (*F)[p.cs + m]->view;
-        } else {
-            for (int d = 0; d < 3; ++d) { c.fa.c[d] = nullptr; c.fa.dlo[d] = 0; c.fa.n[d] = 0; }
-        }
+        c.fa = face_view<T>(p, faces, P.cs + m);
         c.push = v.push ? 1 : 0;
     }
     return cc;
@@ -387,8 +424,7 @@ void rebuild(bxmg_batch_s* b) {
     b->members.clear();
     for (int s = 0; s < b->max_slots; ++s)
         if (b->slots[s] && b->h_active[s]) b->members.push_back(s);
-    b->d_members.upload(b->members);
-    b->lev.clear();
+    b->d_members.assign(b->members);
     b->lmax = 0;
     b->ncc = 0;
     b->nseg = 0;
@@ -396,107 +432,87 @@ void rebuild(bxmg_batch_s* b) {
     if (b->members.empty()) return;
     size_t depth = 0;
     for (int s : b->members) {
-        depth = std::max(depth, b->slots[s]->L.size());
-        b->lmax = std::max(b->lmax, b->slots[s]->cs);
+        depth = std::max(depth, b->slots[s]->plan->L.size());
+        b->lmax = std::max(b->lmax, b->slots[s]->plan->cs);
     }
-    b->lev.resize(depth);
+    if (b->lev.size() < depth) b->lev.resize(depth);
     std::vector<std::vector<int>> first(depth, std::vector<int>(b->max_slots, -1));  // first box of slot at level
     std::vector<std::vector<RBox>> rbs(depth);
     for (size_t l = 0; l < depth; ++l)
         for (int s : b->members) {
             const Problem& p = *b->slots[s];
-            if (l >= p.L.size()) continue;
+            if (l >= p.plan->L.size()) continue;
             first[l][s] = (int)rbs[l].size();
-            for (const RBox& r0 : p.L[l].rb) {
+            for (const RBox& r0 : p.plan->L[l].rb) {
                 RBox r = r0;
+                r.base += p.off;
                 r.pid = s;
                 for (int q = 0; q < 6; ++q)
                     if (r.nb[q] >= 0) r.nb[q] += first[l][s];
                 rbs[l].push_back(r);
             }
         }
-    const int zc = b->ctx->zc, zcp = b->ctx->zc_planes;
     std::vector<int> tstart{0}, segslot;
     for (size_t l = 0; l < depth; ++l) {
         BLevel& B = b->lev[l];
-        B.rb.upload(rbs[l]);
+        B.rb.assign(rbs[l]);
         B.res = (b->ctx->res && boxes_fit_res(rbs[l])) ? 1 : 0;
+        B.ntcol = B.ntdown = B.nface = B.nfullc = B.nzr = 0;
         if ((int)l >= b->lmax) continue;
-        // tiled problems at l: colour tiles, transfer tiles, lists
-        std::vector<std::array<int, 3>> ecol, edown;
-        std::vector<int> gcol, gdown, cbox;
-        std::vector<GhostCopy> face[2], fullc;
+        // tiled problems at l: colour tiles, transfer tiles, ghost sets
+        std::vector<Tile> tcol, tdown;
+        std::vector<int> cbox_full(rbs[l].size(), -1);
+        std::vector<GhostSet> face[2], fullc;
         std::vector<ZeroRange> zr;
         B.push = true;
+        B.mface = B.mfullc = B.zmax = 0;
         for (int s : b->members) {
             const Problem& p = *b->slots[s];
-            if ((int)l >= p.cs) continue;
-            const PLevel& v = p.L[l];
-            const auto ce = colour_extents(v.boxes);
-            const auto de = coarse_extents(v.boxes, v.dom, -1);
-            for (size_t q = 0; q < v.boxes.size(); ++q) {
-                ecol.push_back(ce[q]);
-                gcol.push_back(first[l][s] + (int)q);
-                edown.push_back(de[q]);
-                gdown.push_back(first[l][s] + (int)q);
-                cbox.push_back(first[l + 1][s] + v.cbox[q]);
-            }
+            if ((int)l >= p.plan->cs) continue;
+            const PlanLevel& v = p.plan->L[l];
+            const int f0 = first[l][s];
+            if (l == 0) segslot.push_back(s);
+            for (Tile t : v.tcol) { t.box += f0; tcol.push_back(t); }
+            for (Tile t : v.tdown) { t.box += f0; tdown.push_back(t); }
+            if (l == 0) tstart.push_back((int)tcol.size());
+            for (size_t q = 0; q < v.boxes.size(); ++q) cbox_full[f0 + q] = first[l + 1][s] + v.cbox[q];
             B.push = B.push && v.push;
-            for (int c = 0; c < 2; ++c) face[c].insert(face[c].end(), v.face[c].begin(), v.face[c].end());
-            const PLevel& w = p.L[l + 1];
-            fullc.insert(fullc.end(), w.full.begin(), w.full.end());
-            zr.push_back(ZeroRange{w.off, w.nelem, s, 0});
+            for (int c = 0; c < 2; ++c) face[c].push_back(GhostSet{v.face[c].p, (long long)v.face[c].n, p.off, s, 0});
+            B.mface = std::max(B.mface, (long long)std::max(v.face[0].n, v.face[1].n));
+            const PlanLevel& w = p.plan->L[l + 1];
+            fullc.push_back(GhostSet{w.full.p, (long long)w.full.n, p.off, s, 0});
+            B.mfullc = std::max(B.mfullc, (long long)w.full.n);
+            zr.push_back(ZeroRange{p.off + w.off, w.nelem, s, 0});
             B.zmax = std::max(B.zmax, w.nelem);
         }
-        TileSet tc = make_tiles(ecol, zc);
-        if (tc.sh.lz == 0) tc = make_tiles(ecol, zcp);
-        for (auto& t : tc.tiles) t.box = gcol[t.box];
-        TileSet td = make_tiles(edown, zc);
-        std::vector<int> cb(td.tiles.size());
-        // the transfer kernels index cbox by the fine box of the tile
-        std::vector<int> cbox_full(rbs[l].size(), -1);
-        for (size_t q = 0; q < gdown.size(); ++q) cbox_full[gdown[q]] = cbox[q];
-        for (auto& t : td.tiles) t.box = gdown[t.box];
-        B.tcol.upload(tc.tiles);
-        B.ntcol = (int)tc.tiles.size();
-        B.shcol = tc.sh;
-        B.tdown.upload(td.tiles);
-        B.ntdown = (int)td.tiles.size();
-        B.shdown = td.sh;
-        B.cbox.upload(cbox_full);
-        if (!B.push)
-            for (int c = 0; c < 2; ++c) { B.face[c].upload(face[c]); B.nface[c] = (long long)face[c].size(); }
-        B.fullc.upload(fullc);
-        B.nfullc = (long long)fullc.size();
-        B.zr.upload(zr);
-        B.nzr = (int)zr.size();
-        if (l == 0) {
-            // per-problem segments of the level-0 tiles (tiles run problem-major)
-            int cur = -1;
-            for (size_t t = 0; t < tc.tiles.size(); ++t) {
-                const int s = rbs[0][tc.tiles[t].box].pid;
-                if (s != cur) {
-                    if (cur >= 0) tstart.push_back((int)t);
-                    segslot.push_back(s);
-                    cur = s;
-                }
-            }
-            tstart.push_back((int)tc.tiles.size());
+        B.tcol.assign(tcol);
+        B.ntcol = (int)tcol.size();
+        B.tdown.assign(tdown);
+        B.ntdown = (int)tdown.size();
+        B.cbox.assign(cbox_full);
+        if (!B.push) {
+            for (int c = 0; c < 2; ++c) B.face[c].assign(face[c]);
+            B.nface = (int)face[0].size();
         }
+        B.fullc.assign(fullc);
+        B.nfullc = (int)fullc.size();
+        B.zr.assign(zr);
+        B.nzr = (int)zr.size();
     }
-    b->tstart.upload(tstart);
-    b->segslot.upload(segslot);
+    b->tstart.assign(tstart);
+    b->segslot.assign(segslot);
     b->nseg = (int)segslot.size();
-    b->partials.alloc(3 * (size_t)std::max(1, b->lev[0].ntcol) + 8);
+    b->partials.reserve(3 * (size_t)std::max(1, b->lev[0].ntcol) + 8);
     // level-0 ranges (the FP32 correction starts from zero every cycle)
     std::vector<ZeroRange> z0;
     b->z0max = 0;
     for (int s : b->members) {
-        const PLevel& v = b->slots[s]->L[0];
-        z0.push_back(ZeroRange{v.off, v.nelem, s, 0});
+        const Problem& p = *b->slots[s];
+        const PlanLevel& v = p.plan->L[0];
+        z0.push_back(ZeroRange{p.off + v.off, v.nelem, s, 0});
         b->z0max = std::max(b->z0max, v.nelem);
     }
-    b->z0.upload(z0);
+    b->z0.assign(z0);
     b->nz0 = (int)z0.size();
     // coefficient tables by slot
     if (b->var)
@@ -506,26 +522,26 @@ void rebuild(bxmg_batch_s* b) {
                 std::vector<FaceArrays<double>> t(b->max_slots);
                 std::memset(t.data(), 0, t.size() * sizeof(t[0]));
                 for (int s : b->members)
-                    if (l < b->slots[s]->L.size()) t[s] = b->slots[s]->f64[l]->view;
-                B.fat64.upload(t);
+                    if (l < b->slots[s]->plan->L.size()) t[s] = face_view<double>(*b->slots[s], b->fa64.p, l);
+                B.fat64.assign(t);
             } else {
                 std::vector<FaceArrays<float>> t(b->max_slots);
                 std::memset(t.data(), 0, t.size() * sizeof(t[0]));
                 for (int s : b->members)
-                    if (l < b->slots[s]->L.size()) t[s] = b->slots[s]->f32[l]->view;
-                B.fat32.upload(t);
+                    if (l < b->slots[s]->plan->L.size()) t[s] = face_view<float>(*b->slots[s], b->fa32.p, l);
+                B.fat32.assign(t);
             }
         }
     // fused coarse cycles
-    b->cc64_host.clear();
-    b->cc32_host.clear();
-    for (int s : b->members) {
-        const Problem& p = *b->slots[s];
-        if (b->prec == 0) b->cc64_host.push_back(coarse_desc<double>(b, p, b->u64.p, b->f64.p, b->var ? &p.f64 : nullptr));
-        else b->cc32_host.push_back(coarse_desc<float>(b, p, b->u32.p, b->f32.p, b->var ? &p.f32 : nullptr));
+    if (b->prec == 0) {
+        std::vector<CoarseCycle<double>> cc;
+        for (int s : b->members) cc.push_back(coarse_desc<double>(b, *b->slots[s], b->u64.p, b->f64.p, b->fa64.p));
+        b->cc64.assign(cc);
+    } else {
+        std::vector<CoarseCycle<float>> cc;
+        for (int s : b->members) cc.push_back(coarse_desc<float>(b, *b->slots[s], b->u32.p, b->f32.p, b->fa32.p));
+        b->cc32.assign(cc);
     }
-    if (b->prec == 0) b->cc64.upload(b->cc64_host);
-    else b->cc32.upload(b->cc32_host);
     b->ncc = (int)b->members.size();
 }
 
@@ -552,29 +568,30 @@ template <class T>
 const FaceArrays<T>* level_fat(bxmg_batch_s* b, size_t l);
 template <>
 const FaceArrays<double>* level_fat<double>(bxmg_batch_s* b, size_t l) {
-    return (b->var && l >= 1) ? b->lev[l].fat64.p : nullptr;
+    return (b->var && l >= 1) ? b->lev[l].fat64.p() : nullptr;
 }
 template <>
 const FaceArrays<float>* level_fat<float>(bxmg_batch_s* b, size_t l) {
-    return (b->var && l >= 1) ? b->lev[l].fat32.p : nullptr;
+    return (b->var && l >= 1) ? b->lev[l].fat32.p() : nullptr;
 }
 template <class T>
 const CoarseCycle<T>* coarse_descs(bxmg_batch_s* b);
 template <>
-const CoarseCycle<double>* coarse_descs<double>(bxmg_batch_s* b) { return b->cc64.p; }
+const CoarseCycle<double>* coarse_descs<double>(bxmg_batch_s* b) { return b->cc64.p(); }
 template <>
-const CoarseCycle<float>* coarse_descs<float>(bxmg_batch_s* b) { return b->cc32.p; }
+const CoarseCycle<float>* coarse_descs<float>(bxmg_batch_s* b) { return b->cc32.p(); }
 
 Grid level_grid(bxmg_batch_s* b, size_t l) {
     BLevel& B = b->lev[l];
-    Grid g{B.rb.p, B.tcol.p, B.ntcol, B.shcol, B.push ? 1 : 0, b->active.p, B.flip, B.res};
+    Grid g{B.rb.p(), B.tcol.p(), B.ntcol, B.push ? 1 : 0, b->active.p, B.flip, B.res};
     B.flip ^= 1;
     return g;
 }
 
 XGrid level_xgrid(bxmg_batch_s* b, size_t l) {
     BLevel& B = b->lev[l];
-    XGrid x{B.rb.p, b->lev[l + 1].rb.p, B.cbox.p, B.tdown.p, B.ntdown, B.shdown, B.push ? 1 : 0, b->active.p, B.flip};
+    XGrid x{B.rb.p(), b->lev[l + 1].rb.p(), B.cbox.p(), B.tdown.p(), B.ntdown, B.push ? 1 : 0,
+            b->active.p, B.flip, (B.res && b->lev[l + 1].res) ? 1 : 0};
     B.flip ^= 1;
     return x;
 }
@@ -585,7 +602,8 @@ void b_smooth(bxmg_batch_s* b, hipStream_t s, size_t l, int nsweeps) {
     T* u = arena_u<T>(b);
     for (int k = 0; k < nsweeps; ++k)
         for (int c = 0; c < 2; ++c) {
-            if (!B.push) HIPCHK(launch_fill_rb(s, u, sizeof(T) == 4, B.face[c ^ 1].p, B.nface[c ^ 1]));
+            if (!B.push)
+                HIPCHK(launch_fill_sets(s, u, sizeof(T) == 4, B.face[c ^ 1].p(), B.nface, B.mface, b->active.p));
             HIPCHK(launch_gs<T>(s, level_grid(b, l), u, arena_f<T>(b), arena_beta<T>(b, l), level_fat<T>(b, l), c));
         }
 }
@@ -599,17 +617,18 @@ void b_vcycle(bxmg_batch_s* b, hipStream_t s) {
         BLevel& B = b->lev[l];
         b_smooth<T>(b, s, l, b->P.nu1);
         if (!B.push) {
-            HIPCHK(launch_fill_rb(s, u, f32, B.face[0].p, B.nface[0]));
-            HIPCHK(launch_fill_rb(s, u, f32, B.face[1].p, B.nface[1]));
+            HIPCHK(launch_fill_sets(s, u, f32, B.face[0].p(), B.nface, B.mface, b->active.p));
+            HIPCHK(launch_fill_sets(s, u, f32, B.face[1].p(), B.nface, B.mface, b->active.p));
         }
         HIPCHK(launch_resid_restrict<T>(s, level_xgrid(b, l), u, f, arena_beta<T>(b, l), level_fat<T>(b, l), f));
-        HIPCHK(launch_zero_ranges<T>(s, u, B.zr.p, B.nzr, B.zmax, b->active.p));
+        HIPCHK(launch_zero_ranges<T>(s, u, B.zr.p(), B.nzr, B.zmax, b->active.p));
     }
     HIPCHK(launch_coarse_cycle<T>(s, coarse_descs<T>(b), b->ncc, b->active.p, b->var));
     for (int l = b->lmax - 1; l >= 0; --l) {
         BLevel& B = b->lev[l];
-        HIPCHK(launch_fill_rb(s, u, f32, B.fullc.p, B.nfullc));
-        HIPCHK(launch_prolong<T>(s, level_grid(b, l), b->lev[l + 1].rb.p, B.cbox.p, u, u, b->P.prolong));
+        HIPCHK(launch_fill_sets(s, u, f32, B.fullc.p(), B.nfullc, B.mfullc, b->active.p));
+        HIPCHK(launch_prolong<T>(s, level_grid(b, l), b->lev[l + 1].rb.p(), B.cbox.p(), u, u, b->P.prolong,
+                                 b->lev[l + 1].res));
         b_smooth<T>(b, s, l, b->P.nu2);
     }
 }
@@ -620,17 +639,17 @@ void enqueue_cycle(bxmg_batch_s* b, hipStream_t s) {
     const double* beta0 = b->var ? b->b64.p : nullptr;
     if (b->prec == 0)
         HIPCHK(launch_resid<double, double>(s, level_grid(b, 0), b->u64.p, b->f64.p, beta0, nullptr, (double*)nullptr,
-                                            b->partials.p));
+                                            b->partials.p()));
     else
         HIPCHK(launch_resid<double, float>(s, level_grid(b, 0), b->u64.p, b->f64.p, beta0, nullptr, b->f32.p,
-                                           b->partials.p));
-    HIPCHK(launch_norm_seg(s, b->partials.p, b->tstart.p, b->segslot.p, b->nseg, b->active.p, b->norms.p));
-    HIPCHK(launch_batch_check(s, b->d_members.p, (int)b->members.size(), b->norms.p, b->st.p, b->active.p,
+                                           b->partials.p()));
+    HIPCHK(launch_norm_seg(s, b->partials.p(), b->tstart.p(), b->segslot.p(), b->nseg, b->active.p, b->norms.p));
+    HIPCHK(launch_batch_check(s, b->d_members.p(), (int)b->members.size(), b->norms.p, b->st.p, b->active.p,
                               b->hist.p, b->hist_l2.p, b->nactive.p));
     if (b->prec == 0) {
         b_vcycle<double>(b, s);
     } else {
-        HIPCHK(launch_zero_ranges<float>(s, b->u32.p, b->z0.p, b->nz0, b->z0max, b->active.p));
+        HIPCHK(launch_zero_ranges<float>(s, b->u32.p, b->z0.p(), b->nz0, b->z0max, b->active.p));
         b_vcycle<float>(b, s);
         HIPCHK(launch_add_f32(s, level_grid(b, 0), b->u64.p, b->u32.p));
     }
@@ -639,56 +658,56 @@ void enqueue_cycle(bxmg_batch_s* b, hipStream_t s) {
 // -------------------------------------------------------- finish / release
 void release_problem(bxmg_batch_s* b, int s) {
     Problem& p = *b->slots[s];
-    if (p.len > 0) b->ranges.give(p.off, p.len);
-    b->face_used -= p.face_bytes;
+    b->ranges.give(p.off, p.plan->len);
+    if (b->var) b->franges.give(p.foff, p.plan->face_len);
     b->slots[s].reset();
+    b->h_active[s] = 0;
     b->free_slots.push_back(s);
 }
 
-// Writes the solution of a stopped problem into its phi and queues its result.
-void grow(DevBuf<double>& d, size_t n) {
-    if (d.n < n) d.alloc(n);
+// Enqueues the conversion of a stopped problem's solution into its phi and
+// the copy of its history (convert == false: phi is left as it was).
+void retire_enqueue(bxmg_batch_s* b, int s, bool convert) {
+    const Problem& p = *b->slots[s];
+    const GeoPlan& P = *p.plan;
+    hipStream_t st = b->stream;
+    HIPCHK(hipMemcpyAsync(b->h_hist + (size_t)s * 2 * kHist, b->hist.p + (size_t)s * kHist, kHist * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(b->h_hist + (size_t)s * 2 * kHist + kHist, b->hist_l2.p + (size_t)s * kHist,
+                          kHist * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (!convert) return;
+    const Grid g0 = P.grid0();
+    if (P.per[0] && P.per[1] && P.per[2]) {
+        b->scratch.reserve(3 * (size_t)P.nt0 + 8);
+        HIPCHK(launch_mean_sub(st, g0, b->u64.p + p.off, b->scratch.p()));
+    }
+    HIPCHK(launch_rb_to_fab(st, g0, b->u64.p + p.off, (double*)p.phi->data, p.phi->d_fboxes.p));
 }
 
-// convert == false: phi is left as it was (non-finite right-hand side)
-void finish_problem(bxmg_batch_s* b, int s, hipStream_t st, bool convert) {
-    Problem& p = *b->slots[s];
+// After the stream drained: the result record, then the slot and ranges go back.
+void retire_finish(bxmg_batch_s* b, int s) {
+    const Problem& p = *b->slots[s];
     const BatchSlot S = b->h_st[s];
     Done d;
     d.id = p.id;
     std::memset(&d.info, 0, sizeof d.info);
     d.info.status = S.status;
     d.info.cycles = S.cycles;
-    d.info.levels = (int)p.L.size();
+    d.info.levels = (int)p.plan->L.size();
     d.info.nhist = std::min(S.nhist, kHist);
-    d.info.f_inf = p.f_inf;
+    d.info.f_inf = (S.status == kStatusNonFinite && S.nhist == 0) ? NAN : S.fnorm;
+    const double* h = b->h_hist + (size_t)s * 2 * kHist;
+    for (int k = 0; k < d.info.nhist; ++k) {
+        d.info.hist[k] = h[k];
+        d.info.hist_l2[k] = h[kHist + k];
+    }
     if (d.info.nhist > 0) {
-        HIPCHK(hipMemcpy(d.info.hist, b->hist.p + (size_t)s * kHist, d.info.nhist * sizeof(double),
-                         hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(d.info.hist_l2, b->hist_l2.p + (size_t)s * kHist, d.info.nhist * sizeof(double),
-                         hipMemcpyDeviceToHost));
         d.info.rel_resid_inf = d.info.hist[d.info.nhist - 1];
         d.info.resid_l2 = d.info.hist_l2[d.info.nhist - 1];
-    }
-    if (convert) {
-        const Grid g0 = p.grid0();
-        if (p.per[0] && p.per[1] && p.per[2]) {
-            grow(b->scratch, 3 * (size_t)p.nt0 + 8);
-            HIPCHK(launch_mean_sub(st, g0, b->u64.p, b->scratch.p));
-        }
-        HIPCHK(launch_rb_to_fab(st, g0, b->u64.p, (double*)p.phi->data, p.phi->d_fboxes.p));
-        HIPCHK(hipStreamSynchronize(st));
     }
     d.info.seconds = std::chrono::duration<double>(Clock::now() - p.t_add).count();
     b->done.push_back(d);
     release_problem(b, s);
-}
-
-size_t arena_bytes_per_elem(int prec, bool var) {
-    size_t e = 16;              // u, f FP64
-    if (prec == 1) e += 8;      // u, f FP32
-    if (var) e += prec ? 12 : 8;  // beta FP64 (+ FP32)
-    return e;
 }
 
 }  // namespace
@@ -715,36 +734,43 @@ bxmg_status bxmg_batch_create(bxmg_ctx ctx, size_t hbm_budget_bytes, int32_t max
     const size_t per = arena_bytes_per_elem(b->prec, b->var);
     const size_t fes = b->var ? (b->prec ? 4 : 8) : 0;
     const double face_share = b->var ? (double)fes * 0.45 / (double)(per + fes * 0.45) : 0.0;
-    b->face_budget = (size_t)(face_share * (double)hbm_budget_bytes);
-    long long cap = (long long)((hbm_budget_bytes - b->face_budget) / per);
+    const size_t face_bytes = (size_t)(face_share * (double)hbm_budget_bytes);
+    long long cap = (long long)((hbm_budget_bytes - face_bytes) / per);
     cap = std::min<long long>(cap, 0x7fffffffLL) / 64 * 64;
     if (cap < 64) return fail(BXMG_EINVAL, "batch_create: budget too small");
     b->cap = cap;
-    b->arena_bytes = (size_t)cap * per;
+    b->fcap = b->var ? (long long)(face_bytes / fes) / 64 * 64 : 0;
     std::lock_guard<std::mutex> lock(ctx->mu);
     try {
         HIPCHK(hipSetDevice(ctx->device));
         HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&b->caller_ready, hipEventDisableTiming));
         b->u64.alloc(cap);
         b->f64.alloc(cap);
         if (b->prec == 1) { b->u32.alloc(cap); b->f32.alloc(cap); }
-        if (b->var) { b->b64.alloc(cap); if (b->prec == 1) b->b32.alloc(cap); }
+        if (b->var) {
+            b->b64.alloc(cap);
+            if (b->prec == 1) { b->b32.alloc(cap); b->fa32.alloc(std::max<long long>(b->fcap, 64)); }
+            else b->fa64.alloc(std::max<long long>(b->fcap, 64));
+        }
         b->active.alloc(max_problems);
         HIPCHK(hipMemset(b->active.p, 0, max_problems * sizeof(int)));
         b->nactive.alloc(1);
         b->st.alloc(max_problems);
         b->norms.alloc(3 * (size_t)max_problems);
+        b->fn3.alloc(3 * (size_t)max_problems);
         b->hist.alloc((size_t)max_problems * kHist);
         b->hist_l2.alloc((size_t)max_problems * kHist);
         HIPCHK(hipHostMalloc((void**)&b->h_active, max_problems * sizeof(int)));
-        HIPCHK(hipHostMalloc((void**)&b->h_nactive, sizeof(int)));
         HIPCHK(hipHostMalloc((void**)&b->h_st, max_problems * sizeof(BatchSlot)));
+        HIPCHK(hipHostMalloc((void**)&b->h_hist, (size_t)max_problems * 2 * kHist * sizeof(double)));
         std::memset(b->h_active, 0, max_problems * sizeof(int));
     } catch (HipError& e) {
         return fail(e.e == hipErrorOutOfMemory ? BXMG_ENOMEM : BXMG_EDEVICE,
                     std::string("batch_create: ") + hipGetErrorString(e.e));
     }
     b->ranges.init(cap);
+    b->franges.init(b->fcap);
     b->slots.resize(max_problems);
     for (int s = 0; s < max_problems; ++s) b->free_slots.push_back(s);
     *out = b.release();
@@ -761,14 +787,14 @@ void bxmg_batch_destroy(bxmg_batch b) {
 
 size_t bxmg_batch_footprint(bxmg_batch b, bxmg_boxarray ba) {
     if (!b || !ba) return 0;
-    Problem p;
-    long long len = 0;
+    GeoPlan P;
     try {
-        if (!plan_problem(ba, 1.0, p, &len, nullptr)) return 0;
+        if (!plan_geometry(ba, 1.0, P, nullptr)) return 0;
     } catch (std::exception&) {
         return 0;
     }
-    return (size_t)len * arena_bytes_per_elem(b->prec, b->var) + (b->var ? face_bytes_of(p, b->prec ? 4 : 8) : 0);
+    return (size_t)P.len * arena_bytes_per_elem(b->prec, b->var) +
+           (b->var ? (size_t)P.face_len * (b->prec ? 4 : 8) : 0);
 }
 
 bxmg_status bxmg_batch_add(bxmg_batch b, bxmg_multifab phi, bxmg_multifab rhs, bxmg_multifab beta, double rel_tol,
@@ -785,90 +811,85 @@ bxmg_status bxmg_batch_add(bxmg_batch b, bxmg_multifab phi, bxmg_multifab rhs, b
     if (phi->ctx != b->ctx) return fail(BXMG_EINVAL, "batch_add: phi belongs to another context");
     std::lock_guard<std::mutex> lock(b->ctx->mu);
     if (b->inflight) return fail(BXMG_EINVAL, "batch_add: collect the launched cycles first");
-    auto p = std::make_unique<Problem>();
     const double h = (b->P.dx > 0) ? b->P.dx : 1.0 / ba->dom.n(0);
-    long long len = 0;
-    std::string why;
-    try {
-        if (!plan_problem(ba, h, *p, &len, &why)) return fail(BXMG_EINVAL, "batch_add: " + why);
-    } catch (std::exception& e) {
-        return fail(BXMG_EINVAL, std::string("batch_add: ") + e.what());
-    }
-    const size_t fbytes = b->var ? face_bytes_of(*p, b->prec ? 4 : 8) : 0;
-    if (b->free_slots.empty()) return fail(BXMG_EBUSY, "batch_add: every slot is taken");
-    if (b->face_used + fbytes > b->face_budget) return fail(BXMG_EBUSY, "batch_add: coefficient storage is full");
-    if (len > b->cap) return fail(BXMG_EINVAL, "batch_add: the problem is larger than the whole arena");
-    const long long base = b->ranges.take(len);
-    if (base < 0) return fail(BXMG_EBUSY, "batch_add: the arena has no free range of this size");
-    const int slot = b->free_slots.front();
-    p->slot = slot;
-    p->len = len;
-    p->id = b->next_id;
-    p->phi = phi;
-    p->rhs = rhs;
-    p->beta = beta;
-    p->rel_tol = rel_tol > 0 ? rel_tol : b->P.rel_tol;
-    p->t_add = Clock::now();
     hipStream_t s = b->stream;
     try {
         HIPCHK(hipSetDevice(b->ctx->device));
-        HIPCHK(hipStreamSynchronize(b->ctx->stream));  // the caller's writes to phi, rhs, beta
-        place_problem(*p, base, b->var);
-        problem_tiles(*p, b->ctx->zc, b->ctx->zc_planes, b->ctx->res, b->var);
-        const Grid g0 = p->grid0();
-        const PLevel& L0 = p->L[0];
-        HIPCHK(launch_fab_to_rb(s, g0, (const double*)phi->data, phi->d_fboxes.p, b->u64.p, false));
-        HIPCHK(launch_fab_to_rb(s, g0, (const double*)rhs->data, rhs->d_fboxes.p, b->f64.p, false));
+        std::string why;
+        std::shared_ptr<GeoPlan> plan;
+        try {
+            plan = get_plan(b, ba, h, &why);
+        } catch (std::exception& e) {
+            return fail(BXMG_EINVAL, std::string("batch_add: ") + e.what());
+        }
+        if (!plan) return fail(BXMG_EINVAL, "batch_add: " + why);
+        const GeoPlan& P = *plan;
+        if (P.len > b->cap || (b->var && P.face_len > b->fcap))
+            return fail(BXMG_EINVAL, "batch_add: the problem is larger than the whole arena");
+        if (b->free_slots.empty()) return fail(BXMG_EBUSY, "batch_add: every slot is taken");
+        const long long base = b->ranges.take(P.len);
+        if (base < 0) return fail(BXMG_EBUSY, "batch_add: the arena has no free range of this size");
+        long long fbase = 0;
         if (b->var) {
-            HIPCHK(launch_fab_to_rb(s, g0, (const double*)beta->data, beta->d_fboxes.p, b->b64.p, false));
-            p->face_bytes = fbytes;
+            fbase = b->franges.take(P.face_len);
+            if (fbase < 0) {
+                b->ranges.give(base, P.len);
+                return fail(BXMG_EBUSY, "batch_add: coefficient storage is full");
+            }
+        }
+        const int slot = b->free_slots.front();
+        b->free_slots.pop_front();
+        auto p = std::make_unique<Problem>();
+        p->slot = slot;
+        p->id = b->next_id++;
+        p->phi = phi;
+        p->plan = plan;
+        p->off = base;
+        p->foff = fbase;
+        p->rel_tol = rel_tol > 0 ? rel_tol : b->P.rel_tol;
+        p->t_add = Clock::now();
+        b->slots[slot] = std::move(p);
+        b->h_active[slot] = 1;  // until the device says otherwise
+        b->dirty = true;
+        *id = b->slots[slot]->id;
+        const Problem& q = *b->slots[slot];
+        // the caller's writes to phi, rhs and beta come first
+        HIPCHK(hipEventRecord(b->caller_ready, b->ctx->stream));
+        HIPCHK(hipStreamWaitEvent(s, b->caller_ready, 0));
+        const Grid g0 = P.grid0();
+        double* u = b->u64.p + base;
+        double* f = b->f64.p + base;
+        HIPCHK(launch_fab_to_rb(s, g0, (const double*)phi->data, phi->d_fboxes.p, u, false));
+        HIPCHK(launch_fab_to_rb(s, g0, (const double*)rhs->data, rhs->d_fboxes.p, f, false));
+        if (b->var) {
+            double* bt = b->b64.p + base;
+            HIPCHK(launch_fab_to_rb(s, g0, (const double*)beta->data, beta->d_fboxes.p, bt, false));
             if (b->prec == 0) {
-                alloc_faces<double>(*p, p->f64);
-                setup_faces<double>(s, *p, p->f64, b->b64.p);
+                setup_faces<double>(s, q, bt, b->fa64.p);
             } else {
-                alloc_faces<float>(*p, p->f32);
-                HIPCHK(launch_fill_rb(s, b->b64.p, false, p->full_even0.p, (long long)p->full_even0.n));
-                HIPCHK(launch_cast_f32(s, b->b64.p + L0.off, b->b32.p + L0.off, L0.nelem));
-                setup_faces<float>(s, *p, p->f32, b->b32.p);
+                HIPCHK(launch_fill_rb(s, bt, false, P.full_even0.p, (long long)P.full_even0.n));
+                HIPCHK(launch_cast_f32(s, bt + P.L[0].off, b->b32.p + base + P.L[0].off, P.L[0].nelem));
+                setup_faces<float>(s, q, b->b32.p + base, b->fa32.p);
             }
         }
         // ghosts of the converted guess (later producers keep them current)
-        HIPCHK(launch_fill_rb(s, b->u64.p, false, p->face0[0].p, (long long)p->face0[0].n));
-        HIPCHK(launch_fill_rb(s, b->u64.p, false, p->face0[1].p, (long long)p->face0[1].n));
-        grow(b->scratch, 3 * (size_t)p->nt0 + 8);
-        HIPCHK(launch_field_norm(s, g0, b->f64.p, b->scratch.p));
-        HIPCHK(launch_norm_final(s, b->scratch.p, p->nt0, b->scratch.p + 3 * (size_t)p->nt0));
-        double fn[3];
-        HIPCHK(hipMemcpyAsync(fn, b->scratch.p + 3 * (size_t)p->nt0, sizeof fn, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(launch_fill_rb(s, u, false, P.L[0].face[0].p, (long long)P.L[0].face[0].n));
+        HIPCHK(launch_fill_rb(s, u, false, P.L[0].face[1].p, (long long)P.L[0].face[1].n));
+        // ||f||_inf and the slot state, decided on the device
+        b->scratch.reserve(3 * (size_t)P.nt0 + 8);
+        HIPCHK(launch_field_norm(s, g0, f, b->scratch.p()));
+        HIPCHK(launch_norm_final(s, b->scratch.p(), P.nt0, b->fn3.p + 3 * (size_t)slot));
         BatchSlot S{};
-        S.fnorm = fn[0];
-        S.rel_tol = p->rel_tol;
+        S.rel_tol = q.rel_tol;
         S.abs_tol = b->P.abs_tol;
         S.max_cycles = b->P.max_cycles;
         S.fixed_cycles = b->P.fixed_cycles;
-        p->f_inf = fn[2] > 0 ? NAN : fn[0];
-        int act = 1;
-        if (fn[2] > 0) { S.status = BXMG_ENONFINITE; act = 0; }
-        else if (!(fn[0] > 0.0)) act = 0;  // f == 0: u stays the guess
-        HIPCHK(hipMemcpy(b->st.p + slot, &S, sizeof S, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(b->active.p + slot, &act, sizeof act, hipMemcpyHostToDevice));
-        b->free_slots.pop_front();
-        b->face_used += p->face_bytes;
-        b->slots[slot] = std::move(p);
-        b->h_active[slot] = act;
-        b->h_st[slot] = S;
-        ++b->next_id;
-        *id = b->slots[slot]->id;
-        if (act) b->dirty = true;
-        else finish_problem(b, slot, s, fn[2] == 0);
+        b->h_st[slot] = S;  // pinned: the source of the copy below
+        HIPCHK(hipMemcpyAsync(b->st.p + slot, b->h_st + slot, sizeof S, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_batch_admit(s, b->fn3.p + 3 * (size_t)slot, b->st.p, b->active.p, slot));
     } catch (HipError& e) {
-        if (!b->slots[slot]) b->ranges.give(base, len);
         return fail(e.e == hipErrorOutOfMemory ? BXMG_ENOMEM : BXMG_EDEVICE,
                     std::string("batch_add: ") + e.where + ": " + hipGetErrorString(e.e));
-    } catch (std::exception& e) {
-        if (!b->slots[slot]) b->ranges.give(base, len);
-        return fail(BXMG_EINVAL, std::string("batch_add: ") + e.what());
     }
     return BXMG_OK;
 }
@@ -879,24 +900,32 @@ static bxmg_status batch_launch(bxmg_batch b, int32_t ncycles) {
     hipStream_t s = b->stream;
     try {
         HIPCHK(hipSetDevice(b->ctx->device));
-        if (b->dirty) rebuild(b);
-        if (b->members.empty()) return BXMG_OK;
-        if (b->use_graph && !b->exec) {
-            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            try {
-                enqueue_cycle(b, s);
-            } catch (HipError&) {
-                hipGraph_t g = nullptr;
-                (void)hipStreamEndCapture(s, &g);
-                if (g) (void)hipGraphDestroy(g);
-                throw;
-            }
-            HIPCHK(hipStreamEndCapture(s, &b->graph));
-            HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        if (b->dirty) {
+            rebuild(b);
+            b->stable = 0;
         }
-        for (int c = 0; c < ncycles; ++c) {
-            if (b->exec) HIPCHK(hipGraphLaunch(b->exec, s));
-            else enqueue_cycle(b, s);
+        if (!b->members.empty()) {
+            // capture once the running set has stayed the same for a launch:
+            // while problems come and go every step, stage-by-stage launches
+            // cost less than a capture per step
+            if (b->use_graph && !b->exec && b->stable >= 1) {
+                HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                try {
+                    enqueue_cycle(b, s);
+                } catch (HipError&) {
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(s, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                HIPCHK(hipStreamEndCapture(s, &b->graph));
+                HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+            }
+            for (int c = 0; c < ncycles; ++c) {
+                if (b->exec) HIPCHK(hipGraphLaunch(b->exec, s));
+                else enqueue_cycle(b, s);
+            }
+            ++b->stable;
         }
         HIPCHK(hipMemcpyAsync(b->h_active, b->active.p, b->max_slots * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(b->h_st, b->st.p, b->max_slots * sizeof(BatchSlot), hipMemcpyDeviceToHost, s));
@@ -914,11 +943,17 @@ static bxmg_status batch_collect(bxmg_batch b, int32_t* nrunning) {
         if (b->inflight) {
             HIPCHK(hipStreamSynchronize(s));
             b->inflight = false;
-            for (int m : b->members)
-                if (b->slots[m] && !b->h_active[m]) {
-                    finish_problem(b, m, s, true);
-                    b->dirty = true;
-                }
+            std::vector<int> stopped;
+            for (int m = 0; m < b->max_slots; ++m)
+                if (b->slots[m] && !b->h_active[m]) stopped.push_back(m);
+            if (!stopped.empty()) {
+                // a right-hand side that was not finite leaves phi untouched
+                for (int m : stopped)
+                    retire_enqueue(b, m, !(b->h_st[m].status == kStatusNonFinite && b->h_st[m].nhist == 0));
+                HIPCHK(hipStreamSynchronize(s));
+                for (int m : stopped) retire_finish(b, m);
+                b->dirty = true;
+            }
         }
     } catch (HipError& e) {
         b->inflight = false;
@@ -986,7 +1021,6 @@ bxmg_status bxmg_batch_remove(bxmg_batch b, int64_t id) {
             } catch (HipError& e) {
                 return fail(BXMG_EDEVICE, std::string("batch_remove: ") + hipGetErrorString(e.e));
             }
-            b->h_active[s] = 0;
             release_problem(b, s);
             b->dirty = true;
             return BXMG_OK;
@@ -999,9 +1033,9 @@ bxmg_status bxmg_batch_stats(bxmg_batch b, size_t* bytes_used, size_t* bytes_bud
     if (!b) return fail(BXMG_EINVAL, "batch_stats: NULL batch");
     std::lock_guard<std::mutex> lock(b->ctx->mu);
     const size_t per = arena_bytes_per_elem(b->prec, b->var);
-    long long free_el = 0;
-    for (auto& r : b->ranges.free) free_el += r.second;
-    if (bytes_used) *bytes_used = (size_t)(b->cap - free_el) * per + b->face_used;
+    if (bytes_used)
+        *bytes_used = (size_t)(b->cap - b->ranges.free_total()) * per +
+                      (b->var ? (size_t)(b->fcap - b->franges.free_total()) * (b->prec ? 4 : 8) : 0);
     if (bytes_budget) *bytes_budget = b->budget;
     if (nrunning) {
         int n = 0;

@@ -64,23 +64,20 @@ struct Level {
     // colour-cell tiles (valid cells, one colour per thread per plane)
     DevBuf<Tile> tcol;
     int ntcol = 0;
-    TileShape shcol{};
     // transfer tiles to level + 1 (coarse cells of every box)
     DevBuf<Tile> tdown;
     int ntdown = 0;
-    TileShape shdown{};
     DevBuf<int> cbox;
     // coefficient setup tiles (coarse faces anchored in every box), level 0
     DevBuf<Tile> tface[3];
     int ntface[3] = {0, 0, 0};
-    TileShape shface[3]{};
     GhostList face[2];  // face ghosts of colour c: exchange + Dirichlet
     GhostList full;     // every ghost: exchange + Dirichlet
     GhostList full_even;  // every ghost: exchange + even reflection (cell beta)
     bool push = false;    // producers refresh the face ghosts they mirror
     mutable int flip = 0; // direction of the next sweep over the level's tiles
     bool res = false;     // 32-bit buffer addressing of the boxes
-    Grid grid() const { return Grid{d_rb.p, tcol.p, ntcol, shcol, push ? 1 : 0, nullptr, 0, res ? 1 : 0}; }
+    Grid grid() const { return Grid{d_rb.p, tcol.p, ntcol, push ? 1 : 0, nullptr, 0, res ? 1 : 0}; }
     // grid of the next sweep in the alternating order (see tile_index)
     Grid walk() const {
         Grid g = grid();
@@ -116,7 +113,8 @@ struct Hier {
     XGrid xgrid(size_t l) const {
         const Level& F = *L[l];
         const Level& C = *L[l + 1];
-        return XGrid{F.d_rb.p, C.d_rb.p, F.cbox.p, F.tdown.p, F.ntdown, F.shdown, F.push ? 1 : 0, nullptr, 0};
+        return XGrid{F.d_rb.p, C.d_rb.p, F.cbox.p, F.tdown.p, F.ntdown, F.push ? 1 : 0, nullptr, 0,
+                     (F.res && C.res) ? 1 : 0};
     }
     XGrid xwalk(size_t l) const {
         XGrid x = xgrid(l);
@@ -127,7 +125,7 @@ struct Hier {
     XGrid face_grid(int d) const {
         const Level& F = *L[0];
         const Level& C = *L[1];
-        return XGrid{F.d_rb.p, C.d_rb.p, F.cbox.p, F.tface[d].p, F.ntface[d], F.shface[d], 0, nullptr, 0};
+        return XGrid{F.d_rb.p, C.d_rb.p, F.cbox.p, F.tface[d].p, F.ntface[d], 0, nullptr, 0, 0};
     }
 };
 
@@ -137,12 +135,12 @@ struct Tuning {
     int zc = 4;
     int zc_planes = 4;
     int res = 1;
+    int ly_cap = 8;
 };
 
-static void upload_tiles(const TileSet& t, DevBuf<Tile>& buf, int& n, TileShape& sh) {
+static void upload_tiles(const TileSet& t, DevBuf<Tile>& buf, int& n) {
     buf.upload(t.tiles);
     n = (int)t.tiles.size();
-    sh = t.sh;
 }
 
 static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool var, double h0, const Tuning& tune) {
@@ -164,18 +162,17 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
         lv->res = tune.res && boxes_fit_res(lv->rb);
         lv->d_rb.upload(lv->rb);
         {
-            TileSet ts = make_tiles(colour_extents(lv->boxes), tune.zc);
-            if (ts.sh.lz == 0) ts = make_tiles(colour_extents(lv->boxes), tune.zc_planes);
-            upload_tiles(ts, lv->tcol, lv->ntcol, lv->shcol);
+            TileSet ts = make_tiles(colour_extents(lv->boxes), tune.zc, tune.ly_cap);
+            if (ts.sh.lz == 0) ts = make_tiles(colour_extents(lv->boxes), tune.zc_planes, tune.ly_cap);
+            upload_tiles(ts, lv->tcol, lv->ntcol);
         }
         max_tiles = std::max<long long>(max_tiles, lv->ntcol);
         if (l + 1 < lb.size()) {
-            upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, -1), tune.zc), lv->tdown, lv->ntdown, lv->shdown);
+            upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, -1), tune.zc, tune.ly_cap), lv->tdown, lv->ntdown);
             lv->cbox.upload(coarse_owner(lv->boxes, lb[l + 1].boxes));
             if (var && l == 0)
                 for (int d = 0; d < 3; ++d)
-                    upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, d), tune.zc), lv->tface[d], lv->ntface[d],
-                                 lv->shface[d]);
+                    upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, d), tune.zc), lv->tface[d], lv->ntface[d]);
         }
         const std::vector<Tag> faces = build_tags(lv->dom, H->per, lv->boxes, 1, true, 2, true);
         lv->face[0].set(ghost_list(faces, lv->rb, 1));
@@ -439,7 +436,7 @@ void vcycle(Run& R, size_t l) {
     vcycle<T>(R, l + 1);
     fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full);
     R.pre(l, kStageProlong);
-    HIPCHK(launch_prolong<T>(R.s, L.walk(), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong));
+    HIPCHK(launch_prolong<T>(R.s, L.walk(), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong, C.res ? 1 : 0));
     R.post(l, kStageProlong);
     smooth<T>(R, l, R.nu2);
 }
@@ -709,12 +706,57 @@ static bxmg_status set_status(bxmg_solve_info* info, bxmg_status st) {
     return st;
 }
 
+// Hierarchies are cached per geometry (domain, boundary conditions, boxes)
+// and settings, so BoxArrays of the same shape share one; the least recently
+// used are dropped beyond kCacheEntries entries or kCacheBytes of storage.
+constexpr size_t kCacheEntries = 16;
+constexpr size_t kCacheBytes = size_t(48) << 30;
+
+static std::string hier_key(const bxmg_ctx_s* ctx, const bxmg_ba_s* ba, int precision, bool var, double h) {
+    std::string k;
+    auto put = [&](long long x) { k.append((const char*)&x, sizeof x); };
+    long long hb;
+    std::memcpy(&hb, &h, sizeof hb);
+    put(precision);
+    put(var);
+    put(hb);
+    put(ctx->zc);
+    put(ctx->zc_planes);
+    put(ctx->res);
+    put(ctx->ly_cap);
+    for (int d = 0; d < 3; ++d) { put(ba->dom.lo[d]); put(ba->dom.hi[d]); put(ba->per[d]); }
+    for (auto& b : ba->boxes)
+        for (int d = 0; d < 3; ++d) { put(b.lo[d]); put(b.hi[d]); }
+    return k;
+}
+
+static void cache_touch(bxmg_ctx ctx, const std::string& key) {
+    for (auto it = ctx->lru.begin(); it != ctx->lru.end(); ++it)
+        if (*it == key) { ctx->lru.erase(it); break; }
+    ctx->lru.push_back(key);
+}
+
+static void cache_trim(bxmg_ctx ctx, const std::string& keep) {
+    auto total = [&]() {
+        size_t t = 0;
+        for (auto& e : ctx->cache) t += e.second->bytes;
+        return t;
+    };
+    while (ctx->lru.size() > 1 && (ctx->lru.size() > kCacheEntries || total() > kCacheBytes)) {
+        const std::string victim = ctx->lru.front();
+        if (victim == keep) break;
+        ctx->lru.pop_front();
+        ctx->cache.erase(victim);
+    }
+}
+
 static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var, double h, bxmg_status* st) {
-    char key[128];
-    std::snprintf(key, sizeof key, "%llu/%d/%d/%.17g/%d/%d/%d", (unsigned long long)ba->id, precision, (int)var, h,
-                  ctx->zc, ctx->zc_planes, ctx->res);
+    const std::string key = hier_key(ctx, ba, precision, var, h);
     auto it = ctx->cache.find(key);
-    if (it != ctx->cache.end()) return it->second.get();
+    if (it != ctx->cache.end()) {
+        cache_touch(ctx, key);
+        return it->second.get();
+    }
     auto lb = make_hierarchy(ba->dom, ba->boxes);
     const LevelBoxes& bot = lb.back();
     if (!bottom_fits(bot.dom)) {
@@ -728,6 +770,7 @@ static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var
         tune.zc = ctx->zc;
         tune.zc_planes = ctx->zc_planes;
         tune.res = ctx->res;
+        tune.ly_cap = ctx->ly_cap;
         H = build_hier(ba, precision, var, h, tune);
     } catch (HipError& e) {
         *st = fail(e.e == hipErrorOutOfMemory ? BXMG_ENOMEM : BXMG_EDEVICE,
@@ -739,6 +782,8 @@ static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var
     }
     Hier* raw = H.get();
     ctx->cache[key] = std::move(H);
+    cache_touch(ctx, key);
+    cache_trim(ctx, key);
     return raw;
 }
 
@@ -857,13 +902,70 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
 
 bxmg_status bxmg_ctx_tune(bxmg_ctx ctx, int32_t param, int32_t value) {
     if (!ctx) return fail(BXMG_EINVAL, "ctx_tune: NULL context");
-    if (param < 0 || param > 2) return fail(BXMG_EINVAL, "ctx_tune: unknown parameter");
+    if (param < 0 || param > 3) return fail(BXMG_EINVAL, "ctx_tune: unknown parameter");
     if (param <= 1 && (value < 1 || value > 64)) return fail(BXMG_EINVAL, "ctx_tune: value out of range [1, 64]");
     if (param == 2 && value != 0 && value != 1) return fail(BXMG_EINVAL, "ctx_tune: value must be 0 or 1");
+    if (param == 3 && (value < 0 || value > 8)) return fail(BXMG_EINVAL, "ctx_tune: value out of range [0, 8]");
     std::lock_guard<std::mutex> lock(ctx->mu);
     if (param == 0) ctx->zc = value;
     else if (param == 1) ctx->zc_planes = value;
-    else ctx->res = value;
+    else if (param == 2) ctx->res = value;
+    else ctx->ly_cap = value;
+    return BXMG_OK;
+}
+
+bxmg_status bxmg_autotune(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi, bxmg_multifab rhs,
+                          bxmg_multifab beta, int32_t cycles, int32_t best[4], double* best_ms, int32_t* ntried) {
+    if (!ctx || !phi || !rhs) return fail(BXMG_EINVAL, "autotune: NULL argument");
+    if (cycles < 1 || cycles > 64) return fail(BXMG_EINVAL, "autotune: cycles out of [1, 64]");
+    bxmg_solve_params P;
+    if (params) P = *params;
+    else bxmg_solve_params_default(&P);
+    P.fixed_cycles = cycles;
+    // candidates: planes per thread x tile rows x addressing
+    const int zcs[] = {1, 2, 4, 8};
+    const int lys[] = {2, 3, 8};
+    const int ress[] = {1, 0};
+    int prev[4];
+    {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        prev[0] = ctx->zc;
+        prev[1] = ctx->res;
+        prev[2] = ctx->ly_cap;
+        prev[3] = ctx->zc_planes;
+    }
+    double best_t = 1e300;
+    int bz = prev[0], bl = prev[2], br = prev[1], n = 0;
+    bxmg_solve_info info;
+    for (int zc : zcs)
+        for (int ly : lys)
+            for (int res : ress) {
+                {
+                    std::lock_guard<std::mutex> lock(ctx->mu);
+                    ctx->zc = ctx->zc_planes = zc;
+                    ctx->ly_cap = ly;
+                    ctx->res = res;
+                }
+                bxmg_status st = bxmg_mlmg_solve(ctx, &P, phi, rhs, beta, &info);  // builds the hierarchy
+                if (st != BXMG_OK && st != BXMG_ENOCONV) return st;
+                double t = 1e300;
+                for (int rep = 0; rep < 2; ++rep) {
+                    st = bxmg_mlmg_solve(ctx, &P, phi, rhs, beta, &info);
+                    if (st != BXMG_OK && st != BXMG_ENOCONV) return st;
+                    t = std::min(t, info.seconds);
+                }
+                ++n;
+                if (t < best_t) { best_t = t; bz = zc; bl = ly; br = res; }
+            }
+    {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        ctx->zc = ctx->zc_planes = bz;
+        ctx->ly_cap = bl;
+        ctx->res = br;
+    }
+    if (best) { best[0] = bz; best[1] = bz; best[2] = br; best[3] = bl; }
+    if (best_ms) *best_ms = best_t * 1000.0 / cycles;
+    if (ntried) *ntried = n;
     return BXMG_OK;
 }
 
@@ -1015,7 +1117,8 @@ bxmg_status bxmg_prolong_add(bxmg_ctx ctx, bxmg_multifab coarse, bxmg_multifab f
         HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)fine->data, fine->d_fboxes.p, H->u64[0]->p, false));
         HIPCHK(launch_fab_to_rb(R.s, L1.grid(), (const double*)coarse->data, coarse->d_fboxes.p, H->u64[1]->p, false));
         fill<double>(R, 1, H->u64[1]->p, L1.full);
-        HIPCHK(launch_prolong<double>(R.s, L0.grid(), L1.d_rb.p, L0.cbox.p, H->u64[1]->p, H->u64[0]->p, order));
+        HIPCHK(launch_prolong<double>(R.s, L0.grid(), L1.d_rb.p, L0.cbox.p, H->u64[1]->p, H->u64[0]->p, order,
+                                      L1.res ? 1 : 0));
         HIPCHK(launch_rb_to_fab(R.s, L0.grid(), H->u64[0]->p, (double*)fine->data, fine->d_fboxes.p));
         HIPCHK(hipStreamSynchronize(R.s));
     } catch (HipError& e) {

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <deque>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -249,12 +250,13 @@ inline int ilog2ceil(int n) {
     return l;
 }
 
-inline TileSet make_tiles(const std::vector<std::array<int, 3>>& ext, int zc_target) {
+inline TileSet make_tiles(const std::vector<std::array<int, 3>>& ext, int zc_target, int ly_cap = 8) {
     int mx = 1, my = 1, mz = 1;
     for (auto& e : ext) { mx = std::max(mx, e[0]); my = std::max(my, e[1]); mz = std::max(mz, e[2]); }
+    if (mx > 65535 || my > 65535 || mz > 65535) throw std::runtime_error("a box edge exceeds 65535 cells");
     TileSet t;
     t.sh.lx = std::min(ilog2ceil(mx), 6);
-    t.sh.ly = std::min(ilog2ceil(my), 8 - t.sh.lx);
+    t.sh.ly = std::min(std::min(ilog2ceil(my), 8 - t.sh.lx), std::max(ly_cap, 0));
     t.sh.lz = 8 - t.sh.lx - t.sh.ly;
     const int TX = 1 << t.sh.lx, TY = 1 << t.sh.ly, TZ = 1 << t.sh.lz;
     t.sh.zc = std::max(1, std::min(zc_target, (mz + TZ - 1) / TZ));
@@ -262,7 +264,19 @@ inline TileSet make_tiles(const std::vector<std::array<int, 3>>& ext, int zc_tar
     for (size_t b = 0; b < ext.size(); ++b)
         for (int z0 = 0; z0 < ext[b][2]; z0 += KZ)
             for (int y0 = 0; y0 < ext[b][1]; y0 += TY)
-                for (int x0 = 0; x0 < ext[b][0]; x0 += TX) t.tiles.push_back(Tile{(int)b, x0, y0, z0});
+                for (int x0 = 0; x0 < ext[b][0]; x0 += TX) {
+                    Tile tl;
+                    tl.box = (int)b;
+                    tl.x0 = (uint16_t)x0;
+                    tl.y0 = (uint16_t)y0;
+                    tl.z0 = (uint16_t)z0;
+                    tl.lx = (uint8_t)t.sh.lx;
+                    tl.ly = (uint8_t)t.sh.ly;
+                    tl.lz = (uint8_t)t.sh.lz;
+                    tl.zc = (uint8_t)t.sh.zc;
+                    tl.pad = 0;
+                    t.tiles.push_back(tl);
+                }
     return t;
 }
 
@@ -316,6 +330,7 @@ inline std::vector<RBox> rb_layout(const std::vector<Box>& boxes, int ng, double
         for (int q = 0; q < 6; ++q) { r.nb[q] = -2; r.shift[q] = 0; }
         const long long half = (long long)r.H * r.G[1] * r.G[2];
         const long long padded = (half + 63) / 64 * 64;
+        if (2 * padded > 0x7fffffffLL) throw std::runtime_error("a box holds more than 2^31 elements");
         r.base = off;
         r.cstride = padded;
         off += 2 * padded;
@@ -421,6 +436,22 @@ struct DevBuf {
     }
 };
 
+// Device array that keeps its allocation and only grows (no free on refill).
+template <class T>
+struct DevVec {
+    DevBuf<T> b;
+    size_t len = 0;
+    T* p() const { return b.p; }
+    void reserve(size_t count) {
+        if (count > b.n) b.alloc(std::max<size_t>(count, b.n + b.n / 2));
+    }
+    void assign(const std::vector<T>& v) {
+        reserve(std::max<size_t>(v.size(), 1));
+        len = v.size();
+        if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
+};
+
 struct Plan {
     DevBuf<Tag> tags;
     int ntags = 0;
@@ -491,7 +522,9 @@ struct bxmg_ctx_s {
     Profiler prof;
     int zc = 4, zc_planes = 4;  // tile depths for hierarchies built from now on
     int res = 1;                // 32-bit buffer addressing where the boxes allow it
-    std::map<std::string, std::unique_ptr<Hier>> cache;
+    int ly_cap = 8;             // at most 2^ly_cap threads of a tile along y
+    std::map<std::string, std::unique_ptr<Hier>> cache;  // by geometry and settings
+    std::deque<std::string> lru;                          // cache keys, least recently used first
     double* h_norm = nullptr;  // pinned
     std::mutex mu;
 };

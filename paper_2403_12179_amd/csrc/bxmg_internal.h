@@ -67,16 +67,21 @@ struct GhostCopy {
 };
 
 // A tile is the work of one block: threads (tx, ty, tz) of a TX x TY x TZ
-// block cover x-index x0 + tx, y-index y0 + ty and z-indices
-// z0 + tz + z*TZ for z < ZC, relative to the box's lower corner; x counts
-// half-row cells (colour kernels) or coarse cells (transfer kernels).
+// block (TX = 2^lx, TY = 2^ly, TZ = 2^lz, TX*TY*TZ = kBlock) cover x-index
+// x0 + tx, y-index y0 + ty and z-indices z0 + tz + z*TZ for z < zc,
+// relative to the box's lower corner; x counts half-row cells (colour
+// kernels) or coarse cells (transfer kernels).  Each tile carries its own
+// shape, so boxes of different sizes share a launch without idle threads.
 struct Tile {
     int box;
-    int x0, y0, z0;
+    uint16_t x0, y0, z0;
+    uint8_t lx, ly, lz, zc;
+    uint16_t pad;
 };
+static_assert(sizeof(Tile) == 16, "tile descriptor size");
 
 struct TileShape {
-    int lx, ly, lz;  // log2 of TX, TY, TZ (TX*TY*TZ = kBlock)
+    int lx, ly, lz;  // log2 of TX, TY, TZ
     int zc;          // z iterations per thread
 };
 
@@ -100,7 +105,6 @@ struct Grid {
     const RBox* boxes;
     const Tile* tiles;
     int ntiles;
-    TileShape sh;
     int push;
     const int* active;
     int rev;  // walk the tiles in reverse order (see tile_index)
@@ -115,10 +119,10 @@ struct XGrid {
     const int* cbox;
     const Tile* tiles;
     int ntiles;
-    TileShape sh;
     int push;  // as Grid::push, for the fine level
     const int* active;
     int rev;
+    int res;   // fine and coarse boxes allow 32-bit buffer addressing
 };
 
 // One level of the fused coarse V-cycle: a single box in RB storage.
@@ -191,11 +195,13 @@ hipError_t launch_resid_restrict(hipStream_t s, const XGrid& x, const T* u, cons
                                  const FaceArrays<T>* fat, T* fc);
 template <class T>
 hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* fc);
-// fine += P coarse: one thread per fine cell over the fine level's colour
-// tiles; cbox[b] = coarse box holding the coarsened fine box b
+// fine += P coarse: one thread per pair of fine cells (2I, 2I+1) over the
+// fine level's colour tiles (fine boxes pair aligned); cbox[b] = coarse box
+// holding the coarsened fine box b; cres: the coarse boxes allow 32-bit
+// buffer addressing too
 template <class T>
 hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
-                          int order);
+                          int order, int cres);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n);
@@ -238,6 +244,18 @@ hipError_t launch_norm_seg(hipStream_t s, const double* partials, const int* tst
 // history, retires finished problems, counts the rest into *nactive.
 hipError_t launch_batch_check(hipStream_t s, const int* slots, int n, const double* norms, BatchSlot* st,
                               int* active, double* hist, double* hist_l2, int* nactive);
+// Ghost lists of many problems in one launch: set q copies list[0..n) with
+// indices relative to data + off (active slots only).
+struct GhostSet {
+    const GhostCopy* list;
+    long long n, off;
+    int pid, pad;
+};
+hipError_t launch_fill_sets(hipStream_t s, void* data, bool f32, const GhostSet* sets, int nsets, long long max_n,
+                            const int* active);
+// Admission of one problem: ||f||_inf from fn3 (max, sum, bad) into st[slot],
+// and active[slot] = 1 unless f is zero or not finite.
+hipError_t launch_batch_admit(hipStream_t s, const double* fn3, BatchSlot* st, int* active, int slot);
 // Zero element ranges [start, start + len) of the problems still active.
 struct ZeroRange {
     long long start, len;

@@ -45,6 +45,11 @@ __device__ __forceinline__ long long rb_idx(const RBox& b, int i, int j, int k) 
     return rb_row(b, (i + j + k) & 1, j, k) + ((i - b.glo[0]) >> 1);
 }
 
+// rb_idx relative to the box start, 32-bit (boxes small enough for buffer addressing)
+__device__ __forceinline__ int rb_off(const RBox& B, int i, int j, int k) {
+    return ((i + j + k) & 1) * (int)B.cstride + ((k - B.glo[2]) * B.G[1] + (j - B.glo[1])) * B.H + ((i - B.glo[0]) >> 1);
+}
+
 __device__ __forceinline__ long long fab_idx(const FBox& b, int i, int j, int k) {
     return b.base + (long long)(i - b.glo[0]) + (long long)b.G[0] * ((long long)(j - b.glo[1]) + (long long)b.G[1] * (k - b.glo[2]));
 }
@@ -71,13 +76,13 @@ struct TileThread {
     int x, y, z0, dz;  // box-relative x and y, first z and z step
 };
 
-__device__ __forceinline__ TileThread tile_thread(const Tile& tl, const TileShape& sh) {
+__device__ __forceinline__ TileThread tile_thread(const Tile& tl) {
     const int tid = threadIdx.x;
     TileThread r;
-    r.x = tl.x0 + (tid & ((1 << sh.lx) - 1));
-    r.y = tl.y0 + ((tid >> sh.lx) & ((1 << sh.ly) - 1));
-    r.z0 = tl.z0 + (tid >> (sh.lx + sh.ly));
-    r.dz = 1 << sh.lz;
+    r.x = tl.x0 + (tid & ((1 << tl.lx) - 1));
+    r.y = tl.y0 + ((tid >> tl.lx) & ((1 << tl.ly) - 1));
+    r.z0 = tl.z0 + (tid >> (tl.lx + tl.ly));
+    r.dz = 1 << tl.lz;
     return r;
 }
 
@@ -268,7 +273,7 @@ __device__ __forceinline__ int gather_res(const BoxRes<T>& U, const BoxRes<T>& B
 // Cells whose loads a thread issues together: the z planes it walks, in
 // groups of kZB (constant coefficient) or kZBVar (coefficient loads too).
 #ifndef BXMG_ZB
-#define BXMG_ZB 2
+#define BXMG_ZB 1
 #endif
 constexpr int kZB = BXMG_ZB;
 constexpr int kZBVar = 1;
@@ -372,13 +377,13 @@ __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const 
     FaceArrays<T> fa;
     if constexpr (MODE == 2) fa = fat[B.pid];
     const T h2 = (T)(B.h * B.h);
-    const TileThread th = tile_thread(tl, g.sh);
+    const TileThread th = tile_thread(tl);
     const int j = B.lo[1] + th.y;
     if (j > B.hi[1]) return;
     const long long ne = 2 * B.cstride;
     const BoxRes<T> U(u + B.base, ne), F(f + B.base, ne), Bt((MODE == 1 ? beta : f) + B.base, ne);
     constexpr int ZB = (MODE == 0) ? kZB : kZBVar;
-    for (int z0 = 0; z0 < g.sh.zc; z0 += ZB) {
+    for (int z0 = 0; z0 < (int)tl.zc; z0 += ZB) {
         Nbr<T> nb[ZB];
         T fv[ZB];
         long long idx[ZB];
@@ -390,7 +395,7 @@ __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const 
             const int i = colour_i(B, th.x, j, k, colour);
             ii[q] = i;
             kk[q] = k;
-            ok[q] = (z0 + q < g.sh.zc) && k <= B.hi[2] && i <= B.hi[0];
+            ok[q] = (z0 + q < (int)tl.zc) && k <= B.hi[2] && i <= B.hi[0];
             if (ok[q]) {
                 if constexpr (RES) {
                     idx[q] = gather_res<T, MODE, false>(U, Bt, fa, B, i, j, k, nb[q]);
@@ -430,14 +435,14 @@ __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ 
     FaceArrays<T> fa;
     if constexpr (MODE == 2) fa = fat[B.pid];
     const T ih2 = (T)(1.0 / (B.h * B.h));
-    const TileThread th = tile_thread(tl, g.sh);
+    const TileThread th = tile_thread(tl);
     const int j = B.lo[1] + th.y;
     const long long ne = 2 * B.cstride;
     const BoxRes<T> U(u + B.base, ne), F(f + B.base, ne), Bt((MODE == 1 ? beta : f) + B.base, ne);
     const BoxRes<R> Rr(r ? r + B.base : (R*)nullptr, r ? ne : 0);
     if (j <= B.hi[1]) {
         constexpr int ZB = (MODE == 0) ? kZB : kZBVar;
-        for (int z0 = 0; z0 < g.sh.zc; z0 += ZB) {
+        for (int z0 = 0; z0 < (int)tl.zc; z0 += ZB) {
             Nbr<T> nb[ZB][2];
             T fv[ZB][2];
             long long idx[ZB][2];
@@ -448,7 +453,7 @@ __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ 
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     const int i = colour_i(B, th.x, j, k, c);
-                    ok[q][c] = (z0 + q < g.sh.zc) && k <= B.hi[2] && i <= B.hi[0];
+                    ok[q][c] = (z0 + q < (int)tl.zc) && k <= B.hi[2] && i <= B.hi[0];
                     if (ok[q][c]) {
                         if constexpr (RES) {
                             idx[q][c] = gather_res<T, MODE, true>(U, Bt, fa, B, i, j, k, nb[q][c]);
@@ -504,10 +509,10 @@ __global__ void __launch_bounds__(kBlock) k_field_norm(Grid g, const double* __r
     double mx = 0.0, s2 = 0.0, bad = 0.0;
     const Tile tl = g.tiles[tile_index(g.rev)];
     const RBox B = g.boxes[tl.box];
-    const TileThread th = tile_thread(tl, g.sh);
+    const TileThread th = tile_thread(tl);
     const int j = B.lo[1] + th.y;
     if (j <= B.hi[1])
-        for (int z = 0; z < g.sh.zc; ++z) {
+        for (int z = 0; z < (int)tl.zc; ++z) {
             const int k = B.lo[2] + th.z0 + z * th.dz;
             if (k > B.hi[2]) break;
             for (int c = 0; c < 2; ++c) {
@@ -552,10 +557,65 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(XGrid x, const T* __r
     if constexpr (MODE == 2) fa = fat[B.pid];
     const T ih2 = (T)(1.0 / (B.h * B.h));
     const RBox C = x.cboxes[x.cbox[tl.box]];
-    const TileThread th = tile_thread(tl, x.sh);
+    const TileThread th = tile_thread(tl);
     const int I = (B.lo[0] >> 1) + th.x, J = (B.lo[1] >> 1) + th.y;
     if (I > (B.hi[0] >> 1) || J > (B.hi[1] >> 1)) return;
-    for (int z = 0; z < x.sh.zc; ++z) {
+    if constexpr (MODE == 0) {
+        // The 8 children's stencils touch 32 distinct cells of u: the 2x2x2
+        // block and the 4 cells beyond each of its 6 faces.  Load each once
+        // (v[x][y][z], offsets -1..2 around the block's lower corner), then
+        // form the 8 residuals as resid_at does.
+        const BoxRes<T> U(u + B.base, 2 * B.cstride), F(f + B.base, 2 * B.cstride);
+        const BoxRes<T> Cw(fc + C.base, 2 * C.cstride);
+        for (int z = 0; z < (int)tl.zc; ++z) {
+            const int K = (B.lo[2] >> 1) + th.z0 + z * th.dz;
+            if (K > (B.hi[2] >> 1)) break;
+            const int i = 2 * I, j = 2 * J, k = 2 * K;
+            T v[4][4][4], fv[2][2][2];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int outer = (a == 0 || a == 3) + (b == 0 || b == 3) + (c == 0 || c == 3);
+                        if (outer > 1) continue;  // edges and corners of the 4x4x4 cube are not needed
+                        const int o = rb_off(B, i - 1 + a, j - 1 + b, k - 1 + c);
+                        if (x.res) v[a][b][c] = U.ld(o);
+                        else v[a][b][c] = u[B.base + o];
+                        if (outer == 0) {
+                            if (x.res) fv[a - 1][b - 1][c - 1] = F.ld(o);
+                            else fv[a - 1][b - 1][c - 1] = f[B.base + o];
+                        }
+                    }
+            T r[2][2][2];
+#pragma unroll
+            for (int a = 1; a <= 2; ++a)
+#pragma unroll
+                for (int b = 1; b <= 2; ++b)
+#pragma unroll
+                    for (int c = 1; c <= 2; ++c) {
+                        Nbr<T> n;
+                        n.xm = v[a - 1][b][c];
+                        n.xp = v[a + 1][b][c];
+                        n.ym = v[a][b - 1][c];
+                        n.yp = v[a][b + 1][c];
+                        n.zm = v[a][b][c - 1];
+                        n.zp = v[a][b][c + 1];
+                        n.c = v[a][b][c];
+                        T su, sb;
+                        sums<T, 0>(n, su, sb);
+                        r[a - 1][b - 1][c - 1] = fv[a - 1][b - 1][c - 1] - (su - sb * n.c) * ih2;
+                    }
+            const T s = ((r[0][0][0] + r[1][0][0]) + (r[0][1][0] + r[1][1][0])) +
+                        ((r[0][0][1] + r[1][0][1]) + (r[0][1][1] + r[1][1][1]));
+            const int oc = rb_off(C, I, J, K);
+            if (x.res) Cw.st(oc, s * T(0.125));
+            else fc[C.base + oc] = s * T(0.125);
+        }
+        return;
+    }
+    for (int z = 0; z < (int)tl.zc; ++z) {
         const int K = (B.lo[2] >> 1) + th.z0 + z * th.dz;
         if (K > (B.hi[2] >> 1)) break;
         const int i = 2 * I, j = 2 * J, k = 2 * K;
@@ -577,10 +637,10 @@ __global__ void __launch_bounds__(kBlock) k_restrict_plain(XGrid x, const T* __r
     const Tile tl = x.tiles[tile_index(x.rev)];
     const RBox B = x.fboxes[tl.box];
     const RBox C = x.cboxes[x.cbox[tl.box]];
-    const TileThread th = tile_thread(tl, x.sh);
+    const TileThread th = tile_thread(tl);
     const int I = (B.lo[0] >> 1) + th.x, J = (B.lo[1] >> 1) + th.y;
     if (I > (B.hi[0] >> 1) || J > (B.hi[1] >> 1)) return;
-    for (int z = 0; z < x.sh.zc; ++z) {
+    for (int z = 0; z < (int)tl.zc; ++z) {
         const int K = (B.lo[2] >> 1) + th.z0 + z * th.dz;
         if (K > (B.hi[2] >> 1)) break;
         const int i = 2 * I, j = 2 * J, k = 2 * K;
@@ -593,48 +653,71 @@ __global__ void __launch_bounds__(kBlock) k_restrict_plain(XGrid x, const T* __r
 }
 
 // ---------------------------------------------------- prolongation + add
-// One thread per fine cell (both colours of a colour-tile slot): the parent
-// is P = floor(i/2) per direction and the neighbour on the child's side is
-// P + s, s = +1 for an odd index, -1 for an even one; with c_abc the coarse
-// value at P shifted by a*sx, b*sy, c*sz,
+// Every fine cell gets e from its parent P = floor(i/2) per direction and the
+// coarse neighbours on the child's side (P + s, s = +1 for an odd index, -1
+// for an even one); with c_abc the coarse value at P shifted by a*sx, b*sy,
+// c*sz,
 //   e = (((27 c000 + 9 ((c100 + c010) + c001)) + 3 ((c110 + c101) + c011)) + c111) / 64
 // (trilinear) or e = c000 (piecewise constant).  Coarse ghosts must be current.
-template <class T, bool PUSH>
+//
+// One thread per pair of fine cells (2I, 2I+1) of a row (fine boxes of a
+// coarsened level are pair aligned): the pair shares its parent and its y/z
+// neighbours, so 12 coarse values serve both cells (x = I-1, I, I+1 on the
+// four rows (J, K), (J+sy, K), (J, K+sz), (J+sy, K+sz)).
+template <class T>
+__device__ __forceinline__ T prolong_e(const T a[4][3], int x, int order) {
+    if (order == 1) return a[0][1];
+    const T c000 = a[0][1], c100 = a[0][x], c010 = a[1][1], c001 = a[2][1];
+    const T c110 = a[1][x], c101 = a[2][x], c011 = a[3][1], c111 = a[3][x];
+    return (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) * T(0.015625);
+}
+
+template <class T, bool PUSH, bool RES>
 __global__ void __launch_bounds__(kBlock) k_prolong(Grid g, const RBox* __restrict__ cboxes, const int* __restrict__ cbox,
                                                    const T* __restrict__ ec, T* __restrict__ uf, int order) {
     const Tile tl = g.tiles[tile_index(g.rev)];
     const RBox B = g.boxes[tl.box];
     if (g.active && !g.active[B.pid]) return;
     const RBox C = cboxes[cbox[tl.box]];
-    const TileThread th = tile_thread(tl, g.sh);
+    const TileThread th = tile_thread(tl);
     const int j = B.lo[1] + th.y;
-    if (j > B.hi[1]) return;
-    const int J = j >> 1, sj = (j & 1) ? 1 : -1;
-    for (int z = 0; z < g.sh.zc; ++z) {
+    const int i0 = B.lo[0] + 2 * th.x;  // the even cell of the pair
+    if (j > B.hi[1] || i0 > B.hi[0]) return;
+    const int J = j >> 1, sj = (j & 1) ? 1 : -1, I = i0 >> 1;
+    const BoxRes<T> Cr(ec + C.base, 2 * C.cstride), Fr(uf + B.base, 2 * B.cstride);
+    for (int z = 0; z < (int)tl.zc; ++z) {
         const int k = B.lo[2] + th.z0 + z * th.dz;
         if (k > B.hi[2]) break;
         const int K = k >> 1, sk = (k & 1) ? 1 : -1;
-        for (int c = 0; c < 2; ++c) {
-            const int i = colour_i(B, th.x, j, k, c);
-            if (i > B.hi[0]) continue;
-            const int I = i >> 1, si = (i & 1) ? 1 : -1;
-            T e;
-            const T c000 = ec[rb_idx(C, I, J, K)];
-            if (order == 1) {
-                e = c000;
-            } else {
-                const T c100 = ec[rb_idx(C, I + si, J, K)], c010 = ec[rb_idx(C, I, J + sj, K)];
-                const T c001 = ec[rb_idx(C, I, J, K + sk)];
-                const T c110 = ec[rb_idx(C, I + si, J + sj, K)], c101 = ec[rb_idx(C, I + si, J, K + sk)];
-                const T c011 = ec[rb_idx(C, I, J + sj, K + sk)];
-                const T c111 = ec[rb_idx(C, I + si, J + sj, K + sk)];
-                e = (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
-                    T(0.015625);
+        const int rj[4] = {J, J + sj, J, J + sj}, rk[4] = {K, K, K + sk, K + sk};
+        T a[4][3];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (order == 1 && r > 0) break;
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                if (order == 1 && x != 1) continue;
+                const int o = rb_off(C, I - 1 + x, rj[r], rk[r]);
+                if constexpr (RES) a[r][x] = Cr.ld(o);
+                else a[r][x] = ec[C.base + o];
             }
-            const long long idx = rb_idx(B, i, j, k);
-            const T v = uf[idx] + e;
-            uf[idx] = v;
-            if constexpr (PUSH) push_ghosts(uf, g.boxes, B, i, j, k, v);
+        }
+        const int oe = rb_off(B, i0, j, k), oo = rb_off(B, i0 + 1, j, k);
+        T ve, vo;
+        if constexpr (RES) {
+            ve = Fr.ld(oe) + prolong_e<T>(a, 0, order);
+            vo = Fr.ld(oo) + prolong_e<T>(a, 2, order);
+            Fr.st(oe, ve);
+            Fr.st(oo, vo);
+        } else {
+            ve = uf[B.base + oe] + prolong_e<T>(a, 0, order);
+            vo = uf[B.base + oo] + prolong_e<T>(a, 2, order);
+            uf[B.base + oe] = ve;
+            uf[B.base + oo] = vo;
+        }
+        if constexpr (PUSH) {
+            push_ghosts(uf, g.boxes, B, i0, j, k, ve);
+            push_ghosts(uf, g.boxes, B, i0 + 1, j, k, vo);
         }
     }
 }
@@ -657,10 +740,10 @@ __global__ void __launch_bounds__(kBlock) k_cast_f32(const double* __restrict__ 
     const Tile tl = (g).tiles[tile_index((g).rev)];                                 \
     const RBox B = (g).boxes[tl.box];                                        \
     if ((g).active && !(g).active[B.pid]) return;                            \
-    const TileThread th = tile_thread(tl, (g).sh);                           \
+    const TileThread th = tile_thread(tl);                           \
     const int j = B.lo[1] + th.y;                                            \
     if (j > B.hi[1]) return;                                                 \
-    for (int z = 0; z < (g).sh.zc; ++z) {                                    \
+    for (int z = 0; z < (int)tl.zc; ++z) {                                    \
         const int k = B.lo[2] + th.z0 + z * th.dz;                           \
         if (k > B.hi[2]) break;                                              \
         for (int c = 0; c < 2; ++c) {                                        \
@@ -694,10 +777,10 @@ __global__ void __launch_bounds__(kBlock) k_sum_valid(Grid g, const double* __re
     double mx = 0.0, s = 0.0, cnt = 0.0;
     const Tile tl = g.tiles[tile_index(g.rev)];
     const RBox B = g.boxes[tl.box];
-    const TileThread th = tile_thread(tl, g.sh);
+    const TileThread th = tile_thread(tl);
     const int j = B.lo[1] + th.y;
     if (j <= B.hi[1])
-        for (int z = 0; z < g.sh.zc; ++z) {
+        for (int z = 0; z < (int)tl.zc; ++z) {
             const int k = B.lo[2] + th.z0 + z * th.dz;
             if (k > B.hi[2]) break;
             for (int c = 0; c < 2; ++c) {
@@ -733,13 +816,13 @@ __global__ void __launch_bounds__(kBlock) k_faces_from_cells(XGrid x, const T* _
                                                             FaceArrays<T> out, T* __restrict__ dst) {
     const Tile tl = x.tiles[tile_index(x.rev)];
     const RBox B = x.fboxes[tl.box];
-    const TileThread th = tile_thread(tl, x.sh);
+    const TileThread th = tile_thread(tl);
     int chi[3] = {B.hi[0] >> 1, B.hi[1] >> 1, B.hi[2] >> 1};
     if (B.hi[d] == fdom_hi) chi[d] += 1;
     const int I = (B.lo[0] >> 1) + th.x, J = (B.lo[1] >> 1) + th.y;
     if (I > chi[0] || J > chi[1]) return;
     const int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-    for (int z = 0; z < x.sh.zc; ++z) {
+    for (int z = 0; z < (int)tl.zc; ++z) {
         const int K = (B.lo[2] >> 1) + th.z0 + z * th.dz;
         if (K > chi[2]) break;
         const int f0[3] = {2 * I, 2 * J, 2 * K};
@@ -1222,15 +1305,23 @@ template hipError_t launch_restrict_plain<double>(hipStream_t, const XGrid&, con
 
 template <class T>
 hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
-                          int order) {
+                          int order, int cres) {
     if (fine.ntiles <= 0) return hipSuccess;
-    if (fine.push) hipLaunchKernelGGL((k_prolong<T, true>), dim3(fine.ntiles), dim3(kBlock), 0, s, fine, cboxes, cbox, ec, uf, order);
-    else hipLaunchKernelGGL((k_prolong<T, false>), dim3(fine.ntiles), dim3(kBlock), 0, s, fine, cboxes, cbox, ec, uf, order);
+    const dim3 G(fine.ntiles), B(kBlock);
+#define BXMG_PR(PUSH, RES) hipLaunchKernelGGL((k_prolong<T, PUSH, RES>), G, B, 0, s, fine, cboxes, cbox, ec, uf, order)
+    const bool res = fine.res && cres;
+    if (fine.push) {
+        if (res) BXMG_PR(true, true); else BXMG_PR(true, false);
+    } else {
+        if (res) BXMG_PR(false, true); else BXMG_PR(false, false);
+    }
+#undef BXMG_PR
     return hipGetLastError();
 }
 template hipError_t launch_prolong<double>(hipStream_t, const Grid&, const RBox*, const int*, const double*, double*,
-                                           int);
-template hipError_t launch_prolong<float>(hipStream_t, const Grid&, const RBox*, const int*, const float*, float*, int);
+                                           int, int);
+template hipError_t launch_prolong<float>(hipStream_t, const Grid&, const RBox*, const int*, const float*, float*, int,
+                                          int);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n) {
@@ -1396,6 +1487,50 @@ __global__ void __launch_bounds__(kBlock) k_zero_ranges(T* __restrict__ p, const
     if (active && !active[R.pid]) return;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < R.len; q += stride) p[R.start + q] = T(0);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fill_sets(T* __restrict__ data, const GhostSet* __restrict__ sets,
+                                                     const int* __restrict__ active) {
+    const GhostSet S = sets[blockIdx.y];
+    if (active && !active[S.pid]) return;
+    T* d = data + S.off;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < S.n; g += stride) {
+        const GhostCopy p = S.list[g];
+        const T v = d[p.src & 0x7fffffffu];
+        d[p.dst] = (p.src >> 31) ? -v : v;
+    }
+}
+
+__global__ void k_batch_admit(const double* __restrict__ fn3, BatchSlot* __restrict__ st, int* __restrict__ active,
+                              int slot) {
+    if (threadIdx.x != 0) return;
+    BatchSlot S = st[slot];
+    S.fnorm = fn3[0];
+    int act = 1;
+    if (fn3[2] > 0.0) {
+        S.status = kStatusNonFinite;
+        act = 0;
+    } else if (!(fn3[0] > 0.0)) {
+        act = 0;  // f == 0: the solution is the initial guess
+    }
+    st[slot] = S;
+    active[slot] = act;
+}
+
+hipError_t launch_fill_sets(hipStream_t s, void* data, bool f32, const GhostSet* sets, int nsets, long long max_n,
+                            const int* active) {
+    if (nsets <= 0 || max_n <= 0) return hipSuccess;
+    const dim3 G((unsigned)std::min<long long>(nblk(max_n), 1024), (unsigned)nsets);
+    if (f32) hipLaunchKernelGGL(k_fill_sets<float>, G, dim3(kBlock), 0, s, (float*)data, sets, active);
+    else hipLaunchKernelGGL(k_fill_sets<double>, G, dim3(kBlock), 0, s, (double*)data, sets, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_admit(hipStream_t s, const double* fn3, BatchSlot* st, int* active, int slot) {
+    hipLaunchKernelGGL(k_batch_admit, dim3(1), dim3(64), 0, s, fn3, st, active, slot);
+    return hipGetLastError();
 }
 
 hipError_t launch_norm_seg(hipStream_t s, const double* partials, const int* tstart, const int* seg_slot, int nseg,

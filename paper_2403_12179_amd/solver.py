@@ -56,6 +56,20 @@ def mlmg_solve(phi: MultiFab, rhs: MultiFab, beta: MultiFab | None = None, raise
     return res
 
 
+def autotune(phi, rhs, beta=None, cycles=2, **params):
+    """Time every candidate launch shape on this problem and keep the fastest
+    on phi's context; returns the chosen knobs and the time per V-cycle.
+    phi is overwritten."""
+    p = solve_params(**params)
+    best = (C.c_int32 * 4)()
+    ms = C.c_double()
+    n = C.c_int32()
+    L.check(L.lib().bxmg_autotune(phi.ctx._h, C.byref(p), phi._h, rhs._h, beta._h if beta is not None else None,
+                                  int(cycles), best, C.byref(ms), C.byref(n)))
+    return {"planes_per_thread": best[0], "buffer_addressing": best[2], "tile_rows_log2_cap": best[3],
+            "ms_per_cycle": ms.value, "candidates": n.value}
+
+
 def gs_colour(phi, rhs, h, colour, beta=None):
     L.check(L.lib().bxmg_gs_colour(phi.ctx._h, phi._h, rhs._h, beta._h if beta is not None else None, float(h),
                                    int(colour)))

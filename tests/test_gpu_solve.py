@@ -208,3 +208,53 @@ def test_non_aligned_boxes_use_ghost_refresh(bx, orc):
         orc.apply_bc((0, 0, 0), (n - 1,) * 3, per, boxes, 1, U)
         orc.gs((0, 0, 0), (n - 1,) * 3, per, boxes, 1.0 / n, 1, U, F)
         assert np.array_equal(phi.to_global(), orc.unpack_valid(U, (0, 0, 0), (n - 1,) * 3, boxes, 1))
+
+
+def test_launch_knobs_do_not_change_results(bx):
+    """Tile depth, tile rows and buffer addressing change the work split and
+    the instructions, never the arithmetic: fixed-cycle iterates are bitwise
+    equal under every setting, and the autotuner leaves a valid setting."""
+    n = 64
+    f = W.uniform_rhs((n, n, n), 27)
+    ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 32, (0, 0, 0), f)
+    lib, ctx = bx.lib(), phi.ctx
+    ref = None
+    try:
+        for zc, res, ly in [(4, 1, 8), (1, 0, 8), (8, 1, 2), (2, 0, 3)]:
+            for param, value in ((0, zc), (1, zc), (2, res), (3, ly)):
+                bx._lib.check(lib.bxmg_ctx_tune(ctx._h, param, value))
+            for precision in (0, 1):
+                phi.set_val(0.0)
+                r = bx.mlmg_solve(phi, rhs, fixed_cycles=3, precision=precision)
+                out = (phi.to_global(), r.hist)
+                if ref is None:
+                    ref = {}
+                if precision not in ref:
+                    ref[precision] = out
+                else:
+                    assert np.array_equal(out[0], ref[precision][0]) and out[1] == ref[precision][1]
+        phi.set_val(0.0)
+        best = bx.autotune(phi, rhs, cycles=1)
+        assert best["candidates"] == 24 and best["planes_per_thread"] in (1, 2, 4, 8)
+        phi.set_val(0.0)
+        r = bx.mlmg_solve(phi, rhs, fixed_cycles=3)
+        assert np.array_equal(phi.to_global(), ref[0][0])
+    finally:
+        for param, value in ((0, 4), (1, 4), (2, 1), (3, 8)):
+            bx._lib.check(lib.bxmg_ctx_tune(ctx._h, param, value))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_unit_beta_equals_constant_coefficient(bx, precision):
+    """beta == 1 through the variable-coefficient kernels gives the constant
+    path's bits: harmonic means of 1 and 1, face averages and sums of six
+    ones are exact."""
+    n = 48
+    f = W.uniform_rhs((n, n, n), 28)
+    ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 16, (0, 0, 0), f)
+    ones = bx.MultiFab(ba).set_val(1.0)
+    r1 = bx.mlmg_solve(phi, rhs, fixed_cycles=3, precision=precision)
+    u1 = phi.to_global()
+    phi.set_val(0.0)
+    r2 = bx.mlmg_solve(phi, rhs, ones, fixed_cycles=3, precision=precision)
+    assert np.array_equal(phi.to_global(), u1) and r1.hist == r2.hist
