@@ -303,7 +303,7 @@ def section_serving(bx, W, nreq):
     out = {"workload": "serving_trace_%d_req_200per_s_edges_32-256_dirichlet_tol1e-8..1e-10" % nreq,
            "requests": nreq, "mean_cells": sum(r["q"]["edge"] ** 3 for r in reqs) / nreq,
            "lognormal_share": sum(r["q"]["kind"] for r in reqs) / nreq}
-    srv = bx.Server(ctx, 24 << 30, max_problems=512, chunk=1, precision=1)
+    srv = bx.Server(ctx, 24 << 30, max_problems=512, chunk=2, precision=1)
     # warm-up: one request of each kind through the server
     for r in reqs[:2]:
         srv.submit(-1, r["phi"], r["rhs"], r["beta"], r["q"]["tol"])
@@ -352,9 +352,19 @@ def section_serving(bx, W, nreq):
 
 
 def summarize_trace(csv_path, out_path, command):
-    """The rocprofv3 --stats kernel table (csv) as a short text summary."""
+    """The rocprofv3 --stats kernel table (csv) as a short text summary, and,
+    from the kernel trace next to it, the same kernels split by launch size
+    (the largest grids of the level kernels are the finest level's)."""
     import csv
     rows = list(csv.DictReader(open(csv_path)))
+    trace = csv_path.replace("kernel_stats.csv", "kernel_trace.csv")
+    by_grid = {}
+    if os.path.exists(trace):
+        for r in csv.DictReader(open(trace)):
+            key = (r["Kernel_Name"], int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
+            d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            n, t = by_grid.get(key, (0, 0))
+            by_grid[key] = (n + 1, t + d)
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
     lines = ["# rocprofv3 --kernel-trace --stats summary", "# command: " + command,
              "# %d kernels, %.3f ms total GPU time" % (len(rows), tot / 1e6),
@@ -363,6 +373,14 @@ def summarize_trace(csv_path, out_path, command):
         name = r["Name"] if len(r["Name"]) <= 90 else r["Name"][:87] + "..."
         lines.append("%-90s %8d %12.1f %12.2f %7.2f" % (name, int(r["Calls"]), float(r["TotalDurationNs"]) / 1e3,
                                                         float(r["AverageNs"]) / 1e3, 100.0 * float(r["TotalDurationNs"]) / tot))
+    if by_grid:
+        lines += ["", "# by launch size (threads per launch), kernels above 1% of the time",
+                  "%-90s %12s %8s %12s" % ("kernel", "threads", "calls", "avg_us")]
+        big = {r["Name"] for r in rows if 100.0 * float(r["TotalDurationNs"]) / tot >= 1.0}
+        for (name, g), (n, t) in sorted(by_grid.items(), key=lambda kv: (kv[0][0], -kv[0][1])):
+            if name in big:
+                short = name if len(name) <= 90 else name[:87] + "..."
+                lines.append("%-90s %12d %8d %12.2f" % (short, g, n, t / n / 1e3))
     open(out_path, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines[:25]))
 

@@ -627,8 +627,7 @@ void b_vcycle(bxmg_batch_s* b, hipStream_t s) {
     for (int l = b->lmax - 1; l >= 0; --l) {
         BLevel& B = b->lev[l];
         HIPCHK(launch_fill_sets(s, u, f32, B.fullc.p(), B.nfullc, B.mfullc, b->active.p));
-        HIPCHK(launch_prolong<T>(s, level_grid(b, l), b->lev[l + 1].rb.p(), B.cbox.p(), u, u, b->P.prolong,
-                                 b->lev[l + 1].res));
+        HIPCHK(launch_prolong<T>(s, level_grid(b, l), b->lev[l + 1].rb.p(), B.cbox.p(), u, u, b->P.prolong));
         b_smooth<T>(b, s, l, b->P.nu2);
     }
 }
@@ -952,7 +951,13 @@ static bxmg_status batch_collect(bxmg_batch b, int32_t* nrunning) {
                     retire_enqueue(b, m, !(b->h_st[m].status == kStatusNonFinite && b->h_st[m].nhist == 0));
                 HIPCHK(hipStreamSynchronize(s));
                 for (int m : stopped) retire_finish(b, m);
-                b->dirty = true;
+                // retired problems cost only idle blocks; the launch lists are
+                // rebuilt when problems join (add marks them) or once a
+                // quarter of the running set has left
+                int left = 0;
+                for (int m : b->members)
+                    if (!b->slots[m]) ++left;
+                if (4 * left > (int)b->members.size()) b->dirty = true;
             }
         }
     } catch (HipError& e) {

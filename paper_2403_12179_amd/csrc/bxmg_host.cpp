@@ -436,7 +436,7 @@ void vcycle(Run& R, size_t l) {
     vcycle<T>(R, l + 1);
     fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full);
     R.pre(l, kStageProlong);
-    HIPCHK(launch_prolong<T>(R.s, L.walk(), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong, C.res ? 1 : 0));
+    HIPCHK(launch_prolong<T>(R.s, L.walk(), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong));
     R.post(l, kStageProlong);
     smooth<T>(R, l, R.nu2);
 }
@@ -1117,8 +1117,7 @@ bxmg_status bxmg_prolong_add(bxmg_ctx ctx, bxmg_multifab coarse, bxmg_multifab f
         HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)fine->data, fine->d_fboxes.p, H->u64[0]->p, false));
         HIPCHK(launch_fab_to_rb(R.s, L1.grid(), (const double*)coarse->data, coarse->d_fboxes.p, H->u64[1]->p, false));
         fill<double>(R, 1, H->u64[1]->p, L1.full);
-        HIPCHK(launch_prolong<double>(R.s, L0.grid(), L1.d_rb.p, L0.cbox.p, H->u64[1]->p, H->u64[0]->p, order,
-                                      L1.res ? 1 : 0));
+        HIPCHK(launch_prolong<double>(R.s, L0.grid(), L1.d_rb.p, L0.cbox.p, H->u64[1]->p, H->u64[0]->p, order));
         HIPCHK(launch_rb_to_fab(R.s, L0.grid(), H->u64[0]->p, (double*)fine->data, fine->d_fboxes.p));
         HIPCHK(hipStreamSynchronize(R.s));
     } catch (HipError& e) {

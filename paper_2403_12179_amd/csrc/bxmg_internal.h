@@ -197,11 +197,11 @@ template <class T>
 hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* fc);
 // fine += P coarse: one thread per pair of fine cells (2I, 2I+1) over the
 // fine level's colour tiles (fine boxes pair aligned); cbox[b] = coarse box
-// holding the coarsened fine box b; cres: the coarse boxes allow 32-bit
-// buffer addressing too
+// holding the coarsened fine box b (plain 32-bit offsets from the box starts:
+// buffer addressing measured slower for this kernel)
 template <class T>
 hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
-                          int order, int cres);
+                          int order);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n);

@@ -560,18 +560,19 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(XGrid x, const T* __r
     const TileThread th = tile_thread(tl);
     const int I = (B.lo[0] >> 1) + th.x, J = (B.lo[1] >> 1) + th.y;
     if (I > (B.hi[0] >> 1) || J > (B.hi[1] >> 1)) return;
-    if constexpr (MODE == 0) {
-        // The 8 children's stencils touch 32 distinct cells of u: the 2x2x2
-        // block and the 4 cells beyond each of its 6 faces.  Load each once
-        // (v[x][y][z], offsets -1..2 around the block's lower corner), then
-        // form the 8 residuals as resid_at does.
+    if constexpr (MODE != 2) {
+        // The 8 children's stencils touch 32 distinct cells of u (and of the
+        // cell beta): the 2x2x2 block and the 4 cells beyond each of its 6
+        // faces.  Load each once (v[x][y][z], offsets -1..2 around the
+        // block's lower corner), then form the 8 residuals as resid_at does.
         const BoxRes<T> U(u + B.base, 2 * B.cstride), F(f + B.base, 2 * B.cstride);
+        const BoxRes<T> Bt((MODE == 1 ? beta : f) + B.base, 2 * B.cstride);
         const BoxRes<T> Cw(fc + C.base, 2 * C.cstride);
         for (int z = 0; z < (int)tl.zc; ++z) {
             const int K = (B.lo[2] >> 1) + th.z0 + z * th.dz;
             if (K > (B.hi[2] >> 1)) break;
             const int i = 2 * I, j = 2 * J, k = 2 * K;
-            T v[4][4][4], fv[2][2][2];
+            T v[4][4][4], bv[4][4][4], fv[2][2][2];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -583,6 +584,10 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(XGrid x, const T* __r
                         const int o = rb_off(B, i - 1 + a, j - 1 + b, k - 1 + c);
                         if (x.res) v[a][b][c] = U.ld(o);
                         else v[a][b][c] = u[B.base + o];
+                        if constexpr (MODE == 1) {
+                            if (x.res) bv[a][b][c] = Bt.ld(o);
+                            else bv[a][b][c] = beta[B.base + o];
+                        }
                         if (outer == 0) {
                             if (x.res) fv[a - 1][b - 1][c - 1] = F.ld(o);
                             else fv[a - 1][b - 1][c - 1] = f[B.base + o];
@@ -603,8 +608,17 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(XGrid x, const T* __r
                         n.zm = v[a][b][c - 1];
                         n.zp = v[a][b][c + 1];
                         n.c = v[a][b][c];
+                        if constexpr (MODE == 1) {
+                            n.bxm = bv[a - 1][b][c];
+                            n.bxp = bv[a + 1][b][c];
+                            n.bym = bv[a][b - 1][c];
+                            n.byp = bv[a][b + 1][c];
+                            n.bzm = bv[a][b][c - 1];
+                            n.bzp = bv[a][b][c + 1];
+                            n.bc = bv[a][b][c];
+                        }
                         T su, sb;
-                        sums<T, 0>(n, su, sb);
+                        sums<T, MODE>(n, su, sb);
                         r[a - 1][b - 1][c - 1] = fv[a - 1][b - 1][c - 1] - (su - sb * n.c) * ih2;
                     }
             const T s = ((r[0][0][0] + r[1][0][0]) + (r[0][1][0] + r[1][1][0])) +
@@ -672,7 +686,7 @@ __device__ __forceinline__ T prolong_e(const T a[4][3], int x, int order) {
     return (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) * T(0.015625);
 }
 
-template <class T, bool PUSH, bool RES>
+template <class T, bool PUSH>
 __global__ void __launch_bounds__(kBlock) k_prolong(Grid g, const RBox* __restrict__ cboxes, const int* __restrict__ cbox,
                                                    const T* __restrict__ ec, T* __restrict__ uf, int order) {
     const Tile tl = g.tiles[tile_index(g.rev)];
@@ -684,7 +698,8 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid g, const RBox* __restri
     const int i0 = B.lo[0] + 2 * th.x;  // the even cell of the pair
     if (j > B.hi[1] || i0 > B.hi[0]) return;
     const int J = j >> 1, sj = (j & 1) ? 1 : -1, I = i0 >> 1;
-    const BoxRes<T> Cr(ec + C.base, 2 * C.cstride), Fr(uf + B.base, 2 * B.cstride);
+    const T* __restrict__ cb = ec + C.base;
+    T* __restrict__ fb = uf + B.base;
     for (int z = 0; z < (int)tl.zc; ++z) {
         const int k = B.lo[2] + th.z0 + z * th.dz;
         if (k > B.hi[2]) break;
@@ -697,24 +712,14 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid g, const RBox* __restri
 #pragma unroll
             for (int x = 0; x < 3; ++x) {
                 if (order == 1 && x != 1) continue;
-                const int o = rb_off(C, I - 1 + x, rj[r], rk[r]);
-                if constexpr (RES) a[r][x] = Cr.ld(o);
-                else a[r][x] = ec[C.base + o];
+                a[r][x] = cb[rb_off(C, I - 1 + x, rj[r], rk[r])];
             }
         }
         const int oe = rb_off(B, i0, j, k), oo = rb_off(B, i0 + 1, j, k);
-        T ve, vo;
-        if constexpr (RES) {
-            ve = Fr.ld(oe) + prolong_e<T>(a, 0, order);
-            vo = Fr.ld(oo) + prolong_e<T>(a, 2, order);
-            Fr.st(oe, ve);
-            Fr.st(oo, vo);
-        } else {
-            ve = uf[B.base + oe] + prolong_e<T>(a, 0, order);
-            vo = uf[B.base + oo] + prolong_e<T>(a, 2, order);
-            uf[B.base + oe] = ve;
-            uf[B.base + oo] = vo;
-        }
+        const T ve = fb[oe] + prolong_e<T>(a, 0, order);
+        const T vo = fb[oo] + prolong_e<T>(a, 2, order);
+        fb[oe] = ve;
+        fb[oo] = vo;
         if constexpr (PUSH) {
             push_ghosts(uf, g.boxes, B, i0, j, k, ve);
             push_ghosts(uf, g.boxes, B, i0 + 1, j, k, vo);
@@ -1305,23 +1310,16 @@ template hipError_t launch_restrict_plain<double>(hipStream_t, const XGrid&, con
 
 template <class T>
 hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
-                          int order, int cres) {
+                          int order) {
     if (fine.ntiles <= 0) return hipSuccess;
     const dim3 G(fine.ntiles), B(kBlock);
-#define BXMG_PR(PUSH, RES) hipLaunchKernelGGL((k_prolong<T, PUSH, RES>), G, B, 0, s, fine, cboxes, cbox, ec, uf, order)
-    const bool res = fine.res && cres;
-    if (fine.push) {
-        if (res) BXMG_PR(true, true); else BXMG_PR(true, false);
-    } else {
-        if (res) BXMG_PR(false, true); else BXMG_PR(false, false);
-    }
-#undef BXMG_PR
+    if (fine.push) hipLaunchKernelGGL((k_prolong<T, true>), G, B, 0, s, fine, cboxes, cbox, ec, uf, order);
+    else hipLaunchKernelGGL((k_prolong<T, false>), G, B, 0, s, fine, cboxes, cbox, ec, uf, order);
     return hipGetLastError();
 }
 template hipError_t launch_prolong<double>(hipStream_t, const Grid&, const RBox*, const int*, const double*, double*,
-                                           int, int);
-template hipError_t launch_prolong<float>(hipStream_t, const Grid&, const RBox*, const int*, const float*, float*, int,
-                                          int);
+                                           int);
+template hipError_t launch_prolong<float>(hipStream_t, const Grid&, const RBox*, const int*, const float*, float*, int);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n) {

@@ -155,12 +155,21 @@ class Batch:
         L.check(L.lib().bxmg_batch_collect(self._h, C.byref(n)))
         return n.value
 
-    def poll(self, max_results=64):
-        ids = (C.c_int64 * max_results)()
-        infos = (L.SolveInfo * max_results)()
-        n = C.c_int32()
-        L.check(L.lib().bxmg_batch_poll(self._h, int(max_results), ids, infos, C.byref(n)))
-        return [(ids[i], _result(infos[i])) for i in range(n.value)]
+    def poll(self, max_results=None):
+        """Finished problems [(id, SolveResult)], oldest first (all of them
+        when max_results is None), in chunks of at most 64 per library call."""
+        out = []
+        chunk = 64
+        ids = (C.c_int64 * chunk)()
+        infos = (L.SolveInfo * chunk)()
+        while max_results is None or len(out) < max_results:
+            want = chunk if max_results is None else min(chunk, max_results - len(out))
+            n = C.c_int32()
+            L.check(L.lib().bxmg_batch_poll(self._h, int(want), ids, infos, C.byref(n)))
+            out += [(ids[i], _result(infos[i])) for i in range(n.value)]
+            if n.value < want:
+                break
+        return out
 
     def remove(self, pid):
         L.check(L.lib().bxmg_batch_remove(self._h, int(pid)))
@@ -176,7 +185,6 @@ class Batch:
         out = []
         while True:
             n = self.step(chunk)
-            out += self.poll(1 << 16)
+            out += self.poll()
             if n == 0:
-                out += self.poll(1 << 16)
                 return out
