@@ -112,7 +112,7 @@ def traffic_from_counters():
     return c.get("hbm_bytes_per_launch")
 
 
-def summarize_counters(d):
+def summarize_counters(d, knobs=""):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the level-0 GS launches
     and of the 1 GiB elementwise calibration kernel, from the rocprofv3 --pmc
     databases under d/fetch and d/write; writes the committed summary."""
@@ -137,7 +137,11 @@ def summarize_counters(d):
         return list(vals.values())
 
     level0_threads = (N ** 3) // 2 // 4  # one colour of level 0, >= 1 cell per thread
-    out = {"kernel": GS_KERNEL, "workload": "256^3 in 512 boxes of 32^3, FP64", "kernel_src_sha": src_sha()}
+    out = {"kernel": GS_KERNEL, "workload": "256^3 in 512 boxes of 32^3, FP64", "kernel_src_sha": src_sha(),
+           "commands": ["cd /tmp && timeout -s KILL 300 rocprofv3 --pmc %s -d $REPO/%s/%s -o c2 -- python3 "
+                        "$REPO/bench.py --steps 1 --warmup 0 --no-cpu-baseline --sections '' --knobs %s "
+                        "--calibrate-copy" % (c, os.path.normpath(d), sub, knobs or "<autotuned>")
+                        for c, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write"))]}
     for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
         rs = rows(sub, counter)
         gs = per_dispatch(rs, "k_gs", level0_threads)
@@ -393,6 +397,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--summarize-counters", metavar="DIR")
+    ap.add_argument("--knobs-used", default="",
+                    help="launch shape the counter runs used (recorded with --summarize-counters)")
     ap.add_argument("--sections", default="mixed,batched,serving",
                     help="other rows to measure after the headline (comma list; '' for none)")
     ap.add_argument("--serving-requests", type=int, default=400)
@@ -403,7 +409,7 @@ def main():
     args = ap.parse_args()
 
     if args.summarize_counters:
-        summarize_counters(args.summarize_counters)
+        summarize_counters(args.summarize_counters, args.knobs_used)
         return 0
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)

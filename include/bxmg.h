@@ -120,6 +120,13 @@ bxmg_status bxmg_multifab_box_view(bxmg_multifab mf, int32_t box, void** dptr, i
 bxmg_status bxmg_multifab_info(bxmg_multifab mf, void** base, size_t* bytes, int32_t* ncomp, int32_t* nghost,
                                int32_t* dtype);
 
+/* Copies component `comp` of the valid cells between the MultiFab and a
+ * host array over the whole domain in Fortran order (x fastest), of the
+ * MultiFab's dtype (to_device != 0: host -> MultiFab).  Ghost cells and the
+ * other components keep their values.  Goes through a host copy of the
+ * slab; synchronous on hip_stream (NULL = the context's stream). */
+bxmg_status bxmg_multifab_copy_host(bxmg_multifab mf, int32_t to_device, void* host, int32_t comp, void* hip_stream);
+
 /* Releases the handle.  Library-owned memory is freed after the work already
  * queued on the context's stream has completed (stream-ordered free). */
 void bxmg_multifab_release(bxmg_multifab mf);
@@ -190,7 +197,9 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
  * 32-bit buffer offsets where every box allows it (1, default) or with
  * 64-bit addresses (0).  Other values: EINVAL.  Results do not depend on the
  * knobs; only the work decomposition and instruction selection do.
- * param 3 = at most 2^value threads of a tile along y (0..8, default 8). */
+ * param 3 = at most 2^value threads of a tile along y (0..8, default 8).
+ * param 4 = the fused coarse cycle keeps its levels' data in LDS when it
+ * fits (1, default) or works on device memory (0). */
 bxmg_status bxmg_ctx_tune(bxmg_ctx ctx, int32_t param, int32_t value);
 
 /* Launch-shape autotuner: solves the given problem for `cycles` V-cycles
@@ -210,7 +219,8 @@ bxmg_status bxmg_autotune(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_mu
  * every launch of one stage on the finest level (level 0) during solves:
  *   0 red-black Gauss-Seidel colour, 1 convergence residual + norms,
  *   2 residual + restriction, 3 prolongation + correction,
- *   4 ghost fills of the solution; -1 switches timing off (default).
+ *   4 ghost fills of the solution, 5 the fused coarse cycle (whichever
+ *   level it starts at); -1 switches timing off (default).
  * Times accumulate until read; the events add a few microseconds per timed
  * launch to the stream. */
 bxmg_status bxmg_profile_stage(bxmg_ctx ctx, int32_t stage);

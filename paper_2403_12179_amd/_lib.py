@@ -60,6 +60,7 @@ def _declare(lib):
         "bxmg_alloc_multifab": (C.c_int, [H, H, C.c_int32, C.c_int32, C.c_int, VP, C.POINTER(H)]),
         "bxmg_multifab_box_view": (C.c_int, [H, C.c_int32, C.POINTER(VP), I32P, I32P, I64P]),
         "bxmg_multifab_info": (C.c_int, [H, C.POINTER(VP), C.POINTER(C.c_size_t), I32P, I32P, I32P]),
+        "bxmg_multifab_copy_host": (C.c_int, [H, C.c_int32, VP, C.c_int32, VP]),
         "bxmg_multifab_release": (None, [H]),
         "bxmg_fill_boundary": (C.c_int, [H, C.c_int32, C.c_int32, C.c_int32, VP]),
         "bxmg_apply_domain_bc": (C.c_int, [H, C.c_int32, C.c_int32, C.c_int32, VP]),

@@ -263,6 +263,15 @@ class MultiFab:
             v[ng:v.shape[0] - ng, ng:v.shape[1] - ng, ng:v.shape[2] - ng].copy_(src)
         return self
 
+    def copy_host(self, glob, to_device, comp=0):
+        """bxmg_multifab_copy_host: valid cells of component comp <-> a
+        domain-sized F-order numpy array of the MultiFab's dtype."""
+        dt = np.float64 if self.dtype == "f64" else np.float32
+        assert glob.dtype == dt and glob.flags.f_contiguous and glob.shape == self.ba.domain.size
+        L.check(L.lib().bxmg_multifab_copy_host(self._h, 1 if to_device else 0, glob.ctypes.data_as(C.c_void_p),
+                                                int(comp), C.c_void_p(self.ctx.stream.cuda_stream)))
+        return glob
+
     def from_packed(self, packed):
         """Set all cells (valid + ghost) from the oracle's packed layout."""
         import torch

@@ -173,9 +173,8 @@ void plan_device(GeoPlan& P, const bxmg_ctx_s* ctx, bool var) {
     for (size_t l = 0; l < P.L.size(); ++l) {
         PlanLevel& v = P.L[l];
         if ((int)l < P.cs) {
-            TileSet tc = make_tiles(v.ecol, ctx->zc, ctx->ly_cap);
-            if (tc.sh.lz == 0) tc = make_tiles(v.ecol, ctx->zc_planes, ctx->ly_cap);
-            v.tcol = tc.tiles;
+            // batched launches have many problems' tiles: no minimum per problem
+            v.tcol = level_tiles(v.ecol, ctx->zc, ctx->zc_planes, ctx->ly_cap, 0).tiles;
             v.tdown = make_tiles(v.edown, ctx->zc, ctx->ly_cap).tiles;
         }
         const std::vector<Tag> faces = build_tags(v.dom, P.per, v.boxes, 1, true, 2, true);
@@ -205,8 +204,12 @@ void plan_device(GeoPlan& P, const bxmg_ctx_s* ctx, bool var) {
     P.rb1.upload(P.L[1].rb);
     P.cbox0.upload(L0.cbox);
     P.res0 = (ctx->res && boxes_fit_res(L0.rb)) ? 1 : 0;
-    P.t0.upload(L0.tcol);
-    P.nt0 = (int)L0.tcol.size();
+    // the problem's own level-0 tiles, exactly those of a lone solve: the
+    // conversions, the norm of f and the periodic mean run over them
+    const std::vector<Tile> t0 =
+        level_tiles(L0.ecol, ctx->zc, ctx->zc_planes, ctx->ly_cap, kMinLevelTiles).tiles;
+    P.t0.upload(t0);
+    P.nt0 = (int)t0.size();
     if (var) {
         P.full_even0.upload(ghost_list(build_tags(L0.dom, P.per, L0.boxes, 1, false, 2, false), L0.rb, 3));
         for (int d = 0; d < 3; ++d) {
@@ -309,6 +312,7 @@ struct bxmg_batch_s {
     DevVec<CoarseCycle<double>> cc64;
     DevVec<CoarseCycle<float>> cc32;
     int ncc = 0;
+    int cc_lds = 0;  // dynamic LDS of the coarse-cycle launch
     bool use_graph = true;
     int stable = 0;         // launches since the running set last changed
     bool inflight = false;  // cycles launched and not yet collected
@@ -532,14 +536,21 @@ void rebuild(bxmg_batch_s* b) {
                 B.fat32.assign(t);
             }
         }
-    // fused coarse cycles
+    // fused coarse cycles (dynamic LDS: the largest need of a member)
+    b->cc_lds = 0;
     if (b->prec == 0) {
         std::vector<CoarseCycle<double>> cc;
-        for (int s : b->members) cc.push_back(coarse_desc<double>(b, *b->slots[s], b->u64.p, b->f64.p, b->fa64.p));
+        for (int s : b->members) {
+            cc.push_back(coarse_desc<double>(b, *b->slots[s], b->u64.p, b->f64.p, b->fa64.p));
+            b->cc_lds = std::max(b->cc_lds, coarse_lds_layout<double>(cc.back(), b->ctx->lds_coarse));
+        }
         b->cc64.assign(cc);
     } else {
         std::vector<CoarseCycle<float>> cc;
-        for (int s : b->members) cc.push_back(coarse_desc<float>(b, *b->slots[s], b->u32.p, b->f32.p, b->fa32.p));
+        for (int s : b->members) {
+            cc.push_back(coarse_desc<float>(b, *b->slots[s], b->u32.p, b->f32.p, b->fa32.p));
+            b->cc_lds = std::max(b->cc_lds, coarse_lds_layout<float>(cc.back(), b->ctx->lds_coarse));
+        }
         b->cc32.assign(cc);
     }
     b->ncc = (int)b->members.size();
@@ -623,7 +634,7 @@ void b_vcycle(bxmg_batch_s* b, hipStream_t s) {
         HIPCHK(launch_resid_restrict<T>(s, level_xgrid(b, l), u, f, arena_beta<T>(b, l), level_fat<T>(b, l), f));
         HIPCHK(launch_zero_ranges<T>(s, u, B.zr.p(), B.nzr, B.zmax, b->active.p));
     }
-    HIPCHK(launch_coarse_cycle<T>(s, coarse_descs<T>(b), b->ncc, b->active.p, b->var));
+    HIPCHK(launch_coarse_cycle<T>(s, coarse_descs<T>(b), b->ncc, b->active.p, b->var, b->cc_lds));
     for (int l = b->lmax - 1; l >= 0; --l) {
         BLevel& B = b->lev[l];
         HIPCHK(launch_fill_sets(s, u, f32, B.fullc.p(), B.nfullc, B.mfullc, b->active.p));

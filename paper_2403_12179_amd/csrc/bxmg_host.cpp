@@ -106,6 +106,7 @@ struct Hier {
     DevBuf<CoarseCycle<float>> cc32;
     CoarseCycle<double> cc64_host{};   // ... and what they hold
     CoarseCycle<float> cc32_host{};
+    int cc64_lds = 0, cc32_lds = 0;    // dynamic LDS of the coarse-cycle launch
     DevBuf<double> partials;  // 3 per tile of the largest tiled launch, + 3
     DevBuf<double> fnorm;     // 3
     DevBuf<int> iters;
@@ -162,13 +163,13 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
         lv->res = tune.res && boxes_fit_res(lv->rb);
         lv->d_rb.upload(lv->rb);
         {
-            TileSet ts = make_tiles(colour_extents(lv->boxes), tune.zc, tune.ly_cap);
-            if (ts.sh.lz == 0) ts = make_tiles(colour_extents(lv->boxes), tune.zc_planes, tune.ly_cap);
-            upload_tiles(ts, lv->tcol, lv->ntcol);
+            upload_tiles(level_tiles(colour_extents(lv->boxes), tune.zc, tune.zc_planes, tune.ly_cap, kMinLevelTiles),
+                         lv->tcol, lv->ntcol);
         }
         max_tiles = std::max<long long>(max_tiles, lv->ntcol);
         if (l + 1 < lb.size()) {
-            upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, -1), tune.zc, tune.ly_cap), lv->tdown, lv->ntdown);
+            upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, -1), tune.zc, tune.ly_cap, kMinLevelTiles),
+                         lv->tdown, lv->ntdown);
             lv->cbox.upload(coarse_owner(lv->boxes, lb[l + 1].boxes));
             if (var && l == 0)
                 for (int d = 0; d < 3; ++d)
@@ -337,12 +338,13 @@ struct Run {
     int nu1, nu2, prolong;
     double bottom_rtol;
     Profiler* prof = nullptr;
+    bool lds_coarse = true;  // the fused coarse cycle may keep its levels in LDS
     // event brackets around level-0 launches of the profiled stage
     void pre(size_t l, int stage) { if (prof && prof->stage == stage && l == 0) prof->mark(s); }
     void post(size_t l, int stage) { if (prof && prof->stage == stage && l == 0) prof->mark(s); }
 };
 
-enum { kStageGS = 0, kStageResid = 1, kStageRestrict = 2, kStageProlong = 3, kStageFill = 4 };
+enum { kStageGS = 0, kStageResid = 1, kStageRestrict = 2, kStageProlong = 3, kStageFill = 4, kStageCoarse = 5 };
 
 template <class T>
 void fill(Run& R, size_t l, T* data, const GhostList& g) {
@@ -397,18 +399,30 @@ CoarseCycle<float>& cc_host<float>(Hier* H) { return H->cc32_host; }
 
 // the fused coarse cycle; its descriptor is uploaded when the settings change
 template <class T>
+int& cc_lds(Hier* H);
+template <>
+int& cc_lds<double>(Hier* H) { return H->cc64_lds; }
+template <>
+int& cc_lds<float>(Hier* H) { return H->cc32_lds; }
+
+template <class T>
 void coarse_cycle(Run& R) {
     Hier* H = R.H;
     static_assert(std::is_trivially_copyable<CoarseCycle<T>>::value, "descriptor must be plain data");
     DevBuf<CoarseCycle<T>>& buf = cc_buf<T>(H);
     CoarseCycle<T>& host = cc_host<T>(H);
-    const CoarseCycle<T> cc = coarse_desc<T>(H, R.nu1, R.nu2, R.prolong, R.bottom_rtol);
+    CoarseCycle<T> cc = coarse_desc<T>(H, R.nu1, R.nu2, R.prolong, R.bottom_rtol);
+    const int lds = coarse_lds_layout<T>(cc, R.lds_coarse);
     if (!buf.p || std::memcmp(&cc, &host, sizeof cc) != 0) {
         if (!buf.p) buf.alloc(1);
         host = cc;  // lives as long as the hierarchy: safe source for the async copy
+        cc_lds<T>(H) = lds;
         HIPCHK(hipMemcpyAsync(buf.p, &host, sizeof host, hipMemcpyHostToDevice, R.s));
     }
-    HIPCHK(launch_coarse_cycle<T>(R.s, buf.p, 1, nullptr, H->var));
+    // the correction on the top level starts from zero (in LDS, the kernel
+    // zeroes its copy and writes the whole level back)
+    if (!host.lds) HIPCHK(launch_zero<T>(R.s, lvl_u<T>(H, H->coarse_start), H->L[H->coarse_start]->nelem));
+    HIPCHK(launch_coarse_cycle<T>(R.s, buf.p, 1, nullptr, H->var, cc_lds<T>(H)));
 }
 
 template <class T>
@@ -416,7 +430,9 @@ void vcycle(Run& R, size_t l) {
     Hier* H = R.H;
     const size_t last = H->L.size() - 1;
     if ((int)l == H->coarse_start) {
+        R.pre(0, kStageCoarse);
         coarse_cycle<T>(R);
+        R.post(0, kStageCoarse);
         return;
     }
     if (l == last) {
@@ -432,7 +448,8 @@ void vcycle(Run& R, size_t l) {
     HIPCHK(launch_resid_restrict<T>(R.s, H->xwalk(l), u, lvl_f<T>(H, l), lvl_beta<T>(H, l), lvl_fat<T>(H, l),
                                     lvl_f<T>(H, l + 1)));
     R.post(l, kStageRestrict);
-    HIPCHK(launch_zero<T>(R.s, lvl_u<T>(H, l + 1), C.nelem));
+    // the fused coarse cycle zeroes its top level itself
+    if ((int)l + 1 != H->coarse_start) HIPCHK(launch_zero<T>(R.s, lvl_u<T>(H, l + 1), C.nelem));
     vcycle<T>(R, l + 1);
     fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full);
     R.pre(l, kStageProlong);
@@ -467,6 +484,28 @@ double norm_readback(Run& R, double* h_norm, const double* dev) {
 }  // namespace
 
 // ================================================================== C ABI
+// Host scatter/gather of one component between a domain-sized F-order host
+// array and the valid cells of every box, through a host copy of the slab.
+template <class T>
+static void copy_valid(bxmg_multifab mf, std::vector<unsigned char>& slab, T* glob, int comp, bool to_dev) {
+    T* sl = (T*)slab.data();
+    const Box& D = mf->ba->dom;
+    const long long nx = D.n(0), ny = D.n(1);
+    for (size_t b = 0; b < mf->fboxes.size(); ++b) {
+        const FBox& f = mf->fboxes[b];
+        for (int k = f.lo[2]; k <= f.hi[2]; ++k)
+            for (int j = f.lo[1]; j <= f.hi[1]; ++j) {
+                T* row = sl + f.base + comp * f.cs +
+                         (long long)(f.lo[0] - f.glo[0]) +
+                         (long long)f.G[0] * ((long long)(j - f.glo[1]) + (long long)f.G[1] * (k - f.glo[2]));
+                T* g = glob + (long long)(f.lo[0] - D.lo[0]) + nx * ((long long)(j - D.lo[1]) + ny * (k - D.lo[2]));
+                const int n = f.hi[0] - f.lo[0] + 1;
+                if (to_dev) std::memcpy(row, g, n * sizeof(T));
+                else std::memcpy(g, row, n * sizeof(T));
+            }
+    }
+}
+
 extern "C" {
 
 int bxmg_version(void) { return 100; }
@@ -652,6 +691,28 @@ bxmg_status bxmg_multifab_info(bxmg_multifab mf, void** base, size_t* bytes, int
     return BXMG_OK;
 }
 
+bxmg_status bxmg_multifab_copy_host(bxmg_multifab mf, int32_t to_device, void* host, int32_t comp, void* hip_stream) {
+    if (!mf || !host) return fail(BXMG_EINVAL, "multifab_copy_host: NULL argument");
+    if (comp < 0 || comp >= mf->ncomp) return fail(BXMG_EINVAL, "multifab_copy_host: component out of range");
+    try {
+        HIPCHK(hipSetDevice(mf->ctx->device));
+        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : mf->ctx->stream;
+        std::vector<unsigned char> slab(mf->bytes);
+        // the whole slab: ghosts and other components keep their values
+        HIPCHK(hipMemcpyAsync(slab.data(), mf->data, mf->bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (mf->dtype == BXMG_F64) copy_valid<double>(mf, slab, (double*)host, comp, to_device != 0);
+        else copy_valid<float>(mf, slab, (float*)host, comp, to_device != 0);
+        if (to_device) {
+            HIPCHK(hipMemcpyAsync(mf->data, slab.data(), mf->bytes, hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+    } catch (HipError& e) {
+        return fail(BXMG_EDEVICE, std::string("multifab_copy_host: ") + hipGetErrorString(e.e));
+    }
+    return BXMG_OK;
+}
+
 void bxmg_multifab_release(bxmg_multifab mf) {
     if (!mf) return;
     (void)hipSetDevice(mf->ctx->device);
@@ -814,6 +875,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         info->levels = (int)H->L.size();
         Run R{H, ctx->stream, P.nu1, P.nu2, P.prolong, P.bottom_rtol};
         R.prof = &ctx->prof;
+        R.lds_coarse = ctx->lds_coarse != 0;
         const Level& L0 = *H->L[0];
         double* u = H->u64[0]->p;
         double* f = H->f64[0]->p;
@@ -902,15 +964,16 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
 
 bxmg_status bxmg_ctx_tune(bxmg_ctx ctx, int32_t param, int32_t value) {
     if (!ctx) return fail(BXMG_EINVAL, "ctx_tune: NULL context");
-    if (param < 0 || param > 3) return fail(BXMG_EINVAL, "ctx_tune: unknown parameter");
+    if (param < 0 || param > 4) return fail(BXMG_EINVAL, "ctx_tune: unknown parameter");
     if (param <= 1 && (value < 1 || value > 64)) return fail(BXMG_EINVAL, "ctx_tune: value out of range [1, 64]");
-    if (param == 2 && value != 0 && value != 1) return fail(BXMG_EINVAL, "ctx_tune: value must be 0 or 1");
+    if ((param == 2 || param == 4) && value != 0 && value != 1) return fail(BXMG_EINVAL, "ctx_tune: value must be 0 or 1");
     if (param == 3 && (value < 0 || value > 8)) return fail(BXMG_EINVAL, "ctx_tune: value out of range [0, 8]");
     std::lock_guard<std::mutex> lock(ctx->mu);
     if (param == 0) ctx->zc = value;
     else if (param == 1) ctx->zc_planes = value;
     else if (param == 2) ctx->res = value;
-    else ctx->ly_cap = value;
+    else if (param == 3) ctx->ly_cap = value;
+    else ctx->lds_coarse = value;
     return BXMG_OK;
 }
 
@@ -971,7 +1034,7 @@ bxmg_status bxmg_autotune(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_mu
 
 bxmg_status bxmg_profile_stage(bxmg_ctx ctx, int32_t stage) {
     if (!ctx) return fail(BXMG_EINVAL, "profile_stage: NULL context");
-    if (stage < -1 || stage > kStageFill) return fail(BXMG_EINVAL, "profile_stage: unknown stage");
+    if (stage < -1 || stage > kStageCoarse) return fail(BXMG_EINVAL, "profile_stage: unknown stage");
     std::lock_guard<std::mutex> lock(ctx->mu);
     ctx->prof.stage = stage;
     ctx->prof.n = 0;

@@ -250,7 +250,15 @@ inline int ilog2ceil(int n) {
     return l;
 }
 
-inline TileSet make_tiles(const std::vector<std::array<int, 3>>& ext, int zc_target, int ly_cap = 8) {
+// Tiles a level launch should have at least (8 per compute unit of the
+// 256) before threads walk several planes each.
+constexpr long long kMinLevelTiles = 2048;
+
+// min_tiles > 0: walk fewer planes per thread than zc_target where the
+// launch would otherwise have fewer than min_tiles tiles (small levels are
+// latency-bound: more, shallower threads finish sooner).
+inline TileSet make_tiles(const std::vector<std::array<int, 3>>& ext, int zc_target, int ly_cap = 8,
+                          long long min_tiles = 0) {
     int mx = 1, my = 1, mz = 1;
     for (auto& e : ext) { mx = std::max(mx, e[0]); my = std::max(my, e[1]); mz = std::max(mz, e[2]); }
     if (mx > 65535 || my > 65535 || mz > 65535) throw std::runtime_error("a box edge exceeds 65535 cells");
@@ -260,6 +268,13 @@ inline TileSet make_tiles(const std::vector<std::array<int, 3>>& ext, int zc_tar
     t.sh.lz = 8 - t.sh.lx - t.sh.ly;
     const int TX = 1 << t.sh.lx, TY = 1 << t.sh.ly, TZ = 1 << t.sh.lz;
     t.sh.zc = std::max(1, std::min(zc_target, (mz + TZ - 1) / TZ));
+    auto count = [&](int zc) {
+        long long n = 0;
+        for (auto& e : ext)
+            n += (long long)((e[0] + TX - 1) / TX) * ((e[1] + TY - 1) / TY) * ((e[2] + TZ * zc - 1) / (TZ * zc));
+        return n;
+    };
+    while (t.sh.zc > 1 && count(t.sh.zc) < min_tiles) t.sh.zc = std::max(1, t.sh.zc / 2);
     const int KZ = TZ * t.sh.zc;
     for (size_t b = 0; b < ext.size(); ++b)
         for (int z0 = 0; z0 < ext[b][2]; z0 += KZ)
@@ -278,6 +293,17 @@ inline TileSet make_tiles(const std::vector<std::array<int, 3>>& ext, int zc_tar
                     t.tiles.push_back(tl);
                 }
     return t;
+}
+
+// The colour-cell tiles of a level: zc planes per thread, or zc_planes where
+// a tile spans whole box planes.  The single-problem solver uses them for its
+// level launches and the periodic mean; a batch uses the same level-0 tiles
+// for the mean, so both sum the mean in the same order.
+inline TileSet level_tiles(const std::vector<std::array<int, 3>>& ecol, int zc, int zc_planes, int ly_cap,
+                           long long min_tiles) {
+    TileSet ts = make_tiles(ecol, zc, ly_cap, min_tiles);
+    if (ts.sh.lz == 0) ts = make_tiles(ecol, zc_planes, ly_cap, min_tiles);
+    return ts;
 }
 
 // Colour-cell extents: ceil(nx/2) cells of one colour per row.
@@ -523,6 +549,7 @@ struct bxmg_ctx_s {
     int zc = 4, zc_planes = 4;  // tile depths for hierarchies built from now on
     int res = 1;                // 32-bit buffer addressing where the boxes allow it
     int ly_cap = 8;             // at most 2^ly_cap threads of a tile along y
+    int lds_coarse = 1;         // fused coarse cycle keeps its levels in LDS when they fit
     std::map<std::string, std::unique_ptr<Hier>> cache;  // by geometry and settings
     std::deque<std::string> lru;                          // cache keys, least recently used first
     double* h_norm = nullptr;  // pinned

@@ -150,10 +150,20 @@ struct CoarseCycle {
     int nu1, nu2, prolong;
     int per[3];
     int pid;  // problem slot (checked against the active flags of a batch)
+    // lds != 0: u and f of level m live at byte offsets lds_u[m], lds_f[m] of
+    // the workgroup's dynamic LDS; the bottom CG's vectors at bot_off
+    int lds;
+    int lds_u[kMaxCoarseLevels], lds_f[kMaxCoarseLevels];
+    int bot_off;
     double rtol;
     int* iters;
     CoarseLevel<T> L[kMaxCoarseLevels];
 };
+
+// LDS of the bottom CG over n cells (ngrown with its ghost layer).
+inline size_t bottom_lds_bytes(int n, int ngrown) { return 8 * ((size_t)ngrown + 3 * (size_t)n + 40); }
+// LDS a workgroup may take on this device (bytes); queried once.
+int lds_limit_bytes();
 
 // Per-problem state of a batch, one entry per slot, in device memory.
 struct BatchSlot {
@@ -228,9 +238,15 @@ hipError_t launch_bottom(hipStream_t s, T* u, const T* f, FaceArrays<T> fa, bool
                          int* iters_out);
 
 // the fused coarse V-cycle, one workgroup per descriptor cc[0..n); with
-// active != nullptr a descriptor whose problem slot is inactive is skipped
+// active != nullptr a descriptor whose problem slot is inactive is skipped;
+// lds_bytes: dynamic LDS per workgroup (the largest descriptor's need)
 template <class T>
-hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, int n, const int* active, bool var);
+hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, int n, const int* active, bool var,
+                               int lds_bytes);
+// LDS layout of a coarse cycle (sets cc.lds, offsets, bot_off); returns the
+// bytes it needs.  Levels go to LDS when everything fits in lds_limit_bytes().
+template <class T>
+int coarse_lds_layout(CoarseCycle<T>& cc, bool allow_levels);
 
 // ---------------------------------------------------------------- batches
 constexpr int kStatusNoConv = -4;     // = BXMG_ENOCONV

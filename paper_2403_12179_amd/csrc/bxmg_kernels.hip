@@ -489,14 +489,29 @@ __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ 
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm_final(const double* __restrict__ partials, int n,
-                                                      double* __restrict__ out) {
-    __shared__ double sh[3 * (kBlock / 64)];
+// One workgroup of kNormThreads; each thread issues the loads of kNormUnroll
+// partials before adding them (the reduction is latency-bound), in a fixed
+// order, so the result does not depend on timing.
+constexpr int kNormThreads = 1024, kNormUnroll = 4;
+__global__ void __launch_bounds__(kNormThreads) k_norm_final(const double* __restrict__ partials, int n,
+                                                            double* __restrict__ out) {
+    __shared__ double sh[3 * (kNormThreads / 64)];
     double mx = 0.0, s2 = 0.0, bad = 0.0;
-    for (int q = threadIdx.x; q < n; q += blockDim.x) {
-        mx = fmax(mx, partials[3 * q]);
-        s2 = s2 + partials[3 * q + 1];
-        bad = bad + partials[3 * q + 2];
+    for (int q0 = threadIdx.x; q0 < n; q0 += kNormUnroll * kNormThreads) {
+        double a[kNormUnroll][3];
+#pragma unroll
+        for (int v = 0; v < kNormUnroll; ++v) {
+            const int q = q0 + v * kNormThreads;
+            const bool in = q < n;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[v][c] = in ? partials[3 * (long long)q + c] : 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < kNormUnroll; ++v) {
+            mx = fmax(mx, a[v][0]);
+            s2 = s2 + a[v][1];
+            bad = bad + a[v][2];
+        }
     }
     block_reduce3(mx, s2, bad, sh);
     if (threadIdx.x == 0) { out[0] = mx; out[1] = s2; out[2] = bad; }
@@ -678,17 +693,22 @@ __global__ void __launch_bounds__(kBlock) k_restrict_plain(XGrid x, const T* __r
 // coarsened level are pair aligned): the pair shares its parent and its y/z
 // neighbours, so 12 coarse values serve both cells (x = I-1, I, I+1 on the
 // four rows (J, K), (J+sy, K), (J, K+sz), (J+sy, K+sz)).
-template <class T>
-__device__ __forceinline__ T prolong_e(const T a[4][3], int x, int order) {
-    if (order == 1) return a[0][1];
-    const T c000 = a[0][1], c100 = a[0][x], c010 = a[1][1], c001 = a[2][1];
-    const T c110 = a[1][x], c101 = a[2][x], c011 = a[3][1], c111 = a[3][x];
+template <class T, int ORDER>
+__device__ __forceinline__ T prolong_e(const T (&p0)[2][3], const T (&p1)[2][3], int x) {
+    if constexpr (ORDER == 1) return p0[0][1];
+    const T c000 = p0[0][1], c100 = p0[0][x], c010 = p0[1][1], c001 = p1[0][1];
+    const T c110 = p0[1][x], c101 = p1[0][x], c011 = p1[1][1], c111 = p1[1][x];
     return (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) * T(0.015625);
 }
 
-template <class T, bool PUSH>
+// Planes whose fine values one thread loads before it computes any of them:
+// fine u comes from HBM and there are only two such loads per plane, so they
+// are issued as a group to keep enough of them in flight.
+constexpr int kProlongGroup = 4;
+
+template <class T, bool PUSH, int ORDER>
 __global__ void __launch_bounds__(kBlock) k_prolong(Grid g, const RBox* __restrict__ cboxes, const int* __restrict__ cbox,
-                                                   const T* __restrict__ ec, T* __restrict__ uf, int order) {
+                                                   const T* __restrict__ ec, T* __restrict__ uf) {
     const Tile tl = g.tiles[tile_index(g.rev)];
     const RBox B = g.boxes[tl.box];
     if (g.active && !g.active[B.pid]) return;
@@ -700,29 +720,75 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid g, const RBox* __restri
     const int J = j >> 1, sj = (j & 1) ? 1 : -1, I = i0 >> 1;
     const T* __restrict__ cb = ec + C.base;
     T* __restrict__ fb = uf + B.base;
-    for (int z = 0; z < (int)tl.zc; ++z) {
-        const int k = B.lo[2] + th.z0 + z * th.dz;
-        if (k > B.hi[2]) break;
-        const int K = k >> 1, sk = (k & 1) ? 1 : -1;
-        const int rj[4] = {J, J + sj, J, J + sj}, rk[4] = {K, K, K + sk, K + sk};
-        T a[4][3];
+    // The two coarse planes (K and K+sz) a fine plane needs, each as rows J
+    // and J+sy by x = I-1..I+1.  Planes the previous fine plane of this
+    // thread used stay in registers: walking planes 2 apart, one of the two
+    // carries over; walking consecutive planes, one or both do.  All lanes of
+    // a wave walk the same planes, so the reuse tests are wave-uniform.
+    T pa[2][3], pb[2][3];
+    int ka = -0x7fffffff, kb = -0x7fffffff;  // no plane yet
+    auto load_plane = [&](int Kq, T (&pl)[2][3]) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (order == 1 && r > 0) break;
+        for (int r = 0; r < 2; ++r)
 #pragma unroll
             for (int x = 0; x < 3; ++x) {
-                if (order == 1 && x != 1) continue;
-                a[r][x] = cb[rb_off(C, I - 1 + x, rj[r], rk[r])];
+                if (ORDER == 1 && (r > 0 || x != 1)) continue;
+                pl[r][x] = cb[rb_off(C, I - 1 + x, r ? J + sj : J, Kq)];
             }
+    };
+    auto take = [](T (&dst)[2][3], const T (&src)[2][3]) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int x = 0; x < 3; ++x) dst[r][x] = src[r][x];
+    };
+    const int zc = tl.zc;
+    for (int z0 = 0; z0 < zc; z0 += kProlongGroup) {
+        T fe[kProlongGroup], fo[kProlongGroup];
+        int oe[kProlongGroup], oo[kProlongGroup];
+#pragma unroll
+        for (int q = 0; q < kProlongGroup; ++q) {
+            const int k = min(B.lo[2] + th.z0 + (z0 + q) * th.dz, B.hi[2]);  // clamped: loads stay in the box
+            oe[q] = rb_off(B, i0, j, k);
+            oo[q] = rb_off(B, i0 + 1, j, k);
+            fe[q] = fb[oe[q]];
+            fo[q] = fb[oo[q]];
         }
-        const int oe = rb_off(B, i0, j, k), oo = rb_off(B, i0 + 1, j, k);
-        const T ve = fb[oe] + prolong_e<T>(a, 0, order);
-        const T vo = fb[oo] + prolong_e<T>(a, 2, order);
-        fb[oe] = ve;
-        fb[oo] = vo;
-        if constexpr (PUSH) {
-            push_ghosts(uf, g.boxes, B, i0, j, k, ve);
-            push_ghosts(uf, g.boxes, B, i0 + 1, j, k, vo);
+        // one copy of the compute and push code: plane q's values are moved
+        // to slot 0 (static register moves) instead of indexing by q
+#pragma unroll 1
+        for (int q = 0; q < kProlongGroup; ++q) {
+            const int k = B.lo[2] + th.z0 + (z0 + q) * th.dz;
+            if (z0 + q >= zc || k > B.hi[2]) break;
+            const int K = k >> 1, K2 = K + ((k & 1) ? 1 : -1);
+            T p0[2][3], p1[2][3];
+            if (K == ka) take(p0, pa);
+            else if (K == kb) take(p0, pb);
+            else load_plane(K, p0);
+            if constexpr (ORDER != 1) {
+                if (K2 == ka) take(p1, pa);
+                else if (K2 == kb) take(p1, pb);
+                else load_plane(K2, p1);
+                take(pb, p1);
+                kb = K2;
+            }
+            take(pa, p0);
+            ka = K;
+            const T ve = fe[0] + prolong_e<T, ORDER>(p0, p1, 0);
+            const T vo = fo[0] + prolong_e<T, ORDER>(p0, p1, 2);
+            fb[oe[0]] = ve;
+            fb[oo[0]] = vo;
+            if constexpr (PUSH) {
+                push_ghosts(uf, g.boxes, B, i0, j, k, ve);
+                push_ghosts(uf, g.boxes, B, i0 + 1, j, k, vo);
+            }
+#pragma unroll
+            for (int m = 0; m + 1 < kProlongGroup; ++m) {
+                fe[m] = fe[m + 1];
+                fo[m] = fo[m + 1];
+                oe[m] = oe[m + 1];
+                oo[m] = oo[m + 1];
+            }
         }
     }
 }
@@ -879,7 +945,10 @@ __global__ void __launch_bounds__(kBlock) k_faces_coarsen(FaceArrays<T> fine, Fa
 // FP64 conjugate gradients on the coarsest level by one workgroup, vectors
 // in LDS over the level domain (natural order, p with a ghost layer).
 constexpr int kBotThreads = 1024;
-constexpr int kBotGrown = kBottomGrown;
+
+// Dynamic LDS of the one-workgroup kernels (bottom CG, fused coarse cycle);
+// the host sizes it per launch.
+extern __shared__ __align__(16) unsigned char bxmg_lds[];
 
 struct BottomGeom {
     int dlo[3], n[3];
@@ -902,10 +971,17 @@ __device__ __forceinline__ double bot_reduce(double v, double* sh) {
     return sh[32];
 }
 
+// The CG's vectors in LDS: p over the bottom grown by one cell, x, r, q over
+// its N cells, 40 reduction slots (bottom_lds_bytes on the host side).
 struct BottomLds {
-    double p[kBotGrown];
-    double x[kMaxBottomCells], r[kMaxBottomCells], q[kMaxBottomCells];
-    double sh[40];
+    double *p, *x, *r, *q, *sh;
+    __device__ BottomLds(unsigned char* base, int n, int ngrown) {
+        p = (double*)base;
+        x = p + ngrown;
+        r = x + n;
+        q = r + n;
+        sh = q + n;
+    }
 };
 
 // The whole CG, executed by one workgroup (any block size, multiple of 64).
@@ -1045,7 +1121,7 @@ template <class T, bool VAR>
 __global__ void __launch_bounds__(kBotThreads) k_bottom(T* __restrict__ u, const T* __restrict__ f, FaceArrays<T> fa,
                                                        const RBox* __restrict__ boxes, BottomGeom G, double h,
                                                        double rtol, int* __restrict__ iters_out) {
-    __shared__ BottomLds S;
+    BottomLds S(bxmg_lds, G.n[0] * G.n[1] * G.n[2], (G.n[0] + 2) * (G.n[1] + 2) * (G.n[2] + 2));
     bottom_cg<T, VAR>(u, f, fa, boxes, G, h, rtol, iters_out, S);
 }
 
@@ -1084,39 +1160,48 @@ __device__ __forceinline__ long long box_colour_cells(const RBox& B) {
     return ((nx + 1) >> 1) * ny * nz;
 }
 
+// A level of the coarse cycle: its descriptor and where its u and f live
+// (LDS or global memory).
+template <class T>
+struct LevelData {
+    const CoarseLevel<T>& L;
+    T* u;
+    T* f;
+};
+
 template <class T, int MODE>
-__device__ void blk_gs(const CoarseLevel<T>& L, int colour) {
-    const RBox& B = L.box;
+__device__ void blk_gs(const LevelData<T>& D, int colour) {
+    const RBox& B = D.L.box;
     const long long n = box_colour_cells(B);
-    const T h2 = (T)(L.h * L.h);
+    const T h2 = (T)(D.L.h * D.L.h);
     for (long long g = threadIdx.x; g < n; g += blockDim.x) {
         int i, j, k;
         if (!box_colour_cell(B, g, colour, i, j, k)) continue;
         T su, sb, uc;
         long long idx;
-        stencil<T, MODE>(L.u, (const T*)nullptr, L.fa, B, i, j, k, su, sb, uc, idx);
-        const T v = (su - h2 * L.f[idx]) / sb;
-        L.u[idx] = v;
-        if (L.push) push_ghosts(L.u, &L.box, B, i, j, k, v);
+        stencil<T, MODE>(D.u, (const T*)nullptr, D.L.fa, B, i, j, k, su, sb, uc, idx);
+        const T v = (su - h2 * D.f[idx]) / sb;
+        D.u[idx] = v;
+        if (D.L.push) push_ghosts(D.u, &D.L.box, B, i, j, k, v);
     }
     __syncthreads();
 }
 
 template <class T, int MODE>
-__device__ void blk_smooth(const CoarseLevel<T>& L, int nsweeps) {
+__device__ void blk_smooth(const LevelData<T>& D, int nsweeps) {
     for (int s = 0; s < nsweeps; ++s)
         for (int c = 0; c < 2; ++c) {
-            if (!L.push) blk_fill(L.u, L.face[c ^ 1], L.nface[c ^ 1]);
-            blk_gs<T, MODE>(L, c);
+            if (!D.L.push) blk_fill(D.u, D.L.face[c ^ 1], D.L.nface[c ^ 1]);
+            blk_gs<T, MODE>(D, c);
         }
 }
 
 template <class T, int MODE>
-__device__ void blk_resid_restrict(const CoarseLevel<T>& F, const CoarseLevel<T>& C) {
-    const RBox& B = F.box;
+__device__ void blk_resid_restrict(const LevelData<T>& F, const LevelData<T>& C) {
+    const RBox& B = F.L.box;
     const int cnx = (B.hi[0] - B.lo[0] + 1) >> 1, cny = (B.hi[1] - B.lo[1] + 1) >> 1, cnz = (B.hi[2] - B.lo[2] + 1) >> 1;
     const long long n = (long long)cnx * cny * cnz;
-    const T ih2 = (T)(1.0 / (F.h * F.h));
+    const T ih2 = (T)(1.0 / (F.L.h * F.L.h));
     for (long long g = threadIdx.x; g < n; g += blockDim.x) {
         const int I = (B.lo[0] >> 1) + (int)(g % cnx);
         const int J = (B.lo[1] >> 1) + (int)((g / cnx) % cny);
@@ -1125,27 +1210,33 @@ __device__ void blk_resid_restrict(const CoarseLevel<T>& F, const CoarseLevel<T>
         auto ra = [&](int a, int b, int c) {
             T su, sb, uc;
             long long idx;
-            stencil<T, MODE>(F.u, (const T*)nullptr, F.fa, B, a, b, c, su, sb, uc, idx);
+            stencil<T, MODE>(F.u, (const T*)nullptr, F.L.fa, B, a, b, c, su, sb, uc, idx);
             return F.f[idx] - (su - sb * uc) * ih2;
         };
         const T r000 = ra(i, j, k), r100 = ra(i + 1, j, k), r010 = ra(i, j + 1, k), r110 = ra(i + 1, j + 1, k);
         const T r001 = ra(i, j, k + 1), r101 = ra(i + 1, j, k + 1), r011 = ra(i, j + 1, k + 1);
         const T r111 = ra(i + 1, j + 1, k + 1);
         const T s = ((r000 + r100) + (r010 + r110)) + ((r001 + r101) + (r011 + r111));
-        C.f[rb_idx(C.box, I, J, K)] = s * T(0.125);
+        C.f[rb_idx(C.L.box, I, J, K)] = s * T(0.125);
     }
     __syncthreads();
 }
 
 template <class T>
-__device__ void blk_zero(const CoarseLevel<T>& L) {
-    for (long long g = threadIdx.x; g < L.nelem; g += blockDim.x) L.u[g] = T(0);
+__device__ void blk_zero(T* __restrict__ u, long long n) {
+    for (long long g = threadIdx.x; g < n; g += blockDim.x) u[g] = T(0);
     __syncthreads();
 }
 
 template <class T>
-__device__ void blk_prolong(const CoarseLevel<T>& C, const CoarseLevel<T>& F, int order) {
-    const RBox& B = F.box;
+__device__ void blk_copy(T* __restrict__ dst, const T* __restrict__ src, long long n) {
+    for (long long g = threadIdx.x; g < n; g += blockDim.x) dst[g] = src[g];
+    __syncthreads();
+}
+
+template <class T>
+__device__ void blk_prolong(const LevelData<T>& C, const LevelData<T>& F, int order) {
+    const RBox& B = F.L.box;
     const long long n = box_colour_cells(B);
     for (long long g = threadIdx.x; g < n; g += blockDim.x)
         for (int c = 0; c < 2; ++c) {
@@ -1153,7 +1244,7 @@ __device__ void blk_prolong(const CoarseLevel<T>& C, const CoarseLevel<T>& F, in
             if (!box_colour_cell(B, g, c, i, j, k)) continue;
             const int I = i >> 1, J = j >> 1, K = k >> 1;
             const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
-            const RBox& Q = C.box;
+            const RBox& Q = C.L.box;
             const T c000 = C.u[rb_idx(Q, I, J, K)];
             T e;
             if (order == 1) {
@@ -1170,29 +1261,42 @@ __device__ void blk_prolong(const CoarseLevel<T>& C, const CoarseLevel<T>& F, in
             const long long idx = rb_idx(B, i, j, k);
             const T v = F.u[idx] + e;
             F.u[idx] = v;
-            if (F.push) push_ghosts(F.u, &F.box, B, i, j, k, v);
+            if (F.L.push) push_ghosts(F.u, &F.L.box, B, i, j, k, v);
         }
     __syncthreads();
 }
 
+// The fused coarse V-cycle of one problem per workgroup.  With cc.lds the
+// levels' u and f live in LDS for the whole cycle (they are scratch below
+// the top level); the top level's f is read at the start and its u, the
+// correction, is written back at the end.
 template <class T, int MODE>
 __global__ void __launch_bounds__(kBotThreads) k_coarse_cycle(const CoarseCycle<T>* __restrict__ ccs,
                                                              const int* __restrict__ active) {
-    __shared__ BottomLds S;
     const CoarseCycle<T>& cc = ccs[blockIdx.x];
     if (active && !active[cc.pid]) return;
     const int nl = cc.nlev;
+    auto lev = [&](int m) {
+        if (cc.lds) return LevelData<T>{cc.L[m], (T*)(bxmg_lds + cc.lds_u[m]), (T*)(bxmg_lds + cc.lds_f[m])};
+        return LevelData<T>{cc.L[m], cc.L[m].u, cc.L[m].f};
+    };
+    if (cc.lds) {
+        const LevelData<T> top = lev(0);
+        blk_zero(top.u, cc.L[0].nelem);
+        blk_copy(top.f, (const T*)cc.L[0].f, cc.L[0].nelem);
+    }
     for (int l = 0; l + 1 < nl; ++l) {
-        const CoarseLevel<T>& F = cc.L[l];
+        const LevelData<T> F = lev(l), C = lev(l + 1);
         blk_smooth<T, MODE>(F, cc.nu1);
-        if (!F.push) {
-            blk_fill(F.u, F.face[0], F.nface[0]);
-            blk_fill(F.u, F.face[1], F.nface[1]);
+        if (!F.L.push) {
+            blk_fill(F.u, F.L.face[0], F.L.nface[0]);
+            blk_fill(F.u, F.L.face[1], F.L.nface[1]);
         }
-        blk_resid_restrict<T, MODE>(F, cc.L[l + 1]);
-        blk_zero(cc.L[l + 1]);
+        blk_resid_restrict<T, MODE>(F, C);
+        blk_zero(C.u, C.L.nelem);
     }
     {
+        const LevelData<T> Db = lev(nl - 1);
         const CoarseLevel<T>& Lb = cc.L[nl - 1];
         BottomGeom G;
         for (int d = 0; d < 3; ++d) {
@@ -1201,20 +1305,64 @@ __global__ void __launch_bounds__(kBotThreads) k_coarse_cycle(const CoarseCycle<
             G.per[d] = cc.per[d];
         }
         G.nboxes = 1;
-        bottom_cg<T, MODE == 2>(Lb.u, Lb.f, Lb.fa, &Lb.box, G, Lb.h, cc.rtol, cc.iters, S);
+        BottomLds S(bxmg_lds + cc.bot_off, G.n[0] * G.n[1] * G.n[2], (G.n[0] + 2) * (G.n[1] + 2) * (G.n[2] + 2));
+        bottom_cg<T, MODE == 2>(Db.u, Db.f, Lb.fa, &Lb.box, G, Lb.h, cc.rtol, cc.iters, S);
         __syncthreads();
     }
     for (int l = nl - 2; l >= 0; --l) {
-        const CoarseLevel<T>& F = cc.L[l];
-        const CoarseLevel<T>& C = cc.L[l + 1];
-        blk_fill(C.u, C.full, C.nfull);
+        const LevelData<T> F = lev(l), C = lev(l + 1);
+        blk_fill(C.u, C.L.full, C.L.nfull);
         blk_prolong(C, F, cc.prolong);
         blk_smooth<T, MODE>(F, cc.nu2);
     }
+    if (cc.lds) blk_copy(cc.L[0].u, (const T*)lev(0).u, cc.L[0].nelem);
 }
 
 // ================================================================ launchers
 static inline unsigned nblk(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+int lds_limit_bytes() {
+    static int limit = 0;
+    if (!limit) {
+        int dev = 0, a = 0, b = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&a, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        (void)hipDeviceGetAttribute(&b, hipDeviceAttributeSharedMemPerBlockOptin, dev);
+        limit = std::max(std::max(a, b), 65536);
+    }
+    return limit;
+}
+
+template <class T>
+int coarse_lds_layout(CoarseCycle<T>& cc, bool allow_levels) {
+    const RBox& B = cc.L[cc.nlev - 1].box;
+    const int n0 = B.hi[0] - B.lo[0] + 1, n1 = B.hi[1] - B.lo[1] + 1, n2 = B.hi[2] - B.lo[2] + 1;
+    const size_t bot = bottom_lds_bytes(n0 * n1 * n2, (n0 + 2) * (n1 + 2) * (n2 + 2));
+    auto a16 = [](size_t x) { return (x + 15) / 16 * 16; };
+    size_t off = 0;
+    for (int m = 0; m < cc.nlev; ++m) {
+        cc.lds_u[m] = (int)off;
+        off += a16((size_t)cc.L[m].nelem * sizeof(T));
+        cc.lds_f[m] = (int)off;
+        off += a16((size_t)cc.L[m].nelem * sizeof(T));
+    }
+    if (allow_levels && off + bot <= (size_t)lds_limit_bytes()) {
+        cc.lds = 1;
+        cc.bot_off = (int)off;
+        return (int)(off + bot);
+    }
+    cc.lds = 0;
+    cc.bot_off = 0;
+    return (int)bot;
+}
+template int coarse_lds_layout<double>(CoarseCycle<double>&, bool);
+template int coarse_lds_layout<float>(CoarseCycle<float>&, bool);
+
+// Lets a one-workgroup kernel take the device's whole LDS as dynamic LDS.
+static bool allow_lds(const void* fn) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit_bytes());
+    return true;
+}
 
 hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* list, long long n) {
     if (n <= 0) return hipSuccess;
@@ -1275,7 +1423,7 @@ template hipError_t launch_resid<float, float>(hipStream_t, const Grid&, const f
                                                const FaceArrays<float>*, float*, double*);
 
 hipError_t launch_norm_final(hipStream_t s, const double* partials, int n, double* out3) {
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, s, partials, n, out3);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kNormThreads), 0, s, partials, n, out3);
     return hipGetLastError();
 }
 
@@ -1313,8 +1461,15 @@ hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, c
                           int order) {
     if (fine.ntiles <= 0) return hipSuccess;
     const dim3 G(fine.ntiles), B(kBlock);
-    if (fine.push) hipLaunchKernelGGL((k_prolong<T, true>), G, B, 0, s, fine, cboxes, cbox, ec, uf, order);
-    else hipLaunchKernelGGL((k_prolong<T, false>), G, B, 0, s, fine, cboxes, cbox, ec, uf, order);
+#define BXMG_PROLONG(PUSH, ORDER) hipLaunchKernelGGL((k_prolong<T, PUSH, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf)
+    if (order == 1) {
+        if (fine.push) BXMG_PROLONG(true, 1);
+        else BXMG_PROLONG(false, 1);
+    } else {
+        if (fine.push) BXMG_PROLONG(true, 2);
+        else BXMG_PROLONG(false, 2);
+    }
+#undef BXMG_PROLONG
     return hipGetLastError();
 }
 template hipError_t launch_prolong<double>(hipStream_t, const Grid&, const RBox*, const int*, const double*, double*,
@@ -1360,7 +1515,8 @@ hipError_t launch_add_f32(hipStream_t s, const Grid& g, double* u, const float* 
 hipError_t launch_mean_sub(hipStream_t s, const Grid& g, double* u, double* scratch) {
     if (g.ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sum_valid, dim3(g.ntiles), dim3(kBlock), 0, s, g, u, scratch);
-    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kBlock), 0, s, scratch, g.ntiles, scratch + 3 * (long long)g.ntiles);
+    hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kNormThreads), 0, s, scratch, g.ntiles,
+                       scratch + 3 * (long long)g.ntiles);
     hipLaunchKernelGGL(k_sub_mean, dim3(g.ntiles), dim3(kBlock), 0, s, g, u, scratch + 3 * (long long)g.ntiles);
     return hipGetLastError();
 }
@@ -1398,8 +1554,17 @@ hipError_t launch_bottom(hipStream_t s, T* u, const T* f, FaceArrays<T> fa, bool
         G.per[d] = periodic[d];
     }
     G.nboxes = nboxes;
-    if (var) hipLaunchKernelGGL((k_bottom<T, true>), dim3(1), dim3(kBotThreads), 0, s, u, f, fa, boxes, G, h, rtol, iters_out);
-    else hipLaunchKernelGGL((k_bottom<T, false>), dim3(1), dim3(kBotThreads), 0, s, u, f, fa, boxes, G, h, rtol, iters_out);
+    const int n = G.n[0] * G.n[1] * G.n[2], ng = (G.n[0] + 2) * (G.n[1] + 2) * (G.n[2] + 2);
+    const size_t lds = bottom_lds_bytes(n, ng);
+    if (var) {
+        static const bool once = allow_lds((const void*)k_bottom<T, true>);
+        (void)once;
+        hipLaunchKernelGGL((k_bottom<T, true>), dim3(1), dim3(kBotThreads), lds, s, u, f, fa, boxes, G, h, rtol, iters_out);
+    } else {
+        static const bool once = allow_lds((const void*)k_bottom<T, false>);
+        (void)once;
+        hipLaunchKernelGGL((k_bottom<T, false>), dim3(1), dim3(kBotThreads), lds, s, u, f, fa, boxes, G, h, rtol, iters_out);
+    }
     return hipGetLastError();
 }
 template hipError_t launch_bottom<double>(hipStream_t, double*, const double*, FaceArrays<double>, bool, const RBox*,
@@ -1408,18 +1573,27 @@ template hipError_t launch_bottom<float>(hipStream_t, float*, const float*, Face
                                          const int*, const int*, const int*, double, double, int*);
 
 template <class T>
-hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, int n, const int* active, bool var) {
+hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, int n, const int* active, bool var,
+                               int lds_bytes) {
     if (n <= 0) return hipSuccess;
-    if (var) hipLaunchKernelGGL((k_coarse_cycle<T, 2>), dim3(n), dim3(kBotThreads), 0, s, cc, active);
-    else hipLaunchKernelGGL((k_coarse_cycle<T, 0>), dim3(n), dim3(kBotThreads), 0, s, cc, active);
+    if (var) {
+        static const bool once = allow_lds((const void*)k_coarse_cycle<T, 2>);
+        (void)once;
+        hipLaunchKernelGGL((k_coarse_cycle<T, 2>), dim3(n), dim3(kBotThreads), lds_bytes, s, cc, active);
+    } else {
+        static const bool once = allow_lds((const void*)k_coarse_cycle<T, 0>);
+        (void)once;
+        hipLaunchKernelGGL((k_coarse_cycle<T, 0>), dim3(n), dim3(kBotThreads), lds_bytes, s, cc, active);
+    }
     return hipGetLastError();
 }
-template hipError_t launch_coarse_cycle<double>(hipStream_t, const CoarseCycle<double>*, int, const int*, bool);
-template hipError_t launch_coarse_cycle<float>(hipStream_t, const CoarseCycle<float>*, int, const int*, bool);
+template hipError_t launch_coarse_cycle<double>(hipStream_t, const CoarseCycle<double>*, int, const int*, bool, int);
+template hipError_t launch_coarse_cycle<float>(hipStream_t, const CoarseCycle<float>*, int, const int*, bool, int);
 
 // ------------------------------------------------------------ batch kernels
-// One block per segment: the fixed-tree reduction of k_norm_final over the
-// segment's tiles, in tile order.
+// One block per segment: a fixed-tree reduction over the segment's tiles, in
+// tile order (max norms are exact in any order; the L2 sums depend on the
+// tree only in rounding).
 __global__ void __launch_bounds__(kBlock) k_norm_seg(const double* __restrict__ partials, const int* __restrict__ tstart,
                                                     const int* __restrict__ seg_slot, const int* __restrict__ active,
                                                     double* __restrict__ norms) {

@@ -139,8 +139,10 @@ def test_admission_by_footprint_and_continuous_add(bx):
     p1["phi"].set_val(0.0)
     b = bx.Batch(p1["phi"].ctx, 256 * MB, 8)
     b.add(p1["phi"], p1["rhs"])
-    # a problem admitted while another is mid-solve
+    # a problem admitted while another is mid-solve (from a zero guess, as
+    # the lone solve below)
     b.step(2)
+    p2["phi"].set_val(0.0)
     b.add(p2["phi"], p2["rhs"])
     b.run(1)
     assert np.array_equal(p1["phi"].to_global(), u1)

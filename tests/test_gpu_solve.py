@@ -211,17 +211,18 @@ def test_non_aligned_boxes_use_ghost_refresh(bx, orc):
 
 
 def test_launch_knobs_do_not_change_results(bx):
-    """Tile depth, tile rows and buffer addressing change the work split and
-    the instructions, never the arithmetic: fixed-cycle iterates are bitwise
-    equal under every setting, and the autotuner leaves a valid setting."""
+    """Tile depth, tile rows, buffer addressing and where the coarse cycle
+    keeps its levels change the work split and the instructions, never the
+    arithmetic: fixed-cycle iterates are bitwise equal under every setting,
+    and the autotuner leaves a valid setting."""
     n = 64
     f = W.uniform_rhs((n, n, n), 27)
     ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 32, (0, 0, 0), f)
     lib, ctx = bx.lib(), phi.ctx
     ref = None
     try:
-        for zc, res, ly in [(4, 1, 8), (1, 0, 8), (8, 1, 2), (2, 0, 3)]:
-            for param, value in ((0, zc), (1, zc), (2, res), (3, ly)):
+        for zc, res, ly, lds in [(4, 1, 8, 1), (1, 0, 8, 0), (8, 1, 2, 1), (2, 0, 3, 0)]:
+            for param, value in ((0, zc), (1, zc), (2, res), (3, ly), (4, lds)):
                 bx._lib.check(lib.bxmg_ctx_tune(ctx._h, param, value))
             for precision in (0, 1):
                 phi.set_val(0.0)
@@ -240,7 +241,7 @@ def test_launch_knobs_do_not_change_results(bx):
         r = bx.mlmg_solve(phi, rhs, fixed_cycles=3)
         assert np.array_equal(phi.to_global(), ref[0][0])
     finally:
-        for param, value in ((0, 4), (1, 4), (2, 1), (3, 8)):
+        for param, value in ((0, 4), (1, 4), (2, 1), (3, 8), (4, 1)):
             bx._lib.check(lib.bxmg_ctx_tune(ctx._h, param, value))
 
 

@@ -202,3 +202,23 @@ def test_bottom_cg(bx, orc, shape, per):
     Lu = orc.apply_op(dlo, dhi, per, h, got)
     fp = f - f.mean() if per == (1, 1, 1) else f
     assert np.max(np.abs(fp - Lu)) <= 1e-10 * np.max(np.abs(f))
+
+
+def test_multifab_copy_host_roundtrip(bx):
+    """bxmg_multifab_copy_host writes exactly the valid cells of one
+    component (ghosts and other components keep their values) and reads them
+    back in the global F-order layout."""
+    ba = bx.BoxArray.chop((-4, 0, 2), (11, 9, 13), 8, bc=(bx.PERIODIC, bx.DIRICHLET0, bx.PERIODIC))
+    shape = ba.domain.size
+    for dtype, npdt in (("f64", np.float64), ("f32", np.float32)):
+        mf = bx.MultiFab(ba, ncomp=2, nghost=2, dtype=dtype).set_val(-7.0)
+        g = np.asfortranarray(W.dyadic_codes(shape, 3).astype(npdt))
+        mf.copy_host(g, to_device=True, comp=1)
+        packed = mf.to_packed()
+        assert np.array_equal(mf.to_global(comp=1), g)
+        assert np.all(mf.to_global(comp=0) == -7.0)
+        n_valid = int(np.prod(shape))
+        assert np.count_nonzero(packed != -7.0) == n_valid  # ghosts and component 0 untouched
+        back = np.asfortranarray(np.zeros(shape, npdt))
+        mf.copy_host(back, to_device=False, comp=1)
+        assert np.array_equal(back, g)
