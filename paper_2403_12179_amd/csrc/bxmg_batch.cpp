@@ -638,7 +638,8 @@ void b_vcycle(bxmg_batch_s* b, hipStream_t s) {
     for (int l = b->lmax - 1; l >= 0; --l) {
         BLevel& B = b->lev[l];
         HIPCHK(launch_fill_sets(s, u, f32, B.fullc.p(), B.nfullc, B.mfullc, b->active.p));
-        HIPCHK(launch_prolong<T>(s, level_grid(b, l), b->lev[l + 1].rb.p(), B.cbox.p(), u, u, b->P.prolong));
+        HIPCHK(launch_prolong<T>(s, level_grid(b, l), b->lev[l + 1].rb.p(), B.cbox.p(), u, u, b->P.prolong,
+                                 b->P.nu2 > 0));
         b_smooth<T>(b, s, l, b->P.nu2);
     }
 }

@@ -453,7 +453,8 @@ void vcycle(Run& R, size_t l) {
     vcycle<T>(R, l + 1);
     fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full);
     R.pre(l, kStageProlong);
-    HIPCHK(launch_prolong<T>(R.s, L.walk(), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong));
+    // with post-smoothing, its first (colour-0) sweep overwrites colour 0
+    HIPCHK(launch_prolong<T>(R.s, L.walk(), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong, R.nu2 > 0));
     R.post(l, kStageProlong);
     smooth<T>(R, l, R.nu2);
 }

@@ -208,10 +208,13 @@ hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* 
 // fine += P coarse: one thread per pair of fine cells (2I, 2I+1) over the
 // fine level's colour tiles (fine boxes pair aligned); cbox[b] = coarse box
 // holding the coarsened fine box b (plain 32-bit offsets from the box starts:
-// buffer addressing measured slower for this kernel)
+// buffer addressing measured slower for this kernel).  only_c1: a colour-0
+// Gauss-Seidel sweep follows; on levels that push their ghosts, correct the
+// colour-1 cells and only the Dirichlet ghosts of colour-0 cells (the sweep
+// overwrites colour 0 reading it only through those ghosts).
 template <class T>
 hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
-                          int order);
+                          int order, bool only_c1 = false);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n);

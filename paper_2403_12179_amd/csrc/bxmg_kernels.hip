@@ -793,6 +793,147 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid g, const RBox* __restri
     }
 }
 
+// Across a homogeneous-Dirichlet domain face only: -v into the box's own
+// ghost beyond each such face the cell lies on (the rest of push_ghosts).
+template <class T>
+__device__ __forceinline__ void push_dirichlet(T* __restrict__ u, const RBox& B, int i, int j, int k, T v) {
+    const int c[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            if (c[d] != (side ? B.hi[d] : B.lo[d]) || B.nb[2 * d + side] >= 0) continue;
+            int t[3] = {i, j, k};
+            t[d] += side ? 1 : -1;
+            u[rb_idx(B, t[0], t[1], t[2])] = -v;
+        }
+}
+
+// Prolongation that corrects only the colour-1 cells, for a V-cycle whose
+// post-smoothing starts with a colour-0 sweep on a level that pushes its
+// ghosts.  That sweep computes each colour-0 value from its neighbours only --
+// except through the ghost beyond a Dirichlet face, which mirrors the cell
+// itself (-u).  So: colour-1 cells are corrected and pushed as the two-colour
+// kernel does; of the colour-0 cells only those on a Dirichlet face matter, and
+// only through that mirrored ghost, which gets -(u + P e); correcting the
+// other colour-0 values would be dead work (the sweep overwrites them before
+// anything reads them, and their copies in neighbours' ghosts too).  One thread
+// per colour-1 cell; the 8 coarse values are the parent and its neighbours
+// towards the cell.
+template <class T, int ORDER>
+__global__ void __launch_bounds__(kBlock) k_prolong_c1(Grid g, const RBox* __restrict__ cboxes,
+                                                      const int* __restrict__ cbox, const T* __restrict__ ec,
+                                                      T* __restrict__ uf) {
+    const Tile tl = g.tiles[tile_index(g.rev)];
+    const RBox B = g.boxes[tl.box];
+    if (g.active && !g.active[B.pid]) return;
+    const RBox C = cboxes[cbox[tl.box]];
+    const TileThread th = tile_thread(tl);
+    const int j = B.lo[1] + th.y;
+    if (j > B.hi[1]) return;
+    const int J = j >> 1, sj = (j & 1) ? 1 : -1;
+    const T* __restrict__ cb = ec + C.base;
+    T* __restrict__ fb = uf + B.base;
+    // coarse rows J and J+sy at x = I and I+sx of the planes the previous fine
+    // plane used stay in registers (see k_prolong)
+    T pa[2][2], pb[2][2];
+    int ka = -0x7fffffff, kb = -0x7fffffff;  // no plane yet
+    auto load_plane = [&](int I, int si, int Kq, T (&pl)[2][2]) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                if (ORDER == 1 && (r > 0 || x > 0)) continue;
+                pl[r][x] = cb[rb_off(C, I + x * si, r ? J + sj : J, Kq)];
+            }
+    };
+    auto take = [](T (&dst)[2][2], const T (&src)[2][2]) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) dst[r][x] = src[r][x];
+    };
+    const int zc = tl.zc;
+    for (int z0 = 0; z0 < zc; z0 += kProlongGroup) {
+        T fv[kProlongGroup];
+        int off[kProlongGroup];
+#pragma unroll
+        for (int q = 0; q < kProlongGroup; ++q) {
+            const int k = min(B.lo[2] + th.z0 + (z0 + q) * th.dz, B.hi[2]);  // clamped: loads stay in the box
+            const int i = min(colour_i(B, th.x, j, k, 1), B.hi[0]);
+            off[q] = rb_off(B, i, j, k);  // the clamped cell may be colour 0: its value is never used
+            fv[q] = fb[off[q]];
+        }
+        // one copy of the compute and push code (see k_prolong)
+#pragma unroll 1
+        for (int q = 0; q < kProlongGroup; ++q) {
+            const int k = B.lo[2] + th.z0 + (z0 + q) * th.dz;
+            if (z0 + q >= zc || k > B.hi[2]) break;
+            const int i = colour_i(B, th.x, j, k, 1);
+            const int I = i >> 1, si = (i & 1) ? 1 : -1;
+            const int K = k >> 1, K2 = K + ((k & 1) ? 1 : -1);
+            if (i <= B.hi[0]) {
+                // the x side si is the same for every plane this thread walks
+                // when the planes are 2 apart; otherwise the cached planes are
+                // keyed by (plane, side)
+                const int key = 2 * K + (si > 0), key2 = 2 * K2 + (si > 0);
+                T p0[2][2], p1[2][2];
+                if (key == ka) take(p0, pa);
+                else if (key == kb) take(p0, pb);
+                else load_plane(I, si, K, p0);
+                if constexpr (ORDER != 1) {
+                    if (key2 == ka) take(p1, pa);
+                    else if (key2 == kb) take(p1, pb);
+                    else load_plane(I, si, K2, p1);
+                    take(pb, p1);
+                    kb = key2;
+                }
+                take(pa, p0);
+                ka = key;
+                T e;
+                if constexpr (ORDER == 1) {
+                    e = p0[0][0];
+                } else {
+                    const T c000 = p0[0][0], c100 = p0[0][1], c010 = p0[1][0], c001 = p1[0][0];
+                    const T c110 = p0[1][1], c101 = p1[0][1], c011 = p1[1][0], c111 = p1[1][1];
+                    e = (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
+                        T(0.015625);
+                }
+                const T v = fv[0] + e;
+                fb[off[0]] = v;
+                push_ghosts(uf, g.boxes, B, i, j, k, v);
+            }
+            // the colour-0 cell of this row and plane, if it lies on a
+            // Dirichlet face (few threads)
+            const int i0 = colour_i(B, th.x, j, k, 0);
+            const bool dir = i0 <= B.hi[0] &&
+                             ((i0 == B.lo[0] && B.nb[0] < 0) || (i0 == B.hi[0] && B.nb[1] < 0) ||
+                              (j == B.lo[1] && B.nb[2] < 0) || (j == B.hi[1] && B.nb[3] < 0) ||
+                              (k == B.lo[2] && B.nb[4] < 0) || (k == B.hi[2] && B.nb[5] < 0));
+            if (dir) {
+                const int I = i0 >> 1, si = (i0 & 1) ? 1 : -1, K = k >> 1, sk = (k & 1) ? 1 : -1;
+                T e;
+                if constexpr (ORDER == 1) {
+                    e = cb[rb_off(C, I, J, K)];
+                } else {
+                    const T c000 = cb[rb_off(C, I, J, K)], c100 = cb[rb_off(C, I + si, J, K)];
+                    const T c010 = cb[rb_off(C, I, J + sj, K)], c001 = cb[rb_off(C, I, J, K + sk)];
+                    const T c110 = cb[rb_off(C, I + si, J + sj, K)], c101 = cb[rb_off(C, I + si, J, K + sk)];
+                    const T c011 = cb[rb_off(C, I, J + sj, K + sk)], c111 = cb[rb_off(C, I + si, J + sj, K + sk)];
+                    e = (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
+                        T(0.015625);
+                }
+                push_dirichlet(uf, B, i0, j, k, fb[rb_off(B, i0, j, k)] + e);
+            }
+#pragma unroll
+            for (int m = 0; m + 1 < kProlongGroup; ++m) {
+                fv[m] = fv[m + 1];
+                off[m] = off[m + 1];
+            }
+        }
+    }
+}
+
 // -------------------------------------------------------------- utilities
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_zero(T* __restrict__ p, long long n) {
@@ -1117,12 +1258,140 @@ __device__ void bottom_cg(T* __restrict__ u, const T* __restrict__ f, const Face
     if (threadIdx.x == 0 && iters_out) *iters_out = it;
 }
 
+// Bottoms of at most 64 cells: the same CG run by one wave (lane n owns cell
+// n), with wave-wide butterfly sums and no workgroup barriers -- a tiny
+// bottom is all latency.  The butterfly leaves bitwise the same sum in every
+// lane (IEEE addition commutes), so every lane takes the same decisions.
+constexpr int kWaveBottomCells = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o);
+    return v;
+}
+
+// orders this wave's LDS writes before its later LDS reads of other lanes' cells
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Executed by the 64 threads of wave 0 only; N = cells <= kWaveBottomCells.
+template <class T, bool VAR>
+__device__ void bottom_cg_wave(T* __restrict__ u, const T* __restrict__ f, const FaceArrays<T>& fa,
+                               const RBox* __restrict__ boxes, const BottomGeom& G, double h, double rtol,
+                               int* __restrict__ iters_out, BottomLds& S) {
+    double* p = S.p;
+    const int lane = threadIdx.x;
+    const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+    const int N = nx * ny * nz;
+    const int gx = nx + 2, gy = ny + 2;
+    const double ih2 = 1.0 / (h * h);
+    const bool mine = lane < N;
+    const int a = lane % nx, b = (lane / nx) % ny, c = lane / (nx * ny);
+    const int pc = (a + 1) + gx * ((b + 1) + gy * (c + 1));
+    // gather rhs into the owning lanes
+    double r = 0.0;
+    for (int bi = 0; bi < G.nboxes; ++bi) {
+        const RBox B = boxes[bi];
+        if (mine && G.dlo[0] + a >= B.lo[0] && G.dlo[0] + a <= B.hi[0] && G.dlo[1] + b >= B.lo[1] &&
+            G.dlo[1] + b <= B.hi[1] && G.dlo[2] + c >= B.lo[2] && G.dlo[2] + c <= B.hi[2])
+            r = (double)f[rb_idx(B, G.dlo[0] + a, G.dlo[1] + b, G.dlo[2] + c)];
+    }
+    const bool sing = G.per[0] && G.per[1] && G.per[2];
+    if (sing) {
+        const double mean = wave_sum(r) / (double)N;
+        if (mine) r = r - mean;
+    }
+    double x = 0.0, pv = r;
+    double rs = wave_sum(r * r);
+    const double rs0 = rs;
+    int it = 0;
+    if (rs0 != 0.0) {
+        const int maxit = 4 * N;
+        for (it = 0; it < maxit;) {
+            // p with its face ghosts in LDS (7-point stencil)
+            if (mine) p[pc] = pv;
+            wave_lds_sync();
+            const int nfx = ny * nz, nfy = nx * nz, nfz = nx * ny;
+            for (int t = lane; t < 2 * (nfx + nfy + nfz); t += 64) {
+                int d, side, e, g;
+                int tt = t;
+                if (tt < 2 * nfx) { d = 0; side = tt / nfx; tt %= nfx; e = tt % ny; g = tt / ny; }
+                else if ((tt -= 2 * nfx) < 2 * nfy) { d = 1; side = tt / nfy; tt %= nfy; e = tt % nx; g = tt / nx; }
+                else { tt -= 2 * nfy; d = 2; side = tt / nfz; tt %= nfz; e = tt % nx; g = tt / nx; }
+                int gc[3], sc[3];
+                if (d == 0) { gc[1] = sc[1] = e; gc[2] = sc[2] = g; }
+                else if (d == 1) { gc[0] = sc[0] = e; gc[2] = sc[2] = g; }
+                else { gc[0] = sc[0] = e; gc[1] = sc[1] = g; }
+                const int nd = G.n[d];
+                gc[d] = side ? nd : -1;
+                double sgn = 1.0;
+                if (G.per[d]) sc[d] = side ? 0 : nd - 1;
+                else { sc[d] = side ? nd - 1 : 0; sgn = -1.0; }
+                p[(gc[0] + 1) + gx * ((gc[1] + 1) + gy * (gc[2] + 1))] =
+                    sgn * p[(sc[0] + 1) + gx * ((sc[1] + 1) + gy * (sc[2] + 1))];
+            }
+            wave_lds_sync();
+            double qv = 0.0;
+            if (mine) {
+                double su, sb;
+                const double pxm = p[pc - 1], pxp = p[pc + 1], pym = p[pc - gx], pyp = p[pc + gx];
+                const double pzm = p[pc - gx * gy], pzp = p[pc + gx * gy];
+                if constexpr (!VAR) {
+                    su = ((pxm + pxp) + (pym + pyp)) + (pzm + pzp);
+                    sb = 6.0;
+                } else {
+                    const long long ix = (long long)a + (long long)(nx + 1) * ((long long)b + (long long)ny * c);
+                    const long long iy = (long long)a + (long long)nx * ((long long)b + (long long)(ny + 1) * c);
+                    const long long iz = (long long)a + (long long)nx * ((long long)b + (long long)ny * c);
+                    const double bxm = (double)fa.c[0][ix], bxp = (double)fa.c[0][ix + 1];
+                    const double bym = (double)fa.c[1][iy], byp = (double)fa.c[1][iy + nx];
+                    const double bzm = (double)fa.c[2][iz], bzp = (double)fa.c[2][iz + (long long)nx * ny];
+                    sb = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
+                    su = ((bxm * pxm + bxp * pxp) + (bym * pym + byp * pyp)) + (bzm * pzm + bzp * pzp);
+                }
+                qv = (su - sb * pv) * ih2;
+            }
+            const double pAp = wave_sum(pv * qv);
+            const double alpha = rs / pAp;
+            if (mine) {
+                x = x + alpha * pv;
+                r = r - alpha * qv;
+            }
+            const double rsn = wave_sum(r * r);
+            ++it;
+            if (sqrt(rsn) <= rtol * sqrt(rs0)) break;
+            const double beta = rsn / rs;
+            if (mine) pv = r + beta * pv;
+            rs = rsn;
+            wave_lds_sync();  // this iteration's reads of p come before the next writes
+        }
+        if (sing) {
+            const double mean = wave_sum(x) / (double)N;
+            if (mine) x = x - mean;
+        }
+    }
+    for (int bi = 0; bi < G.nboxes; ++bi) {
+        const RBox B = boxes[bi];
+        if (mine && G.dlo[0] + a >= B.lo[0] && G.dlo[0] + a <= B.hi[0] && G.dlo[1] + b >= B.lo[1] &&
+            G.dlo[1] + b <= B.hi[1] && G.dlo[2] + c >= B.lo[2] && G.dlo[2] + c <= B.hi[2])
+            u[rb_idx(B, G.dlo[0] + a, G.dlo[1] + b, G.dlo[2] + c)] = (T)x;
+    }
+    if (lane == 0 && iters_out) *iters_out = it;
+}
+
 template <class T, bool VAR>
 __global__ void __launch_bounds__(kBotThreads) k_bottom(T* __restrict__ u, const T* __restrict__ f, FaceArrays<T> fa,
                                                        const RBox* __restrict__ boxes, BottomGeom G, double h,
                                                        double rtol, int* __restrict__ iters_out) {
-    BottomLds S(bxmg_lds, G.n[0] * G.n[1] * G.n[2], (G.n[0] + 2) * (G.n[1] + 2) * (G.n[2] + 2));
-    bottom_cg<T, VAR>(u, f, fa, boxes, G, h, rtol, iters_out, S);
+    const int N = G.n[0] * G.n[1] * G.n[2];
+    BottomLds S(bxmg_lds, N, (G.n[0] + 2) * (G.n[1] + 2) * (G.n[2] + 2));
+    if (N <= kWaveBottomCells) {
+        if (threadIdx.x < 64) bottom_cg_wave<T, VAR>(u, f, fa, boxes, G, h, rtol, iters_out, S);
+    } else {
+        bottom_cg<T, VAR>(u, f, fa, boxes, G, h, rtol, iters_out, S);
+    }
 }
 
 // --------------------------------------------------- fused coarse V-cycle
@@ -1144,19 +1413,22 @@ __device__ void blk_fill(T* __restrict__ data, const GhostCopy* __restrict__ lis
 }
 
 // colour cell g of a single box: (i, j, k) or false
-__device__ __forceinline__ bool box_colour_cell(const RBox& B, long long g, int c, int& i, int& j, int& k) {
+// (the levels a workgroup handles hold at most kMaxBottomCells cells: 32-bit
+// index arithmetic; 64-bit division would dominate these small stages)
+__device__ __forceinline__ bool box_colour_cell(const RBox& B, int g, int c, int& i, int& j, int& k) {
     const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1;
     const int tn = (nx + 1) >> 1;
-    const int t = (int)(g % tn);
-    const long long r = g / tn;
-    j = B.lo[1] + (int)(r % ny);
-    k = B.lo[2] + (int)(r / ny);
+    const int r = g / tn;
+    const int t = g - r * tn;
+    const int rz = r / ny;
+    j = B.lo[1] + (r - rz * ny);
+    k = B.lo[2] + rz;
     i = colour_i(B, t, j, k, c);
     return i <= B.hi[0];
 }
 
-__device__ __forceinline__ long long box_colour_cells(const RBox& B) {
-    const long long nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1, nz = B.hi[2] - B.lo[2] + 1;
+__device__ __forceinline__ int box_colour_cells(const RBox& B) {
+    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1, nz = B.hi[2] - B.lo[2] + 1;
     return ((nx + 1) >> 1) * ny * nz;
 }
 
@@ -1172,14 +1444,15 @@ struct LevelData {
 template <class T, int MODE>
 __device__ void blk_gs(const LevelData<T>& D, int colour) {
     const RBox& B = D.L.box;
-    const long long n = box_colour_cells(B);
+    const int n = box_colour_cells(B);
     const T h2 = (T)(D.L.h * D.L.h);
-    for (long long g = threadIdx.x; g < n; g += blockDim.x) {
+    for (int g = threadIdx.x; g < n; g += blockDim.x) {
         int i, j, k;
         if (!box_colour_cell(B, g, colour, i, j, k)) continue;
-        T su, sb, uc;
-        long long idx;
-        stencil<T, MODE>(D.u, (const T*)nullptr, D.L.fa, B, i, j, k, su, sb, uc, idx);
+        Nbr<T> nb;
+        const long long idx = gather<T, MODE, false>(D.u, (const T*)nullptr, D.L.fa, B, i, j, k, nb);
+        T su, sb;
+        sums<T, MODE>(nb, su, sb);
         const T v = (su - h2 * D.f[idx]) / sb;
         D.u[idx] = v;
         if (D.L.push) push_ghosts(D.u, &D.L.box, B, i, j, k, v);
@@ -1200,12 +1473,13 @@ template <class T, int MODE>
 __device__ void blk_resid_restrict(const LevelData<T>& F, const LevelData<T>& C) {
     const RBox& B = F.L.box;
     const int cnx = (B.hi[0] - B.lo[0] + 1) >> 1, cny = (B.hi[1] - B.lo[1] + 1) >> 1, cnz = (B.hi[2] - B.lo[2] + 1) >> 1;
-    const long long n = (long long)cnx * cny * cnz;
+    const int n = cnx * cny * cnz;
     const T ih2 = (T)(1.0 / (F.L.h * F.L.h));
-    for (long long g = threadIdx.x; g < n; g += blockDim.x) {
-        const int I = (B.lo[0] >> 1) + (int)(g % cnx);
-        const int J = (B.lo[1] >> 1) + (int)((g / cnx) % cny);
-        const int K = (B.lo[2] >> 1) + (int)(g / ((long long)cnx * cny));
+    for (int g = threadIdx.x; g < n; g += blockDim.x) {
+        const int gy = g / cnx, gz = gy / cny;
+        const int I = (B.lo[0] >> 1) + (g - gy * cnx);
+        const int J = (B.lo[1] >> 1) + (gy - gz * cny);
+        const int K = (B.lo[2] >> 1) + gz;
         const int i = 2 * I, j = 2 * J, k = 2 * K;
         auto ra = [&](int a, int b, int c) {
             T su, sb, uc;
@@ -1237,8 +1511,8 @@ __device__ void blk_copy(T* __restrict__ dst, const T* __restrict__ src, long lo
 template <class T>
 __device__ void blk_prolong(const LevelData<T>& C, const LevelData<T>& F, int order) {
     const RBox& B = F.L.box;
-    const long long n = box_colour_cells(B);
-    for (long long g = threadIdx.x; g < n; g += blockDim.x)
+    const int n = box_colour_cells(B);
+    for (int g = threadIdx.x; g < n; g += blockDim.x)
         for (int c = 0; c < 2; ++c) {
             int i, j, k;
             if (!box_colour_cell(B, g, c, i, j, k)) continue;
@@ -1305,8 +1579,13 @@ __global__ void __launch_bounds__(kBotThreads) k_coarse_cycle(const CoarseCycle<
             G.per[d] = cc.per[d];
         }
         G.nboxes = 1;
-        BottomLds S(bxmg_lds + cc.bot_off, G.n[0] * G.n[1] * G.n[2], (G.n[0] + 2) * (G.n[1] + 2) * (G.n[2] + 2));
-        bottom_cg<T, MODE == 2>(Db.u, Db.f, Lb.fa, &Lb.box, G, Lb.h, cc.rtol, cc.iters, S);
+        const int N = G.n[0] * G.n[1] * G.n[2];
+        BottomLds S(bxmg_lds + cc.bot_off, N, (G.n[0] + 2) * (G.n[1] + 2) * (G.n[2] + 2));
+        if (N <= kWaveBottomCells) {
+            if (threadIdx.x < 64) bottom_cg_wave<T, MODE == 2>(Db.u, Db.f, Lb.fa, &Lb.box, G, Lb.h, cc.rtol, cc.iters, S);
+        } else {
+            bottom_cg<T, MODE == 2>(Db.u, Db.f, Lb.fa, &Lb.box, G, Lb.h, cc.rtol, cc.iters, S);
+        }
         __syncthreads();
     }
     for (int l = nl - 2; l >= 0; --l) {
@@ -1458,10 +1737,17 @@ template hipError_t launch_restrict_plain<double>(hipStream_t, const XGrid&, con
 
 template <class T>
 hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
-                          int order) {
+                          int order, bool only_c1) {
     if (fine.ntiles <= 0) return hipSuccess;
     const dim3 G(fine.ntiles), B(kBlock);
-#define BXMG_PROLONG(PUSH, ORDER) hipLaunchKernelGGL((k_prolong<T, PUSH, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf)
+    // levels refreshed by fill lists copy ghosts from both colours' cells:
+    // they keep the two-colour kernel
+    const bool c1 = only_c1 && fine.push;
+#define BXMG_PROLONG(PUSH, ORDER)                                                                    \
+    do {                                                                                            \
+        if (PUSH && c1) hipLaunchKernelGGL((k_prolong_c1<T, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
+        else hipLaunchKernelGGL((k_prolong<T, PUSH, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
+    } while (0)
     if (order == 1) {
         if (fine.push) BXMG_PROLONG(true, 1);
         else BXMG_PROLONG(false, 1);
@@ -1473,8 +1759,9 @@ hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, c
     return hipGetLastError();
 }
 template hipError_t launch_prolong<double>(hipStream_t, const Grid&, const RBox*, const int*, const double*, double*,
-                                           int);
-template hipError_t launch_prolong<float>(hipStream_t, const Grid&, const RBox*, const int*, const float*, float*, int);
+                                           int, bool);
+template hipError_t launch_prolong<float>(hipStream_t, const Grid&, const RBox*, const int*, const float*, float*, int,
+                                          bool);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n) {

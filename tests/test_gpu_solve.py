@@ -107,6 +107,25 @@ def test_fixed_cycles_iterates_match(bx, orc):
     assert res0.status == -4 and res0.cycles == 0 and res0.hist[0] == 1.0
 
 
+@pytest.mark.parametrize("nu", [(2, 2), (1, 1), (2, 0), (0, 2), (3, 1)])
+@pytest.mark.parametrize("per,var", [(0, False), (1, False), (0, True)])
+def test_smoothing_counts_iterates_match(bx, orc, nu, per, var):
+    """Fixed cycles with other pre/post sweep counts follow the oracle's
+    iterates: covers the V-cycle paths that depend on them (prolongation of
+    one colour before a post-smoothing sweep, the zero first guess of a
+    coarse level before a pre-smoothing sweep) and their fallbacks."""
+    n = 64  # levels 64^3 and 32^3 in 8 boxes, then the fused coarse cycle
+    f = W.uniform_rhs((n, n, n), 71, mean_zero=bool(per))
+    beta = W.smooth_gaussian_beta((n, n, n), 72) if var else None
+    ba, phi, rhs, bmf = setup(bx, (0, 0, 0), (n - 1,) * 3, 32, (per,) * 3, f, beta)
+    res = bx.mlmg_solve(phi, rhs, bmf, fixed_cycles=3, nu1=nu[0], nu2=nu[1])
+    uo, io = orc.solve((0, 0, 0), (n - 1,) * 3, (per,) * 3, [(b.small, b.big) for b in ba.boxes], f, beta,
+                       fixed_cycles=3, nu1=nu[0], nu2=nu[1])
+    assert res.cycles == 3 and io["cycles"] == 3
+    u = phi.to_global()
+    assert np.max(np.abs(u - uo)) <= 1e-12 * np.max(np.abs(uo))
+
+
 def test_decomposition_independence_and_repeatability(bx):
     n = 64
     f = W.uniform_rhs((n, n, n), 24)
