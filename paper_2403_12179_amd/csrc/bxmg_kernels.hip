@@ -108,9 +108,12 @@ struct Nbr {
 };
 
 // Loads of cell (i,j,k); returns its element index.  CENTRE: also u there.
+// skip_zm: the z- neighbour (u, and cell beta in MODE 1) is already in n
+// (carried from the plane below by a thread walking planes 2 apart).
 template <class T, int MODE, bool CENTRE>
 __device__ __forceinline__ long long gather(const T* __restrict__ u, const T* __restrict__ beta,
-                                            const FaceArrays<T>& fa, const RBox& B, int i, int j, int k, Nbr<T>& n) {
+                                            const FaceArrays<T>& fa, const RBox& B, int i, int j, int k, Nbr<T>& n,
+                                            bool skip_zm = false) {
     const int c = (i + j + k) & 1;
     const long long rc = rb_row(B, c, j, k);
     const long long ro = rb_row(B, c ^ 1, j, k);
@@ -122,7 +125,7 @@ __device__ __forceinline__ long long gather(const T* __restrict__ u, const T* __
     n.xp = u[ro + mxp];
     n.ym = u[ro - Hy + m];
     n.yp = u[ro + Hy + m];
-    n.zm = u[ro - Hz + m];
+    if (!skip_zm) n.zm = u[ro - Hz + m];
     n.zp = u[ro + Hz + m];
     if constexpr (CENTRE) n.c = u[idx];
     if constexpr (MODE == 1) {
@@ -131,7 +134,7 @@ __device__ __forceinline__ long long gather(const T* __restrict__ u, const T* __
         n.bxp = beta[ro + mxp];
         n.bym = beta[ro - Hy + m];
         n.byp = beta[ro + Hy + m];
-        n.bzm = beta[ro - Hz + m];
+        if (!skip_zm) n.bzm = beta[ro - Hz + m];
         n.bzp = beta[ro + Hz + m];
     } else if constexpr (MODE == 2) {
         const int x = i - fa.dlo[0], y = j - fa.dlo[1], z = k - fa.dlo[2];
@@ -230,7 +233,7 @@ struct BoxRes<float> {
 // gather() through box resources; offsets relative to the box start
 template <class T, int MODE, bool CENTRE>
 __device__ __forceinline__ int gather_res(const BoxRes<T>& U, const BoxRes<T>& Bt, const FaceArrays<T>& fa,
-                                          const RBox& B, int i, int j, int k, Nbr<T>& n) {
+                                          const RBox& B, int i, int j, int k, Nbr<T>& n, bool skip_zm = false) {
     const int c = (i + j + k) & 1;
     const int row = ((k - B.glo[2]) * B.G[1] + (j - B.glo[1])) * B.H;
     const int cs = (int)B.cstride;
@@ -243,7 +246,7 @@ __device__ __forceinline__ int gather_res(const BoxRes<T>& U, const BoxRes<T>& B
     n.xp = U.ld(ro + mxp);
     n.ym = U.ld(ro - Hy + m);
     n.yp = U.ld(ro + Hy + m);
-    n.zm = U.ld(ro - Hz + m);
+    if (!skip_zm) n.zm = U.ld(ro - Hz + m);
     n.zp = U.ld(ro + Hz + m);
     if constexpr (CENTRE) n.c = U.ld(idx);
     if constexpr (MODE == 1) {
@@ -252,7 +255,7 @@ __device__ __forceinline__ int gather_res(const BoxRes<T>& U, const BoxRes<T>& B
         n.bxp = Bt.ld(ro + mxp);
         n.bym = Bt.ld(ro - Hy + m);
         n.byp = Bt.ld(ro + Hy + m);
-        n.bzm = Bt.ld(ro - Hz + m);
+        if (!skip_zm) n.bzm = Bt.ld(ro - Hz + m);
         n.bzp = Bt.ld(ro + Hz + m);
     } else if constexpr (MODE == 2) {
         const int x = i - fa.dlo[0], y = j - fa.dlo[1], z = k - fa.dlo[2];
@@ -270,13 +273,6 @@ __device__ __forceinline__ int gather_res(const BoxRes<T>& U, const BoxRes<T>& B
     return idx;
 }
 
-// Cells whose loads a thread issues together: the z planes it walks, in
-// groups of kZB (constant coefficient) or kZBVar (coefficient loads too).
-#ifndef BXMG_ZB
-#define BXMG_ZB 1
-#endif
-constexpr int kZB = BXMG_ZB;
-constexpr int kZBVar = 1;
 
 // Ghost exchange fused into a producer: cell (i,j,k) of box B just took value
 // v; write v into every face ghost cell that mirrors it -- the ghost of the
@@ -382,40 +378,41 @@ __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const 
     if (j > B.hi[1]) return;
     const long long ne = 2 * B.cstride;
     const BoxRes<T> U(u + B.base, ne), F(f + B.base, ne), Bt((MODE == 1 ? beta : f) + B.base, ne);
-    constexpr int ZB = (MODE == 0) ? kZB : kZBVar;
-    for (int z0 = 0; z0 < (int)tl.zc; z0 += ZB) {
-        Nbr<T> nb[ZB];
-        T fv[ZB];
-        long long idx[ZB];
-        int ii[ZB], kk[ZB];
-        bool ok[ZB];
-#pragma unroll
-        for (int q = 0; q < ZB; ++q) {
-            const int k = B.lo[2] + th.z0 + (z0 + q) * th.dz;
-            const int i = colour_i(B, th.x, j, k, colour);
-            ii[q] = i;
-            kk[q] = k;
-            ok[q] = (z0 + q < (int)tl.zc) && k <= B.hi[2] && i <= B.hi[0];
-            if (ok[q]) {
-                if constexpr (RES) {
-                    idx[q] = gather_res<T, MODE, false>(U, Bt, fa, B, i, j, k, nb[q]);
-                    fv[q] = F.ld((int)idx[q]);
-                } else {
-                    idx[q] = gather<T, MODE, false>(u, beta, fa, B, i, j, k, nb[q]);
-                    fv[q] = f[idx[q]];
-                }
-            }
+    // Walking planes 2 apart, a thread's cell keeps its x position (same
+    // colour parity), so the z+ neighbour of one plane is the z- neighbour of
+    // the next: kept in registers instead of loaded again (one load of seven).
+    const bool walk2 = th.dz == 2;
+    T carry_u = T(0), carry_b = T(0);
+    bool carry = false;
+    for (int z = 0; z < (int)tl.zc; ++z) {
+        const int k = B.lo[2] + th.z0 + z * th.dz;
+        const int i = colour_i(B, th.x, j, k, colour);
+        if (k > B.hi[2]) break;
+        if (i > B.hi[0]) {  // only where the walk changes the cell's parity
+            carry = false;
+            continue;
         }
-#pragma unroll
-        for (int q = 0; q < ZB; ++q) {
-            if (!ok[q]) continue;
-            T su, sb;
-            sums<T, MODE>(nb[q], su, sb);
-            const T v = (su - h2 * fv[q]) / sb;
-            if constexpr (RES) U.st((int)idx[q], v);
-            else u[idx[q]] = v;
-            if constexpr (PUSH) push_ghosts(u, g.boxes, B, ii[q], j, kk[q], v);
+        Nbr<T> nb;
+        nb.zm = carry_u;
+        nb.bzm = carry_b;
+        long long idx;
+        T fv;
+        if constexpr (RES) {
+            idx = gather_res<T, MODE, false>(U, Bt, fa, B, i, j, k, nb, carry);
+            fv = F.ld((int)idx);
+        } else {
+            idx = gather<T, MODE, false>(u, beta, fa, B, i, j, k, nb, carry);
+            fv = f[idx];
         }
+        T su, sb;
+        sums<T, MODE>(nb, su, sb);
+        const T v = (su - h2 * fv) / sb;
+        if constexpr (RES) U.st((int)idx, v);
+        else u[idx] = v;
+        if constexpr (PUSH) push_ghosts(u, g.boxes, B, i, j, k, v);
+        carry = walk2;
+        carry_u = nb.zp;
+        if constexpr (MODE == 1) carry_b = nb.bzp;
     }
 }
 
@@ -441,44 +438,48 @@ __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ 
     const BoxRes<T> U(u + B.base, ne), F(f + B.base, ne), Bt((MODE == 1 ? beta : f) + B.base, ne);
     const BoxRes<R> Rr(r ? r + B.base : (R*)nullptr, r ? ne : 0);
     if (j <= B.hi[1]) {
-        constexpr int ZB = (MODE == 0) ? kZB : kZBVar;
-        for (int z0 = 0; z0 < (int)tl.zc; z0 += ZB) {
-            Nbr<T> nb[ZB][2];
-            T fv[ZB][2];
-            long long idx[ZB][2];
-            bool ok[ZB][2];
+        // z+ of one plane is z- of the next when walking planes 2 apart (see k_gs)
+        const bool walk2 = th.dz == 2;
+        T carry_u[2] = {T(0), T(0)}, carry_b[2] = {T(0), T(0)};
+        bool carry[2] = {false, false};
+        for (int z = 0; z < (int)tl.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            if (k > B.hi[2]) break;
+            Nbr<T> nb[2];
+            T fv[2];
+            long long idx[2];
+            bool ok[2];
 #pragma unroll
-            for (int q = 0; q < ZB; ++q) {
-                const int k = B.lo[2] + th.z0 + (z0 + q) * th.dz;
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int i = colour_i(B, th.x, j, k, c);
-                    ok[q][c] = (z0 + q < (int)tl.zc) && k <= B.hi[2] && i <= B.hi[0];
-                    if (ok[q][c]) {
-                        if constexpr (RES) {
-                            idx[q][c] = gather_res<T, MODE, true>(U, Bt, fa, B, i, j, k, nb[q][c]);
-                            fv[q][c] = F.ld((int)idx[q][c]);
-                        } else {
-                            idx[q][c] = gather<T, MODE, true>(u, beta, fa, B, i, j, k, nb[q][c]);
-                            fv[q][c] = f[idx[q][c]];
-                        }
+            for (int c = 0; c < 2; ++c) {
+                const int i = colour_i(B, th.x, j, k, c);
+                ok[c] = i <= B.hi[0];
+                nb[c].zm = carry_u[c];
+                nb[c].bzm = carry_b[c];
+                if (ok[c]) {
+                    if constexpr (RES) {
+                        idx[c] = gather_res<T, MODE, true>(U, Bt, fa, B, i, j, k, nb[c], carry[c]);
+                        fv[c] = F.ld((int)idx[c]);
+                    } else {
+                        idx[c] = gather<T, MODE, true>(u, beta, fa, B, i, j, k, nb[c], carry[c]);
+                        fv[c] = f[idx[c]];
                     }
                 }
             }
 #pragma unroll
-            for (int q = 0; q < ZB; ++q)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    if (!ok[q][c]) continue;
-                    T su, sb;
-                    sums<T, MODE>(nb[q][c], su, sb);
-                    const T rv = fv[q][c] - (su - sb * nb[q][c].c) * ih2;
-                    if (r) {
-                        if constexpr (RES) Rr.st((int)idx[q][c], (R)rv);
-                        else r[idx[q][c]] = (R)rv;
-                    }
-                    acc_norm((double)rv, mx, s2, bad);
+            for (int c = 0; c < 2; ++c) {
+                carry[c] = walk2 && ok[c];
+                carry_u[c] = nb[c].zp;
+                if constexpr (MODE == 1) carry_b[c] = nb[c].bzp;
+                if (!ok[c]) continue;
+                T su, sb;
+                sums<T, MODE>(nb[c], su, sb);
+                const T rv = fv[c] - (su - sb * nb[c].c) * ih2;
+                if (r) {
+                    if constexpr (RES) Rr.st((int)idx[c], (R)rv);
+                    else r[idx[c]] = (R)rv;
                 }
+                acc_norm((double)rv, mx, s2, bad);
+            }
         }
     }
     block_reduce3(mx, s2, bad, sh);
