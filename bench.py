@@ -56,6 +56,7 @@ PEAK_GBPS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_2403_12179_amd", "csrc", "bxmg_kernels.hip")
 COUNTERS = os.path.join(ROOT, "profiles", "counters_gs_level0_256c512.json")
 GS_KERNEL = "k_gs<double, 0>"
+GS_MATCH = "k_gs<double, 0"
 COPY_BYTES = 1 << 30
 
 # Compulsory bytes per fine cell per V(2,2) cycle, FP64 (s = 8 B), per level
@@ -129,14 +130,17 @@ def summarize_counters(d, knobs=""):
                                     "where counter_name = ?", (counter,)))
         return out
 
-    def per_dispatch(rs, match, min_grid):
-        vals = {}
+    def per_dispatch(rs, match, largest_only):
+        vals, grids = {}, {}
         for disp, name, grid, value in rs:
-            if match in name and grid >= min_grid:
+            if match in name:
                 vals[disp] = vals.get(disp, 0.0) + float(value)
+                grids[disp] = grid
+        if largest_only:  # the level-0 launches are the largest of the kernel
+            top = max(grids.values(), default=0)
+            return [v for d, v in vals.items() if grids[d] == top]
         return list(vals.values())
 
-    level0_threads = (N ** 3) // 2 // 4  # one colour of level 0, >= 1 cell per thread
     out = {"kernel": GS_KERNEL, "workload": "256^3 in 512 boxes of 32^3, FP64", "kernel_src_sha": src_sha(),
            "commands": ["cd /tmp && timeout -s KILL 300 rocprofv3 --pmc %s -d $REPO/%s/%s -o c2 -- python3 "
                         "$REPO/bench.py --steps 1 --warmup 0 --no-cpu-baseline --sections '' --knobs %s "
@@ -144,8 +148,8 @@ def summarize_counters(d, knobs=""):
                         for c, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write"))]}
     for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
         rs = rows(sub, counter)
-        gs = per_dispatch(rs, "k_gs", level0_threads)
-        cp = per_dispatch(rs, "MulFunctor", 0)
+        gs = per_dispatch(rs, GS_MATCH, True)
+        cp = per_dispatch(rs, "MulFunctor", False)
         if not gs or not cp:
             raise SystemExit("missing dispatches for %s (gs %d, copy %d)" % (counter, len(gs), len(cp)))
         out[counter.lower() + "_kib_per_launch"] = sum(gs) / len(gs)

@@ -204,10 +204,9 @@ void plan_device(GeoPlan& P, const bxmg_ctx_s* ctx, bool var) {
     P.rb1.upload(P.L[1].rb);
     P.cbox0.upload(L0.cbox);
     P.res0 = (ctx->res && boxes_fit_res(L0.rb)) ? 1 : 0;
-    // the problem's own level-0 tiles, exactly those of a lone solve: the
-    // conversions, the norm of f and the periodic mean run over them
-    const std::vector<Tile> t0 =
-        level_tiles(L0.ecol, ctx->zc, ctx->zc_planes, ctx->ly_cap, kMinLevelTiles).tiles;
+    // the problem's own level-0 tiles: those over which a lone solve sums the
+    // periodic mean (the conversions and the norm of f run over them too)
+    const std::vector<Tile> t0 = mean_tiles(L0.ecol).tiles;
     P.t0.upload(t0);
     P.nt0 = (int)t0.size();
     if (var) {

@@ -77,6 +77,10 @@ struct Level {
     bool push = false;    // producers refresh the face ghosts they mirror
     mutable int flip = 0; // direction of the next sweep over the level's tiles
     bool res = false;     // 32-bit buffer addressing of the boxes
+    // level 0: the fixed tiles of the periodic mean (mean_tiles)
+    DevBuf<Tile> tmean;
+    int ntmean = 0;
+    Grid mean_grid() const { return Grid{d_rb.p, tmean.p, ntmean, push ? 1 : 0, nullptr, 0, res ? 1 : 0}; }
     Grid grid() const { return Grid{d_rb.p, tcol.p, ntcol, push ? 1 : 0, nullptr, 0, res ? 1 : 0}; }
     // grid of the next sweep in the alternating order (see tile_index)
     Grid walk() const {
@@ -85,6 +89,7 @@ struct Level {
         flip ^= 1;
         return g;
     }
+
 };
 
 }  // namespace
@@ -165,6 +170,10 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
         {
             upload_tiles(level_tiles(colour_extents(lv->boxes), tune.zc, tune.zc_planes, tune.ly_cap, kMinLevelTiles),
                          lv->tcol, lv->ntcol);
+            if (l == 0) {
+                upload_tiles(mean_tiles(colour_extents(lv->boxes)), lv->tmean, lv->ntmean);
+                max_tiles = std::max<long long>(max_tiles, lv->ntmean);
+            }
         }
         max_tiles = std::max<long long>(max_tiles, lv->ntcol);
         if (l + 1 < lb.size()) {
@@ -948,7 +957,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         }
         info->cycles = cyc;
         if (ba->per[0] && ba->per[1] && ba->per[2])
-            HIPCHK(launch_mean_sub(R.s, L0.grid(), u, H->partials.p));
+            HIPCHK(launch_mean_sub(R.s, L0.mean_grid(), u, H->partials.p));
         HIPCHK(launch_rb_to_fab(R.s, L0.grid(), u, (double*)phi->data, phi->d_fboxes.p));
         HIPCHK(hipStreamSynchronize(R.s));
         ctx->prof.harvest();

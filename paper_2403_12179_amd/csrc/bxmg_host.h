@@ -296,15 +296,19 @@ inline TileSet make_tiles(const std::vector<std::array<int, 3>>& ext, int zc_tar
 }
 
 // The colour-cell tiles of a level: zc planes per thread, or zc_planes where
-// a tile spans whole box planes.  The single-problem solver uses them for its
-// level launches and the periodic mean; a batch uses the same level-0 tiles
-// for the mean, so both sum the mean in the same order.
+// a tile spans whole box planes.
 inline TileSet level_tiles(const std::vector<std::array<int, 3>>& ecol, int zc, int zc_planes, int ly_cap,
                            long long min_tiles) {
     TileSet ts = make_tiles(ecol, zc, ly_cap, min_tiles);
     if (ts.sh.lz == 0) ts = make_tiles(ecol, zc_planes, ly_cap, min_tiles);
     return ts;
 }
+
+// The tiles over which the periodic solution mean is summed: a fixed shape
+// that no launch knob changes, so the mean's rounding -- and with it every
+// bit of a periodic solution -- does not depend on the knobs; the lone and
+// the batched solve both use it.
+inline TileSet mean_tiles(const std::vector<std::array<int, 3>>& ecol) { return level_tiles(ecol, 4, 4, 8, 0); }
 
 // Colour-cell extents: ceil(nx/2) cells of one colour per row.
 inline std::vector<std::array<int, 3>> colour_extents(const std::vector<Box>& boxes) {

@@ -229,18 +229,20 @@ def test_non_aligned_boxes_use_ghost_refresh(bx, orc):
         assert np.array_equal(phi.to_global(), orc.unpack_valid(U, (0, 0, 0), (n - 1,) * 3, boxes, 1))
 
 
-def test_launch_knobs_do_not_change_results(bx):
+@pytest.mark.parametrize("per", [0, 1])
+def test_launch_knobs_do_not_change_results(bx, per):
     """Tile depth, tile rows, buffer addressing and where the coarse cycle
     keeps its levels change the work split and the instructions, never the
-    arithmetic: fixed-cycle iterates are bitwise equal under every setting,
-    and the autotuner leaves a valid setting."""
+    arithmetic: fixed-cycle iterates are bitwise equal under every setting
+    (periodic ones too: the solution mean is summed over fixed tiles), and the
+    autotuner leaves a valid setting."""
     n = 64
-    f = W.uniform_rhs((n, n, n), 27)
-    ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 32, (0, 0, 0), f)
+    f = W.uniform_rhs((n, n, n), 27, mean_zero=bool(per))
+    ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 32, (per,) * 3, f)
     lib, ctx = bx.lib(), phi.ctx
     ref = None
     try:
-        for zc, res, ly, lds in [(4, 1, 8, 1), (1, 0, 8, 0), (8, 1, 2, 1), (2, 0, 3, 0)]:
+        for zc, res, ly, lds in [(4, 1, 8, 1), (1, 0, 8, 0), (8, 1, 2, 1), (2, 0, 3, 0), (1, 1, 2, 0)]:
             for param, value in ((0, zc), (1, zc), (2, res), (3, ly), (4, lds)):
                 bx._lib.check(lib.bxmg_ctx_tune(ctx._h, param, value))
             for precision in (0, 1):
