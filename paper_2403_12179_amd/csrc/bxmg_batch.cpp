@@ -144,13 +144,13 @@ bool plan_geometry(const bxmg_ba_s* ba, double h0, GeoPlan& P, std::string* why)
         v.dom = lb[l].dom;
         v.h = h;
         h *= 2.0;
-        v.boxes = lb[l].boxes;
+        v.boxes = execution_boxes(lb[l], l);
         v.rb = rb_layout(v.boxes, 1, v.h, &v.nelem);
         v.push = face_neighbours(v.dom, P.per, v.boxes, v.rb);
         v.off = off;
         for (auto& r : v.rb) r.base += off;
         off += v.nelem;
-        if (l + 1 < nl) v.cbox = coarse_owner(v.boxes, lb[l + 1].boxes);
+        if (l + 1 < nl) v.cbox = coarse_owner(v.boxes, execution_boxes(lb[l + 1], l + 1));
         v.ecol = colour_extents(v.boxes);
         if (l + 1 < nl) v.edown = coarse_extents(v.boxes, v.dom, -1);
         if (l >= 1)

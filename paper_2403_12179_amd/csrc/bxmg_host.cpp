@@ -149,7 +149,10 @@ static void upload_tiles(const TileSet& t, DevBuf<Tile>& buf, int& n) {
     n = (int)t.tiles.size();
 }
 
-static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool var, double h0, const Tuning& tune) {
+// merge: coarse levels run on execution_boxes (solves); the stage calls keep
+// the logical boxes, which their caller's MultiFabs are laid out on.
+static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool var, double h0, const Tuning& tune,
+                                        bool merge) {
     auto H = std::make_unique<Hier>();
     for (int d = 0; d < 3; ++d) H->per[d] = ba->per[d];
     H->precision = precision;
@@ -162,7 +165,7 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
         lv->dom = lb[l].dom;
         lv->h = h;
         h *= 2.0;
-        lv->boxes = lb[l].boxes;
+        lv->boxes = merge ? execution_boxes(lb[l], l) : lb[l].boxes;
         lv->rb = rb_layout(lv->boxes, 1, lv->h, &lv->nelem);
         lv->push = face_neighbours(lv->dom, H->per, lv->boxes, lv->rb);
         lv->res = tune.res && boxes_fit_res(lv->rb);
@@ -179,7 +182,7 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
         if (l + 1 < lb.size()) {
             upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, -1), tune.zc, tune.ly_cap, kMinLevelTiles),
                          lv->tdown, lv->ntdown);
-            lv->cbox.upload(coarse_owner(lv->boxes, lb[l + 1].boxes));
+            lv->cbox.upload(coarse_owner(lv->boxes, merge ? execution_boxes(lb[l + 1], l + 1) : lb[l + 1].boxes));
             if (var && l == 0)
                 for (int d = 0; d < 3; ++d)
                     upload_tiles(make_tiles(coarse_extents(lv->boxes, lv->dom, d), tune.zc), lv->tface[d], lv->ntface[d]);
@@ -783,13 +786,15 @@ static bxmg_status set_status(bxmg_solve_info* info, bxmg_status st) {
 constexpr size_t kCacheEntries = 16;
 constexpr size_t kCacheBytes = size_t(48) << 30;
 
-static std::string hier_key(const bxmg_ctx_s* ctx, const bxmg_ba_s* ba, int precision, bool var, double h) {
+static std::string hier_key(const bxmg_ctx_s* ctx, const bxmg_ba_s* ba, int precision, bool var, double h,
+                            bool merge) {
     std::string k;
     auto put = [&](long long x) { k.append((const char*)&x, sizeof x); };
     long long hb;
     std::memcpy(&hb, &h, sizeof hb);
     put(precision);
     put(var);
+    put(merge);
     put(hb);
     put(ctx->zc);
     put(ctx->zc_planes);
@@ -821,8 +826,9 @@ static void cache_trim(bxmg_ctx ctx, const std::string& keep) {
     }
 }
 
-static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var, double h, bxmg_status* st) {
-    const std::string key = hier_key(ctx, ba, precision, var, h);
+static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var, double h, bxmg_status* st,
+                      bool merge = true) {
+    const std::string key = hier_key(ctx, ba, precision, var, h, merge);
     auto it = ctx->cache.find(key);
     if (it != ctx->cache.end()) {
         cache_touch(ctx, key);
@@ -842,7 +848,7 @@ static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var
         tune.zc_planes = ctx->zc_planes;
         tune.res = ctx->res;
         tune.ly_cap = ctx->ly_cap;
-        H = build_hier(ba, precision, var, h, tune);
+        H = build_hier(ba, precision, var, h, tune, merge);
     } catch (HipError& e) {
         *st = fail(e.e == hipErrorOutOfMemory ? BXMG_ENOMEM : BXMG_EDEVICE,
                    std::string("solve: hierarchy setup: ") + e.where + ": " + hipGetErrorString(e.e));
@@ -1073,7 +1079,7 @@ static bxmg_status stage_prepare(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab 
     if (beta && (st = check_solve_mf(beta, phi->ba, "beta")) != BXMG_OK) return st;
     if (!(h > 0)) return fail(BXMG_EINVAL, "stage: h must be positive");
     st = BXMG_OK;
-    Hier* H = get_hier(ctx, phi->ba, 0, beta != nullptr, h, &st);
+    Hier* H = get_hier(ctx, phi->ba, 0, beta != nullptr, h, &st, false);
     if (!H) return st;
     *Hout = H;
     return BXMG_OK;

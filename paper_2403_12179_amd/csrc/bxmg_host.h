@@ -126,6 +126,26 @@ inline std::vector<LevelBoxes> make_hierarchy(const Box& dom, const std::vector<
     return L;
 }
 
+// The boxes a level runs on (its storage and launches).  Level 0 keeps the
+// caller's boxes.  A coarser level whose boxes tile its whole domain runs as
+// the one domain box, up to kMergeCells cells: the smoother, transfers and
+// residuals give the same values under any decomposition (every ghost a
+// kernel reads holds exactly the neighbour's value), and one large box has no
+// exchange between boxes, long rows and fewer ghost cells.  The logical
+// hierarchy (make_hierarchy) is unchanged.
+constexpr long long kMergeCells = 1LL << 26;
+
+inline std::vector<Box> execution_boxes(const LevelBoxes& lv, size_t l) {
+    if (l == 0 || lv.boxes.size() <= 1 || lv.dom.cells() > kMergeCells) return lv.boxes;
+    long long vol = 0;
+    for (auto& b : lv.boxes) {
+        if (!lv.dom.contains(b)) return lv.boxes;
+        vol += b.cells();
+    }
+    if (vol != lv.dom.cells()) return lv.boxes;  // boxes are disjoint: equal volume = exact tiling
+    return {lv.dom};
+}
+
 // --------------------------------------------------------- ghost-copy plans
 // Region tags for the ghost cells of every box grown by ng.
 // mode 0: FillBoundary (periodic shifts; ghosts outside a non-periodic face
