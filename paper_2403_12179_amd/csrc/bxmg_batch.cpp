@@ -88,6 +88,7 @@ struct PlanLevel {
     std::vector<int> cbox;  // coarse owner (level l+1, local index)
     std::vector<std::array<int, 3>> ecol, edown;
     std::vector<Tile> tcol, tdown;  // tiles of the level alone (box = local index)
+    int stage_values = 0;           // prolongation: coarse values a colour tile reads (bound)
     DevBuf<GhostCopy> face[2], full;    // indices relative to the problem start
     DevBuf<GhostCopy> cface[2], cfull;  // relative to the level start (coarse-cycle levels)
     long long fface[3] = {0, 0, 0};     // face-array offsets (variable coefficient)
@@ -174,7 +175,9 @@ void plan_device(GeoPlan& P, const bxmg_ctx_s* ctx, bool var) {
         PlanLevel& v = P.L[l];
         if ((int)l < P.cs) {
             // batched launches have many problems' tiles: no minimum per problem
-            v.tcol = level_tiles(v.ecol, ctx->zc, ctx->zc_planes, ctx->ly_cap, 0).tiles;
+            const TileSet tc = level_tiles(v.ecol, ctx->zc, ctx->zc_planes, ctx->ly_cap, 0);
+            v.tcol = tc.tiles;
+            v.stage_values = prolong_stage_values(tc.sh);
             v.tdown = make_tiles(v.edown, ctx->zc, ctx->ly_cap).tiles;
         }
         const std::vector<Tag> faces = build_tags(v.dom, P.per, v.boxes, 1, true, 2, true);
@@ -254,6 +257,7 @@ struct BLevel {
     DevVec<int> cbox;
     bool push = true;
     int res = 1;
+    int stage_values = 0;  // largest prolongation stage of the member problems' tiles
     DevVec<GhostSet> face[2], fullc;  // face ghosts of l; every ghost of l + 1
     int nface = 0, nfullc = 0;
     long long mface = 0, mfullc = 0;
@@ -468,6 +472,7 @@ void rebuild(bxmg_batch_s* b) {
         std::vector<GhostSet> face[2], fullc;
         std::vector<ZeroRange> zr;
         B.push = true;
+        B.stage_values = 0;
         B.mface = B.mfullc = B.zmax = 0;
         for (int s : b->members) {
             const Problem& p = *b->slots[s];
@@ -476,6 +481,7 @@ void rebuild(bxmg_batch_s* b) {
             const int f0 = first[l][s];
             if (l == 0) segslot.push_back(s);
             for (Tile t : v.tcol) { t.box += f0; tcol.push_back(t); }
+            B.stage_values = std::max(B.stage_values, v.stage_values);
             for (Tile t : v.tdown) { t.box += f0; tdown.push_back(t); }
             if (l == 0) tstart.push_back((int)tcol.size());
             for (size_t q = 0; q < v.boxes.size(); ++q) cbox_full[f0 + q] = first[l + 1][s] + v.cbox[q];
@@ -638,7 +644,7 @@ void b_vcycle(bxmg_batch_s* b, hipStream_t s) {
         BLevel& B = b->lev[l];
         HIPCHK(launch_fill_sets(s, u, f32, B.fullc.p(), B.nfullc, B.mfullc, b->active.p));
         HIPCHK(launch_prolong<T>(s, level_grid(b, l), b->lev[l + 1].rb.p(), B.cbox.p(), u, u, b->P.prolong,
-                                 b->P.nu2 > 0));
+                                 b->P.nu2 > 0, B.stage_values));
         b_smooth<T>(b, s, l, b->P.nu2);
     }
 }

@@ -81,6 +81,7 @@ struct Level {
     DevBuf<Tile> tmean;
     int ntmean = 0;
     Grid mean_grid() const { return Grid{d_rb.p, tmean.p, ntmean, push ? 1 : 0, nullptr, 0, res ? 1 : 0}; }
+    int stage_values = 0;  // coarse values a colour tile reads in a prolongation (bound)
     Grid grid() const { return Grid{d_rb.p, tcol.p, ntcol, push ? 1 : 0, nullptr, 0, res ? 1 : 0}; }
     // grid of the next sweep in the alternating order (see tile_index)
     Grid walk() const {
@@ -171,8 +172,10 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
         lv->res = tune.res && boxes_fit_res(lv->rb);
         lv->d_rb.upload(lv->rb);
         {
-            upload_tiles(level_tiles(colour_extents(lv->boxes), tune.zc, tune.zc_planes, tune.ly_cap, kMinLevelTiles),
-                         lv->tcol, lv->ntcol);
+            const TileSet ts =
+                level_tiles(colour_extents(lv->boxes), tune.zc, tune.zc_planes, tune.ly_cap, kMinLevelTiles);
+            upload_tiles(ts, lv->tcol, lv->ntcol);
+            lv->stage_values = prolong_stage_values(ts.sh);
             if (l == 0) {
                 upload_tiles(mean_tiles(colour_extents(lv->boxes)), lv->tmean, lv->ntmean);
                 max_tiles = std::max<long long>(max_tiles, lv->ntmean);
@@ -466,7 +469,8 @@ void vcycle(Run& R, size_t l) {
     fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full);
     R.pre(l, kStageProlong);
     // with post-smoothing, its first (colour-0) sweep overwrites colour 0
-    HIPCHK(launch_prolong<T>(R.s, L.walk(), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong, R.nu2 > 0));
+    HIPCHK(launch_prolong<T>(R.s, L.walk(), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong, R.nu2 > 0,
+                             L.stage_values));
     R.post(l, kStageProlong);
     smooth<T>(R, l, R.nu2);
 }

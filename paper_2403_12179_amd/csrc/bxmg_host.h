@@ -324,6 +324,14 @@ inline TileSet level_tiles(const std::vector<std::array<int, 3>>& ecol, int zc, 
     return ts;
 }
 
+// Upper bound of the coarse values a tile of this shape reads in a
+// prolongation (parents of its cells and one layer around them; the fine
+// boxes are pair aligned): what the LDS-staged kernel must hold.
+inline int prolong_stage_values(const TileShape& sh) {
+    const int TX = 1 << sh.lx, TY = 1 << sh.ly, TZ = (1 << sh.lz) * sh.zc;
+    return (TX + 3) * (((TY + 1) >> 1) + 3) * (((TZ + 1) >> 1) + 3);
+}
+
 // The tiles over which the periodic solution mean is summed: a fixed shape
 // that no launch knob changes, so the mean's rounding -- and with it every
 // bit of a periodic solution -- does not depend on the knobs; the lone and

@@ -212,9 +212,12 @@ hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* 
 // Gauss-Seidel sweep follows; on levels that push their ghosts, correct the
 // colour-1 cells and only the Dirichlet ghosts of colour-0 cells (the sweep
 // overwrites colour 0 reading it only through those ghosts).
+// stage_values: the largest coarse region (values) a tile of the fine level
+// reads (prolong_stage_values); where it fits the LDS stage, the colour-1
+// kernel stages it (0: never).
 template <class T>
 hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
-                          int order, bool only_c1 = false);
+                          int order, bool only_c1 = false, int stage_values = 0);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n);

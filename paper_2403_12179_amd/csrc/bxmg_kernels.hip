@@ -935,6 +935,90 @@ __global__ void __launch_bounds__(kBlock) k_prolong_c1(Grid g, const RBox* __res
     }
 }
 
+// k_prolong_c1 with the tile's coarse region staged in LDS: the workgroup
+// loads every coarse value its tile reads (parents and the layer around
+// them) once, then each cell takes its 8 values from LDS instead of from the
+// vector memory path.  Same cells, values and arithmetic as k_prolong_c1.
+// The host launches it where the region fits kStageCoarse values.
+constexpr int kStageCoarse = 2048;
+
+template <class T, int ORDER>
+__global__ void __launch_bounds__(kBlock) k_prolong_c1s(Grid g, const RBox* __restrict__ cboxes,
+                                                       const int* __restrict__ cbox, const T* __restrict__ ec,
+                                                       T* __restrict__ uf) {
+    __shared__ T cs[kStageCoarse];
+    const Tile tl = g.tiles[tile_index(g.rev)];
+    const RBox B = g.boxes[tl.box];
+    if (g.active && !g.active[B.pid]) return;  // the whole workgroup
+    const RBox C = cboxes[cbox[tl.box]];
+    // the tile's fine cells (clamped to the box) and the coarse cells around
+    // their parents (inside the coarse box grown by its ghost layer)
+    const int TX = 1 << tl.lx, TY = 1 << tl.ly, TZ = 1 << tl.lz;
+    const int ilo = B.lo[0] + 2 * tl.x0, ihi = min(B.hi[0], B.lo[0] + 2 * (tl.x0 + TX) - 1);
+    const int jlo = B.lo[1] + tl.y0, jhi = min(B.hi[1], jlo + TY - 1);
+    const int klo = B.lo[2] + tl.z0, khi = min(B.hi[2], klo + TZ * tl.zc - 1);
+    const int Ilo = (ilo >> 1) - 1, Jlo = (jlo >> 1) - 1, Klo = (klo >> 1) - 1;
+    const int nI = (ihi >> 1) + 2 - Ilo, nJ = (jhi >> 1) + 2 - Jlo, nK = (khi >> 1) + 2 - Klo;
+    const int n = nI * nJ * nK;
+    const T* __restrict__ cb = ec + C.base;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int r = q / nI, c = r / nJ;
+        cs[q] = cb[rb_off(C, Ilo + (q - r * nI), Jlo + (r - c * nJ), Klo + c)];
+    }
+    __syncthreads();
+    const TileThread th = tile_thread(tl);
+    const int j = B.lo[1] + th.y;
+    if (j > B.hi[1]) return;
+    const int J = j >> 1, sj = (j & 1) ? 1 : -1;
+    T* __restrict__ fb = uf + B.base;
+    auto at = [&](int I, int Jq, int K) { return cs[(I - Ilo) + nI * ((Jq - Jlo) + nJ * (K - Klo))]; };
+    auto interp = [&](int i, int k) -> T {
+        const int I = i >> 1, si = (i & 1) ? 1 : -1, K = k >> 1, sk = (k & 1) ? 1 : -1;
+        if constexpr (ORDER == 1) return at(I, J, K);
+        const T c000 = at(I, J, K), c100 = at(I + si, J, K), c010 = at(I, J + sj, K), c001 = at(I, J, K + sk);
+        const T c110 = at(I + si, J + sj, K), c101 = at(I + si, J, K + sk), c011 = at(I, J + sj, K + sk);
+        const T c111 = at(I + si, J + sj, K + sk);
+        return (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
+               T(0.015625);
+    };
+    const int zc = tl.zc;
+    for (int z0 = 0; z0 < zc; z0 += kProlongGroup) {
+        T fv[kProlongGroup];
+        int off[kProlongGroup];
+#pragma unroll
+        for (int q = 0; q < kProlongGroup; ++q) {
+            const int k = min(B.lo[2] + th.z0 + (z0 + q) * th.dz, B.hi[2]);  // clamped: loads stay in the box
+            const int i = min(colour_i(B, th.x, j, k, 1), B.hi[0]);
+            off[q] = rb_off(B, i, j, k);  // the clamped cell may be colour 0: its value is never used
+            fv[q] = fb[off[q]];
+        }
+#pragma unroll 1
+        for (int q = 0; q < kProlongGroup; ++q) {
+            const int k = B.lo[2] + th.z0 + (z0 + q) * th.dz;
+            if (z0 + q >= zc || k > B.hi[2]) break;
+            const int i = colour_i(B, th.x, j, k, 1);
+            if (i <= B.hi[0]) {
+                const T v = fv[0] + interp(i, k);
+                fb[off[0]] = v;
+                push_ghosts(uf, g.boxes, B, i, j, k, v);
+            }
+            // the colour-0 cell of this row and plane, if it lies on a
+            // Dirichlet face: its mirrored ghost gets -(u + P e)
+            const int i0 = colour_i(B, th.x, j, k, 0);
+            const bool dir = i0 <= B.hi[0] &&
+                             ((i0 == B.lo[0] && B.nb[0] < 0) || (i0 == B.hi[0] && B.nb[1] < 0) ||
+                              (j == B.lo[1] && B.nb[2] < 0) || (j == B.hi[1] && B.nb[3] < 0) ||
+                              (k == B.lo[2] && B.nb[4] < 0) || (k == B.hi[2] && B.nb[5] < 0));
+            if (dir) push_dirichlet(uf, B, i0, j, k, fb[rb_off(B, i0, j, k)] + interp(i0, k));
+#pragma unroll
+            for (int m = 0; m + 1 < kProlongGroup; ++m) {
+                fv[m] = fv[m + 1];
+                off[m] = off[m + 1];
+            }
+        }
+    }
+}
+
 // -------------------------------------------------------------- utilities
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_zero(T* __restrict__ p, long long n) {
@@ -1738,15 +1822,18 @@ template hipError_t launch_restrict_plain<double>(hipStream_t, const XGrid&, con
 
 template <class T>
 hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
-                          int order, bool only_c1) {
+                          int order, bool only_c1, int stage_values) {
     if (fine.ntiles <= 0) return hipSuccess;
     const dim3 G(fine.ntiles), B(kBlock);
     // levels refreshed by fill lists copy ghosts from both colours' cells:
     // they keep the two-colour kernel
     const bool c1 = only_c1 && fine.push;
+    const bool staged = stage_values > 0 && stage_values <= kStageCoarse;
 #define BXMG_PROLONG(PUSH, ORDER)                                                                    \
     do {                                                                                            \
-        if (PUSH && c1) hipLaunchKernelGGL((k_prolong_c1<T, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
+        if (PUSH && c1 && staged)                                                                   \
+            hipLaunchKernelGGL((k_prolong_c1s<T, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf);   \
+        else if (PUSH && c1) hipLaunchKernelGGL((k_prolong_c1<T, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
         else hipLaunchKernelGGL((k_prolong<T, PUSH, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
     } while (0)
     if (order == 1) {
@@ -1760,9 +1847,9 @@ hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, c
     return hipGetLastError();
 }
 template hipError_t launch_prolong<double>(hipStream_t, const Grid&, const RBox*, const int*, const double*, double*,
-                                           int, bool);
+                                           int, bool, int);
 template hipError_t launch_prolong<float>(hipStream_t, const Grid&, const RBox*, const int*, const float*, float*, int,
-                                          bool);
+                                          bool, int);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n) {
