@@ -77,10 +77,22 @@ struct Level {
     bool push = false;    // producers refresh the face ghosts they mirror
     mutable int flip = 0; // direction of the next sweep over the level's tiles
     bool res = false;     // 32-bit buffer addressing of the boxes
-    // level 0: the fixed tiles of the periodic mean (mean_tiles)
+    // level 0 of a solve whose caller boxes were merged: one view per caller
+    // box (its valid cells, addressed in the merged storage) and tiles over
+    // them, for the layout conversions and the field norm
+    bool merged = false;
+    DevBuf<RBox> d_vrb;
+    DevBuf<Tile> tview;
+    int ntview = 0;
+    Grid view_grid() const { return merged ? Grid{d_vrb.p, tview.p, ntview, 0, nullptr, 0, 0} : grid(); }
+    // level 0: the fixed tiles of the periodic mean (mean_tiles over the
+    // caller's boxes, so the sum's order does not depend on merging)
     DevBuf<Tile> tmean;
     int ntmean = 0;
-    Grid mean_grid() const { return Grid{d_rb.p, tmean.p, ntmean, push ? 1 : 0, nullptr, 0, res ? 1 : 0}; }
+    Grid mean_grid() const {
+        return merged ? Grid{d_vrb.p, tmean.p, ntmean, 0, nullptr, 0, 0}
+                      : Grid{d_rb.p, tmean.p, ntmean, push ? 1 : 0, nullptr, 0, res ? 1 : 0};
+    }
     int stage_values = 0;  // coarse values a colour tile reads in a prolongation (bound)
     Grid grid() const { return Grid{d_rb.p, tcol.p, ntcol, push ? 1 : 0, nullptr, 0, res ? 1 : 0}; }
     // grid of the next sweep in the alternating order (see tile_index)
@@ -166,8 +178,26 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
         lv->dom = lb[l].dom;
         lv->h = h;
         h *= 2.0;
-        lv->boxes = merge ? execution_boxes(lb[l], l) : lb[l].boxes;
+        lv->boxes = merge ? execution_boxes(lb[l], l, true) : lb[l].boxes;
         lv->rb = rb_layout(lv->boxes, 1, lv->h, &lv->nelem);
+        if (l == 0 && lv->boxes.size() != lb[0].boxes.size()) {
+            // views of the caller's boxes: their own valid range, the merged
+            // box's addressing (colour parity is global, so rb_idx and
+            // colour_i agree with the merged box)
+            lv->merged = true;
+            std::vector<RBox> v;
+            for (const Box& b : lb[0].boxes) {
+                RBox r = lv->rb[0];
+                for (int d = 0; d < 3; ++d) { r.lo[d] = b.lo[d]; r.hi[d] = b.hi[d]; }
+                for (int q = 0; q < 6; ++q) { r.nb[q] = -1; r.shift[q] = 0; }
+                v.push_back(r);
+            }
+            lv->d_vrb.upload(v);
+            const TileSet tv =
+                level_tiles(colour_extents(lb[0].boxes), tune.zc, tune.zc_planes, tune.ly_cap, kMinLevelTiles);
+            upload_tiles(tv, lv->tview, lv->ntview);
+            max_tiles = std::max<long long>(max_tiles, lv->ntview);
+        }
         lv->push = face_neighbours(lv->dom, H->per, lv->boxes, lv->rb);
         lv->res = tune.res && boxes_fit_res(lv->rb);
         lv->d_rb.upload(lv->rb);
@@ -177,7 +207,7 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
             upload_tiles(ts, lv->tcol, lv->ntcol);
             lv->stage_values = prolong_stage_values(ts.sh);
             if (l == 0) {
-                upload_tiles(mean_tiles(colour_extents(lv->boxes)), lv->tmean, lv->ntmean);
+                upload_tiles(mean_tiles(colour_extents(lb[0].boxes)), lv->tmean, lv->ntmean);
                 max_tiles = std::max<long long>(max_tiles, lv->ntmean);
             }
         }
@@ -900,10 +930,10 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         double* u = H->u64[0]->p;
         double* f = H->f64[0]->p;
         // caller layout -> colour-split level 0
-        HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)phi->data, phi->d_fboxes.p, u, false));
-        HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)rhs->data, rhs->d_fboxes.p, f, false));
+        HIPCHK(launch_fab_to_rb(R.s, L0.view_grid(), (const double*)phi->data, phi->d_fboxes.p, u, false));
+        HIPCHK(launch_fab_to_rb(R.s, L0.view_grid(), (const double*)rhs->data, rhs->d_fboxes.p, f, false));
         if (beta) {
-            HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)beta->data, beta->d_fboxes.p, H->beta64.p, false));
+            HIPCHK(launch_fab_to_rb(R.s, L0.view_grid(), (const double*)beta->data, beta->d_fboxes.p, H->beta64.p, false));
             if (P.precision == 0) {
                 setup_faces<double>(R, H->beta64.p);
             } else {
@@ -916,8 +946,8 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         // level-0 values refreshes the face ghosts it mirrors (push levels)
         fill_faces<double>(R, 0, u);
         const FaceArrays<double>* nf = nullptr;
-        HIPCHK(launch_field_norm(R.s, L0.grid(), f, H->partials.p));
-        HIPCHK(launch_norm_final(R.s, H->partials.p, L0.ntcol, H->fnorm.p));
+        HIPCHK(launch_field_norm(R.s, L0.view_grid(), f, H->partials.p));
+        HIPCHK(launch_norm_final(R.s, H->partials.p, L0.view_grid().ntiles, H->fnorm.p));
         norm_readback(R, ctx->h_norm, H->fnorm.p);
         const double fnorm = ctx->h_norm[0];
         info->f_inf = fnorm;
@@ -968,7 +998,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         info->cycles = cyc;
         if (ba->per[0] && ba->per[1] && ba->per[2])
             HIPCHK(launch_mean_sub(R.s, L0.mean_grid(), u, H->partials.p));
-        HIPCHK(launch_rb_to_fab(R.s, L0.grid(), u, (double*)phi->data, phi->d_fboxes.p));
+        HIPCHK(launch_rb_to_fab(R.s, L0.view_grid(), u, (double*)phi->data, phi->d_fboxes.p));
         HIPCHK(hipStreamSynchronize(R.s));
         ctx->prof.harvest();
         info->status = status;

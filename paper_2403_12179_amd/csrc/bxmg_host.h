@@ -127,7 +127,9 @@ inline std::vector<LevelBoxes> make_hierarchy(const Box& dom, const std::vector<
 }
 
 // The boxes a level runs on (its storage and launches).  Level 0 keeps the
-// caller's boxes.  A coarser level whose boxes tile its whole domain runs as
+// caller's boxes unless fine_too (solves, which reach the caller's boxes
+// through per-box views of the merged storage).  A level whose boxes tile its
+// whole domain runs as
 // the one domain box, up to kMergeCells cells: the smoother, transfers and
 // residuals give the same values under any decomposition (every ghost a
 // kernel reads holds exactly the neighbour's value), and one large box has no
@@ -135,8 +137,8 @@ inline std::vector<LevelBoxes> make_hierarchy(const Box& dom, const std::vector<
 // hierarchy (make_hierarchy) is unchanged.
 constexpr long long kMergeCells = 1LL << 26;
 
-inline std::vector<Box> execution_boxes(const LevelBoxes& lv, size_t l) {
-    if (l == 0 || lv.boxes.size() <= 1 || lv.dom.cells() > kMergeCells) return lv.boxes;
+inline std::vector<Box> execution_boxes(const LevelBoxes& lv, size_t l, bool fine_too = false) {
+    if ((l == 0 && !fine_too) || lv.boxes.size() <= 1 || lv.dom.cells() > kMergeCells) return lv.boxes;
     long long vol = 0;
     for (auto& b : lv.boxes) {
         if (!lv.dom.contains(b)) return lv.boxes;
