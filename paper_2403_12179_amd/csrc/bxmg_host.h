@@ -135,7 +135,7 @@ inline std::vector<LevelBoxes> make_hierarchy(const Box& dom, const std::vector<
 // kernel reads holds exactly the neighbour's value), and one large box has no
 // exchange between boxes, long rows and fewer ghost cells.  The logical
 // hierarchy (make_hierarchy) is unchanged.
-constexpr long long kMergeCells = 1LL << 26;
+constexpr long long kMergeCells = 1LL << 27;
 
 inline std::vector<Box> execution_boxes(const LevelBoxes& lv, size_t l, bool fine_too = false) {
     if ((l == 0 && !fine_too) || lv.boxes.size() <= 1 || lv.dom.cells() > kMergeCells) return lv.boxes;
