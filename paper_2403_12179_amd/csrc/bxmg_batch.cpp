@@ -102,6 +102,11 @@ struct GeoPlan {
     long long len = 0, face_len = 0;
     // level 0 (and 1, for the coefficient setup) of one problem alone
     DevBuf<RBox> rb0, rb1;
+    // the caller's level-0 boxes; when level 0 runs merged, views of them
+    // into the merged storage serve the conversions, the norm of f and the mean
+    std::vector<Box> boxes0;
+    bool merged0 = false;
+    DevBuf<RBox> vrb0;
     DevBuf<Tile> t0;
     int nt0 = 0;
     int res0 = 0;
@@ -109,7 +114,10 @@ struct GeoPlan {
     DevBuf<int> cbox0;
     DevBuf<Tile> tface[3];
     int ntface[3] = {0, 0, 0};
-    Grid grid0() const { return Grid{rb0.p, t0.p, nt0, L[0].push ? 1 : 0, nullptr, 0, res0}; }
+    Grid grid0() const {
+        return merged0 ? Grid{vrb0.p, t0.p, nt0, 0, nullptr, 0, 0}
+                       : Grid{rb0.p, t0.p, nt0, L[0].push ? 1 : 0, nullptr, 0, res0};
+    }
     XGrid face_grid(int d) const {
         return XGrid{rb0.p, rb1.p, cbox0.p, tface[d].p, ntface[d], 0, nullptr, 0, 0};
     }
@@ -138,6 +146,7 @@ bool plan_geometry(const bxmg_ba_s* ba, double h0, GeoPlan& P, std::string* why)
     }
     P.L.clear();
     P.L.resize(nl);
+    P.boxes0 = lb[0].boxes;
     long long off = 0, foff = 0;
     double h = h0;
     for (size_t l = 0; l < nl; ++l) {
@@ -145,7 +154,7 @@ bool plan_geometry(const bxmg_ba_s* ba, double h0, GeoPlan& P, std::string* why)
         v.dom = lb[l].dom;
         v.h = h;
         h *= 2.0;
-        v.boxes = execution_boxes(lb[l], l);
+        v.boxes = execution_boxes(lb[l], l, true);
         v.rb = rb_layout(v.boxes, 1, v.h, &v.nelem);
         v.push = face_neighbours(v.dom, P.per, v.boxes, v.rb);
         v.off = off;
@@ -207,9 +216,21 @@ void plan_device(GeoPlan& P, const bxmg_ctx_s* ctx, bool var) {
     P.rb1.upload(P.L[1].rb);
     P.cbox0.upload(L0.cbox);
     P.res0 = (ctx->res && boxes_fit_res(L0.rb)) ? 1 : 0;
-    // the problem's own level-0 tiles: those over which a lone solve sums the
-    // periodic mean (the conversions and the norm of f run over them too)
-    const std::vector<Tile> t0 = mean_tiles(L0.ecol).tiles;
+    P.merged0 = L0.boxes.size() != P.boxes0.size();
+    if (P.merged0) {
+        std::vector<RBox> v;
+        for (const Box& b : P.boxes0) {
+            RBox r = L0.rb[0];
+            for (int d = 0; d < 3; ++d) { r.lo[d] = b.lo[d]; r.hi[d] = b.hi[d]; }
+            for (int q = 0; q < 6; ++q) { r.nb[q] = -1; r.shift[q] = 0; }
+            v.push_back(r);
+        }
+        P.vrb0.upload(v);
+    }
+    // the problem's own level-0 tiles over the caller's boxes: those over
+    // which a lone solve sums the periodic mean (the conversions and the
+    // norm of f run over them too)
+    const std::vector<Tile> t0 = mean_tiles(colour_extents(P.boxes0)).tiles;
     P.t0.upload(t0);
     P.nt0 = (int)t0.size();
     if (var) {
