@@ -53,7 +53,10 @@ MAX_BOX = 32
 SEED = 2
 TOL = 1e-10
 PEAK_GBPS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2403_12179_amd", "csrc", "bxmg_kernels.hip")
+# the sources that decide what the counted launches do: the kernels, and the
+# host code that lays out the levels and picks their tiles
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2403_12179_amd", "csrc", f)
+               for f in ("bxmg_kernels.hip", "bxmg_host.cpp", "bxmg_host.h")]
 COUNTERS = os.path.join(ROOT, "profiles", "counters_gs_level0_256c512.json")
 GS_KERNEL = "k_gs<double, 0>"
 GS_MATCH = "k_gs<double, 0"
@@ -69,7 +72,10 @@ GS_BYTES_PER_CELL = 1.5 * 8.0  # one colour: read other colour, rhs of this colo
 
 
 def src_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def cpu_info():
