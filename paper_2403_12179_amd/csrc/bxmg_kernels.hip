@@ -199,6 +199,8 @@ __device__ __forceinline__ void stencil(const T* __restrict__ u, const T* __rest
 // of 64-bit addresses.  The hardware bounds-checks every access against the
 // box: a read past its end returns 0 and a write there is dropped.
 constexpr int kBufferDword3 = 0x00020000;  // raw buffer, gfx9 data format
+// A byte offset beyond every box resource (their sizes stay below 2^31 bytes).
+constexpr int kOffPastBox = (int)0x80000000u;
 
 template <class T>
 struct BoxRes;
@@ -210,6 +212,11 @@ struct BoxRes<double> {
         : r(__builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(nelem * 8), kBufferDword3)) {}
     __device__ __forceinline__ double ld(int e) const {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, e * 8, 0, 0));
+    }
+    // element e, or (skip) an offset past every box: the hardware returns 0
+    // without a memory access, so the load needs no branch around it
+    __device__ __forceinline__ double ld_unless(int e, bool skip) const {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, skip ? kOffPastBox : e * 8, 0, 0));
     }
     __device__ __forceinline__ void st(int e, double v) const {
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -225,6 +232,9 @@ struct BoxRes<float> {
     __device__ __forceinline__ float ld(int e) const {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, e * 4, 0, 0));
     }
+    __device__ __forceinline__ float ld_unless(int e, bool skip) const {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, skip ? kOffPastBox : e * 4, 0, 0));
+    }
     __device__ __forceinline__ void st(int e, float v) const {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, e * 4, 0, 0);
     }
@@ -233,7 +243,8 @@ struct BoxRes<float> {
 // gather() through box resources; offsets relative to the box start
 template <class T, int MODE, bool CENTRE>
 __device__ __forceinline__ int gather_res(const BoxRes<T>& U, const BoxRes<T>& Bt, const FaceArrays<T>& fa,
-                                          const RBox& B, int i, int j, int k, Nbr<T>& n, bool skip_zm = false) {
+                                          const RBox& B, int i, int j, int k, Nbr<T>& n, bool skip_zm = false,
+                                          const BoxRes<T>* F = nullptr, T* fv = nullptr) {
     const int c = (i + j + k) & 1;
     const int row = ((k - B.glo[2]) * B.G[1] + (j - B.glo[1])) * B.H;
     const int cs = (int)B.cstride;
@@ -242,11 +253,14 @@ __device__ __forceinline__ int gather_res(const BoxRes<T>& U, const BoxRes<T>& B
     const int m = (i - B.glo[0]) >> 1;
     const int mxm = (i - 1 - B.glo[0]) >> 1, mxp = (i + 1 - B.glo[0]) >> 1;
     const int idx = rc + m;
+    if (F) *fv = F->ld(idx);  // first, so every load of the cell leaves together
     n.xm = U.ld(ro + mxm);
     n.xp = U.ld(ro + mxp);
     n.ym = U.ld(ro - Hy + m);
     n.yp = U.ld(ro + Hy + m);
-    if (!skip_zm) n.zm = U.ld(ro - Hz + m);
+    // branch-free: a branch here would make the wave wait for every load
+    // issued so far before issuing the rest
+    const T zm = U.ld_unless(ro - Hz + m, skip_zm);
     n.zp = U.ld(ro + Hz + m);
     if constexpr (CENTRE) n.c = U.ld(idx);
     if constexpr (MODE == 1) {
@@ -255,7 +269,8 @@ __device__ __forceinline__ int gather_res(const BoxRes<T>& U, const BoxRes<T>& B
         n.bxp = Bt.ld(ro + mxp);
         n.bym = Bt.ld(ro - Hy + m);
         n.byp = Bt.ld(ro + Hy + m);
-        if (!skip_zm) n.bzm = Bt.ld(ro - Hz + m);
+        const T bzm = Bt.ld_unless(ro - Hz + m, skip_zm);
+        n.bzm = skip_zm ? n.bzm : bzm;
         n.bzp = Bt.ld(ro + Hz + m);
     } else if constexpr (MODE == 2) {
         const int x = i - fa.dlo[0], y = j - fa.dlo[1], z = k - fa.dlo[2];
@@ -270,6 +285,7 @@ __device__ __forceinline__ int gather_res(const BoxRes<T>& U, const BoxRes<T>& B
         n.bzm = fa.c[2][iz];
         n.bzp = fa.c[2][iz + (long long)nx * ny];
     }
+    n.zm = skip_zm ? n.zm : zm;
     return idx;
 }
 
@@ -398,8 +414,7 @@ __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const 
         long long idx;
         T fv;
         if constexpr (RES) {
-            idx = gather_res<T, MODE, false>(U, Bt, fa, B, i, j, k, nb, carry);
-            fv = F.ld((int)idx);
+            idx = gather_res<T, MODE, false>(U, Bt, fa, B, i, j, k, nb, carry, &F, &fv);
         } else {
             idx = gather<T, MODE, false>(u, beta, fa, B, i, j, k, nb, carry);
             fv = f[idx];
@@ -455,14 +470,14 @@ __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ 
                 ok[c] = i <= B.hi[0];
                 nb[c].zm = carry_u[c];
                 nb[c].bzm = carry_b[c];
-                if (ok[c]) {
-                    if constexpr (RES) {
-                        idx[c] = gather_res<T, MODE, true>(U, Bt, fa, B, i, j, k, nb[c], carry[c]);
-                        fv[c] = F.ld((int)idx[c]);
-                    } else {
-                        idx[c] = gather<T, MODE, true>(u, beta, fa, B, i, j, k, nb[c], carry[c]);
-                        fv[c] = f[idx[c]];
-                    }
+                if constexpr (RES) {
+                    // without a branch: a missing cell (odd row length)
+                    // gathers the row's last cell, and its result is unused
+                    idx[c] = gather_res<T, MODE, true>(U, Bt, fa, B, ok[c] ? i : B.hi[0], j, k, nb[c],
+                                                       carry[c] && ok[c], &F, &fv[c]);
+                } else if (ok[c]) {
+                    idx[c] = gather<T, MODE, true>(u, beta, fa, B, i, j, k, nb[c], carry[c]);
+                    fv[c] = f[idx[c]];
                 }
             }
 #pragma unroll
@@ -961,37 +976,73 @@ __global__ void __launch_bounds__(kBlock) k_prolong_c1s(Grid g, const RBox* __re
     const int nI = (ihi >> 1) + 2 - Ilo, nJ = (jhi >> 1) + 2 - Jlo, nK = (khi >> 1) + 2 - Klo;
     const int n = nI * nJ * nK;
     const T* __restrict__ cb = ec + C.base;
-    for (int q = threadIdx.x; q < n; q += blockDim.x) {
-        const int r = q / nI, c = r / nJ;
-        cs[q] = cb[rb_off(C, Ilo + (q - r * nI), Jlo + (r - c * nJ), Klo + c)];
-    }
-    __syncthreads();
     const TileThread th = tile_thread(tl);
     const int j = B.lo[1] + th.y;
+    T* __restrict__ fb = uf + B.base;
+    // the fine values of a group of planes (clamped to the box: loads stay
+    // in it; a clamped cell may be colour 0, and its value is never used)
+    // The colour-0 cell of a row and plane that lies on a Dirichlet face
+    // (few lanes, but in most waves) also needs its value: loaded with the
+    // group, so no wave waits on a load inside the plane loop.
+    auto dirichlet0 = [&](int i0, int k) {
+        return i0 <= B.hi[0] && ((i0 == B.lo[0] && B.nb[0] < 0) || (i0 == B.hi[0] && B.nb[1] < 0) ||
+                                 (j == B.lo[1] && B.nb[2] < 0) || (j == B.hi[1] && B.nb[3] < 0) ||
+                                 (k == B.lo[2] && B.nb[4] < 0) || (k == B.hi[2] && B.nb[5] < 0));
+    };
+    T fv[kProlongGroup], f0[kProlongGroup];
+    int off[kProlongGroup];
+    auto load_group = [&](int z0) {
+#pragma unroll
+        for (int q = 0; q < kProlongGroup; ++q) {
+            const int kk = B.lo[2] + th.z0 + (z0 + q) * th.dz;
+            const int k = min(kk, B.hi[2]);
+            const int i = min(colour_i(B, th.x, j, k, 1), B.hi[0]);
+            off[q] = rb_off(B, i, j, k);
+            fv[q] = fb[off[q]];
+            const int i0 = colour_i(B, th.x, j, kk, 0);
+            f0[q] = (kk <= B.hi[2] && dirichlet0(i0, kk)) ? fb[rb_off(B, i0, j, kk)] : T(0);
+        }
+    };
+    // the first group is loaded before the stage barrier, so its latency
+    // overlaps that of the coarse stage
+    if (j <= B.hi[1]) load_group(0);
+    {
+        // stage index q = x + nI (y + nJ z), advanced by the block size
+        // without divisions (the steps are uniform)
+        const int bs = blockDim.x, qx = bs / nI, sx = bs - qx * nI, sz = qx / nJ, sy = qx - sz * nJ;
+        const int t = threadIdx.x, ty = t / nI;
+        int x = t - ty * nI, z = ty / nJ, y = ty - z * nJ;
+        for (int q = t; q < n; q += bs) {
+            cs[q] = cb[rb_off(C, Ilo + x, Jlo + y, Klo + z)];
+            // q + bs: x, y, z stay in [0,nI) x [0,nJ) x [0,..) with one carry each
+            x += sx;
+            y += sy;
+            z += sz;
+            if (x >= nI) { x -= nI; ++y; }
+            if (y >= nJ) { y -= nJ; ++z; }
+        }
+    }
+    __syncthreads();
     if (j > B.hi[1]) return;
     const int J = j >> 1, sj = (j & 1) ? 1 : -1;
-    T* __restrict__ fb = uf + B.base;
-    auto at = [&](int I, int Jq, int K) { return cs[(I - Ilo) + nI * ((Jq - Jlo) + nJ * (K - Klo))]; };
+    // LDS offsets: a cell's parent at (I - Ilo) + row + nIJ (K - Klo) with
+    // this thread's coarse row (J - Jlo) nI; the other 7 values at fixed
+    // offsets from it (24-bit products: the stage is at most 2048 values)
+    const int nIJ = nI * nJ, row = __mul24(J - Jlo, nI), oy = sj * nI;
     auto interp = [&](int i, int k) -> T {
-        const int I = i >> 1, si = (i & 1) ? 1 : -1, K = k >> 1, sk = (k & 1) ? 1 : -1;
-        if constexpr (ORDER == 1) return at(I, J, K);
-        const T c000 = at(I, J, K), c100 = at(I + si, J, K), c010 = at(I, J + sj, K), c001 = at(I, J, K + sk);
-        const T c110 = at(I + si, J + sj, K), c101 = at(I + si, J, K + sk), c011 = at(I, J + sj, K + sk);
-        const T c111 = at(I + si, J + sj, K + sk);
+        const int I = i >> 1, si = (i & 1) ? 1 : -1, K = k >> 1;
+        const int b = (I - Ilo) + row + __mul24(K - Klo, nIJ);
+        if constexpr (ORDER == 1) return cs[b];
+        const int oz = (k & 1) ? nIJ : -nIJ;
+        const T c000 = cs[b], c100 = cs[b + si], c010 = cs[b + oy], c001 = cs[b + oz];
+        const T c110 = cs[b + si + oy], c101 = cs[b + si + oz], c011 = cs[b + oy + oz];
+        const T c111 = cs[b + si + oy + oz];
         return (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
                T(0.015625);
     };
     const int zc = tl.zc;
     for (int z0 = 0; z0 < zc; z0 += kProlongGroup) {
-        T fv[kProlongGroup];
-        int off[kProlongGroup];
-#pragma unroll
-        for (int q = 0; q < kProlongGroup; ++q) {
-            const int k = min(B.lo[2] + th.z0 + (z0 + q) * th.dz, B.hi[2]);  // clamped: loads stay in the box
-            const int i = min(colour_i(B, th.x, j, k, 1), B.hi[0]);
-            off[q] = rb_off(B, i, j, k);  // the clamped cell may be colour 0: its value is never used
-            fv[q] = fb[off[q]];
-        }
+        if (z0 > 0) load_group(z0);
 #pragma unroll 1
         for (int q = 0; q < kProlongGroup; ++q) {
             const int k = B.lo[2] + th.z0 + (z0 + q) * th.dz;
@@ -1005,14 +1056,11 @@ __global__ void __launch_bounds__(kBlock) k_prolong_c1s(Grid g, const RBox* __re
             // the colour-0 cell of this row and plane, if it lies on a
             // Dirichlet face: its mirrored ghost gets -(u + P e)
             const int i0 = colour_i(B, th.x, j, k, 0);
-            const bool dir = i0 <= B.hi[0] &&
-                             ((i0 == B.lo[0] && B.nb[0] < 0) || (i0 == B.hi[0] && B.nb[1] < 0) ||
-                              (j == B.lo[1] && B.nb[2] < 0) || (j == B.hi[1] && B.nb[3] < 0) ||
-                              (k == B.lo[2] && B.nb[4] < 0) || (k == B.hi[2] && B.nb[5] < 0));
-            if (dir) push_dirichlet(uf, B, i0, j, k, fb[rb_off(B, i0, j, k)] + interp(i0, k));
+            if (dirichlet0(i0, k)) push_dirichlet(uf, B, i0, j, k, f0[0] + interp(i0, k));
 #pragma unroll
             for (int m = 0; m + 1 < kProlongGroup; ++m) {
                 fv[m] = fv[m + 1];
+                f0[m] = f0[m + 1];
                 off[m] = off[m + 1];
             }
         }
