@@ -127,6 +127,13 @@ struct Hier {
     int cc64_lds = 0, cc32_lds = 0;    // dynamic LDS of the coarse-cycle launch
     DevBuf<double> partials;  // 3 per tile of the largest tiled launch, + 3
     DevBuf<double> fnorm;     // 3
+    // the solve's stop test on the device (the batch engine's, one slot):
+    // slot state, flags {active, slot index 0, active count}, the history
+    // (kHist of |r|/|f|, then kHist of |r|_2) and the norms of f
+    DevBuf<BatchSlot> st;
+    DevBuf<int> flags;
+    DevBuf<double> hist;
+    DevBuf<double> fn3;
     DevBuf<int> iters;
     size_t bytes = 0;
     XGrid xgrid(size_t l) const {
@@ -280,6 +287,11 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
     }
     H->partials.alloc(3 * max_tiles + 8);
     H->fnorm.alloc(4);
+    H->st.alloc(1);
+    H->flags.alloc(4);
+    HIPCHK(hipMemset(H->flags.p, 0, 4 * sizeof(int)));
+    H->hist.alloc(2 * kHist);
+    H->fn3.alloc(4);
     H->iters.alloc(1);
     // fused coarse cycle: from the first level l >= 1 below which every level
     // is one box of at most kMaxBottomCells cells
@@ -384,6 +396,14 @@ struct Run {
     double bottom_rtol;
     Profiler* prof = nullptr;
     bool lds_coarse = true;  // the fused coarse cycle may keep its levels in LDS
+    // the solve's stop flag (active[0]); the V-cycle's kernels do nothing
+    // once the device-side stop test has cleared it
+    const int* active = nullptr;
+    Grid grid(const Grid& g) const {
+        Grid r = g;
+        r.active = active;
+        return r;
+    }
     // event brackets around level-0 launches of the profiled stage
     void pre(size_t l, int stage) { if (prof && prof->stage == stage && l == 0) prof->mark(s); }
     void post(size_t l, int stage) { if (prof && prof->stage == stage && l == 0) prof->mark(s); }
@@ -394,7 +414,7 @@ enum { kStageGS = 0, kStageResid = 1, kStageRestrict = 2, kStageProlong = 3, kSt
 template <class T>
 void fill(Run& R, size_t l, T* data, const GhostList& g) {
     R.pre(l, kStageFill);
-    HIPCHK(launch_fill_rb(R.s, data, sizeof(T) == 4, g.list.p, g.n));
+    HIPCHK(launch_fill_rb(R.s, data, sizeof(T) == 4, g.list.p, g.n, R.active));
     R.post(l, kStageFill);
 }
 
@@ -416,7 +436,7 @@ void smooth(Run& R, size_t l, int nsweeps) {
         for (int c = 0; c < 2; ++c) {
             if (!L.push) fill<T>(R, l, u, L.face[c ^ 1]);
             R.pre(l, kStageGS);
-            HIPCHK(launch_gs<T>(R.s, L.walk(), u, f, lvl_beta<T>(H, l), lvl_fat<T>(H, l), c));
+            HIPCHK(launch_gs<T>(R.s, R.grid(L.walk()), u, f, lvl_beta<T>(H, l), lvl_fat<T>(H, l), c));
             R.post(l, kStageGS);
         }
 }
@@ -466,8 +486,8 @@ void coarse_cycle(Run& R) {
     }
     // the correction on the top level starts from zero (in LDS, the kernel
     // zeroes its copy and writes the whole level back)
-    if (!host.lds) HIPCHK(launch_zero<T>(R.s, lvl_u<T>(H, H->coarse_start), H->L[H->coarse_start]->nelem));
-    HIPCHK(launch_coarse_cycle<T>(R.s, buf.p, 1, nullptr, H->var, cc_lds<T>(H)));
+    if (!host.lds) HIPCHK(launch_zero<T>(R.s, lvl_u<T>(H, H->coarse_start), H->L[H->coarse_start]->nelem, R.active));
+    HIPCHK(launch_coarse_cycle<T>(R.s, buf.p, 1, R.active, H->var, cc_lds<T>(H)));
 }
 
 template <class T>
@@ -490,16 +510,18 @@ void vcycle(Run& R, size_t l) {
     smooth<T>(R, l, R.nu1);
     if (!L.push) fill_faces<T>(R, l, u);
     R.pre(l, kStageRestrict);
-    HIPCHK(launch_resid_restrict<T>(R.s, H->xwalk(l), u, lvl_f<T>(H, l), lvl_beta<T>(H, l), lvl_fat<T>(H, l),
+    XGrid x = H->xwalk(l);
+    x.active = R.active;
+    HIPCHK(launch_resid_restrict<T>(R.s, x, u, lvl_f<T>(H, l), lvl_beta<T>(H, l), lvl_fat<T>(H, l),
                                     lvl_f<T>(H, l + 1)));
     R.post(l, kStageRestrict);
     // the fused coarse cycle zeroes its top level itself
-    if ((int)l + 1 != H->coarse_start) HIPCHK(launch_zero<T>(R.s, lvl_u<T>(H, l + 1), C.nelem));
+    if ((int)l + 1 != H->coarse_start) HIPCHK(launch_zero<T>(R.s, lvl_u<T>(H, l + 1), C.nelem, R.active));
     vcycle<T>(R, l + 1);
     fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full);
     R.pre(l, kStageProlong);
     // with post-smoothing, its first (colour-0) sweep overwrites colour 0
-    HIPCHK(launch_prolong<T>(R.s, L.walk(), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong, R.nu2 > 0,
+    HIPCHK(launch_prolong<T>(R.s, R.grid(L.walk()), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong, R.nu2 > 0,
                              L.stage_values));
     R.post(l, kStageProlong);
     smooth<T>(R, l, R.nu2);
@@ -521,6 +543,14 @@ void setup_faces(Run& R, T* beta0) {
         }
     }
 }
+
+// Host copy of a solve's stop-test state: the two histories, the slot, the flag.
+struct SolveState {
+    double hist[kHist];
+    double hist_l2[kHist];
+    BatchSlot st;
+    int active;
+};
 
 double norm_readback(Run& R, double* h_norm, const double* dev) {
     HIPCHK(hipMemcpyAsync(h_norm, dev, 3 * sizeof(double), hipMemcpyDeviceToHost, R.s));
@@ -568,7 +598,9 @@ bxmg_status bxmg_ctx_create(int device, void* hip_stream, bxmg_ctx* out) {
     auto* c = new bxmg_ctx_s();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
-    if (hipHostMalloc((void**)&c->h_norm, 8 * sizeof(double)) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->h_norm, 8 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc(&c->h_solve, sizeof(SolveState)) != hipSuccess) {
+        if (c->h_norm) (void)hipHostFree(c->h_norm);
         delete c;
         return fail(BXMG_ENOMEM, "ctx_create: pinned host allocation failed");
     }
@@ -582,6 +614,7 @@ void bxmg_ctx_destroy(bxmg_ctx ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     ctx->cache.clear();
     if (ctx->h_norm) (void)hipHostFree(ctx->h_norm);
+    if (ctx->h_solve) (void)hipHostFree(ctx->h_solve);
     delete ctx;
 }
 
@@ -946,56 +979,107 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         // level-0 values refreshes the face ghosts it mirrors (push levels)
         fill_faces<double>(R, 0, u);
         const FaceArrays<double>* nf = nullptr;
+        // The stop test runs on the device (the batch engine's, for one
+        // slot): k_batch_admit takes the norm of f, and k_batch_check after
+        // every residual records the history and clears the active flag once
+        // the solve stops (converged, max_cycles, fixed_cycles, non-finite).
+        // Every kernel of a V-cycle honours the flag, so the host enqueues
+        // cycles ahead of the device and reads the state back only now and
+        // then, instead of once per cycle.
+        SolveState* hs = (SolveState*)ctx->h_solve;
+        BatchSlot S0{};
+        S0.rel_tol = P.rel_tol;
+        S0.abs_tol = P.abs_tol;
+        S0.max_cycles = P.max_cycles;
+        S0.fixed_cycles = P.fixed_cycles;
+        hs->st = S0;  // pinned: the source of the copy
+        HIPCHK(hipMemcpyAsync(H->st.p, &hs->st, sizeof S0, hipMemcpyHostToDevice, R.s));
         HIPCHK(launch_field_norm(R.s, L0.view_grid(), f, H->partials.p));
-        HIPCHK(launch_norm_final(R.s, H->partials.p, L0.view_grid().ntiles, H->fnorm.p));
-        norm_readback(R, ctx->h_norm, H->fnorm.p);
-        const double fnorm = ctx->h_norm[0];
-        info->f_inf = fnorm;
-        if (ctx->h_norm[2] > 0) {
-            info->f_inf = NAN;
-            return set_status(info, fail(BXMG_ENONFINITE, "solve: non-finite right-hand side"));
+        HIPCHK(launch_norm_final(R.s, H->partials.p, L0.view_grid().ntiles, H->fn3.p));
+        HIPCHK(launch_batch_admit(R.s, H->fn3.p, H->st.p, H->flags.p, 0));
+        R.active = H->flags.p;
+        auto check = [&]() {  // residual of the current iterate, then the stop test
+            if (!L0.push) fill_faces<double>(R, 0, u);
+            R.pre(0, kStageResid);
+            if (P.precision == 0) {
+                HIPCHK(launch_resid<double, double>(R.s, R.grid(L0.walk()), u, f, beta ? H->beta64.p : nullptr, nf,
+                                                    (double*)nullptr, H->partials.p));
+            } else {
+                HIPCHK(launch_resid<double, float>(R.s, R.grid(L0.walk()), u, f, beta ? H->beta64.p : nullptr, nf,
+                                                   H->f32[0]->p, H->partials.p));
+            }
+            R.post(0, kStageResid);
+            HIPCHK(launch_norm_final(R.s, H->partials.p, L0.ntcol, H->fnorm.p));
+            HIPCHK(launch_batch_check(R.s, H->flags.p + 1, 1, H->fnorm.p, H->st.p, H->flags.p, H->hist.p,
+                                      H->hist.p + kHist, H->flags.p + 2));
+        };
+        auto cycle = [&]() {
+            if (P.precision == 0) {
+                vcycle<double>(R, 0);
+            } else {
+                HIPCHK(launch_zero<float>(R.s, H->u32[0]->p, L0.nelem, R.active));
+                vcycle<float>(R, 0);
+                HIPCHK(launch_add_f32(R.s, R.grid(L0.walk()), u, H->u32[0]->p));
+            }
+        };
+        auto look = [&]() {
+            HIPCHK(hipMemcpyAsync(hs->hist, H->hist.p, 2 * kHist * sizeof(double), hipMemcpyDeviceToHost, R.s));
+            HIPCHK(hipMemcpyAsync(&hs->st, H->st.p, sizeof(BatchSlot), hipMemcpyDeviceToHost, R.s));
+            HIPCHK(hipMemcpyAsync(&hs->active, H->flags.p, sizeof(int), hipMemcpyDeviceToHost, R.s));
+            HIPCHK(hipStreamSynchronize(R.s));
+        };
+        // queued = V-cycles enqueued; residual number c follows cycle c
+        const int limit = P.fixed_cycles > 0 ? P.fixed_cycles : P.max_cycles;
+        check();
+        int queued = 0;
+        if (limit > 0) {
+            cycle();
+            check();
+            queued = 1;
         }
-        int status = BXMG_OK;
-        int cyc = 0;
-        if (fnorm > 0.0) {
-            for (;; ++cyc) {
-                if (!L0.push) fill_faces<double>(R, 0, u);
-                R.pre(0, kStageResid);
-                if (P.precision == 0) {
-                    HIPCHK(launch_resid<double, double>(R.s, L0.walk(), u, f, beta ? H->beta64.p : nullptr, nf,
-                                                        (double*)nullptr, H->partials.p));
-                } else {
-                    HIPCHK(launch_resid<double, float>(R.s, L0.walk(), u, f, beta ? H->beta64.p : nullptr, nf,
-                                                       H->f32[0]->p, H->partials.p));
+        for (;;) {
+            look();
+            if (!hs->active) break;
+            // the device wants cycle queued + 1: enqueue as many as the
+            // residual history predicts are still needed, less one, so a
+            // solve rarely runs on into cycles that do nothing
+            int ahead = limit - queued;
+            if (P.fixed_cycles <= 0) {
+                int pred = 1;
+                const int c = queued;
+                if (c >= 1 && c < kHist && hs->st.fnorm > 0.0) {
+                    const double r1 = hs->hist[c], rho = r1 / hs->hist[c - 1];
+                    const double t = std::max(P.rel_tol, P.abs_tol / hs->st.fnorm);
+                    if (rho > 0.0 && rho < 1.0 && r1 > t && t > 0.0)
+                        pred = (int)std::min(32.0, std::max(1.0, std::ceil(std::log(t / r1) / std::log(rho)) - 1.0));
                 }
-                R.post(0, kStageResid);
-                HIPCHK(launch_norm_final(R.s, H->partials.p, L0.ntcol, H->fnorm.p));
-                norm_readback(R, ctx->h_norm, H->fnorm.p);
-                const double rinf = ctx->h_norm[2] > 0 ? NAN : ctx->h_norm[0];
-                if (cyc < 256) {
-                    info->hist[cyc] = rinf / fnorm;
-                    info->hist_l2[cyc] = std::sqrt(ctx->h_norm[1]);
-                    info->nhist = cyc + 1;
-                }
-                info->rel_resid_inf = rinf / fnorm;
-                info->resid_l2 = std::sqrt(ctx->h_norm[1]);
-                if (!std::isfinite(rinf)) { status = BXMG_ENONFINITE; break; }
-                if (P.fixed_cycles > 0) {
-                    if (cyc == P.fixed_cycles) break;
-                } else {
-                    if (rinf <= P.rel_tol * fnorm || rinf <= P.abs_tol) break;
-                    if (cyc == P.max_cycles) { status = BXMG_ENOCONV; break; }
-                }
-                if (P.precision == 0) {
-                    vcycle<double>(R, 0);
-                } else {
-                    HIPCHK(launch_zero<float>(R.s, H->u32[0]->p, L0.nelem));
-                    vcycle<float>(R, 0);
-                    HIPCHK(launch_add_f32(R.s, L0.walk(), u, H->u32[0]->p));
-                }
+                ahead = std::min(ahead, pred);
+            }
+            for (int a = 0; a < std::max(ahead, 1); ++a) {
+                cycle();
+                check();
+                ++queued;
             }
         }
-        info->cycles = cyc;
+        const BatchSlot& Sf = hs->st;
+        info->f_inf = Sf.fnorm;
+        const int nh = std::min(Sf.nhist, kHist);
+        for (int c = 0; c < nh; ++c) {
+            info->hist[c] = hs->hist[c];
+            info->hist_l2[c] = hs->hist_l2[c];
+        }
+        info->nhist = nh;
+        if (nh > 0) {
+            info->rel_resid_inf = hs->hist[nh - 1];
+            info->resid_l2 = hs->hist_l2[nh - 1];
+        }
+        info->cycles = Sf.cycles;
+        const int status = Sf.status;
+        if (status == BXMG_ENONFINITE && nh == 0) {  // rejected at admission: phi is left as it was
+            info->f_inf = NAN;
+            ctx->prof.harvest();
+            return set_status(info, fail(BXMG_ENONFINITE, "solve: non-finite right-hand side"));
+        }
         if (ba->per[0] && ba->per[1] && ba->per[2])
             HIPCHK(launch_mean_sub(R.s, L0.mean_grid(), u, H->partials.p));
         HIPCHK(launch_rb_to_fab(R.s, L0.view_grid(), u, (double*)phi->data, phi->d_fboxes.p));

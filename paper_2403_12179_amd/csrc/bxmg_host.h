@@ -587,6 +587,7 @@ struct bxmg_ctx_s {
     std::map<std::string, std::unique_ptr<Hier>> cache;  // by geometry and settings
     std::deque<std::string> lru;                          // cache keys, least recently used first
     double* h_norm = nullptr;  // pinned
+    void* h_solve = nullptr;   // pinned: a solve's stop-test state read back (history, slot, flag)
     std::mutex mu;
 };
 

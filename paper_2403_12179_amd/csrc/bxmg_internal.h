@@ -180,7 +180,9 @@ constexpr int kHist = 256;
 
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `s` and return hipSuccess or the launch error.
-hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* list, long long n);
+// active != nullptr: nothing happens while active[0] == 0 (a stopped solve)
+hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* list, long long n,
+                          const int* active = nullptr);
 hipError_t launch_fill_fab(hipStream_t s, void* data, bool f32, const FBox* boxes, const Tag* tags, int ntags,
                            long long ncells, int comp0, int ncomp);
 
@@ -220,7 +222,7 @@ hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, c
                           int order, bool only_c1 = false, int stage_values = 0);
 
 template <class T>
-hipError_t launch_zero(hipStream_t s, T* p, long long n);
+hipError_t launch_zero(hipStream_t s, T* p, long long n, const int* active = nullptr);
 hipError_t launch_cast_f32(hipStream_t s, const double* src, float* dst, long long n);
 
 // layout conversions: F-order caller MultiFab (FP64, comp 0) <-> RB level

@@ -346,9 +346,10 @@ __device__ __forceinline__ void acc_norm(double rv, double& mx, double& s2, doub
 // -------------------------------------------------------------- ghost fill
 // Level ghost cells: one precomputed (dst, src) pair per cell.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_fill_rb(T* __restrict__ data, const GhostCopy* __restrict__ list, long long n) {
+__global__ void __launch_bounds__(kBlock) k_fill_rb(T* __restrict__ data, const GhostCopy* __restrict__ list, long long n,
+                                                   const int* __restrict__ active) {
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
+    if (g >= n || (active && !active[0])) return;
     const GhostCopy p = list[g];
     const T v = data[p.src & 0x7fffffffu];
     data[p.dst] = (p.src >> 31) ? -v : v;
@@ -1069,7 +1070,8 @@ __global__ void __launch_bounds__(kBlock) k_prolong_c1s(Grid g, const RBox* __re
 
 // -------------------------------------------------------------- utilities
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_zero(T* __restrict__ p, long long n) {
+__global__ void __launch_bounds__(kBlock) k_zero(T* __restrict__ p, long long n, const int* __restrict__ active) {
+    if (active && !active[0]) return;
     const long long stride = (long long)gridDim.x * blockDim.x;
     for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = T(0);
 }
@@ -1776,10 +1778,10 @@ static bool allow_lds(const void* fn) {
     return true;
 }
 
-hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* list, long long n) {
+hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* list, long long n, const int* active) {
     if (n <= 0) return hipSuccess;
-    if (f32) hipLaunchKernelGGL(k_fill_rb<float>, dim3(nblk(n)), dim3(kBlock), 0, s, (float*)data, list, n);
-    else hipLaunchKernelGGL(k_fill_rb<double>, dim3(nblk(n)), dim3(kBlock), 0, s, (double*)data, list, n);
+    if (f32) hipLaunchKernelGGL(k_fill_rb<float>, dim3(nblk(n)), dim3(kBlock), 0, s, (float*)data, list, n, active);
+    else hipLaunchKernelGGL(k_fill_rb<double>, dim3(nblk(n)), dim3(kBlock), 0, s, (double*)data, list, n, active);
     return hipGetLastError();
 }
 
@@ -1900,14 +1902,14 @@ template hipError_t launch_prolong<float>(hipStream_t, const Grid&, const RBox*,
                                           bool, int);
 
 template <class T>
-hipError_t launch_zero(hipStream_t s, T* p, long long n) {
+hipError_t launch_zero(hipStream_t s, T* p, long long n, const int* active) {
     if (n <= 0) return hipSuccess;
     const long long nb = std::min<long long>(nblk(n), 8192);
-    hipLaunchKernelGGL(k_zero<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, p, n);
+    hipLaunchKernelGGL(k_zero<T>, dim3((unsigned)nb), dim3(kBlock), 0, s, p, n, active);
     return hipGetLastError();
 }
-template hipError_t launch_zero<double>(hipStream_t, double*, long long);
-template hipError_t launch_zero<float>(hipStream_t, float*, long long);
+template hipError_t launch_zero<double>(hipStream_t, double*, long long, const int*);
+template hipError_t launch_zero<float>(hipStream_t, float*, long long, const int*);
 
 hipError_t launch_cast_f32(hipStream_t s, const double* src, float* dst, long long n) {
     if (n <= 0) return hipSuccess;

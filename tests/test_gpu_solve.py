@@ -172,9 +172,10 @@ def test_status_codes(bx):
     bad = f.copy()
     bad[1, 2, 3] = np.nan
     rhs.from_global(bad)
-    phi.set_val(0.0)
+    phi.set_val(0.5)
     res = bx.mlmg_solve(phi, rhs)
-    assert res.status == -5
+    assert res.status == -5 and res.cycles == 0 and np.isnan(res.f_inf)
+    assert np.all(phi.to_global() == 0.5)  # a rejected right-hand side leaves phi as it was
     rhs.set_val(0.0)
     phi.set_val(0.0)
     res = bx.mlmg_solve(phi, rhs)
