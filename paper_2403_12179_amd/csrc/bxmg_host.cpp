@@ -512,17 +512,23 @@ void vcycle(Run& R, size_t l) {
     R.pre(l, kStageRestrict);
     XGrid x = H->xwalk(l);
     x.active = R.active;
+    // the coarse correction starts from zero: zeroed by the same launch (the
+    // fused coarse cycle zeroes its top level itself)
+    const bool zero_c = (int)l + 1 != H->coarse_start;
     HIPCHK(launch_resid_restrict<T>(R.s, x, u, lvl_f<T>(H, l), lvl_beta<T>(H, l), lvl_fat<T>(H, l),
-                                    lvl_f<T>(H, l + 1)));
+                                    lvl_f<T>(H, l + 1), zero_c ? lvl_u<T>(H, l + 1) : nullptr));
     R.post(l, kStageRestrict);
-    // the fused coarse cycle zeroes its top level itself
-    if ((int)l + 1 != H->coarse_start) HIPCHK(launch_zero<T>(R.s, lvl_u<T>(H, l + 1), C.nelem, R.active));
     vcycle<T>(R, l + 1);
-    fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full);
+    // a small one-box coarse level needs no ghost refresh where the staged
+    // prolongation reads the cells its ghosts mirror (on large levels the
+    // refresh launch costs less than the mirroring in every tile)
+    const bool self = C.boxes.size() == 1 && C.dom.cells() <= kSelfGhostCells &&
+                      prolong_staged(L.push, R.nu2 > 0, L.stage_values);
+    if (!self) fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full);
     R.pre(l, kStageProlong);
     // with post-smoothing, its first (colour-0) sweep overwrites colour 0
     HIPCHK(launch_prolong<T>(R.s, R.grid(L.walk()), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong, R.nu2 > 0,
-                             L.stage_values));
+                             L.stage_values, self));
     R.post(l, kStageProlong);
     smooth<T>(R, l, R.nu2);
 }

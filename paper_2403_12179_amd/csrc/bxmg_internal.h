@@ -202,9 +202,11 @@ hipError_t launch_resid(hipStream_t s, const Grid& g, const T* u, const T* f, co
 hipError_t launch_norm_final(hipStream_t s, const double* partials, int n, double* out3);
 hipError_t launch_field_norm(hipStream_t s, const Grid& g, const double* x, double* partials);
 
+// uz != nullptr: also zero the coarse u there (its cells and the face ghosts
+// that mirror them), in place of zeroing the whole coarse level
 template <class T>
 hipError_t launch_resid_restrict(hipStream_t s, const XGrid& x, const T* u, const T* f, const T* beta,
-                                 const FaceArrays<T>* fat, T* fc);
+                                 const FaceArrays<T>* fat, T* fc, T* uz = nullptr);
 template <class T>
 hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* fc);
 // fine += P coarse: one thread per pair of fine cells (2I, 2I+1) over the
@@ -216,10 +218,18 @@ hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* 
 // overwrites colour 0 reading it only through those ghosts).
 // stage_values: the largest coarse region (values) a tile of the fine level
 // reads (prolong_stage_values); where it fits the LDS stage, the colour-1
-// kernel stages it (0: never).
+// kernel stages it (0: never).  coarse_self: the coarse level is one box, so
+// each of its ghosts mirrors one of its own cells (odd reflection across a
+// Dirichlet face, the periodic image otherwise); the staged kernel then reads
+// those cells instead of the ghosts, which need no refresh before it.
+constexpr int kProlongStage = 2048;  // values of the LDS stage
+constexpr long long kSelfGhostCells = 1LL << 18;  // coarse levels up to 64^3 resolve their ghosts in the stage
+inline bool prolong_staged(bool fine_push, bool only_c1, int stage_values) {
+    return fine_push && only_c1 && stage_values > 0 && stage_values <= kProlongStage;
+}
 template <class T>
 hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
-                          int order, bool only_c1 = false, int stage_values = 0);
+                          int order, bool only_c1 = false, int stage_values = 0, bool coarse_self = false);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n, const int* active = nullptr);

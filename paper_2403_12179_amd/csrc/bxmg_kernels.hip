@@ -317,6 +317,32 @@ __device__ __forceinline__ void push_ghosts(T* __restrict__ u, const RBox* __res
         }
 }
 
+// The face ghost cells that mirror cell (i,j,k) of box B (the targets of
+// push_ghosts), set to +0: with the cell zeroed, what a ghost refresh would
+// leave there, except that a Dirichlet ghost gets +0 rather than -0, as a
+// zeroed level holds everywhere.
+template <class T>
+__device__ __forceinline__ void zero_ghosts(T* __restrict__ u, const RBox* __restrict__ boxes, const RBox& B, int i,
+                                            int j, int k) {
+    const int c[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            if (c[d] != (side ? B.hi[d] : B.lo[d])) continue;
+            const int q = 2 * d + side;
+            const int nb = B.nb[q];
+            int t[3] = {i, j, k};
+            if (nb >= 0) {
+                t[d] += B.shift[q];
+                u[rb_idx(boxes[nb], t[0], t[1], t[2])] = T(0);
+            } else {
+                t[d] += side ? 1 : -1;
+                u[rb_idx(B, t[0], t[1], t[2])] = T(0);
+            }
+        }
+}
+
 // Fixed-tree block reduction of (max, sum, sum): wave64 butterflies, then
 // the 4 wave results in order.  The result is valid in thread 0.
 __device__ __forceinline__ void block_reduce3(double& mx, double& s2, double& bad, double* sh) {
@@ -578,10 +604,14 @@ __device__ __forceinline__ T resid_at(const T* __restrict__ u, const T* __restri
     return f[idx] - (su - sb * uc) * ih2;
 }
 
+// uz != nullptr: also zero the coarse level's u (the coarse correction's
+// first guess) at each coarse cell written, with the face ghosts mirroring
+// it -- every value of it the first coarse sweep reads (levels that push).
 template <class T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_resid_restrict(XGrid x, const T* __restrict__ u, const T* __restrict__ f,
                                                           const T* __restrict__ beta,
-                                                          const FaceArrays<T>* __restrict__ fat, T* __restrict__ fc) {
+                                                          const FaceArrays<T>* __restrict__ fat, T* __restrict__ fc,
+                                                          T* __restrict__ uz) {
     const Tile tl = x.tiles[tile_index(x.rev)];
     const RBox B = x.fboxes[tl.box];
     if (x.active && !x.active[B.pid]) return;
@@ -658,6 +688,10 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(XGrid x, const T* __r
             const int oc = rb_off(C, I, J, K);
             if (x.res) Cw.st(oc, s * T(0.125));
             else fc[C.base + oc] = s * T(0.125);
+            if (uz) {
+                uz[C.base + oc] = T(0);
+                zero_ghosts(uz, x.cboxes, C, I, J, K);
+            }
         }
         return;
     }
@@ -675,6 +709,10 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(XGrid x, const T* __r
         const T r111 = resid_at<T, MODE>(u, f, beta, fa, B, i + 1, j + 1, k + 1, ih2);
         const T s = ((r000 + r100) + (r010 + r110)) + ((r001 + r101) + (r011 + r111));
         fc[rb_idx(C, I, J, K)] = s * T(0.125);
+        if (uz) {
+            uz[rb_idx(C, I, J, K)] = T(0);
+            zero_ghosts(uz, x.cboxes, C, I, J, K);
+        }
     }
 }
 
@@ -955,14 +993,15 @@ __global__ void __launch_bounds__(kBlock) k_prolong_c1(Grid g, const RBox* __res
 // loads every coarse value its tile reads (parents and the layer around
 // them) once, then each cell takes its 8 values from LDS instead of from the
 // vector memory path.  Same cells, values and arithmetic as k_prolong_c1.
-// The host launches it where the region fits kStageCoarse values.
-constexpr int kStageCoarse = 2048;
+// The host launches it where the region fits kProlongStage values.  SELF:
+// the coarse level is one box, and the stage reads each ghost's mirror cell
+// (see launch_prolong) instead of the ghost.
 
-template <class T, int ORDER>
+template <class T, int ORDER, bool SELF>
 __global__ void __launch_bounds__(kBlock) k_prolong_c1s(Grid g, const RBox* __restrict__ cboxes,
                                                        const int* __restrict__ cbox, const T* __restrict__ ec,
                                                        T* __restrict__ uf) {
-    __shared__ T cs[kStageCoarse];
+    __shared__ T cs[kProlongStage];
     const Tile tl = g.tiles[tile_index(g.rev)];
     const RBox B = g.boxes[tl.box];
     if (g.active && !g.active[B.pid]) return;  // the whole workgroup
@@ -1013,8 +1052,30 @@ __global__ void __launch_bounds__(kBlock) k_prolong_c1s(Grid g, const RBox* __re
         const int bs = blockDim.x, qx = bs / nI, sx = bs - qx * nI, sz = qx / nJ, sy = qx - sz * nJ;
         const int t = threadIdx.x, ty = t / nI;
         int x = t - ty * nI, z = ty / nJ, y = ty - z * nJ;
+        // a ghost of a one-box level: the cell it mirrors, negated once per
+        // Dirichlet face crossed (the stage reaches one layer beyond the box)
+        auto mirror = [&](int v, int d, bool& neg) {
+            if (v < C.lo[d]) {
+                if (C.nb[2 * d] >= 0) return v + (C.hi[d] - C.lo[d] + 1);
+                neg = !neg;
+                return 2 * C.lo[d] - 1 - v;
+            }
+            if (v > C.hi[d]) {
+                if (C.nb[2 * d + 1] >= 0) return v - (C.hi[d] - C.lo[d] + 1);
+                neg = !neg;
+                return 2 * C.hi[d] + 1 - v;
+            }
+            return v;
+        };
         for (int q = t; q < n; q += bs) {
-            cs[q] = cb[rb_off(C, Ilo + x, Jlo + y, Klo + z)];
+            if constexpr (SELF) {
+                bool neg = false;
+                const int I = mirror(Ilo + x, 0, neg), Jq = mirror(Jlo + y, 1, neg), K = mirror(Klo + z, 2, neg);
+                const T v = cb[rb_off(C, I, Jq, K)];
+                cs[q] = neg ? -v : v;
+            } else {
+                cs[q] = cb[rb_off(C, Ilo + x, Jlo + y, Klo + z)];
+            }
             // q + bs: x, y, z stay in [0,nI) x [0,nJ) x [0,..) with one carry each
             x += sx;
             y += sy;
@@ -1849,18 +1910,18 @@ hipError_t launch_field_norm(hipStream_t s, const Grid& g, const double* x, doub
 
 template <class T>
 hipError_t launch_resid_restrict(hipStream_t s, const XGrid& x, const T* u, const T* f, const T* beta,
-                                 const FaceArrays<T>* fat, T* fc) {
+                                 const FaceArrays<T>* fat, T* fc, T* uz) {
     if (x.ntiles <= 0) return hipSuccess;
     const dim3 G(x.ntiles), B(kBlock);
-    if (beta) hipLaunchKernelGGL((k_resid_restrict<T, 1>), G, B, 0, s, x, u, f, beta, fat, fc);
-    else if (fat) hipLaunchKernelGGL((k_resid_restrict<T, 2>), G, B, 0, s, x, u, f, beta, fat, fc);
-    else hipLaunchKernelGGL((k_resid_restrict<T, 0>), G, B, 0, s, x, u, f, beta, fat, fc);
+    if (beta) hipLaunchKernelGGL((k_resid_restrict<T, 1>), G, B, 0, s, x, u, f, beta, fat, fc, uz);
+    else if (fat) hipLaunchKernelGGL((k_resid_restrict<T, 2>), G, B, 0, s, x, u, f, beta, fat, fc, uz);
+    else hipLaunchKernelGGL((k_resid_restrict<T, 0>), G, B, 0, s, x, u, f, beta, fat, fc, uz);
     return hipGetLastError();
 }
 template hipError_t launch_resid_restrict<double>(hipStream_t, const XGrid&, const double*, const double*,
-                                                  const double*, const FaceArrays<double>*, double*);
+                                                  const double*, const FaceArrays<double>*, double*, double*);
 template hipError_t launch_resid_restrict<float>(hipStream_t, const XGrid&, const float*, const float*, const float*,
-                                                 const FaceArrays<float>*, float*);
+                                                 const FaceArrays<float>*, float*, float*);
 
 template <class T>
 hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* fc) {
@@ -1872,17 +1933,19 @@ template hipError_t launch_restrict_plain<double>(hipStream_t, const XGrid&, con
 
 template <class T>
 hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
-                          int order, bool only_c1, int stage_values) {
+                          int order, bool only_c1, int stage_values, bool coarse_self) {
     if (fine.ntiles <= 0) return hipSuccess;
     const dim3 G(fine.ntiles), B(kBlock);
     // levels refreshed by fill lists copy ghosts from both colours' cells:
     // they keep the two-colour kernel
     const bool c1 = only_c1 && fine.push;
-    const bool staged = stage_values > 0 && stage_values <= kStageCoarse;
+    const bool staged = prolong_staged(fine.push, only_c1, stage_values);
 #define BXMG_PROLONG(PUSH, ORDER)                                                                    \
     do {                                                                                            \
-        if (PUSH && c1 && staged)                                                                   \
-            hipLaunchKernelGGL((k_prolong_c1s<T, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf);   \
+        if (PUSH && c1 && staged && coarse_self)                                                    \
+            hipLaunchKernelGGL((k_prolong_c1s<T, ORDER, true>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
+        else if (PUSH && c1 && staged)                                                              \
+            hipLaunchKernelGGL((k_prolong_c1s<T, ORDER, false>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
         else if (PUSH && c1) hipLaunchKernelGGL((k_prolong_c1<T, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
         else hipLaunchKernelGGL((k_prolong<T, PUSH, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
     } while (0)
@@ -1897,9 +1960,9 @@ hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, c
     return hipGetLastError();
 }
 template hipError_t launch_prolong<double>(hipStream_t, const Grid&, const RBox*, const int*, const double*, double*,
-                                           int, bool, int);
+                                           int, bool, int, bool);
 template hipError_t launch_prolong<float>(hipStream_t, const Grid&, const RBox*, const int*, const float*, float*, int,
-                                          bool, int);
+                                          bool, int, bool);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n, const int* active) {
