@@ -337,6 +337,7 @@ struct bxmg_batch_s {
     DevVec<CoarseCycle<float>> cc32;
     int ncc = 0;
     int cc_lds = 0;  // dynamic LDS of the coarse-cycle launch
+    bool cc_all_lds = false;  // every member's coarse levels fit in LDS
     bool use_graph = true;
     int stable = 0;         // launches since the running set last changed
     bool inflight = false;  // cycles launched and not yet collected
@@ -564,11 +565,13 @@ void rebuild(bxmg_batch_s* b) {
         }
     // fused coarse cycles (dynamic LDS: the largest need of a member)
     b->cc_lds = 0;
+    b->cc_all_lds = true;
     if (b->prec == 0) {
         std::vector<CoarseCycle<double>> cc;
         for (int s : b->members) {
             cc.push_back(coarse_desc<double>(b, *b->slots[s], b->u64.p, b->f64.p, b->fa64.p));
             b->cc_lds = std::max(b->cc_lds, coarse_lds_layout<double>(cc.back(), b->ctx->lds_coarse));
+            b->cc_all_lds = b->cc_all_lds && cc.back().lds;
         }
         b->cc64.assign(cc);
     } else {
@@ -576,6 +579,7 @@ void rebuild(bxmg_batch_s* b) {
         for (int s : b->members) {
             cc.push_back(coarse_desc<float>(b, *b->slots[s], b->u32.p, b->f32.p, b->fa32.p));
             b->cc_lds = std::max(b->cc_lds, coarse_lds_layout<float>(cc.back(), b->ctx->lds_coarse));
+            b->cc_all_lds = b->cc_all_lds && cc.back().lds;
         }
         b->cc32.assign(cc);
     }
@@ -660,7 +664,7 @@ void b_vcycle(bxmg_batch_s* b, hipStream_t s) {
         HIPCHK(launch_resid_restrict<T>(s, level_xgrid(b, l), u, f, arena_beta<T>(b, l), level_fat<T>(b, l), f));
         HIPCHK(launch_zero_ranges<T>(s, u, B.zr.p(), B.nzr, B.zmax, b->active.p));
     }
-    HIPCHK(launch_coarse_cycle<T>(s, coarse_descs<T>(b), b->ncc, b->active.p, b->var, b->cc_lds));
+    HIPCHK(launch_coarse_cycle<T>(s, coarse_descs<T>(b), b->ncc, b->active.p, b->var, b->cc_lds, b->cc_all_lds));
     for (int l = b->lmax - 1; l >= 0; --l) {
         BLevel& B = b->lev[l];
         HIPCHK(launch_fill_sets(s, u, f32, B.fullc.p(), B.nfullc, B.mfullc, b->active.p));

@@ -484,10 +484,8 @@ void coarse_cycle(Run& R) {
         cc_lds<T>(H) = lds;
         HIPCHK(hipMemcpyAsync(buf.p, &host, sizeof host, hipMemcpyHostToDevice, R.s));
     }
-    // the correction on the top level starts from zero (in LDS, the kernel
-    // zeroes its copy and writes the whole level back)
-    if (!host.lds) HIPCHK(launch_zero<T>(R.s, lvl_u<T>(H, H->coarse_start), H->L[H->coarse_start]->nelem, R.active));
-    HIPCHK(launch_coarse_cycle<T>(R.s, buf.p, 1, R.active, H->var, cc_lds<T>(H)));
+    // (the kernel zeroes the top level's correction itself)
+    HIPCHK(launch_coarse_cycle<T>(R.s, buf.p, 1, R.active, H->var, cc_lds<T>(H), host.lds != 0));
 }
 
 template <class T>

@@ -257,10 +257,13 @@ hipError_t launch_bottom(hipStream_t s, T* u, const T* f, FaceArrays<T> fa, bool
 
 // the fused coarse V-cycle, one workgroup per descriptor cc[0..n); with
 // active != nullptr a descriptor whose problem slot is inactive is skipped;
-// lds_bytes: dynamic LDS per workgroup (the largest descriptor's need)
+// lds_bytes: dynamic LDS per workgroup (the largest descriptor's need);
+// levels_lds: every descriptor has cc.lds set -- the levels then live in
+// LDS, otherwise all of them run from device memory (same values either way).
+// The cycle zeroes its top level's u itself.
 template <class T>
 hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, int n, const int* active, bool var,
-                               int lds_bytes);
+                               int lds_bytes, bool levels_lds);
 // LDS layout of a coarse cycle (sets cc.lds, offsets, bot_off); returns the
 // bytes it needs.  Levels go to LDS when everything fits in lds_limit_bytes().
 template <class T>

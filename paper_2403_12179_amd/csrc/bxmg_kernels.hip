@@ -1598,66 +1598,166 @@ __global__ void __launch_bounds__(kBotThreads) k_bottom(T* __restrict__ u, const
 // of the coarse level, prolongation, post-smoothing), each a block-strided
 // loop closed by a barrier.  Launch latency, not bandwidth, bounds these
 // levels, so one launch replaces some 20 per level.
+// Level storage of the fused coarse cycle, by 32-bit element offsets (the
+// levels hold at most kMaxBottomCells cells): LDS through an address-space-3
+// pointer, so the compiler emits LDS instructions rather than flat ones, or
+// device memory.
+template <class T, bool LDS>
+struct LvMem;
 template <class T>
-__device__ void blk_fill(T* __restrict__ data, const GhostCopy* __restrict__ list, long long n) {
-    for (long long g = threadIdx.x; g < n; g += blockDim.x) {
+struct LvMem<T, true> {
+    __attribute__((address_space(3))) T* p;
+    __device__ __forceinline__ T ld(int e) const { return p[e]; }
+    __device__ __forceinline__ void st(int e, T v) const { p[e] = v; }
+};
+template <class T>
+struct LvMem<T, false> {
+    T* p;
+    __device__ __forceinline__ T ld(int e) const { return p[e]; }
+    __device__ __forceinline__ void st(int e, T v) const { p[e] = v; }
+};
+
+template <class T, bool LDS>
+__device__ void blk_fill(const LvMem<T, LDS>& u, const GhostCopy* __restrict__ list, long long n) {
+    for (int g = threadIdx.x; g < (int)n; g += blockDim.x) {
         const GhostCopy pc = list[g];
-        const T v = data[pc.src & 0x7fffffffu];
-        data[pc.dst] = (pc.src >> 31) ? -v : v;
+        const T v = u.ld((int)(pc.src & 0x7fffffffu));
+        u.st((int)pc.dst, (pc.src >> 31) ? -v : v);
     }
     __syncthreads();
 }
 
-// colour cell g of a single box: (i, j, k) or false
-// (the levels a workgroup handles hold at most kMaxBottomCells cells: 32-bit
-// index arithmetic; 64-bit division would dominate these small stages)
-__device__ __forceinline__ bool box_colour_cell(const RBox& B, int g, int c, int& i, int& j, int& k) {
-    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1;
-    const int tn = (nx + 1) >> 1;
-    const int r = g / tn;
-    const int t = g - r * tn;
-    const int rz = r / ny;
-    j = B.lo[1] + (r - rz * ny);
+// q = a / d, r = a % d for 0 <= a < 2^20 and d >= 1: the float estimate with
+// rd = 1/d is off by less than one, so one correction step makes it exact
+__device__ __forceinline__ void small_divmod(int a, int d, float rd, int& q, int& r) {
+    q = (int)((float)a * rd);
+    r = a - q * d;
+    if (r < 0) {
+        --q;
+        r += d;
+    } else if (r >= d) {
+        ++q;
+        r -= d;
+    }
+}
+
+// The colour cells of a single box, numbered g = t + tn (y + ny z).
+struct BoxCells {
+    int tn, ny, n;
+    float rtn, rny;
+};
+__device__ __forceinline__ BoxCells box_cells(const RBox& B) {
+    BoxCells c;
+    const int nx = B.hi[0] - B.lo[0] + 1, nz = B.hi[2] - B.lo[2] + 1;
+    c.ny = B.hi[1] - B.lo[1] + 1;
+    c.tn = (nx + 1) >> 1;
+    c.n = c.tn * c.ny * nz;
+    c.rtn = 1.0f / (float)c.tn;
+    c.rny = 1.0f / (float)c.ny;
+    return c;
+}
+// colour cell g of colour c: (i, j, k), or false past the row's end
+__device__ __forceinline__ bool box_colour_cell(const RBox& B, const BoxCells& bc, int g, int c, int& i, int& j,
+                                                int& k) {
+    int r, t, rz, y;
+    small_divmod(g, bc.tn, bc.rtn, r, t);
+    small_divmod(r, bc.ny, bc.rny, rz, y);
+    j = B.lo[1] + y;
     k = B.lo[2] + rz;
     i = colour_i(B, t, j, k, c);
     return i <= B.hi[0];
 }
 
-__device__ __forceinline__ int box_colour_cells(const RBox& B) {
-    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1, nz = B.hi[2] - B.lo[2] + 1;
-    return ((nx + 1) >> 1) * ny * nz;
+// element of cell (i,j,k) in a coarse-cycle level's storage
+__device__ __forceinline__ int blk_off(const RBox& B, int i, int j, int k) { return (int)B.base + rb_off(B, i, j, k); }
+
+// gather() for the coarse-cycle levels: 32-bit offsets, level storage M
+template <class T, int MODE, bool CENTRE, class M>
+__device__ __forceinline__ int blk_gather(const M& U, const FaceArrays<T>& fa, const RBox& B, int i, int j, int k,
+                                          Nbr<T>& n) {
+    const int c = (i + j + k) & 1;
+    const int row = (int)B.base + ((k - B.glo[2]) * B.G[1] + (j - B.glo[1])) * B.H;
+    const int cs = (int)B.cstride;
+    const int rc = c * cs + row, ro = (c ^ 1) * cs + row;
+    const int Hy = B.H, Hz = B.H * B.G[1];
+    const int m = (i - B.glo[0]) >> 1;
+    const int mxm = (i - 1 - B.glo[0]) >> 1, mxp = (i + 1 - B.glo[0]) >> 1;
+    n.xm = U.ld(ro + mxm);
+    n.xp = U.ld(ro + mxp);
+    n.ym = U.ld(ro - Hy + m);
+    n.yp = U.ld(ro + Hy + m);
+    n.zm = U.ld(ro - Hz + m);
+    n.zp = U.ld(ro + Hz + m);
+    if constexpr (CENTRE) n.c = U.ld(rc + m);
+    if constexpr (MODE == 2) {
+        const int x = i - fa.dlo[0], y = j - fa.dlo[1], z = k - fa.dlo[2];
+        const int nx = fa.n[0], ny = fa.n[1];
+        const int ix = x + (nx + 1) * (y + ny * z);
+        const int iy = x + nx * (y + (ny + 1) * z);
+        const int iz = x + nx * (y + ny * z);
+        n.bxm = fa.c[0][ix];
+        n.bxp = fa.c[0][ix + 1];
+        n.bym = fa.c[1][iy];
+        n.byp = fa.c[1][iy + nx];
+        n.bzm = fa.c[2][iz];
+        n.bzp = fa.c[2][iz + nx * ny];
+    }
+    return rc + m;
 }
 
-// A level of the coarse cycle: its descriptor and where its u and f live
-// (LDS or global memory).
-template <class T>
+// push_ghosts() on a one-box coarse-cycle level: a face neighbour >= 0 is the
+// box itself (periodic), else the face is a Dirichlet face
+template <class T, class M>
+__device__ __forceinline__ void blk_push(const M& U, const RBox& B, int i, int j, int k, T v) {
+    const int c[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            if (c[d] != (side ? B.hi[d] : B.lo[d])) continue;
+            const int q = 2 * d + side;
+            int t[3] = {i, j, k};
+            if (B.nb[q] >= 0) {
+                t[d] += B.shift[q];
+                U.st(blk_off(B, t[0], t[1], t[2]), v);
+            } else {
+                t[d] += side ? 1 : -1;
+                U.st(blk_off(B, t[0], t[1], t[2]), -v);
+            }
+        }
+}
+
+// A level of the coarse cycle: its descriptor and its u and f (LDS or device
+// memory), with generic pointers for the bottom solver.
+template <class T, bool LDS>
 struct LevelData {
     const CoarseLevel<T>& L;
-    T* u;
-    T* f;
+    LvMem<T, LDS> u, f;
+    T* ug;
+    T* fg;
 };
 
-template <class T, int MODE>
-__device__ void blk_gs(const LevelData<T>& D, int colour) {
+template <class T, int MODE, bool LDS>
+__device__ void blk_gs(const LevelData<T, LDS>& D, int colour) {
     const RBox& B = D.L.box;
-    const int n = box_colour_cells(B);
+    const BoxCells bc = box_cells(B);
     const T h2 = (T)(D.L.h * D.L.h);
-    for (int g = threadIdx.x; g < n; g += blockDim.x) {
+    for (int g = threadIdx.x; g < bc.n; g += blockDim.x) {
         int i, j, k;
-        if (!box_colour_cell(B, g, colour, i, j, k)) continue;
+        if (!box_colour_cell(B, bc, g, colour, i, j, k)) continue;
         Nbr<T> nb;
-        const long long idx = gather<T, MODE, false>(D.u, (const T*)nullptr, D.L.fa, B, i, j, k, nb);
+        const int idx = blk_gather<T, MODE, false>(D.u, D.L.fa, B, i, j, k, nb);
         T su, sb;
         sums<T, MODE>(nb, su, sb);
-        const T v = (su - h2 * D.f[idx]) / sb;
-        D.u[idx] = v;
-        if (D.L.push) push_ghosts(D.u, &D.L.box, B, i, j, k, v);
+        const T v = (su - h2 * D.f.ld(idx)) / sb;
+        D.u.st(idx, v);
+        if (D.L.push) blk_push(D.u, B, i, j, k, v);
     }
     __syncthreads();
 }
 
-template <class T, int MODE>
-__device__ void blk_smooth(const LevelData<T>& D, int nsweeps) {
+template <class T, int MODE, bool LDS>
+__device__ void blk_smooth(const LevelData<T, LDS>& D, int nsweeps) {
     for (int s = 0; s < nsweeps; ++s)
         for (int c = 0; c < 2; ++c) {
             if (!D.L.push) blk_fill(D.u, D.L.face[c ^ 1], D.L.nface[c ^ 1]);
@@ -1665,98 +1765,107 @@ __device__ void blk_smooth(const LevelData<T>& D, int nsweeps) {
         }
 }
 
-template <class T, int MODE>
-__device__ void blk_resid_restrict(const LevelData<T>& F, const LevelData<T>& C) {
+template <class T, int MODE, bool LDS>
+__device__ void blk_resid_restrict(const LevelData<T, LDS>& F, const LevelData<T, LDS>& C) {
     const RBox& B = F.L.box;
     const int cnx = (B.hi[0] - B.lo[0] + 1) >> 1, cny = (B.hi[1] - B.lo[1] + 1) >> 1, cnz = (B.hi[2] - B.lo[2] + 1) >> 1;
     const int n = cnx * cny * cnz;
+    const float rnx = 1.0f / (float)cnx, rny = 1.0f / (float)cny;
     const T ih2 = (T)(1.0 / (F.L.h * F.L.h));
     for (int g = threadIdx.x; g < n; g += blockDim.x) {
-        const int gy = g / cnx, gz = gy / cny;
-        const int I = (B.lo[0] >> 1) + (g - gy * cnx);
-        const int J = (B.lo[1] >> 1) + (gy - gz * cny);
-        const int K = (B.lo[2] >> 1) + gz;
+        int gy, gx, gz, gyy;
+        small_divmod(g, cnx, rnx, gy, gx);
+        small_divmod(gy, cny, rny, gz, gyy);
+        const int I = (B.lo[0] >> 1) + gx, J = (B.lo[1] >> 1) + gyy, K = (B.lo[2] >> 1) + gz;
         const int i = 2 * I, j = 2 * J, k = 2 * K;
         auto ra = [&](int a, int b, int c) {
-            T su, sb, uc;
-            long long idx;
-            stencil<T, MODE>(F.u, (const T*)nullptr, F.L.fa, B, a, b, c, su, sb, uc, idx);
-            return F.f[idx] - (su - sb * uc) * ih2;
+            Nbr<T> nb;
+            const int idx = blk_gather<T, MODE, true>(F.u, F.L.fa, B, a, b, c, nb);
+            T su, sb;
+            sums<T, MODE>(nb, su, sb);
+            return F.f.ld(idx) - (su - sb * nb.c) * ih2;
         };
         const T r000 = ra(i, j, k), r100 = ra(i + 1, j, k), r010 = ra(i, j + 1, k), r110 = ra(i + 1, j + 1, k);
         const T r001 = ra(i, j, k + 1), r101 = ra(i + 1, j, k + 1), r011 = ra(i, j + 1, k + 1);
         const T r111 = ra(i + 1, j + 1, k + 1);
         const T s = ((r000 + r100) + (r010 + r110)) + ((r001 + r101) + (r011 + r111));
-        C.f[rb_idx(C.L.box, I, J, K)] = s * T(0.125);
+        C.f.st(blk_off(C.L.box, I, J, K), s * T(0.125));
     }
     __syncthreads();
 }
 
-template <class T>
-__device__ void blk_zero(T* __restrict__ u, long long n) {
-    for (long long g = threadIdx.x; g < n; g += blockDim.x) u[g] = T(0);
+template <class T, bool LDS>
+__device__ void blk_zero(const LvMem<T, LDS>& u, long long n) {
+    for (int g = threadIdx.x; g < (int)n; g += blockDim.x) u.st(g, T(0));
     __syncthreads();
 }
 
-template <class T>
-__device__ void blk_copy(T* __restrict__ dst, const T* __restrict__ src, long long n) {
-    for (long long g = threadIdx.x; g < n; g += blockDim.x) dst[g] = src[g];
+template <class T, bool LD, bool LS>
+__device__ void blk_copy(const LvMem<T, LD>& dst, const LvMem<T, LS>& src, long long n) {
+    for (int g = threadIdx.x; g < (int)n; g += blockDim.x) dst.st(g, src.ld(g));
     __syncthreads();
 }
 
-template <class T>
-__device__ void blk_prolong(const LevelData<T>& C, const LevelData<T>& F, int order) {
+template <class T, bool LDS>
+__device__ void blk_prolong(const LevelData<T, LDS>& C, const LevelData<T, LDS>& F, int order) {
     const RBox& B = F.L.box;
-    const int n = box_colour_cells(B);
-    for (int g = threadIdx.x; g < n; g += blockDim.x)
+    const RBox& Q = C.L.box;
+    const BoxCells bc = box_cells(B);
+    for (int g = threadIdx.x; g < bc.n; g += blockDim.x)
         for (int c = 0; c < 2; ++c) {
             int i, j, k;
-            if (!box_colour_cell(B, g, c, i, j, k)) continue;
+            if (!box_colour_cell(B, bc, g, c, i, j, k)) continue;
             const int I = i >> 1, J = j >> 1, K = k >> 1;
             const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
-            const RBox& Q = C.L.box;
-            const T c000 = C.u[rb_idx(Q, I, J, K)];
+            const T c000 = C.u.ld(blk_off(Q, I, J, K));
             T e;
             if (order == 1) {
                 e = c000;
             } else {
-                const T c100 = C.u[rb_idx(Q, I + si, J, K)], c010 = C.u[rb_idx(Q, I, J + sj, K)];
-                const T c001 = C.u[rb_idx(Q, I, J, K + sk)];
-                const T c110 = C.u[rb_idx(Q, I + si, J + sj, K)], c101 = C.u[rb_idx(Q, I + si, J, K + sk)];
-                const T c011 = C.u[rb_idx(Q, I, J + sj, K + sk)];
-                const T c111 = C.u[rb_idx(Q, I + si, J + sj, K + sk)];
+                const T c100 = C.u.ld(blk_off(Q, I + si, J, K)), c010 = C.u.ld(blk_off(Q, I, J + sj, K));
+                const T c001 = C.u.ld(blk_off(Q, I, J, K + sk));
+                const T c110 = C.u.ld(blk_off(Q, I + si, J + sj, K)), c101 = C.u.ld(blk_off(Q, I + si, J, K + sk));
+                const T c011 = C.u.ld(blk_off(Q, I, J + sj, K + sk));
+                const T c111 = C.u.ld(blk_off(Q, I + si, J + sj, K + sk));
                 e = (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
                     T(0.015625);
             }
-            const long long idx = rb_idx(B, i, j, k);
-            const T v = F.u[idx] + e;
-            F.u[idx] = v;
-            if (F.L.push) push_ghosts(F.u, &F.L.box, B, i, j, k, v);
+            const int idx = blk_off(B, i, j, k);
+            const T v = F.u.ld(idx) + e;
+            F.u.st(idx, v);
+            if (F.L.push) blk_push(F.u, B, i, j, k, v);
         }
     __syncthreads();
 }
 
-// The fused coarse V-cycle of one problem per workgroup.  With cc.lds the
-// levels' u and f live in LDS for the whole cycle (they are scratch below
-// the top level); the top level's f is read at the start and its u, the
-// correction, is written back at the end.
-template <class T, int MODE>
+// The fused coarse V-cycle of one problem per workgroup.  LDS: the levels'
+// u and f live in LDS for the whole cycle (they are scratch below the top
+// level); the top level's f is read at the start and its u, the correction,
+// written back at the end.  Otherwise they stay in device memory.  Either
+// way the cycle starts by zeroing the top level's u.
+template <class T, int MODE, bool LDS>
 __global__ void __launch_bounds__(kBotThreads) k_coarse_cycle(const CoarseCycle<T>* __restrict__ ccs,
                                                              const int* __restrict__ active) {
+    typedef __attribute__((address_space(3))) T lds_T;
     const CoarseCycle<T>& cc = ccs[blockIdx.x];
     if (active && !active[cc.pid]) return;
     const int nl = cc.nlev;
     auto lev = [&](int m) {
-        if (cc.lds) return LevelData<T>{cc.L[m], (T*)(bxmg_lds + cc.lds_u[m]), (T*)(bxmg_lds + cc.lds_f[m])};
-        return LevelData<T>{cc.L[m], cc.L[m].u, cc.L[m].f};
+        if constexpr (LDS) {
+            T* ug = (T*)(bxmg_lds + cc.lds_u[m]);
+            T* fg = (T*)(bxmg_lds + cc.lds_f[m]);
+            return LevelData<T, true>{cc.L[m], {(lds_T*)ug}, {(lds_T*)fg}, ug, fg};
+        } else {
+            return LevelData<T, false>{cc.L[m], {cc.L[m].u}, {cc.L[m].f}, cc.L[m].u, cc.L[m].f};
+        }
     };
-    if (cc.lds) {
-        const LevelData<T> top = lev(0);
+    {
+        const auto top = lev(0);
         blk_zero(top.u, cc.L[0].nelem);
-        blk_copy(top.f, (const T*)cc.L[0].f, cc.L[0].nelem);
+        if constexpr (LDS) blk_copy(top.f, LvMem<T, false>{cc.L[0].f}, cc.L[0].nelem);
     }
     for (int l = 0; l + 1 < nl; ++l) {
-        const LevelData<T> F = lev(l), C = lev(l + 1);
+        const auto F = lev(l), C = lev(l + 1);
         blk_smooth<T, MODE>(F, cc.nu1);
         if (!F.L.push) {
             blk_fill(F.u, F.L.face[0], F.L.nface[0]);
@@ -1766,7 +1875,7 @@ __global__ void __launch_bounds__(kBotThreads) k_coarse_cycle(const CoarseCycle<
         blk_zero(C.u, C.L.nelem);
     }
     {
-        const LevelData<T> Db = lev(nl - 1);
+        const auto Db = lev(nl - 1);
         const CoarseLevel<T>& Lb = cc.L[nl - 1];
         BottomGeom G;
         for (int d = 0; d < 3; ++d) {
@@ -1778,19 +1887,19 @@ __global__ void __launch_bounds__(kBotThreads) k_coarse_cycle(const CoarseCycle<
         const int N = G.n[0] * G.n[1] * G.n[2];
         BottomLds S(bxmg_lds + cc.bot_off, N, (G.n[0] + 2) * (G.n[1] + 2) * (G.n[2] + 2));
         if (N <= kWaveBottomCells) {
-            if (threadIdx.x < 64) bottom_cg_wave<T, MODE == 2>(Db.u, Db.f, Lb.fa, &Lb.box, G, Lb.h, cc.rtol, cc.iters, S);
+            if (threadIdx.x < 64) bottom_cg_wave<T, MODE == 2>(Db.ug, Db.fg, Lb.fa, &Lb.box, G, Lb.h, cc.rtol, cc.iters, S);
         } else {
-            bottom_cg<T, MODE == 2>(Db.u, Db.f, Lb.fa, &Lb.box, G, Lb.h, cc.rtol, cc.iters, S);
+            bottom_cg<T, MODE == 2>(Db.ug, Db.fg, Lb.fa, &Lb.box, G, Lb.h, cc.rtol, cc.iters, S);
         }
         __syncthreads();
     }
     for (int l = nl - 2; l >= 0; --l) {
-        const LevelData<T> F = lev(l), C = lev(l + 1);
+        const auto F = lev(l), C = lev(l + 1);
         blk_fill(C.u, C.L.full, C.L.nfull);
         blk_prolong(C, F, cc.prolong);
         blk_smooth<T, MODE>(F, cc.nu2);
     }
-    if (cc.lds) blk_copy(cc.L[0].u, (const T*)lev(0).u, cc.L[0].nelem);
+    if constexpr (LDS) blk_copy(LvMem<T, false>{cc.L[0].u}, lev(0).u, cc.L[0].nelem);
 }
 
 // ================================================================ launchers
@@ -2062,21 +2171,28 @@ template hipError_t launch_bottom<float>(hipStream_t, float*, const float*, Face
 
 template <class T>
 hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, int n, const int* active, bool var,
-                               int lds_bytes) {
+                               int lds_bytes, bool levels_lds) {
     if (n <= 0) return hipSuccess;
+#define BXMG_CC(MODE, LDS)                                                                                 \
+    do {                                                                                                   \
+        static const bool once = allow_lds((const void*)k_coarse_cycle<T, MODE, LDS>);                     \
+        (void)once;                                                                                        \
+        hipLaunchKernelGGL((k_coarse_cycle<T, MODE, LDS>), dim3(n), dim3(kBotThreads), lds_bytes, s, cc, active); \
+    } while (0)
     if (var) {
-        static const bool once = allow_lds((const void*)k_coarse_cycle<T, 2>);
-        (void)once;
-        hipLaunchKernelGGL((k_coarse_cycle<T, 2>), dim3(n), dim3(kBotThreads), lds_bytes, s, cc, active);
+        if (levels_lds) BXMG_CC(2, true);
+        else BXMG_CC(2, false);
     } else {
-        static const bool once = allow_lds((const void*)k_coarse_cycle<T, 0>);
-        (void)once;
-        hipLaunchKernelGGL((k_coarse_cycle<T, 0>), dim3(n), dim3(kBotThreads), lds_bytes, s, cc, active);
+        if (levels_lds) BXMG_CC(0, true);
+        else BXMG_CC(0, false);
     }
+#undef BXMG_CC
     return hipGetLastError();
 }
-template hipError_t launch_coarse_cycle<double>(hipStream_t, const CoarseCycle<double>*, int, const int*, bool, int);
-template hipError_t launch_coarse_cycle<float>(hipStream_t, const CoarseCycle<float>*, int, const int*, bool, int);
+template hipError_t launch_coarse_cycle<double>(hipStream_t, const CoarseCycle<double>*, int, const int*, bool, int,
+                                                bool);
+template hipError_t launch_coarse_cycle<float>(hipStream_t, const CoarseCycle<float>*, int, const int*, bool, int,
+                                               bool);
 
 // ------------------------------------------------------------ batch kernels
 // One block per segment: a fixed-tree reduction over the segment's tiles, in
