@@ -285,7 +285,7 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
             else H->faces32[l]->table.upload({H->faces32[l]->view(D)});
         }
     }
-    H->partials.alloc(3 * max_tiles + 8);
+    H->partials.alloc(6 * max_tiles + 8);  // two sets: the fused residual's colour-1 and colour-0 norms
     H->fnorm.alloc(4);
     H->st.alloc(1);
     H->flags.alloc(4);
@@ -399,6 +399,11 @@ struct Run {
     // the solve's stop flag (active[0]); the V-cycle's kernels do nothing
     // once the device-side stop test has cleared it
     const int* active = nullptr;
+    // fused residual: the last level-0 colour-1 sweep of the V-cycle writes
+    // its cells' residual norms here (and sets fused_sweep), so the stop test
+    // needs the colour-0 residual only
+    double* fuse_norms = nullptr;
+    bool fused_sweep = false;
     Grid grid(const Grid& g) const {
         Grid r = g;
         r.active = active;
@@ -426,8 +431,10 @@ void fill_faces(Run& R, size_t l, T* data) {
     fill<T>(R, l, data, L.face[1]);
 }
 
+// post: the post-smoothing, whose last level-0 sweep may carry the fused
+// residual norms
 template <class T>
-void smooth(Run& R, size_t l, int nsweeps) {
+void smooth(Run& R, size_t l, int nsweeps, bool post = false) {
     Hier* H = R.H;
     const Level& L = *H->L[l];
     T* u = lvl_u<T>(H, l);
@@ -435,9 +442,12 @@ void smooth(Run& R, size_t l, int nsweeps) {
     for (int s = 0; s < nsweeps; ++s)
         for (int c = 0; c < 2; ++c) {
             if (!L.push) fill<T>(R, l, u, L.face[c ^ 1]);
+            const bool fuse = R.fuse_norms && l == 0 && post && s == nsweeps - 1 && c == 1;
             R.pre(l, kStageGS);
-            HIPCHK(launch_gs<T>(R.s, R.grid(L.walk()), u, f, lvl_beta<T>(H, l), lvl_fat<T>(H, l), c));
+            HIPCHK(launch_gs<T>(R.s, R.grid(L.walk()), u, f, lvl_beta<T>(H, l), lvl_fat<T>(H, l), c,
+                                fuse ? R.fuse_norms : nullptr));
             R.post(l, kStageGS);
+            if (fuse) R.fused_sweep = true;
         }
 }
 
@@ -528,7 +538,7 @@ void vcycle(Run& R, size_t l) {
     HIPCHK(launch_prolong<T>(R.s, R.grid(L.walk()), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong, R.nu2 > 0,
                              L.stage_values, self));
     R.post(l, kStageProlong);
-    smooth<T>(R, l, R.nu2);
+    smooth<T>(R, l, R.nu2, true);
 }
 
 // Coefficient setup: cell beta at level 0 (exchange + even reflection), then
@@ -1002,10 +1012,18 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         HIPCHK(launch_norm_final(R.s, H->partials.p, L0.view_grid().ntiles, H->fn3.p));
         HIPCHK(launch_batch_admit(R.s, H->fn3.p, H->st.p, H->flags.p, 0));
         R.active = H->flags.p;
-        auto check = [&]() {  // residual of the current iterate, then the stop test
+        // FP64 solves on a pushing, buffer-addressed level 0 with post-smoothing
+        // take the colour-1 residual norms in the V-cycle's last level-0 sweep
+        const bool fusable = P.precision == 0 && L0.push && L0.res && P.nu2 > 0;
+        double* const norms1 = H->partials.p + 3 * (size_t)L0.ntcol;
+        auto check = [&](bool fused) {  // residual of the current iterate, then the stop test
             if (!L0.push) fill_faces<double>(R, 0, u);
             R.pre(0, kStageResid);
-            if (P.precision == 0) {
+            if (fused) {
+                // colour 0 now; colour 1's norms are in the second set
+                HIPCHK(launch_resid<double, double>(R.s, R.grid(L0.walk()), u, f, beta ? H->beta64.p : nullptr, nf,
+                                                    (double*)nullptr, H->partials.p, true));
+            } else if (P.precision == 0) {
                 HIPCHK(launch_resid<double, double>(R.s, R.grid(L0.walk()), u, f, beta ? H->beta64.p : nullptr, nf,
                                                     (double*)nullptr, H->partials.p));
             } else {
@@ -1013,17 +1031,22 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
                                                    H->f32[0]->p, H->partials.p));
             }
             R.post(0, kStageResid);
-            HIPCHK(launch_norm_final(R.s, H->partials.p, L0.ntcol, H->fnorm.p));
+            HIPCHK(launch_norm_final(R.s, H->partials.p, (fused ? 2 : 1) * L0.ntcol, H->fnorm.p));
             HIPCHK(launch_batch_check(R.s, H->flags.p + 1, 1, H->fnorm.p, H->st.p, H->flags.p, H->hist.p,
                                       H->hist.p + kHist, H->flags.p + 2));
         };
-        auto cycle = [&]() {
+        auto cycle = [&]() {  // returns whether its last level-0 sweep took the colour-1 norms
             if (P.precision == 0) {
+                R.fuse_norms = fusable ? norms1 : nullptr;
+                R.fused_sweep = false;
                 vcycle<double>(R, 0);
+                R.fuse_norms = nullptr;
+                return R.fused_sweep;
             } else {
                 HIPCHK(launch_zero<float>(R.s, H->u32[0]->p, L0.nelem, R.active));
                 vcycle<float>(R, 0);
                 HIPCHK(launch_add_f32(R.s, R.grid(L0.walk()), u, H->u32[0]->p));
+                return false;
             }
         };
         auto look = [&]() {
@@ -1034,11 +1057,10 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         };
         // queued = V-cycles enqueued; residual number c follows cycle c
         const int limit = P.fixed_cycles > 0 ? P.fixed_cycles : P.max_cycles;
-        check();
+        check(false);
         int queued = 0;
         if (limit > 0) {
-            cycle();
-            check();
+            check(cycle());
             queued = 1;
         }
         for (;;) {
@@ -1060,8 +1082,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
                 ahead = std::min(ahead, pred);
             }
             for (int a = 0; a < std::max(ahead, 1); ++a) {
-                cycle();
-                check();
+                check(cycle());
                 ++queued;
             }
         }

@@ -189,16 +189,19 @@ hipError_t launch_fill_fab(hipStream_t s, void* data, bool f32, const FBox* boxe
 // Coefficient modes of the stencil kernels: beta != nullptr -> cell beta of
 // the level (same layout as u); fat != nullptr -> face arrays fat[pid] of the
 // box's problem; both null -> constant coefficient.  Grid spacing: RBox::h.
+// norm_partials != nullptr (FP64, pushing, buffer-addressed levels): also the
+// residual norms of the updated cells per tile, as launch_resid writes them.
 template <class T>
 hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* beta, const FaceArrays<T>* fat,
-                     int colour);
+                     int colour, double* norm_partials = nullptr);
 
 // r = f - L u on both colours, optional store of r (R = T, or float for the
 // mixed-precision cast), partial norms (max|r|, sum r^2, bad count) at
-// 3 * (tile index)
+// 3 * (tile index).  colour0_only (FP64, buffer-addressed, no store): the
+// colour-0 cells only, after a colour-1 sweep that took the others' norms.
 template <class T, class R>
 hipError_t launch_resid(hipStream_t s, const Grid& g, const T* u, const T* f, const T* beta,
-                        const FaceArrays<T>* fat, R* r, double* partials);
+                        const FaceArrays<T>* fat, R* r, double* partials, bool colour0_only = false);
 hipError_t launch_norm_final(hipStream_t s, const double* partials, int n, double* out3);
 hipError_t launch_field_norm(hipStream_t s, const Grid& g, const double* x, double* partials);
 

@@ -19,6 +19,7 @@
 // Floating point: built with -ffp-contract=off; every expression below
 // fixes its operation order, so results are reproducible run to run.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <algorithm>
 
@@ -406,62 +407,82 @@ __global__ void __launch_bounds__(kBlock) k_fill_fab(T* __restrict__ data, const
 
 // ---------------------------------------------------- red-black smoothing
 // One colour: u_c = (su - h^2 f) / sb.  Reads only the other colour of u.
-template <class T, int MODE, bool PUSH, bool RES>
+// NORM: also the residual f - (su - sb u_c) / h^2 of each updated cell, in
+// norms per tile (partials[3 tile] = max |r|, sum r^2, non-finite count):
+// after the last colour-1 sweep of a V-cycle the colour-0 cells it read are
+// final, so this is bitwise what k_resid computes for those cells.
+template <class T, int MODE, bool PUSH, bool RES, bool NORM>
 __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const T* __restrict__ f,
                                               const T* __restrict__ beta, const FaceArrays<T>* __restrict__ fat,
-                                              int colour) {
-    const Tile tl = g.tiles[tile_index(g.rev)];
+                                              int colour, double* __restrict__ partials) {
+    __shared__ double sh[NORM ? 3 * (kBlock / 64) : 1];
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    const int tix = tile_index(g.rev);
+    const Tile tl = g.tiles[tix];
     const RBox B = g.boxes[tl.box];
-    if (g.active && !g.active[B.pid]) return;
+    if (g.active && !g.active[B.pid]) return;  // the whole workgroup
     FaceArrays<T> fa;
     if constexpr (MODE == 2) fa = fat[B.pid];
     const T h2 = (T)(B.h * B.h);
+    const T ih2 = (T)(1.0 / (B.h * B.h));
     const TileThread th = tile_thread(tl);
     const int j = B.lo[1] + th.y;
-    if (j > B.hi[1]) return;
     const long long ne = 2 * B.cstride;
     const BoxRes<T> U(u + B.base, ne), F(f + B.base, ne), Bt((MODE == 1 ? beta : f) + B.base, ne);
-    // Walking planes 2 apart, a thread's cell keeps its x position (same
-    // colour parity), so the z+ neighbour of one plane is the z- neighbour of
-    // the next: kept in registers instead of loaded again (one load of seven).
-    const bool walk2 = th.dz == 2;
-    T carry_u = T(0), carry_b = T(0);
-    bool carry = false;
-    for (int z = 0; z < (int)tl.zc; ++z) {
-        const int k = B.lo[2] + th.z0 + z * th.dz;
-        const int i = colour_i(B, th.x, j, k, colour);
-        if (k > B.hi[2]) break;
-        if (i > B.hi[0]) {  // only where the walk changes the cell's parity
-            carry = false;
-            continue;
+    if (j <= B.hi[1]) {
+        // Walking planes 2 apart, a thread's cell keeps its x position (same
+        // colour parity), so the z+ neighbour of one plane is the z- neighbour
+        // of the next: kept in registers instead of loaded again (one load of seven).
+        const bool walk2 = th.dz == 2;
+        T carry_u = T(0), carry_b = T(0);
+        bool carry = false;
+        for (int z = 0; z < (int)tl.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            const int i = colour_i(B, th.x, j, k, colour);
+            if (k > B.hi[2]) break;
+            if (i > B.hi[0]) {  // only where the walk changes the cell's parity
+                carry = false;
+                continue;
+            }
+            Nbr<T> nb;
+            nb.zm = carry_u;
+            nb.bzm = carry_b;
+            long long idx;
+            T fv;
+            if constexpr (RES) {
+                idx = gather_res<T, MODE, false>(U, Bt, fa, B, i, j, k, nb, carry, &F, &fv);
+            } else {
+                idx = gather<T, MODE, false>(u, beta, fa, B, i, j, k, nb, carry);
+                fv = f[idx];
+            }
+            T su, sb;
+            sums<T, MODE>(nb, su, sb);
+            const T v = (su - h2 * fv) / sb;
+            if constexpr (RES) U.st((int)idx, v);
+            else u[idx] = v;
+            if constexpr (PUSH) push_ghosts(u, g.boxes, B, i, j, k, v);
+            if constexpr (NORM) acc_norm((double)(fv - (su - sb * v) * ih2), mx, s2, bad);
+            carry = walk2;
+            carry_u = nb.zp;
+            if constexpr (MODE == 1) carry_b = nb.bzp;
         }
-        Nbr<T> nb;
-        nb.zm = carry_u;
-        nb.bzm = carry_b;
-        long long idx;
-        T fv;
-        if constexpr (RES) {
-            idx = gather_res<T, MODE, false>(U, Bt, fa, B, i, j, k, nb, carry, &F, &fv);
-        } else {
-            idx = gather<T, MODE, false>(u, beta, fa, B, i, j, k, nb, carry);
-            fv = f[idx];
+    }
+    if constexpr (NORM) {
+        block_reduce3(mx, s2, bad, sh);
+        if (threadIdx.x == 0) {
+            partials[3 * tix] = mx;
+            partials[3 * tix + 1] = s2;
+            partials[3 * tix + 2] = bad;
         }
-        T su, sb;
-        sums<T, MODE>(nb, su, sb);
-        const T v = (su - h2 * fv) / sb;
-        if constexpr (RES) U.st((int)idx, v);
-        else u[idx] = v;
-        if constexpr (PUSH) push_ghosts(u, g.boxes, B, i, j, k, v);
-        carry = walk2;
-        carry_u = nb.zp;
-        if constexpr (MODE == 1) carry_b = nb.bzp;
     }
 }
 
 // ---------------------------------------------------------------- residual
 // r = f - (su - sb u) / h^2 on both colours; optional store of r (same type
 // and layout) or of float(r) (mixed precision); fused norms per block.
-template <class T, int MODE, class R, bool RES>
+// COLS: bit c set = colour c's cells (3: all; 1: colour 0 only, when a
+// fused colour-1 sweep has taken the colour-1 residuals).
+template <class T, int MODE, class R, bool RES, int COLS>
 __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ u, const T* __restrict__ f,
                                                  const T* __restrict__ beta, const FaceArrays<T>* __restrict__ fat,
                                                  R* __restrict__ r, double* __restrict__ partials) {
@@ -494,7 +515,8 @@ __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ 
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const int i = colour_i(B, th.x, j, k, c);
-                ok[c] = i <= B.hi[0];
+                ok[c] = i <= B.hi[0] && ((COLS >> c) & 1);
+                if (!((COLS >> c) & 1)) continue;
                 nb[c].zm = carry_u[c];
                 nb[c].bzm = carry_b[c];
                 if constexpr (RES) {
@@ -509,6 +531,7 @@ __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ 
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
+                if (!((COLS >> c) & 1)) continue;
                 carry[c] = walk2 && ok[c];
                 carry_u[c] = nb[c].zp;
                 if constexpr (MODE == 1) carry_b[c] = nb[c].bzp;
@@ -1965,10 +1988,25 @@ hipError_t launch_fill_fab(hipStream_t s, void* data, bool f32, const FBox* boxe
 
 template <class T>
 hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* beta, const FaceArrays<T>* fat,
-                     int colour) {
+                     int colour, double* norm_partials) {
     if (g.ntiles <= 0) return hipSuccess;
     const dim3 G(g.ntiles), B(kBlock);
-#define BXMG_GS(MODE, PUSH, RES) hipLaunchKernelGGL((k_gs<T, MODE, PUSH, RES>), G, B, 0, s, g, u, f, beta, fat, colour)
+    if (norm_partials) {  // the fused residual: FP64, pushing, buffer-addressed levels
+        if constexpr (std::is_same<T, double>::value) {
+            if (!g.push || !g.res) return hipErrorInvalidValue;
+#define BXMG_GSN(MODE) \
+    hipLaunchKernelGGL((k_gs<T, MODE, true, true, true>), G, B, 0, s, g, u, f, beta, fat, colour, norm_partials)
+            if (beta) BXMG_GSN(1);
+            else if (fat) BXMG_GSN(2);
+            else BXMG_GSN(0);
+#undef BXMG_GSN
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
+#define BXMG_GS(MODE, PUSH, RES) \
+    hipLaunchKernelGGL((k_gs<T, MODE, PUSH, RES, false>), G, B, 0, s, g, u, f, beta, fat, colour, (double*)nullptr)
 #define BXMG_GS_MODES(PUSH, RES) \
     if (beta) BXMG_GS(1, PUSH, RES); else if (fat) BXMG_GS(2, PUSH, RES); else BXMG_GS(0, PUSH, RES)
     if (g.push) {
@@ -1981,16 +2019,31 @@ hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* be
     return hipGetLastError();
 }
 template hipError_t launch_gs<double>(hipStream_t, const Grid&, double*, const double*, const double*,
-                                      const FaceArrays<double>*, int);
+                                      const FaceArrays<double>*, int, double*);
 template hipError_t launch_gs<float>(hipStream_t, const Grid&, float*, const float*, const float*,
-                                     const FaceArrays<float>*, int);
+                                     const FaceArrays<float>*, int, double*);
 
 template <class T, class R>
 hipError_t launch_resid(hipStream_t s, const Grid& g, const T* u, const T* f, const T* beta,
-                        const FaceArrays<T>* fat, R* r, double* partials) {
+                        const FaceArrays<T>* fat, R* r, double* partials, bool colour0_only) {
     if (g.ntiles <= 0) return hipSuccess;
     const dim3 G(g.ntiles), B(kBlock);
-#define BXMG_RS(MODE, RES) hipLaunchKernelGGL((k_resid<T, MODE, R, RES>), G, B, 0, s, g, u, f, beta, fat, r, partials)
+    if (colour0_only) {  // after a fused colour-1 sweep: FP64, buffer-addressed, norms only
+        if constexpr (std::is_same<T, double>::value && std::is_same<R, double>::value) {
+            if (!g.res || r) return hipErrorInvalidValue;
+#define BXMG_RS0(MODE) \
+    hipLaunchKernelGGL((k_resid<T, MODE, R, true, 1>), G, B, 0, s, g, u, f, beta, fat, r, partials)
+            if (beta) BXMG_RS0(1);
+            else if (fat) BXMG_RS0(2);
+            else BXMG_RS0(0);
+#undef BXMG_RS0
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
+#define BXMG_RS(MODE, RES) \
+    hipLaunchKernelGGL((k_resid<T, MODE, R, RES, 3>), G, B, 0, s, g, u, f, beta, fat, r, partials)
     if (g.res) {
         if (beta) BXMG_RS(1, true); else if (fat) BXMG_RS(2, true); else BXMG_RS(0, true);
     } else {
@@ -2000,11 +2053,11 @@ hipError_t launch_resid(hipStream_t s, const Grid& g, const T* u, const T* f, co
     return hipGetLastError();
 }
 template hipError_t launch_resid<double, double>(hipStream_t, const Grid&, const double*, const double*, const double*,
-                                                 const FaceArrays<double>*, double*, double*);
+                                                 const FaceArrays<double>*, double*, double*, bool);
 template hipError_t launch_resid<double, float>(hipStream_t, const Grid&, const double*, const double*, const double*,
-                                                const FaceArrays<double>*, float*, double*);
+                                                const FaceArrays<double>*, float*, double*, bool);
 template hipError_t launch_resid<float, float>(hipStream_t, const Grid&, const float*, const float*, const float*,
-                                               const FaceArrays<float>*, float*, double*);
+                                               const FaceArrays<float>*, float*, double*, bool);
 
 hipError_t launch_norm_final(hipStream_t s, const double* partials, int n, double* out3) {
     hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kNormThreads), 0, s, partials, n, out3);
