@@ -535,8 +535,14 @@ void vcycle(Run& R, size_t l) {
     if (!self) fill<T>(R, l + 1, lvl_u<T>(H, l + 1), C.full);
     R.pre(l, kStageProlong);
     // with post-smoothing, its first (colour-0) sweep overwrites colour 0
+    // a large one-box fine level takes its face work in a second launch
+    long long faces = 0;
+    if (L.boxes.size() == 1 && !self) {
+        const Box& b = L.boxes[0];
+        faces = 2 * ((long long)b.n(1) * b.n(2) + (long long)b.n(0) * b.n(2) + (long long)b.n(0) * b.n(1));
+    }
     HIPCHK(launch_prolong<T>(R.s, R.grid(L.walk()), C.d_rb.p, L.cbox.p, lvl_u<T>(H, l + 1), u, R.prolong, R.nu2 > 0,
-                             L.stage_values, self));
+                             L.stage_values, self, faces));
     R.post(l, kStageProlong);
     smooth<T>(R, l, R.nu2, true);
 }

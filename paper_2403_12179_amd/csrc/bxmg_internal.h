@@ -225,6 +225,9 @@ hipError_t launch_restrict_plain(hipStream_t s, const XGrid& x, const T* rf, T* 
 // each of its ghosts mirrors one of its own cells (odd reflection across a
 // Dirichlet face, the periodic image otherwise); the staged kernel then reads
 // those cells instead of the ghosts, which need no refresh before it.
+// fine_face_cells > 0: the fine level is one box with that many cells on its
+// faces (counted once per face); the staged kernel then leaves the face work
+// (ghost pushes, Dirichlet colour-0 ghosts) to a second launch over them.
 constexpr int kProlongStage = 2048;  // values of the LDS stage
 constexpr long long kSelfGhostCells = 1LL << 18;  // coarse levels up to 64^3 resolve their ghosts in the stage
 inline bool prolong_staged(bool fine_push, bool only_c1, int stage_values) {
@@ -232,7 +235,8 @@ inline bool prolong_staged(bool fine_push, bool only_c1, int stage_values) {
 }
 template <class T>
 hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
-                          int order, bool only_c1 = false, int stage_values = 0, bool coarse_self = false);
+                          int order, bool only_c1 = false, int stage_values = 0, bool coarse_self = false,
+                          long long fine_face_cells = 0);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n, const int* active = nullptr);

@@ -1020,7 +1020,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_c1(Grid g, const RBox* __res
 // the coarse level is one box, and the stage reads each ghost's mirror cell
 // (see launch_prolong) instead of the ghost.
 
-template <class T, int ORDER, bool SELF>
+template <class T, int ORDER, bool SELF, bool FACES>
 __global__ void __launch_bounds__(kBlock) k_prolong_c1s(Grid g, const RBox* __restrict__ cboxes,
                                                        const int* __restrict__ cbox, const T* __restrict__ ec,
                                                        T* __restrict__ uf) {
@@ -1063,7 +1063,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_c1s(Grid g, const RBox* __re
             off[q] = rb_off(B, i, j, k);
             fv[q] = fb[off[q]];
             const int i0 = colour_i(B, th.x, j, kk, 0);
-            f0[q] = (kk <= B.hi[2] && dirichlet0(i0, kk)) ? fb[rb_off(B, i0, j, kk)] : T(0);
+            if constexpr (FACES) f0[q] = (kk <= B.hi[2] && dirichlet0(i0, kk)) ? fb[rb_off(B, i0, j, kk)] : T(0);
         }
     };
     // the first group is loaded before the stage barrier, so its latency
@@ -1136,12 +1136,13 @@ __global__ void __launch_bounds__(kBlock) k_prolong_c1s(Grid g, const RBox* __re
             if (i <= B.hi[0]) {
                 const T v = fv[0] + interp(i, k);
                 fb[off[0]] = v;
-                push_ghosts(uf, g.boxes, B, i, j, k, v);
+                if constexpr (FACES) push_ghosts(uf, g.boxes, B, i, j, k, v);
             }
             // the colour-0 cell of this row and plane, if it lies on a
             // Dirichlet face: its mirrored ghost gets -(u + P e)
             const int i0 = colour_i(B, th.x, j, k, 0);
-            if (dirichlet0(i0, k)) push_dirichlet(uf, B, i0, j, k, f0[0] + interp(i0, k));
+            if constexpr (FACES)
+                if (dirichlet0(i0, k)) push_dirichlet(uf, B, i0, j, k, f0[0] + interp(i0, k));
 #pragma unroll
             for (int m = 0; m + 1 < kProlongGroup; ++m) {
                 fv[m] = fv[m + 1];
@@ -1150,6 +1151,72 @@ __global__ void __launch_bounds__(kBlock) k_prolong_c1s(Grid g, const RBox* __re
             }
         }
     }
+}
+
+// The face work k_prolong_c1s<..., FACES = false> leaves out, for a fine
+// level that is one box: after it, every cell on a face of the box pushes
+// its corrected colour-1 value into the ghosts that mirror it, and a
+// colour-0 cell on a Dirichlet face writes -(u + P e) into its own ghosts
+// there.  The same values, written by a second launch over the face cells
+// only: in the main launch every wave holds a face lane and paid for this
+// code on every plane.  A cell on an edge or corner is visited once per face
+// and writes the same values each time.
+template <class T, int ORDER>
+__global__ void __launch_bounds__(kBlock) k_prolong_faces(Grid g, const RBox* __restrict__ cboxes,
+                                                         const int* __restrict__ cbox, const T* __restrict__ ec,
+                                                         T* __restrict__ uf) {
+    const RBox B = g.boxes[0];
+    if (g.active && !g.active[B.pid]) return;
+    const RBox C = cboxes[cbox[0]];
+    const int n0 = B.hi[0] - B.lo[0] + 1, n1 = B.hi[1] - B.lo[1] + 1, n2 = B.hi[2] - B.lo[2] + 1;
+    const long long fx = (long long)n1 * n2, fy = (long long)n0 * n2, fz = (long long)n0 * n1;
+    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int i, j, k;
+    if (q < 2 * fx) {  // x faces: (j, k)
+        const int side = q >= fx;
+        q -= side * fx;
+        i = side ? B.hi[0] : B.lo[0];
+        j = B.lo[1] + (int)(q % n1);
+        k = B.lo[2] + (int)(q / n1);
+    } else if ((q -= 2 * fx) < 2 * fy) {  // y faces: (i, k)
+        const int side = q >= fy;
+        q -= side * fy;
+        j = side ? B.hi[1] : B.lo[1];
+        i = B.lo[0] + (int)(q % n0);
+        k = B.lo[2] + (int)(q / n0);
+    } else if ((q -= 2 * fy) < 2 * fz) {  // z faces: (i, j)
+        const int side = q >= fz;
+        q -= side * fz;
+        k = side ? B.hi[2] : B.lo[2];
+        i = B.lo[0] + (int)(q % n0);
+        j = B.lo[1] + (int)(q / n0);
+    } else {
+        return;
+    }
+    const long long idx = rb_idx(B, i, j, k);
+    if ((i + j + k) & 1) {
+        push_ghosts(uf, g.boxes, B, i, j, k, uf[idx]);
+        return;
+    }
+    const bool dir = (i == B.lo[0] && B.nb[0] < 0) || (i == B.hi[0] && B.nb[1] < 0) ||
+                     (j == B.lo[1] && B.nb[2] < 0) || (j == B.hi[1] && B.nb[3] < 0) ||
+                     (k == B.lo[2] && B.nb[4] < 0) || (k == B.hi[2] && B.nb[5] < 0);
+    if (!dir) return;
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+    const T* __restrict__ cb = ec + C.base;
+    T e;
+    if constexpr (ORDER == 1) {
+        e = cb[rb_off(C, I, J, K)];
+    } else {
+        const T c000 = cb[rb_off(C, I, J, K)], c100 = cb[rb_off(C, I + si, J, K)];
+        const T c010 = cb[rb_off(C, I, J + sj, K)], c001 = cb[rb_off(C, I, J, K + sk)];
+        const T c110 = cb[rb_off(C, I + si, J + sj, K)], c101 = cb[rb_off(C, I + si, J, K + sk)];
+        const T c011 = cb[rb_off(C, I, J + sj, K + sk)], c111 = cb[rb_off(C, I + si, J + sj, K + sk)];
+        e = (((T(27) * c000 + T(9) * ((c100 + c010) + c001)) + T(3) * ((c110 + c101) + c011)) + c111) *
+            T(0.015625);
+    }
+    push_dirichlet(uf, B, i, j, k, uf[idx] + e);
 }
 
 // -------------------------------------------------------------- utilities
@@ -2095,8 +2162,11 @@ template hipError_t launch_restrict_plain<double>(hipStream_t, const XGrid&, con
 
 template <class T>
 hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, const int* cbox, const T* ec, T* uf,
-                          int order, bool only_c1, int stage_values, bool coarse_self) {
+                          int order, bool only_c1, int stage_values, bool coarse_self, long long fine_face_cells) {
     if (fine.ntiles <= 0) return hipSuccess;
+    // a one-box fine level: its face work goes to a second launch over the face cells
+    const bool faces_apart = fine_face_cells > 0;
+    const long long nface = fine_face_cells;
     const dim3 G(fine.ntiles), B(kBlock);
     // levels refreshed by fill lists copy ghosts from both colours' cells:
     // they keep the two-colour kernel
@@ -2105,9 +2175,12 @@ hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, c
 #define BXMG_PROLONG(PUSH, ORDER)                                                                    \
     do {                                                                                            \
         if (PUSH && c1 && staged && coarse_self)                                                    \
-            hipLaunchKernelGGL((k_prolong_c1s<T, ORDER, true>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
-        else if (PUSH && c1 && staged)                                                              \
-            hipLaunchKernelGGL((k_prolong_c1s<T, ORDER, false>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
+            hipLaunchKernelGGL((k_prolong_c1s<T, ORDER, true, true>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
+        else if (PUSH && c1 && staged && faces_apart) {                                             \
+            hipLaunchKernelGGL((k_prolong_c1s<T, ORDER, false, false>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
+            hipLaunchKernelGGL((k_prolong_faces<T, ORDER>), dim3(nblk(nface)), B, 0, s, fine, cboxes, cbox, ec, uf); \
+        } else if (PUSH && c1 && staged)                                                            \
+            hipLaunchKernelGGL((k_prolong_c1s<T, ORDER, false, true>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
         else if (PUSH && c1) hipLaunchKernelGGL((k_prolong_c1<T, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
         else hipLaunchKernelGGL((k_prolong<T, PUSH, ORDER>), G, B, 0, s, fine, cboxes, cbox, ec, uf); \
     } while (0)
@@ -2122,9 +2195,9 @@ hipError_t launch_prolong(hipStream_t s, const Grid& fine, const RBox* cboxes, c
     return hipGetLastError();
 }
 template hipError_t launch_prolong<double>(hipStream_t, const Grid&, const RBox*, const int*, const double*, double*,
-                                           int, bool, int, bool);
+                                           int, bool, int, bool, long long);
 template hipError_t launch_prolong<float>(hipStream_t, const Grid&, const RBox*, const int*, const float*, float*, int,
-                                          bool, int, bool);
+                                          bool, int, bool, long long);
 
 template <class T>
 hipError_t launch_zero(hipStream_t s, T* p, long long n, const int* active) {
