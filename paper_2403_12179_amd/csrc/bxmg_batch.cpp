@@ -901,7 +901,9 @@ bxmg_status bxmg_batch_add(bxmg_batch b, bxmg_multifab phi, bxmg_multifab rhs, b
         double* u = b->u64.p + base;
         double* f = b->f64.p + base;
         HIPCHK(launch_fab_to_rb(s, g0, (const double*)phi->data, phi->d_fboxes.p, u, false));
-        HIPCHK(launch_fab_to_rb(s, g0, (const double*)rhs->data, rhs->d_fboxes.p, f, false));
+        // f, with the norms of f per tile on the way (reduced below)
+        b->scratch.reserve(3 * (size_t)P.nt0 + 8);
+        HIPCHK(launch_fab_to_rb_norm(s, g0, (const double*)rhs->data, rhs->d_fboxes.p, f, b->scratch.p()));
         if (b->var) {
             double* bt = b->b64.p + base;
             HIPCHK(launch_fab_to_rb(s, g0, (const double*)beta->data, beta->d_fboxes.p, bt, false));
@@ -917,8 +919,6 @@ bxmg_status bxmg_batch_add(bxmg_batch b, bxmg_multifab phi, bxmg_multifab rhs, b
         HIPCHK(launch_fill_rb(s, u, false, P.L[0].face[0].p, (long long)P.L[0].face[0].n));
         HIPCHK(launch_fill_rb(s, u, false, P.L[0].face[1].p, (long long)P.L[0].face[1].n));
         // ||f||_inf and the slot state, decided on the device
-        b->scratch.reserve(3 * (size_t)P.nt0 + 8);
-        HIPCHK(launch_field_norm(s, g0, f, b->scratch.p()));
         HIPCHK(launch_norm_final(s, b->scratch.p(), P.nt0, b->fn3.p + 3 * (size_t)slot));
         BatchSlot S{};
         S.rel_tol = q.rel_tol;

@@ -984,7 +984,8 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         double* f = H->f64[0]->p;
         // caller layout -> colour-split level 0
         HIPCHK(launch_fab_to_rb(R.s, L0.view_grid(), (const double*)phi->data, phi->d_fboxes.p, u, false));
-        HIPCHK(launch_fab_to_rb(R.s, L0.view_grid(), (const double*)rhs->data, rhs->d_fboxes.p, f, false));
+        // f, with the norms of f per tile on the way (reduced below)
+        HIPCHK(launch_fab_to_rb_norm(R.s, L0.view_grid(), (const double*)rhs->data, rhs->d_fboxes.p, f, H->partials.p));
         if (beta) {
             HIPCHK(launch_fab_to_rb(R.s, L0.view_grid(), (const double*)beta->data, beta->d_fboxes.p, H->beta64.p, false));
             if (P.precision == 0) {
@@ -1014,7 +1015,6 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         S0.fixed_cycles = P.fixed_cycles;
         hs->st = S0;  // pinned: the source of the copy
         HIPCHK(hipMemcpyAsync(H->st.p, &hs->st, sizeof S0, hipMemcpyHostToDevice, R.s));
-        HIPCHK(launch_field_norm(R.s, L0.view_grid(), f, H->partials.p));
         HIPCHK(launch_norm_final(R.s, H->partials.p, L0.view_grid().ntiles, H->fn3.p));
         HIPCHK(launch_batch_admit(R.s, H->fn3.p, H->st.p, H->flags.p, 0));
         R.active = H->flags.p;

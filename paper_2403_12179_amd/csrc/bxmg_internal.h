@@ -244,6 +244,9 @@ hipError_t launch_cast_f32(hipStream_t s, const double* src, float* dst, long lo
 
 // layout conversions: F-order caller MultiFab (FP64, comp 0) <-> RB level
 hipError_t launch_fab_to_rb(hipStream_t s, const Grid& g, const double* fab, const FBox* fb, void* rb, bool f32);
+// launch_fab_to_rb (FP64) and launch_field_norm of the result in one pass
+hipError_t launch_fab_to_rb_norm(hipStream_t s, const Grid& g, const double* fab, const FBox* fb, double* rb,
+                                double* partials);
 hipError_t launch_rb_to_fab(hipStream_t s, const Grid& g, const double* rb, double* fab, const FBox* fb);
 hipError_t launch_add_f32(hipStream_t s, const Grid& g, double* u, const float* e);
 

@@ -609,6 +609,38 @@ __global__ void __launch_bounds__(kBlock) k_field_norm(Grid g, const double* __r
     }
 }
 
+// k_fab_to_rb<double> and k_field_norm of what it writes in one pass: the
+// same tiles and cell order as k_field_norm, so the same partials.
+__global__ void __launch_bounds__(kBlock) k_fab_to_rb_norm(Grid g, const double* __restrict__ fab,
+                                                          const FBox* __restrict__ fb, double* __restrict__ rb,
+                                                          double* __restrict__ partials) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    const Tile tl = g.tiles[tile_index(g.rev)];
+    const RBox B = g.boxes[tl.box];
+    const FBox F = fb[tl.box];
+    const TileThread th = tile_thread(tl);
+    const int j = B.lo[1] + th.y;
+    if (j <= B.hi[1])
+        for (int z = 0; z < (int)tl.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            if (k > B.hi[2]) break;
+            for (int c = 0; c < 2; ++c) {
+                const int i = colour_i(B, th.x, j, k, c);
+                if (i > B.hi[0]) continue;
+                const double v = fab[fab_idx(F, i, j, k)];
+                rb[rb_idx(B, i, j, k)] = v;
+                acc_norm(v, mx, s2, bad);
+            }
+        }
+    block_reduce3(mx, s2, bad, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = mx;
+        partials[3 * blockIdx.x + 1] = s2;
+        partials[3 * blockIdx.x + 2] = bad;
+    }
+}
+
 // ---------------------------------------------------------- fine <-> coarse
 // Coarse cell (I, J, K) of the tile's fine box, or false past its end.
 struct CoarseCell {
@@ -2213,6 +2245,13 @@ hipError_t launch_cast_f32(hipStream_t s, const double* src, float* dst, long lo
     if (n <= 0) return hipSuccess;
     const long long nb = std::min<long long>(nblk(n), 8192);
     hipLaunchKernelGGL(k_cast_f32, dim3((unsigned)nb), dim3(kBlock), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fab_to_rb_norm(hipStream_t s, const Grid& g, const double* fab, const FBox* fb, double* rb,
+                                double* partials) {
+    if (g.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fab_to_rb_norm, dim3(g.ntiles), dim3(kBlock), 0, s, g, fab, fb, rb, partials);
     return hipGetLastError();
 }
 
