@@ -182,6 +182,26 @@ def test_status_codes(bx):
     assert res.ok and res.cycles == 0 and not np.any(phi.to_global())
 
 
+def test_periodic_large_one_box_levels(bx, orc):
+    """A periodic 192^3 domain in 64^3 boxes runs level 0 as one box: its
+    prolongation leaves the face ghosts (periodic images) to a launch over
+    the face cells, and the 96^3 level below it mirrors its ghosts in the
+    prolongation stage.  The fused colour-1 residual decides the stop test.
+    Two fixed cycles follow the oracle's iterates; a full solve converges."""
+    n = 192
+    f = W.uniform_rhs((n, n, n), 29, mean_zero=True)
+    ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 64, (1, 1, 1), f)
+    res = bx.mlmg_solve(phi, rhs, fixed_cycles=2)
+    uo, io = orc.solve((0, 0, 0), (n - 1,) * 3, (1, 1, 1), [(b.small, b.big) for b in ba.boxes], f, fixed_cycles=2)
+    assert res.cycles == 2 and io["cycles"] == 2
+    u = phi.to_global()
+    assert np.max(np.abs(u - uo)) <= 1e-12 * np.max(np.abs(uo))
+    hist_match(res.hist, io["hist"])
+    phi.set_val(0.0)
+    res = bx.mlmg_solve(phi, rhs)
+    assert res.ok and res.rel_resid_inf <= 1e-10
+
+
 def test_full_size_256_in_512_boxes(bx, orc):
     """The 256^3 / 512 x 32^3 Dirichlet workload at full size: the FP64
     solve reaches 1e-10 as recomputed by the oracle's operator, and two
