@@ -94,7 +94,7 @@ struct Level {
                       : Grid{d_rb.p, tmean.p, ntmean, push ? 1 : 0, nullptr, 0, res ? 1 : 0};
     }
     int stage_values = 0;  // coarse values a colour tile reads in a prolongation (bound)
-    Grid grid() const { return Grid{d_rb.p, tcol.p, ntcol, push ? 1 : 0, nullptr, 0, res ? 1 : 0}; }
+    Grid grid() const { return Grid{d_rb.p, tcol.p, ntcol, push ? (boxes.size() == 1 ? 2 : 1) : 0, nullptr, 0, res ? 1 : 0}; }
     // grid of the next sweep in the alternating order (see tile_index)
     Grid walk() const {
         Grid g = grid();

@@ -105,7 +105,7 @@ struct Grid {
     const RBox* boxes;
     const Tile* tiles;
     int ntiles;
-    int push;
+    int push;  // producers refresh the face ghosts they mirror; 2: the level is one box
     const int* active;
     int rev;  // walk the tiles in reverse order (see tile_index)
     int res;  // every box's colour blocks span < 2^31 bytes: 32-bit buffer addressing

@@ -245,7 +245,7 @@ struct BoxRes<float> {
 template <class T, int MODE, bool CENTRE>
 __device__ __forceinline__ int gather_res(const BoxRes<T>& U, const BoxRes<T>& Bt, const FaceArrays<T>& fa,
                                           const RBox& B, int i, int j, int k, Nbr<T>& n, bool skip_zm = false,
-                                          const BoxRes<T>* F = nullptr, T* fv = nullptr) {
+                                          const BoxRes<T>* F = nullptr, T* fv = nullptr, int* nbo = nullptr) {
     const int c = (i + j + k) & 1;
     const int row = ((k - B.glo[2]) * B.G[1] + (j - B.glo[1])) * B.H;
     const int cs = (int)B.cstride;
@@ -287,6 +287,14 @@ __device__ __forceinline__ int gather_res(const BoxRes<T>& U, const BoxRes<T>& B
         n.bzp = fa.c[2][iz + (long long)nx * ny];
     }
     n.zm = skip_zm ? n.zm : zm;
+    if (nbo) {  // the 6 neighbours' offsets, x-, x+, y-, y+, z-, z+ (face order)
+        nbo[0] = ro + mxm;
+        nbo[1] = ro + mxp;
+        nbo[2] = ro - Hy + m;
+        nbo[3] = ro + Hy + m;
+        nbo[4] = ro - Hz + m;
+        nbo[5] = ro + Hz + m;
+    }
     return idx;
 }
 
@@ -405,13 +413,38 @@ __global__ void __launch_bounds__(kBlock) k_fill_fab(T* __restrict__ data, const
     }
 }
 
+// push_ghosts() on a one-box level addressed through its buffer resource: a
+// face neighbour >= 0 is the box itself (its periodic image, the cell
+// shifted by the period), and across a Dirichlet face the ghost to write is
+// the neighbour the stencil just read, whose offset nbo[face] is at hand.
+template <class T>
+__device__ __forceinline__ void push_self(const BoxRes<T>& U, const RBox& B, int i, int j, int k, T v,
+                                          const int* nbo) {
+    const int c[3] = {i, j, k};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            if (c[d] != (side ? B.hi[d] : B.lo[d])) continue;
+            const int q = 2 * d + side;
+            if (B.nb[q] >= 0) {
+                int t[3] = {i, j, k};
+                t[d] += B.shift[q];
+                U.st(rb_off(B, t[0], t[1], t[2]), v);
+            } else {
+                U.st(nbo[q], -v);
+            }
+        }
+}
+
 // ---------------------------------------------------- red-black smoothing
 // One colour: u_c = (su - h^2 f) / sb.  Reads only the other colour of u.
 // NORM: also the residual f - (su - sb u_c) / h^2 of each updated cell, in
 // norms per tile (partials[3 tile] = max |r|, sum r^2, non-finite count):
 // after the last colour-1 sweep of a V-cycle the colour-0 cells it read are
 // final, so this is bitwise what k_resid computes for those cells.
-template <class T, int MODE, bool PUSH, bool RES, bool NORM>
+// PUSH: 0 none; 1 push_ghosts; 2 push_self (one-box level, RES).
+template <class T, int MODE, int PUSH, bool RES, bool NORM>
 __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const T* __restrict__ f,
                                               const T* __restrict__ beta, const FaceArrays<T>* __restrict__ fat,
                                               int colour, double* __restrict__ partials) {
@@ -449,8 +482,9 @@ __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const 
             nb.bzm = carry_b;
             long long idx;
             T fv;
+            int nbo[6];
             if constexpr (RES) {
-                idx = gather_res<T, MODE, false>(U, Bt, fa, B, i, j, k, nb, carry, &F, &fv);
+                idx = gather_res<T, MODE, false>(U, Bt, fa, B, i, j, k, nb, carry, &F, &fv, PUSH == 2 ? nbo : nullptr);
             } else {
                 idx = gather<T, MODE, false>(u, beta, fa, B, i, j, k, nb, carry);
                 fv = f[idx];
@@ -460,7 +494,8 @@ __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const 
             const T v = (su - h2 * fv) / sb;
             if constexpr (RES) U.st((int)idx, v);
             else u[idx] = v;
-            if constexpr (PUSH) push_ghosts(u, g.boxes, B, i, j, k, v);
+            if constexpr (PUSH == 1) push_ghosts(u, g.boxes, B, i, j, k, v);
+            if constexpr (PUSH == 2) push_self(U, B, i, j, k, v, nbo);
             if constexpr (NORM) acc_norm((double)(fv - (su - sb * v) * ih2), mx, s2, bad);
             carry = walk2;
             carry_u = nb.zp;
@@ -2093,11 +2128,17 @@ hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* be
     if (norm_partials) {  // the fused residual: FP64, pushing, buffer-addressed levels
         if constexpr (std::is_same<T, double>::value) {
             if (!g.push || !g.res) return hipErrorInvalidValue;
-#define BXMG_GSN(MODE) \
-    hipLaunchKernelGGL((k_gs<T, MODE, true, true, true>), G, B, 0, s, g, u, f, beta, fat, colour, norm_partials)
-            if (beta) BXMG_GSN(1);
-            else if (fat) BXMG_GSN(2);
-            else BXMG_GSN(0);
+#define BXMG_GSN(MODE, PUSH) \
+    hipLaunchKernelGGL((k_gs<T, MODE, PUSH, true, true>), G, B, 0, s, g, u, f, beta, fat, colour, norm_partials)
+            if (g.push == 2) {
+                if (beta) BXMG_GSN(1, 2);
+                else if (fat) BXMG_GSN(2, 2);
+                else BXMG_GSN(0, 2);
+            } else {
+                if (beta) BXMG_GSN(1, 1);
+                else if (fat) BXMG_GSN(2, 1);
+                else BXMG_GSN(0, 1);
+            }
 #undef BXMG_GSN
             return hipGetLastError();
         } else {
@@ -2108,10 +2149,12 @@ hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* be
     hipLaunchKernelGGL((k_gs<T, MODE, PUSH, RES, false>), G, B, 0, s, g, u, f, beta, fat, colour, (double*)nullptr)
 #define BXMG_GS_MODES(PUSH, RES) \
     if (beta) BXMG_GS(1, PUSH, RES); else if (fat) BXMG_GS(2, PUSH, RES); else BXMG_GS(0, PUSH, RES)
-    if (g.push) {
-        if (g.res) { BXMG_GS_MODES(true, true); } else { BXMG_GS_MODES(true, false); }
+    if (g.push == 2 && g.res) {
+        BXMG_GS_MODES(2, true);
+    } else if (g.push) {
+        if (g.res) { BXMG_GS_MODES(1, true); } else { BXMG_GS_MODES(1, false); }
     } else {
-        if (g.res) { BXMG_GS_MODES(false, true); } else { BXMG_GS_MODES(false, false); }
+        if (g.res) { BXMG_GS_MODES(0, true); } else { BXMG_GS_MODES(0, false); }
     }
 #undef BXMG_GS_MODES
 #undef BXMG_GS
