@@ -277,6 +277,7 @@ struct BLevel {
     int ntcol = 0, ntdown = 0;
     DevVec<int> cbox;
     bool push = true;
+    bool one_box = true;  // every member problem's level is one box
     int res = 1;
     int stage_values = 0;  // largest prolongation stage of the member problems' tiles
     DevVec<GhostSet> face[2], fullc;  // face ghosts of l; every ghost of l + 1
@@ -494,6 +495,7 @@ void rebuild(bxmg_batch_s* b) {
         std::vector<GhostSet> face[2], fullc;
         std::vector<ZeroRange> zr;
         B.push = true;
+        B.one_box = true;
         B.stage_values = 0;
         B.mface = B.mfullc = B.zmax = 0;
         for (int s : b->members) {
@@ -508,6 +510,7 @@ void rebuild(bxmg_batch_s* b) {
             if (l == 0) tstart.push_back((int)tcol.size());
             for (size_t q = 0; q < v.boxes.size(); ++q) cbox_full[f0 + q] = first[l + 1][s] + v.cbox[q];
             B.push = B.push && v.push;
+            B.one_box = B.one_box && v.boxes.size() == 1;
             for (int c = 0; c < 2; ++c) face[c].push_back(GhostSet{v.face[c].p, (long long)v.face[c].n, p.off, s, 0});
             B.mface = std::max(B.mface, (long long)std::max(v.face[0].n, v.face[1].n));
             const PlanLevel& w = p.plan->L[l + 1];
@@ -624,7 +627,7 @@ const CoarseCycle<float>* coarse_descs<float>(bxmg_batch_s* b) { return b->cc32.
 
 Grid level_grid(bxmg_batch_s* b, size_t l) {
     BLevel& B = b->lev[l];
-    Grid g{B.rb.p(), B.tcol.p(), B.ntcol, B.push ? 1 : 0, b->active.p, B.flip, B.res};
+    Grid g{B.rb.p(), B.tcol.p(), B.ntcol, B.push ? (B.one_box ? 2 : 1) : 0, b->active.p, B.flip, B.res};
     B.flip ^= 1;
     return g;
 }
