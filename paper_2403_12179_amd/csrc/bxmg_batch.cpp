@@ -278,14 +278,12 @@ struct BLevel {
     DevVec<int> cbox;
     bool push = true;
     bool one_box = true;  // every member problem's level is one box
+    bool coarse_self = true;  // ... and its level l + 1 one box of at most kSelfGhostCells cells
     int res = 1;
     int stage_values = 0;  // largest prolongation stage of the member problems' tiles
     DevVec<GhostSet> face[2], fullc;  // face ghosts of l; every ghost of l + 1
     int nface = 0, nfullc = 0;
     long long mface = 0, mfullc = 0;
-    DevVec<ZeroRange> zr;  // level l + 1 of the problems tiled at l
-    int nzr = 0;
-    long long zmax = 0;
     DevVec<FaceArrays<double>> fat64;  // by slot
     DevVec<FaceArrays<float>> fat32;
     int flip = 0;
@@ -487,17 +485,17 @@ void rebuild(bxmg_batch_s* b) {
         BLevel& B = b->lev[l];
         B.rb.assign(rbs[l]);
         B.res = (b->ctx->res && boxes_fit_res(rbs[l])) ? 1 : 0;
-        B.ntcol = B.ntdown = B.nface = B.nfullc = B.nzr = 0;
+        B.ntcol = B.ntdown = B.nface = B.nfullc = 0;
         if ((int)l >= b->lmax) continue;
         // tiled problems at l: colour tiles, transfer tiles, ghost sets
         std::vector<Tile> tcol, tdown;
         std::vector<int> cbox_full(rbs[l].size(), -1);
         std::vector<GhostSet> face[2], fullc;
-        std::vector<ZeroRange> zr;
         B.push = true;
         B.one_box = true;
+        B.coarse_self = true;
         B.stage_values = 0;
-        B.mface = B.mfullc = B.zmax = 0;
+        B.mface = B.mfullc = 0;
         for (int s : b->members) {
             const Problem& p = *b->slots[s];
             if ((int)l >= p.plan->cs) continue;
@@ -514,10 +512,9 @@ void rebuild(bxmg_batch_s* b) {
             for (int c = 0; c < 2; ++c) face[c].push_back(GhostSet{v.face[c].p, (long long)v.face[c].n, p.off, s, 0});
             B.mface = std::max(B.mface, (long long)std::max(v.face[0].n, v.face[1].n));
             const PlanLevel& w = p.plan->L[l + 1];
+            B.coarse_self = B.coarse_self && w.boxes.size() == 1 && w.dom.cells() <= kSelfGhostCells;
             fullc.push_back(GhostSet{w.full.p, (long long)w.full.n, p.off, s, 0});
             B.mfullc = std::max(B.mfullc, (long long)w.full.n);
-            zr.push_back(ZeroRange{p.off + w.off, w.nelem, s, 0});
-            B.zmax = std::max(B.zmax, w.nelem);
         }
         B.tcol.assign(tcol);
         B.ntcol = (int)tcol.size();
@@ -530,8 +527,6 @@ void rebuild(bxmg_batch_s* b) {
         }
         B.fullc.assign(fullc);
         B.nfullc = (int)fullc.size();
-        B.zr.assign(zr);
-        B.nzr = (int)zr.size();
     }
     b->tstart.assign(tstart);
     b->segslot.assign(segslot);
@@ -664,15 +659,20 @@ void b_vcycle(bxmg_batch_s* b, hipStream_t s) {
             HIPCHK(launch_fill_sets(s, u, f32, B.face[0].p(), B.nface, B.mface, b->active.p));
             HIPCHK(launch_fill_sets(s, u, f32, B.face[1].p(), B.nface, B.mface, b->active.p));
         }
-        HIPCHK(launch_resid_restrict<T>(s, level_xgrid(b, l), u, f, arena_beta<T>(b, l), level_fat<T>(b, l), f));
-        HIPCHK(launch_zero_ranges<T>(s, u, B.zr.p(), B.nzr, B.zmax, b->active.p));
+        // the coarse correction starts from zero: zeroed by the same launch
+        // (cells and the face ghosts mirroring them)
+        HIPCHK(launch_resid_restrict<T>(s, level_xgrid(b, l), u, f, arena_beta<T>(b, l), level_fat<T>(b, l), f, u));
     }
     HIPCHK(launch_coarse_cycle<T>(s, coarse_descs<T>(b), b->ncc, b->active.p, b->var, b->cc_lds, b->cc_all_lds));
     for (int l = b->lmax - 1; l >= 0; --l) {
         BLevel& B = b->lev[l];
-        HIPCHK(launch_fill_sets(s, u, f32, B.fullc.p(), B.nfullc, B.mfullc, b->active.p));
-        HIPCHK(launch_prolong<T>(s, level_grid(b, l), b->lev[l + 1].rb.p(), B.cbox.p(), u, u, b->P.prolong,
-                                 b->P.nu2 > 0, B.stage_values));
+        // small one-box coarse levels: the staged prolongation reads the
+        // cells their ghosts mirror, so no ghost refresh before it
+        const Grid g = level_grid(b, l);
+        const bool self = B.coarse_self && prolong_staged(g.push, b->P.nu2 > 0, B.stage_values);
+        if (!self) HIPCHK(launch_fill_sets(s, u, f32, B.fullc.p(), B.nfullc, B.mfullc, b->active.p));
+        HIPCHK(launch_prolong<T>(s, g, b->lev[l + 1].rb.p(), B.cbox.p(), u, u, b->P.prolong, b->P.nu2 > 0,
+                                 B.stage_values, self));
         b_smooth<T>(b, s, l, b->P.nu2);
     }
 }
