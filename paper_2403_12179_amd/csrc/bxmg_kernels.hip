@@ -1330,9 +1330,47 @@ __global__ void __launch_bounds__(kBlock) k_rb_to_fab(Grid g, const double* __re
     BXMG_FOR_VALID_CELLS(g, fab[fab_idx(fb[tl.box], i, j, k)] = rb[rb_idx(B, i, j, k)])
 }
 
+// ONE: a one-box, buffer-addressed level (Grid::push == 2, res): 32-bit
+// offsets and the one-box push (a ghost is the box's own cell's mirror).
+template <bool ONE>
 __global__ void __launch_bounds__(kBlock) k_add_f32(Grid g, double* __restrict__ u, const float* __restrict__ e) {
-    BXMG_FOR_VALID_CELLS(g, const long long idx = rb_idx(B, i, j, k); const double v = u[idx] + (double)e[idx];
-                         u[idx] = v; if (g.push) push_ghosts(u, g.boxes, B, i, j, k, v))
+    if constexpr (ONE) {
+        const Tile tl = g.tiles[tile_index(g.rev)];
+        const RBox B = g.boxes[tl.box];
+        if (g.active && !g.active[B.pid]) return;
+        const TileThread th = tile_thread(tl);
+        const int j = B.lo[1] + th.y;
+        if (j > B.hi[1]) return;
+        const long long ne = 2 * B.cstride;
+        const BoxRes<double> U(u + B.base, ne);
+        const BoxRes<float> E(e + B.base, ne);
+        for (int z = 0; z < (int)tl.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            if (k > B.hi[2]) break;
+            for (int c = 0; c < 2; ++c) {
+                const int i = colour_i(B, th.x, j, k, c);
+                if (i > B.hi[0]) continue;
+                const int idx = rb_off(B, i, j, k);
+                const double v = U.ld(idx) + (double)E.ld(idx);
+                U.st(idx, v);
+                // the face ghosts mirroring the cell (push_self's targets)
+                const int cc[3] = {i, j, k};
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int side = 0; side < 2; ++side) {
+                        if (cc[d] != (side ? B.hi[d] : B.lo[d])) continue;
+                        const int q = 2 * d + side;
+                        int t[3] = {i, j, k};
+                        t[d] += B.nb[q] >= 0 ? B.shift[q] : (side ? 1 : -1);
+                        U.st(rb_off(B, t[0], t[1], t[2]), B.nb[q] >= 0 ? v : -v);
+                    }
+            }
+        }
+    } else {
+        BXMG_FOR_VALID_CELLS(g, const long long idx = rb_idx(B, i, j, k); const double v = u[idx] + (double)e[idx];
+                             u[idx] = v; if (g.push) push_ghosts(u, g.boxes, B, i, j, k, v))
+    }
 }
 
 // Sum of valid cells (periodic mean projection), then subtraction.
@@ -2313,7 +2351,8 @@ hipError_t launch_rb_to_fab(hipStream_t s, const Grid& g, const double* rb, doub
 
 hipError_t launch_add_f32(hipStream_t s, const Grid& g, double* u, const float* e) {
     if (g.ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_add_f32, dim3(g.ntiles), dim3(kBlock), 0, s, g, u, e);
+    if (g.push == 2 && g.res) hipLaunchKernelGGL(k_add_f32<true>, dim3(g.ntiles), dim3(kBlock), 0, s, g, u, e);
+    else hipLaunchKernelGGL(k_add_f32<false>, dim3(g.ntiles), dim3(kBlock), 0, s, g, u, e);
     return hipGetLastError();
 }
 
