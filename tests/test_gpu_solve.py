@@ -182,6 +182,24 @@ def test_status_codes(bx):
     assert res.ok and res.cycles == 0 and not np.any(phi.to_global())
 
 
+@pytest.mark.parametrize("per,precision", [(0, 0), (1, 0), (0, 1)])
+def test_cycles_past_the_stop_change_nothing(bx, per, precision):
+    """The stop test runs on the device and the host enqueues cycles ahead of
+    it: a solve that stops at tolerance after c cycles leaves exactly the
+    iterate of c fixed cycles (the cycles enqueued past the stop do nothing),
+    with the same history."""
+    n = 64
+    f = W.uniform_rhs((n, n, n), 31, mean_zero=bool(per))
+    ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 32, (per,) * 3, f)
+    res = bx.mlmg_solve(phi, rhs, rel_tol=1e-9, precision=precision)
+    assert res.ok and res.cycles > 2
+    u = phi.to_global()
+    phi.set_val(0.0)
+    fix = bx.mlmg_solve(phi, rhs, fixed_cycles=res.cycles, precision=precision)
+    assert fix.cycles == res.cycles and fix.hist == res.hist
+    assert np.array_equal(phi.to_global(), u)
+
+
 def test_periodic_large_one_box_levels(bx, orc):
     """A periodic 192^3 domain in 64^3 boxes runs level 0 as one box: its
     prolongation leaves the face ghosts (periodic images) to a launch over
