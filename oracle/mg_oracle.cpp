@@ -25,8 +25,11 @@
 //   prolongation: trilinear cell-centred (27/9/3/1 over 64) or piecewise const
 //   coarsening : by 2 while every domain edge is even and >= 4 and every box
 //                holds whole cell pairs (even lower corner and edges); boxes
-//                are coarsened one by one while every box edge is also >= 32,
-//                else the coarse level is one box covering the domain
+//                are coarsened one by one while every box edge is also >= 4,
+//                else the coarse level is one box covering the domain.  Where boxes
+//                are merged does not change any value (the iterates do not
+//                depend on the decomposition), so the threshold is a
+//                parameter: tests run both thresholds and compare bits
 //   bottom     : FP64 conjugate gradients, rel. L2 residual 1e-12,
 //                at most 4*cells iterations; periodic: mean-zero projection
 //   stop test  : ||f - L u||_inf <= rel_tol * ||f||_inf (or <= abs_tol)
@@ -161,13 +164,15 @@ static bool pair_aligned(const std::vector<Box>& bs) {
     return true;
 }
 
-// Boxes are coarsened one by one while every box edge is at least 32 (and
-// they hold whole cell pairs); smaller boxes are merged: the coarser level is
+// Boxes are coarsened one by one while every box edge is at least min_edge
+// (default 4) and they hold whole cell pairs; otherwise the coarser level is
 // one box covering its domain.
-static bool can_coarsen_boxes(const std::vector<Box>& bs) {
+constexpr int kDefaultMinBoxEdge = 4;
+
+static bool can_coarsen_boxes(const std::vector<Box>& bs, int min_edge) {
     for (auto& b : bs)
         for (int d = 0; d < 3; ++d)
-            if (b.n(d) % 2 != 0 || b.n(d) < 32 || (b.lo[d] & 1)) return false;
+            if (b.n(d) % 2 != 0 || b.n(d) < min_edge || (b.lo[d] & 1)) return false;
     return true;
 }
 
@@ -176,7 +181,8 @@ struct Level {
     std::vector<Box> boxes;
 };
 
-static std::vector<Level> hierarchy(const Geom& g0, const std::vector<Box>& b0) {
+static std::vector<Level> hierarchy(const Geom& g0, const std::vector<Box>& b0, int min_edge = kDefaultMinBoxEdge) {
+    if (min_edge < 2) min_edge = kDefaultMinBoxEdge;
     std::vector<Level> L;
     L.push_back(Level{g0, b0});
     while (can_coarsen_domain(L.back().g.dom) && pair_aligned(L.back().boxes)) {
@@ -184,7 +190,7 @@ static std::vector<Level> hierarchy(const Geom& g0, const std::vector<Box>& b0) 
         c.g = L.back().g;
         c.g.dom = coarsen(L.back().g.dom);
         c.g.h = L.back().g.h * 2.0;
-        if (can_coarsen_boxes(L.back().boxes)) {
+        if (can_coarsen_boxes(L.back().boxes, min_edge)) {
             for (auto& b : L.back().boxes) c.boxes.push_back(coarsen(b));
         } else {
             c.boxes.push_back(c.g.dom);
@@ -588,6 +594,7 @@ static CGStats bottom_cg(const Geom& g, const std::vector<Box>& bs, const MF<dou
 struct Params {
     int nu1 = 2, nu2 = 2, max_cycles = 200, precision = 0, prolong = 2, fixed_cycles = 0;
     double rel_tol = 1e-10, abs_tol = 0.0, h = 0.0, bottom_rtol = 1e-12;
+    int min_box_edge = kDefaultMinBoxEdge;
 };
 
 // Multigrid hierarchy of storage type T: per level u, f, r and (variable
@@ -735,7 +742,7 @@ static double max_abs_valid(const MF<double>& a) {
 // V-cycle.  Status codes: 0 ok, -4 not converged, -5 non-finite.
 static int solve(const Params& P, const Geom& g0, const std::vector<Box>& b0, const double* fglob, const double* beta,
                  double* uglob, Info* info) {
-    std::vector<Level> L = hierarchy(g0, b0);
+    std::vector<Level> L = hierarchy(g0, b0, P.min_box_edge);
     std::memset(info, 0, sizeof(Info));
     info->levels = (int)L.size();
 
@@ -870,13 +877,14 @@ int orc_chop(const int* dom6, int max_box, int cap, int* out_lohi) {
     return (int)bs.size();
 }
 
-// Hierarchy of levels: per level the domain and the boxes.  Returns the
-// number of levels, or a negative count if the caps are too small.
-int orc_hierarchy(const int* dom6, int nb, const int* lohi, int cap_levels, int cap_boxes, int* lev_nb,
-                  int* lev_dom6, int* lev_lohi) {
+// Hierarchy of levels: per level the domain and the boxes (min_edge < 2:
+// the default threshold).  Returns the number of levels, or a negative count
+// if the caps are too small.
+int orc_hierarchy(const int* dom6, int nb, const int* lohi, int min_edge, int cap_levels, int cap_boxes,
+                  int* lev_nb, int* lev_dom6, int* lev_lohi) {
     const int noper[3] = {0, 0, 0};
     Geom g = geom_of(dom6, noper, 1.0);
-    std::vector<Level> L = hierarchy(g, boxes_of(nb, lohi));
+    std::vector<Level> L = hierarchy(g, boxes_of(nb, lohi), min_edge);
     int tot = 0;
     for (auto& l : L) tot += (int)l.boxes.size();
     if ((int)L.size() > cap_levels || tot > cap_boxes) return -1;
@@ -914,13 +922,15 @@ void orc_apply_bc(const int* dom6, const int* per, int nb, const int* lohi, int 
     }
 }
 
-void orc_fill_boundary_f32(const int* dom6, const int* per, int nb, const int* lohi, int ng, float* data) {
+void orc_fill_boundary_f32(const int* dom6, const int* per, int nb, const int* lohi, int ng, int ncomp, float* data) {
     MF<float> mf;
     mf.define(boxes_of(nb, lohi), ng);
     Geom g = geom_of(dom6, per, 1.0);
-    unpack(mf, data, 0, 1);
-    fill_boundary(g, mf);
-    pack(mf, data, 0, 1);
+    for (int c = 0; c < ncomp; ++c) {
+        unpack(mf, data, c, ncomp);
+        fill_boundary(g, mf);
+        pack(mf, data, c, ncomp);
+    }
 }
 
 // One red-black colour on a level (ng = 1, ghosts must be current).
@@ -1031,6 +1041,7 @@ void orc_apply_op(const int* dom6, const int* per, double h, const double* u_glo
 typedef struct {
     int nu1, nu2, max_cycles, precision, prolong, fixed_cycles;
     double rel_tol, abs_tol, h, bottom_rtol;
+    int min_box_edge;  // < 2: the default hierarchy threshold
 } orc_params;
 
 int orc_solve(const orc_params* p, const int* dom6, const int* per, int nb, const int* lohi, const double* f_glob,
@@ -1039,6 +1050,7 @@ int orc_solve(const orc_params* p, const int* dom6, const int* per, int nb, cons
     P.nu1 = p->nu1; P.nu2 = p->nu2; P.max_cycles = p->max_cycles; P.precision = p->precision;
     P.prolong = p->prolong; P.fixed_cycles = p->fixed_cycles;
     P.rel_tol = p->rel_tol; P.abs_tol = p->abs_tol; P.h = p->h; P.bottom_rtol = p->bottom_rtol;
+    P.min_box_edge = p->min_box_edge >= 2 ? p->min_box_edge : kDefaultMinBoxEdge;
     Geom g = geom_of(dom6, per, p->h);
     return solve(P, g, boxes_of(nb, lohi), f_glob, beta_glob, u_glob, info);
 }

@@ -38,7 +38,8 @@ def build(force: bool = False) -> str:
 class Params(C.Structure):
     _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("max_cycles", C.c_int), ("precision", C.c_int),
                 ("prolong", C.c_int), ("fixed_cycles", C.c_int), ("rel_tol", C.c_double),
-                ("abs_tol", C.c_double), ("h", C.c_double), ("bottom_rtol", C.c_double)]
+                ("abs_tol", C.c_double), ("h", C.c_double), ("bottom_rtol", C.c_double),
+                ("min_box_edge", C.c_int)]
 
 
 class Info(C.Structure):
@@ -133,15 +134,17 @@ def chop(dom_lo, dom_hi, max_box):
     return [(tuple(int(x) for x in out[6 * b:6 * b + 3]), tuple(int(x) for x in out[6 * b + 3:6 * b + 6])) for b in range(n)]
 
 
-def hierarchy(dom_lo, dom_hi, boxes):
-    """List of (dom_lo, dom_hi, boxes) per multigrid level."""
+def hierarchy(dom_lo, dom_hi, boxes, min_box_edge=0):
+    """List of (dom_lo, dom_hi, boxes) per multigrid level.  Boxes coarsen one
+    by one while every box edge is >= min_box_edge (0: the oracle's default,
+    4), else the coarse level is one box."""
     L = lib()
     capl, capb = 64, 1 << 20
     nb = np.zeros(capl, np.int32)
     d6 = np.zeros(capl * 6, np.int32)
     lh = np.zeros(capb * 6, np.int32)
-    nl = L.orc_hierarchy(_ip(dom6(dom_lo, dom_hi)), len(boxes), _ip(lohi_array(boxes)), capl, capb, _ip(nb),
-                         _ip(d6), _ip(lh))
+    nl = L.orc_hierarchy(_ip(dom6(dom_lo, dom_hi)), len(boxes), _ip(lohi_array(boxes)), int(min_box_edge), capl,
+                         capb, _ip(nb), _ip(d6), _ip(lh))
     assert nl > 0
     levels, o = [], 0
     for l in range(nl):
@@ -159,9 +162,8 @@ def fill_boundary(dom_lo, dom_hi, periodic, boxes, ng, packed, ncomp=1):
     L = lib()
     assert packed.flags.c_contiguous and packed.size == packed_size(boxes, ng, ncomp)
     if packed.dtype == np.float32:
-        assert ncomp == 1
         L.orc_fill_boundary_f32(_ip(dom6(dom_lo, dom_hi)), _ip(_i32(periodic)), len(boxes), _ip(lohi_array(boxes)),
-                                int(ng), _fp(packed))
+                                int(ng), int(ncomp), _fp(packed))
         return packed
     assert packed.dtype == np.float64
     L.orc_fill_boundary(_ip(dom6(dom_lo, dom_hi)), _ip(_i32(periodic)), len(boxes), _ip(lohi_array(boxes)), int(ng),
@@ -269,14 +271,16 @@ def bottom(dom_lo, dom_hi, periodic, h, f_glob, beta_glob=None, rtol=1e-12):
 
 
 def solve(dom_lo, dom_hi, periodic, boxes, f_glob, beta_glob=None, h=None, nu1=2, nu2=2, max_cycles=200,
-          precision=0, prolong=2, fixed_cycles=0, rel_tol=1e-10, abs_tol=0.0, bottom_rtol=1e-12):
-    """Full multigrid solve; returns (u_glob, info dict)."""
+          precision=0, prolong=2, fixed_cycles=0, rel_tol=1e-10, abs_tol=0.0, bottom_rtol=1e-12, min_box_edge=0):
+    """Full multigrid solve; returns (u_glob, info dict).  min_box_edge: the
+    hierarchy's box-merging threshold (0: default)."""
     L = lib()
     f = np.asfortranarray(f_glob, dtype=np.float64)
     assert f.shape == box_shape(dom_lo, dom_hi)
     if h is None:
         h = 1.0 / f.shape[0]
-    p = Params(nu1, nu2, max_cycles, precision, prolong, fixed_cycles, rel_tol, abs_tol, h, bottom_rtol)
+    p = Params(nu1, nu2, max_cycles, precision, prolong, fixed_cycles, rel_tol, abs_tol, h, bottom_rtol,
+               int(min_box_edge))
     info = Info()
     u = np.zeros(f.shape, order="F")
     b = None if beta_glob is None else np.asfortranarray(beta_glob, dtype=np.float64)

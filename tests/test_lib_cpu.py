@@ -72,11 +72,18 @@ def test_chop_matches_oracle(bx, orc, dom, mb):
     assert mine == orc.chop(dom[0], dom[1], mb)
 
 
+LIB_MIN_BOX_EDGE = 32  # the library's box-merging threshold (bxmg_boxarray_hierarchy)
+
+
 @pytest.mark.parametrize("n,mb", [(256, 32), (512, 64), (48, 32), (96, 32), (240, 32), (64, 16), (32, 32), (6, 4)])
 def test_hierarchy_matches_oracle(bx, orc, n, mb):
+    # the library merges boxes once an edge drops below 32 (the oracle's
+    # threshold is a parameter; the level domains do not depend on it)
     ba = bx.BoxArray.chop((0, 0, 0), (n - 1,) * 3, mb)
+    boxes = [(b.small, b.big) for b in ba.boxes]
     mine = [(d.small, d.big, [(b.small, b.big) for b in bl]) for d, bl in ba.hierarchy()]
-    assert mine == orc.hierarchy((0, 0, 0), (n - 1,) * 3, [(b.small, b.big) for b in ba.boxes])
+    assert mine == orc.hierarchy((0, 0, 0), (n - 1,) * 3, boxes, min_box_edge=LIB_MIN_BOX_EDGE)
+    assert [(d[0], d[1]) for d in mine] == [(d[0], d[1]) for d in orc.hierarchy((0, 0, 0), (n - 1,) * 3, boxes)]
 
 
 def test_boxarray_list_validation(bx):
@@ -125,4 +132,4 @@ def test_hierarchy_of_box_lists_matches_oracle(bx, orc, boxes):
     dhi = (max(b[1][0] for b in boxes), 7, 7)
     ba = bx.BoxArray.from_boxes(dlo, dhi, boxes)
     mine = [(d.small, d.big, [(b.small, b.big) for b in bl]) for d, bl in ba.hierarchy()]
-    assert mine == orc.hierarchy(dlo, dhi, boxes)
+    assert mine == orc.hierarchy(dlo, dhi, boxes, min_box_edge=LIB_MIN_BOX_EDGE)

@@ -59,10 +59,14 @@ def test_hierarchy_single_box_32(orc):
 
 
 def test_hierarchy_256_in_512_boxes(orc):
+    # boxes halve one by one while every box edge is even and >= 4
+    # (32, 16, 8, 4, 2); 2-cell boxes cannot halve again, so the next level
+    # is one box, which keeps halving down to the 2^3 bottom
     boxes = orc.chop((0, 0, 0), (255, 255, 255), 32)
     lv = orc.hierarchy((0, 0, 0), (255, 255, 255), boxes)
     assert [l[1][0] + 1 for l in lv] == [256, 128, 64, 32, 16, 8, 4, 2]
-    assert [len(l[2]) for l in lv] == [512, 512, 1, 1, 1, 1, 1, 1]
+    assert [len(l[2]) for l in lv] == [512, 512, 512, 512, 512, 1, 1, 1]
+    assert lv[4][2][0] == ((0, 0, 0), (1, 1, 1))
     # boxes coarsen one by one with floor division
     for (lo, hi), (clo, chi) in zip(lv[0][2], lv[1][2]):
         assert clo == tuple(x // 2 for x in lo) and chi == tuple(x // 2 for x in hi)
@@ -73,7 +77,20 @@ def test_hierarchy_negative_lower_corner(orc):
     lv = orc.hierarchy((-64, -64, -64), (63, 63, 63), boxes)
     assert lv[1][0] == (-32, -32, -32) and lv[1][1] == (31, 31, 31)
     assert sorted(lv[1][2]) == sorted(((tuple(x // 2 for x in lo), tuple(x // 2 for x in hi)) for lo, hi in boxes))
-    assert lv[2][2] == [((-16, -16, -16), (15, 15, 15))]  # 16-cell boxes are merged
+    # floor division below zero: the box [-64, -33] halves to [-32, -17]
+    assert ((-32, -32, -32), (-17, -17, -17)) in lv[1][2]
+    assert [len(l[2]) for l in lv] == [64, 64, 64, 64, 64, 1, 1]
+    assert lv[5][2] == [((-2, -2, -2), (1, 1, 1))]
+
+
+@pytest.mark.parametrize("min_edge,counts", [(32, [512, 512, 1, 1, 1, 1, 1, 1]), (8, [512, 512, 512, 512, 1, 1, 1, 1]),
+                                             (1 << 20, [512, 1, 1, 1, 1, 1, 1, 1])])
+def test_hierarchy_merge_threshold(orc, min_edge, counts):
+    # the threshold moves where boxes are merged, never the level domains
+    boxes = orc.chop((0, 0, 0), (255, 255, 255), 32)
+    lv = orc.hierarchy((0, 0, 0), (255, 255, 255), boxes, min_box_edge=min_edge)
+    assert [l[1][0] + 1 for l in lv] == [256, 128, 64, 32, 16, 8, 4, 2]
+    assert [len(l[2]) for l in lv] == counts
 
 
 @pytest.mark.parametrize("n,bottom", [(48, 3), (96, 3), (64, 2), (80, 5), (112, 7), (240, 15)])

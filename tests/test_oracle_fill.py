@@ -119,3 +119,28 @@ def test_fill_float32(orc):
     for (lo, hi), v in zip(boxes, orc.box_views(packed, boxes, 1)):
         s = tuple(slice(lo[d], hi[d] + 3) for d in range(3))
         assert np.array_equal(v, exp[s])
+
+
+@pytest.mark.parametrize("ng,ncomp,periodic", [(2, 2, (1, 0, 1)), (2, 1, (1, 1, 1)), (1, 3, (0, 1, 1))])
+def test_fill_float32_multighost_multicomp(orc, ng, ncomp, periodic):
+    # the FP32 exchange against numpy.pad, several ghost layers and components
+    dlo, dhi = (0, 0, 0), (11, 11, 7)
+    shape = (12, 12, 8)
+    boxes = orc.chop(dlo, dhi, 4)
+    comps = [W.dyadic_codes(shape, 20 + c) for c in range(ncomp)]
+    per_comp = [orc.pack(g, dlo, boxes, ng, dtype=np.float32) for g in comps]
+    packed, offs = [], [0] * ncomp
+    for lo, hi in boxes:
+        n = int(np.prod(orc.box_shape(lo, hi, ng)))
+        for c in range(ncomp):
+            packed.append(per_comp[c][offs[c]:offs[c] + n])
+            offs[c] += n
+    packed = np.ascontiguousarray(np.concatenate(packed))
+    orc.fill_boundary(dlo, dhi, periodic, boxes, ng, packed, ncomp=ncomp)
+    views = orc.box_views(packed, boxes, ng, ncomp)
+    for c in range(ncomp):
+        exp = padded_expect(comps[c], periodic, ng, False).astype(np.float32)
+        for (lo, hi), v in zip(boxes, views):
+            vv = v[..., c] if ncomp > 1 else v
+            s = tuple(slice(lo[d] - dlo[d], hi[d] - dlo[d] + 1 + 2 * ng) for d in range(3))
+            assert np.array_equal(vv, exp[s], equal_nan=True), (lo, hi, c)

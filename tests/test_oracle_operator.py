@@ -157,3 +157,109 @@ def test_residual_norms(orc):
     assert np.array_equal(rg, fg - Lu)
     assert rinf == np.abs(rg).max()
     assert np.isclose(rl2, np.sum(rg ** 2), rtol=1e-14)
+
+
+# ------------------------------------------------ variable-coefficient faces
+# Independent pins of the face rules (reading R16): a fine face between two
+# cells is the conductance of the two half cells in series, 2 / (1/a + 1/b);
+# a coarse face is the area mean of the four fine faces it covers.  Both are
+# computed here in exact rational arithmetic, not with the oracle's formula.
+from fractions import Fraction
+
+
+def _pow2_beta(shape, seed):
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(np.exp2(rng.integers(-4, 5, size=shape)).astype(np.float64))
+
+
+def _series(a, b):
+    return 2 / (1 / Fraction(a) + 1 / Fraction(b))
+
+
+def _fine_faces_exact(beta, periodic):
+    """Level-0 faces from cell beta: series conductance of the two cells; the
+    cell beyond a Dirichlet face is the boundary cell itself (no jump across
+    the wall), beyond a periodic face the wrapped cell."""
+    out = []
+    for d in range(3):
+        n = beta.shape[d]
+        shp = list(beta.shape)
+        shp[d] += 1
+        F = np.zeros(shp, order="F")
+        for idx in np.ndindex(*shp):
+            i = idx[d]
+            left = list(idx)
+            right = list(idx)
+            left[d] = i - 1
+            if i == 0:
+                left[d] = n - 1 if periodic[d] else 0
+            if i == n:
+                right[d] = 0 if periodic[d] else n - 1
+            F[idx] = float(_series(beta[tuple(left)], beta[tuple(right)]))
+        out.append(F)
+    return out
+
+
+@pytest.mark.parametrize("periodic", [(0, 0, 0), (1, 0, 1), (1, 1, 1)])
+def test_level0_faces_are_series_conductances(orc, periodic):
+    # beta = 2^k: 1/a + 1/b is exact, so the oracle's face must be the
+    # correctly rounded exact series conductance, bit for bit
+    shape = (8, 6, 4)
+    beta = _pow2_beta(shape, 5)
+    lo, hi = (0, 0, 0), tuple(s - 1 for s in shape)
+    got = orc.faces(lo, hi, periodic, [(lo, hi)], beta)[0]
+    exp = _fine_faces_exact(beta, periodic)
+    for d in range(3):
+        assert np.array_equal(got[d], exp[d]), d
+    # a wall face carries the boundary cell's own beta
+    if not periodic[0]:
+        assert np.array_equal(got[0][0], beta[0]) and np.array_equal(got[0][-1], beta[-1])
+
+
+def test_layered_coefficient_keeps_flux_continuous(orc):
+    # beta varies along x only, u is the exact flux-continuous profile of
+    # d/dx(beta du/dx) = 0 with unit flux: between two cell centres u rises
+    # by h/2 (1/beta_left + 1/beta_right).  The 7-point operator with
+    # series-conductance faces maps it to zero at every cell whose x
+    # neighbours are both interior (an arithmetic face mean does not).
+    n, ny = 16, 4
+    h = 1.0 / n
+    rng = np.random.default_rng(8)
+    b1 = np.exp2(rng.integers(-3, 4, size=n)).astype(np.float64)
+    u1 = np.zeros(n)
+    for i in range(1, n):
+        u1[i] = u1[i - 1] + 0.5 * h * (1.0 / b1[i - 1] + 1.0 / b1[i])
+    beta = np.asfortranarray(np.broadcast_to(b1[:, None, None], (n, ny, ny)).copy())
+    u = np.asfortranarray(np.broadcast_to(u1[:, None, None], (n, ny, ny)).copy())
+    Lu = orc.apply_op((0, 0, 0), (n - 1, ny - 1, ny - 1), (0, 1, 1), h, u, beta)
+    assert np.max(np.abs(Lu[1:n - 1])) <= 1e-9 / h
+    # and the flux is not zero in the mean: the walls see it
+    assert np.min(np.abs(Lu[[0, n - 1]])) > 1.0
+
+
+@pytest.mark.parametrize("periodic", [(0, 0, 0), (1, 1, 0)])
+def test_coarse_faces_are_area_means(orc, periodic):
+    # coarse face (d, I) = mean of the 4 fine d-faces at 2I whose tangential
+    # indices are (2J, 2J+1) x (2K, 2K+1); checked on levels 1 and 2 against
+    # exact rational means of the level above (the oracle rounds the three
+    # additions and the scaling: at most a few ulp)
+    n = 8
+    beta = _pow2_beta((n, n, n), 6)
+    lo, hi = (0, 0, 0), (n - 1,) * 3
+    levels = orc.faces(lo, hi, periodic, orc.chop(lo, hi, 4), beta)
+    assert len(levels) == 3
+    for l in (1, 2):
+        for d in range(3):
+            fine, coarse = levels[l - 1][d], levels[l][d]
+            t = [e for e in range(3) if e != d]
+            for idx in np.ndindex(*coarse.shape):
+                base = [2 * x for x in idx]
+                acc = Fraction(0)
+                for p in (0, 1):
+                    for q in (0, 1):
+                        c = list(base)
+                        c[t[0]] += p
+                        c[t[1]] += q
+                        acc += Fraction(fine[tuple(c)])
+                exact = acc / 4
+                assert abs(Fraction(coarse[idx]) - exact) <= abs(exact) * Fraction(1, 2 ** 50), (l, d, idx)

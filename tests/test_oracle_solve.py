@@ -137,6 +137,27 @@ def test_decomposition_independence_bitwise(orc, periodic):
             assert info["hist"] == rinfo["hist"]
 
 
+@pytest.mark.parametrize("n,mb,var", [(64, 16, False), (64, 32, True), (128, 32, False)])
+def test_merge_threshold_does_not_change_bits(orc, n, mb, var):
+    # C2-shaped problems (Dirichlet, boxes of 16^3 or 32^3, U[-1,1] right-hand
+    # side): merging boxes into one box at any level, or never above the
+    # bottom, changes where ghost cells sit, not a single value
+    lo, hi = cube(n)
+    f = W.uniform_rhs((n, n, n), 12)
+    beta = W.smooth_gaussian_beta((n, n, n), 13) if var else None
+    boxes = orc.chop(lo, hi, mb)
+    ref = None
+    for edge in (0, 8, 32, 1 << 20):
+        counts = [len(l[2]) for l in orc.hierarchy(lo, hi, boxes, min_box_edge=edge)]
+        u, info = orc.solve(lo, hi, (0, 0, 0), boxes, f, beta, fixed_cycles=2, min_box_edge=edge)
+        if ref is None:
+            ref, rinfo, rcounts = u, info, counts
+        else:
+            assert counts != rcounts  # a different hierarchy ...
+            assert np.array_equal(u, ref), edge  # ... and the same bits
+            assert info["hist"] == rinfo["hist"] and info["hist_l2"] == rinfo["hist_l2"]
+
+
 @pytest.mark.parametrize("var", [False, True])
 def test_mixed_precision_reaches_fp64_tolerance(orc, var):
     n = 32
