@@ -127,8 +127,14 @@ bxmg_status bxmg_multifab_info(bxmg_multifab mf, void** base, size_t* bytes, int
  * slab; synchronous on hip_stream (NULL = the context's stream). */
 bxmg_status bxmg_multifab_copy_host(bxmg_multifab mf, int32_t to_device, void* host, int32_t comp, void* hip_stream);
 
-/* Releases the handle.  Library-owned memory is freed after the work already
- * queued on the context's stream has completed (stream-ordered free). */
+/* Releases the handle without waiting (paper, Section 3.7: temporaries
+ * freed only after the kernels using them finish).  The device memory the
+ * library owns for it -- the slab when it allocated one, the box table, the
+ * ghost-exchange plans -- is freed in stream order on the context's stream:
+ * after the work queued there before the call.  Work that uses the MultiFab
+ * on another stream must be ordered before that point by the caller (an
+ * event the context's stream waits on) or completed.  A caller-owned slab is
+ * left alone. */
 void bxmg_multifab_release(bxmg_multifab mf);
 
 /* FillBoundary (paper, Section 2 and Section 3.5): for components
@@ -199,7 +205,9 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
  * knobs; only the work decomposition and instruction selection do.
  * param 3 = at most 2^value threads of a tile along y (0..8, default 8).
  * param 4 = the fused coarse cycle keeps its levels' data in LDS when it
- * fits (1, default) or works on device memory (0). */
+ * fits (1, default) or works on device memory (0).  param 5 = solves run a
+ * level whose boxes tile its domain as one box (1, default) or keep the
+ * caller's boxes and their ghost exchange on every level (0). */
 bxmg_status bxmg_ctx_tune(bxmg_ctx ctx, int32_t param, int32_t value);
 
 /* Launch-shape autotuner: solves the given problem for `cycles` V-cycles

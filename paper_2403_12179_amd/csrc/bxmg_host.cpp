@@ -753,10 +753,12 @@ bxmg_status bxmg_alloc_multifab(bxmg_ctx ctx, bxmg_boxarray ba, int32_t ncomp, i
         if (device_buf) {
             mf->data = device_buf;
         } else {
-            if (hipMalloc(&mf->data, std::max<size_t>(mf->bytes, 256)) != hipSuccess) return fail(BXMG_ENOMEM, "alloc_multifab: hipMalloc failed");
+            // stream-ordered, so that the release can be too
+            if (hipMallocAsync(&mf->data, std::max<size_t>(mf->bytes, 256), ctx->stream) != hipSuccess)
+                return fail(BXMG_ENOMEM, "alloc_multifab: hipMallocAsync failed");
             mf->owned = true;
         }
-        mf->d_fboxes.upload(mf->fboxes);
+        mf->d_fboxes.upload_async(mf->fboxes, ctx->stream);
     } catch (HipError& e) {
         return fail(BXMG_EDEVICE, std::string("alloc_multifab: ") + hipGetErrorString(e.e));
     }
@@ -816,10 +818,10 @@ bxmg_status bxmg_multifab_copy_host(bxmg_multifab mf, int32_t to_device, void* h
 void bxmg_multifab_release(bxmg_multifab mf) {
     if (!mf) return;
     (void)hipSetDevice(mf->ctx->device);
-    if (mf->owned) {
-        (void)hipStreamSynchronize(mf->ctx->stream);
-        (void)hipFree(mf->data);
-    }
+    const hipStream_t s = mf->ctx->stream;
+    if (mf->owned) (void)hipFreeAsync(mf->data, s);
+    mf->d_fboxes.release_async(s);
+    for (auto& kv : mf->plans) kv.second->tags.release_async(s);
     ba_release(mf->ba);
     delete mf;
 }
@@ -973,7 +975,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
     try {
         HIPCHK(hipSetDevice(ctx->device));
         st = BXMG_OK;
-        Hier* H = get_hier(ctx, ba, P.precision, beta != nullptr, h, &st);
+        Hier* H = get_hier(ctx, ba, P.precision, beta != nullptr, h, &st, ctx->merge != 0);
         if (!H) return set_status(info, st);
         info->levels = (int)H->L.size();
         Run R{H, ctx->stream, P.nu1, P.nu2, P.prolong, P.bottom_rtol};
@@ -1129,16 +1131,17 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
 
 bxmg_status bxmg_ctx_tune(bxmg_ctx ctx, int32_t param, int32_t value) {
     if (!ctx) return fail(BXMG_EINVAL, "ctx_tune: NULL context");
-    if (param < 0 || param > 4) return fail(BXMG_EINVAL, "ctx_tune: unknown parameter");
+    if (param < 0 || param > 5) return fail(BXMG_EINVAL, "ctx_tune: unknown parameter");
     if (param <= 1 && (value < 1 || value > 64)) return fail(BXMG_EINVAL, "ctx_tune: value out of range [1, 64]");
-    if ((param == 2 || param == 4) && value != 0 && value != 1) return fail(BXMG_EINVAL, "ctx_tune: value must be 0 or 1");
+    if ((param == 2 || param >= 4) && value != 0 && value != 1) return fail(BXMG_EINVAL, "ctx_tune: value must be 0 or 1");
     if (param == 3 && (value < 0 || value > 8)) return fail(BXMG_EINVAL, "ctx_tune: value out of range [0, 8]");
     std::lock_guard<std::mutex> lock(ctx->mu);
     if (param == 0) ctx->zc = value;
     else if (param == 1) ctx->zc_planes = value;
     else if (param == 2) ctx->res = value;
     else if (param == 3) ctx->ly_cap = value;
-    else ctx->lds_coarse = value;
+    else if (param == 4) ctx->lds_coarse = value;
+    else ctx->merge = value;
     return BXMG_OK;
 }
 

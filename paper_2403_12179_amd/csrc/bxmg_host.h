@@ -494,6 +494,22 @@ struct DevBuf {
         alloc(v.size());
         if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     }
+    // From the stream-ordered allocator on stream s; the stream is drained
+    // before returning, so the memory is ready for work on any stream.
+    void upload_async(const std::vector<T>& v, hipStream_t s) {
+        if (p) { (void)hipFree(p); p = nullptr; }
+        n = v.size();
+        if (v.empty()) return;
+        HIPCHK(hipMallocAsync((void**)&p, v.size() * sizeof(T), s));
+        HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    // Stream-ordered free on s: after the work queued there so far.
+    void release_async(hipStream_t s) {
+        if (p) (void)hipFreeAsync(p, s);
+        p = nullptr;
+        n = 0;
+    }
 };
 
 // Device array that keeps its allocation and only grows (no free on refill).
@@ -516,8 +532,8 @@ struct Plan {
     DevBuf<Tag> tags;
     int ntags = 0;
     long long cells = 0;
-    void set(const std::vector<Tag>& t) {
-        tags.upload(t);
+    void set(const std::vector<Tag>& t, hipStream_t s) {
+        tags.upload_async(t, s);
         ntags = (int)t.size();
         cells = tag_cells(t);
     }
@@ -584,6 +600,7 @@ struct bxmg_ctx_s {
     int res = 1;                // 32-bit buffer addressing where the boxes allow it
     int ly_cap = 8;             // at most 2^ly_cap threads of a tile along y
     int lds_coarse = 1;         // fused coarse cycle keeps its levels in LDS when they fit
+    int merge = 1;              // solves run levels that tile their domain as one box
     std::map<std::string, std::unique_ptr<Hier>> cache;  // by geometry and settings
     std::deque<std::string> lru;                          // cache keys, least recently used first
     double* h_norm = nullptr;  // pinned
@@ -632,7 +649,7 @@ inline Plan* mf_plan(bxmg_mf_s* mf, int mode, bool cross, bool odd) {
     auto it = mf->plans.find(key);
     if (it != mf->plans.end()) return it->second.get();
     auto p = std::make_unique<Plan>();
-    p->set(build_tags(mf->ba->dom, mf->ba->per, mf->ba->boxes, mf->ng, cross, mode, odd));
+    p->set(build_tags(mf->ba->dom, mf->ba->per, mf->ba->boxes, mf->ng, cross, mode, odd), mf->ctx->stream);
     Plan* raw = p.get();
     mf->plans[key] = std::move(p);
     return raw;

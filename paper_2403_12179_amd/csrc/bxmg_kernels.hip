@@ -437,12 +437,33 @@ __device__ __forceinline__ void push_self(const BoxRes<T>& U, const RBox& B, int
         }
 }
 
+// Whether cell (i,j,k) of a pushing level lies on a face of its box that is
+// a homogeneous-Dirichlet domain face (no neighbour box there).
+__device__ __forceinline__ bool on_dirichlet_face(const RBox& B, int i, int j, int k) {
+    return (i == B.lo[0] && B.nb[0] < 0) || (i == B.hi[0] && B.nb[1] < 0) || (j == B.lo[1] && B.nb[2] < 0) ||
+           (j == B.hi[1] && B.nb[3] < 0) || (k == B.lo[2] && B.nb[4] < 0) || (k == B.hi[2] && B.nb[5] < 0);
+}
+
+// The neighbour values of cell (i,j,k) that are its own ghosts beyond a
+// Dirichlet face (they mirror the cell itself), set to g.
+template <class T>
+__device__ __forceinline__ void dirichlet_self(const RBox& B, int i, int j, int k, T g, Nbr<T>& n) {
+    if (i == B.lo[0] && B.nb[0] < 0) n.xm = g;
+    if (i == B.hi[0] && B.nb[1] < 0) n.xp = g;
+    if (j == B.lo[1] && B.nb[2] < 0) n.ym = g;
+    if (j == B.hi[1] && B.nb[3] < 0) n.yp = g;
+    if (k == B.lo[2] && B.nb[4] < 0) n.zm = g;
+    if (k == B.hi[2] && B.nb[5] < 0) n.zp = g;
+}
+
 // ---------------------------------------------------- red-black smoothing
 // One colour: u_c = (su - h^2 f) / sb.  Reads only the other colour of u.
 // NORM: also the residual f - (su - sb u_c) / h^2 of each updated cell, in
 // norms per tile (partials[3 tile] = max |r|, sum r^2, non-finite count):
 // after the last colour-1 sweep of a V-cycle the colour-0 cells it read are
-// final, so this is bitwise what k_resid computes for those cells.
+// final.  A cell on a Dirichlet face read its own ghost before this sweep
+// refreshed it; its residual is formed again with the refreshed ghost, so
+// every value is bitwise what k_resid computes for the stored iterate.
 // PUSH: 0 none; 1 push_ghosts; 2 push_self (one-box level, RES).
 template <class T, int MODE, int PUSH, bool RES, bool NORM>
 __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const T* __restrict__ f,
@@ -496,7 +517,19 @@ __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const 
             else u[idx] = v;
             if constexpr (PUSH == 1) push_ghosts(u, g.boxes, B, i, j, k, v);
             if constexpr (PUSH == 2) push_self(U, B, i, j, k, v, nbo);
-            if constexpr (NORM) acc_norm((double)(fv - (su - sb * v) * ih2), mx, s2, bad);
+            if constexpr (NORM) {
+                // su read the ghost beyond a Dirichlet face before the push
+                // replaced it (-u_old -> -v); the residual of the stored
+                // iterate takes the refreshed value, summed in the same order
+                T sr = su;
+                if (on_dirichlet_face(B, i, j, k)) {
+                    Nbr<T> nr = nb;
+                    dirichlet_self(B, i, j, k, -v, nr);
+                    T sbr;
+                    sums<T, MODE>(nr, sr, sbr);
+                }
+                acc_norm((double)(fv - (sr - sb * v) * ih2), mx, s2, bad);
+            }
             carry = walk2;
             carry_u = nb.zp;
             if constexpr (MODE == 1) carry_b = nb.bzp;

@@ -319,3 +319,47 @@ def test_unit_beta_equals_constant_coefficient(bx, precision):
     phi.set_val(0.0)
     r2 = bx.mlmg_solve(phi, rhs, ones, fixed_cycles=3, precision=precision)
     assert np.array_equal(phi.to_global(), u1) and r1.hist == r2.hist
+
+
+def _tune(bx, ctx, **kw):
+    names = {"merge": 5}
+    for k, v in kw.items():
+        bx._lib.check(bx.lib().bxmg_ctx_tune(ctx._h, names[k], int(v)))
+
+
+@pytest.mark.parametrize("merge,var,spike", [(1, False, False), (1, False, True), (0, False, True),
+                                             (0, False, False), (1, True, True)])
+def test_history_is_the_residual_of_the_iterate(bx, orc, merge, var, spike):
+    """The stop test's norms (taken partly inside the last level-0 sweep of an
+    FP64 V-cycle) are those of f - L u for the iterate the cycle leaves:
+    hist[k] equals the oracle operator's max-norm of the GPU's own k-cycle
+    iterate bitwise, hist_l2 to 1e-13.  Level 0 runs as one box (merge=1,
+    ghost writes through the stencil's offsets) or as 8 boxes of 32^3 with
+    exchange into neighbour ghosts (merge=0).  With a spike of f at two
+    colour-1 corners (on three Dirichlet faces) the largest residual after
+    cycles 1 and 2 sits on such a cell, whose ghosts the last sweep refreshed
+    after reading them."""
+    n = 64
+    f = W.uniform_rhs((n, n, n), 41)
+    if spike:
+        f[n - 1, 0, 0] = 60.0
+        f[0, n - 1, 0] = -45.0
+    beta = W.smooth_gaussian_beta((n, n, n), 42) if var else None
+    ba, phi, rhs, bmf = setup(bx, (0, 0, 0), (n - 1,) * 3, 32, (0, 0, 0), f, beta)
+    _tune(bx, phi.ctx, merge=merge)
+    try:
+        for cyc in (1, 2, 3):
+            phi.set_val(0.0)
+            res = bx.mlmg_solve(phi, rhs, bmf, fixed_cycles=cyc)
+            assert res.cycles == cyc and len(res.hist) == cyc + 1
+            u = phi.to_global()
+            r = f - orc.apply_op((0, 0, 0), (n - 1,) * 3, (0, 0, 0), 1.0 / n, u, beta)
+            a = np.abs(r)
+            assert res.hist[cyc] == a.max() / np.abs(f).max(), (cyc, res.hist[cyc], a.max() / np.abs(f).max())
+            l2 = float(np.sqrt(np.sum(r * r)))
+            assert abs(res.hist_l2[cyc] - l2) <= 1e-13 * l2, (cyc, res.hist_l2[cyc], l2)
+            if spike and cyc <= 2 and not var:
+                i, j, k = np.unravel_index(np.argmax(a), a.shape)
+                assert (i + j + k) % 2 == 1 and (i in (0, n - 1) or j in (0, n - 1) or k in (0, n - 1))
+    finally:
+        _tune(bx, phi.ctx, merge=1)

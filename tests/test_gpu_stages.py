@@ -45,8 +45,6 @@ FILL_CASES = [
 @pytest.mark.parametrize("dlo,dhi,mb,per,ng,ncomp", FILL_CASES)
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_fill_boundary_bitwise(bx, orc, dlo, dhi, mb, per, ng, ncomp, dtype):
-    if dtype == "f32" and (ncomp > 1 or ng > 1):
-        pytest.skip("oracle FP32 exchange covers one component, one ghost")
     ba = make_ba(bx, dlo, dhi, mb, per)
     B = boxes_of(ba)
     shape = tuple(dhi[d] - dlo[d] + 1 for d in range(3))
@@ -222,3 +220,29 @@ def test_multifab_copy_host_roundtrip(bx):
         back = np.asfortranarray(np.zeros(shape, npdt))
         mf.copy_host(back, to_device=False, comp=1)
         assert np.array_equal(back, g)
+
+
+def test_library_owned_multifab_stream_ordered_release(bx):
+    """A MultiFab whose slab the library allocates (device_buf = NULL) takes
+    and returns data; releasing it right after enqueueing ghost exchanges on
+    the context's stream, without waiting, leaves later allocations and
+    their data intact."""
+    import ctypes as C
+    lib, ctx = bx.lib(), bx.default_context()
+    ba = bx.BoxArray.chop((0, 0, 0), (31, 23, 15), 8, bc=(bx.PERIODIC, bx.DIRICHLET0, bx.PERIODIC))
+    shape = ba.domain.size
+    for it in range(4):
+        g = np.asfortranarray(W.dyadic_codes(shape, 50 + it))
+        h = C.c_void_p()
+        bx._lib.check(lib.bxmg_alloc_multifab(ctx._h, ba._h, 2, 1, 0, None, C.byref(h)))
+        bx._lib.check(lib.bxmg_multifab_copy_host(h, 1, g.ctypes.data, 1, None))
+        for _ in range(3):
+            bx._lib.check(lib.bxmg_fill_boundary(h, 0, 2, 0, None))
+        back = np.asfortranarray(np.zeros(shape))
+        bx._lib.check(lib.bxmg_multifab_copy_host(h, 0, back.ctypes.data, 1, None))
+        assert np.array_equal(back, g)
+        for _ in range(3):
+            bx._lib.check(lib.bxmg_fill_boundary(h, 0, 2, 0, None))
+        lib.bxmg_multifab_release(h)  # exchanges may still be queued
+    import torch
+    torch.cuda.synchronize()
