@@ -153,6 +153,19 @@ bxmg_status bxmg_fill_boundary(bxmg_multifab mf, int32_t scomp, int32_t ncomp, i
  * own grown data, so call it after bxmg_fill_boundary.  Asynchronous. */
 bxmg_status bxmg_apply_domain_bc(bxmg_multifab mf, int32_t scomp, int32_t ncomp, int32_t odd, void* hip_stream);
 
+/* bxmg_fill_boundary for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same result, but the call allocates nothing
+ * on the device.  Its copy-region list is built once per MultiFab on the
+ * host and staged, on every call, into a fixed per-GPU array of 4 MiB
+ * (kept until the process ends) with an asynchronous host-to-device copy on
+ * `hip_stream`, which the exchange then reads.  EINVAL when the list needs
+ * more than 4 MiB (72 bytes per region: 58254 regions).  Every call on one GPU
+ * shares that array: calls on one stream are ordered, calls that overlap on
+ * different streams of the same GPU race and must not be issued. */
+bxmg_status bxmg_fill_boundary_noalloc(bxmg_multifab mf, int32_t scomp, int32_t ncomp, int32_t cross,
+                                       void* hip_stream);
+
 /* -------------------------------------------------------------- solve ---- */
 typedef struct {
     int32_t nu1, nu2;       /* pre/post red-black sweeps per level (2, 2)            */

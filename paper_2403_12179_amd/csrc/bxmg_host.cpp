@@ -618,6 +618,11 @@ bxmg_status bxmg_ctx_create(int device, void* hip_stream, bxmg_ctx* out) {
     auto* c = new bxmg_ctx_s();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    const hipError_t se = scratch_address(device, &c->scratch);  // with the device current
+    if (se != hipSuccess) {
+        delete c;
+        return fail(BXMG_EDEVICE, std::string("ctx_create: staging array address: ") + hipGetErrorString(se));
+    }
     if (hipHostMalloc((void**)&c->h_norm, 8 * sizeof(double)) != hipSuccess ||
         hipHostMalloc(&c->h_solve, sizeof(SolveState)) != hipSuccess) {
         if (c->h_norm) (void)hipHostFree(c->h_norm);
@@ -848,6 +853,39 @@ bxmg_status bxmg_fill_boundary(bxmg_multifab mf, int32_t scomp, int32_t ncomp, i
 
 bxmg_status bxmg_apply_domain_bc(bxmg_multifab mf, int32_t scomp, int32_t ncomp, int32_t odd, void* hip_stream) {
     return run_fill(mf, scomp, ncomp, 1, false, odd != 0, hip_stream);
+}
+
+bxmg_status bxmg_fill_boundary_noalloc(bxmg_multifab mf, int32_t scomp, int32_t ncomp, int32_t cross,
+                                       void* hip_stream) {
+    if (!mf) return fail(BXMG_EINVAL, "fill_noalloc: NULL MultiFab");
+    if (scomp < 0 || ncomp < 1 || scomp + ncomp > mf->ncomp) return fail(BXMG_EINVAL, "fill_noalloc: component range");
+    // the region list, built once per MultiFab and setting, lives on the host
+    const int key = cross ? 2 : 0;
+    auto it = mf->host_plans.find(key);
+    if (it == mf->host_plans.end()) {
+        std::vector<Tag> t = build_tags(mf->ba->dom, mf->ba->per, mf->ba->boxes, mf->ng, cross != 0, 0, false);
+        const long long cells = tag_cells(t);
+        it = mf->host_plans.emplace(key, std::make_pair(std::move(t), cells)).first;
+    }
+    const std::vector<Tag>& tags = it->second.first;
+    const size_t bytes = tags.size() * sizeof(Tag);
+    if (bytes > kScratchBytes)
+        return fail(BXMG_EINVAL, "fill_noalloc: " + std::to_string(tags.size()) + " ghost regions need " +
+                                     std::to_string(bytes) + " bytes of staging, more than the " +
+                                     std::to_string(kScratchBytes) + " available");
+    if (tags.empty()) return BXMG_OK;
+    try {
+        HIPCHK(hipSetDevice(mf->ctx->device));
+        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : mf->ctx->stream;
+        // staged in stream order: an earlier call's exchange on this stream
+        // has read its list before this copy overwrites it
+        HIPCHK(hipMemcpyAsync(mf->ctx->scratch, tags.data(), bytes, hipMemcpyHostToDevice, s));
+        HIPCHK(launch_fill_fab(s, mf->data, mf->dtype == BXMG_F32, mf->d_fboxes.p, (const Tag*)mf->ctx->scratch,
+                               (int)tags.size(), it->second.second, scomp, ncomp));
+    } catch (HipError& e) {
+        return fail(BXMG_EDEVICE, std::string("fill_noalloc: ") + hipGetErrorString(e.e));
+    }
+    return BXMG_OK;
 }
 
 void bxmg_solve_params_default(bxmg_solve_params* p) {

@@ -605,6 +605,7 @@ struct bxmg_ctx_s {
     std::deque<std::string> lru;                          // cache keys, least recently used first
     double* h_norm = nullptr;  // pinned
     void* h_solve = nullptr;   // pinned: a solve's stop-test state read back (history, slot, flag)
+    void* scratch = nullptr;   // the device's staging array (scratch_address), kScratchBytes
     std::mutex mu;
 };
 
@@ -619,6 +620,8 @@ struct bxmg_mf_s {
     std::vector<FBox> fboxes;
     DevBuf<FBox> d_fboxes;
     std::map<int, std::unique_ptr<Plan>> plans;  // key: mode*4 + cross*2 + odd
+    // region lists kept on the host only, staged per call (allocation-free calls)
+    std::map<int, std::pair<std::vector<Tag>, long long>> host_plans;
 };
 
 inline size_t mf_layout(const bxmg_ba_s* ba, int ncomp, int ng, bxmg_dtype dt, std::vector<FBox>* out) {

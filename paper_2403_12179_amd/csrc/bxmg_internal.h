@@ -311,4 +311,12 @@ struct ZeroRange {
 template <class T>
 hipError_t launch_zero_ranges(hipStream_t s, T* p, const ZeroRange* r, int n, long long max_len, const int* active);
 
+// Device memory for the allocation-free entry points: a fixed array per GPU
+// (kScratchBytes), held until the process ends.  scratch_address() returns
+// its address on `device`, which must be the current device; the first call
+// per device looks the address up, later calls return the cached value.
+constexpr size_t kScratchBytes = size_t(4) << 20;
+constexpr int kMaxScratchDevices = 64;
+hipError_t scratch_address(int device, void** out);
+
 }  // namespace bxmg

@@ -25,6 +25,8 @@
 
 #include "bxmg_internal.h"
 
+#include <mutex>
+
 namespace bxmg {
 
 // ----------------------------------------------------------------- helpers
@@ -2611,5 +2613,25 @@ hipError_t launch_zero_ranges(hipStream_t s, T* p, const ZeroRange* r, int n, lo
 }
 template hipError_t launch_zero_ranges<double>(hipStream_t, double*, const ZeroRange*, int, long long, const int*);
 template hipError_t launch_zero_ranges<float>(hipStream_t, float*, const ZeroRange*, int, long long, const int*);
+
+// ------------------------------------------------ allocation-free staging
+// One copy per GPU.  On the host this name stands for the array but is not
+// its device address: host code uses only what scratch_address() returns.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(int device, void** out) {
+    static std::mutex mu;
+    static void* addr[kMaxScratchDevices] = {};
+    if (device < 0 || device >= kMaxScratchDevices || !out) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
 
 }  // namespace bxmg
