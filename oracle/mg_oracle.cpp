@@ -595,6 +595,7 @@ struct Params {
     int nu1 = 2, nu2 = 2, max_cycles = 200, precision = 0, prolong = 2, fixed_cycles = 0;
     double rel_tol = 1e-10, abs_tol = 0.0, h = 0.0, bottom_rtol = 1e-12;
     int min_box_edge = kDefaultMinBoxEdge;
+    int krylov = 0;  // 1: conjugate gradients preconditioned by one V-cycle
 };
 
 // Multigrid hierarchy of storage type T: per level u, f, r and (variable
@@ -737,6 +738,143 @@ static double max_abs_valid(const MF<double>& a) {
     return bad ? std::nan("") : m;
 }
 
+template <class F>
+static void for_valid(const MF<double>& a, F fn) {
+    for (size_t q = 0; q < a.f.size(); ++q) {
+        const Box& B = a.f[q].bx;
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) fn(q, i, j, k);
+    }
+}
+
+// z = M r: one V(nu1, nu2) from a zero guess with r as its right-hand side,
+// in FP64 (precision 0) or in float storage and arithmetic with an FP64
+// bottom (precision 1).
+static void precondition(const Params& P, Hier<double>& H64, Hier<float>& H32, const MF<double>& r, MF<double>& z,
+                         std::vector<CGStats>* cgs) {
+    if (P.precision == 0) {
+        for_valid(r, [&](size_t q, int i, int j, int k) { H64.f[0].f[q](i, j, k) = r.f[q](i, j, k); });
+        H64.u[0].zero();
+        vcycle(H64, P, 0, cgs);
+        for_valid(r, [&](size_t q, int i, int j, int k) { z.f[q](i, j, k) = H64.u[0].f[q](i, j, k); });
+    } else {
+        for_valid(r, [&](size_t q, int i, int j, int k) { H32.f[0].f[q](i, j, k) = (float)r.f[q](i, j, k); });
+        H32.u[0].zero();
+        vcycle(H32, P, 0, cgs);
+        for_valid(r, [&](size_t q, int i, int j, int k) { z.f[q](i, j, k) = (double)H32.u[0].f[q](i, j, k); });
+    }
+}
+
+// Multigrid-preconditioned conjugate gradients for L u = f (the Krylov use
+// of the multigrid cycle among the framework's linear solvers, Section 2).
+// L is negative definite (semidefinite when fully periodic); in the SPD form
+// A = -L, b = -f the residual is -r and the preconditioned residual is
+// z = M r itself, so the signs cancel in alpha = (r.z) / (p.Lp).  The
+// V-cycle preconditioner is not exactly symmetric (both smoothing passes
+// sweep red then black, the Dirichlet ghosts lag) and in FP32 it is not
+// exactly linear, so the update of p takes the flexible (Polak-Ribiere)
+// form beta = z'.(r' - r) / (z.r) of Notay's flexible CG, which equals the
+// Fletcher-Reeves value when the preconditioner is fixed and symmetric.
+// With r' - r = -alpha q it reads beta = -alpha (z'.q) / (z.r).
+// Each iteration records the max-norm of the updated residual; when it
+// meets the tolerance the residual f - L u is computed afresh and the solve
+// stops only if that meets it too (else the iteration restarts from it).
+static int pcg(const Params& P, const Geom& g0, const std::vector<Box>& b0, Hier<double>& H64, Hier<float>& H32,
+               MF<double>& u, MF<double>& f, MF<double>& r, const Faces* fc0, double fnorm, Info* info,
+               std::vector<CGStats>* cgs, int* cycles) {
+    MF<double> z, p, q, rt;
+    z.define(b0, 0);
+    p.define(b0, 1);
+    q.define(b0, 0);
+    rt.define(b0, 1);
+    auto norms = [&](const MF<double>& a, double* rinf, double* rl2) {
+        double mx = 0.0, s2 = 0.0;
+        bool bad = false;
+        for_valid(a, [&](size_t c, int i, int j, int k) {
+            const double v = a.f[c](i, j, k);
+            const double av = std::fabs(v);
+            if (std::isnan(av)) bad = true;
+            else if (av > mx) mx = av;
+            s2 += v * v;
+        });
+        *rinf = bad ? std::nan("") : mx;
+        *rl2 = s2;
+    };
+    auto record = [&](int cyc, double rinf, double rl2) {
+        if (cyc < 256) { info->hist[cyc] = rinf / fnorm; info->hist_l2[cyc] = std::sqrt(rl2); info->nhist = cyc + 1; }
+    };
+    auto converged = [&](double rinf) { return rinf <= P.rel_tol * fnorm || rinf <= P.abs_tol; };
+    auto true_residual = [&](double* rinf, double* rl2) {
+        fill_and_bc(g0, u);
+        residual(g0, u, f, fc0, rt, nullptr, nullptr);
+        norms(rt, rinf, rl2);
+    };
+    double rinf, rl2;
+    true_residual(&rinf, &rl2);
+    for_valid(rt, [&](size_t c, int i, int j, int k) { r.f[c](i, j, k) = rt.f[c](i, j, k); });
+    record(0, rinf, rl2);
+    info->rel_inf = rinf / fnorm;
+    info->rel_l2 = std::sqrt(rl2);
+    int cyc = 0, status = 0;
+    bool restart = true;
+    double rz = 0.0;
+    for (;;) {
+        if (!std::isfinite(rinf)) { status = -5; break; }
+        if (P.fixed_cycles > 0) {
+            if (cyc == P.fixed_cycles) break;
+        } else if (converged(rinf)) {
+            break;
+        } else if (cyc == P.max_cycles) {
+            status = -4;
+            break;
+        }
+        if (restart) {  // p = z = M r
+            precondition(P, H64, H32, r, z, cgs);
+            for_valid(z, [&](size_t c, int i, int j, int k) { p.f[c](i, j, k) = z.f[c](i, j, k); });
+            rz = dot(r, z);
+            restart = false;
+        }
+        apply_op(g0, p, fc0, q);  // q = L p (fills p's ghosts)
+        const double alpha = rz / dot(p, q);
+        for_valid(r, [&](size_t c, int i, int j, int k) {
+            u.f[c](i, j, k) += alpha * p.f[c](i, j, k);
+            r.f[c](i, j, k) -= alpha * q.f[c](i, j, k);
+        });
+        ++cyc;
+        norms(r, &rinf, &rl2);
+        record(cyc, rinf, rl2);
+        info->rel_inf = rinf / fnorm;
+        info->rel_l2 = std::sqrt(rl2);
+        const bool stop = (P.fixed_cycles > 0) ? cyc == P.fixed_cycles : converged(rinf);
+        if (stop && std::isfinite(rinf)) {
+            // the updated residual says stop: check f - L u itself
+            double tinf, tl2;
+            true_residual(&tinf, &tl2);
+            info->rel_inf = tinf / fnorm;
+            info->rel_l2 = std::sqrt(tl2);
+            if (P.fixed_cycles > 0 || converged(tinf) || !std::isfinite(tinf)) {
+                rinf = tinf;
+                if (!std::isfinite(tinf)) status = -5;
+                break;
+            }
+            for_valid(rt, [&](size_t c, int i, int j, int k) { r.f[c](i, j, k) = rt.f[c](i, j, k); });
+            rinf = tinf;
+            restart = true;
+            continue;
+        }
+        if (!std::isfinite(rinf) || cyc == P.max_cycles) continue;  // decided at the top of the loop
+        precondition(P, H64, H32, r, z, cgs);
+        const double zq = dot(z, q);
+        const double rz_new = dot(r, z);
+        const double beta = -alpha * zq / rz;
+        for_valid(z, [&](size_t c, int i, int j, int k) { p.f[c](i, j, k) = z.f[c](i, j, k) + beta * p.f[c](i, j, k); });
+        rz = rz_new;
+    }
+    *cycles = cyc;
+    return status;
+}
+
 // Driver.  u starts at zero; each cycle: ghosts, residual and its norms, stop
 // test, then one V-cycle (FP64) or one refinement step around an FP32
 // V-cycle.  Status codes: 0 ok, -4 not converged, -5 non-finite.
@@ -754,12 +892,15 @@ static int solve(const Params& P, const Geom& g0, const std::vector<Box>& b0, co
     MF<double>* f;
     MF<double>* r;
     const Faces* fc0;
-    if (P.precision == 0) {
+    if (P.precision == 0 && !P.krylov) {
         H64.define(L, beta);
         u = &H64.u[0]; f = &H64.f[0]; r = &H64.r[0];
         fc0 = H64.fc(0);
     } else {
-        H32.define(L, beta);
+        // the iterate lives outside the hierarchy, whose level 0 holds the
+        // correction of the inner V-cycle
+        if (P.precision == 0) H64.define(L, beta);
+        else H32.define(L, beta);
         u_ir.define(b0, 1); f_ir.define(b0, 1); r_ir.define(b0, 1);
         u = &u_ir; f = &f_ir; r = &r_ir;
         if (beta) faces64.push_back(faces_from_beta<double>(g0, beta));
@@ -778,7 +919,9 @@ static int solve(const Params& P, const Geom& g0, const std::vector<Box>& b0, co
         return status;
     }
     int cyc = 0;
-    for (;; ++cyc) {
+    if (P.krylov) {
+        status = pcg(P, g0, b0, H64, H32, *u, *f, *r, fc0, fnorm, info, &cgs, &cyc);
+    } else for (;; ++cyc) {
         fill_and_bc(g0, *u);
         double rinf, rl2;
         residual(g0, *u, *f, fc0, *r, &rinf, &rl2);
@@ -1042,6 +1185,7 @@ typedef struct {
     int nu1, nu2, max_cycles, precision, prolong, fixed_cycles;
     double rel_tol, abs_tol, h, bottom_rtol;
     int min_box_edge;  // < 2: the default hierarchy threshold
+    int krylov;        // 1: multigrid-preconditioned conjugate gradients
 } orc_params;
 
 int orc_solve(const orc_params* p, const int* dom6, const int* per, int nb, const int* lohi, const double* f_glob,
@@ -1051,6 +1195,7 @@ int orc_solve(const orc_params* p, const int* dom6, const int* per, int nb, cons
     P.prolong = p->prolong; P.fixed_cycles = p->fixed_cycles;
     P.rel_tol = p->rel_tol; P.abs_tol = p->abs_tol; P.h = p->h; P.bottom_rtol = p->bottom_rtol;
     P.min_box_edge = p->min_box_edge >= 2 ? p->min_box_edge : kDefaultMinBoxEdge;
+    P.krylov = p->krylov;
     Geom g = geom_of(dom6, per, p->h);
     return solve(P, g, boxes_of(nb, lohi), f_glob, beta_glob, u_glob, info);
 }

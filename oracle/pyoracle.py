@@ -39,7 +39,7 @@ class Params(C.Structure):
     _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("max_cycles", C.c_int), ("precision", C.c_int),
                 ("prolong", C.c_int), ("fixed_cycles", C.c_int), ("rel_tol", C.c_double),
                 ("abs_tol", C.c_double), ("h", C.c_double), ("bottom_rtol", C.c_double),
-                ("min_box_edge", C.c_int)]
+                ("min_box_edge", C.c_int), ("krylov", C.c_int)]
 
 
 class Info(C.Structure):
@@ -271,16 +271,19 @@ def bottom(dom_lo, dom_hi, periodic, h, f_glob, beta_glob=None, rtol=1e-12):
 
 
 def solve(dom_lo, dom_hi, periodic, boxes, f_glob, beta_glob=None, h=None, nu1=2, nu2=2, max_cycles=200,
-          precision=0, prolong=2, fixed_cycles=0, rel_tol=1e-10, abs_tol=0.0, bottom_rtol=1e-12, min_box_edge=0):
+          precision=0, prolong=2, fixed_cycles=0, rel_tol=1e-10, abs_tol=0.0, bottom_rtol=1e-12, min_box_edge=0,
+          krylov=0):
     """Full multigrid solve; returns (u_glob, info dict).  min_box_edge: the
-    hierarchy's box-merging threshold (0: default)."""
+    hierarchy's box-merging threshold (0: default).  krylov=1: conjugate
+    gradients preconditioned by one V-cycle per iteration (cycles counts the
+    iterations)."""
     L = lib()
     f = np.asfortranarray(f_glob, dtype=np.float64)
     assert f.shape == box_shape(dom_lo, dom_hi)
     if h is None:
         h = 1.0 / f.shape[0]
     p = Params(nu1, nu2, max_cycles, precision, prolong, fixed_cycles, rel_tol, abs_tol, h, bottom_rtol,
-               int(min_box_edge))
+               int(min_box_edge), int(krylov))
     info = Info()
     u = np.zeros(f.shape, order="F")
     b = None if beta_glob is None else np.asfortranarray(beta_glob, dtype=np.float64)
