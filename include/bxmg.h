@@ -177,6 +177,11 @@ typedef struct {
     double abs_tol;         /*  ... or when ||f - L u||_inf <= abs_tol                 */
     double dx;              /* cell width h (cubic cells); <= 0: 1 / (x-edge of domain) */
     double bottom_rtol;     /* bottom CG relative L2 tolerance (1e-12)                 */
+    int32_t krylov;         /* 0: the V-cycles are the iteration; 1: conjugate gradients
+                               (flexible form) preconditioned by one V-cycle from zero
+                               per iteration, in the precision above (paper Section 2,
+                               linear solvers); cycles then counts CG iterations       */
+    int32_t reserved;       /* 0                                                      */
 } bxmg_solve_params;
 
 typedef struct {

@@ -27,7 +27,8 @@ class BxmgError(RuntimeError):
 class SolveParams(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("max_cycles", C.c_int32), ("precision", C.c_int32),
                 ("prolong", C.c_int32), ("fixed_cycles", C.c_int32), ("rel_tol", C.c_double),
-                ("abs_tol", C.c_double), ("dx", C.c_double), ("bottom_rtol", C.c_double)]
+                ("abs_tol", C.c_double), ("dx", C.c_double), ("bottom_rtol", C.c_double),
+                ("krylov", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

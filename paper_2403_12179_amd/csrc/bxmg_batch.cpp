@@ -770,6 +770,7 @@ bxmg_status bxmg_batch_create(bxmg_ctx ctx, size_t hbm_budget_bytes, int32_t max
     if (b->P.nu1 < 0 || b->P.nu2 < 0 || b->P.max_cycles < 0 || (b->P.precision != 0 && b->P.precision != 1) ||
         (b->P.prolong != 1 && b->P.prolong != 2))
         return fail(BXMG_EINVAL, "batch_create: bad parameters");
+    if (b->P.krylov != 0) return fail(BXMG_EINVAL, "batch_create: batches run V-cycle iterations only (krylov = 0)");
     b->var = var != 0;
     b->prec = b->P.precision;
     b->max_slots = max_problems;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <array>
 #include <atomic>
 #include <stdexcept>
@@ -135,6 +136,15 @@ struct Hier {
     DevBuf<double> hist;
     DevBuf<double> fn3;
     DevBuf<int> iters;
+    // multigrid-preconditioned CG on level 0 (allocated by its first solve):
+    // residual, two directions (read one, write the other), q = L p, the
+    // iterate and right-hand side when the FP64 V-cycle needs level 0's own
+    // arrays, per-tile partial sums, their reduction and the scalars
+    struct Krylov {
+        DevBuf<double> r, q, x, f, part, sums;
+        DevBuf<double> p[2];
+        DevBuf<KrylovScalars> sc;
+    } kr;
     size_t bytes = 0;
     XGrid xgrid(size_t l) const {
         const Level& F = *L[l];
@@ -900,6 +910,8 @@ void bxmg_solve_params_default(bxmg_solve_params* p) {
     p->abs_tol = 0.0;
     p->dx = 0.0;
     p->bottom_rtol = 1e-12;
+    p->krylov = 0;
+    p->reserved = 0;
 }
 
 static bxmg_status set_status(bxmg_solve_info* info, bxmg_status st) {
@@ -991,6 +1003,163 @@ static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var
     return raw;
 }
 
+// Multigrid-preconditioned conjugate gradients on level 0 (reading R23):
+// flexible CG, one V-cycle from zero per iteration as the preconditioner
+// (FP32 with its FP64 bottom, or FP64), every scalar on the device.  On
+// entry level 0 holds u (with current face ghosts) and f, and the slot is
+// admitted; on return u is in level 0's FP64 array and the stop test's
+// history in the slot.  Per iteration:
+//   p' = z + beta p, q = L p', alpha = rz / (p'.q)       (direction pass)
+//   u += alpha p', r -= alpha q, stop test on |r|_inf     (update pass)
+//   z = M r                                               (the V-cycle)
+//   beta = -alpha (z.q) / rz, rz = z.r                    (dot pass)
+// When the updated residual meets the tolerance, f - L u is computed afresh;
+// if that misses it, the iteration restarts from it (p = z = M r).
+static void krylov_iterate(Run& R, Hier* H, const bxmg_solve_params& P, bxmg_ctx ctx, SolveState* hs, bool var,
+                           int limit, const std::function<void()>& look, const std::function<int(int, int)>& predict,
+                           double* true_inf, double* true_l2) {
+    const Level& L0 = *H->L[0];
+    const long long n = L0.nelem;
+    Hier::Krylov& K = H->kr;
+    if (!K.r.p) {
+        K.r.alloc(n);
+        K.q.alloc(n);
+        K.p[0].alloc(n);
+        K.p[1].alloc(n);
+        K.part.alloc(3 * (size_t)std::max(L0.ntcol, 1));
+        K.sums.alloc(3);
+        K.sc.alloc(1);
+        HIPCHK(hipMemsetAsync(K.sc.p, 0, sizeof(KrylovScalars), R.s));
+        // ghosts of r are never written, q is read before its first write
+        // (a restart's dot pass discards z.q): both start at zero
+        HIPCHK(launch_zero<double>(R.s, K.r.p, n));
+        HIPCHK(launch_zero<double>(R.s, K.q.p, n));
+        H->bytes += 32 * (size_t)n;
+    }
+    const bool fp32 = P.precision == 1;
+    double* u = H->u64[0]->p;
+    double* x = u;
+    const double* f = H->f64[0]->p;
+    if (!fp32) {
+        // the FP64 V-cycle works in level 0's own arrays: the iterate and the
+        // right-hand side move out for the solve
+        if (!K.x.p) {
+            K.x.alloc(n);
+            K.f.alloc(n);
+            H->bytes += 16 * (size_t)n;
+        }
+        HIPCHK(hipMemcpyAsync(K.x.p, u, n * sizeof(double), hipMemcpyDeviceToDevice, R.s));
+        HIPCHK(hipMemcpyAsync(K.f.p, H->f64[0]->p, n * sizeof(double), hipMemcpyDeviceToDevice, R.s));
+        x = K.x.p;
+        f = K.f.p;
+    }
+    const double* b64 = var ? H->beta64.p : nullptr;
+    const FaceArrays<double>* nf = nullptr;
+    double* pc = K.p[0].p;
+    double* pn = K.p[1].p;
+    HIPCHK(launch_zero<double>(R.s, pc, n));  // beta = 0 reads it: keep it finite
+    HIPCHK(launch_zero<double>(R.s, pn, n));
+    Run R0 = R;  // the same, with launches that run whatever the stop flag says
+    R0.active = nullptr;
+    auto stop_test = [&]() {
+        HIPCHK(launch_norm_final(R.s, H->partials.p, L0.ntcol, H->fnorm.p));
+        HIPCHK(launch_batch_check(R.s, H->flags.p + 1, 1, H->fnorm.p, H->st.p, H->flags.p, H->hist.p,
+                                  H->hist.p + kHist, H->flags.p + 2));
+    };
+    auto precondition = [&]() {  // z = M r, from the right-hand side already in place
+        if (fp32) {
+            HIPCHK(launch_zero<float>(R.s, H->u32[0]->p, n, R.active));
+            vcycle<float>(R, 0);
+            fill_faces<float>(R, 0, H->u32[0]->p);
+        } else {
+            HIPCHK(launch_zero<double>(R.s, H->u64[0]->p, n, R.active));
+            vcycle<double>(R, 0);
+            fill_faces<double>(R, 0, H->u64[0]->p);
+        }
+    };
+    auto dots = [&](int step) {
+        if (fp32) HIPCHK(launch_kr_dots<float>(R.s, R.grid(L0.walk()), H->u32[0]->p, K.r.p, K.q.p, K.part.p));
+        else HIPCHK(launch_kr_dots<double>(R.s, R.grid(L0.walk()), H->u64[0]->p, K.r.p, K.q.p, K.part.p));
+        HIPCHK(launch_norm_final(R.s, K.part.p, L0.ntcol, K.sums.p));
+        HIPCHK(launch_kr_step(R.s, K.sums.p, K.sc.p, step, R.active));
+    };
+    // f - L u into r (and its norms into the partials); u's ghosts refreshed first
+    auto residual = [&](Run& Rx, const Grid& g) {
+        fill_faces<double>(Rx, 0, x);
+        HIPCHK(launch_resid<double, double>(R.s, g, x, f, b64, nf, K.r.p, H->partials.p));
+    };
+    auto restart = [&]() {  // p = z = M r
+        if (fp32) HIPCHK(launch_cast_f32(R.s, K.r.p, H->f32[0]->p, n));
+        else HIPCHK(hipMemcpyAsync(H->f64[0]->p, K.r.p, n * sizeof(double), hipMemcpyDeviceToDevice, R.s));
+        precondition();
+        dots(2);
+    };
+    auto iterate = [&]() {
+        if (fp32)
+            HIPCHK(launch_kr_direction<float>(R.s, R.grid(L0.walk()), H->u32[0]->p, pc, b64, pn, K.q.p, K.sc.p,
+                                              K.part.p));
+        else
+            HIPCHK(launch_kr_direction<double>(R.s, R.grid(L0.walk()), H->u64[0]->p, pc, b64, pn, K.q.p, K.sc.p,
+                                               K.part.p));
+        HIPCHK(launch_norm_final(R.s, K.part.p, L0.ntcol, K.sums.p));
+        HIPCHK(launch_kr_step(R.s, K.sums.p, K.sc.p, 0, R.active));
+        fill_faces<double>(R, 0, pn);
+        std::swap(pc, pn);
+        if (fp32)
+            HIPCHK(launch_kr_update<float>(R.s, R.grid(L0.walk()), x, pc, K.r.p, K.q.p, H->f32[0]->p, K.sc.p,
+                                           H->partials.p));
+        else
+            HIPCHK(launch_kr_update<double>(R.s, R.grid(L0.walk()), x, pc, K.r.p, K.q.p, H->f64[0]->p, K.sc.p,
+                                            H->partials.p));
+        stop_test();
+        precondition();
+        dots(1);
+    };
+    residual(R, R.grid(L0.walk()));
+    stop_test();
+    int queued = 0;
+    if (limit > 0) {
+        restart();
+        iterate();
+        queued = 1;
+    }
+    for (;;) {
+        look();
+        if (hs->active) {
+            const int ahead = predict(queued, limit);
+            for (int a = 0; a < ahead; ++a) {
+                iterate();
+                ++queued;
+            }
+            continue;
+        }
+        if (hs->st.status != 0 || hs->st.nhist == 0) break;  // no convergence, non-finite, or not admitted
+        // the updated residual met the test: take f - L u itself
+        residual(R0, L0.grid());
+        HIPCHK(launch_norm_final(R.s, H->partials.p, L0.ntcol, H->fnorm.p));
+        HIPCHK(hipMemcpyAsync(ctx->h_norm, H->fnorm.p, 3 * sizeof(double), hipMemcpyDeviceToHost, R.s));
+        HIPCHK(hipStreamSynchronize(R.s));
+        const double tinf = ctx->h_norm[2] > 0.0 ? (double)NAN : ctx->h_norm[0];
+        *true_inf = tinf;
+        *true_l2 = std::sqrt(ctx->h_norm[1]);
+        const double fn = hs->st.fnorm;
+        if (P.fixed_cycles > 0 || !(tinf == tinf) || tinf <= P.rel_tol * fn || tinf <= P.abs_tol) break;
+        if (hs->st.cycles >= limit) {  // no room left to restart
+            hs->st.status = BXMG_ENOCONV;
+            break;
+        }
+        // restart from the fresh residual (already in r): the slot runs on
+        hs->st.cycles += 1;
+        hs->active = 1;
+        HIPCHK(hipMemcpyAsync(H->st.p, &hs->st, sizeof(BatchSlot), hipMemcpyHostToDevice, R.s));
+        HIPCHK(hipMemcpyAsync(H->flags.p, &hs->active, sizeof(int), hipMemcpyHostToDevice, R.s));
+        restart();
+        iterate();
+        queued = hs->st.cycles;
+    }
+    if (!fp32) HIPCHK(hipMemcpyAsync(u, x, n * sizeof(double), hipMemcpyDeviceToDevice, R.s));
+}
+
 bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi, bxmg_multifab rhs,
                             bxmg_multifab beta, bxmg_solve_info* info) {
     if (!ctx || !phi || !rhs || !info) return fail(BXMG_EINVAL, "solve: NULL argument");
@@ -1005,7 +1174,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
     if (beta && (st = check_solve_mf(beta, ba, "beta")) != BXMG_OK) return set_status(info, st);
     if (!covers_domain(ba)) return set_status(info, fail(BXMG_EINVAL, "solve: the BoxArray must cover its domain"));
     if (P.nu1 < 0 || P.nu2 < 0 || P.max_cycles < 0 || (P.precision != 0 && P.precision != 1) ||
-        (P.prolong != 1 && P.prolong != 2))
+        (P.prolong != 1 && P.prolong != 2) || (P.krylov != 0 && P.krylov != 1))
         return set_status(info, fail(BXMG_EINVAL, "solve: bad parameters"));
     const double h = (P.dx > 0) ? P.dx : 1.0 / ba->dom.n(0);
     std::lock_guard<std::mutex> lock(ctx->mu);
@@ -1101,20 +1270,10 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
             HIPCHK(hipMemcpyAsync(&hs->active, H->flags.p, sizeof(int), hipMemcpyDeviceToHost, R.s));
             HIPCHK(hipStreamSynchronize(R.s));
         };
-        // queued = V-cycles enqueued; residual number c follows cycle c
-        const int limit = P.fixed_cycles > 0 ? P.fixed_cycles : P.max_cycles;
-        check(false);
-        int queued = 0;
-        if (limit > 0) {
-            check(cycle());
-            queued = 1;
-        }
-        for (;;) {
-            look();
-            if (!hs->active) break;
-            // the device wants cycle queued + 1: enqueue as many as the
-            // residual history predicts are still needed, less one, so a
-            // solve rarely runs on into cycles that do nothing
+        // cycles to enqueue ahead of the device, predicted from the history:
+        // as many as still seem needed, less one, so that a solve rarely runs
+        // on into cycles that do nothing
+        auto predict = [&](int queued, int limit) {
             int ahead = limit - queued;
             if (P.fixed_cycles <= 0) {
                 int pred = 1;
@@ -1127,10 +1286,30 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
                 }
                 ahead = std::min(ahead, pred);
             }
-            for (int a = 0; a < std::max(ahead, 1); ++a) {
+            return std::max(ahead, 1);
+        };
+        const int limit = P.fixed_cycles > 0 ? P.fixed_cycles : P.max_cycles;
+        double true_inf = -1.0, true_l2 = 0.0;  // f - L u at the end (Krylov solves), when taken
+        if (P.krylov) {
+            krylov_iterate(R, H, P, ctx, hs, beta != nullptr, limit, look, predict, &true_inf, &true_l2);
+        } else {
+        // queued = V-cycles enqueued; residual number c follows cycle c
+        check(false);
+        int queued = 0;
+        if (limit > 0) {
+            check(cycle());
+            queued = 1;
+        }
+        for (;;) {
+            look();
+            if (!hs->active) break;
+            // the device wants cycle queued + 1
+            const int ahead = predict(queued, limit);
+            for (int a = 0; a < ahead; ++a) {
                 check(cycle());
                 ++queued;
             }
+        }
         }
         const BatchSlot& Sf = hs->st;
         info->f_inf = Sf.fnorm;
@@ -1143,6 +1322,10 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         if (nh > 0) {
             info->rel_resid_inf = hs->hist[nh - 1];
             info->resid_l2 = hs->hist_l2[nh - 1];
+        }
+        if (true_inf >= 0.0 && Sf.fnorm > 0.0) {  // a Krylov solve's closing f - L u
+            info->rel_resid_inf = true_inf / Sf.fnorm;
+            info->resid_l2 = true_l2;
         }
         info->cycles = Sf.cycles;
         const int status = Sf.status;

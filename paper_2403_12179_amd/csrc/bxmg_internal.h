@@ -311,6 +311,35 @@ struct ZeroRange {
 template <class T>
 hipError_t launch_zero_ranges(hipStream_t s, T* p, const ZeroRange* r, int n, long long max_len, const int* active);
 
+// Scalars of a multigrid-preconditioned conjugate gradient solve, kept on
+// the device so that iterations need no host round trip.
+struct KrylovScalars {
+    double rz;     // r.z of the residual the current direction was built from
+    double alpha;  // step along the current direction
+    double beta;   // weight of the previous direction in the next one
+    double pq;     // p.Lp of the current direction
+};
+// p' = (double) e + beta p at every valid cell of a level (and, for the
+// stencil, its neighbours), stored in pn; q = L p'; partials[3 tile + 1] =
+// the tile's sum of p'.q.  e and p must have current face ghosts.
+template <class E>
+hipError_t launch_kr_direction(hipStream_t s, const Grid& g, const E* e, const double* p, const double* beta,
+                               double* pn, double* q, const KrylovScalars* sc, double* partials);
+// x += alpha p, r -= alpha q, rhs = (E) r at every valid cell; partials of
+// the new residual's norms as launch_resid writes them.
+template <class E>
+hipError_t launch_kr_update(hipStream_t s, const Grid& g, double* x, const double* p, double* r, const double* q,
+                            E* rhs, const KrylovScalars* sc, double* partials);
+// partials[3 tile + 1] = sum of z.q, partials[3 tile + 2] = sum of z.r with
+// z = (double) e, over every valid cell.
+template <class E>
+hipError_t launch_kr_dots(hipStream_t s, const Grid& g, const E* e, const double* r, const double* q,
+                          double* partials);
+// From reduced sums (sums3[1], sums3[2]): step 0: alpha = rz / (p.q);
+// step 1: beta = -alpha (z.q) / rz, then rz = z.r; step 2 (a restart):
+// beta = 0, rz = z.r.  Nothing while active[0] == 0.
+hipError_t launch_kr_step(hipStream_t s, const double* sums3, KrylovScalars* sc, int step, const int* active);
+
 // Device memory for the allocation-free entry points: a fixed array per GPU
 // (kScratchBytes), held until the process ends.  scratch_address() returns
 // its address on `device`, which must be the current device; the first call

@@ -2614,6 +2614,217 @@ hipError_t launch_zero_ranges(hipStream_t s, T* p, const ZeroRange* r, int n, lo
 template hipError_t launch_zero_ranges<double>(hipStream_t, double*, const ZeroRange*, int, long long, const int*);
 template hipError_t launch_zero_ranges<float>(hipStream_t, float*, const ZeroRange*, int, long long, const int*);
 
+// ------------------------------------ multigrid-preconditioned CG (level 0)
+// Both colours of the valid cells of every tile, as k_resid walks them.
+
+// p' = z + beta p, z = (double) e, at the cell and its six neighbours, then
+// q = L p' = (su - sb p'_c) / h^2 (k_resid's operation order).  The face
+// ghosts of e and p hold reflections (-v) or periodic images of cells, and
+// z + beta p of such values is exactly the same reflection or image of the
+// cell's p', so the neighbours need no refreshed p' ghosts.
+template <class E, int MODE, bool RES>
+__global__ void __launch_bounds__(kBlock) k_kr_direction(Grid g, const E* __restrict__ e,
+                                                        const double* __restrict__ p,
+                                                        const double* __restrict__ beta, double* __restrict__ pn,
+                                                        double* __restrict__ q, const KrylovScalars* __restrict__ sc,
+                                                        double* __restrict__ partials) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    double z0 = 0.0, pq = 0.0, z1 = 0.0;
+    const int tix = tile_index(g.rev);
+    const Tile tl = g.tiles[tix];
+    const RBox B = g.boxes[tl.box];
+    if (g.active && !g.active[B.pid]) return;
+    const double bs = sc->beta;
+    const double ih2 = 1.0 / (B.h * B.h);
+    const FaceArrays<double> fa{};
+    const FaceArrays<E> fe{};
+    const TileThread th = tile_thread(tl);
+    const int j = B.lo[1] + th.y;
+    const long long ne = 2 * B.cstride;
+    const BoxRes<double> P(p + B.base, ne), Bt((MODE == 1 ? beta : p) + B.base, ne);
+    const BoxRes<double> Pn(pn + B.base, ne), Q(q + B.base, ne);
+    const BoxRes<E> Ee(e + B.base, ne);
+    if (j <= B.hi[1])
+        for (int z = 0; z < (int)tl.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            if (k > B.hi[2]) break;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int i = colour_i(B, th.x, j, k, c);
+                if (i > B.hi[0]) continue;
+                Nbr<double> np;
+                Nbr<E> nz;
+                long long idx;
+                if constexpr (RES) {
+                    idx = gather_res<double, MODE, true>(P, Bt, fa, B, i, j, k, np);
+                    gather_res<E, 0, true>(Ee, Ee, fe, B, i, j, k, nz);
+                } else {
+                    idx = gather<double, MODE, true>(p, beta, fa, B, i, j, k, np);
+                    gather<E, 0, true>(e, nullptr, fe, B, i, j, k, nz);
+                }
+                Nbr<double> nn = np;
+                nn.xm = (double)nz.xm + bs * np.xm;
+                nn.xp = (double)nz.xp + bs * np.xp;
+                nn.ym = (double)nz.ym + bs * np.ym;
+                nn.yp = (double)nz.yp + bs * np.yp;
+                nn.zm = (double)nz.zm + bs * np.zm;
+                nn.zp = (double)nz.zp + bs * np.zp;
+                nn.c = (double)nz.c + bs * np.c;
+                double su, sb;
+                sums<double, MODE>(nn, su, sb);
+                const double qv = (su - sb * nn.c) * ih2;
+                if constexpr (RES) {
+                    Pn.st((int)idx, nn.c);
+                    Q.st((int)idx, qv);
+                } else {
+                    pn[idx] = nn.c;
+                    q[idx] = qv;
+                }
+                pq = pq + nn.c * qv;
+            }
+        }
+    block_reduce3(z0, pq, z1, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * tix] = 0.0;
+        partials[3 * tix + 1] = pq;
+        partials[3 * tix + 2] = 0.0;
+    }
+}
+
+// x += alpha p, r -= alpha q, rhs = (E) r; norms of the new r
+template <class E>
+__global__ void __launch_bounds__(kBlock) k_kr_update(Grid g, double* __restrict__ x, const double* __restrict__ p,
+                                                     double* __restrict__ r, const double* __restrict__ q,
+                                                     E* __restrict__ rhs, const KrylovScalars* __restrict__ sc,
+                                                     double* __restrict__ partials) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    const int tix = tile_index(g.rev);
+    const Tile tl = g.tiles[tix];
+    const RBox B = g.boxes[tl.box];
+    if (g.active && !g.active[B.pid]) return;
+    const double a = sc->alpha;
+    const TileThread th = tile_thread(tl);
+    const int j = B.lo[1] + th.y;
+    if (j <= B.hi[1])
+        for (int z = 0; z < (int)tl.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            if (k > B.hi[2]) break;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int i = colour_i(B, th.x, j, k, c);
+                if (i > B.hi[0]) continue;
+                const long long idx = rb_idx(B, i, j, k);
+                const double pv = p[idx], qv = q[idx], xv = x[idx], rv0 = r[idx];
+                x[idx] = xv + a * pv;
+                const double rv = rv0 - a * qv;
+                r[idx] = rv;
+                rhs[idx] = (E)rv;
+                acc_norm(rv, mx, s2, bad);
+            }
+        }
+    block_reduce3(mx, s2, bad, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * tix] = mx;
+        partials[3 * tix + 1] = s2;
+        partials[3 * tix + 2] = bad;
+    }
+}
+
+// sums of z.q and z.r, z = (double) e
+template <class E>
+__global__ void __launch_bounds__(kBlock) k_kr_dots(Grid g, const E* __restrict__ e, const double* __restrict__ r,
+                                                   const double* __restrict__ q, double* __restrict__ partials) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    double z0 = 0.0, zq = 0.0, zr = 0.0;
+    const int tix = tile_index(g.rev);
+    const Tile tl = g.tiles[tix];
+    const RBox B = g.boxes[tl.box];
+    if (g.active && !g.active[B.pid]) return;
+    const TileThread th = tile_thread(tl);
+    const int j = B.lo[1] + th.y;
+    if (j <= B.hi[1])
+        for (int z = 0; z < (int)tl.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            if (k > B.hi[2]) break;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int i = colour_i(B, th.x, j, k, c);
+                if (i > B.hi[0]) continue;
+                const long long idx = rb_idx(B, i, j, k);
+                const double zv = (double)e[idx];
+                zq = zq + zv * q[idx];
+                zr = zr + zv * r[idx];
+            }
+        }
+    block_reduce3(z0, zq, zr, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * tix] = 0.0;
+        partials[3 * tix + 1] = zq;
+        partials[3 * tix + 2] = zr;
+    }
+}
+
+__global__ void k_kr_step(const double* __restrict__ s3, KrylovScalars* __restrict__ sc, int step,
+                          const int* __restrict__ active) {
+    if (threadIdx.x != 0 || (active && !active[0])) return;
+    KrylovScalars S = *sc;
+    if (step == 0) {
+        S.pq = s3[1];
+        S.alpha = S.pq != 0.0 ? S.rz / S.pq : 0.0;
+    } else if (step == 1) {
+        S.beta = S.rz != 0.0 ? -S.alpha * s3[1] / S.rz : 0.0;
+        S.rz = s3[2];
+    } else {
+        S.beta = 0.0;
+        S.rz = s3[2];
+    }
+    *sc = S;
+}
+
+template <class E>
+hipError_t launch_kr_direction(hipStream_t s, const Grid& g, const E* e, const double* p, const double* beta,
+                               double* pn, double* q, const KrylovScalars* sc, double* partials) {
+    if (g.ntiles <= 0) return hipSuccess;
+    const dim3 G(g.ntiles), B(kBlock);
+#define BXMG_KRD(MODE, RES) \
+    hipLaunchKernelGGL((k_kr_direction<E, MODE, RES>), G, B, 0, s, g, e, p, beta, pn, q, sc, partials)
+    if (g.res) {
+        if (beta) BXMG_KRD(1, true); else BXMG_KRD(0, true);
+    } else {
+        if (beta) BXMG_KRD(1, false); else BXMG_KRD(0, false);
+    }
+#undef BXMG_KRD
+    return hipGetLastError();
+}
+template <class E>
+hipError_t launch_kr_update(hipStream_t s, const Grid& g, double* x, const double* p, double* r, const double* q,
+                            E* rhs, const KrylovScalars* sc, double* partials) {
+    if (g.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_kr_update<E>, dim3(g.ntiles), dim3(kBlock), 0, s, g, x, p, r, q, rhs, sc, partials);
+    return hipGetLastError();
+}
+template <class E>
+hipError_t launch_kr_dots(hipStream_t s, const Grid& g, const E* e, const double* r, const double* q,
+                          double* partials) {
+    if (g.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_kr_dots<E>, dim3(g.ntiles), dim3(kBlock), 0, s, g, e, r, q, partials);
+    return hipGetLastError();
+}
+hipError_t launch_kr_step(hipStream_t s, const double* sums3, KrylovScalars* sc, int step, const int* active) {
+    hipLaunchKernelGGL(k_kr_step, dim3(1), dim3(64), 0, s, sums3, sc, step, active);
+    return hipGetLastError();
+}
+#define BXMG_KR_INST(E)                                                                                          \
+    template hipError_t launch_kr_direction<E>(hipStream_t, const Grid&, const E*, const double*, const double*, \
+                                               double*, double*, const KrylovScalars*, double*);                 \
+    template hipError_t launch_kr_update<E>(hipStream_t, const Grid&, double*, const double*, double*,           \
+                                            const double*, E*, const KrylovScalars*, double*);                   \
+    template hipError_t launch_kr_dots<E>(hipStream_t, const Grid&, const E*, const double*, const double*, double*);
+BXMG_KR_INST(float)
+BXMG_KR_INST(double)
+#undef BXMG_KR_INST
+
 // ------------------------------------------------ allocation-free staging
 // One copy per GPU.  On the host this name stands for the array but is not
 // its device address: host code uses only what scratch_address() returns.

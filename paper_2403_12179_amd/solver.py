@@ -45,7 +45,8 @@ def mlmg_solve(phi: MultiFab, rhs: MultiFab, beta: MultiFab | None = None, raise
 
     params: nu1, nu2, max_cycles, precision (0 FP64, 1 FP32 V-cycle inside
     FP64 refinement), prolong (2 trilinear, 1 constant), fixed_cycles,
-    rel_tol, abs_tol, dx, bottom_rtol."""
+    rel_tol, abs_tol, dx, bottom_rtol, krylov (1: conjugate gradients
+    preconditioned by one V-cycle per iteration)."""
     p = solve_params(**params)
     info = L.SolveInfo()
     st = L.lib().bxmg_mlmg_solve(phi.ctx._h, C.byref(p), phi._h, rhs._h, beta._h if beta is not None else None,
