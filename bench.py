@@ -20,18 +20,32 @@ The JSON line also carries
                  sample (two V-cycles of the same problem).
 
 After the headline the same line carries, unless --sections says otherwise:
+  c1              : 32^3 periodic sine problem in one box, FP64: time per
+                    V-cycle (latency-bound; no roofline claim)
   mixed_precision : 512^3 variable coefficient in 512 boxes of 64^3, FP64
-                    V-cycles vs FP32 V-cycles inside FP64 refinement
+                    V-cycles vs FP32 V-cycles inside FP64 refinement vs
+                    conjugate gradients preconditioned by the FP32 V-cycle
   batched         : 256 periodic problems of edges 32..128, batch engine vs
                     plain FP64 solves one at a time
-  serving         : an open-loop request trace (200/s), continuous batching
-                    vs plain FP64 first-come-first-served, p50/p99 latency
+  serving         : an open-loop trace of 2000 requests (200/s), continuous
+                    batching vs plain FP64 first-come-first-served, p50/p99
+                    latency, and a sweep of the arrival rate (x0.5 .. x4)
+                    for the largest sustainable solves/s
+The CPU leg (the oracle, on the host's cores; --no-cpu-baseline skips it)
+adds to those rows: the oracle's time per cycle (C1, and the 512^3 problem
+in a background process started before the GPU work), its solves/s on the
+host's cores for a sample of the batch, and, per result of each row, the
+relative residual recomputed with the oracle's FP64 operator and the error
+against the oracle's solution (against the GPU's FP64 solution at 512^3,
+where an oracle solve would take hours).
 
 Other modes (not the benchmark line):
   --calibrate-copy          also run one elementwise kernel that reads and
                             writes 1 GiB (scales the counters)
-  --summarize-counters DIR  turn two rocprofv3 --pmc outputs into
+  --summarize-counters DIR  turn the rocprofv3 --pmc outputs under
+                            DIR/<shape>/{fetch,write} into
                             profiles/counters_gs_level0_256c512.json
+  --no-headline             run only the sections (for profiling them)
 """
 from __future__ import annotations
 
@@ -44,6 +58,8 @@ import platform
 import subprocess
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -95,40 +111,35 @@ def make_problem(bx, W):
     return ba, f, phi, rhs
 
 
-def cpu_baseline(f, cycles=2):
-    """The oracle, as it stands, on two V-cycles of the same problem."""
-    from oracle import pyoracle as orc
-    orc.build()
-    boxes = orc.chop((0, 0, 0), (N - 1,) * 3, MAX_BOX)
-    t0 = time.perf_counter()
-    u, info = orc.solve((0, 0, 0), (N - 1,) * 3, (0, 0, 0), boxes, f, fixed_cycles=cycles)
-    dt = time.perf_counter() - t0
-    model, ncpu = cpu_info()
-    return {"value": N ** 3 * cycles / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d V(2,2) cycles of the 256^3 / 512-box FP64 problem incl. setup, 1 thread, %.1f s; host %s, "
-                      "%s logical CPUs" % (cycles, dt, model, ncpu),
-            "seconds": dt}
+def shape_key(z, r, ly):
+    return "%d,%d,%d" % (z, r, ly)
 
 
-def traffic_from_counters():
+def traffic_from_counters(key):
+    """HBM bytes per level-0 GS launch for launch shape `key` (planes per
+    thread, buffer addressing, log2 tile-row cap), from the committed counter
+    summary, if it was taken on the current kernel source and that shape."""
     if not os.path.exists(COUNTERS):
         return None
     c = json.load(open(COUNTERS))
     if c.get("kernel_src_sha") != src_sha():
         return None
-    return c.get("hbm_bytes_per_launch")
+    e = c.get("shapes", {}).get(key)
+    return e.get("hbm_bytes_per_launch") if e else None
 
 
-def summarize_counters(d, knobs=""):
+def summarize_counters(d):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the level-0 GS launches
     and of the 1 GiB elementwise calibration kernel, from the rocprofv3 --pmc
-    databases under d/fetch and d/write; writes the committed summary."""
+    databases under d/<shape>/fetch and d/<shape>/write (shape directories
+    named z<Z>_r<R>_l<L>, one pair of runs per launch shape); writes the
+    committed summary."""
     import sqlite3
 
     def rows(sub, counter):
-        dbs = glob.glob(os.path.join(d, sub, "**", "*.db"), recursive=True)
+        dbs = glob.glob(os.path.join(sub, "**", "*.db"), recursive=True)
         if not dbs:
-            raise SystemExit("no rocprofv3 database under %s" % os.path.join(d, sub))
+            raise SystemExit("no rocprofv3 database under %s" % sub)
         out = []
         for db in dbs:
             con = sqlite3.connect(db)
@@ -148,25 +159,36 @@ def summarize_counters(d, knobs=""):
         return list(vals.values())
 
     out = {"kernel": GS_KERNEL, "workload": "256^3 in 512 boxes of 32^3, FP64", "kernel_src_sha": src_sha(),
-           "commands": ["cd /tmp && timeout -s KILL 300 rocprofv3 --pmc %s -d $REPO/%s/%s -o c2 -- python3 "
-                        "$REPO/bench.py --steps 1 --warmup 0 --no-cpu-baseline --sections '' --knobs %s "
-                        "--calibrate-copy" % (c, os.path.normpath(d), sub, knobs or "<autotuned>")
-                        for c, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write"))]}
-    for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
-        rs = rows(sub, counter)
-        gs = per_dispatch(rs, GS_MATCH, True)
-        cp = per_dispatch(rs, "MulFunctor", False)
-        if not gs or not cp:
-            raise SystemExit("missing dispatches for %s (gs %d, copy %d)" % (counter, len(gs), len(cp)))
-        out[counter.lower() + "_kib_per_launch"] = sum(gs) / len(gs)
-        out[counter.lower() + "_copy_kib"] = max(cp)
-        out[counter.lower() + "_launches"] = len(gs)
-    # the calibration kernel reads 1 GiB and writes 1 GiB
-    fscale = (COPY_BYTES / 1024.0) / out["fetch_size_copy_kib"]
-    wscale = (COPY_BYTES / 1024.0) / out["write_size_copy_kib"]
-    out["fetch_scale"], out["write_scale"] = fscale, wscale
-    out["hbm_bytes_per_launch"] = 1024.0 * (out["fetch_size_kib_per_launch"] * fscale +
-                                            out["write_size_kib_per_launch"] * wscale)
+           "command_per_shape": ["cd /tmp && timeout -s KILL 300 rocprofv3 --pmc %s -d $REPO/%s/z<Z>_r<R>_l<L>/%s "
+                                 "-o c2 -- python3 $REPO/bench.py --steps 1 --warmup 0 --no-cpu-baseline "
+                                 "--sections '' --knobs <Z>,<R>,<L> --calibrate-copy"
+                                 % (c, os.path.normpath(d), sub) for c, sub in (("FETCH_SIZE", "fetch"),
+                                                                                 ("WRITE_SIZE", "write"))],
+           "shapes": {}}
+    scales = []
+    for sd in sorted(glob.glob(os.path.join(d, "z*_r*_l*"))):
+        z, r, ly = (int(x[1:]) for x in os.path.basename(sd).split("_"))
+        e = {}
+        for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+            rs = rows(os.path.join(sd, sub), counter)
+            gs = per_dispatch(rs, GS_MATCH, True)
+            cp = per_dispatch(rs, "MulFunctor", False)
+            if not gs or not cp:
+                raise SystemExit("missing dispatches for %s in %s (gs %d, copy %d)" % (counter, sd, len(gs), len(cp)))
+            e[counter.lower() + "_kib_per_launch"] = sum(gs) / len(gs)
+            e[counter.lower() + "_copy_kib"] = max(cp)
+            e[counter.lower() + "_launches"] = len(gs)
+        # the calibration kernel reads 1 GiB and writes 1 GiB
+        fscale = (COPY_BYTES / 1024.0) / e["fetch_size_copy_kib"]
+        wscale = (COPY_BYTES / 1024.0) / e["write_size_copy_kib"]
+        e["fetch_scale"], e["write_scale"] = fscale, wscale
+        e["hbm_bytes_per_launch"] = 1024.0 * (e["fetch_size_kib_per_launch"] * fscale +
+                                              e["write_size_kib_per_launch"] * wscale)
+        e["traffic_over_algorithmic"] = e["hbm_bytes_per_launch"] / (GS_BYTES_PER_CELL * N ** 3)
+        out["shapes"][shape_key(z, r, ly)] = e
+        scales.append((fscale, wscale))
+    if not out["shapes"]:
+        raise SystemExit("no shape directories z<Z>_r<R>_l<L> under %s" % d)
     out["algorithmic_bytes_per_launch"] = GS_BYTES_PER_CELL * N ** 3
     os.makedirs(os.path.dirname(COUNTERS), exist_ok=True)
     json.dump(out, open(COUNTERS, "w"), indent=1)
@@ -174,11 +196,44 @@ def summarize_counters(d, knobs=""):
 
 
 # ------------------------------------------------------------ other rows
+def host(t):
+    return np.asfortranarray(t.double().cpu().numpy())
+
+
+def section_c1(bx, W, reps=20):
+    """32^3 periodic, one box, f = -3 (2 pi)^2 sin sin sin, FP64, to 1e-10:
+    time per V-cycle (the whole problem fits in the caches: latency-bound)."""
+    import torch
+    n = 32
+    f, _ = W.sine_rhs(n, periodic=True)
+    ba = bx.BoxArray.chop((0, 0, 0), (n - 1,) * 3, 32, bc=(bx.PERIODIC,) * 3)
+    phi = bx.MultiFab(ba).set_val(0.0)
+    rhs = bx.MultiFab(ba).set_val(0.0).from_global(f)
+    for _ in range(3):
+        phi.set_val(0.0)
+        bx.mlmg_solve(phi, rhs, rel_tol=TOL)
+    times = []
+    for _ in range(reps):
+        phi.set_val(0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = bx.mlmg_solve(phi, rhs, rel_tol=TOL)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    times.sort()
+    med = times[len(times) // 2]
+    out = {"workload": "poisson_periodic_32c_1box_sine_fp64_tol1e-10", "cycles": res.cycles, "ok": res.ok,
+           "ms_per_solve_median": 1000.0 * med, "us_per_cycle": 1e6 * med / max(res.cycles, 1),
+           "final_rel_resid_inf": res.rel_resid_inf}
+    keep = {"f": f, "u": phi.to_global(), "n": n}
+    return out, keep
+
+
 def section_mixed(bx, W, reps=3):
     """512^3 in 512 boxes of 64^3, Dirichlet, beta = exp(g) (g: 3 box-filter
     passes, std 1), f ~ U[-1,1]: FP64 V-cycles vs FP32 V-cycles inside FP64
-    refinement, both to 1e-10; error of the mixed solution against the FP64
-    one.  Fields drawn on the device (seeds 3 and 33)."""
+    refinement vs conjugate gradients preconditioned by the FP32 V-cycle, all
+    to 1e-10.  Fields drawn on the device (seeds 3 and 33)."""
     import torch
     n = 512
     ba = bx.BoxArray.chop((0, 0, 0), (n - 1,) * 3, 64, bc=(bx.DIRICHLET0,) * 3)
@@ -186,33 +241,34 @@ def section_mixed(bx, W, reps=3):
     beta = W.smooth_gaussian_beta_device((n, n, n), 33)
     rhs = bx.MultiFab(ba).set_val(0.0).from_tensor(f)
     bmf = bx.MultiFab(ba).set_val(1.0).from_tensor(beta)
+    keep = {"n": n, "f": host(f), "beta": host(beta), "u": {}}
     del f, beta
     phi = bx.MultiFab(ba)
     out = {"workload": "poisson_varcoef_512c_512x64c_dirichlet_tol1e-10", "boxes": len(ba)}
-    sols = {}
-    for prec in (0, 1):
+    for key, prec, kr in (("fp64", 0, 0), ("fp32_in_fp64_ir", 1, 0), ("pcg_fp32_vcycle", 1, 1)):
         times, res = [], None
         for r in range(reps + 1):
             phi.set_val(0.0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            res = bx.mlmg_solve(phi, rhs, bmf, rel_tol=TOL, precision=prec)
+            res = bx.mlmg_solve(phi, rhs, bmf, rel_tol=TOL, precision=prec, krylov=kr)
             torch.cuda.synchronize()
             if r > 0:
                 times.append(time.perf_counter() - t0)
             if not res.ok:
                 raise SystemExit("mixed-precision section: solve failed: %s" % res)
-        key = "fp64" if prec == 0 else "fp32_in_fp64_ir"
         ms = 1000.0 * min(times)
         out[key] = {"ms_per_solve": ms, "solves_per_s": 1000.0 / ms, "cycles": res.cycles,
                     "final_rel_resid_inf": res.rel_resid_inf}
-        sols[prec] = phi.slab.clone()
-    d = (sols[1] - sols[0]).abs().max().item() / sols[0].abs().max().item()
-    out["mixed_vs_fp64_rel_max_diff"] = d
+        keep["u"][key] = phi.to_global()
+    u64 = keep["u"]["fp64"]
+    for key in ("fp32_in_fp64_ir", "pcg_fp32_vcycle"):
+        out[key]["rel_max_diff_vs_gpu_fp64"] = float(np.max(np.abs(keep["u"][key] - u64)) / np.max(np.abs(u64)))
     out["speedup_mixed_over_fp64"] = out["fp64"]["ms_per_solve"] / out["fp32_in_fp64_ir"]["ms_per_solve"]
-    del sols, phi, rhs, bmf
+    out["speedup_pcg_over_fp64"] = out["fp64"]["ms_per_solve"] / out["pcg_fp32_vcycle"]["ms_per_solve"]
+    del phi, rhs, bmf
     torch.cuda.empty_cache()
-    return out
+    return out, keep
 
 
 def make_batch_problems(bx, W, nprob=256, seed=4):
@@ -221,11 +277,12 @@ def make_batch_problems(bx, W, nprob=256, seed=4):
     for p, e in enumerate(edges):
         ba = bx.BoxArray.chop((0, 0, 0), (e - 1,) * 3, 32, bc=(bx.PERIODIC,) * 3)
         f = W.uniform_rhs_device((e, e, e), 4000 + p, mean_zero=True)
-        probs.append(dict(e=e, ba=ba, phi=bx.MultiFab(ba).set_val(0.0), rhs=bx.MultiFab(ba).set_val(0.0).from_tensor(f)))
+        probs.append(dict(e=e, ba=ba, f=f, phi=bx.MultiFab(ba).set_val(0.0),
+                          rhs=bx.MultiFab(ba).set_val(0.0).from_tensor(f)))
     return probs
 
 
-def section_batched(bx, W):
+def section_batched(bx, W, nsample=4):
     """256 periodic problems, edges uniform over {32,48,64,96,128} (seed 4),
     max box 32, f ~ U[-1,1] minus its mean (seed 4000+p): the batch engine
     (FP32 V-cycles inside FP64 refinement, one launch per stage over all
@@ -248,9 +305,12 @@ def section_batched(bx, W):
         p["phi"].set_val(0.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for p in probs:
-        if b.add(p["phi"], p["rhs"], rel_tol=TOL) is None:
+    ids = {}
+    for q, p in enumerate(probs):
+        pid = b.add(p["phi"], p["rhs"], rel_tol=TOL)
+        if pid is None:
             raise SystemExit("batched section: arena too small")
+        ids[pid] = q
     t_add = time.perf_counter() - t0
     done = b.run(2)
     t_batch = time.perf_counter() - t0
@@ -258,6 +318,12 @@ def section_batched(bx, W):
     cyc = [r.cycles for _, r in done]
     worst = max(r.rel_resid_inf for _, r in done)
     b.close()
+    # the sampled problems' batched results, for the oracle's check
+    rng = np.random.default_rng(44)
+    sample = sorted(int(q) for q in rng.choice(len(probs), size=nsample, replace=False))
+    by_q = {ids[i]: r for i, r in done}
+    keep = [dict(q=q, e=probs[q]["e"], f=host(probs[q]["f"]), u=probs[q]["phi"].to_global(),
+                 cycles=by_q[q].cycles, per=(1, 1, 1), beta=None, tol=TOL) for q in sample]
     # plain FP64, one problem after another
     t0 = time.perf_counter()
     cyc64 = []
@@ -275,9 +341,10 @@ def section_batched(bx, W):
                 "fp64_cycles_mean": sum(cyc64) / len(cyc64),
                 "speedup_batched_over_fp64": t_one / t_batch,
                 "batched_cell_updates_per_s": sum(p["e"] ** 3 * c for p, c in zip(probs, cyc)) / t_batch})
+    edges = [p["e"] for p in probs]
     del probs
     torch.cuda.empty_cache()
-    return out
+    return out, keep, edges
 
 
 def stage_requests(bx, W, trace):
@@ -291,24 +358,58 @@ def stage_requests(bx, W, trace):
         if q["kind"]:
             bmf = bx.MultiFab(ba).set_val(1.0).from_tensor(W.smooth_gaussian_beta_device((e, e, e), q["seed"] + 1))
         reqs.append(dict(q=q, ba=ba, phi=bx.MultiFab(ba).set_val(0.0), rhs=rhs, beta=bmf))
+        del f
     return reqs
 
 
 def latency_stats(lat, t_first, t_last):
-    import numpy as np
     a = np.asarray(lat)
     return {"p50_ms": 1000.0 * float(np.percentile(a, 50)), "p99_ms": 1000.0 * float(np.percentile(a, 99)),
             "mean_ms": 1000.0 * float(a.mean()), "solves_per_s": len(a) / (t_last - t_first)}
 
 
-def section_serving(bx, W, nreq):
+def run_served(bx, ctx, reqs, speed):
+    """One open-loop pass of the trace through a fresh server, arrivals at
+    `speed` times the trace's rate; returns (stats, per-request results)."""
+    import torch
+    for r in reqs:
+        r["phi"].set_val(0.0)
+    srv = bx.Server(ctx, 24 << 30, max_problems=512, chunk=2, precision=1)
+    torch.cuda.synchronize()
+    nreq = len(reqs)
+    lat, res_of, ok, nxt = {}, {}, True, 0
+    t0 = time.perf_counter()
+    while len(lat) + len(srv.rejected) < nreq:
+        now = (time.perf_counter() - t0) * speed
+        while nxt < nreq and reqs[nxt]["q"]["t"] <= now:
+            r = reqs[nxt]
+            srv.submit(nxt, r["phi"], r["rhs"], r["beta"], r["q"]["tol"])
+            nxt += 1
+        if srv.idle():
+            continue
+        for tag, res, t_done in srv.pump():
+            lat[tag] = (t_done - t0) - reqs[tag]["q"]["t"] / speed
+            res_of[tag] = res
+            ok = ok and res.ok and res.rel_resid_inf <= reqs[tag]["q"]["tol"]
+    t_end = max(lat[k] + reqs[k]["q"]["t"] / speed for k in lat)
+    st = latency_stats(list(lat.values()), reqs[0]["q"]["t"] / speed, t_end)
+    st["ok"] = ok and not srv.rejected
+    st["offered_per_s"] = nreq / ((reqs[-1]["q"]["t"] - reqs[0]["q"]["t"]) / speed)
+    srv.close()
+    return st, res_of
+
+
+def section_serving(bx, W, nreq, sweep=(0.5, 2.0, 4.0), nsample=4):
     """Open-loop trace: exponential inter-arrivals of mean 5 ms (seed 5),
     edge = clamp(16 round(exp(U(ln 32, ln 256)) / 16), 32, 256), Dirichlet,
     beta constant or lognormal (1/2 each), tol 10^U(-10,-8), f ~ U[-1,1]
     (seed 5000+q); inputs staged in HBM before the clock starts.  Served:
     continuous batching (FP32 V-cycles inside FP64 refinement, admission by
-    footprint, one cycle per pump); baseline: plain FP64 solves one at a
-    time in arrival order.  Latency = completion - arrival."""
+    footprint, two cycles per pump); baseline: plain FP64 solves one at a
+    time in arrival order.  Latency = completion - arrival.  The sweep
+    replays the trace with the arrival times scaled (x0.5 .. x4 the rate)
+    through the server: a rate is sustained when the served solves/s keep
+    within 5% of the offered rate."""
     import torch
     trace = W.serving_trace(nreq, 5)
     reqs = stage_requests(bx, W, trace)
@@ -317,32 +418,34 @@ def section_serving(bx, W, nreq):
     out = {"workload": "serving_trace_%d_req_200per_s_edges_32-256_dirichlet_tol1e-8..1e-10" % nreq,
            "requests": nreq, "mean_cells": sum(r["q"]["edge"] ** 3 for r in reqs) / nreq,
            "lognormal_share": sum(r["q"]["kind"] for r in reqs) / nreq}
+    # warm-up: a few requests of each kind through a server
     srv = bx.Server(ctx, 24 << 30, max_problems=512, chunk=2, precision=1)
-    # warm-up: one request of each kind through the server
-    for r in reqs[:2]:
+    for r in reqs[:4]:
         srv.submit(-1, r["phi"], r["rhs"], r["beta"], r["q"]["tol"])
     while not srv.idle():
         srv.pump()
-    for r in reqs:
-        r["phi"].set_val(0.0)
-    torch.cuda.synchronize()
-    lat, ok, nxt = {}, True, 0
-    t0 = time.perf_counter()
-    while len(lat) + len(srv.rejected) < nreq:
-        now = time.perf_counter() - t0
-        while nxt < nreq and reqs[nxt]["q"]["t"] <= now:
-            r = reqs[nxt]
-            srv.submit(nxt, r["phi"], r["rhs"], r["beta"], r["q"]["tol"])
-            nxt += 1
-        if srv.idle():
-            continue
-        for tag, res, t_done in srv.pump():
-            lat[tag] = (t_done - t0) - reqs[tag]["q"]["t"]
-            ok = ok and res.ok and res.rel_resid_inf <= reqs[tag]["q"]["tol"]
-    t_end = max(lat[k] + reqs[k]["q"]["t"] for k in lat)
-    out["served"] = latency_stats(list(lat.values()), reqs[0]["q"]["t"], t_end)
-    out["served"]["ok"] = ok and not srv.rejected
     srv.close()
+    out["served"], res_of = run_served(bx, ctx, reqs, 1.0)
+    # the sampled requests' served results, for the oracle's check (edges
+    # up to 128, where an oracle solve takes seconds)
+    small = [q for q in range(nreq) if reqs[q]["q"]["edge"] <= 128]
+    rng = np.random.default_rng(55)
+    sample = sorted(int(q) for q in rng.choice(small, size=min(nsample, len(small)), replace=False))
+    keep = []
+    for q in sample:
+        r = reqs[q]
+        keep.append(dict(q=q, e=r["q"]["edge"], f=r["rhs"].to_global(), u=r["phi"].to_global(),
+                         beta=r["beta"].to_global() if r["beta"] is not None else None, per=(0, 0, 0),
+                         tol=r["q"]["tol"], cycles=res_of[q].cycles))
+    sw = {}
+    for speed in sweep:
+        st, _ = run_served(bx, ctx, reqs, speed)
+        sw["x%g" % speed] = st
+    sw["x1"] = out["served"]
+    sustained = [v["offered_per_s"] for v in sw.values() if v["solves_per_s"] >= 0.95 * v["offered_per_s"]]
+    out["rate_sweep"] = dict(sorted(sw.items(), key=lambda kv: kv[1]["offered_per_s"]))
+    out["max_sustained_offered_per_s"] = max(sustained) if sustained else None
+    out["max_served_solves_per_s"] = max(v["solves_per_s"] for v in sw.values())
     # baseline: FP64 solves one at a time, first come first served
     for r in reqs:
         r["phi"].set_val(0.0)
@@ -362,6 +465,142 @@ def section_serving(bx, W, nreq):
     out["p99_ratio_fcfs_over_served"] = out["fp64_fcfs"]["p99_ms"] / out["served"]["p99_ms"]
     del reqs
     torch.cuda.empty_cache()
+    return out, keep
+
+
+# ------------------------------------------------- CPU leg (the oracle)
+# Everything below runs the oracle: the baseline timings on the host's cores
+# and the check of sampled GPU results against the oracle's operator and
+# solutions.  Worker processes are started as children that never touch the
+# GPU.
+
+
+def cpu_baseline(f, cycles=2):
+    """The oracle, as it stands, on two V-cycles of the headline problem."""
+    from oracle import pyoracle as orc
+    orc.build()
+    boxes = orc.chop((0, 0, 0), (N - 1,) * 3, MAX_BOX)
+    t0 = time.perf_counter()
+    u, info = orc.solve((0, 0, 0), (N - 1,) * 3, (0, 0, 0), boxes, f, fixed_cycles=cycles)
+    dt = time.perf_counter() - t0
+    model, ncpu = cpu_info()
+    return {"value": N ** 3 * cycles / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d V(2,2) cycles of the 256^3 / 512-box FP64 problem incl. setup, 1 thread, %.1f s; host %s, "
+                      "%s logical CPUs" % (cycles, dt, model, ncpu),
+            "seconds": dt}
+
+
+def cpu_c1():
+    """The oracle's C1 solve: time per V-cycle, one thread."""
+    import workloads as W
+    from oracle import pyoracle as orc
+    orc.build()
+    n = 32
+    f, s = W.sine_rhs(n, periodic=True)
+    t0 = time.perf_counter()
+    u, info = orc.solve((0, 0, 0), (n - 1,) * 3, (1, 1, 1), orc.chop((0, 0, 0), (n - 1,) * 3, 32), f)
+    dt = time.perf_counter() - t0
+    return {"us_per_cycle": 1e6 * dt / max(info["cycles"], 1), "cycles": info["cycles"], "cores": 1,
+            "sample": "the whole 32^3 solve incl. setup, 1 thread"}, u
+
+
+def cpu_leg_c3(out_path):
+    """Child process: the oracle on the 512^3 variable-coefficient problem
+    (host draws of the same recipe, seeds 3 and 33), one thread: setup plus
+    the first residual, then the same plus one V-cycle; the difference is
+    the time per cycle."""
+    import workloads as W
+    from oracle import pyoracle as orc
+    orc.build()
+    n = 512
+    f = W.uniform_rhs((n, n, n), 3)
+    beta = W.smooth_gaussian_beta((n, n, n), 33)
+    boxes = orc.chop((0, 0, 0), (n - 1,) * 3, 64)
+    t0 = time.perf_counter()
+    orc.solve((0, 0, 0), (n - 1,) * 3, (0, 0, 0), boxes, f, beta, max_cycles=0, rel_tol=0.0)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    orc.solve((0, 0, 0), (n - 1,) * 3, (0, 0, 0), boxes, f, beta, fixed_cycles=1)
+    t_one = time.perf_counter() - t0
+    json.dump({"setup_and_residual_s": t_setup, "seconds_per_cycle": t_one - t_setup, "cores": 1,
+               "sample": "512^3 / 512 boxes of 64^3, variable beta, FP64: one V(2,2) cycle (plus its residual), "
+                         "timed as the difference of a 1-cycle and a 0-cycle solve, 1 thread"},
+              open(out_path, "w"))
+
+
+def cpu_leg_c4(problems, out_path):
+    """Child process: oracle FP64 solves (to 1e-10) of the given batch
+    problems, one after another, one thread (host draws of the same recipe)."""
+    import workloads as W
+    from oracle import pyoracle as orc
+    orc.build()
+    res = []
+    for q, e in problems:
+        f = W.uniform_rhs((e, e, e), 4000 + q, mean_zero=True)
+        t0 = time.perf_counter()
+        _, info = orc.solve((0, 0, 0), (e - 1,) * 3, (1, 1, 1), orc.chop((0, 0, 0), (e - 1,) * 3, 32), f,
+                            rel_tol=TOL)
+        res.append({"q": q, "e": e, "seconds": time.perf_counter() - t0, "cycles": info["cycles"]})
+    json.dump(res, open(out_path, "w"))
+
+
+def spawn_cpu_leg(args):
+    """Start `python bench.py --cpu-leg ...` as a child process (it never
+    initialises the GPU)."""
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__)] + args, cwd=ROOT,
+                            stdout=subprocess.DEVNULL, stderr=subprocess.PIPE, text=True)
+
+
+def cpu_c4(edges, tmpdir, budget_s=20.0):
+    """The batch on the host's cores: P worker processes (P = min(16,
+    logical CPUs)), each solving its share of a sample of the problems with
+    the oracle; CPU solves/s = solves / wall time."""
+    ncpu = os.cpu_count() or 1
+    P = max(1, min(16, ncpu))
+    # a sample of the batch in the batch's own edge mix: the first problems,
+    # sized so that the whole run stays near budget_s
+    per_cell_s = 1.2e-7 * 10  # ~10 cycles at the oracle's ~0.12 us per cell-cycle
+    take, cost = [], 0.0
+    for q, e in enumerate(edges):
+        cost += per_cell_s * e ** 3
+        take.append((q, e))
+        if cost >= budget_s * P or len(take) == len(edges):
+            break
+    shares = [take[i::P] for i in range(P)]
+    procs = []
+    t0 = time.perf_counter()
+    for i, sh in enumerate(shares):
+        if not sh:
+            continue
+        path = os.path.join(tmpdir, "c4_%d.json" % i)
+        arg = ";".join("%d,%d" % qe for qe in sh)
+        procs.append((spawn_cpu_leg(["--cpu-leg", "c4", "--cpu-problems", arg, "--cpu-out", path]), path))
+    results = []
+    for pr, path in procs:
+        pr.wait()
+        if pr.returncode != 0:
+            raise SystemExit("oracle worker failed: %s" % pr.stderr.read())
+        results += json.load(open(path))
+    wall = time.perf_counter() - t0
+    return {"solves_per_s": len(results) / wall, "solves": len(results), "cores": len(procs), "wall_s": wall,
+            "cycles_mean": sum(r["cycles"] for r in results) / len(results),
+            "sample": "the first %d of the 256 batch problems (edges %s), FP64 oracle solves to 1e-10 on %d "
+                      "processes of 1 thread" % (len(results), sorted({e for _, e in take}), len(procs))}
+
+
+def oracle_check(orc, n, per, f, beta, u, tol, solve_oracle=True, u_ref=None):
+    """P9: the relative residual of u by the oracle's FP64 operator, and the
+    relative error against the oracle's solution (or against u_ref)."""
+    dlo, dhi = (0, 0, 0), (n - 1,) * 3
+    r = f - orc.apply_op(dlo, dhi, per, 1.0 / n, u, beta)
+    out = {"oracle_rel_resid_inf": float(np.max(np.abs(r)) / np.max(np.abs(f))), "tol": tol}
+    out["meets_tol"] = out["oracle_rel_resid_inf"] <= tol
+    if solve_oracle:
+        uo, io = orc.solve(dlo, dhi, per, orc.chop(dlo, dhi, 32), f, beta, rel_tol=tol)
+        out["e_rel_vs_oracle"] = float(np.max(np.abs(u - uo)) / np.max(np.abs(uo)))
+        out["oracle_cycles"] = io["cycles"]
+    elif u_ref is not None:
+        out["e_rel_vs_gpu_fp64"] = float(np.max(np.abs(u - u_ref)) / np.max(np.abs(u_ref)))
     return out
 
 
@@ -407,19 +646,28 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--summarize-counters", metavar="DIR")
-    ap.add_argument("--knobs-used", default="",
-                    help="launch shape the counter runs used (recorded with --summarize-counters)")
-    ap.add_argument("--sections", default="mixed,batched,serving",
+    ap.add_argument("--sections", default="c1,mixed,batched,serving",
                     help="other rows to measure after the headline (comma list; '' for none)")
-    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-headline", action="store_true", help="run only the sections (profiling)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("CSV", "OUT", "COMMAND"),
                     help="write a text summary of a rocprofv3 kernel_stats.csv")
     ap.add_argument("--knobs", metavar="Z,R,L", help="planes per thread, buffer addressing (0/1), log2 tile-row cap")
+    ap.add_argument("--cpu-leg", choices=("c3", "c4"), help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-problems", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-out", help=argparse.SUPPRESS)
     args = ap.parse_args()
 
+    if args.cpu_leg == "c3":
+        cpu_leg_c3(args.cpu_out)
+        return 0
+    if args.cpu_leg == "c4":
+        probs = [tuple(int(v) for v in x.split(",")) for x in args.cpu_problems.split(";") if x]
+        cpu_leg_c4(probs, args.cpu_out)
+        return 0
     if args.summarize_counters:
-        summarize_counters(args.summarize_counters, args.knobs_used)
+        summarize_counters(args.summarize_counters)
         return 0
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
@@ -429,108 +677,164 @@ def main():
               "shard by problem across GPUs)" % args.gpus, file=sys.stderr)
         return 3
 
+    import tempfile
+    secs = [x for x in args.sections.split(",") if x]
+    cpu = not args.no_cpu_baseline and not args.no_headline
+    tmpdir = tempfile.mkdtemp(prefix="bxmg_bench_")
+    c3_proc = None
+    if cpu and "mixed" in secs:
+        # the oracle on the 512^3 problem takes minutes: in a child process
+        # on its own core while the GPU rows run
+        c3_proc = spawn_cpu_leg(["--cpu-leg", "c3", "--cpu-out", os.path.join(tmpdir, "c3.json")])
+
     import torch
     import paper_2403_12179_amd as bx
     import workloads as W
 
-    ba, f, phi, rhs = make_problem(bx, W)
-    ctx = phi.ctx
-    lib = bx.lib()
-    tuned = None
-    if args.knobs:
-        # launch shapes given explicitly (e.g. the autotuner's choice of an
-        # earlier run, so that a profiled run times exactly those launches)
-        z, r, ly = (int(x) for x in args.knobs.split(","))
+    line = {}
+    keep = {}
+    if not args.no_headline:
+        ba, f, phi, rhs = make_problem(bx, W)
+        ctx = phi.ctx
+        lib = bx.lib()
+        tuned = None
+        if args.knobs:
+            # launch shapes given explicitly (e.g. for a profiled run)
+            z, r, ly = (int(x) for x in args.knobs.split(","))
+            tuned = {"planes_per_thread": z, "buffer_addressing": r, "tile_rows_log2_cap": ly, "source": "--knobs"}
+        elif not args.no_autotune:
+            # the project autotuner picks the launch shapes on this workload
+            tuned = bx.autotune(bx.MultiFab(ba), rhs, cycles=6)
+            z, r, ly = tuned["planes_per_thread"], tuned["buffer_addressing"], tuned["tile_rows_log2_cap"]
+        else:
+            z, r, ly = 4, 1, 8
         for param, value in ((0, z), (1, z), (2, r), (3, ly)):
             bx._lib.check(lib.bxmg_ctx_tune(ctx._h, param, value))
-        tuned = {"planes_per_thread": z, "buffer_addressing": r, "tile_rows_log2_cap": ly, "source": "--knobs"}
-    elif not args.no_autotune:
-        # the project autotuner picks the launch shapes on this workload
-        tuned = bx.autotune(bx.MultiFab(ba), rhs, cycles=6)
-    for _ in range(args.warmup):
-        phi.set_val(0.0)
-        res = bx.mlmg_solve(phi, rhs, rel_tol=TOL)
-        assert res.ok, res
-    import ctypes as C
-    bx._lib.check(lib.bxmg_profile_stage(ctx._h, 0))
-    bx._lib.check(lib.bxmg_profile_read(ctx._h, None, None, 1))
-    cycles = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for step in range(args.steps):
-        phi.set_val(0.0)
-        res = bx.mlmg_solve(phi, rhs, rel_tol=TOL)
-        cycles.append(res.cycles)
-        if step == 0:
-            # the level-0 GS launches of the first timed step carry the event
-            # brackets; the later steps run without them
-            bx._lib.check(lib.bxmg_profile_stage(ctx._h, -1))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    launches = C.c_int64()
-    gs_ms = C.c_double()
-    bx._lib.check(lib.bxmg_profile_read(ctx._h, C.byref(launches), C.byref(gs_ms), 1))
-    bx._lib.check(lib.bxmg_profile_stage(ctx._h, -1))
-    if not res.ok:
-        raise SystemExit("solve failed: %s" % res)
-    if args.calibrate_copy:
-        # an elementwise kernel that reads 1 GiB and writes 1 GiB
-        a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
-        b = torch.empty_like(a)
+        for _ in range(args.warmup):
+            phi.set_val(0.0)
+            res = bx.mlmg_solve(phi, rhs, rel_tol=TOL)
+            assert res.ok, res
+        import ctypes as C
+        bx._lib.check(lib.bxmg_profile_stage(ctx._h, 0))
+        bx._lib.check(lib.bxmg_profile_read(ctx._h, None, None, 1))
+        cycles = []
         torch.cuda.synchronize()
-        torch.mul(a, 1.0, out=b)
+        t0 = time.perf_counter()
+        for step in range(args.steps):
+            phi.set_val(0.0)
+            res = bx.mlmg_solve(phi, rhs, rel_tol=TOL)
+            cycles.append(res.cycles)
+            if step == 0:
+                # the level-0 GS launches of the first timed step carry the
+                # event brackets; the later steps run without them
+                bx._lib.check(lib.bxmg_profile_stage(ctx._h, -1))
         torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        launches = C.c_int64()
+        gs_ms = C.c_double()
+        bx._lib.check(lib.bxmg_profile_read(ctx._h, C.byref(launches), C.byref(gs_ms), 1))
+        bx._lib.check(lib.bxmg_profile_stage(ctx._h, -1))
+        if not res.ok:
+            raise SystemExit("solve failed: %s" % res)
+        if args.calibrate_copy:
+            # an elementwise kernel that reads 1 GiB and writes 1 GiB
+            a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+            b = torch.empty_like(a)
+            torch.cuda.synchronize()
+            torch.mul(a, 1.0, out=b)
+            torch.cuda.synchronize()
+            del a, b
 
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    mean_cycles = sum(cycles) / len(cycles)
-    value = N ** 3 * mean_cycles / (ms_per_step / 1000.0)
-    gs_avg_ms = gs_ms.value / max(launches.value, 1)
-    gs_bytes = GS_BYTES_PER_CELL * N ** 3
-    achieved = gs_bytes / (gs_avg_ms / 1000.0) / 1e9
-    traffic = traffic_from_counters()
-    line = {
-        "metric": "V-cycle cell-updates/s + HBM GB/s; batched solves/s & p99 latency at 1e-10",
-        "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "poisson_dirichlet_256c_512x32c_fp64_vcycle22_tol1e-10", "domain": [N, N, N],
-                   "boxes": len(ba), "box": [MAX_BOX] * 3, "nghost": 1, "levels": res.levels,
-                   "cycles_per_solve": mean_cycles, "rhs": "uniform[-1,1] seed 2"},
-        "vcycle_effective_GBps": BYTES_PER_CELL_CYCLE * N ** 3 * mean_cycles / (ms_per_step / 1000.0) / 1e9,
-        "vcycle_model_bytes_per_cell": BYTES_PER_CELL_CYCLE,
-        "solves_per_s": 1000.0 / ms_per_step,
-        "autotuned_launch_shape": tuned,
-        "final_rel_resid_inf": res.rel_resid_inf,
-        "roofline": {"bound": "hbm", "kernel": GS_KERNEL + " (level 0, one colour)", "achieved": achieved,
-                     "peak": PEAK_GBPS, "unit": "GB/s", "frac": achieved / PEAK_GBPS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": gs_bytes, "avg_launch_ms": gs_avg_ms,
-                     "launches_timed": launches.value},
-    }
-    del phi, rhs
-    torch.cuda.empty_cache()
-    secs = [x for x in args.sections.split(",") if x]
+        ms_per_step = (t1 - t0) * 1000.0 / args.steps
+        mean_cycles = sum(cycles) / len(cycles)
+        value = N ** 3 * mean_cycles / (ms_per_step / 1000.0)
+        gs_avg_ms = gs_ms.value / max(launches.value, 1)
+        gs_bytes = GS_BYTES_PER_CELL * N ** 3
+        achieved = gs_bytes / (gs_avg_ms / 1000.0) / 1e9
+        key = shape_key(z, r, ly)
+        traffic = traffic_from_counters(key)
+        line = {
+            "metric": "V-cycle cell-updates/s + HBM GB/s; batched solves/s & p99 latency at 1e-10",
+            "value": value,
+            "unit": "cell-updates/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": ms_per_step,
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "poisson_dirichlet_256c_512x32c_fp64_vcycle22_tol1e-10", "domain": [N, N, N],
+                       "boxes": len(ba), "box": [MAX_BOX] * 3, "nghost": 1, "levels": res.levels,
+                       "cycles_per_solve": mean_cycles, "rhs": "uniform[-1,1] seed 2"},
+            "vcycle_effective_GBps": BYTES_PER_CELL_CYCLE * N ** 3 * mean_cycles / (ms_per_step / 1000.0) / 1e9,
+            "vcycle_model_bytes_per_cell": BYTES_PER_CELL_CYCLE,
+            "solves_per_s": 1000.0 / ms_per_step,
+            "autotuned_launch_shape": tuned,
+            "final_rel_resid_inf": res.rel_resid_inf,
+            "roofline": {"bound": "hbm", "kernel": GS_KERNEL + " (level 0, one colour)", "achieved": achieved,
+                         "peak": PEAK_GBPS, "unit": "GB/s", "frac": achieved / PEAK_GBPS, "traffic": traffic,
+                         "algorithmic_bytes_per_launch": gs_bytes, "avg_launch_ms": gs_avg_ms,
+                         "launches_timed": launches.value, "launch_shape": key},
+        }
+        del phi, rhs
+        torch.cuda.empty_cache()
     for name in secs:
         print("bench: section %s" % name, file=sys.stderr, flush=True)
-        if name == "mixed":
-            line["mixed_precision"] = section_mixed(bx, W)
+        if name == "c1":
+            line["c1"], keep["c1"] = section_c1(bx, W)
+        elif name == "mixed":
+            line["mixed_precision"], keep["mixed"] = section_mixed(bx, W)
         elif name == "batched":
-            line["batched"] = section_batched(bx, W)
+            line["batched"], keep["batched"], keep["edges"] = section_batched(bx, W)
         elif name == "serving":
-            line["serving"] = section_serving(bx, W, args.serving_requests)
+            line["serving"], keep["serving"] = section_serving(bx, W, args.serving_requests)
         else:
             raise SystemExit("unknown section %r" % name)
-    if not args.no_cpu_baseline:
+    if cpu:
+        print("bench: cpu leg", file=sys.stderr, flush=True)
         cb = cpu_baseline(f)
         cb.pop("seconds", None)
         line["cpu_baseline"] = cb
+        from oracle import pyoracle as orc
+        if "c1" in keep:
+            c1, uo = cpu_c1()
+            k = keep["c1"]
+            c1["e_rel_gpu_vs_oracle"] = float(np.max(np.abs(k["u"] - uo)) / np.max(np.abs(uo)))
+            line["c1"]["cpu_oracle"] = c1
+        if "mixed" in keep:
+            k = keep.pop("mixed")
+            chk = {}
+            for key, u in k["u"].items():
+                chk[key] = oracle_check(orc, k["n"], (0, 0, 0), k["f"], k["beta"], u, TOL, solve_oracle=False,
+                                        u_ref=None if key == "fp64" else k["u"]["fp64"])
+            line["mixed_precision"]["error_vs_oracle"] = chk
+            del k
+        if "batched" in keep:
+            line["batched"]["error_vs_oracle"] = [
+                dict(problem=s["q"], edge=s["e"], gpu_cycles=s["cycles"],
+                     **oracle_check(orc, s["e"], s["per"], s["f"], s["beta"], s["u"], s["tol"]))
+                for s in keep.pop("batched")]
+            line["batched"]["cpu_oracle"] = cpu_c4(keep["edges"], tmpdir)
+        if "serving" in keep:
+            line["serving"]["error_vs_oracle"] = [
+                dict(request=s["q"], edge=s["e"], lognormal_beta=s["beta"] is not None, gpu_cycles=s["cycles"],
+                     **oracle_check(orc, s["e"], s["per"], s["f"], s["beta"], s["u"], s["tol"]))
+                for s in keep.pop("serving")]
+        if c3_proc is not None:
+            try:
+                c3_proc.wait(timeout=600)
+            except subprocess.TimeoutExpired:
+                c3_proc.kill()
+            path = os.path.join(tmpdir, "c3.json")
+            if c3_proc.returncode == 0 and os.path.exists(path):
+                line["mixed_precision"]["cpu_oracle"] = json.load(open(path))
+            else:
+                line["mixed_precision"]["cpu_oracle"] = {"error": "oracle child failed or timed out"}
+    elif c3_proc is not None:
+        c3_proc.kill()
     print(json.dumps(line), flush=True)
     return 0
 
