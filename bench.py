@@ -162,11 +162,11 @@ def summarize_counters(d):
            "command_per_shape": ["cd /tmp && timeout -s KILL 300 rocprofv3 --pmc %s -d $REPO/%s/z<Z>_r<R>_l<L>/%s "
                                  "-o c2 -- python3 $REPO/bench.py --steps 1 --warmup 0 --no-cpu-baseline "
                                  "--sections '' --knobs <Z>,<R>,<L> --calibrate-copy"
-                                 % (c, os.path.normpath(d), sub) for c, sub in (("FETCH_SIZE", "fetch"),
+                                 % (c, os.path.relpath(d, ROOT), sub) for c, sub in (("FETCH_SIZE", "fetch"),
                                                                                  ("WRITE_SIZE", "write"))],
            "shapes": {}}
     scales = []
-    for sd in sorted(glob.glob(os.path.join(d, "z*_r*_l*"))):
+    for sd in sorted(x for x in glob.glob(os.path.join(d, "z*_r*_l*")) if os.path.isdir(x)):
         z, r, ly = (int(x[1:]) for x in os.path.basename(sd).split("_"))
         e = {}
         for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
