@@ -1009,7 +1009,7 @@ static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var
 // entry level 0 holds u (with current face ghosts) and f, and the slot is
 // admitted; on return u is in level 0's FP64 array and the stop test's
 // history in the slot.  Per iteration:
-//   p' = z + beta p, q = L p', alpha = rz / (p'.q)       (direction pass)
+//   p' = z + beta p (every element), q = L p', alpha = rz / (p'.q)
 //   u += alpha p', r -= alpha q, stop test on |r|_inf     (update pass)
 //   z = M r                                               (the V-cycle)
 //   beta = -alpha (z.q) / rz, rz = z.r                    (dot pass)
@@ -1066,13 +1066,15 @@ static void krylov_iterate(Run& R, Hier* H, const bxmg_solve_params& P, bxmg_ctx
         HIPCHK(launch_batch_check(R.s, H->flags.p + 1, 1, H->fnorm.p, H->st.p, H->flags.p, H->hist.p,
                                   H->hist.p + kHist, H->flags.p + 2));
     };
-    auto precondition = [&]() {  // z = M r, from the right-hand side already in place
+    // z = M r, from the right-hand side already in place; zero: clear the
+    // correction first (the direction pass clears it on the way otherwise)
+    auto precondition = [&](bool zero) {
         if (fp32) {
-            HIPCHK(launch_zero<float>(R.s, H->u32[0]->p, n, R.active));
+            if (zero) HIPCHK(launch_zero<float>(R.s, H->u32[0]->p, n, R.active));
             vcycle<float>(R, 0);
             fill_faces<float>(R, 0, H->u32[0]->p);
         } else {
-            HIPCHK(launch_zero<double>(R.s, H->u64[0]->p, n, R.active));
+            if (zero) HIPCHK(launch_zero<double>(R.s, H->u64[0]->p, n, R.active));
             vcycle<double>(R, 0);
             fill_faces<double>(R, 0, H->u64[0]->p);
         }
@@ -1091,20 +1093,16 @@ static void krylov_iterate(Run& R, Hier* H, const bxmg_solve_params& P, bxmg_ctx
     auto restart = [&]() {  // p = z = M r
         if (fp32) HIPCHK(launch_cast_f32(R.s, K.r.p, H->f32[0]->p, n));
         else HIPCHK(hipMemcpyAsync(H->f64[0]->p, K.r.p, n * sizeof(double), hipMemcpyDeviceToDevice, R.s));
-        precondition();
+        precondition(true);
         dots(2);
     };
     auto iterate = [&]() {
-        if (fp32)
-            HIPCHK(launch_kr_direction<float>(R.s, R.grid(L0.walk()), H->u32[0]->p, pc, b64, pn, K.q.p, K.sc.p,
-                                              K.part.p));
-        else
-            HIPCHK(launch_kr_direction<double>(R.s, R.grid(L0.walk()), H->u64[0]->p, pc, b64, pn, K.q.p, K.sc.p,
-                                               K.part.p));
+        if (fp32) HIPCHK(launch_kr_axpy<float>(R.s, H->u32[0]->p, pc, pn, n, K.sc.p, R.active));
+        else HIPCHK(launch_kr_axpy<double>(R.s, H->u64[0]->p, pc, pn, n, K.sc.p, R.active));
+        std::swap(pc, pn);
+        HIPCHK(launch_kr_apply(R.s, R.grid(L0.walk()), pc, b64, K.q.p, K.part.p));
         HIPCHK(launch_norm_final(R.s, K.part.p, L0.ntcol, K.sums.p));
         HIPCHK(launch_kr_step(R.s, K.sums.p, K.sc.p, 0, R.active));
-        fill_faces<double>(R, 0, pn);
-        std::swap(pc, pn);
         if (fp32)
             HIPCHK(launch_kr_update<float>(R.s, R.grid(L0.walk()), x, pc, K.r.p, K.q.p, H->f32[0]->p, K.sc.p,
                                            H->partials.p));
@@ -1112,7 +1110,7 @@ static void krylov_iterate(Run& R, Hier* H, const bxmg_solve_params& P, bxmg_ctx
             HIPCHK(launch_kr_update<double>(R.s, R.grid(L0.walk()), x, pc, K.r.p, K.q.p, H->f64[0]->p, K.sc.p,
                                             H->partials.p));
         stop_test();
-        precondition();
+        precondition(false);
         dots(1);
     };
     residual(R, R.grid(L0.walk()));

@@ -319,12 +319,14 @@ struct KrylovScalars {
     double beta;   // weight of the previous direction in the next one
     double pq;     // p.Lp of the current direction
 };
-// p' = (double) e + beta p at every valid cell of a level (and, for the
-// stencil, its neighbours), stored in pn; q = L p'; partials[3 tile + 1] =
-// the tile's sum of p'.q.  e and p must have current face ghosts.
+// pn = (double) e + beta p over n elements of a level (ghosts included),
+// then e = 0.  e and p must have current face ghosts; pn's follow.
 template <class E>
-hipError_t launch_kr_direction(hipStream_t s, const Grid& g, const E* e, const double* p, const double* beta,
-                               double* pn, double* q, const KrylovScalars* sc, double* partials);
+hipError_t launch_kr_axpy(hipStream_t s, E* e, const double* p, double* pn, long long n, const KrylovScalars* sc,
+                          const int* active);
+// q = L p at every valid cell; partials[3 tile + 1] = the tile's sum of p.q.
+hipError_t launch_kr_apply(hipStream_t s, const Grid& g, const double* p, const double* beta, double* q,
+                           double* partials);
 // x += alpha p, r -= alpha q, rhs = (E) r at every valid cell; partials of
 // the new residual's norms as launch_resid writes them.
 template <class E>

@@ -2617,70 +2617,66 @@ template hipError_t launch_zero_ranges<float>(hipStream_t, float*, const ZeroRan
 // ------------------------------------ multigrid-preconditioned CG (level 0)
 // Both colours of the valid cells of every tile, as k_resid walks them.
 
-// p' = z + beta p, z = (double) e, at the cell and its six neighbours, then
-// q = L p' = (su - sb p'_c) / h^2 (k_resid's operation order).  The face
-// ghosts of e and p hold reflections (-v) or periodic images of cells, and
-// z + beta p of such values is exactly the same reflection or image of the
-// cell's p', so the neighbours need no refreshed p' ghosts.
-template <class E, int MODE, bool RES>
-__global__ void __launch_bounds__(kBlock) k_kr_direction(Grid g, const E* __restrict__ e,
-                                                        const double* __restrict__ p,
-                                                        const double* __restrict__ beta, double* __restrict__ pn,
-                                                        double* __restrict__ q, const KrylovScalars* __restrict__ sc,
-                                                        double* __restrict__ partials) {
+// p' = z + beta p, z = (double) e, over every element of the level (valid
+// cells, ghosts and padding): the face ghosts of e and p hold reflections
+// (-v) or periodic images of cells, and z + beta p of such values is exactly
+// the same reflection or image of the cell's p', so p' needs no ghost
+// refresh.  e is zeroed on the way: the next V-cycle starts from it.
+template <class E>
+__global__ void __launch_bounds__(kBlock) k_kr_axpy(E* __restrict__ e, const double* __restrict__ p,
+                                                   double* __restrict__ pn, long long n,
+                                                   const KrylovScalars* __restrict__ sc,
+                                                   const int* __restrict__ active) {
+    if (active && !active[0]) return;
+    const double bs = sc->beta;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        pn[q] = (double)e[q] + bs * p[q];
+        e[q] = E(0);
+    }
+}
+
+// q = L p = (su - sb p_c) / h^2 (k_resid's operation order) at every valid
+// cell, partial sums of p.q per tile
+template <int MODE, bool RES>
+__global__ void __launch_bounds__(kBlock) k_kr_apply(Grid g, const double* __restrict__ p,
+                                                    const double* __restrict__ beta, double* __restrict__ q,
+                                                    double* __restrict__ partials) {
     __shared__ double sh[3 * (kBlock / 64)];
     double z0 = 0.0, pq = 0.0, z1 = 0.0;
     const int tix = tile_index(g.rev);
     const Tile tl = g.tiles[tix];
     const RBox B = g.boxes[tl.box];
     if (g.active && !g.active[B.pid]) return;
-    const double bs = sc->beta;
     const double ih2 = 1.0 / (B.h * B.h);
     const FaceArrays<double> fa{};
-    const FaceArrays<E> fe{};
     const TileThread th = tile_thread(tl);
     const int j = B.lo[1] + th.y;
     const long long ne = 2 * B.cstride;
-    const BoxRes<double> P(p + B.base, ne), Bt((MODE == 1 ? beta : p) + B.base, ne);
-    const BoxRes<double> Pn(pn + B.base, ne), Q(q + B.base, ne);
-    const BoxRes<E> Ee(e + B.base, ne);
+    const BoxRes<double> P(p + B.base, ne), Bt((MODE == 1 ? beta : p) + B.base, ne), Q(q + B.base, ne);
     if (j <= B.hi[1])
         for (int z = 0; z < (int)tl.zc; ++z) {
             const int k = B.lo[2] + th.z0 + z * th.dz;
             if (k > B.hi[2]) break;
+            Nbr<double> nb[2];
+            long long idx[2];
+            bool ok[2];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {  // the loads of both cells first
+                const int i = colour_i(B, th.x, j, k, c);
+                ok[c] = i <= B.hi[0];
+                if constexpr (RES) idx[c] = gather_res<double, MODE, true>(P, Bt, fa, B, ok[c] ? i : B.hi[0], j, k, nb[c]);
+                else if (ok[c]) idx[c] = gather<double, MODE, true>(p, beta, fa, B, i, j, k, nb[c]);
+            }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const int i = colour_i(B, th.x, j, k, c);
-                if (i > B.hi[0]) continue;
-                Nbr<double> np;
-                Nbr<E> nz;
-                long long idx;
-                if constexpr (RES) {
-                    idx = gather_res<double, MODE, true>(P, Bt, fa, B, i, j, k, np);
-                    gather_res<E, 0, true>(Ee, Ee, fe, B, i, j, k, nz);
-                } else {
-                    idx = gather<double, MODE, true>(p, beta, fa, B, i, j, k, np);
-                    gather<E, 0, true>(e, nullptr, fe, B, i, j, k, nz);
-                }
-                Nbr<double> nn = np;
-                nn.xm = (double)nz.xm + bs * np.xm;
-                nn.xp = (double)nz.xp + bs * np.xp;
-                nn.ym = (double)nz.ym + bs * np.ym;
-                nn.yp = (double)nz.yp + bs * np.yp;
-                nn.zm = (double)nz.zm + bs * np.zm;
-                nn.zp = (double)nz.zp + bs * np.zp;
-                nn.c = (double)nz.c + bs * np.c;
+                if (!ok[c]) continue;
                 double su, sb;
-                sums<double, MODE>(nn, su, sb);
-                const double qv = (su - sb * nn.c) * ih2;
-                if constexpr (RES) {
-                    Pn.st((int)idx, nn.c);
-                    Q.st((int)idx, qv);
-                } else {
-                    pn[idx] = nn.c;
-                    q[idx] = qv;
-                }
-                pq = pq + nn.c * qv;
+                sums<double, MODE>(nb[c], su, sb);
+                const double qv = (su - sb * nb[c].c) * ih2;
+                if constexpr (RES) Q.st((int)idx[c], qv);
+                else q[idx[c]] = qv;
+                pq = pq + nb[c].c * qv;
             }
         }
     block_reduce3(z0, pq, z1, sh);
@@ -2783,18 +2779,24 @@ __global__ void k_kr_step(const double* __restrict__ s3, KrylovScalars* __restri
 }
 
 template <class E>
-hipError_t launch_kr_direction(hipStream_t s, const Grid& g, const E* e, const double* p, const double* beta,
-                               double* pn, double* q, const KrylovScalars* sc, double* partials) {
+hipError_t launch_kr_axpy(hipStream_t s, E* e, const double* p, double* pn, long long n, const KrylovScalars* sc,
+                          const int* active) {
+    if (n <= 0) return hipSuccess;
+    const long long nb = std::min<long long>(nblk(n), 8192);
+    hipLaunchKernelGGL(k_kr_axpy<E>, dim3((unsigned)nb), dim3(kBlock), 0, s, e, p, pn, n, sc, active);
+    return hipGetLastError();
+}
+hipError_t launch_kr_apply(hipStream_t s, const Grid& g, const double* p, const double* beta, double* q,
+                           double* partials) {
     if (g.ntiles <= 0) return hipSuccess;
     const dim3 G(g.ntiles), B(kBlock);
-#define BXMG_KRD(MODE, RES) \
-    hipLaunchKernelGGL((k_kr_direction<E, MODE, RES>), G, B, 0, s, g, e, p, beta, pn, q, sc, partials)
     if (g.res) {
-        if (beta) BXMG_KRD(1, true); else BXMG_KRD(0, true);
+        if (beta) hipLaunchKernelGGL((k_kr_apply<1, true>), G, B, 0, s, g, p, beta, q, partials);
+        else hipLaunchKernelGGL((k_kr_apply<0, true>), G, B, 0, s, g, p, beta, q, partials);
     } else {
-        if (beta) BXMG_KRD(1, false); else BXMG_KRD(0, false);
+        if (beta) hipLaunchKernelGGL((k_kr_apply<1, false>), G, B, 0, s, g, p, beta, q, partials);
+        else hipLaunchKernelGGL((k_kr_apply<0, false>), G, B, 0, s, g, p, beta, q, partials);
     }
-#undef BXMG_KRD
     return hipGetLastError();
 }
 template <class E>
@@ -2816,8 +2818,8 @@ hipError_t launch_kr_step(hipStream_t s, const double* sums3, KrylovScalars* sc,
     return hipGetLastError();
 }
 #define BXMG_KR_INST(E)                                                                                          \
-    template hipError_t launch_kr_direction<E>(hipStream_t, const Grid&, const E*, const double*, const double*, \
-                                               double*, double*, const KrylovScalars*, double*);                 \
+    template hipError_t launch_kr_axpy<E>(hipStream_t, E*, const double*, double*, long long,                    \
+                                          const KrylovScalars*, const int*);                                     \
     template hipError_t launch_kr_update<E>(hipStream_t, const Grid&, double*, const double*, double*,           \
                                             const double*, E*, const KrylovScalars*, double*);                   \
     template hipError_t launch_kr_dots<E>(hipStream_t, const Grid&, const E*, const double*, const double*, double*);
