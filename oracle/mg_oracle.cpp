@@ -17,7 +17,9 @@
 // The paper names the solver family only ("linear solvers for cell-centered
 // data", Section 2).  The multigrid steps below are the textbook cell-centred
 // V-cycle; every point the paper leaves open is a documented reading:
-//   operator   : div(beta grad u) = f, 7-point, cubic cells of width h
+//   operator   : div(beta grad u) - alpha u = f (alpha >= 0; 0: Poisson),
+//                7-point, cubic cells of width h; backward-Euler heat steps
+//                are such solves with alpha = 1/dt
 //   Dirichlet  : homogeneous, ghost = -(mirror cell), one sign per outside dim
 //   smoother   : red-black Gauss-Seidel, red = (i+j+k) even (global indices),
 //                ghosts refreshed before every colour
@@ -63,8 +65,14 @@ static int parity(int i, int j, int k) { return (i + j + k) & 1; }
 struct Geom {
     Box dom;
     int per[3];
-    double h;  // cell width (cubic cells)
+    double h;            // cell width (cubic cells)
+    double alpha = 0.0;  // Helmholtz coefficient: the operator is div(beta grad u) - alpha u
     bool all_periodic() const { return per[0] && per[1] && per[2]; }
+    // the operator annihilates the constants (fully periodic, no alpha term)
+    bool singular() const { return all_periodic() && alpha == 0.0; }
+    // alpha h^2, added to the stencil's diagonal weight sb
+    template <class T>
+    T shift() const { return (T)(alpha * (h * h)); }
 };
 
 // One FArrayBox: box grown by ng, F-order.
@@ -369,9 +377,11 @@ static inline void stencil(const Fab<T>& U, const FacesT<T>* fc, int i, int j, i
 }
 
 // One colour of red-black Gauss-Seidel (ghosts of u must be current).
+// With the Helmholtz term: u = (su - h^2 f) / (sb + alpha h^2).
 template <class T>
 static void gs_colour(const Geom& g, MF<T>& u, const MF<T>& f, const FacesT<T>* fc, int colour) {
     const T h2 = (T)(g.h * g.h);
+    const T dg = g.shift<T>();
     for (size_t b = 0; b < u.f.size(); ++b) {
         Fab<T>& U = u.f[b];
         const Fab<T>& Fb = f.f[b];
@@ -382,7 +392,7 @@ static void gs_colour(const Geom& g, MF<T>& u, const MF<T>& f, const FacesT<T>* 
                     if (parity(i, j, k) != colour) continue;
                     T su, sb;
                     stencil(U, fc, i, j, k, su, sb);
-                    U(i, j, k) = (su - h2 * Fb(i, j, k)) / sb;
+                    U(i, j, k) = (su - h2 * Fb(i, j, k)) / (sb + dg);
                 }
     }
 }
@@ -393,6 +403,7 @@ template <class T>
 static void residual(const Geom& g, const MF<T>& u, const MF<T>& f, const FacesT<T>* fc, MF<T>& r, double* rinf,
                      double* rl2sq) {
     const T ih2 = (T)(1.0 / (g.h * g.h));
+    const T dg = g.shift<T>();
     double mx = 0.0, s2 = 0.0;
     bool bad = false;
     for (size_t b = 0; b < u.f.size(); ++b) {
@@ -403,7 +414,7 @@ static void residual(const Geom& g, const MF<T>& u, const MF<T>& f, const FacesT
                 for (int i = B.lo[0]; i <= B.hi[0]; ++i) {
                     T su, sb;
                     stencil(U, fc, i, j, k, su, sb);
-                    T Lu = (su - sb * U(i, j, k)) * ih2;
+                    T Lu = (su - (sb + dg) * U(i, j, k)) * ih2;
                     T rv = f.f[b](i, j, k) - Lu;
                     r.f[b](i, j, k) = rv;
                     double a = std::fabs((double)rv);
@@ -519,6 +530,7 @@ static void add_const_valid(MF<double>& a, double c) {
 static void apply_op(const Geom& g, MF<double>& p, const Faces* fc, MF<double>& Ap) {
     fill_and_bc(g, p);
     const double ih2 = 1.0 / (g.h * g.h);
+    const double dg = g.shift<double>();
     for (size_t b = 0; b < p.f.size(); ++b) {
         const Box& B = p.f[b].bx;
         for (int k = B.lo[2]; k <= B.hi[2]; ++k)
@@ -526,7 +538,7 @@ static void apply_op(const Geom& g, MF<double>& p, const Faces* fc, MF<double>& 
                 for (int i = B.lo[0]; i <= B.hi[0]; ++i) {
                     double su, sb;
                     stencil(p.f[b], fc, i, j, k, su, sb);
-                    Ap.f[b](i, j, k) = (su - sb * p.f[b](i, j, k)) * ih2;
+                    Ap.f[b](i, j, k) = (su - (sb + dg) * p.f[b](i, j, k)) * ih2;
                 }
     }
 }
@@ -545,7 +557,7 @@ static CGStats bottom_cg(const Geom& g, const std::vector<Box>& bs, const MF<dou
             for (int j = B.lo[1]; j <= B.hi[1]; ++j)
                 for (int i = B.lo[0]; i <= B.hi[0]; ++i) r.f[b](i, j, k) = rhs_in.f[b](i, j, k);
     }
-    const bool sing = g.all_periodic();
+    const bool sing = g.singular();
     if (sing) add_const_valid(r, mean_valid(r));
     for (size_t b = 0; b < bs.size(); ++b) {
         const Box& B = bs[b];
@@ -595,7 +607,8 @@ struct Params {
     int nu1 = 2, nu2 = 2, max_cycles = 200, precision = 0, prolong = 2, fixed_cycles = 0;
     double rel_tol = 1e-10, abs_tol = 0.0, h = 0.0, bottom_rtol = 1e-12;
     int min_box_edge = kDefaultMinBoxEdge;
-    int krylov = 0;  // 1: conjugate gradients preconditioned by one V-cycle
+    int krylov = 0;      // 1: conjugate gradients preconditioned by one V-cycle
+    int use_guess = 0;   // 1: start from the caller's u (else from zero)
 };
 
 // Multigrid hierarchy of storage type T: per level u, f, r and (variable
@@ -912,12 +925,15 @@ static int solve(const Params& P, const Geom& g0, const std::vector<Box>& b0, co
     std::vector<CGStats> cgs;
 
     int status = 0;
-    if (!(fnorm > 0.0)) {
+    if (!(fnorm > 0.0)) {  // f == 0: u = 0; non-finite f: u left as it was
         if (std::isnan(fnorm)) status = -5;
+        if (status == 0 || !P.use_guess) u->zero();
+        else scatter_global(g0.dom, uglob, *u);
         gather_global(g0.dom, *u, uglob);
         info->status = status;
         return status;
     }
+    if (P.use_guess) scatter_global(g0.dom, uglob, *u);
     int cyc = 0;
     if (P.krylov) {
         status = pcg(P, g0, b0, H64, H32, *u, *f, *r, fc0, fnorm, info, &cgs, &cyc);
@@ -957,7 +973,7 @@ static int solve(const Params& P, const Geom& g0, const std::vector<Box>& b0, co
     info->cycles = cyc;
     for (auto& s : cgs) info->cg_iters_max = std::max(info->cg_iters_max, s.iters);
     gather_global(g0.dom, *u, uglob);
-    if (g0.all_periodic()) {
+    if (g0.singular()) {
         // mean-zero representative; the mean is summed in global F-order so
         // that it does not depend on the box decomposition
         const size_t N = (size_t)g0.dom.cells();
@@ -1080,8 +1096,9 @@ void orc_fill_boundary_f32(const int* dom6, const int* per, int nb, const int* l
 // beta_glob: NULL for constant coefficient, else the level's cell beta as a
 // global array (only valid for a level-0 call: faces from the cell field).
 static void gs_impl(const int* dom6, const int* per, int nb, const int* lohi, double h, int colour, double* u,
-                    const double* f, const double* beta_glob) {
+                    const double* f, const double* beta_glob, double alpha) {
     Geom g = geom_of(dom6, per, h);
+    g.alpha = alpha;
     MF<double> U, F;
     U.define(boxes_of(nb, lohi), 1);
     F.define(boxes_of(nb, lohi), 1);
@@ -1094,8 +1111,8 @@ static void gs_impl(const int* dom6, const int* per, int nb, const int* lohi, do
 }
 
 void orc_gs(const int* dom6, const int* per, int nb, const int* lohi, double h, int colour, double* u,
-            const double* f, const double* beta_glob) {
-    gs_impl(dom6, per, nb, lohi, h, colour, u, f, beta_glob);
+            const double* f, const double* beta_glob, double alpha) {
+    gs_impl(dom6, per, nb, lohi, h, colour, u, f, beta_glob, alpha);
 }
 
 void orc_gs_f32(const int* dom6, const int* per, int nb, const int* lohi, double h, int colour, float* u,
@@ -1111,8 +1128,9 @@ void orc_gs_f32(const int* dom6, const int* per, int nb, const int* lohi, double
 }
 
 void orc_residual(const int* dom6, const int* per, int nb, const int* lohi, double h, const double* u,
-                  const double* f, const double* beta_glob, double* r, double* norms) {
+                  const double* f, const double* beta_glob, double alpha, double* r, double* norms) {
     Geom g = geom_of(dom6, per, h);
+    g.alpha = alpha;
     MF<double> U, F, R;
     U.define(boxes_of(nb, lohi), 1);
     F.define(boxes_of(nb, lohi), 1);
@@ -1168,8 +1186,9 @@ long orc_faces(const int* dom6, const int* per, int nb, const int* lohi, const d
 
 // L u for a global array u (one box covering the domain), FP64.
 void orc_apply_op(const int* dom6, const int* per, double h, const double* u_glob, const double* beta_glob,
-                  double* Lu_glob) {
+                  double alpha, double* Lu_glob) {
     Geom g = geom_of(dom6, per, h);
+    g.alpha = alpha;
     std::vector<Box> one{g.dom};
     MF<double> U, A;
     U.define(one, 1);
@@ -1186,6 +1205,9 @@ typedef struct {
     double rel_tol, abs_tol, h, bottom_rtol;
     int min_box_edge;  // < 2: the default hierarchy threshold
     int krylov;        // 1: multigrid-preconditioned conjugate gradients
+    int use_guess;     // 1: u_glob holds the initial guess on entry
+    int pad;
+    double alpha;      // Helmholtz coefficient: solves div(beta grad u) - alpha u = f
 } orc_params;
 
 int orc_solve(const orc_params* p, const int* dom6, const int* per, int nb, const int* lohi, const double* f_glob,
@@ -1196,14 +1218,39 @@ int orc_solve(const orc_params* p, const int* dom6, const int* per, int nb, cons
     P.rel_tol = p->rel_tol; P.abs_tol = p->abs_tol; P.h = p->h; P.bottom_rtol = p->bottom_rtol;
     P.min_box_edge = p->min_box_edge >= 2 ? p->min_box_edge : kDefaultMinBoxEdge;
     P.krylov = p->krylov;
+    P.use_guess = p->use_guess;
     Geom g = geom_of(dom6, per, p->h);
+    g.alpha = p->alpha;
     return solve(P, g, boxes_of(nb, lohi), f_glob, beta_glob, u_glob, info);
+}
+
+// One backward-Euler step of the heat equation u_t = div(beta grad u) + s:
+// (u' - u) / dt = div(beta grad u') + s, i.e. div(beta grad u') - u'/dt = f
+// with f = -(u/dt + s): a Helmholtz solve with alpha = 1/dt, started from u.
+// u_glob: u on entry, u' on return; s_glob may be NULL.  p->alpha and
+// p->use_guess are ignored (alpha = 1/dt, guess = u).
+int orc_heat_step(const orc_params* p, const int* dom6, const int* per, int nb, const int* lohi, double dt,
+                  const double* s_glob, const double* beta_glob, double* u_glob, Info* info) {
+    const Box D = box6(dom6);
+    const size_t N = (size_t)D.cells();
+    const double inv = 1.0 / dt;
+    std::vector<double> f(N);
+    for (size_t q = 0; q < N; ++q) {
+        double t = u_glob[q] * inv;
+        if (s_glob) t = t + s_glob[q];
+        f[q] = -t;
+    }
+    orc_params q = *p;
+    q.alpha = inv;
+    q.use_guess = 1;
+    return orc_solve(&q, dom6, per, nb, lohi, f.data(), beta_glob, u_glob, info);
 }
 
 // Bottom solve on its own (global arrays, one box): for tests of the CG stage.
 int orc_bottom(const int* dom6, const int* per, double h, const double* f_glob, const double* beta_glob,
-               double rtol, double* u_glob, int* iters) {
+               double alpha, double rtol, double* u_glob, int* iters) {
     Geom g = geom_of(dom6, per, h);
+    g.alpha = alpha;
     std::vector<Box> one{g.dom};
     std::vector<Level> L{Level{g, one}};
     std::vector<Faces> F = build_faces<double>(L, beta_glob);

@@ -39,7 +39,8 @@ class Params(C.Structure):
     _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("max_cycles", C.c_int), ("precision", C.c_int),
                 ("prolong", C.c_int), ("fixed_cycles", C.c_int), ("rel_tol", C.c_double),
                 ("abs_tol", C.c_double), ("h", C.c_double), ("bottom_rtol", C.c_double),
-                ("min_box_edge", C.c_int), ("krylov", C.c_int)]
+                ("min_box_edge", C.c_int), ("krylov", C.c_int), ("use_guess", C.c_int), ("pad", C.c_int),
+                ("alpha", C.c_double)]
 
 
 class Info(C.Structure):
@@ -179,28 +180,28 @@ def apply_bc(dom_lo, dom_hi, periodic, boxes, ng, packed, ncomp=1, odd=True):
     return packed
 
 
-def gs(dom_lo, dom_hi, periodic, boxes, h, colour, u, f, beta_glob=None):
+def gs(dom_lo, dom_hi, periodic, boxes, h, colour, u, f, beta_glob=None, alpha=0.0):
     """One red-black colour (ng = 1, ghosts of u current) in place on u."""
     L = lib()
     if u.dtype == np.float32:
-        assert beta_glob is None
+        assert beta_glob is None and alpha == 0.0
         L.orc_gs_f32(_ip(dom6(dom_lo, dom_hi)), _ip(_i32(periodic)), len(boxes), _ip(lohi_array(boxes)),
                      C.c_double(h), int(colour), _fp(u), _fp(f))
         return u
     b = None if beta_glob is None else np.asfortranarray(beta_glob, dtype=np.float64)
     L.orc_gs(_ip(dom6(dom_lo, dom_hi)), _ip(_i32(periodic)), len(boxes), _ip(lohi_array(boxes)), C.c_double(h),
-             int(colour), _dp(u), _dp(f), _dp(b.ravel(order="F")) if b is not None else None)
+             int(colour), _dp(u), _dp(f), _dp(b.ravel(order="F")) if b is not None else None, C.c_double(alpha))
     return u
 
 
-def residual(dom_lo, dom_hi, periodic, boxes, h, u, f, beta_glob=None):
+def residual(dom_lo, dom_hi, periodic, boxes, h, u, f, beta_glob=None, alpha=0.0):
     """r = f - L u on valid cells (packed, ng = 1); returns (r, rinf, rl2sq)."""
     L = lib()
     r = np.zeros_like(u)
     norms = np.zeros(2)
     b = None if beta_glob is None else np.asfortranarray(beta_glob, dtype=np.float64).ravel(order="F")
     L.orc_residual(_ip(dom6(dom_lo, dom_hi)), _ip(_i32(periodic)), len(boxes), _ip(lohi_array(boxes)),
-                   C.c_double(h), _dp(u), _dp(f), _dp(b), _dp(r), _dp(norms))
+                   C.c_double(h), _dp(u), _dp(f), _dp(b), C.c_double(alpha), _dp(r), _dp(norms))
     return r, norms[0], norms[1]
 
 
@@ -247,50 +248,81 @@ def faces(dom_lo, dom_hi, periodic, boxes, beta_glob):
     return res
 
 
-def apply_op(dom_lo, dom_hi, periodic, h, u_glob, beta_glob=None):
-    """L u on a global array (FP64)."""
+def apply_op(dom_lo, dom_hi, periodic, h, u_glob, beta_glob=None, alpha=0.0):
+    """L u = div(beta grad u) - alpha u on a global array (FP64)."""
     L = lib()
     u = np.asfortranarray(u_glob, dtype=np.float64)
     out = np.zeros(u.shape, order="F")
     b = None if beta_glob is None else np.asfortranarray(beta_glob, dtype=np.float64)
     L.orc_apply_op(_ip(dom6(dom_lo, dom_hi)), _ip(_i32(periodic)), C.c_double(h), _dp(u.ravel(order="F")),
-                   _dp(b.ravel(order="F")) if b is not None else None, _dp(out.ravel(order="F")))
+                   _dp(b.ravel(order="F")) if b is not None else None, C.c_double(alpha),
+                   _dp(out.ravel(order="F")))
     return out
 
 
-def bottom(dom_lo, dom_hi, periodic, h, f_glob, beta_glob=None, rtol=1e-12):
+def bottom(dom_lo, dom_hi, periodic, h, f_glob, beta_glob=None, rtol=1e-12, alpha=0.0):
     L = lib()
     f = np.asfortranarray(f_glob, dtype=np.float64)
     u = np.zeros(f.shape, order="F")
     b = None if beta_glob is None else np.asfortranarray(beta_glob, dtype=np.float64)
     it = C.c_int(0)
     L.orc_bottom(_ip(dom6(dom_lo, dom_hi)), _ip(_i32(periodic)), C.c_double(h), _dp(f.ravel(order="F")),
-                 _dp(b.ravel(order="F")) if b is not None else None, C.c_double(rtol), _dp(u.ravel(order="F")),
+                 _dp(b.ravel(order="F")) if b is not None else None, C.c_double(alpha), C.c_double(rtol),
+                 _dp(u.ravel(order="F")),
                  C.byref(it))
     return u, it.value
 
 
 def solve(dom_lo, dom_hi, periodic, boxes, f_glob, beta_glob=None, h=None, nu1=2, nu2=2, max_cycles=200,
           precision=0, prolong=2, fixed_cycles=0, rel_tol=1e-10, abs_tol=0.0, bottom_rtol=1e-12, min_box_edge=0,
-          krylov=0):
-    """Full multigrid solve; returns (u_glob, info dict).  min_box_edge: the
-    hierarchy's box-merging threshold (0: default).  krylov=1: conjugate
-    gradients preconditioned by one V-cycle per iteration (cycles counts the
-    iterations)."""
+          krylov=0, alpha=0.0, u0=None):
+    """Full multigrid solve of div(beta grad u) - alpha u = f; returns
+    (u_glob, info dict).  min_box_edge: the hierarchy's box-merging threshold
+    (0: default).  krylov=1: conjugate gradients preconditioned by one
+    V-cycle per iteration (cycles counts the iterations).  u0: initial guess
+    (default zero)."""
     L = lib()
     f = np.asfortranarray(f_glob, dtype=np.float64)
     assert f.shape == box_shape(dom_lo, dom_hi)
     if h is None:
         h = 1.0 / f.shape[0]
     p = Params(nu1, nu2, max_cycles, precision, prolong, fixed_cycles, rel_tol, abs_tol, h, bottom_rtol,
-               int(min_box_edge), int(krylov))
+               int(min_box_edge), int(krylov), int(u0 is not None), 0, float(alpha))
     info = Info()
-    u = np.zeros(f.shape, order="F")
+    u = np.zeros(f.shape, order="F") if u0 is None else np.array(u0, dtype=np.float64, order="F", copy=True)
     b = None if beta_glob is None else np.asfortranarray(beta_glob, dtype=np.float64)
     L.orc_solve(C.byref(p), _ip(dom6(dom_lo, dom_hi)), _ip(_i32(periodic)), len(boxes), _ip(lohi_array(boxes)),
                 _dp(f.ravel(order="F")), _dp(b.ravel(order="F")) if b is not None else None,
                 _dp(u.ravel(order="F")), C.byref(info))
-    d = {"status": info.status, "cycles": info.cycles, "levels": info.levels, "rel_inf": info.rel_inf,
-         "rel_l2": info.rel_l2, "f_inf": info.f_inf, "hist": list(info.hist[:info.nhist]),
-         "hist_l2": list(info.hist_l2[:info.nhist]), "cg_iters_max": info.cg_iters_max}
-    return u, d
+    return u, _info_dict(info)
+
+
+def _info_dict(info):
+    return {"status": info.status, "cycles": info.cycles, "levels": info.levels, "rel_inf": info.rel_inf,
+            "rel_l2": info.rel_l2, "f_inf": info.f_inf, "hist": list(info.hist[:info.nhist]),
+            "hist_l2": list(info.hist_l2[:info.nhist]), "cg_iters_max": info.cg_iters_max}
+
+
+def heat_step(dom_lo, dom_hi, periodic, boxes, u_glob, dt, source=None, beta_glob=None, h=None, **kw):
+    """One backward-Euler step of u_t = div(beta grad u) + source: the
+    Helmholtz solve with alpha = 1/dt and f = -(u/dt + source), started from
+    u.  Returns (u', info dict); kw as for solve (nu1, precision, krylov ...)."""
+    L = lib()
+    u = np.array(u_glob, dtype=np.float64, order="F", copy=True)
+    assert u.shape == box_shape(dom_lo, dom_hi)
+    if h is None:
+        h = 1.0 / u.shape[0]
+    names = ("nu1", "nu2", "max_cycles", "precision", "prolong", "fixed_cycles", "rel_tol", "abs_tol",
+             "bottom_rtol", "min_box_edge", "krylov")
+    defaults = dict(nu1=2, nu2=2, max_cycles=200, precision=0, prolong=2, fixed_cycles=0, rel_tol=1e-10,
+                    abs_tol=0.0, bottom_rtol=1e-12, min_box_edge=0, krylov=0)
+    defaults.update(kw)
+    v = [defaults[n] for n in names]
+    p = Params(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], h, v[8], int(v[9]), int(v[10]), 1, 0, 0.0)
+    info = Info()
+    s = None if source is None else np.asfortranarray(source, dtype=np.float64)
+    b = None if beta_glob is None else np.asfortranarray(beta_glob, dtype=np.float64)
+    L.orc_heat_step(C.byref(p), _ip(dom6(dom_lo, dom_hi)), _ip(_i32(periodic)), len(boxes), _ip(lohi_array(boxes)),
+                    C.c_double(dt), _dp(s.ravel(order="F")) if s is not None else None,
+                    _dp(b.ravel(order="F")) if b is not None else None, _dp(u.ravel(order="F")), C.byref(info))
+    return u, _info_dict(info)

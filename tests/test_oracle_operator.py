@@ -49,7 +49,7 @@ def test_mixed_bc_eigenvector(orc):
     assert np.max(np.abs(Ls - lam * s)) <= 1e-11 * abs(lam)
 
 
-def assemble(orc, shape, periodic, h, beta=None):
+def assemble(orc, shape, periodic, h, beta=None, alpha=0.0):
     N = int(np.prod(shape))
     A = np.zeros((N, N))
     e = np.zeros(shape, order="F")
@@ -58,7 +58,7 @@ def assemble(orc, shape, periodic, h, beta=None):
         e.ravel(order="F")[q] = 1.0
         e2 = np.zeros(shape, order="F")
         e2.ravel(order="F")[q] = 1.0
-        A[:, q] = orc.apply_op((0, 0, 0), tuple(x - 1 for x in shape), periodic, h, e2, beta).ravel(order="F")
+        A[:, q] = orc.apply_op((0, 0, 0), tuple(x - 1 for x in shape), periodic, h, e2, beta, alpha).ravel(order="F")
     return A
 
 
@@ -104,9 +104,9 @@ def test_varcoef_beta_one_equals_constant(orc):
         assert np.array_equal(U1, U2)
 
 
-@pytest.mark.parametrize("var", [False, True])
+@pytest.mark.parametrize("var,alpha", [(False, 0.0), (True, 0.0), (False, 300.0), (True, 5000.0)])
 @pytest.mark.parametrize("periodic", [(1, 1, 1), (0, 0, 0)])
-def test_gs_zeroes_residual_of_updated_colour(orc, var, periodic):
+def test_gs_zeroes_residual_of_updated_colour(orc, var, periodic, alpha):
     # Ghosts (including the Dirichlet -(mirror) ghosts) are refreshed before
     # each colour and held during it, so the update solves every updated
     # cell's equation with exactly those ghosts: the residual evaluated with
@@ -128,15 +128,15 @@ def test_gs_zeroes_residual_of_updated_colour(orc, var, periodic):
     for colour in (0, 1):
         orc.fill_boundary(dlo, dhi, periodic, boxes, 1, u)
         orc.apply_bc(dlo, dhi, periodic, boxes, 1, u)
-        orc.gs(dlo, dhi, periodic, boxes, h, colour, u, f, beta)
+        orc.gs(dlo, dhi, periodic, boxes, h, colour, u, f, beta, alpha)
         ug = orc.unpack_valid(u, dlo, dhi, boxes, 1)
-        scale = 12.0 * np.abs(ug).max() / h ** 2 * (np.abs(beta).max() if var else 1.0)
-        r, _, _ = orc.residual(dlo, dhi, periodic, boxes, h, u, f, beta)   # same ghosts as the update
+        scale = (12.0 / h ** 2 + alpha) * np.abs(ug).max() * (np.abs(beta).max() if var else 1.0)
+        r, _, _ = orc.residual(dlo, dhi, periodic, boxes, h, u, f, beta, alpha)   # same ghosts as the update
         rg = orc.unpack_valid(r, dlo, dhi, boxes, 1)
         assert np.abs(rg[par == colour]).max() <= 1e-13 * scale
         orc.fill_boundary(dlo, dhi, periodic, boxes, 1, u)
         orc.apply_bc(dlo, dhi, periodic, boxes, 1, u)
-        r, _, _ = orc.residual(dlo, dhi, periodic, boxes, h, u, f, beta)
+        r, _, _ = orc.residual(dlo, dhi, periodic, boxes, h, u, f, beta, alpha)
         rg = orc.unpack_valid(r, dlo, dhi, boxes, 1)
         assert np.abs(rg[(par == colour) & inner]).max() <= 1e-13 * scale
         assert np.abs(rg[par != colour]).max() > 1e-6  # the other colour is not solved
