@@ -182,6 +182,9 @@ typedef struct {
                                per iteration, in the precision above (paper Section 2,
                                linear solvers); cycles then counts CG iterations       */
     int32_t reserved;       /* 0                                                      */
+    double alpha;           /* >= 0: solve div(beta grad phi) - alpha phi = rhs (Helmholtz;
+                               0 = Poisson); with alpha > 0 a fully periodic problem is
+                               not singular and no mean is removed                     */
 } bxmg_solve_params;
 
 typedef struct {
@@ -212,6 +215,20 @@ void bxmg_solve_params_default(bxmg_solve_params* p);
  * arguments; bottom level above 4096 cells), ENOMEM or EDEVICE. */
 bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi, bxmg_multifab rhs,
                             bxmg_multifab beta, bxmg_solve_info* info);
+
+/* One backward-Euler step of the heat equation u_t = div(beta grad u) + s
+ * (the heat-equation use of the solvers in the paper's tutorials, Section
+ * 4): (u' - u)/dt = div(beta grad u') + s, solved as the Helmholtz problem
+ * div(beta grad u') - u'/dt = -(u/dt + s), with the right-hand side formed
+ * on the device from u and s and the solve started from u.  u: FP64
+ * MultiFab, nghost >= 1, the state on entry and the new state on return
+ * (it stays on the device: a time loop calls this once per step).  source:
+ * NULL or an FP64 MultiFab over the same boxes (any nghost; valid cells
+ * read).  params->alpha is ignored (1/dt is used); the other parameters and
+ * the info are those of bxmg_mlmg_solve (rel_tol relative to |f|_inf).
+ * EINVAL for dt <= 0 or a non-finite dt. */
+bxmg_status bxmg_heat_step(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab u, bxmg_multifab source,
+                           bxmg_multifab beta, double dt, bxmg_solve_info* info);
 
 /* -------------------------------------------------------------- tuning --- */
 /* Launch-shape knobs for hierarchies built after the call (hierarchies are

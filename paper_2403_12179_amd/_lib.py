@@ -28,7 +28,7 @@ class SolveParams(C.Structure):
     _fields_ = [("nu1", C.c_int32), ("nu2", C.c_int32), ("max_cycles", C.c_int32), ("precision", C.c_int32),
                 ("prolong", C.c_int32), ("fixed_cycles", C.c_int32), ("rel_tol", C.c_double),
                 ("abs_tol", C.c_double), ("dx", C.c_double), ("bottom_rtol", C.c_double),
-                ("krylov", C.c_int32), ("reserved", C.c_int32)]
+                ("krylov", C.c_int32), ("reserved", C.c_int32), ("alpha", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -68,6 +68,7 @@ def _declare(lib):
         "bxmg_fill_boundary_noalloc": (C.c_int, [H, C.c_int32, C.c_int32, C.c_int32, VP]),
         "bxmg_solve_params_default": (None, [C.POINTER(SolveParams)]),
         "bxmg_mlmg_solve": (C.c_int, [H, C.POINTER(SolveParams), H, H, H, C.POINTER(SolveInfo)]),
+        "bxmg_heat_step": (C.c_int, [H, C.POINTER(SolveParams), H, H, H, C.c_double, C.POINTER(SolveInfo)]),
         "bxmg_ctx_tune": (C.c_int, [H, C.c_int32, C.c_int32]),
         "bxmg_autotune": (C.c_int, [H, C.POINTER(SolveParams), H, H, H, C.c_int32, I32P, DP, I32P]),
         "bxmg_profile_stage": (C.c_int, [H, C.c_int32]),

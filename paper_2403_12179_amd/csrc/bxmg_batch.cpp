@@ -721,6 +721,8 @@ void retire_enqueue(bxmg_batch_s* b, int s, bool convert) {
                           kHist * sizeof(double), hipMemcpyDeviceToHost, st));
     if (!convert) return;
     const Grid g0 = P.grid0();
+    if (b->h_st[s].fnorm == 0.0 && b->h_st[s].status == 0)  // f == 0: the solution is u = 0
+        HIPCHK(launch_zero<double>(st, b->u64.p + p.off + P.L[0].off, P.L[0].nelem));
     if (P.per[0] && P.per[1] && P.per[2]) {
         b->scratch.reserve(3 * (size_t)P.nt0 + 8);
         HIPCHK(launch_mean_sub(st, g0, b->u64.p + p.off, b->scratch.p()));
@@ -771,6 +773,7 @@ bxmg_status bxmg_batch_create(bxmg_ctx ctx, size_t hbm_budget_bytes, int32_t max
         (b->P.prolong != 1 && b->P.prolong != 2))
         return fail(BXMG_EINVAL, "batch_create: bad parameters");
     if (b->P.krylov != 0) return fail(BXMG_EINVAL, "batch_create: batches run V-cycle iterations only (krylov = 0)");
+    if (b->P.alpha != 0.0) return fail(BXMG_EINVAL, "batch_create: batches solve the Poisson operator (alpha = 0)");
     b->var = var != 0;
     b->prec = b->P.precision;
     b->max_slots = max_problems;

@@ -112,6 +112,7 @@ struct Hier {
     int per[3];
     int precision;
     bool var;
+    double alpha = 0.0;  // Helmholtz coefficient of every level's operator
     std::vector<std::unique_ptr<Level>> L;
     // FP64 storage: all levels (precision 0) or level 0 only (precision 1)
     std::vector<std::unique_ptr<DevBuf<double>>> u64, f64;
@@ -182,11 +183,12 @@ static void upload_tiles(const TileSet& t, DevBuf<Tile>& buf, int& n) {
 // merge: coarse levels run on execution_boxes (solves); the stage calls keep
 // the logical boxes, which their caller's MultiFabs are laid out on.
 static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool var, double h0, const Tuning& tune,
-                                        bool merge) {
+                                        bool merge, double alpha) {
     auto H = std::make_unique<Hier>();
     for (int d = 0; d < 3; ++d) H->per[d] = ba->per[d];
     H->precision = precision;
     H->var = var;
+    H->alpha = alpha;
     std::vector<LevelBoxes> lb = make_hierarchy(ba->dom, ba->boxes);
     double h = h0;
     long long max_tiles = 1;
@@ -197,6 +199,7 @@ static std::unique_ptr<Hier> build_hier(const bxmg_ba_s* ba, int precision, bool
         h *= 2.0;
         lv->boxes = merge ? execution_boxes(lb[l], l, true) : lb[l].boxes;
         lv->rb = rb_layout(lv->boxes, 1, lv->h, &lv->nelem);
+        for (auto& r : lv->rb) r.a = alpha;
         if (l == 0 && lv->boxes.size() != lb[0].boxes.size()) {
             // views of the caller's boxes: their own valid range, the merged
             // box's addressing (colour parity is global, so rb_idx and
@@ -466,7 +469,7 @@ void bottom(Run& R, size_t l) {
     Hier* H = R.H;
     const Level& L = *H->L[l];
     HIPCHK(launch_bottom<T>(R.s, lvl_u<T>(H, l), lvl_f<T>(H, l), lvl_faces<T>(H, l), H->var && l > 0, L.d_rb.p,
-                            (int)L.boxes.size(), L.dom.lo, L.dom.hi, H->per, L.h, R.bottom_rtol, H->iters.p));
+                            (int)L.boxes.size(), L.dom.lo, L.dom.hi, H->per, L.h, H->alpha, R.bottom_rtol, H->iters.p));
 }
 
 template <class T>
@@ -912,6 +915,7 @@ void bxmg_solve_params_default(bxmg_solve_params* p) {
     p->bottom_rtol = 1e-12;
     p->krylov = 0;
     p->reserved = 0;
+    p->alpha = 0.0;
 }
 
 static bxmg_status set_status(bxmg_solve_info* info, bxmg_status st) {
@@ -926,11 +930,13 @@ constexpr size_t kCacheEntries = 16;
 constexpr size_t kCacheBytes = size_t(48) << 30;
 
 static std::string hier_key(const bxmg_ctx_s* ctx, const bxmg_ba_s* ba, int precision, bool var, double h,
-                            bool merge) {
+                            bool merge, double alpha) {
     std::string k;
     auto put = [&](long long x) { k.append((const char*)&x, sizeof x); };
-    long long hb;
+    long long hb, ab;
     std::memcpy(&hb, &h, sizeof hb);
+    std::memcpy(&ab, &alpha, sizeof ab);
+    put(ab);
     put(precision);
     put(var);
     put(merge);
@@ -966,8 +972,8 @@ static void cache_trim(bxmg_ctx ctx, const std::string& keep) {
 }
 
 static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var, double h, bxmg_status* st,
-                      bool merge = true) {
-    const std::string key = hier_key(ctx, ba, precision, var, h, merge);
+                      bool merge = true, double alpha = 0.0) {
+    const std::string key = hier_key(ctx, ba, precision, var, h, merge, alpha);
     auto it = ctx->cache.find(key);
     if (it != ctx->cache.end()) {
         cache_touch(ctx, key);
@@ -987,7 +993,7 @@ static Hier* get_hier(bxmg_ctx ctx, const bxmg_ba_s* ba, int precision, bool var
         tune.zc_planes = ctx->zc_planes;
         tune.res = ctx->res;
         tune.ly_cap = ctx->ly_cap;
-        H = build_hier(ba, precision, var, h, tune, merge);
+        H = build_hier(ba, precision, var, h, tune, merge, alpha);
     } catch (HipError& e) {
         *st = fail(e.e == hipErrorOutOfMemory ? BXMG_ENOMEM : BXMG_EDEVICE,
                    std::string("solve: hierarchy setup: ") + e.where + ": " + hipGetErrorString(e.e));
@@ -1158,21 +1164,29 @@ static void krylov_iterate(Run& R, Hier* H, const bxmg_solve_params& P, bxmg_ctx
     if (!fp32) HIPCHK(hipMemcpyAsync(u, x, n * sizeof(double), hipMemcpyDeviceToDevice, R.s));
 }
 
-bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi, bxmg_multifab rhs,
-                            bxmg_multifab beta, bxmg_solve_info* info) {
-    if (!ctx || !phi || !rhs || !info) return fail(BXMG_EINVAL, "solve: NULL argument");
+// A solve; heat_dt > 0 makes it a backward-Euler heat step: the right-hand
+// side is formed on the device from phi (the state) and src (NULL: no
+// source) as f = -(phi * (1/dt) + src), and alpha = 1/dt (reading R24).
+static bxmg_status solve_impl(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi, bxmg_multifab rhs,
+                              bxmg_multifab beta, bxmg_solve_info* info, double heat_dt, bxmg_multifab src) {
+    const bool heat = heat_dt > 0.0;
+    if (!ctx || !phi || (!rhs && !heat) || !info) return fail(BXMG_EINVAL, "solve: NULL argument");
     std::memset(info, 0, sizeof(*info));
     bxmg_solve_params P;
     if (params) P = *params;
     else bxmg_solve_params_default(&P);
+    const double inv_dt = heat ? 1.0 / heat_dt : 0.0;
+    if (heat) P.alpha = inv_dt;
     const bxmg_ba_s* ba = phi->ba;
     bxmg_status st;
     if ((st = check_solve_mf(phi, ba, "phi")) != BXMG_OK) return set_status(info, st);
-    if ((st = check_solve_mf(rhs, ba, "rhs")) != BXMG_OK) return set_status(info, st);
+    if (!heat && (st = check_solve_mf(rhs, ba, "rhs")) != BXMG_OK) return set_status(info, st);
+    if (src && (st = check_field_mf(src, ba, "source")) != BXMG_OK) return set_status(info, st);
     if (beta && (st = check_solve_mf(beta, ba, "beta")) != BXMG_OK) return set_status(info, st);
     if (!covers_domain(ba)) return set_status(info, fail(BXMG_EINVAL, "solve: the BoxArray must cover its domain"));
     if (P.nu1 < 0 || P.nu2 < 0 || P.max_cycles < 0 || (P.precision != 0 && P.precision != 1) ||
-        (P.prolong != 1 && P.prolong != 2) || (P.krylov != 0 && P.krylov != 1))
+        (P.prolong != 1 && P.prolong != 2) || (P.krylov != 0 && P.krylov != 1) ||
+        !(P.alpha >= 0.0 && P.alpha <= 1.7976931348623157e308))
         return set_status(info, fail(BXMG_EINVAL, "solve: bad parameters"));
     const double h = (P.dx > 0) ? P.dx : 1.0 / ba->dom.n(0);
     std::lock_guard<std::mutex> lock(ctx->mu);
@@ -1180,7 +1194,7 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
     try {
         HIPCHK(hipSetDevice(ctx->device));
         st = BXMG_OK;
-        Hier* H = get_hier(ctx, ba, P.precision, beta != nullptr, h, &st, ctx->merge != 0);
+        Hier* H = get_hier(ctx, ba, P.precision, beta != nullptr, h, &st, ctx->merge != 0, P.alpha);
         if (!H) return set_status(info, st);
         info->levels = (int)H->L.size();
         Run R{H, ctx->stream, P.nu1, P.nu2, P.prolong, P.bottom_rtol};
@@ -1192,7 +1206,13 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
         // caller layout -> colour-split level 0
         HIPCHK(launch_fab_to_rb(R.s, L0.view_grid(), (const double*)phi->data, phi->d_fboxes.p, u, false));
         // f, with the norms of f per tile on the way (reduced below)
-        HIPCHK(launch_fab_to_rb_norm(R.s, L0.view_grid(), (const double*)rhs->data, rhs->d_fboxes.p, f, H->partials.p));
+        if (heat)
+            HIPCHK(launch_heat_rhs(R.s, L0.view_grid(), (const double*)phi->data, phi->d_fboxes.p,
+                                   src ? (const double*)src->data : nullptr, src ? src->d_fboxes.p : nullptr, inv_dt,
+                                   f, H->partials.p));
+        else
+            HIPCHK(launch_fab_to_rb_norm(R.s, L0.view_grid(), (const double*)rhs->data, rhs->d_fboxes.p, f,
+                                         H->partials.p));
         if (beta) {
             HIPCHK(launch_fab_to_rb(R.s, L0.view_grid(), (const double*)beta->data, beta->d_fboxes.p, H->beta64.p, false));
             if (P.precision == 0) {
@@ -1332,7 +1352,9 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
             ctx->prof.harvest();
             return set_status(info, fail(BXMG_ENONFINITE, "solve: non-finite right-hand side"));
         }
-        if (ba->per[0] && ba->per[1] && ba->per[2])
+        if (Sf.fnorm == 0.0 && status == 0)  // f == 0: the solution is u = 0 (reading R13)
+            HIPCHK(launch_zero<double>(R.s, u, L0.nelem));
+        if (ba->per[0] && ba->per[1] && ba->per[2] && P.alpha == 0.0)
             HIPCHK(launch_mean_sub(R.s, L0.mean_grid(), u, H->partials.p));
         HIPCHK(launch_rb_to_fab(R.s, L0.view_grid(), u, (double*)phi->data, phi->d_fboxes.p));
         HIPCHK(hipStreamSynchronize(R.s));
@@ -1345,6 +1367,21 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
     }
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return (bxmg_status)info->status;
+}
+
+bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi, bxmg_multifab rhs,
+                            bxmg_multifab beta, bxmg_solve_info* info) {
+    return solve_impl(ctx, params, phi, rhs, beta, info, 0.0, nullptr);
+}
+
+bxmg_status bxmg_heat_step(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab u, bxmg_multifab source,
+                           bxmg_multifab beta, double dt, bxmg_solve_info* info) {
+    if (!(dt > 0.0 && dt <= 1.7976931348623157e308)) {
+        if (info) std::memset(info, 0, sizeof(*info));
+        return info ? set_status(info, fail(BXMG_EINVAL, "heat_step: dt must be positive and finite"))
+                    : fail(BXMG_EINVAL, "heat_step: dt must be positive and finite");
+    }
+    return solve_impl(ctx, params, u, nullptr, beta, info, dt, source);
 }
 
 
@@ -1593,7 +1630,7 @@ bxmg_status bxmg_bottom_solve(bxmg_ctx ctx, bxmg_multifab phi, bxmg_multifab rhs
         const Level& L0 = *H->L[0];
         HIPCHK(launch_fab_to_rb(R.s, L0.grid(), (const double*)rhs->data, rhs->d_fboxes.p, H->f64[0]->p, false));
         HIPCHK(launch_bottom<double>(R.s, H->u64[0]->p, H->f64[0]->p, no_faces<double>(), false, L0.d_rb.p,
-                                     (int)L0.boxes.size(), L0.dom.lo, L0.dom.hi, H->per, L0.h, rtol, H->iters.p));
+                                     (int)L0.boxes.size(), L0.dom.lo, L0.dom.hi, H->per, L0.h, 0.0, rtol, H->iters.p));
         HIPCHK(launch_rb_to_fab(R.s, L0.grid(), H->u64[0]->p, (double*)phi->data, phi->d_fboxes.p));
         int it = 0;
         HIPCHK(hipMemcpyAsync(&it, H->iters.p, sizeof(int), hipMemcpyDeviceToHost, R.s));

@@ -387,6 +387,7 @@ inline std::vector<RBox> rb_layout(const std::vector<Box>& boxes, int ng, double
         r.H = (r.G[0] + 1) / 2;
         r.pid = 0;
         r.h = h;
+        r.a = 0.0;
         for (int q = 0; q < 6; ++q) { r.nb[q] = -2; r.shift[q] = 0; }
         const long long half = (long long)r.H * r.G[1] * r.G[2];
         const long long padded = (half + 63) / 64 * 64;
@@ -666,6 +667,15 @@ inline bxmg_status check_solve_mf(bxmg_multifab m, const bxmg_ba_s* ba, const ch
         return fail(BXMG_EINVAL, std::string("solve: ") + name + " is on a different BoxArray");
     if (m->dtype != BXMG_F64) return fail(BXMG_EINVAL, std::string("solve: ") + name + " must be FP64");
     if (m->ng < 1) return fail(BXMG_EINVAL, std::string("solve: ") + name + " needs nghost >= 1");
+    return BXMG_OK;
+}
+
+// A field read at valid cells only (a source term): same boxes, FP64, any ghost width
+inline bxmg_status check_field_mf(bxmg_multifab m, const bxmg_ba_s* ba, const char* name) {
+    if (m->ba != ba && (m->ba->boxes.size() != ba->boxes.size() ||
+                        std::memcmp(m->ba->boxes.data(), ba->boxes.data(), ba->boxes.size() * sizeof(Box)) != 0))
+        return fail(BXMG_EINVAL, std::string("solve: ") + name + " is on a different BoxArray");
+    if (m->dtype != BXMG_F64) return fail(BXMG_EINVAL, std::string("solve: ") + name + " must be FP64");
     return BXMG_OK;
 }
 

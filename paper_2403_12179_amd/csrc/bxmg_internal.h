@@ -32,6 +32,7 @@ struct RBox {
     long long base;    // element offset of colour 0
     long long cstride; // elements between colour 0 and colour 1
     double h;          // grid spacing of the box's level
+    double a;          // Helmholtz coefficient alpha: the operator is div(beta grad u) - alpha u
     int nb[6];
     int shift[6];
 };
@@ -247,6 +248,10 @@ hipError_t launch_fab_to_rb(hipStream_t s, const Grid& g, const double* fab, con
 // launch_fab_to_rb (FP64) and launch_field_norm of the result in one pass
 hipError_t launch_fab_to_rb_norm(hipStream_t s, const Grid& g, const double* fab, const FBox* fb, double* rb,
                                 double* partials);
+// Heat-step right-hand side f = -(u * inv_dt + s) (s == NULL: no source) from
+// caller MultiFabs into level storage, with the norms of f per tile.
+hipError_t launch_heat_rhs(hipStream_t s, const Grid& g, const double* u, const FBox* fu, const double* src,
+                           const FBox* fs, double inv_dt, double* f, double* partials);
 hipError_t launch_rb_to_fab(hipStream_t s, const Grid& g, const double* rb, double* fab, const FBox* fb);
 hipError_t launch_add_f32(hipStream_t s, const Grid& g, double* u, const float* e);
 
@@ -262,8 +267,8 @@ hipError_t launch_faces_coarsen(hipStream_t s, FaceArrays<T> fine, FaceArrays<T>
 // bottom: one workgroup, FP64 CG in LDS
 template <class T>
 hipError_t launch_bottom(hipStream_t s, T* u, const T* f, FaceArrays<T> fa, bool var, const RBox* boxes, int nboxes,
-                         const int* dom_lo, const int* dom_hi, const int* periodic, double h, double rtol,
-                         int* iters_out);
+                         const int* dom_lo, const int* dom_hi, const int* periodic, double h, double alpha,
+                         double rtol, int* iters_out);
 
 // the fused coarse V-cycle, one workgroup per descriptor cc[0..n); with
 // active != nullptr a descriptor whose problem slot is inactive is skipped;

@@ -62,6 +62,13 @@ __device__ __forceinline__ T harm(T a, T b) {
     return (a * b) * T(2) / (a + b);
 }
 
+// alpha h^2: the Helmholtz term's addition to the stencil's diagonal weight
+// sb (an exact zero for Poisson)
+template <class T>
+__device__ __forceinline__ T diag_shift(const RBox& B) {
+    return (T)(B.a * (B.h * B.h));
+}
+
 // Block -> tile: XCD x (= block % 8) receives tiles [x*n/8, (x+1)*n/8),
 // walked upwards, or downwards when rev != 0.  Consecutive launches over a
 // level alternate the direction, so each starts on the data the previous
@@ -195,6 +202,7 @@ __device__ __forceinline__ void stencil(const T* __restrict__ u, const T* __rest
     idx = gather<T, MODE, true>(u, beta, fa, B, i, j, k, n);
     uc = n.c;
     sums<T, MODE>(n, su, sb);
+    sb = sb + diag_shift<T>(B);
 }
 
 // Raw-buffer access to the colour blocks of one box: a resource descriptor
@@ -481,6 +489,7 @@ __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const 
     if constexpr (MODE == 2) fa = fat[B.pid];
     const T h2 = (T)(B.h * B.h);
     const T ih2 = (T)(1.0 / (B.h * B.h));
+    const T dg = diag_shift<T>(B);
     const TileThread th = tile_thread(tl);
     const int j = B.lo[1] + th.y;
     const long long ne = 2 * B.cstride;
@@ -514,6 +523,7 @@ __global__ void __launch_bounds__(kBlock) k_gs(Grid g, T* __restrict__ u, const 
             }
             T su, sb;
             sums<T, MODE>(nb, su, sb);
+            sb = sb + dg;
             const T v = (su - h2 * fv) / sb;
             if constexpr (RES) U.st((int)idx, v);
             else u[idx] = v;
@@ -565,6 +575,7 @@ __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ 
     FaceArrays<T> fa;
     if constexpr (MODE == 2) fa = fat[B.pid];
     const T ih2 = (T)(1.0 / (B.h * B.h));
+    const T dg = diag_shift<T>(B);
     const TileThread th = tile_thread(tl);
     const int j = B.lo[1] + th.y;
     const long long ne = 2 * B.cstride;
@@ -608,6 +619,7 @@ __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ 
                 if (!ok[c]) continue;
                 T su, sb;
                 sums<T, MODE>(nb[c], su, sb);
+                sb = sb + dg;
                 const T rv = fv[c] - (su - sb * nb[c].c) * ih2;
                 if (r) {
                     if constexpr (RES) Rr.st((int)idx[c], (R)rv);
@@ -711,6 +723,41 @@ __global__ void __launch_bounds__(kBlock) k_fab_to_rb_norm(Grid g, const double*
     }
 }
 
+// Heat-step right-hand side: f = -((u * inv_dt) + s) at every valid cell,
+// written into level storage, with its norms (as k_fab_to_rb_norm).
+__global__ void __launch_bounds__(kBlock) k_heat_rhs(Grid g, const double* __restrict__ u,
+                                                    const FBox* __restrict__ fu, const double* __restrict__ src,
+                                                    const FBox* __restrict__ fs, double inv_dt,
+                                                    double* __restrict__ rb, double* __restrict__ partials) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    const Tile tl = g.tiles[tile_index(g.rev)];
+    const RBox B = g.boxes[tl.box];
+    const FBox F = fu[tl.box];
+    const TileThread th = tile_thread(tl);
+    const int j = B.lo[1] + th.y;
+    if (j <= B.hi[1])
+        for (int z = 0; z < (int)tl.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            if (k > B.hi[2]) break;
+            for (int c = 0; c < 2; ++c) {
+                const int i = colour_i(B, th.x, j, k, c);
+                if (i > B.hi[0]) continue;
+                double t = u[fab_idx(F, i, j, k)] * inv_dt;
+                if (src) t = t + src[fab_idx(fs[tl.box], i, j, k)];
+                const double v = -t;
+                rb[rb_idx(B, i, j, k)] = v;
+                acc_norm(v, mx, s2, bad);
+            }
+        }
+    block_reduce3(mx, s2, bad, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * blockIdx.x] = mx;
+        partials[3 * blockIdx.x + 1] = s2;
+        partials[3 * blockIdx.x + 2] = bad;
+    }
+}
+
 // ---------------------------------------------------------- fine <-> coarse
 // Coarse cell (I, J, K) of the tile's fine box, or false past its end.
 struct CoarseCell {
@@ -743,6 +790,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(XGrid x, const T* __r
     FaceArrays<T> fa;
     if constexpr (MODE == 2) fa = fat[B.pid];
     const T ih2 = (T)(1.0 / (B.h * B.h));
+    const T dg = diag_shift<T>(B);
     const RBox C = x.cboxes[x.cbox[tl.box]];
     const TileThread th = tile_thread(tl);
     const int I = (B.lo[0] >> 1) + th.x, J = (B.lo[1] >> 1) + th.y;
@@ -806,6 +854,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(XGrid x, const T* __r
                         }
                         T su, sb;
                         sums<T, MODE>(n, su, sb);
+                        sb = sb + dg;
                         r[a - 1][b - 1][c - 1] = fv[a - 1][b - 1][c - 1] - (su - sb * n.c) * ih2;
                     }
             const T s = ((r[0][0][0] + r[1][0][0]) + (r[0][1][0] + r[1][1][0])) +
@@ -1521,6 +1570,7 @@ struct BottomGeom {
     int dlo[3], n[3];
     int per[3];
     int nboxes;
+    double a;  // Helmholtz coefficient (0: Poisson; a fully periodic bottom is then singular)
 };
 
 __device__ __forceinline__ double bot_reduce(double v, double* sh) {
@@ -1577,7 +1627,8 @@ __device__ void bottom_cg(T* __restrict__ u, const T* __restrict__ f, const Face
         }
     }
     __syncthreads();
-    const bool sing = G.per[0] && G.per[1] && G.per[2];
+    const bool sing = G.per[0] && G.per[1] && G.per[2] && G.a == 0.0;
+    const double dg = G.a * (h * h);
     if (sing) {
         double s = 0.0;
         for (int n = threadIdx.x; n < N; n += blockDim.x) s = s + r[n];
@@ -1638,7 +1689,7 @@ __device__ void bottom_cg(T* __restrict__ u, const T* __restrict__ f, const Face
                     sb = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
                     su = ((bxm * pxm + bxp * pxp) + (bym * pym + byp * pyp)) + (bzm * pzm + bzp * pzp);
                 }
-                const double qv = (su - sb * p[pc]) * ih2;
+                const double qv = (su - (sb + dg) * p[pc]) * ih2;
                 q[n] = qv;
                 pAp = pAp + p[pc] * qv;
             }
@@ -1724,7 +1775,8 @@ __device__ void bottom_cg_wave(T* __restrict__ u, const T* __restrict__ f, const
             G.dlo[1] + b <= B.hi[1] && G.dlo[2] + c >= B.lo[2] && G.dlo[2] + c <= B.hi[2])
             r = (double)f[rb_idx(B, G.dlo[0] + a, G.dlo[1] + b, G.dlo[2] + c)];
     }
-    const bool sing = G.per[0] && G.per[1] && G.per[2];
+    const bool sing = G.per[0] && G.per[1] && G.per[2] && G.a == 0.0;
+    const double dg = G.a * (h * h);
     if (sing) {
         const double mean = wave_sum(r) / (double)N;
         if (mine) r = r - mean;
@@ -1777,7 +1829,7 @@ __device__ void bottom_cg_wave(T* __restrict__ u, const T* __restrict__ f, const
                     sb = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
                     su = ((bxm * pxm + bxp * pxp) + (bym * pym + byp * pyp)) + (bzm * pzm + bzp * pzp);
                 }
-                qv = (su - sb * pv) * ih2;
+                qv = (su - (sb + dg) * pv) * ih2;
             }
             const double pAp = wave_sum(pv * qv);
             const double alpha = rs / pAp;
@@ -1972,6 +2024,7 @@ __device__ void blk_gs(const LevelData<T, LDS>& D, int colour) {
     const RBox& B = D.L.box;
     const BoxCells bc = box_cells(B);
     const T h2 = (T)(D.L.h * D.L.h);
+    const T dg = diag_shift<T>(B);
     for (int g = threadIdx.x; g < bc.n; g += blockDim.x) {
         int i, j, k;
         if (!box_colour_cell(B, bc, g, colour, i, j, k)) continue;
@@ -1979,6 +2032,7 @@ __device__ void blk_gs(const LevelData<T, LDS>& D, int colour) {
         const int idx = blk_gather<T, MODE, false>(D.u, D.L.fa, B, i, j, k, nb);
         T su, sb;
         sums<T, MODE>(nb, su, sb);
+        sb = sb + dg;
         const T v = (su - h2 * D.f.ld(idx)) / sb;
         D.u.st(idx, v);
         if (D.L.push) blk_push(D.u, B, i, j, k, v);
@@ -2002,6 +2056,7 @@ __device__ void blk_resid_restrict(const LevelData<T, LDS>& F, const LevelData<T
     const int n = cnx * cny * cnz;
     const float rnx = 1.0f / (float)cnx, rny = 1.0f / (float)cny;
     const T ih2 = (T)(1.0 / (F.L.h * F.L.h));
+    const T dg = diag_shift<T>(B);
     for (int g = threadIdx.x; g < n; g += blockDim.x) {
         int gy, gx, gz, gyy;
         small_divmod(g, cnx, rnx, gy, gx);
@@ -2013,6 +2068,7 @@ __device__ void blk_resid_restrict(const LevelData<T, LDS>& F, const LevelData<T
             const int idx = blk_gather<T, MODE, true>(F.u, F.L.fa, B, a, b, c, nb);
             T su, sb;
             sums<T, MODE>(nb, su, sb);
+            sb = sb + dg;
             return F.f.ld(idx) - (su - sb * nb.c) * ih2;
         };
         const T r000 = ra(i, j, k), r100 = ra(i + 1, j, k), r010 = ra(i, j + 1, k), r110 = ra(i + 1, j + 1, k);
@@ -2114,6 +2170,7 @@ __global__ void __launch_bounds__(kBotThreads) k_coarse_cycle(const CoarseCycle<
             G.per[d] = cc.per[d];
         }
         G.nboxes = 1;
+        G.a = Lb.box.a;
         const int N = G.n[0] * G.n[1] * G.n[2];
         BottomLds S(bxmg_lds + cc.bot_off, N, (G.n[0] + 2) * (G.n[1] + 2) * (G.n[2] + 2));
         if (N <= kWaveBottomCells) {
@@ -2371,6 +2428,13 @@ hipError_t launch_fab_to_rb_norm(hipStream_t s, const Grid& g, const double* fab
     return hipGetLastError();
 }
 
+hipError_t launch_heat_rhs(hipStream_t s, const Grid& g, const double* u, const FBox* fu, const double* src,
+                           const FBox* fs, double inv_dt, double* f, double* partials) {
+    if (g.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_heat_rhs, dim3(g.ntiles), dim3(kBlock), 0, s, g, u, fu, src, fs, inv_dt, f, partials);
+    return hipGetLastError();
+}
+
 hipError_t launch_fab_to_rb(hipStream_t s, const Grid& g, const double* fab, const FBox* fb, void* rb, bool f32) {
     if (g.ntiles <= 0) return hipSuccess;
     if (f32) hipLaunchKernelGGL(k_fab_to_rb<float>, dim3(g.ntiles), dim3(kBlock), 0, s, g, fab, fb, (float*)rb);
@@ -2424,9 +2488,10 @@ template hipError_t launch_faces_coarsen<float>(hipStream_t, FaceArrays<float>, 
 
 template <class T>
 hipError_t launch_bottom(hipStream_t s, T* u, const T* f, FaceArrays<T> fa, bool var, const RBox* boxes, int nboxes,
-                         const int* dom_lo, const int* dom_hi, const int* periodic, double h, double rtol,
-                         int* iters_out) {
+                         const int* dom_lo, const int* dom_hi, const int* periodic, double h, double alpha,
+                         double rtol, int* iters_out) {
     BottomGeom G;
+    G.a = alpha;
     for (int d = 0; d < 3; ++d) {
         G.dlo[d] = dom_lo[d];
         G.n[d] = dom_hi[d] - dom_lo[d] + 1;
@@ -2447,9 +2512,9 @@ hipError_t launch_bottom(hipStream_t s, T* u, const T* f, FaceArrays<T> fa, bool
     return hipGetLastError();
 }
 template hipError_t launch_bottom<double>(hipStream_t, double*, const double*, FaceArrays<double>, bool, const RBox*,
-                                          int, const int*, const int*, const int*, double, double, int*);
+                                          int, const int*, const int*, const int*, double, double, double, int*);
 template hipError_t launch_bottom<float>(hipStream_t, float*, const float*, FaceArrays<float>, bool, const RBox*, int,
-                                         const int*, const int*, const int*, double, double, int*);
+                                         const int*, const int*, const int*, double, double, double, int*);
 
 template <class T>
 hipError_t launch_coarse_cycle(hipStream_t s, const CoarseCycle<T>* cc, int n, const int* active, bool var,
@@ -2649,6 +2714,7 @@ __global__ void __launch_bounds__(kBlock) k_kr_apply(Grid g, const double* __res
     const RBox B = g.boxes[tl.box];
     if (g.active && !g.active[B.pid]) return;
     const double ih2 = 1.0 / (B.h * B.h);
+    const double dg = diag_shift<double>(B);
     const FaceArrays<double> fa{};
     const TileThread th = tile_thread(tl);
     const int j = B.lo[1] + th.y;
@@ -2673,6 +2739,7 @@ __global__ void __launch_bounds__(kBlock) k_kr_apply(Grid g, const double* __res
                 if (!ok[c]) continue;
                 double su, sb;
                 sums<double, MODE>(nb[c], su, sb);
+                sb = sb + dg;
                 const double qv = (su - sb * nb[c].c) * ih2;
                 if constexpr (RES) Q.st((int)idx[c], qv);
                 else q[idx[c]] = qv;

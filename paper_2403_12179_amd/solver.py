@@ -57,6 +57,26 @@ def mlmg_solve(phi: MultiFab, rhs: MultiFab, beta: MultiFab | None = None, raise
     return res
 
 
+def heat_step(u: MultiFab, dt, beta: MultiFab | None = None, source: MultiFab | None = None, raise_on_error=True,
+              **params):
+    """One backward-Euler step of u_t = div(beta grad u) + source, in place
+    on u (a Helmholtz solve with alpha = 1/dt started from u).  params as
+    for mlmg_solve (alpha is set by dt)."""
+    p = solve_params(**params)
+    info = L.SolveInfo()
+    st = L.lib().bxmg_heat_step(u.ctx._h, C.byref(p), u._h, source._h if source is not None else None,
+                                beta._h if beta is not None else None, float(dt), C.byref(info))
+    res = _result(info)
+    if raise_on_error and st not in (0, -4, -5):
+        L.check(st)
+    return res
+
+
+def heat_run(u: MultiFab, dt, nsteps, beta: MultiFab | None = None, source: MultiFab | None = None, **params):
+    """nsteps heat steps on the device-resident u; returns their results."""
+    return [heat_step(u, dt, beta, source, **params) for _ in range(int(nsteps))]
+
+
 def autotune(phi, rhs, beta=None, cycles=2, **params):
     """Time every candidate launch shape on this problem and keep the fastest
     on phi's context; returns the chosen knobs and the time per V-cycle.
