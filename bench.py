@@ -25,6 +25,8 @@ After the headline the same line carries, unless --sections says otherwise:
   mixed_precision : 512^3 variable coefficient in 512 boxes of 64^3, FP64
                     V-cycles vs FP32 V-cycles inside FP64 refinement vs
                     conjugate gradients preconditioned by the FP32 V-cycle
+  heat            : backward-Euler heat steps on the headline geometry, each
+                    a Helmholtz solve started from the previous state
   batched         : 256 periodic problems of edges 32..128, batch engine vs
                     plain FP64 solves one at a time
   serving         : an open-loop trace of 2000 requests (200/s), continuous
@@ -267,6 +269,46 @@ def section_mixed(bx, W, reps=3):
     out["speedup_mixed_over_fp64"] = out["fp64"]["ms_per_solve"] / out["fp32_in_fp64_ir"]["ms_per_solve"]
     out["speedup_pcg_over_fp64"] = out["fp64"]["ms_per_solve"] / out["pcg_fp32_vcycle"]["ms_per_solve"]
     del phi, rhs, bmf
+    torch.cuda.empty_cache()
+    return out, keep
+
+
+def section_heat(bx, W, steps=20, dt=1e-4):
+    """Backward-Euler heat steps u_t = lap u + s on the headline geometry
+    (256^3 in 512 boxes of 32^3, Dirichlet), s ~ U[-1,1] (seed 6), u0 = 0,
+    each step a Helmholtz solve (alpha = 1/dt, alpha h^2 = 0.15) to 1e-10
+    started from the previous state, FP64 V-cycles; the state stays on the
+    device.  Reported: time per step, cycles per step, fine-cell V-cycle
+    updates per second."""
+    import torch
+    n = N
+    ba = bx.BoxArray.chop((0, 0, 0), (n - 1,) * 3, MAX_BOX, bc=(bx.DIRICHLET0,) * 3)
+    src_t = W.uniform_rhs_device((n, n, n), 6)
+    src = bx.MultiFab(ba, nghost=0).from_tensor(src_t)
+    keep = {"n": n, "dt": dt, "src": host(src_t)}
+    del src_t
+    u = bx.MultiFab(ba).set_val(0.0)
+    bx.heat_run(u, dt, 2, source=src, rel_tol=TOL)
+    u.set_val(0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = []
+    for k in range(steps):
+        if k == steps - 1:
+            torch.cuda.synchronize()
+            t_last = time.perf_counter()
+            keep["u_prev"] = u.to_global()
+            t_skip = time.perf_counter() - t_last
+        res.append(bx.heat_step(u, dt, source=src, rel_tol=TOL))
+    torch.cuda.synchronize()
+    dt_run = time.perf_counter() - t0 - t_skip
+    keep["u"] = u.to_global()
+    cyc = [r.cycles for r in res]
+    out = {"workload": "heat_backward_euler_256c_512x32c_dirichlet_dt1e-4_tol1e-10", "steps": steps,
+           "ok": all(r.ok for r in res), "ms_per_step": 1000.0 * dt_run / steps,
+           "cycles_per_step_mean": sum(cyc) / len(cyc), "cycles_per_step": cyc,
+           "cell_updates_per_s": n ** 3 * sum(cyc) / dt_run, "alpha_h2": 1.0 / dt / n / n}
+    del u, src
     torch.cuda.empty_cache()
     return out, keep
 
@@ -646,7 +688,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--summarize-counters", metavar="DIR")
-    ap.add_argument("--sections", default="c1,mixed,batched,serving",
+    ap.add_argument("--sections", default="c1,mixed,heat,batched,serving",
                     help="other rows to measure after the headline (comma list; '' for none)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--no-autotune", action="store_true")
@@ -787,6 +829,8 @@ def main():
             line["c1"], keep["c1"] = section_c1(bx, W)
         elif name == "mixed":
             line["mixed_precision"], keep["mixed"] = section_mixed(bx, W)
+        elif name == "heat":
+            line["heat"], keep["heat"] = section_heat(bx, W)
         elif name == "batched":
             line["batched"], keep["batched"], keep["edges"] = section_batched(bx, W)
         elif name == "serving":
@@ -812,6 +856,14 @@ def main():
                                         u_ref=None if key == "fp64" else k["u"]["fp64"])
             line["mixed_precision"]["error_vs_oracle"] = chk
             del k
+        if "heat" in keep:
+            k = keep.pop("heat")
+            n, dt = k["n"], k["dt"]
+            f = -(k["u_prev"] * (1.0 / dt) + k["src"])
+            r = f - orc.apply_op((0, 0, 0), (n - 1,) * 3, (0, 0, 0), 1.0 / n, k["u"], None, 1.0 / dt)
+            line["heat"]["error_vs_oracle"] = {
+                "last_step_oracle_rel_resid_inf": float(np.max(np.abs(r)) / np.max(np.abs(f))), "tol": TOL}
+            del k, f, r
         if "batched" in keep:
             line["batched"]["error_vs_oracle"] = [
                 dict(problem=s["q"], edge=s["e"], gpu_cycles=s["cycles"],
