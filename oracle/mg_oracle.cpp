@@ -986,6 +986,310 @@ static int solve(const Params& P, const Geom& g0, const std::vector<Box>& b0, co
     return status;
 }
 
+
+
+// ====================================================== nodal Poisson
+// Node-centred data (the framework's other solver family, Section 2): on a
+// domain of n_d cells of width h per direction the nodes sit at x = i h,
+// i = 0 .. n_d.  A homogeneous-Dirichlet direction keeps its boundary nodes
+// (i = 0, n_d) at 0; they are not unknowns.  In a periodic direction node
+// n_d is node 0 (its value is kept equal to node 0's).  Arrays hold every
+// node of the domain, (n_0+1)(n_1+1)(n_2+1) values in F-order.
+//   operator    : (L u)_i = (sum of the 6 neighbours - 6 u_i) / h^2, summed as
+//                 ((x- + x+) + (y- + y+)) + (z- + z+)
+//   smoother    : red-black Gauss-Seidel over the unknown nodes, red =
+//                 (i+j+k) even first, u = (s - h^2 f) / 6
+//   coarsening  : coarse node I is fine node 2I, while every n_d is even and
+//                 > 2 (a Dirichlet n_d = 2 leaves one unknown node)
+//   restriction : full weighting, weights w(0) = 1/2, w(+-1) = 1/4 per
+//                 direction (their product over the 27 fine neighbours of 2I)
+//   prolongation: trilinear: fine node 2I + o (o in {0,1}^3) takes the mean
+//                 of the 2^|o| coarse nodes I + o' with o' <= o componentwise
+//   bottom      : FP64 CG on the unknowns, rel. L2 1e-12, at most 4 N
+//                 iterations; fully periodic: right-hand side projected to
+//                 mean 0, solution mean 0 (over the n_0 n_1 n_2 distinct nodes)
+namespace nodal {
+
+struct NGrid {
+    int n[3];     // cells per direction
+    int per[3];
+    double h;
+    long nx() const { return n[0] + 1; }
+    long size() const { return (long)(n[0] + 1) * (n[1] + 1) * (n[2] + 1); }
+    long idx(int i, int j, int k) const { return i + (long)(n[0] + 1) * (j + (long)(n[1] + 1) * k); }
+    // an unknown: not a Dirichlet boundary node, not the periodic copy n_d
+    bool unknown(int i, int j, int k) const {
+        const int c[3] = {i, j, k};
+        for (int d = 0; d < 3; ++d) {
+            if (per[d] ? c[d] == n[d] : (c[d] == 0 || c[d] == n[d])) return false;
+        }
+        return true;
+    }
+    // neighbour index along d by +-1, wrapped in periodic directions
+    int wrap(int d, int c) const {
+        if (!per[d]) return c;
+        if (c < 0) return c + n[d];
+        if (c >= n[d]) return c - n[d];
+        return c;
+    }
+    bool singular() const { return per[0] && per[1] && per[2]; }
+    NGrid coarse() const {
+        NGrid c = *this;
+        for (int d = 0; d < 3; ++d) c.n[d] = n[d] / 2;
+        c.h = h * 2.0;
+        return c;
+    }
+    bool coarsenable() const {
+        for (int d = 0; d < 3; ++d)
+            if (n[d] % 2 || n[d] <= 2) return false;
+        return true;
+    }
+};
+
+template <class F>
+static void for_unknowns(const NGrid& g, F fn) {
+    for (int k = 0; k <= g.n[2]; ++k)
+        for (int j = 0; j <= g.n[1]; ++j)
+            for (int i = 0; i <= g.n[0]; ++i)
+                if (g.unknown(i, j, k)) fn(i, j, k);
+}
+
+// sum of the six neighbours of an unknown node
+static double nsum(const NGrid& g, const std::vector<double>& u, int i, int j, int k) {
+    const double xm = u[g.idx(g.wrap(0, i - 1), j, k)], xp = u[g.idx(g.wrap(0, i + 1), j, k)];
+    const double ym = u[g.idx(i, g.wrap(1, j - 1), k)], yp = u[g.idx(i, g.wrap(1, j + 1), k)];
+    const double zm = u[g.idx(i, j, g.wrap(2, k - 1))], zp = u[g.idx(i, j, g.wrap(2, k + 1))];
+    return ((xm + xp) + (ym + yp)) + (zm + zp);
+}
+
+// the periodic copies n_d take the values of nodes 0 (after any update)
+static void sync_copies(const NGrid& g, std::vector<double>& u) {
+    for (int k = 0; k <= g.n[2]; ++k)
+        for (int j = 0; j <= g.n[1]; ++j)
+            for (int i = 0; i <= g.n[0]; ++i) {
+                int c[3] = {i, j, k};
+                bool copy = false;
+                for (int d = 0; d < 3; ++d)
+                    if (g.per[d] && c[d] == g.n[d]) { c[d] = 0; copy = true; }
+                if (copy) u[g.idx(i, j, k)] = u[g.idx(c[0], c[1], c[2])];
+            }
+}
+
+static void gs(const NGrid& g, std::vector<double>& u, const std::vector<double>& f, int colour) {
+    const double h2 = g.h * g.h;
+    for_unknowns(g, [&](int i, int j, int k) {
+        if (((i + j + k) & 1) != colour) return;
+        u[g.idx(i, j, k)] = (nsum(g, u, i, j, k) - h2 * f[g.idx(i, j, k)]) / 6.0;
+    });
+    sync_copies(g, u);
+}
+
+// r = f - L u at the unknowns (0 elsewhere); returns max |r| and sum r^2
+static void residual(const NGrid& g, const std::vector<double>& u, const std::vector<double>& f,
+                     std::vector<double>& r, double* rinf, double* rl2) {
+    const double ih2 = 1.0 / (g.h * g.h);
+    std::fill(r.begin(), r.end(), 0.0);
+    double mx = 0.0, s2 = 0.0;
+    bool bad = false;
+    for_unknowns(g, [&](int i, int j, int k) {
+        const long q = g.idx(i, j, k);
+        const double rv = f[q] - (nsum(g, u, i, j, k) - 6.0 * u[q]) * ih2;
+        r[q] = rv;
+        const double a = std::fabs(rv);
+        if (std::isnan(a)) bad = true;
+        else if (a > mx) mx = a;
+        s2 += rv * rv;
+    });
+    if (rinf) *rinf = bad ? std::nan("") : mx;
+    if (rl2) *rl2 = s2;
+}
+
+// full weighting of r onto the coarse unknowns
+static void restrict_fw(const NGrid& gf, const std::vector<double>& r, const NGrid& gc, std::vector<double>& fc) {
+    std::fill(fc.begin(), fc.end(), 0.0);
+    const double w[3] = {0.25, 0.5, 0.25};
+    for_unknowns(gc, [&](int I, int J, int K) {
+        double s = 0.0;
+        for (int c = -1; c <= 1; ++c)
+            for (int b = -1; b <= 1; ++b)
+                for (int a = -1; a <= 1; ++a) {
+                    const int i = gf.wrap(0, 2 * I + a), j = gf.wrap(1, 2 * J + b), k = gf.wrap(2, 2 * K + c);
+                    s += ((w[a + 1] * w[b + 1]) * w[c + 1]) * r[gf.idx(i, j, k)];
+                }
+        fc[gc.idx(I, J, K)] = s;
+    });
+    sync_copies(gc, fc);
+}
+
+// u_f += P e_c (trilinear) at the fine unknowns
+static void prolong_add(const NGrid& gc, const std::vector<double>& e, const NGrid& gf, std::vector<double>& u) {
+    for_unknowns(gf, [&](int i, int j, int k) {
+        const int c[3] = {i, j, k};
+        int I[3], o[3];
+        for (int d = 0; d < 3; ++d) { I[d] = c[d] >> 1; o[d] = c[d] & 1; }
+        double s = 0.0;
+        int cnt = 0;
+        for (int cz = 0; cz <= o[2]; ++cz)
+            for (int cy = 0; cy <= o[1]; ++cy)
+                for (int cx = 0; cx <= o[0]; ++cx) {
+                    s += e[gc.idx(I[0] + cx, I[1] + cy, I[2] + cz)];
+                    ++cnt;
+                }
+        u[gf.idx(i, j, k)] += s / (double)cnt;
+    });
+    sync_copies(gf, u);
+}
+
+static double dotu(const NGrid& g, const std::vector<double>& a, const std::vector<double>& b) {
+    double s = 0.0;
+    for_unknowns(g, [&](int i, int j, int k) { s += a[g.idx(i, j, k)] * b[g.idx(i, j, k)]; });
+    return s;
+}
+
+static long nunknowns(const NGrid& g) {
+    long n = 0;
+    for_unknowns(g, [&](int, int, int) { ++n; });
+    return n;
+}
+
+static double mean_unknowns(const NGrid& g, const std::vector<double>& a) {
+    double s = 0.0;
+    for_unknowns(g, [&](int i, int j, int k) { s += a[g.idx(i, j, k)]; });
+    return s / (double)nunknowns(g);
+}
+
+static void add_unknowns(const NGrid& g, std::vector<double>& a, double c) {
+    for_unknowns(g, [&](int i, int j, int k) { a[g.idx(i, j, k)] += c; });
+    sync_copies(g, a);
+}
+
+// L u at the unknowns (0 elsewhere)
+static void apply(const NGrid& g, const std::vector<double>& u, std::vector<double>& Lu) {
+    const double ih2 = 1.0 / (g.h * g.h);
+    std::fill(Lu.begin(), Lu.end(), 0.0);
+    for_unknowns(g, [&](int i, int j, int k) {
+        const long q = g.idx(i, j, k);
+        Lu[q] = (nsum(g, u, i, j, k) - 6.0 * u[q]) * ih2;
+    });
+}
+
+static int bottom_cg(const NGrid& g, const std::vector<double>& f, std::vector<double>& x, double rtol) {
+    const long N = g.size();
+    std::vector<double> r(N, 0.0), p(N, 0.0), Ap(N, 0.0);
+    for_unknowns(g, [&](int i, int j, int k) { r[g.idx(i, j, k)] = f[g.idx(i, j, k)]; });
+    std::fill(x.begin(), x.end(), 0.0);
+    if (g.singular()) add_unknowns(g, r, -mean_unknowns(g, r));
+    p = r;
+    sync_copies(g, p);
+    double rs = dotu(g, r, r);
+    const double rs0 = rs;
+    int it = 0;
+    if (rs0 == 0.0) return 0;
+    const long maxit = 4 * nunknowns(g);
+    for (; it < maxit;) {
+        apply(g, p, Ap);
+        const double alpha = rs / dotu(g, p, Ap);
+        for_unknowns(g, [&](int i, int j, int k) {
+            const long q = g.idx(i, j, k);
+            x[q] += alpha * p[q];
+            r[q] -= alpha * Ap[q];
+        });
+        const double rsn = dotu(g, r, r);
+        ++it;
+        if (std::sqrt(rsn) <= rtol * std::sqrt(rs0)) break;
+        const double beta = rsn / rs;
+        for_unknowns(g, [&](int i, int j, int k) {
+            const long q = g.idx(i, j, k);
+            p[q] = r[q] + beta * p[q];
+        });
+        sync_copies(g, p);
+        rs = rsn;
+    }
+    if (g.singular()) add_unknowns(g, x, -mean_unknowns(g, x));
+    sync_copies(g, x);
+    return it;
+}
+
+struct NLevel {
+    NGrid g;
+    std::vector<double> u, f, r;
+};
+
+static void vcycle(std::vector<NLevel>& L, size_t l, int nu1, int nu2, double brtol) {
+    NLevel& F = L[l];
+    if (l + 1 == L.size()) {
+        bottom_cg(F.g, F.f, F.u, brtol);
+        return;
+    }
+    for (int s = 0; s < nu1; ++s) { gs(F.g, F.u, F.f, 0); gs(F.g, F.u, F.f, 1); }
+    residual(F.g, F.u, F.f, F.r, nullptr, nullptr);
+    NLevel& C = L[l + 1];
+    restrict_fw(F.g, F.r, C.g, C.f);
+    std::fill(C.u.begin(), C.u.end(), 0.0);
+    vcycle(L, l + 1, nu1, nu2, brtol);
+    prolong_add(C.g, C.u, F.g, F.u);
+    for (int s = 0; s < nu2; ++s) { gs(F.g, F.u, F.f, 0); gs(F.g, F.u, F.f, 1); }
+}
+
+static std::vector<NLevel> hierarchy(const NGrid& g0) {
+    std::vector<NLevel> L;
+    NGrid g = g0;
+    for (;;) {
+        NLevel lv;
+        lv.g = g;
+        lv.u.assign(g.size(), 0.0);
+        lv.f.assign(g.size(), 0.0);
+        lv.r.assign(g.size(), 0.0);
+        L.push_back(std::move(lv));
+        if (!g.coarsenable()) break;
+        g = g.coarse();
+    }
+    return L;
+}
+
+// Driver as for the cell-centred solve: residual, stop test on the max-norm
+// relative to |f|_inf over the unknowns, one V(nu1, nu2) per cycle.
+static int solve(const NGrid& g0, int nu1, int nu2, int max_cycles, int fixed_cycles, double rel_tol,
+                 double brtol, const double* f_in, double* u_out, Info* info) {
+    std::memset(info, 0, sizeof(Info));
+    std::vector<NLevel> L = hierarchy(g0);
+    info->levels = (int)L.size();
+    NLevel& T = L[0];
+    for (long q = 0; q < g0.size(); ++q) T.f[q] = f_in[q];
+    double fnorm = 0.0;
+    bool bad = false;
+    for_unknowns(g0, [&](int i, int j, int k) {
+        const double a = std::fabs(T.f[g0.idx(i, j, k)]);
+        if (std::isnan(a)) bad = true;
+        else if (a > fnorm) fnorm = a;
+    });
+    info->f_inf = bad ? std::nan("") : fnorm;
+    int status = 0, cyc = 0;
+    if (bad) status = -5;
+    else if (fnorm > 0.0)
+        for (;; ++cyc) {
+            double rinf, rl2;
+            residual(g0, T.u, T.f, T.r, &rinf, &rl2);
+            if (cyc < 256) { info->hist[cyc] = rinf / fnorm; info->hist_l2[cyc] = std::sqrt(rl2); info->nhist = cyc + 1; }
+            info->rel_inf = rinf / fnorm;
+            info->rel_l2 = std::sqrt(rl2);
+            if (!std::isfinite(rinf)) { status = -5; break; }
+            if (fixed_cycles > 0) {
+                if (cyc == fixed_cycles) break;
+            } else {
+                if (rinf <= rel_tol * fnorm) break;
+                if (cyc == max_cycles) { status = -4; break; }
+            }
+            vcycle(L, 0, nu1, nu2, brtol);
+        }
+    info->cycles = cyc;
+    if (status == 0 && g0.singular()) add_unknowns(g0, T.u, -mean_unknowns(g0, T.u));
+    for (long q = 0; q < g0.size(); ++q) u_out[q] = T.u[q];
+    info->status = status;
+    return status;
+}
+
+}  // namespace nodal
 }  // namespace orc
 
 // ====================================================================== C API
@@ -1262,6 +1566,65 @@ int orc_bottom(const int* dom6, const int* per, double h, const double* f_glob, 
     gather_global(g.dom, x, u_glob);
     if (iters) *iters = st.iters;
     return 0;
+}
+
+// ---------------------------------------------------------------- nodal
+static nodal::NGrid ngrid(const int* n, const int* per, double h) {
+    nodal::NGrid g;
+    for (int d = 0; d < 3; ++d) { g.n[d] = n[d]; g.per[d] = per[d] ? 1 : 0; }
+    g.h = h;
+    return g;
+}
+
+// Node arrays are (n0+1)(n1+1)(n2+1) values in F-order.
+int orc_nodal_solve(const int* n, const int* per, double h, int nu1, int nu2, int max_cycles, int fixed_cycles,
+                    double rel_tol, double bottom_rtol, const double* f, double* u, Info* info) {
+    return nodal::solve(ngrid(n, per, h), nu1, nu2, max_cycles, fixed_cycles, rel_tol, bottom_rtol, f, u, info);
+}
+
+void orc_nodal_apply(const int* n, const int* per, double h, const double* u, double* Lu) {
+    nodal::NGrid g = ngrid(n, per, h);
+    std::vector<double> U(u, u + g.size()), A(g.size());
+    nodal::apply(g, U, A);
+    std::memcpy(Lu, A.data(), A.size() * sizeof(double));
+}
+
+void orc_nodal_gs(const int* n, const int* per, double h, int colour, double* u, const double* f) {
+    nodal::NGrid g = ngrid(n, per, h);
+    std::vector<double> U(u, u + g.size()), F(f, f + g.size());
+    nodal::gs(g, U, F, colour);
+    std::memcpy(u, U.data(), U.size() * sizeof(double));
+}
+
+void orc_nodal_residual(const int* n, const int* per, double h, const double* u, const double* f, double* r,
+                        double* norms) {
+    nodal::NGrid g = ngrid(n, per, h);
+    std::vector<double> U(u, u + g.size()), F(f, f + g.size()), R(g.size());
+    nodal::residual(g, U, F, R, &norms[0], &norms[1]);
+    std::memcpy(r, R.data(), R.size() * sizeof(double));
+}
+
+// fine grid n (even edges); the coarse grid has n/2 cells per direction
+void orc_nodal_restrict(const int* n, const int* per, const double* rf, double* fc) {
+    nodal::NGrid g = ngrid(n, per, 1.0), c = g.coarse();
+    std::vector<double> R(rf, rf + g.size()), F(c.size());
+    nodal::restrict_fw(g, R, c, F);
+    std::memcpy(fc, F.data(), F.size() * sizeof(double));
+}
+
+void orc_nodal_prolong_add(const int* n, const int* per, const double* ec, double* uf) {
+    nodal::NGrid g = ngrid(n, per, 1.0), c = g.coarse();
+    std::vector<double> E(ec, ec + c.size()), U(uf, uf + g.size());
+    nodal::prolong_add(c, E, g, U);
+    std::memcpy(uf, U.data(), U.size() * sizeof(double));
+}
+
+int orc_nodal_bottom(const int* n, const int* per, double h, const double* f, double* u, double rtol) {
+    nodal::NGrid g = ngrid(n, per, h);
+    std::vector<double> F(f, f + g.size()), X(g.size());
+    const int it = nodal::bottom_cg(g, F, X, rtol);
+    std::memcpy(u, X.data(), X.size() * sizeof(double));
+    return it;
 }
 
 }  // extern "C"

@@ -326,3 +326,83 @@ def heat_step(dom_lo, dom_hi, periodic, boxes, u_glob, dt, source=None, beta_glo
                     C.c_double(dt), _dp(s.ravel(order="F")) if s is not None else None,
                     _dp(b.ravel(order="F")) if b is not None else None, _dp(u.ravel(order="F")), C.byref(info))
     return u, _info_dict(info)
+
+
+# ------------------------------------------------------------------- nodal
+# Node arrays: (n0+1, n1+1, n2+1) values over the domain's nodes, F-order.
+
+def _nodal_args(n, periodic):
+    return _ip(_i32(n)), _ip(_i32(periodic))
+
+
+def nodal_shape(n):
+    return tuple(int(x) + 1 for x in n)
+
+
+def nodal_solve(n, periodic, f, h=None, nu1=2, nu2=2, max_cycles=200, fixed_cycles=0, rel_tol=1e-10,
+                bottom_rtol=1e-12):
+    """Nodal Poisson solve (FP64 V-cycles); returns (u, info dict)."""
+    L = lib()
+    f = np.asfortranarray(f, dtype=np.float64)
+    assert f.shape == nodal_shape(n)
+    h = 1.0 / n[0] if h is None else h
+    u = np.zeros(f.shape, order="F")
+    info = Info()
+    L.orc_nodal_solve(*_nodal_args(n, periodic), C.c_double(h), int(nu1), int(nu2), int(max_cycles),
+                      int(fixed_cycles), C.c_double(rel_tol), C.c_double(bottom_rtol), _dp(f.ravel(order="F")),
+                      _dp(u.ravel(order="F")), C.byref(info))
+    return u, _info_dict(info)
+
+
+def nodal_apply(n, periodic, h, u):
+    L = lib()
+    u = np.asfortranarray(u, dtype=np.float64)
+    out = np.zeros(u.shape, order="F")
+    L.orc_nodal_apply(*_nodal_args(n, periodic), C.c_double(h), _dp(u.ravel(order="F")), _dp(out.ravel(order="F")))
+    return out
+
+
+def nodal_gs(n, periodic, h, colour, u, f):
+    L = lib()
+    u = np.array(u, dtype=np.float64, order="F", copy=True)
+    f = np.asfortranarray(f, dtype=np.float64)
+    L.orc_nodal_gs(*_nodal_args(n, periodic), C.c_double(h), int(colour), _dp(u.ravel(order="F")),
+                   _dp(f.ravel(order="F")))
+    return u
+
+
+def nodal_residual(n, periodic, h, u, f):
+    L = lib()
+    u = np.asfortranarray(u, dtype=np.float64)
+    f = np.asfortranarray(f, dtype=np.float64)
+    r = np.zeros(u.shape, order="F")
+    norms = np.zeros(2)
+    L.orc_nodal_residual(*_nodal_args(n, periodic), C.c_double(h), _dp(u.ravel(order="F")), _dp(f.ravel(order="F")),
+                         _dp(r.ravel(order="F")), _dp(norms))
+    return r, norms[0], norms[1]
+
+
+def nodal_restrict(n, periodic, rf):
+    L = lib()
+    rf = np.asfortranarray(rf, dtype=np.float64)
+    fc = np.zeros(nodal_shape([x // 2 for x in n]), order="F")
+    L.orc_nodal_restrict(*_nodal_args(n, periodic), _dp(rf.ravel(order="F")), _dp(fc.ravel(order="F")))
+    return fc
+
+
+def nodal_prolong_add(n, periodic, ec, uf):
+    """uf (fine grid of n cells) += P ec (coarse grid of n/2 cells)."""
+    L = lib()
+    ec = np.asfortranarray(ec, dtype=np.float64)
+    uf = np.array(uf, dtype=np.float64, order="F", copy=True)
+    L.orc_nodal_prolong_add(*_nodal_args(n, periodic), _dp(ec.ravel(order="F")), _dp(uf.ravel(order="F")))
+    return uf
+
+
+def nodal_bottom(n, periodic, h, f, rtol=1e-12):
+    L = lib()
+    f = np.asfortranarray(f, dtype=np.float64)
+    u = np.zeros(f.shape, order="F")
+    it = L.orc_nodal_bottom(*_nodal_args(n, periodic), C.c_double(h), _dp(f.ravel(order="F")),
+                            _dp(u.ravel(order="F")), C.c_double(rtol))
+    return u, it
