@@ -230,6 +230,23 @@ bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_
 bxmg_status bxmg_heat_step(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab u, bxmg_multifab source,
                            bxmg_multifab beta, double dt, bxmg_solve_info* info);
 
+/* Nodal-centred Poisson solve (the framework's nodal linear solver, paper
+ * Section 2): div grad phi = rhs for data at the nodes x = i h, i = 0 .. n_d,
+ * of the BoxArray's domain (n_d cells per direction; the solve runs on the
+ * whole domain at once, whatever the boxes).  phi and rhs: device arrays of
+ * (n_0+1)(n_1+1)(n_2+1) FP64 values, F-order, the domain's lower node first;
+ * phi holds the initial guess on entry and the solution on return.  A
+ * homogeneous-Dirichlet direction keeps its boundary nodes at 0 (they are
+ * not unknowns, rhs is not read there); in a periodic direction node n_d is
+ * node 0 (its values are overwritten with node 0's on return), and a fully
+ * periodic problem returns the mean-zero solution over the n_0 n_1 n_2
+ * distinct nodes.  7-point operator, red-black GS on node parity, full
+ * weighting and trilinear transfers, FP64 CG bottom; params as for
+ * bxmg_mlmg_solve with precision 0, krylov 0 and alpha 0 only (EINVAL
+ * otherwise).  Synchronous. */
+bxmg_status bxmg_nodal_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_boxarray ba, double* phi,
+                             const double* rhs, bxmg_solve_info* info);
+
 /* -------------------------------------------------------------- tuning --- */
 /* Launch-shape knobs for hierarchies built after the call (hierarchies are
  * cached per knob setting): param 0 = planes each thread walks in the cell

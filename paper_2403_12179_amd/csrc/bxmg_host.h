@@ -607,6 +607,7 @@ struct bxmg_ctx_s {
     double* h_norm = nullptr;  // pinned
     void* h_solve = nullptr;   // pinned: a solve's stop-test state read back (history, slot, flag)
     void* scratch = nullptr;   // the device's staging array (scratch_address), kScratchBytes
+    std::shared_ptr<void> nodal;  // nodal-solver hierarchies (bxmg_nodal.hip)
     std::mutex mu;
 };
 

@@ -77,6 +77,34 @@ def heat_run(u: MultiFab, dt, nsteps, beta: MultiFab | None = None, source: Mult
     return [heat_step(u, dt, beta, source, **params) for _ in range(int(nsteps))]
 
 
+def nodal_solve(ba, phi, rhs, raise_on_error=True, **params):
+    """Nodal-centred Poisson solve on ba's domain, in place on phi.  phi and
+    rhs: contiguous float64 CUDA tensors of shape (n2+1, n1+1, n0+1), i.e.
+    indexed [k, j, i] (the F-order node arrays of bxmg_nodal_solve); phi
+    holds the initial guess.  params as for mlmg_solve."""
+    shape = tuple(ba.domain.size[d] + 1 for d in (2, 1, 0))
+    for t in (phi, rhs):
+        if tuple(t.shape) != shape or not t.is_contiguous() or t.element_size() != 8 or not t.is_cuda:
+            raise ValueError("nodal arrays must be contiguous float64 CUDA tensors of shape %s" % (shape,))
+    p = solve_params(**params)
+    info = L.SolveInfo()
+    ctx = _ctx_of(phi)
+    st = L.lib().bxmg_nodal_solve(ctx._h, C.byref(p), ba._h, C.c_void_p(phi.data_ptr()), C.c_void_p(rhs.data_ptr()),
+                                  C.byref(info))
+    res = _result(info)
+    if raise_on_error and st not in (0, -4, -5):
+        L.check(st)
+    return res
+
+
+def _ctx_of(t):
+    from .core import default_context
+    ctx = default_context()
+    if ctx.device != t.device.index:
+        raise ValueError("tensor on another device than the default context")
+    return ctx
+
+
 def autotune(phi, rhs, beta=None, cycles=2, **params):
     """Time every candidate launch shape on this problem and keep the fastest
     on phi's context; returns the chosen knobs and the time per V-cycle.
