@@ -1374,6 +1374,50 @@ void orc_fill_boundary(const int* dom6, const int* per, int nb, const int* lohi,
     }
 }
 
+// ParallelCopy between two decompositions of one domain (paper, Section 2:
+// copies from one distribution to another): every cell of a destination box
+// grown by ngc (<= ngd) that, wrapped into the domain through its periodic
+// directions, lies in the valid region of a source box takes that cell's
+// value, components [scomp, scomp+ncomp) into [dcomp, dcomp+ncomp); other
+// cells keep theirs.  Brute force: the owner of every domain cell.
+void orc_parallel_copy(const int* dom6, const int* per, int nbd, const int* lohid, int ngd, int ncd, int ngc,
+                       int nbs, const int* lohis, int ngs, int ncs, int dcomp, int scomp, int ncomp, double* dst,
+                       const double* src) {
+    Geom g = geom_of(dom6, per, 1.0);
+    const std::vector<Box> bd = boxes_of(nbd, lohid), bs = boxes_of(nbs, lohis);
+    const std::vector<int> own = owner_map(g, bs);
+    const Box& D = g.dom;
+    for (int c = 0; c < ncomp; ++c) {
+        MF<double> S, T;
+        S.define(bs, ngs);
+        T.define(bd, ngd);
+        unpack(S, src, scomp + c, ncs);
+        unpack(T, dst, dcomp + c, ncd);
+        for (size_t b = 0; b < bd.size(); ++b) {
+            Fab<double>& F = T.f[b];
+            const Box& B = bd[b];
+            for (int k = B.lo[2] - ngc; k <= B.hi[2] + ngc; ++k)
+                for (int j = B.lo[1] - ngc; j <= B.hi[1] + ngc; ++j)
+                    for (int i = B.lo[0] - ngc; i <= B.hi[0] + ngc; ++i) {
+                        int w[3] = {i, j, k};
+                        bool inside = true;
+                        for (int d = 0; d < 3; ++d)
+                            if (w[d] < D.lo[d] || w[d] > D.hi[d]) {
+                                if (g.per[d]) w[d] = D.lo[d] + pmod(w[d] - D.lo[d], D.n(d));
+                                else inside = false;
+                            }
+                        if (!inside) continue;
+                        const size_t q = (size_t)(w[0] - D.lo[0]) +
+                                         (size_t)D.n(0) * ((size_t)(w[1] - D.lo[1]) + (size_t)D.n(1) * (w[2] - D.lo[2]));
+                        const int o = own[q];
+                        if (o < 0) continue;
+                        F(i, j, k) = S.f[o](w[0], w[1], w[2]);
+                    }
+        }
+        pack(T, dst, dcomp + c, ncd);
+    }
+}
+
 void orc_apply_bc(const int* dom6, const int* per, int nb, const int* lohi, int ng, int ncomp, int odd, double* data) {
     MF<double> mf;
     mf.define(boxes_of(nb, lohi), ng);

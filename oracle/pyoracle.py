@@ -406,3 +406,17 @@ def nodal_bottom(n, periodic, h, f, rtol=1e-12):
     it = L.orc_nodal_bottom(*_nodal_args(n, periodic), C.c_double(h), _dp(f.ravel(order="F")),
                             _dp(u.ravel(order="F")), C.c_double(rtol))
     return u, it
+
+
+def parallel_copy(dom_lo, dom_hi, periodic, dst_boxes, dst_ng, dst, src_boxes, src_ng, src, ncomp=1,
+                  dst_ncomp=1, src_ncomp=1, dcomp=0, scomp=0, copy_ng=0):
+    """ParallelCopy from a packed source (src_boxes, src_ng, src_ncomp
+    components) into a copy of a packed destination; returns the result."""
+    L = lib()
+    out = np.array(dst, dtype=np.float64, copy=True)
+    src = np.ascontiguousarray(src, dtype=np.float64)
+    assert out.size == packed_size(dst_boxes, dst_ng, dst_ncomp) and src.size == packed_size(src_boxes, src_ng, src_ncomp)
+    L.orc_parallel_copy(_ip(dom6(dom_lo, dom_hi)), _ip(_i32(periodic)), len(dst_boxes), _ip(lohi_array(dst_boxes)),
+                        int(dst_ng), int(dst_ncomp), int(copy_ng), len(src_boxes), _ip(lohi_array(src_boxes)),
+                        int(src_ng), int(src_ncomp), int(dcomp), int(scomp), int(ncomp), _dp(out), _dp(src))
+    return out
