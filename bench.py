@@ -27,6 +27,8 @@ After the headline the same line carries, unless --sections says otherwise:
                     conjugate gradients preconditioned by the FP32 V-cycle
   heat            : backward-Euler heat steps on the headline geometry, each
                     a Helmholtz solve started from the previous state
+  nodal           : the nodal Poisson solver on the 257^3 nodes of the
+                    headline domain
   batched         : 256 periodic problems of edges 32..128, batch engine vs
                     plain FP64 solves one at a time
   serving         : an open-loop trace of 2000 requests (200/s), continuous
@@ -309,6 +311,37 @@ def section_heat(bx, W, steps=20, dt=1e-4):
            "cycles_per_step_mean": sum(cyc) / len(cyc), "cycles_per_step": cyc,
            "cell_updates_per_s": n ** 3 * sum(cyc) / dt_run, "alpha_h2": 1.0 / dt / n / n}
     del u, src
+    torch.cuda.empty_cache()
+    return out, keep
+
+
+def section_nodal(bx, W, reps=3):
+    """Nodal Poisson on the nodes of the 256^3 domain (257^3 values),
+    homogeneous Dirichlet, f ~ U[-1,1] (seed 7, drawn on the device), FP64
+    V(2,2) to 1e-10."""
+    import torch
+    n = N
+    ba = bx.BoxArray.chop((0, 0, 0), (n - 1,) * 3, MAX_BOX, bc=(bx.DIRICHLET0,) * 3)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    rhs = torch.rand((n + 1,) * 3, generator=g, device="cuda", dtype=torch.float64) * 2.0 - 1.0
+    phi = torch.zeros_like(rhs)
+    bx.nodal_solve(ba, phi, rhs, rel_tol=TOL)
+    times = []
+    for _ in range(reps):
+        phi.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = bx.nodal_solve(ba, phi, rhs, rel_tol=TOL)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = 1000.0 * min(times)
+    out = {"workload": "nodal_poisson_257^3_nodes_dirichlet_fp64_tol1e-10", "ok": res.ok, "cycles": res.cycles,
+           "ms_per_solve": ms, "node_updates_per_s": (n - 1) ** 3 * res.cycles / (ms / 1000.0),
+           "final_rel_resid_inf": res.rel_resid_inf}
+    keep = {"n": n, "f": np.asfortranarray(rhs.cpu().numpy().transpose(2, 1, 0)),
+            "u": np.asfortranarray(phi.cpu().numpy().transpose(2, 1, 0))}
+    del phi, rhs
     torch.cuda.empty_cache()
     return out, keep
 
@@ -688,7 +721,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--summarize-counters", metavar="DIR")
-    ap.add_argument("--sections", default="c1,mixed,heat,batched,serving",
+    ap.add_argument("--sections", default="c1,mixed,heat,nodal,batched,serving",
                     help="other rows to measure after the headline (comma list; '' for none)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--no-autotune", action="store_true")
@@ -831,6 +864,8 @@ def main():
             line["mixed_precision"], keep["mixed"] = section_mixed(bx, W)
         elif name == "heat":
             line["heat"], keep["heat"] = section_heat(bx, W)
+        elif name == "nodal":
+            line["nodal"], keep["nodal"] = section_nodal(bx, W)
         elif name == "batched":
             line["batched"], keep["batched"], keep["edges"] = section_batched(bx, W)
         elif name == "serving":
@@ -864,6 +899,14 @@ def main():
             line["heat"]["error_vs_oracle"] = {
                 "last_step_oracle_rel_resid_inf": float(np.max(np.abs(r)) / np.max(np.abs(f))), "tol": TOL}
             del k, f, r
+        if "nodal" in keep:
+            k = keep.pop("nodal")
+            n = k["n"]
+            r = (k["f"] - orc.nodal_apply((n, n, n), (0, 0, 0), 1.0 / n, k["u"]))[1:-1, 1:-1, 1:-1]
+            line["nodal"]["error_vs_oracle"] = {
+                "oracle_rel_resid_inf": float(np.max(np.abs(r)) / np.max(np.abs(k["f"][1:-1, 1:-1, 1:-1]))),
+                "tol": TOL}
+            del k, r
         if "batched" in keep:
             line["batched"]["error_vs_oracle"] = [
                 dict(problem=s["q"], edge=s["e"], gpu_cycles=s["cycles"],

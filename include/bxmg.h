@@ -146,6 +146,18 @@ void bxmg_multifab_release(bxmg_multifab mf);
  * `hip_stream`. */
 bxmg_status bxmg_fill_boundary(bxmg_multifab mf, int32_t scomp, int32_t ncomp, int32_t cross, void* hip_stream);
 
+/* ParallelCopy (paper, Section 2: copies from one distribution to another):
+ * dst and src are MultiFabs over BoxArrays of the same domain and boundary
+ * conditions, decomposed differently, of one dtype.  Every cell of a dst box
+ * grown by dst_nghost (0 .. dst's nghost) that -- wrapped into the domain
+ * through the periodic directions -- lies in the valid region of a src box
+ * takes that cell's value, components [scomp, scomp+ncomp) into
+ * [dcomp, dcomp+ncomp); other dst cells keep their values.  One fused
+ * launch over a region list cached on dst per source BoxArray and width.
+ * Asynchronous on hip_stream (NULL = dst's context stream). */
+bxmg_status bxmg_parallel_copy(bxmg_multifab dst, int32_t dcomp, bxmg_multifab src, int32_t scomp, int32_t ncomp,
+                               int32_t dst_nghost, void* hip_stream);
+
 /* Physical boundary ghosts (homogeneous Dirichlet): every ghost cell outside
  * a non-periodic domain face takes s * (mirror cell), the mirror reflected
  * across every such face (index -1-t -> t below, n+t -> n-1-t above); s = -1

@@ -66,6 +66,7 @@ def _declare(lib):
         "bxmg_fill_boundary": (C.c_int, [H, C.c_int32, C.c_int32, C.c_int32, VP]),
         "bxmg_apply_domain_bc": (C.c_int, [H, C.c_int32, C.c_int32, C.c_int32, VP]),
         "bxmg_fill_boundary_noalloc": (C.c_int, [H, C.c_int32, C.c_int32, C.c_int32, VP]),
+        "bxmg_parallel_copy": (C.c_int, [H, C.c_int32, H, C.c_int32, C.c_int32, C.c_int32, VP]),
         "bxmg_solve_params_default": (None, [C.POINTER(SolveParams)]),
         "bxmg_mlmg_solve": (C.c_int, [H, C.POINTER(SolveParams), H, H, H, C.POINTER(SolveInfo)]),
         "bxmg_heat_step": (C.c_int, [H, C.POINTER(SolveParams), H, H, H, C.c_double, C.POINTER(SolveInfo)]),

@@ -312,6 +312,15 @@ class MultiFab:
         L.check(L.lib().bxmg_fill_boundary(self._h, scomp, ncomp, int(bool(cross)), C.c_void_p(s)))
         return self
 
+    def parallel_copy(self, src, scomp=0, dcomp=0, ncomp=None, nghost=0, stream=None):
+        """ParallelCopy from src (another decomposition of the same domain)
+        into this MultiFab's cells grown by nghost."""
+        ncomp = min(self.ncomp - dcomp, src.ncomp - scomp) if ncomp is None else ncomp
+        s = (stream or self.ctx.stream).cuda_stream
+        L.check(L.lib().bxmg_parallel_copy(self._h, int(dcomp), src._h, int(scomp), int(ncomp), int(nghost),
+                                           C.c_void_p(s)))
+        return self
+
     def apply_domain_bc(self, scomp=0, ncomp=None, odd=True, stream=None):
         ncomp = self.ncomp - scomp if ncomp is None else ncomp
         s = (stream or self.ctx.stream).cuda_stream

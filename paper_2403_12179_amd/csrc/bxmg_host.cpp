@@ -840,6 +840,7 @@ void bxmg_multifab_release(bxmg_multifab mf) {
     if (mf->owned) (void)hipFreeAsync(mf->data, s);
     mf->d_fboxes.release_async(s);
     for (auto& kv : mf->plans) kv.second->tags.release_async(s);
+    for (auto& kv : mf->pcopy_plans) kv.second->tags.release_async(s);
     ba_release(mf->ba);
     delete mf;
 }
@@ -866,6 +867,41 @@ bxmg_status bxmg_fill_boundary(bxmg_multifab mf, int32_t scomp, int32_t ncomp, i
 
 bxmg_status bxmg_apply_domain_bc(bxmg_multifab mf, int32_t scomp, int32_t ncomp, int32_t odd, void* hip_stream) {
     return run_fill(mf, scomp, ncomp, 1, false, odd != 0, hip_stream);
+}
+
+bxmg_status bxmg_parallel_copy(bxmg_multifab dst, int32_t dcomp, bxmg_multifab src, int32_t scomp, int32_t ncomp,
+                               int32_t dst_nghost, void* hip_stream) {
+    if (!dst || !src) return fail(BXMG_EINVAL, "parallel_copy: NULL MultiFab");
+    if (ncomp < 1 || dcomp < 0 || scomp < 0 || dcomp + ncomp > dst->ncomp || scomp + ncomp > src->ncomp)
+        return fail(BXMG_EINVAL, "parallel_copy: component range");
+    if (dst->dtype != src->dtype) return fail(BXMG_EINVAL, "parallel_copy: dtypes differ");
+    if (dst_nghost < 0 || dst_nghost > dst->ng) return fail(BXMG_EINVAL, "parallel_copy: dst_nghost out of [0, nghost]");
+    const bxmg_ba_s* db = dst->ba;
+    const bxmg_ba_s* sb = src->ba;
+    for (int d = 0; d < 3; ++d) {
+        if (db->dom.lo[d] != sb->dom.lo[d] || db->dom.hi[d] != sb->dom.hi[d] || db->per[d] != sb->per[d])
+            return fail(BXMG_EINVAL, "parallel_copy: the BoxArrays have different domains or boundaries");
+        if (db->per[d] && dst_nghost > db->dom.n(d))
+            return fail(BXMG_EINVAL, "parallel_copy: dst_nghost exceeds a periodic domain edge");
+    }
+    if (dst->ctx->device != src->ctx->device) return fail(BXMG_EINVAL, "parallel_copy: different devices");
+    try {
+        HIPCHK(hipSetDevice(dst->ctx->device));
+        const auto key = std::make_pair(sb->id, (int)dst_nghost);
+        auto it = dst->pcopy_plans.find(key);
+        if (it == dst->pcopy_plans.end()) {
+            auto p = std::make_unique<Plan>();
+            p->set(pcopy_tags(db->dom, db->per, db->boxes, dst_nghost, sb->boxes), dst->ctx->stream);
+            it = dst->pcopy_plans.emplace(key, std::move(p)).first;
+        }
+        const Plan& P = *it->second;
+        hipStream_t s = hip_stream ? (hipStream_t)hip_stream : dst->ctx->stream;
+        HIPCHK(launch_copy_fab(s, dst->dtype == BXMG_F32, dst->data, dst->d_fboxes.p, src->data, src->d_fboxes.p,
+                               P.tags.p, P.ntags, P.cells, dcomp, scomp, ncomp));
+    } catch (HipError& e) {
+        return fail(BXMG_EDEVICE, std::string("parallel_copy: ") + hipGetErrorString(e.e));
+    }
+    return BXMG_OK;
 }
 
 bxmg_status bxmg_fill_boundary_noalloc(bxmg_multifab mf, int32_t scomp, int32_t ncomp, int32_t cross,

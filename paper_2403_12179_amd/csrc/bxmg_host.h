@@ -624,7 +624,54 @@ struct bxmg_mf_s {
     std::map<int, std::unique_ptr<Plan>> plans;  // key: mode*4 + cross*2 + odd
     // region lists kept on the host only, staged per call (allocation-free calls)
     std::map<int, std::pair<std::vector<Tag>, long long>> host_plans;
+    // ParallelCopy plans into this MultiFab, by (source BoxArray id, copy width)
+    std::map<std::pair<uint64_t, int>, std::unique_ptr<Plan>> pcopy_plans;
 };
+
+// ParallelCopy regions: every box of dst grown by ngc, against every
+// source box and its periodic images (shifts of the domain edge in the
+// periodic directions); a region's source cell is its cell + soff.  With
+// ngc <= the domain edge in periodic directions each destination cell has
+// at most one image in the source's (disjoint) valid regions.
+inline std::vector<Tag> pcopy_tags(const Box& dom, const int per[3], const std::vector<Box>& dst, int ngc,
+                                   const std::vector<Box>& src) {
+    std::vector<Tag> tags;
+    long long prefix = 0;
+    for (size_t b = 0; b < dst.size(); ++b) {
+        Box G = dst[b];
+        for (int d = 0; d < 3; ++d) { G.lo[d] -= ngc; G.hi[d] += ngc; }
+        for (int sz = -1; sz <= 1; ++sz)
+            for (int sy = -1; sy <= 1; ++sy)
+                for (int sx = -1; sx <= 1; ++sx) {
+                    const int sh[3] = {sx, sy, sz};
+                    bool skip = false;
+                    for (int d = 0; d < 3; ++d)
+                        if (sh[d] && !per[d]) skip = true;
+                    if (skip) continue;
+                    for (size_t o = 0; o < src.size(); ++o) {
+                        Box S = src[o];
+                        for (int d = 0; d < 3; ++d) { S.lo[d] += sh[d] * dom.n(d); S.hi[d] += sh[d] * dom.n(d); }
+                        const Box I = intersect(G, S);
+                        if (!I.ok()) continue;
+                        Tag t;
+                        std::memset(&t, 0, sizeof t);
+                        t.dbox = (int)b;
+                        t.sbox = (int)o;
+                        for (int d = 0; d < 3; ++d) {
+                            t.dlo[d] = I.lo[d];
+                            t.n[d] = I.n(d);
+                            t.soff[d] = -sh[d] * dom.n(d);
+                            t.sgn[d] = 1;
+                        }
+                        t.neg = 0;
+                        t.prefix = prefix;
+                        prefix += I.cells();
+                        tags.push_back(t);
+                    }
+                }
+    }
+    return tags;
+}
 
 inline size_t mf_layout(const bxmg_ba_s* ba, int ncomp, int ng, bxmg_dtype dt, std::vector<FBox>* out) {
     const size_t es = (dt == BXMG_F64) ? 8 : 4;

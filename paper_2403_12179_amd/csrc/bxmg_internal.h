@@ -186,6 +186,10 @@ hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* 
                           const int* active = nullptr);
 hipError_t launch_fill_fab(hipStream_t s, void* data, bool f32, const FBox* boxes, const Tag* tags, int ntags,
                            long long ncells, int comp0, int ncomp);
+// ParallelCopy over region tags (source cell = destination cell + soff)
+hipError_t launch_copy_fab(hipStream_t s, bool f32, void* dst, const FBox* dboxes, const void* src,
+                           const FBox* sboxes, const Tag* tags, int ntags, long long ncells, int dcomp, int scomp,
+                           int ncomp);
 
 // Coefficient modes of the stencil kernels: beta != nullptr -> cell beta of
 // the level (same layout as u); fat != nullptr -> face arrays fat[pid] of the

@@ -423,6 +423,27 @@ __global__ void __launch_bounds__(kBlock) k_fill_fab(T* __restrict__ data, const
     }
 }
 
+// ParallelCopy: region tags between two MultiFabs (destination box dbox,
+// source box sbox, source cell = dst cell + soff), components
+// [scomp, scomp+n) into [dcomp, dcomp+n).
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_copy_fab(T* __restrict__ dst, const FBox* __restrict__ dboxes,
+                                                    const T* __restrict__ src, const FBox* __restrict__ sboxes,
+                                                    const Tag* __restrict__ tags, int ntags, long long ncells,
+                                                    int dcomp, int scomp, int ncomp) {
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncells) return;
+    const Tag t = tags[find_tag(tags, ntags, g)];
+    const long long loc = g - t.prefix;
+    const int x = (int)(loc % t.n[0]);
+    const int y = (int)((loc / t.n[0]) % t.n[1]);
+    const int z = (int)(loc / ((long long)t.n[0] * t.n[1]));
+    const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
+    const FBox sb = sboxes[t.sbox], db = dboxes[t.dbox];
+    const long long s0 = fab_idx(sb, di + t.soff[0], dj + t.soff[1], dk + t.soff[2]), d0 = fab_idx(db, di, dj, dk);
+    for (int n = 0; n < ncomp; ++n) dst[d0 + (dcomp + n) * db.cs] = src[s0 + (scomp + n) * sb.cs];
+}
+
 // push_ghosts() on a one-box level addressed through its buffer resource: a
 // face neighbour >= 0 is the box itself (its periodic image, the cell
 // shifted by the period), and across a Dirichlet face the ghost to write is
@@ -2239,6 +2260,19 @@ hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* 
     if (n <= 0) return hipSuccess;
     if (f32) hipLaunchKernelGGL(k_fill_rb<float>, dim3(nblk(n)), dim3(kBlock), 0, s, (float*)data, list, n, active);
     else hipLaunchKernelGGL(k_fill_rb<double>, dim3(nblk(n)), dim3(kBlock), 0, s, (double*)data, list, n, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_fab(hipStream_t s, bool f32, void* dst, const FBox* dboxes, const void* src,
+                           const FBox* sboxes, const Tag* tags, int ntags, long long ncells, int dcomp, int scomp,
+                           int ncomp) {
+    if (ncells <= 0) return hipSuccess;
+    if (f32)
+        hipLaunchKernelGGL(k_copy_fab<float>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (float*)dst, dboxes,
+                           (const float*)src, sboxes, tags, ntags, ncells, dcomp, scomp, ncomp);
+    else
+        hipLaunchKernelGGL(k_copy_fab<double>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (double*)dst, dboxes,
+                           (const double*)src, sboxes, tags, ntags, ncells, dcomp, scomp, ncomp);
     return hipGetLastError();
 }
 
