@@ -1290,6 +1290,394 @@ static int solve(const NGrid& g0, int nu1, int nu2, int max_cycles, int fixed_cy
 }
 
 }  // namespace nodal
+
+// =========================================== two-level composite solve
+// A coarse level over the domain and a fine level (refinement ratio 2) over
+// a union of fine boxes, the paper's block-structured AMR pattern (Sections
+// 1 and 2: levels of boxes, inter-level interpolation and copies).  The
+// unknowns are the fine cells and the coarse cells not covered by the fine
+// boxes; a covered coarse cell holds the mean of its 8 children.
+//   fine ghosts   : from other fine boxes where they are fine cells; across
+//                   the coarse-fine boundary, from the coarse cell C beyond
+//                   it and the two fine cells inward: g = (8/15) U_t +
+//                   (2/3) u_1 - (1/5) u_2 (the quadratic through the three
+//                   centres along the normal); U_t is the quadratic through
+//                   the 3x3 coarse cells around C in the face plane (with
+//                   the mixed term) at the ghost's offset (s_a, s_b) h0/4,
+//                   s = +1 for the upper half of C, -1 for the lower:
+//                   U_C + sum_t [s_t (U_{+t} - U_{-t}) / 8 + (U_{+t} - 2 U_C
+//                   + U_{-t}) / 32] + s_a s_b (U_{++} - U_{+-} - U_{-+} +
+//                   U_{--}) / 64
+//   fine operator : the 7-point operator with those ghosts
+//   coarse        : at an uncovered cell, (sum over faces of the outward
+//                   gradient) / h0; a face against a covered cell takes the
+//                   mean of the 4 fine gradients (u_i - g_i) / h1 across it
+//                   (flux matching), other faces (U_J - U_I) / h0, a
+//                   Dirichlet face (-U_I - U_I) / h0
+//   cycle         : nu1 fine GS sweeps (ghosts refreshed before each
+//                   colour), fine residual, composite coarse residual at the
+//                   uncovered cells and the mean of the fine residuals at the
+//                   covered ones, one coarse V-cycle from zero on it,
+//                   coarse update at the uncovered cells, fine update by
+//                   trilinear interpolation of the coarse correction, nu2
+//                   fine sweeps, covered cells := mean of their children
+// The fine boxes must lie 2 coarse cells inside the domain (so a ghost's
+// coarse cell and its tangential neighbours are domain cells).
+namespace composite {
+
+constexpr double kW8_15 = 8.0 / 15.0, kW2_3 = 2.0 / 3.0, kW1_5 = 1.0 / 5.0;
+
+struct CFGhost {
+    int box;         // fine box
+    int g[3];        // the ghost cell (fine index)
+    int i1[3], i2[3];  // the two fine cells inward
+    int C[3];        // coarse cell of the ghost
+    int ta, tb;      // tangential directions
+    int sa, sb;      // +-1: the ghost's half of C along ta, tb
+};
+
+struct Comp {
+    Geom gc, gf;
+    std::vector<Box> cboxes, fboxes;
+    std::vector<char> covered;  // coarse domain cells, F-order
+    std::vector<int> fown;      // fine domain cells: owning fine box or -1
+    std::vector<CFGhost> ghosts;
+    size_t cq(int I, int J, int K) const {
+        const Box& D = gc.dom;
+        return (size_t)(I - D.lo[0]) + (size_t)D.n(0) * ((size_t)(J - D.lo[1]) + (size_t)D.n(1) * (K - D.lo[2]));
+    }
+    size_t fq(int i, int j, int k) const {
+        const Box& D = gf.dom;
+        return (size_t)(i - D.lo[0]) + (size_t)D.n(0) * ((size_t)(j - D.lo[1]) + (size_t)D.n(1) * (k - D.lo[2]));
+    }
+    bool in_fine(int i, int j, int k) const {
+        const Box& D = gf.dom;
+        if (!D.has(i, j, k)) return false;
+        return fown[fq(i, j, k)] >= 0;
+    }
+};
+
+// The layout this solve supports: fine boxes with even corners and odd
+// upper corners (unions of whole coarse cells), pairwise disjoint, and 2
+// coarse cells away from every domain face.
+static bool layout_ok(const Geom& gc, const std::vector<Box>& fboxes) {
+    for (size_t b = 0; b < fboxes.size(); ++b) {
+        const Box& B = fboxes[b];
+        for (int d = 0; d < 3; ++d) {
+            if ((B.lo[d] & 1) || !(B.hi[d] & 1) || B.hi[d] < B.lo[d]) return false;
+            if (B.lo[d] < 2 * gc.dom.lo[d] + 4 || B.hi[d] > 2 * gc.dom.hi[d] + 1 - 4) return false;
+        }
+        for (size_t q = 0; q < b; ++q) {
+            const Box& Q = fboxes[q];
+            bool sep = false;
+            for (int d = 0; d < 3; ++d) sep = sep || Q.hi[d] < B.lo[d] || B.hi[d] < Q.lo[d];
+            if (!sep) return false;
+        }
+    }
+    return true;
+}
+
+static Comp setup(const Geom& gc, const std::vector<Box>& cboxes, const std::vector<Box>& fboxes) {
+    Comp c;
+    c.gc = gc;
+    c.gf = gc;
+    for (int d = 0; d < 3; ++d) { c.gf.dom.lo[d] = 2 * gc.dom.lo[d]; c.gf.dom.hi[d] = 2 * gc.dom.hi[d] + 1; }
+    c.gf.h = gc.h * 0.5;
+    c.cboxes = cboxes;
+    c.fboxes = fboxes;
+    c.fown = owner_map(c.gf, fboxes);
+    c.covered.assign((size_t)gc.dom.cells(), 0);
+    for (auto& b : fboxes)
+        for (int k = b.lo[2] / 2; k <= b.hi[2] / 2; ++k)
+            for (int j = b.lo[1] / 2; j <= b.hi[1] / 2; ++j)
+                for (int i = b.lo[0] / 2; i <= b.hi[0] / 2; ++i) c.covered[c.cq(i, j, k)] = 1;
+    for (size_t b = 0; b < fboxes.size(); ++b) {
+        const Box& B = fboxes[b];
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i)
+                    for (int d = 0; d < 3; ++d)
+                        for (int side = 0; side < 2; ++side) {
+                            int g[3] = {i, j, k};
+                            g[d] += side ? 1 : -1;
+                            if (B.has(g[0], g[1], g[2]) || c.in_fine(g[0], g[1], g[2])) continue;
+                            CFGhost h;
+                            h.box = (int)b;
+                            for (int e = 0; e < 3; ++e) { h.g[e] = g[e]; h.i1[e] = (e == d) ? g[e] + (side ? -1 : 1) : g[e];
+                                                          h.i2[e] = (e == d) ? g[e] + (side ? -2 : 2) : g[e];
+                                                          h.C[e] = g[e] >> 1; }
+                            h.ta = (d + 1) % 3;
+                            h.tb = (d + 2) % 3;
+                            h.sa = (g[h.ta] & 1) ? 1 : -1;
+                            h.sb = (g[h.tb] & 1) ? 1 : -1;
+                            c.ghosts.push_back(h);
+                        }
+    }
+    return c;
+}
+
+// coarse values at any domain cell (covered cells hold the mean of the fine)
+static double ghost_value(const Comp& c, const std::vector<double>& ug, const Fab<double>& F, const CFGhost& h) {
+    // coarse values on the 3x3 cells around C in the face plane
+    auto U = [&](int p, int q) {
+        int x[3] = {h.C[0], h.C[1], h.C[2]};
+        x[h.ta] += p;
+        x[h.tb] += q;
+        return ug[c.cq(x[0], x[1], x[2])];
+    };
+    const double UC = U(0, 0);
+    const double da = (U(1, 0) - U(-1, 0)) * 0.125 * (double)h.sa, db = (U(0, 1) - U(0, -1)) * 0.125 * (double)h.sb;
+    const double qa = ((U(1, 0) + U(-1, 0)) - 2.0 * UC) * (1.0 / 32.0);
+    const double qb = ((U(0, 1) + U(0, -1)) - 2.0 * UC) * (1.0 / 32.0);
+    const double xab = ((U(1, 1) - U(1, -1)) - (U(-1, 1) - U(-1, -1))) * (1.0 / 64.0) * (double)(h.sa * h.sb);
+    const double Ut = UC + ((da + db) + (qa + qb)) + xab;
+    const double u1 = F(h.i1[0], h.i1[1], h.i1[2]), u2 = F(h.i2[0], h.i2[1], h.i2[2]);
+    return (kW8_15 * Ut + kW2_3 * u1) - kW1_5 * u2;
+}
+
+// fine ghosts: from other fine boxes, then the coarse-fine ones
+static void fill_fine(const Comp& c, const std::vector<double>& ug, MF<double>& uf) {
+    fill_boundary(c.gf, uf);
+    for (const CFGhost& h : c.ghosts) {
+        Fab<double>& F = uf.f[h.box];
+        F(h.g[0], h.g[1], h.g[2]) = ghost_value(c, ug, F, h);
+    }
+}
+
+// covered coarse cells := mean of their 8 children
+static void sync_covered(const Comp& c, const MF<double>& uf, std::vector<double>& ug) {
+    for (size_t b = 0; b < c.fboxes.size(); ++b) {
+        const Box& B = c.fboxes[b];
+        const Fab<double>& F = uf.f[b];
+        for (int K = B.lo[2] / 2; K <= B.hi[2] / 2; ++K)
+            for (int J = B.lo[1] / 2; J <= B.hi[1] / 2; ++J)
+                for (int I = B.lo[0] / 2; I <= B.hi[0] / 2; ++I) {
+                    const int i = 2 * I, j = 2 * J, k = 2 * K;
+                    ug[c.cq(I, J, K)] = (((F(i, j, k) + F(i + 1, j, k)) + (F(i, j + 1, k) + F(i + 1, j + 1, k))) +
+                                         ((F(i, j, k + 1) + F(i + 1, j, k + 1)) + (F(i, j + 1, k + 1) + F(i + 1, j + 1, k + 1)))) * 0.125;
+                }
+    }
+}
+
+// outward gradient across face (d, side) of uncovered coarse cell I
+static double coarse_grad(const Comp& c, const std::vector<double>& ug, const MF<double>& uf, int I, int J, int K,
+                          int d, int side) {
+    const Geom& g = c.gc;
+    const double h0 = g.h, h1 = c.gf.h;
+    int n[3] = {I, J, K};
+    n[d] += side ? 1 : -1;
+    const double UI = ug[c.cq(I, J, K)];
+    if (n[d] < g.dom.lo[d] || n[d] > g.dom.hi[d]) {
+        if (!g.per[d]) return (-UI - UI) / h0;
+        n[d] = g.dom.lo[d] + pmod(n[d] - g.dom.lo[d], g.dom.n(d));
+    }
+    if (!c.covered[c.cq(n[0], n[1], n[2])]) return (ug[c.cq(n[0], n[1], n[2])] - UI) / h0;
+    // flux matching: the 4 fine cells of the neighbour against the face
+    const int ta = (d + 1) % 3, tb = (d + 2) % 3;
+    double a[2][2];
+    for (int q = 0; q < 2; ++q)
+        for (int p = 0; p < 2; ++p) {
+            int fi[3];
+            fi[d] = 2 * n[d] + (side ? 0 : 1);
+            fi[ta] = 2 * n[ta] + p;
+            fi[tb] = 2 * n[tb] + q;
+            const int b = c.fown[c.fq(fi[0], fi[1], fi[2])];
+            const Fab<double>& F = uf.f[b];
+            int gcell[3] = {fi[0], fi[1], fi[2]};
+            gcell[d] += side ? -1 : 1;
+            // the ghost of fine cell fi toward I, as fill_fine computes it
+            CFGhost h;
+            h.box = b;
+            for (int e = 0; e < 3; ++e) { h.g[e] = gcell[e]; h.i1[e] = fi[e]; h.i2[e] = fi[e]; h.C[e] = gcell[e] >> 1; }
+            h.i2[d] += side ? 1 : -1;
+            h.ta = ta;
+            h.tb = tb;
+            h.sa = (gcell[ta] & 1) ? 1 : -1;
+            h.sb = (gcell[tb] & 1) ? 1 : -1;
+            const double gv = ghost_value(c, ug, F, h);
+            a[q][p] = (F(fi[0], fi[1], fi[2]) - gv) / h1;
+        }
+    return ((a[0][0] + a[0][1]) + (a[1][0] + a[1][1])) * 0.25;
+}
+
+static double coarse_op(const Comp& c, const std::vector<double>& ug, const MF<double>& uf, int I, int J, int K) {
+    double gr[6];
+    for (int d = 0; d < 3; ++d)
+        for (int side = 0; side < 2; ++side) gr[2 * d + side] = coarse_grad(c, ug, uf, I, J, K, d, side);
+    return (((gr[0] + gr[1]) + (gr[2] + gr[3])) + (gr[4] + gr[5])) / c.gc.h;
+}
+
+template <class F>
+static void for_uncovered(const Comp& c, F fn) {
+    const Box& D = c.gc.dom;
+    for (int K = D.lo[2]; K <= D.hi[2]; ++K)
+        for (int J = D.lo[1]; J <= D.hi[1]; ++J)
+            for (int I = D.lo[0]; I <= D.hi[0]; ++I)
+                if (!c.covered[c.cq(I, J, K)]) fn(I, J, K);
+}
+
+struct State {
+    std::vector<double> uc, fc;  // global coarse arrays
+    MF<double> uf, ff, rf;
+};
+
+// composite residual: rc at uncovered cells (0 at covered), rf at fine cells;
+// returns max |r| over both and sum r^2
+static void comp_residual(const Comp& c, State& S, std::vector<double>& rc, double* rinf, double* rl2) {
+    fill_fine(c, S.uc, S.uf);
+    double fi, fl;
+    residual(c.gf, S.uf, S.ff, (const Faces*)nullptr, S.rf, &fi, &fl);
+    double mx = fi, s2 = fl;
+    bool bad = std::isnan(fi);
+    std::fill(rc.begin(), rc.end(), 0.0);
+    for_uncovered(c, [&](int I, int J, int K) {
+        const double r = S.fc[c.cq(I, J, K)] - coarse_op(c, S.uc, S.uf, I, J, K);
+        rc[c.cq(I, J, K)] = r;
+        const double a = std::fabs(r);
+        if (std::isnan(a)) bad = true;
+        else if (a > mx) mx = a;
+        s2 += r * r;
+    });
+    *rinf = bad ? std::nan("") : mx;
+    *rl2 = s2;
+}
+
+static void cycle(const Comp& c, State& S, Hier<double>& H, const Params& P, std::vector<double>& rc) {
+    auto sweeps = [&](int n) {
+        for (int s = 0; s < n; ++s)
+            for (int col = 0; col < 2; ++col) {
+                fill_fine(c, S.uc, S.uf);
+                gs_colour(c.gf, S.uf, S.ff, (const Faces*)nullptr, col);
+            }
+    };
+    sweeps(P.nu1);
+    double ri, rl;
+    comp_residual(c, S, rc, &ri, &rl);
+    // covered cells: the mean of the fine residuals below them
+    for (size_t b = 0; b < c.fboxes.size(); ++b) {
+        const Box& B = c.fboxes[b];
+        const Fab<double>& R = S.rf.f[b];
+        for (int K = B.lo[2] / 2; K <= B.hi[2] / 2; ++K)
+            for (int J = B.lo[1] / 2; J <= B.hi[1] / 2; ++J)
+                for (int I = B.lo[0] / 2; I <= B.hi[0] / 2; ++I) {
+                    const int i = 2 * I, j = 2 * J, k = 2 * K;
+                    rc[c.cq(I, J, K)] = (((R(i, j, k) + R(i + 1, j, k)) + (R(i, j + 1, k) + R(i + 1, j + 1, k))) +
+                                         ((R(i, j, k + 1) + R(i + 1, j, k + 1)) + (R(i, j + 1, k + 1) + R(i + 1, j + 1, k + 1)))) * 0.125;
+                }
+    }
+    // coarse correction: one V-cycle from zero
+    scatter_global(c.gc.dom, rc.data(), H.f[0]);
+    H.u[0].zero();
+    vcycle(H, P, 0, nullptr);
+    std::vector<double> e((size_t)c.gc.dom.cells());
+    gather_global(c.gc.dom, H.u[0], e.data());
+    for_uncovered(c, [&](int I, int J, int K) { S.uc[c.cq(I, J, K)] += e[c.cq(I, J, K)]; });
+    // fine update: trilinear interpolation of e (parent and its neighbours on
+    // the child's side, weights 27, 9, 3, 1 over 64)
+    for (size_t b = 0; b < c.fboxes.size(); ++b) {
+        const Box& B = c.fboxes[b];
+        Fab<double>& F = S.uf.f[b];
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) {
+                    const int I = i >> 1, J = j >> 1, K = k >> 1;
+                    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+                    auto E = [&](int a, int bb, int cc) { return e[c.cq(a, bb, cc)]; };
+                    const double c000 = E(I, J, K), c100 = E(I + si, J, K), c010 = E(I, J + sj, K), c001 = E(I, J, K + sk);
+                    const double c110 = E(I + si, J + sj, K), c101 = E(I + si, J, K + sk), c011 = E(I, J + sj, K + sk);
+                    const double c111 = E(I + si, J + sj, K + sk);
+                    const double v = (((27.0 * c000 + 9.0 * ((c100 + c010) + c001)) + 3.0 * ((c110 + c101) + c011)) + c111) * (1.0 / 64.0);
+                    F(i, j, k) += v;
+                }
+    }
+    sweeps(P.nu2);
+    sync_covered(c, S.uf, S.uc);
+}
+
+static int solve(const Geom& gc, const std::vector<Box>& cboxes, const std::vector<Box>& fboxes, const Params& P,
+                 const double* fc_glob, const double* ff_glob, double* uc_glob, double* uf_glob, Info* info) {
+    std::memset(info, 0, sizeof(Info));
+    Comp c = setup(gc, cboxes, fboxes);
+    std::vector<Level> L = hierarchy(gc, cboxes, P.min_box_edge);
+    info->levels = (int)L.size() + 1;
+    Hier<double> H;
+    H.define(L, nullptr);
+    State S;
+    const size_t Nc = (size_t)gc.dom.cells();
+    S.uc.assign(Nc, 0.0);
+    S.fc.assign(fc_glob, fc_glob + Nc);
+    S.uf.define(fboxes, 1);
+    S.ff.define(fboxes, 1);
+    S.rf.define(fboxes, 1);
+    scatter_global(c.gf.dom, ff_glob, S.ff);
+    double fnorm = 0.0;
+    bool bad = false;
+    for_uncovered(c, [&](int I, int J, int K) {
+        const double a = std::fabs(S.fc[c.cq(I, J, K)]);
+        if (std::isnan(a)) bad = true; else if (a > fnorm) fnorm = a;
+    });
+    const double ffn = max_abs_valid(S.ff);
+    if (std::isnan(ffn)) bad = true; else if (ffn > fnorm) fnorm = ffn;
+    info->f_inf = bad ? std::nan("") : fnorm;
+    std::vector<double> rc(Nc, 0.0);
+    int status = 0, cyc = 0;
+    if (bad) status = -5;
+    else if (fnorm > 0.0)
+        for (;; ++cyc) {
+            double rinf, rl2;
+            comp_residual(c, S, rc, &rinf, &rl2);
+            if (cyc < 256) { info->hist[cyc] = rinf / fnorm; info->hist_l2[cyc] = std::sqrt(rl2); info->nhist = cyc + 1; }
+            info->rel_inf = rinf / fnorm;
+            info->rel_l2 = std::sqrt(rl2);
+            if (!std::isfinite(rinf)) { status = -5; break; }
+            if (P.fixed_cycles > 0) {
+                if (cyc == P.fixed_cycles) break;
+            } else {
+                if (rinf <= P.rel_tol * fnorm) break;
+                if (cyc == P.max_cycles) { status = -4; break; }
+            }
+            cycle(c, S, H, P, rc);
+        }
+    info->cycles = cyc;
+    std::memcpy(uc_glob, S.uc.data(), Nc * sizeof(double));
+    const size_t Nf = (size_t)c.gf.dom.cells();
+    for (size_t q = 0; q < Nf; ++q) uf_glob[q] = 0.0;
+    gather_global(c.gf.dom, S.uf, uf_glob);
+    info->status = status;
+    return status;
+}
+
+// The composite operator on given fields (covered coarse cells are taken
+// as the mean of uf): Lc at uncovered cells (0 at covered), Lf at fine cells.
+static void apply(const Geom& gc, const std::vector<Box>& cboxes, const std::vector<Box>& fboxes, const double* uc_glob,
+                  const double* uf_glob, double* Lc_glob, double* Lf_glob) {
+    Comp c = setup(gc, cboxes, fboxes);
+    const size_t Nc = (size_t)gc.dom.cells(), Nf = (size_t)c.gf.dom.cells();
+    std::vector<double> ug(uc_glob, uc_glob + Nc);
+    MF<double> uf, lf;
+    uf.define(fboxes, 1);
+    lf.define(fboxes, 0);
+    scatter_global(c.gf.dom, uf_glob, uf);
+    sync_covered(c, uf, ug);
+    fill_fine(c, ug, uf);
+    const double ih2 = 1.0 / (c.gf.h * c.gf.h);
+    for (size_t b = 0; b < fboxes.size(); ++b) {
+        const Box& B = fboxes[b];
+        for (int k = B.lo[2]; k <= B.hi[2]; ++k)
+            for (int j = B.lo[1]; j <= B.hi[1]; ++j)
+                for (int i = B.lo[0]; i <= B.hi[0]; ++i) {
+                    double su, sb;
+                    stencil(uf.f[b], (const Faces*)nullptr, i, j, k, su, sb);
+                    lf.f[b](i, j, k) = (su - sb * uf.f[b](i, j, k)) * ih2;
+                }
+    }
+    for (size_t q = 0; q < Nc; ++q) Lc_glob[q] = 0.0;
+    for_uncovered(c, [&](int I, int J, int K) { Lc_glob[c.cq(I, J, K)] = coarse_op(c, ug, uf, I, J, K); });
+    for (size_t q = 0; q < Nf; ++q) Lf_glob[q] = 0.0;
+    gather_global(c.gf.dom, lf, Lf_glob);
+}
+
+}  // namespace composite
 }  // namespace orc
 
 // ====================================================================== C API
@@ -1669,6 +2057,29 @@ int orc_nodal_bottom(const int* n, const int* per, double h, const double* f, do
     const int it = nodal::bottom_cg(g, F, X, rtol);
     std::memcpy(u, X.data(), X.size() * sizeof(double));
     return it;
+}
+
+// ------------------------------------------------------------ composite
+// Coarse arrays over the domain (n cells per direction), fine arrays over
+// the refined domain (2n), both F-order; fine boxes in fine indices.
+int orc_composite_solve(const int* dom6, const int* per, int nbc, const int* lohic, int nbf, const int* lohif,
+                        double h, int nu1, int nu2, int max_cycles, int fixed_cycles, double rel_tol,
+                        const double* fc, const double* ff, double* uc, double* uf, Info* info) {
+    Geom g = geom_of(dom6, per, h);
+    Params P;
+    P.nu1 = nu1; P.nu2 = nu2; P.max_cycles = max_cycles; P.fixed_cycles = fixed_cycles; P.rel_tol = rel_tol;
+    std::vector<Box> fb = boxes_of(nbf, lohif);
+    if (!composite::layout_ok(g, fb)) { std::memset(info, 0, sizeof(Info)); info->status = -2; return -2; }
+    return composite::solve(g, boxes_of(nbc, lohic), fb, P, fc, ff, uc, uf, info);
+}
+
+int orc_composite_apply(const int* dom6, const int* per, int nbc, const int* lohic, int nbf, const int* lohif,
+                        double h, const double* uc, const double* uf, double* Lc, double* Lf) {
+    Geom g = geom_of(dom6, per, h);
+    std::vector<Box> fb = boxes_of(nbf, lohif);
+    if (!composite::layout_ok(g, fb)) return -2;
+    composite::apply(g, boxes_of(nbc, lohic), fb, uc, uf, Lc, Lf);
+    return 0;
 }
 
 }  // extern "C"

@@ -420,3 +420,46 @@ def parallel_copy(dom_lo, dom_hi, periodic, dst_boxes, dst_ng, dst, src_boxes, s
                         int(dst_ng), int(dst_ncomp), int(copy_ng), len(src_boxes), _ip(lohi_array(src_boxes)),
                         int(src_ng), int(src_ncomp), int(dcomp), int(scomp), int(ncomp), _dp(out), _dp(src))
     return out
+
+
+# ------------------------------------------------------------ composite
+def composite_solve(n, periodic, coarse_boxes, fine_boxes, fc, ff, h=None, nu1=2, nu2=2, max_cycles=100,
+                    fixed_cycles=0, rel_tol=1e-10):
+    """Two-level composite solve: coarse level over [0, n)^3 (coarse_boxes),
+    fine level (ratio 2) over fine_boxes in fine indices.  fc: coarse rhs
+    (n^3, read at uncovered cells), ff: fine rhs over the refined domain
+    ((2n)^3, read inside fine boxes).  Returns (uc, uf, info)."""
+    L = lib()
+    n = int(n)
+    h = 1.0 / n if h is None else h
+    fc = np.asfortranarray(fc, dtype=np.float64)
+    ff = np.asfortranarray(ff, dtype=np.float64)
+    assert fc.shape == (n, n, n) and ff.shape == (2 * n, 2 * n, 2 * n)
+    uc = np.zeros((n, n, n), order="F")
+    uf = np.zeros((2 * n, 2 * n, 2 * n), order="F")
+    info = Info()
+    L.orc_composite_solve(_ip(dom6((0, 0, 0), (n - 1,) * 3)), _ip(_i32(periodic)), len(coarse_boxes),
+                          _ip(lohi_array(coarse_boxes)), len(fine_boxes), _ip(lohi_array(fine_boxes)), C.c_double(h),
+                          int(nu1), int(nu2), int(max_cycles), int(fixed_cycles), C.c_double(rel_tol),
+                          _dp(fc.ravel(order="F")), _dp(ff.ravel(order="F")), _dp(uc.ravel(order="F")),
+                          _dp(uf.ravel(order="F")), C.byref(info))
+    return uc, uf, _info_dict(info)
+
+
+def composite_apply(n, periodic, coarse_boxes, fine_boxes, h, uc, uf):
+    """The composite operator: (Lc, Lf) with Lc zero at covered coarse cells
+    and Lf zero outside the fine boxes.  Covered coarse values are replaced
+    by the mean of their children first."""
+    L = lib()
+    n = int(n)
+    uc = np.asfortranarray(uc, dtype=np.float64)
+    uf = np.asfortranarray(uf, dtype=np.float64)
+    Lc = np.zeros((n, n, n), order="F")
+    Lf = np.zeros((2 * n, 2 * n, 2 * n), order="F")
+    st = L.orc_composite_apply(_ip(dom6((0, 0, 0), (n - 1,) * 3)), _ip(_i32(periodic)), len(coarse_boxes),
+                               _ip(lohi_array(coarse_boxes)), len(fine_boxes), _ip(lohi_array(fine_boxes)),
+                               C.c_double(h), _dp(uc.ravel(order="F")), _dp(uf.ravel(order="F")),
+                               _dp(Lc.ravel(order="F")), _dp(Lf.ravel(order="F")))
+    if st != 0:
+        raise ValueError("composite layout not supported")
+    return Lc, Lf

@@ -117,3 +117,47 @@ def serving_trace(nreq, seed, rate=200.0, lo=32, hi=256, step=16):
     kinds = rng.integers(0, 2, size=nreq)
     return [dict(t=float(t[q]), edge=int(edges[q]), tol=float(tols[q]), kind=int(kinds[q]), seed=5000 + q)
             for q in range(nreq)]
+
+
+def composite_layout(n, kind="centre", max_box=32):
+    """Two-level layout on a coarse n^3 domain: (coarse boxes, fine boxes),
+    fine boxes in fine indices (refinement ratio 2).
+      centre : the central half of the domain refined ([n/4, 3n/4) coarse
+               cells), chopped into fine boxes of edge max_box
+      lshape : an L of two abutting fine boxes plus a detached one
+    Coarse boxes: the domain chopped into boxes of edge min(n, 32)."""
+    cb = chop_boxes(n, min(n, 32))
+    if kind == "centre":
+        q = n // 4
+        lo, hi = 2 * q, 2 * (n - q)
+        fb = []
+        for k in range(lo, hi, max_box):
+            for j in range(lo, hi, max_box):
+                for i in range(lo, hi, max_box):
+                    fb.append(((i, j, k), (min(i + max_box, hi) - 1, min(j + max_box, hi) - 1,
+                                           min(k + max_box, hi) - 1)))
+        return cb, fb
+    if kind == "lshape":
+        a = n // 4
+        return cb, [((2 * a, 2 * a, 2 * a), (4 * a - 1, 4 * a - 1, 4 * a - 1)),
+                    ((4 * a, 2 * a, 2 * a), (5 * a - 1, 3 * a - 1, 4 * a - 1)),
+                    ((5 * a, 5 * a, 5 * a), (6 * a - 1, 6 * a - 1, 6 * a - 3))]
+    raise ValueError(kind)
+
+
+def chop_boxes(n, edge):
+    """The cube [0, n)^3 cut into boxes of the given edge (last one ragged)."""
+    out = []
+    for k in range(0, n, edge):
+        for j in range(0, n, edge):
+            for i in range(0, n, edge):
+                out.append(((i, j, k), (min(i + edge, n) - 1, min(j + edge, n) - 1, min(k + edge, n) - 1)))
+    return out
+
+
+def fine_mask(n, fine_boxes):
+    """Boolean (2n)^3 mask of the fine cells inside the fine boxes."""
+    m = np.zeros((2 * n,) * 3, bool)
+    for lo, hi in fine_boxes:
+        m[lo[0]:hi[0] + 1, lo[1]:hi[1] + 1, lo[2]:hi[2] + 1] = True
+    return m
