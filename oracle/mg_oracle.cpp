@@ -1317,7 +1317,8 @@ static int solve(const NGrid& g0, int nu1, int nu2, int max_cycles, int fixed_cy
 //   cycle         : nu1 fine GS sweeps (ghosts refreshed before each
 //                   colour), fine residual, composite coarse residual at the
 //                   uncovered cells and the mean of the fine residuals at the
-//                   covered ones, one coarse V-cycle from zero on it,
+//                   covered ones, one coarse V-cycle from zero on it (over
+//                   the coarse domain as one box, whatever the coarse boxes),
 //                   coarse update at the uncovered cells, fine update by
 //                   trilinear interpolation of the coarse correction, nu2
 //                   fine sweeps, covered cells := mean of their children
@@ -1598,7 +1599,11 @@ static int solve(const Geom& gc, const std::vector<Box>& cboxes, const std::vect
                  const double* fc_glob, const double* ff_glob, double* uc_glob, double* uf_glob, Info* info) {
     std::memset(info, 0, sizeof(Info));
     Comp c = setup(gc, cboxes, fboxes);
-    std::vector<Level> L = hierarchy(gc, cboxes, P.min_box_edge);
+    // the coarse correction's V-cycle runs over the coarse domain as one box,
+    // whatever the caller's coarse boxes (the same correction for every
+    // decomposition of the coarse level)
+    (void)cboxes;
+    std::vector<Level> L = hierarchy(gc, std::vector<Box>{gc.dom}, P.min_box_edge);
     info->levels = (int)L.size() + 1;
     Hier<double> H;
     H.define(L, nullptr);
