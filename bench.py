@@ -29,6 +29,9 @@ After the headline the same line carries, unless --sections says otherwise:
                     a Helmholtz solve started from the previous state
   nodal           : the nodal Poisson solver on the 257^3 nodes of the
                     headline domain
+  composite       : two-level composite Poisson (256^3 coarse cells, the
+                    central half refined by 2: 256^3 fine cells in 512
+                    boxes), time per solve and per cycle
   batched         : 256 periodic problems of edges 32..128, batch engine vs
                     plain FP64 solves one at a time
   serving         : an open-loop trace of 2000 requests (200/s), continuous
@@ -342,6 +345,48 @@ def section_nodal(bx, W, reps=3):
     keep = {"n": n, "f": np.asfortranarray(rhs.cpu().numpy().transpose(2, 1, 0)),
             "u": np.asfortranarray(phi.cpu().numpy().transpose(2, 1, 0))}
     del phi, rhs
+    torch.cuda.empty_cache()
+    return out, keep
+
+
+def section_composite(bx, W, reps=3):
+    """Two-level composite Poisson: 256^3 coarse cells (h0 = 1/256), the
+    central half refined by 2 (256^3 fine cells in 512 boxes of 32^3),
+    homogeneous Dirichlet, f ~ U[-1,1] on both levels (coarse seed 71 drawn
+    on the host, fine seed 72 drawn on the device), FP64 to 1e-10."""
+    import torch
+    n = N
+    cb, fb = W.composite_layout(n, "centre", max_box=MAX_BOX)
+    cba = bx.BoxArray.from_boxes((0, 0, 0), (n - 1,) * 3, cb, bc=(bx.DIRICHLET0,) * 3)
+    fba = bx.BoxArray.from_boxes((0, 0, 0), (2 * n - 1,) * 3, fb, bc=(bx.DIRICHLET0,) * 3)
+    fc = W.uniform_rhs((n, n, n), seed=71)
+    pc = bx.MultiFab(cba, nghost=1)
+    rc = bx.MultiFab(cba, nghost=0).from_global(fc)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(72)
+    ffd = torch.zeros((2 * n,) * 3, device="cuda", dtype=torch.float64)
+    lo, hi = n // 2, 3 * n // 2
+    ffd[lo:hi, lo:hi, lo:hi] = torch.rand((n,) * 3, generator=g, device="cuda", dtype=torch.float64) * 2.0 - 1.0
+    pf = bx.MultiFab(fba, nghost=1)
+    rf = bx.MultiFab(fba, nghost=0).from_tensor(ffd)
+    bx.composite_solve(pc, rc, pf, rf, rel_tol=TOL)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = bx.composite_solve(pc, rc, pf, rf, rel_tol=TOL)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ms = 1000.0 * min(times)
+    ncov = (n // 2) ** 3
+    unknowns = n ** 3 - ncov + n ** 3
+    out = {"workload": "composite_poisson_256^3_coarse_+_256^3_fine_in_512_boxes_dirichlet_fp64_tol1e-10",
+           "ok": res.ok, "cycles": res.cycles, "ms_per_solve": ms, "ms_per_cycle": ms / max(res.cycles, 1),
+           "unknowns": unknowns, "unknown_updates_per_s": unknowns * res.cycles / (ms / 1000.0),
+           "final_rel_resid_inf": res.rel_resid_inf, "levels": res.levels}
+    keep = {"n": n, "cb": cb, "fb": fb, "fc": fc, "ff": np.asfortranarray(ffd.cpu().numpy()),
+            "uc": pc.to_global(), "uf": pf.to_global()}
+    del pc, rc, pf, rf, ffd
     torch.cuda.empty_cache()
     return out, keep
 
@@ -721,7 +766,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--summarize-counters", metavar="DIR")
-    ap.add_argument("--sections", default="c1,mixed,heat,nodal,batched,serving",
+    ap.add_argument("--sections", default="c1,mixed,heat,nodal,composite,batched,serving",
                     help="other rows to measure after the headline (comma list; '' for none)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--no-autotune", action="store_true")
@@ -866,6 +911,8 @@ def main():
             line["heat"], keep["heat"] = section_heat(bx, W)
         elif name == "nodal":
             line["nodal"], keep["nodal"] = section_nodal(bx, W)
+        elif name == "composite":
+            line["composite"], keep["composite"] = section_composite(bx, W)
         elif name == "batched":
             line["batched"], keep["batched"], keep["edges"] = section_batched(bx, W)
         elif name == "serving":
@@ -907,6 +954,17 @@ def main():
                 "oracle_rel_resid_inf": float(np.max(np.abs(r)) / np.max(np.abs(k["f"][1:-1, 1:-1, 1:-1]))),
                 "tol": TOL}
             del k, r
+        if "composite" in keep:
+            k = keep.pop("composite")
+            n, fb = k["n"], k["fb"]
+            fm = W.fine_mask(n, fb)
+            cov = fm.reshape(n, 2, n, 2, n, 2).any(axis=(1, 3, 5))
+            uf = np.where(fm, k["uf"], 0.0)
+            Lc, Lf = orc.composite_apply(n, (0, 0, 0), k["cb"], fb, 1.0 / n, k["uc"], uf)
+            fnorm = max(np.abs(k["fc"][~cov]).max(), np.abs(k["ff"][fm]).max())
+            r = max(np.abs(k["fc"] - Lc)[~cov].max(), np.abs(k["ff"] - Lf)[fm].max())
+            line["composite"]["error_vs_oracle"] = {"oracle_rel_resid_inf": float(r / fnorm), "tol": TOL}
+            del k, uf, Lc, Lf
         if "batched" in keep:
             line["batched"]["error_vs_oracle"] = [
                 dict(problem=s["q"], edge=s["e"], gpu_cycles=s["cycles"],

@@ -259,6 +259,44 @@ bxmg_status bxmg_heat_step(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_m
 bxmg_status bxmg_nodal_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_boxarray ba, double* phi,
                              const double* rhs, bxmg_solve_info* info);
 
+/* Two-level composite Poisson solve (the block-structured AMR hierarchy of
+ * the paper, Sections 1 and 2): div grad phi = rhs on a coarse level over
+ * the whole domain and a fine level of refinement ratio 2 over a union of
+ * boxes, solved together.  The unknowns are the fine cells and the coarse
+ * cells no fine box covers.  Fine ghosts across the coarse-fine boundary are
+ * quadratic along the normal through the coarse value and the two fine
+ * cells inward, the coarse value being the quadratic (with the mixed term)
+ * through the 3x3 coarse cells around the ghost in the face plane; the
+ * coarse operator takes the mean of the 4 fine gradients across a face
+ * against a covered cell, so the composite operator conserves.  Iteration:
+ * fine red-black sweeps, composite residual, one coarse V-cycle from zero,
+ * coarse and (trilinear) fine corrections, fine sweeps, covered coarse cells
+ * := mean of their children -- repeated until the max composite residual
+ * meets rel_tol * max|rhs| (or abs_tol).
+ *   phi_c, rhs_c: FP64 MultiFabs over a coarse BoxArray that covers its
+ *     domain (any nghost; valid cells used).  On return phi_c holds the
+ *     solution at uncovered cells and the mean of the children at covered
+ *     ones; rhs_c is read at uncovered cells only.
+ *   phi_f, rhs_f: FP64 MultiFabs over the fine BoxArray, whose domain is the
+ *     coarse one refined by 2 (lo 2*lo, hi 2*hi+1) with the same boundary
+ *     conditions; phi_f needs nghost >= 1 (its ghosts are overwritten).  Every
+ *     fine box must have even lower and odd upper corners (whole coarse
+ *     cells) and lie at least 4 fine cells inside every domain face.
+ *   params: nu1, nu2 (fine and coarse sweeps), max_cycles, fixed_cycles,
+ *     rel_tol, abs_tol, dx (coarse cell width; <= 0: 1 / coarse x-edge),
+ *     bottom_rtol; precision 0, krylov 0, alpha 0, prolong 2 only.
+ * Both solutions start from zero (their contents on entry are ignored).
+ * Component 0 of each field is used.  A fully periodic problem needs a
+ * compatible rhs (zero volume-weighted sum over the unknowns) and returns a
+ * solution defined up to a constant.  The per-layout state (one-box coarse
+ * fields, coverage map, coarse-fine ghost list) is cached on the context for
+ * the last layout; composite solves on one context run one at a time.
+ * Synchronous on the context's stream.  Returns info->status: OK, ENOCONV,
+ * ENONFINITE, EINVAL (bad arguments or layout), ENOMEM or EDEVICE. */
+bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi_c,
+                                 bxmg_multifab rhs_c, bxmg_multifab phi_f, bxmg_multifab rhs_f,
+                                 bxmg_solve_info* info);
+
 /* -------------------------------------------------------------- tuning --- */
 /* Launch-shape knobs for hierarchies built after the call (hierarchies are
  * cached per knob setting): param 0 = planes each thread walks in the cell

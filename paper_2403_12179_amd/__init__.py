@@ -9,8 +9,8 @@ built library, importing the solver raises.
 """
 from ._lib import BxmgError, DIRICHLET0, PERIODIC, lib  # noqa: F401
 from .core import Box, BoxArray, Context, MultiFab, default_context  # noqa: F401
-from .solver import (Batch, SolveResult, autotune, bottom_solve, gs_colour, heat_run, heat_step, mlmg_solve,  # noqa: F401
-                     nodal_solve, prolong_add, residual, restrict, solve_params)
+from .solver import (Batch, SolveResult, autotune, bottom_solve, composite_solve, gs_colour, heat_run, heat_step,  # noqa: F401
+                     mlmg_solve, nodal_solve, prolong_add, residual, restrict, solve_params)
 from .serve import Server  # noqa: F401
 
 __version__ = "0.1.0"

@@ -71,6 +71,7 @@ def _declare(lib):
         "bxmg_mlmg_solve": (C.c_int, [H, C.POINTER(SolveParams), H, H, H, C.POINTER(SolveInfo)]),
         "bxmg_heat_step": (C.c_int, [H, C.POINTER(SolveParams), H, H, H, C.c_double, C.POINTER(SolveInfo)]),
         "bxmg_nodal_solve": (C.c_int, [H, C.POINTER(SolveParams), H, VP, VP, C.POINTER(SolveInfo)]),
+        "bxmg_composite_solve": (C.c_int, [H, C.POINTER(SolveParams), H, H, H, H, C.POINTER(SolveInfo)]),
         "bxmg_ctx_tune": (C.c_int, [H, C.c_int32, C.c_int32]),
         "bxmg_autotune": (C.c_int, [H, C.POINTER(SolveParams), H, H, H, C.c_int32, I32P, DP, I32P]),
         "bxmg_profile_stage": (C.c_int, [H, C.c_int32]),

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbxmg.so")
-SOURCES = ["bxmg_kernels.hip", "bxmg_host.cpp", "bxmg_batch.cpp", "bxmg_nodal.hip"]
+SOURCES = ["bxmg_kernels.hip", "bxmg_host.cpp", "bxmg_batch.cpp", "bxmg_nodal.hip", "bxmg_composite.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -1,0 +1,637 @@
+// Two-level composite Poisson solve: a coarse level over the whole domain and
+// a fine level (refinement ratio 2) over a union of boxes -- the paper's
+// block-structured AMR hierarchy (Sections 1 and 2: levels of boxes,
+// inter-level interpolation and averaging, copies between decompositions).
+//
+// Unknowns are the fine cells and the coarse cells no fine box covers; a
+// covered coarse cell holds the mean of its 8 children.
+//  * A fine ghost across the coarse-fine boundary is the quadratic along the
+//    normal through U_t and the two fine cells inward (u1, u2):
+//    g = (8/15) U_t + (2/3) u1 - (1/5) u2, where U_t is the quadratic through
+//    the 3x3 coarse cells around the ghost's coarse cell C in the face plane
+//    (with the mixed term) taken at the ghost's offset (s_a, s_b) h0/4,
+//    s = +1 on the upper half of C, -1 on the lower.
+//  * Fine operator: the 7-point one with those ghosts (ghosts between fine
+//    boxes by FillBoundary).
+//  * Coarse operator at an uncovered cell: (sum of the 6 outward gradients)
+//    / h0; across a face against a covered cell the gradient is the mean of
+//    the 4 fine gradients (u_i - g_i) / h1 through it, so the coarse flux is
+//    the sum of the fine ones and the composite operator conserves.
+//  * Cycle: nu1 fine red-black sweeps (ghosts refreshed before each colour),
+//    composite residual (covered coarse cells take the mean of the fine
+//    residuals), one coarse V-cycle from zero, correction of the uncovered
+//    coarse cells and of the fine cells (trilinear interpolation, weights
+//    27, 9, 3, 1 over 64 from the parent and its neighbours on the child's
+//    side), nu2 fine sweeps, covered cells := mean of their children.
+//
+// Storage: the coarse level lives in one-box MultiFabs over the domain (the
+// caller's coarse data is ParallelCopy'd in and out), so any coarse cell is
+// one address computation away; a dense int map over the coarse cells holds
+// the fine box that covers each one (-1: uncovered).  The fine level is the
+// caller's MultiFabs; the coarse-fine ghost cells are listed once per layout.
+// Fine boxes must be unions of whole coarse cells (even lower, odd upper
+// corners) and lie at least 2 coarse cells inside the domain, so that every
+// coarse cell a ghost or an interpolation reads is a domain cell.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "bxmg_host.h"
+
+namespace bxmg {
+namespace comp {
+
+constexpr int kCB = 256;         // threads per block
+constexpr int kCellsPerThread = 4;
+constexpr int kMaxCoarseBlocks = 16384;
+
+// The coarse level: layout of the one-box fields and the domain.
+struct CGeo {
+    FBox cb;          // every coarse field has this layout (one box, 1 ghost)
+    int dlo[3], n[3]; // coarse domain
+    int per[3];
+    double h0, h1;
+};
+
+__device__ __forceinline__ long long cq(const CGeo& g, int I, int J, int K) {
+    return (long long)(I - g.dlo[0]) + (long long)g.n[0] * ((long long)(J - g.dlo[1]) + (long long)g.n[1] * (K - g.dlo[2]));
+}
+
+__device__ __forceinline__ long long fidx(const FBox& b, int i, int j, int k) {
+    return b.base + (long long)(i - b.glo[0]) + (long long)b.G[0] * ((long long)(j - b.glo[1]) + (long long)b.G[1] * (k - b.glo[2]));
+}
+
+__device__ __forceinline__ void block_norms(double mx, double s2, double bad, double* __restrict__ partials) {
+    __shared__ double sh[3 * (kCB / 64)];
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = fmax(mx, __shfl_xor(mx, o));
+        s2 = s2 + __shfl_xor(s2, o);
+        bad = bad + __shfl_xor(bad, o);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { sh[3 * wid] = mx; sh[3 * wid + 1] = s2; sh[3 * wid + 2] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kCB / 64; ++w) { mx = fmax(mx, sh[3 * w]); s2 = s2 + sh[3 * w + 1]; bad = bad + sh[3 * w + 2]; }
+        partials[3 * blockIdx.x] = mx;
+        partials[3 * blockIdx.x + 1] = s2;
+        partials[3 * blockIdx.x + 2] = bad;
+    }
+}
+
+__device__ __forceinline__ void norm_add(double rv, double& mx, double& s2, double& bad) {
+    const double a = fabs(rv);
+    if (!(a <= 1.7976931348623157e308)) bad += 1.0;
+    else mx = fmax(mx, a);
+    s2 = s2 + rv * rv;
+}
+
+// Coarse-fine ghosts.  One entry per ghost cell: x = box | d << 24 | side << 26
+// (the ghost lies beyond face (d, side) of its box), y, z, w = its fine index.
+__global__ void __launch_bounds__(kCB) k_cf_ghost(const int4* __restrict__ list, long long n, CGeo g,
+                                                  const double* __restrict__ Uc, const FBox* __restrict__ fu,
+                                                  double* __restrict__ uf) {
+    const long long q = (long long)blockIdx.x * kCB + threadIdx.x;
+    if (q >= n) return;
+    const int4 r = list[q];
+    const int b = r.x & 0xffffff, d = (r.x >> 24) & 3, side = (r.x >> 26) & 1;
+    const int gx[3] = {r.y, r.z, r.w};
+    const FBox B = fu[b];
+    const int step = side ? -1 : 1;  // from the ghost into its box
+    int i1[3] = {gx[0], gx[1], gx[2]}, i2[3] = {gx[0], gx[1], gx[2]};
+    i1[d] += step;
+    i2[d] += 2 * step;
+    const int C[3] = {gx[0] >> 1, gx[1] >> 1, gx[2] >> 1};
+    const int ta = d == 2 ? 0 : d + 1, tb = d == 0 ? 2 : d - 1;
+    const double sa = (gx[ta] & 1) ? 1.0 : -1.0, sb = (gx[tb] & 1) ? 1.0 : -1.0;
+    auto U = [&](int p, int s) {
+        int x[3] = {C[0], C[1], C[2]};
+        x[ta] += p;
+        x[tb] += s;
+        return Uc[fidx(g.cb, x[0], x[1], x[2])];
+    };
+    const double UC = U(0, 0);
+    const double Up0 = U(1, 0), Um0 = U(-1, 0), U0p = U(0, 1), U0m = U(0, -1);
+    const double da = (Up0 - Um0) * 0.125 * sa, db = (U0p - U0m) * 0.125 * sb;
+    const double qa = ((Up0 + Um0) - 2.0 * UC) * (1.0 / 32.0);
+    const double qb = ((U0p + U0m) - 2.0 * UC) * (1.0 / 32.0);
+    const double xab = ((U(1, 1) - U(1, -1)) - (U(-1, 1) - U(-1, -1))) * (1.0 / 64.0) * (sa * sb);
+    const double Ut = UC + ((da + db) + (qa + qb)) + xab;
+    const double u1 = uf[fidx(B, i1[0], i1[1], i1[2])], u2 = uf[fidx(B, i2[0], i2[1], i2[2])];
+    uf[fidx(B, gx[0], gx[1], gx[2])] = ((8.0 / 15.0) * Ut + (2.0 / 3.0) * u1) - (1.0 / 5.0) * u2;
+}
+
+// One colour of red-black Gauss-Seidel on the fine boxes (ghosts current):
+// u = (sum of the 6 neighbours - h1^2 f) / 6 at the cells of that colour.
+// bpb blocks per box; thread t walks half-row positions of its box.
+__global__ void __launch_bounds__(kCB) k_fine_gs(CGeo g, const FBox* __restrict__ fu, const FBox* __restrict__ ff,
+                                                 double* __restrict__ u, const double* __restrict__ f, int colour,
+                                                 int bpb) {
+    const int b = blockIdx.x / bpb, lb = blockIdx.x % bpb;
+    const FBox B = fu[b], F = ff[b];
+    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1, nz = B.hi[2] - B.lo[2] + 1;
+    const int nxh = (nx + 1) >> 1;
+    const long long total = (long long)nxh * ny * nz;
+    const long long sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
+    const double h2 = g.h1 * g.h1;
+    for (long long t = (long long)lb * kCB + threadIdx.x; t < total; t += (long long)bpb * kCB) {
+        const int tx = (int)(t % nxh);
+        const long long rest = t / nxh;
+        const int j = B.lo[1] + (int)(rest % ny), k = B.lo[2] + (int)(rest / ny);
+        const int i = B.lo[0] + 2 * tx + ((B.lo[0] + j + k + colour) & 1);
+        if (i > B.hi[0]) continue;
+        const long long c = fidx(B, i, j, k);
+        const double su = ((u[c - 1] + u[c + 1]) + (u[c - sy] + u[c + sy])) + (u[c - sz] + u[c + sz]);
+        u[c] = (su - h2 * f[fidx(F, i, j, k)]) / 6.0;
+    }
+}
+
+// Fine residual r = f - L u on the valid cells (or r = f with fonly), with
+// per-block norms (max, sum of squares, non-finite count).
+__global__ void __launch_bounds__(kCB) k_fine_resid(CGeo g, const FBox* __restrict__ fu, const FBox* __restrict__ ff,
+                                                    const FBox* __restrict__ fr, const double* __restrict__ u,
+                                                    const double* __restrict__ f, double* __restrict__ r, int bpb,
+                                                    int fonly, double* __restrict__ partials) {
+    const int b = blockIdx.x / bpb, lb = blockIdx.x % bpb;
+    const FBox B = fu[b], F = ff[b], R = fr[b];
+    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1, nz = B.hi[2] - B.lo[2] + 1;
+    const long long total = (long long)nx * ny * nz;
+    const long long sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
+    const double ih2 = 1.0 / (g.h1 * g.h1);
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    for (long long t = (long long)lb * kCB + threadIdx.x; t < total; t += (long long)bpb * kCB) {
+        const int i = B.lo[0] + (int)(t % nx);
+        const long long rest = t / nx;
+        const int j = B.lo[1] + (int)(rest % ny), k = B.lo[2] + (int)(rest / ny);
+        double rv = f[fidx(F, i, j, k)];
+        if (!fonly) {
+            const long long c = fidx(B, i, j, k);
+            const double su = ((u[c - 1] + u[c + 1]) + (u[c - sy] + u[c + sy])) + (u[c - sz] + u[c + sz]);
+            rv = rv - (su - 6.0 * u[c]) * ih2;
+            r[fidx(R, i, j, k)] = rv;
+        }
+        norm_add(rv, mx, s2, bad);
+    }
+    block_norms(mx, s2, bad, partials);
+}
+
+__device__ __forceinline__ double mean8(const double* __restrict__ x, const FBox& B, int i, int j, int k) {
+    const long long c = fidx(B, i, j, k), sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
+    return (((x[c] + x[c + 1]) + (x[c + sy] + x[c + sy + 1])) +
+            ((x[c + sz] + x[c + sz + 1]) + (x[c + sz + sy] + x[c + sz + sy + 1]))) * 0.125;
+}
+
+// Composite residual on the coarse level: uncovered cells f - Lc u (norms
+// taken there), covered cells the mean of the fine residuals below them
+// (fonly: the norms of f at the uncovered cells, Rc untouched).  Fine ghosts
+// of the current state must be in place (the flux-matched faces read them).
+__global__ void __launch_bounds__(kCB) k_coarse_resid(CGeo g, const int* __restrict__ cmap,
+                                                      const double* __restrict__ Uc, const double* __restrict__ Fc,
+                                                      double* __restrict__ Rc, const FBox* __restrict__ fu,
+                                                      const double* __restrict__ uf, const FBox* __restrict__ fr,
+                                                      const double* __restrict__ rf, int fonly,
+                                                      double* __restrict__ partials) {
+    const long long total = (long long)g.n[0] * g.n[1] * g.n[2];
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    for (long long q = (long long)blockIdx.x * kCB + threadIdx.x; q < total; q += (long long)gridDim.x * kCB) {
+        const int I = g.dlo[0] + (int)(q % g.n[0]);
+        const long long rest = q / g.n[0];
+        const int J = g.dlo[1] + (int)(rest % g.n[1]), K = g.dlo[2] + (int)(rest / g.n[1]);
+        const int code = cmap[q];
+        const long long c = fidx(g.cb, I, J, K);
+        if (code >= 0) {
+            if (!fonly) Rc[c] = mean8(rf, fr[code], 2 * I, 2 * J, 2 * K);
+            continue;
+        }
+        double rv = Fc[c];
+        if (!fonly) {
+            const double UI = Uc[c];
+            const int X[3] = {I, J, K};
+            double gr[6];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    int nb[3] = {X[0], X[1], X[2]};
+                    nb[d] += side ? 1 : -1;
+                    double v;
+                    if (nb[d] < g.dlo[d] || nb[d] >= g.dlo[d] + g.n[d]) {
+                        if (!g.per[d]) {
+                            gr[2 * d + side] = (-UI - UI) / g.h0;
+                            continue;
+                        }
+                        nb[d] = nb[d] < g.dlo[d] ? nb[d] + g.n[d] : nb[d] - g.n[d];
+                    }
+                    const int nc = cmap[cq(g, nb[0], nb[1], nb[2])];
+                    if (nc < 0) {
+                        v = (Uc[fidx(g.cb, nb[0], nb[1], nb[2])] - UI) / g.h0;
+                    } else {
+                        // the 4 fine cells of the covered neighbour against the face
+                        const FBox B = fu[nc];
+                        const int ta = d == 2 ? 0 : d + 1, tb = d == 0 ? 2 : d - 1;
+                        double a[2][2];
+#pragma unroll
+                        for (int s = 0; s < 2; ++s)
+#pragma unroll
+                            for (int p = 0; p < 2; ++p) {
+                                int fi[3];
+                                fi[d] = 2 * nb[d] + (side ? 0 : 1);
+                                fi[ta] = 2 * nb[ta] + p;
+                                fi[tb] = 2 * nb[tb] + s;
+                                int gc[3] = {fi[0], fi[1], fi[2]};
+                                gc[d] += side ? -1 : 1;
+                                a[s][p] = (uf[fidx(B, fi[0], fi[1], fi[2])] - uf[fidx(B, gc[0], gc[1], gc[2])]) / g.h1;
+                            }
+                        v = ((a[0][0] + a[0][1]) + (a[1][0] + a[1][1])) * 0.25;
+                    }
+                    gr[2 * d + side] = v;
+                }
+            rv = rv - (((gr[0] + gr[1]) + (gr[2] + gr[3])) + (gr[4] + gr[5])) / g.h0;
+            Rc[c] = rv;
+        }
+        norm_add(rv, mx, s2, bad);
+    }
+    block_norms(mx, s2, bad, partials);
+}
+
+// Uc += Ec at the uncovered coarse cells.
+__global__ void __launch_bounds__(kCB) k_coarse_update(CGeo g, const int* __restrict__ cmap, double* __restrict__ Uc,
+                                                       const double* __restrict__ Ec) {
+    const long long total = (long long)g.n[0] * g.n[1] * g.n[2];
+    for (long long q = (long long)blockIdx.x * kCB + threadIdx.x; q < total; q += (long long)gridDim.x * kCB) {
+        if (cmap[q] >= 0) continue;
+        const int I = g.dlo[0] + (int)(q % g.n[0]);
+        const long long rest = q / g.n[0];
+        const long long c = fidx(g.cb, I, g.dlo[1] + (int)(rest % g.n[1]), g.dlo[2] + (int)(rest / g.n[1]));
+        Uc[c] = Uc[c] + Ec[c];
+    }
+}
+
+// Covered coarse cells := the mean of their 8 children.
+__global__ void __launch_bounds__(kCB) k_coarse_sync(CGeo g, const int* __restrict__ cmap, double* __restrict__ Uc,
+                                                     const FBox* __restrict__ fu, const double* __restrict__ uf) {
+    const long long total = (long long)g.n[0] * g.n[1] * g.n[2];
+    for (long long q = (long long)blockIdx.x * kCB + threadIdx.x; q < total; q += (long long)gridDim.x * kCB) {
+        const int code = cmap[q];
+        if (code < 0) continue;
+        const int I = g.dlo[0] + (int)(q % g.n[0]);
+        const long long rest = q / g.n[0];
+        const int J = g.dlo[1] + (int)(rest % g.n[1]), K = g.dlo[2] + (int)(rest / g.n[1]);
+        Uc[fidx(g.cb, I, J, K)] = mean8(uf, fu[code], 2 * I, 2 * J, 2 * K);
+    }
+}
+
+// Fine cells += trilinear interpolation of the coarse correction Ec.
+__global__ void __launch_bounds__(kCB) k_fine_prolong(CGeo g, const FBox* __restrict__ fu, double* __restrict__ u,
+                                                      const double* __restrict__ Ec, int bpb) {
+    const int b = blockIdx.x / bpb, lb = blockIdx.x % bpb;
+    const FBox B = fu[b];
+    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1, nz = B.hi[2] - B.lo[2] + 1;
+    const long long total = (long long)nx * ny * nz;
+    for (long long t = (long long)lb * kCB + threadIdx.x; t < total; t += (long long)bpb * kCB) {
+        const int i = B.lo[0] + (int)(t % nx);
+        const long long rest = t / nx;
+        const int j = B.lo[1] + (int)(rest % ny), k = B.lo[2] + (int)(rest / ny);
+        const int I = i >> 1, J = j >> 1, K = k >> 1;
+        const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+        auto E = [&](int a, int bb, int cc) { return Ec[fidx(g.cb, a, bb, cc)]; };
+        const double c000 = E(I, J, K), c100 = E(I + si, J, K), c010 = E(I, J + sj, K), c001 = E(I, J, K + sk);
+        const double c110 = E(I + si, J + sj, K), c101 = E(I + si, J, K + sk), c011 = E(I, J + sj, K + sk);
+        const double c111 = E(I + si, J + sj, K + sk);
+        const double v = (((27.0 * c000 + 9.0 * ((c100 + c010) + c001)) + 3.0 * ((c110 + c101) + c011)) + c111) *
+                         (1.0 / 64.0);
+        const long long c = fidx(B, i, j, k);
+        u[c] = u[c] + v;
+    }
+}
+
+// Component 0 of every fine box, valid and ghost cells, := 0.
+__global__ void __launch_bounds__(kCB) k_fine_zero(const FBox* __restrict__ fu, double* __restrict__ u, int bpb) {
+    const int b = blockIdx.x / bpb, lb = blockIdx.x % bpb;
+    const FBox B = fu[b];
+    const long long total = (long long)B.G[0] * B.G[1] * B.G[2];
+    for (long long t = (long long)lb * kCB + threadIdx.x; t < total; t += (long long)bpb * kCB) u[B.base + t] = 0.0;
+}
+
+// ------------------------------------------------------------------ host
+struct Comp {
+    bxmg_ctx ctx = nullptr;
+    uint64_t cba_id = 0, fba_id = 0;
+    double h0 = 0.0;
+    bxmg_boxarray one = nullptr;                              // one box over the coarse domain
+    bxmg_multifab Uc = nullptr, Fc = nullptr, Rc = nullptr, Ec = nullptr;  // over `one`, 1 ghost
+    bxmg_multifab Rf = nullptr;                               // fine residual (caller's fine boxes)
+    CGeo geo{};
+    DevBuf<int> cmap;
+    DevBuf<int4> ghosts;
+    long long nghosts = 0;
+    int nfine = 0, bpb = 1, bpb_gs = 1, nbc = 1;
+    DevBuf<double> part, fn;
+    double* h_norm = nullptr;  // pinned: the norms read back
+    ~Comp() {
+        for (bxmg_multifab m : {Uc, Fc, Rc, Ec, Rf})
+            if (m) bxmg_multifab_release(m);
+        if (one) bxmg_boxarray_release(one);
+        const hipStream_t s = ctx ? ctx->stream : nullptr;
+        cmap.release_async(s);
+        ghosts.release_async(s);
+        part.release_async(s);
+        fn.release_async(s);
+        if (h_norm) {
+            (void)hipStreamSynchronize(s);
+            (void)hipHostFree(h_norm);
+        }
+    }
+};
+
+static unsigned blocks_for(long long n) { return (unsigned)((n + kCB - 1) / kCB); }
+
+// Checks the fine layout against the coarse domain: the fine domain is the
+// coarse one refined by 2 with the same boundaries, every fine box is a union
+// of whole coarse cells and lies 2 coarse cells (4 fine) inside every domain
+// face.  Returns "" or the reason.
+static std::string layout_error(const bxmg_ba_s* cba, const bxmg_ba_s* fba) {
+    for (int d = 0; d < 3; ++d) {
+        if (fba->dom.lo[d] != 2 * cba->dom.lo[d] || fba->dom.hi[d] != 2 * cba->dom.hi[d] + 1)
+            return "the fine domain must be the coarse domain refined by 2";
+        if (fba->per[d] != cba->per[d]) return "the fine and coarse boundaries differ";
+    }
+    if (fba->boxes.size() >= (1u << 24)) return "too many fine boxes";
+    for (const Box& B : fba->boxes)
+        for (int d = 0; d < 3; ++d) {
+            if ((B.lo[d] & 1) || !(B.hi[d] & 1)) return "fine boxes must be unions of whole coarse cells";
+            if (B.lo[d] < fba->dom.lo[d] + 4 || B.hi[d] > fba->dom.hi[d] - 4)
+                return "fine boxes must lie 2 coarse cells inside the domain";
+        }
+    return "";
+}
+
+static bxmg_multifab alloc_mf(bxmg_ctx ctx, bxmg_boxarray ba, int ng) {
+    bxmg_multifab m = nullptr;
+    if (bxmg_alloc_multifab(ctx, ba, 1, ng, BXMG_F64, nullptr, &m) != BXMG_OK) throw std::runtime_error(bxmg_last_error());
+    return m;
+}
+
+static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxmg_ba_s* fba, double h0) {
+    auto c = std::make_unique<Comp>();
+    c->ctx = ctx;
+    c->cba_id = cba->id;
+    c->fba_id = fba->id;
+    c->h0 = h0;
+    const Box& D = cba->dom;
+    const int lohi[6] = {D.lo[0], D.lo[1], D.lo[2], D.hi[0], D.hi[1], D.hi[2]};
+    if (bxmg_define_boxarray_list(D.lo, D.hi, cba->bc, 1, lohi, &c->one) != BXMG_OK)
+        throw std::runtime_error(bxmg_last_error());
+    c->Uc = alloc_mf(ctx, c->one, 1);
+    c->Fc = alloc_mf(ctx, c->one, 1);
+    c->Rc = alloc_mf(ctx, c->one, 1);
+    c->Ec = alloc_mf(ctx, c->one, 1);
+    // the fine residual over the caller's fine boxes
+    bxmg_boxarray fcopy = nullptr;
+    std::vector<int32_t> fl;
+    for (const Box& B : fba->boxes)
+        for (int v : {B.lo[0], B.lo[1], B.lo[2], B.hi[0], B.hi[1], B.hi[2]}) fl.push_back(v);
+    if (bxmg_define_boxarray_list(fba->dom.lo, fba->dom.hi, fba->bc, (int32_t)fba->boxes.size(), fl.data(), &fcopy) !=
+        BXMG_OK)
+        throw std::runtime_error(bxmg_last_error());
+    c->Rf = alloc_mf(ctx, fcopy, 0);
+    bxmg_boxarray_release(fcopy);  // the MultiFab keeps its reference
+    CGeo& g = c->geo;
+    g.cb = c->Uc->fboxes[0];
+    for (int d = 0; d < 3; ++d) {
+        g.dlo[d] = D.lo[d];
+        g.n[d] = D.n(d);
+        g.per[d] = cba->per[d];
+    }
+    g.h0 = h0;
+    g.h1 = h0 * 0.5;
+    // coverage map
+    const long long nc = D.cells();
+    std::vector<int> cmap((size_t)nc, -1);
+    auto cidx = [&](int I, int J, int K) {
+        return (size_t)(I - D.lo[0]) + (size_t)D.n(0) * ((size_t)(J - D.lo[1]) + (size_t)D.n(1) * (K - D.lo[2]));
+    };
+    const auto& fb = fba->boxes;
+    c->nfine = (int)fb.size();
+    long long maxcells = 1;
+    for (size_t b = 0; b < fb.size(); ++b) {
+        const Box& B = fb[b];
+        maxcells = std::max(maxcells, B.cells());
+        for (int K = B.lo[2] / 2; K <= B.hi[2] / 2; ++K)
+            for (int J = B.lo[1] / 2; J <= B.hi[1] / 2; ++J)
+                for (int I = B.lo[0] / 2; I <= B.hi[0] / 2; ++I) cmap[cidx(I, J, K)] = (int)b;
+    }
+    // coarse-fine ghosts: face ghosts of each fine box whose coarse cell no
+    // fine box covers (the others are fine cells, filled by FillBoundary)
+    std::vector<int4> gl;
+    for (size_t b = 0; b < fb.size(); ++b) {
+        const Box& B = fb[b];
+        for (int d = 0; d < 3; ++d)
+            for (int side = 0; side < 2; ++side) {
+                const int ta = d == 2 ? 0 : d + 1, tb = d == 0 ? 2 : d - 1;
+                for (int y = B.lo[tb]; y <= B.hi[tb]; ++y)
+                    for (int x = B.lo[ta]; x <= B.hi[ta]; ++x) {
+                        int gx[3];
+                        gx[d] = side ? B.hi[d] + 1 : B.lo[d] - 1;
+                        gx[ta] = x;
+                        gx[tb] = y;
+                        if (cmap[cidx(gx[0] >> 1, gx[1] >> 1, gx[2] >> 1)] >= 0) continue;
+                        gl.push_back(make_int4((int)b | (d << 24) | (side << 26), gx[0], gx[1], gx[2]));
+                    }
+            }
+    }
+    c->nghosts = (long long)gl.size();
+    const hipStream_t s = ctx->stream;
+    c->cmap.upload_async(cmap, s);
+    c->ghosts.upload_async(gl, s);
+    c->bpb = (int)std::max(1LL, (maxcells + (long long)kCB * kCellsPerThread - 1) / ((long long)kCB * kCellsPerThread));
+    c->bpb_gs = (int)std::max(1LL, (maxcells / 2 + (long long)kCB * kCellsPerThread - 1) / ((long long)kCB * kCellsPerThread));
+    c->nbc = (int)std::min<long long>(kMaxCoarseBlocks, std::max(1LL, (nc + (long long)kCB * kCellsPerThread - 1) /
+                                                                          ((long long)kCB * kCellsPerThread)));
+    std::vector<double> zero((size_t)3 * ((size_t)c->nfine * c->bpb + c->nbc), 0.0);
+    c->part.upload_async(zero, s);
+    c->fn.upload_async(std::vector<double>(3, 0.0), s);
+    HIPCHK(hipHostMalloc((void**)&c->h_norm, 4 * sizeof(double)));
+    return c;
+}
+
+struct Cache {
+    std::unique_ptr<Comp> comp;  // the last layout used
+};
+
+}  // namespace comp
+}  // namespace bxmg
+
+using namespace bxmg;
+
+extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi_c,
+                                            bxmg_multifab rhs_c, bxmg_multifab phi_f, bxmg_multifab rhs_f,
+                                            bxmg_solve_info* info) {
+    if (!ctx || !phi_c || !rhs_c || !phi_f || !rhs_f || !info) return fail(BXMG_EINVAL, "composite_solve: NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    bxmg_solve_params P;
+    if (params) P = *params;
+    else bxmg_solve_params_default(&P);
+    auto bad = [&](const std::string& m) {
+        info->status = fail(BXMG_EINVAL, "composite_solve: " + m);
+        return (bxmg_status)info->status;
+    };
+    if (P.nu1 < 0 || P.nu2 < 0 || P.max_cycles < 0 || P.precision != 0 || P.krylov != 0 || P.alpha != 0.0 ||
+        P.prolong != 2)
+        return bad("FP64 V-cycles of the Poisson operator with trilinear prolongation only "
+                   "(precision 0, krylov 0, alpha 0, prolong 2)");
+    for (bxmg_multifab m : {phi_c, rhs_c, phi_f, rhs_f})
+        if (m->dtype != BXMG_F64) return bad("every field must be FP64");
+    for (bxmg_multifab m : {phi_c, rhs_c, phi_f, rhs_f})
+        if (m->ctx->device != ctx->device) return bad("fields on another device");
+    const bxmg_ba_s* cba = phi_c->ba;
+    const bxmg_ba_s* fba = phi_f->ba;
+    if (check_field_mf(rhs_c, cba, "coarse rhs") != BXMG_OK || check_field_mf(rhs_f, fba, "fine rhs") != BXMG_OK)
+        return (bxmg_status)(info->status = BXMG_EINVAL);
+    if (!covers_domain(cba)) return bad("the coarse BoxArray must cover its domain");
+    if (phi_f->ng < 1) return bad("the fine solution needs nghost >= 1");
+    const std::string le = comp::layout_error(cba, fba);
+    if (!le.empty()) return bad(le);
+    const double h0 = (P.dx > 0) ? P.dx : 1.0 / cba->dom.n(0);
+    // cached state on the context; composite solves on one context run one at a time
+    std::lock_guard<std::mutex> lock(ctx->comp_mu);
+    const auto t0 = std::chrono::steady_clock::now();
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        if (!ctx->composite) ctx->composite = std::make_shared<comp::Cache>();
+        auto* cache = (comp::Cache*)ctx->composite.get();
+        if (!cache->comp || cache->comp->cba_id != cba->id || cache->comp->fba_id != fba->id || cache->comp->h0 != h0) {
+            cache->comp.reset();
+            cache->comp = comp::build(ctx, cba, fba, h0);
+        }
+        comp::Comp& c = *cache->comp;
+        const hipStream_t s = ctx->stream;
+        const comp::CGeo& g = c.geo;
+        double* Uc = (double*)c.Uc->data;
+        double* Fc = (double*)c.Fc->data;
+        double* Rc = (double*)c.Rc->data;
+        double* Ec = (double*)c.Ec->data;
+        double* uf = (double*)phi_f->data;
+        const double* ff = (const double*)rhs_f->data;
+        double* rf = (double*)c.Rf->data;
+        const FBox* fu = phi_f->d_fboxes.p;
+        const FBox* fF = rhs_f->d_fboxes.p;
+        const FBox* fR = c.Rf->d_fboxes.p;
+        const unsigned nfb = (unsigned)c.nfine;
+        double* const part_c = c.part.p + 3 * (size_t)c.nfine * c.bpb;
+        const int nparts = c.nfine * c.bpb + c.nbc;
+        auto chk = [](bxmg_status st) {
+            if (st != BXMG_OK) throw std::runtime_error(bxmg_last_error());
+        };
+        // load: coarse rhs into the one-box field, zero start on both levels
+        chk(bxmg_parallel_copy(c.Fc, 0, rhs_c, 0, 1, 0, s));
+        HIPCHK(hipMemsetAsync(Uc, 0, c.Uc->bytes, s));
+        if (nfb) hipLaunchKernelGGL(comp::k_fine_zero, dim3(nfb * c.bpb), dim3(comp::kCB), 0, s, fu, uf, c.bpb);
+        HIPCHK(hipGetLastError());
+        auto fill_fine = [&]() {
+            if (!nfb) return;
+            chk(bxmg_fill_boundary(phi_f, 0, 1, 1, s));
+            if (c.nghosts)
+                hipLaunchKernelGGL(comp::k_cf_ghost, dim3(comp::blocks_for(c.nghosts)), dim3(comp::kCB), 0, s,
+                                   c.ghosts.p, c.nghosts, g, (const double*)Uc, fu, uf);
+            HIPCHK(hipGetLastError());
+        };
+        // composite residual (fonly: norms of f) into Rf / Rc, norms read back
+        auto residual = [&](bool fonly, double out[3]) {
+            if (!fonly) fill_fine();
+            if (nfb)
+                hipLaunchKernelGGL(comp::k_fine_resid, dim3(nfb * c.bpb), dim3(comp::kCB), 0, s, g, fu, fF, fR,
+                                   (const double*)uf, ff, rf, c.bpb, (int)fonly, c.part.p);
+            hipLaunchKernelGGL(comp::k_coarse_resid, dim3(c.nbc), dim3(comp::kCB), 0, s, g, (const int*)c.cmap.p,
+                               (const double*)Uc, (const double*)Fc, Rc, fu, (const double*)uf, fR,
+                               (const double*)rf, (int)fonly, part_c);
+            HIPCHK(hipGetLastError());
+            HIPCHK(launch_norm_final(s, c.part.p, nparts, c.fn.p));
+            HIPCHK(hipMemcpyAsync(c.h_norm, c.fn.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            out[0] = c.h_norm[2] > 0.0 ? (double)NAN : c.h_norm[0];
+            out[1] = c.h_norm[1];
+            out[2] = c.h_norm[2];
+        };
+        auto sweeps = [&](int n) {
+            for (int q = 0; q < n; ++q)
+                for (int col = 0; col < 2; ++col) {
+                    fill_fine();
+                    if (nfb)
+                        hipLaunchKernelGGL(comp::k_fine_gs, dim3(nfb * c.bpb_gs), dim3(comp::kCB), 0, s, g, fu, fF, uf,
+                                           ff, col, c.bpb_gs);
+                    HIPCHK(hipGetLastError());
+                }
+        };
+        bxmg_solve_params Pc = P;
+        Pc.fixed_cycles = 1;
+        Pc.dx = h0;
+        auto cycle = [&]() {
+            sweeps(P.nu1);
+            double rn[3];
+            residual(false, rn);
+            // coarse correction: one V-cycle from zero on the composite residual
+            HIPCHK(hipMemsetAsync(Ec, 0, c.Ec->bytes, s));
+            bxmg_solve_info ci;
+            const bxmg_status st = bxmg_mlmg_solve(ctx, &Pc, c.Ec, c.Rc, nullptr, &ci);
+            if (st != BXMG_OK) throw std::runtime_error(bxmg_last_error());
+            info->levels = ci.levels + 1;
+            hipLaunchKernelGGL(comp::k_coarse_update, dim3(c.nbc), dim3(comp::kCB), 0, s, g, (const int*)c.cmap.p, Uc,
+                               (const double*)Ec);
+            if (nfb)
+                hipLaunchKernelGGL(comp::k_fine_prolong, dim3(nfb * c.bpb), dim3(comp::kCB), 0, s, g, fu, uf,
+                                   (const double*)Ec, c.bpb);
+            HIPCHK(hipGetLastError());
+            sweeps(P.nu2);
+            hipLaunchKernelGGL(comp::k_coarse_sync, dim3(c.nbc), dim3(comp::kCB), 0, s, g, (const int*)c.cmap.p, Uc, fu,
+                               (const double*)uf);
+            HIPCHK(hipGetLastError());
+        };
+        double fz[3];
+        residual(true, fz);
+        const double fnorm = fz[0];
+        info->f_inf = fnorm;
+        int status = 0, cyc = 0;
+        if (!(fnorm == fnorm)) {
+            status = BXMG_ENONFINITE;
+        } else if (fnorm > 0.0) {
+            for (;; ++cyc) {
+                double rn[3];
+                residual(false, rn);
+                if (cyc < kHist) {
+                    info->hist[cyc] = rn[0] / fnorm;
+                    info->hist_l2[cyc] = std::sqrt(rn[1]);
+                    info->nhist = cyc + 1;
+                }
+                info->rel_resid_inf = rn[0] / fnorm;
+                info->resid_l2 = std::sqrt(rn[1]);
+                if (!(rn[0] == rn[0])) { status = BXMG_ENONFINITE; break; }
+                if (P.fixed_cycles > 0) {
+                    if (cyc == P.fixed_cycles) break;
+                } else {
+                    if (rn[0] <= P.rel_tol * fnorm || rn[0] <= P.abs_tol) break;
+                    if (cyc == P.max_cycles) { status = BXMG_ENOCONV; break; }
+                }
+                cycle();
+            }
+        }
+        info->cycles = cyc;
+        // the coarse solution (covered cells: the mean of their children) back
+        chk(bxmg_parallel_copy(phi_c, 0, c.Uc, 0, 1, 0, s));
+        HIPCHK(hipStreamSynchronize(s));
+        info->status = status;
+        if (status == BXMG_ENOCONV) fail(BXMG_ENOCONV, "composite_solve: max_cycles reached");
+        if (status == BXMG_ENONFINITE) fail(BXMG_ENONFINITE, "composite_solve: non-finite values");
+    } catch (HipError& e) {
+        info->status = fail(BXMG_EDEVICE, std::string("composite_solve: ") + e.where + ": " + hipGetErrorString(e.e));
+    } catch (std::exception& e) {
+        info->status = fail(BXMG_EINVAL, std::string("composite_solve: ") + e.what());
+    }
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return (bxmg_status)info->status;
+}

@@ -651,6 +651,9 @@ void bxmg_ctx_destroy(bxmg_ctx ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     ctx->cache.clear();
+    ctx->composite.reset();
+    ctx->nodal.reset();
+    (void)hipStreamSynchronize(ctx->stream);
     if (ctx->h_norm) (void)hipHostFree(ctx->h_norm);
     if (ctx->h_solve) (void)hipHostFree(ctx->h_solve);
     delete ctx;

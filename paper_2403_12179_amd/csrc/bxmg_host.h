@@ -608,6 +608,8 @@ struct bxmg_ctx_s {
     void* h_solve = nullptr;   // pinned: a solve's stop-test state read back (history, slot, flag)
     void* scratch = nullptr;   // the device's staging array (scratch_address), kScratchBytes
     std::shared_ptr<void> nodal;  // nodal-solver hierarchies (bxmg_nodal.hip)
+    std::shared_ptr<void> composite;  // composite-solve state of the last layout (bxmg_composite.hip)
+    std::mutex comp_mu;               // composite solves on one context run one at a time
     std::mutex mu;
 };
 

@@ -97,6 +97,23 @@ def nodal_solve(ba, phi, rhs, raise_on_error=True, **params):
     return res
 
 
+def composite_solve(phi_c: MultiFab, rhs_c: MultiFab, phi_f: MultiFab, rhs_f: MultiFab, raise_on_error=True,
+                    **params):
+    """Two-level composite Poisson solve (coarse level over the domain, fine
+    level of ratio 2 over phi_f's boxes) into phi_c and phi_f, both started
+    from zero.  phi_f's BoxArray has the coarse domain refined by 2; its
+    boxes are unions of whole coarse cells, 4 fine cells inside the domain.
+    params as for mlmg_solve (FP64 V-cycles of the Poisson operator)."""
+    p = solve_params(**params)
+    info = L.SolveInfo()
+    st = L.lib().bxmg_composite_solve(phi_c.ctx._h, C.byref(p), phi_c._h, rhs_c._h, phi_f._h, rhs_f._h,
+                                      C.byref(info))
+    res = _result(info)
+    if raise_on_error and st not in (0, -4, -5):
+        L.check(st)
+    return res
+
+
 def _ctx_of(t):
     from .core import default_context
     ctx = default_context()
