@@ -46,27 +46,29 @@
 namespace bxmg {
 namespace comp {
 
-constexpr int kCB = 256;         // threads per block
-constexpr int kCellsPerThread = 4;
-constexpr int kMaxCoarseBlocks = 16384;
+constexpr int kCB = 256;  // threads per block
+constexpr int kKZ = 8;    // planes each thread walks
 
 // The coarse level: layout of the one-box fields and the domain.
 struct CGeo {
-    FBox cb;          // every coarse field has this layout (one box, 1 ghost)
-    int dlo[3], n[3]; // coarse domain
+    FBox cb;           // every coarse field has this layout (one box, 1 ghost)
+    int dlo[3], n[3];  // coarse domain
     int per[3];
     double h0, h1;
 };
 
-__device__ __forceinline__ long long cq(const CGeo& g, int I, int J, int K) {
-    return (long long)(I - g.dlo[0]) + (long long)g.n[0] * ((long long)(J - g.dlo[1]) + (long long)g.n[1] * (K - g.dlo[2]));
+// Coverage map entry of a coarse cell: >= 0 the fine box covering it;
+// otherwise -1 - mask, bit 2 d + side of mask set when the face neighbour
+// across (d, side) is covered.
+__device__ __forceinline__ int cq(const CGeo& g, int I, int J, int K) {
+    return (I - g.dlo[0]) + g.n[0] * ((J - g.dlo[1]) + g.n[1] * (K - g.dlo[2]));
 }
 
 __device__ __forceinline__ long long fidx(const FBox& b, int i, int j, int k) {
-    return b.base + (long long)(i - b.glo[0]) + (long long)b.G[0] * ((long long)(j - b.glo[1]) + (long long)b.G[1] * (k - b.glo[2]));
+    return b.base + (long long)((i - b.glo[0]) + b.G[0] * ((j - b.glo[1]) + b.G[1] * (k - b.glo[2])));
 }
 
-__device__ __forceinline__ void block_norms(double mx, double s2, double bad, double* __restrict__ partials) {
+__device__ __forceinline__ void block_norms(double mx, double s2, double bad, double* __restrict__ out3) {
     __shared__ double sh[3 * (kCB / 64)];
     for (int o = 32; o > 0; o >>= 1) {
         mx = fmax(mx, __shfl_xor(mx, o));
@@ -78,9 +80,9 @@ __device__ __forceinline__ void block_norms(double mx, double s2, double bad, do
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < kCB / 64; ++w) { mx = fmax(mx, sh[3 * w]); s2 = s2 + sh[3 * w + 1]; bad = bad + sh[3 * w + 2]; }
-        partials[3 * blockIdx.x] = mx;
-        partials[3 * blockIdx.x + 1] = s2;
-        partials[3 * blockIdx.x + 2] = bad;
+        out3[0] = mx;
+        out3[1] = s2;
+        out3[2] = bad;
     }
 }
 
@@ -91,12 +93,18 @@ __device__ __forceinline__ void norm_add(double rv, double& mx, double& s2, doub
     s2 = s2 + rv * rv;
 }
 
+__device__ __forceinline__ double mean8(const double* __restrict__ x, const FBox& B, int i, int j, int k) {
+    const long long c = fidx(B, i, j, k), sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
+    return (((x[c] + x[c + 1]) + (x[c + sy] + x[c + sy + 1])) +
+            ((x[c + sz] + x[c + sz + 1]) + (x[c + sz + sy] + x[c + sz + sy + 1]))) * 0.125;
+}
+
 // Coarse-fine ghosts.  One entry per ghost cell: x = box | d << 24 | side << 26
 // (the ghost lies beyond face (d, side) of its box), y, z, w = its fine index.
-__global__ void __launch_bounds__(kCB) k_cf_ghost(const int4* __restrict__ list, long long n, CGeo g,
+__global__ void __launch_bounds__(kCB) k_cf_ghost(const int4* __restrict__ list, int n, CGeo g,
                                                   const double* __restrict__ Uc, const FBox* __restrict__ fu,
                                                   double* __restrict__ uf) {
-    const long long q = (long long)blockIdx.x * kCB + threadIdx.x;
+    const int q = blockIdx.x * kCB + threadIdx.x;
     if (q >= n) return;
     const int4 r = list[q];
     const int b = r.x & 0xffffff, d = (r.x >> 24) & 3, side = (r.x >> 26) & 1;
@@ -109,12 +117,10 @@ __global__ void __launch_bounds__(kCB) k_cf_ghost(const int4* __restrict__ list,
     const int C[3] = {gx[0] >> 1, gx[1] >> 1, gx[2] >> 1};
     const int ta = d == 2 ? 0 : d + 1, tb = d == 0 ? 2 : d - 1;
     const double sa = (gx[ta] & 1) ? 1.0 : -1.0, sb = (gx[tb] & 1) ? 1.0 : -1.0;
-    auto U = [&](int p, int s) {
-        int x[3] = {C[0], C[1], C[2]};
-        x[ta] += p;
-        x[tb] += s;
-        return Uc[fidx(g.cb, x[0], x[1], x[2])];
-    };
+    const long long c0 = fidx(g.cb, C[0], C[1], C[2]);
+    const long long st[3] = {1, g.cb.G[0], (long long)g.cb.G[0] * g.cb.G[1]};
+    const long long da_ = st[ta], db_ = st[tb];
+    auto U = [&](int p, int s) { return Uc[c0 + p * da_ + s * db_]; };
     const double UC = U(0, 0);
     const double Up0 = U(1, 0), Um0 = U(-1, 0), U0p = U(0, 1), U0m = U(0, -1);
     const double da = (Up0 - Um0) * 0.125 * sa, db = (U0p - U0m) * 0.125 * sb;
@@ -126,23 +132,24 @@ __global__ void __launch_bounds__(kCB) k_cf_ghost(const int4* __restrict__ list,
     uf[fidx(B, gx[0], gx[1], gx[2])] = ((8.0 / 15.0) * Ut + (2.0 / 3.0) * u1) - (1.0 / 5.0) * u2;
 }
 
+// Fine-box kernels: grid (plane blocks, plane groups of kKZ, box); a thread
+// takes one (i, j) of its box's planes (or half-row position, for the
+// sweeps) and walks kKZ planes.
+
 // One colour of red-black Gauss-Seidel on the fine boxes (ghosts current):
 // u = (sum of the 6 neighbours - h1^2 f) / 6 at the cells of that colour.
-// bpb blocks per box; thread t walks half-row positions of its box.
 __global__ void __launch_bounds__(kCB) k_fine_gs(CGeo g, const FBox* __restrict__ fu, const FBox* __restrict__ ff,
-                                                 double* __restrict__ u, const double* __restrict__ f, int colour,
-                                                 int bpb) {
-    const int b = blockIdx.x / bpb, lb = blockIdx.x % bpb;
-    const FBox B = fu[b], F = ff[b];
-    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1, nz = B.hi[2] - B.lo[2] + 1;
+                                                 double* __restrict__ u, const double* __restrict__ f, int colour) {
+    const FBox B = fu[blockIdx.z], F = ff[blockIdx.z];
+    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1;
     const int nxh = (nx + 1) >> 1;
-    const long long total = (long long)nxh * ny * nz;
+    const int t = blockIdx.x * kCB + threadIdx.x;
+    if (t >= nxh * ny) return;
+    const int tx = t % nxh, j = B.lo[1] + t / nxh;
+    const int k0 = B.lo[2] + blockIdx.y * kKZ, k1 = min(k0 + kKZ - 1, B.hi[2]);
     const long long sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
     const double h2 = g.h1 * g.h1;
-    for (long long t = (long long)lb * kCB + threadIdx.x; t < total; t += (long long)bpb * kCB) {
-        const int tx = (int)(t % nxh);
-        const long long rest = t / nxh;
-        const int j = B.lo[1] + (int)(rest % ny), k = B.lo[2] + (int)(rest / ny);
+    for (int k = k0; k <= k1; ++k) {
         const int i = B.lo[0] + 2 * tx + ((B.lo[0] + j + k + colour) & 1);
         if (i > B.hi[0]) continue;
         const long long c = fidx(B, i, j, k);
@@ -151,158 +158,54 @@ __global__ void __launch_bounds__(kCB) k_fine_gs(CGeo g, const FBox* __restrict_
     }
 }
 
-// Fine residual r = f - L u on the valid cells (or r = f with fonly), with
-// per-block norms (max, sum of squares, non-finite count).
+// Fine residual r = f - L u on the valid cells (or the norms of f only),
+// with per-block norms (max, sum of squares, non-finite count).
 __global__ void __launch_bounds__(kCB) k_fine_resid(CGeo g, const FBox* __restrict__ fu, const FBox* __restrict__ ff,
                                                     const FBox* __restrict__ fr, const double* __restrict__ u,
-                                                    const double* __restrict__ f, double* __restrict__ r, int bpb,
-                                                    int fonly, double* __restrict__ partials) {
-    const int b = blockIdx.x / bpb, lb = blockIdx.x % bpb;
-    const FBox B = fu[b], F = ff[b], R = fr[b];
-    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1, nz = B.hi[2] - B.lo[2] + 1;
-    const long long total = (long long)nx * ny * nz;
-    const long long sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
-    const double ih2 = 1.0 / (g.h1 * g.h1);
+                                                    const double* __restrict__ f, double* __restrict__ r, int fonly,
+                                                    double* __restrict__ partials) {
+    const FBox B = fu[blockIdx.z], F = ff[blockIdx.z], R = fr[blockIdx.z];
+    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1;
+    const int t = blockIdx.x * kCB + threadIdx.x;
     double mx = 0.0, s2 = 0.0, bad = 0.0;
-    for (long long t = (long long)lb * kCB + threadIdx.x; t < total; t += (long long)bpb * kCB) {
-        const int i = B.lo[0] + (int)(t % nx);
-        const long long rest = t / nx;
-        const int j = B.lo[1] + (int)(rest % ny), k = B.lo[2] + (int)(rest / ny);
-        double rv = f[fidx(F, i, j, k)];
-        if (!fonly) {
-            const long long c = fidx(B, i, j, k);
-            const double su = ((u[c - 1] + u[c + 1]) + (u[c - sy] + u[c + sy])) + (u[c - sz] + u[c + sz]);
-            rv = rv - (su - 6.0 * u[c]) * ih2;
-            r[fidx(R, i, j, k)] = rv;
+    if (t < nx * ny) {
+        const int i = B.lo[0] + t % nx, j = B.lo[1] + t / nx;
+        const int k0 = B.lo[2] + blockIdx.y * kKZ, k1 = min(k0 + kKZ - 1, B.hi[2]);
+        const long long sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
+        const double ih2 = 1.0 / (g.h1 * g.h1);
+        for (int k = k0; k <= k1; ++k) {
+            double rv = f[fidx(F, i, j, k)];
+            if (!fonly) {
+                const long long c = fidx(B, i, j, k);
+                const double su = ((u[c - 1] + u[c + 1]) + (u[c - sy] + u[c + sy])) + (u[c - sz] + u[c + sz]);
+                rv = rv - (su - 6.0 * u[c]) * ih2;
+                r[fidx(R, i, j, k)] = rv;
+            }
+            norm_add(rv, mx, s2, bad);
         }
-        norm_add(rv, mx, s2, bad);
     }
-    block_norms(mx, s2, bad, partials);
-}
-
-__device__ __forceinline__ double mean8(const double* __restrict__ x, const FBox& B, int i, int j, int k) {
-    const long long c = fidx(B, i, j, k), sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
-    return (((x[c] + x[c + 1]) + (x[c + sy] + x[c + sy + 1])) +
-            ((x[c + sz] + x[c + sz + 1]) + (x[c + sz + sy] + x[c + sz + sy + 1]))) * 0.125;
-}
-
-// Composite residual on the coarse level: uncovered cells f - Lc u (norms
-// taken there), covered cells the mean of the fine residuals below them
-// (fonly: the norms of f at the uncovered cells, Rc untouched).  Fine ghosts
-// of the current state must be in place (the flux-matched faces read them).
-__global__ void __launch_bounds__(kCB) k_coarse_resid(CGeo g, const int* __restrict__ cmap,
-                                                      const double* __restrict__ Uc, const double* __restrict__ Fc,
-                                                      double* __restrict__ Rc, const FBox* __restrict__ fu,
-                                                      const double* __restrict__ uf, const FBox* __restrict__ fr,
-                                                      const double* __restrict__ rf, int fonly,
-                                                      double* __restrict__ partials) {
-    const long long total = (long long)g.n[0] * g.n[1] * g.n[2];
-    double mx = 0.0, s2 = 0.0, bad = 0.0;
-    for (long long q = (long long)blockIdx.x * kCB + threadIdx.x; q < total; q += (long long)gridDim.x * kCB) {
-        const int I = g.dlo[0] + (int)(q % g.n[0]);
-        const long long rest = q / g.n[0];
-        const int J = g.dlo[1] + (int)(rest % g.n[1]), K = g.dlo[2] + (int)(rest / g.n[1]);
-        const int code = cmap[q];
-        const long long c = fidx(g.cb, I, J, K);
-        if (code >= 0) {
-            if (!fonly) Rc[c] = mean8(rf, fr[code], 2 * I, 2 * J, 2 * K);
-            continue;
-        }
-        double rv = Fc[c];
-        if (!fonly) {
-            const double UI = Uc[c];
-            const int X[3] = {I, J, K};
-            double gr[6];
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-#pragma unroll
-                for (int side = 0; side < 2; ++side) {
-                    int nb[3] = {X[0], X[1], X[2]};
-                    nb[d] += side ? 1 : -1;
-                    double v;
-                    if (nb[d] < g.dlo[d] || nb[d] >= g.dlo[d] + g.n[d]) {
-                        if (!g.per[d]) {
-                            gr[2 * d + side] = (-UI - UI) / g.h0;
-                            continue;
-                        }
-                        nb[d] = nb[d] < g.dlo[d] ? nb[d] + g.n[d] : nb[d] - g.n[d];
-                    }
-                    const int nc = cmap[cq(g, nb[0], nb[1], nb[2])];
-                    if (nc < 0) {
-                        v = (Uc[fidx(g.cb, nb[0], nb[1], nb[2])] - UI) / g.h0;
-                    } else {
-                        // the 4 fine cells of the covered neighbour against the face
-                        const FBox B = fu[nc];
-                        const int ta = d == 2 ? 0 : d + 1, tb = d == 0 ? 2 : d - 1;
-                        double a[2][2];
-#pragma unroll
-                        for (int s = 0; s < 2; ++s)
-#pragma unroll
-                            for (int p = 0; p < 2; ++p) {
-                                int fi[3];
-                                fi[d] = 2 * nb[d] + (side ? 0 : 1);
-                                fi[ta] = 2 * nb[ta] + p;
-                                fi[tb] = 2 * nb[tb] + s;
-                                int gc[3] = {fi[0], fi[1], fi[2]};
-                                gc[d] += side ? -1 : 1;
-                                a[s][p] = (uf[fidx(B, fi[0], fi[1], fi[2])] - uf[fidx(B, gc[0], gc[1], gc[2])]) / g.h1;
-                            }
-                        v = ((a[0][0] + a[0][1]) + (a[1][0] + a[1][1])) * 0.25;
-                    }
-                    gr[2 * d + side] = v;
-                }
-            rv = rv - (((gr[0] + gr[1]) + (gr[2] + gr[3])) + (gr[4] + gr[5])) / g.h0;
-            Rc[c] = rv;
-        }
-        norm_add(rv, mx, s2, bad);
-    }
-    block_norms(mx, s2, bad, partials);
-}
-
-// Uc += Ec at the uncovered coarse cells.
-__global__ void __launch_bounds__(kCB) k_coarse_update(CGeo g, const int* __restrict__ cmap, double* __restrict__ Uc,
-                                                       const double* __restrict__ Ec) {
-    const long long total = (long long)g.n[0] * g.n[1] * g.n[2];
-    for (long long q = (long long)blockIdx.x * kCB + threadIdx.x; q < total; q += (long long)gridDim.x * kCB) {
-        if (cmap[q] >= 0) continue;
-        const int I = g.dlo[0] + (int)(q % g.n[0]);
-        const long long rest = q / g.n[0];
-        const long long c = fidx(g.cb, I, g.dlo[1] + (int)(rest % g.n[1]), g.dlo[2] + (int)(rest / g.n[1]));
-        Uc[c] = Uc[c] + Ec[c];
-    }
-}
-
-// Covered coarse cells := the mean of their 8 children.
-__global__ void __launch_bounds__(kCB) k_coarse_sync(CGeo g, const int* __restrict__ cmap, double* __restrict__ Uc,
-                                                     const FBox* __restrict__ fu, const double* __restrict__ uf) {
-    const long long total = (long long)g.n[0] * g.n[1] * g.n[2];
-    for (long long q = (long long)blockIdx.x * kCB + threadIdx.x; q < total; q += (long long)gridDim.x * kCB) {
-        const int code = cmap[q];
-        if (code < 0) continue;
-        const int I = g.dlo[0] + (int)(q % g.n[0]);
-        const long long rest = q / g.n[0];
-        const int J = g.dlo[1] + (int)(rest % g.n[1]), K = g.dlo[2] + (int)(rest / g.n[1]);
-        Uc[fidx(g.cb, I, J, K)] = mean8(uf, fu[code], 2 * I, 2 * J, 2 * K);
-    }
+    const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    block_norms(mx, s2, bad, partials + 3 * (long long)blk);
 }
 
 // Fine cells += trilinear interpolation of the coarse correction Ec.
 __global__ void __launch_bounds__(kCB) k_fine_prolong(CGeo g, const FBox* __restrict__ fu, double* __restrict__ u,
-                                                      const double* __restrict__ Ec, int bpb) {
-    const int b = blockIdx.x / bpb, lb = blockIdx.x % bpb;
-    const FBox B = fu[b];
-    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1, nz = B.hi[2] - B.lo[2] + 1;
-    const long long total = (long long)nx * ny * nz;
-    for (long long t = (long long)lb * kCB + threadIdx.x; t < total; t += (long long)bpb * kCB) {
-        const int i = B.lo[0] + (int)(t % nx);
-        const long long rest = t / nx;
-        const int j = B.lo[1] + (int)(rest % ny), k = B.lo[2] + (int)(rest / ny);
-        const int I = i >> 1, J = j >> 1, K = k >> 1;
-        const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
-        auto E = [&](int a, int bb, int cc) { return Ec[fidx(g.cb, a, bb, cc)]; };
-        const double c000 = E(I, J, K), c100 = E(I + si, J, K), c010 = E(I, J + sj, K), c001 = E(I, J, K + sk);
-        const double c110 = E(I + si, J + sj, K), c101 = E(I + si, J, K + sk), c011 = E(I, J + sj, K + sk);
-        const double c111 = E(I + si, J + sj, K + sk);
+                                                      const double* __restrict__ Ec) {
+    const FBox B = fu[blockIdx.z];
+    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1;
+    const int t = blockIdx.x * kCB + threadIdx.x;
+    if (t >= nx * ny) return;
+    const int i = B.lo[0] + t % nx, j = B.lo[1] + t / nx;
+    const int k0 = B.lo[2] + blockIdx.y * kKZ, k1 = min(k0 + kKZ - 1, B.hi[2]);
+    const int I = i >> 1, J = j >> 1;
+    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1;
+    const long long sy = g.cb.G[0], sz = (long long)g.cb.G[0] * g.cb.G[1];
+    for (int k = k0; k <= k1; ++k) {
+        const int K = k >> 1, sk = (k & 1) ? 1 : -1;
+        const long long e = fidx(g.cb, I, J, K), ex = si, ey = sj * sy, ez = sk * sz;
+        const double c000 = Ec[e], c100 = Ec[e + ex], c010 = Ec[e + ey], c001 = Ec[e + ez];
+        const double c110 = Ec[e + ex + ey], c101 = Ec[e + ex + ez], c011 = Ec[e + ey + ez];
+        const double c111 = Ec[e + ex + ey + ez];
         const double v = (((27.0 * c000 + 9.0 * ((c100 + c010) + c001)) + 3.0 * ((c110 + c101) + c011)) + c111) *
                          (1.0 / 64.0);
         const long long c = fidx(B, i, j, k);
@@ -311,26 +214,140 @@ __global__ void __launch_bounds__(kCB) k_fine_prolong(CGeo g, const FBox* __rest
 }
 
 // Component 0 of every fine box, valid and ghost cells, := 0.
-__global__ void __launch_bounds__(kCB) k_fine_zero(const FBox* __restrict__ fu, double* __restrict__ u, int bpb) {
-    const int b = blockIdx.x / bpb, lb = blockIdx.x % bpb;
-    const FBox B = fu[b];
-    const long long total = (long long)B.G[0] * B.G[1] * B.G[2];
-    for (long long t = (long long)lb * kCB + threadIdx.x; t < total; t += (long long)bpb * kCB) u[B.base + t] = 0.0;
+__global__ void __launch_bounds__(kCB) k_fine_zero(const FBox* __restrict__ fu, double* __restrict__ u) {
+    const FBox B = fu[blockIdx.z];
+    const int P = B.G[0] * B.G[1];
+    const int t = blockIdx.x * kCB + threadIdx.x;
+    if (t >= P) return;
+    for (int k = blockIdx.y * kKZ; k < min(blockIdx.y * kKZ + kKZ, B.G[2]); ++k) u[B.base + (long long)k * P + t] = 0.0;
+}
+
+// Coarse kernels: grid (plane blocks, plane groups of kKZ) over the domain.
+
+// Composite residual on the coarse level: uncovered cells f - Lc u (norms
+// taken there), covered cells the mean of the fine residuals below them
+// (fonly: the norms of f at the uncovered cells, Rc untouched).  The fine
+// ghosts of the current state must be in place (the flux-matched faces
+// read them).
+__global__ void __launch_bounds__(kCB) k_coarse_resid(CGeo g, const int* __restrict__ cmap,
+                                                      const double* __restrict__ Uc, const double* __restrict__ Fc,
+                                                      double* __restrict__ Rc, const FBox* __restrict__ fu,
+                                                      const double* __restrict__ uf, const FBox* __restrict__ fr,
+                                                      const double* __restrict__ rf, int fonly,
+                                                      double* __restrict__ partials) {
+    const int t = blockIdx.x * kCB + threadIdx.x;
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    if (t < g.n[0] * g.n[1]) {
+        const int I = g.dlo[0] + t % g.n[0], J = g.dlo[1] + t / g.n[0];
+        const int K0 = g.dlo[2] + blockIdx.y * kKZ, K1 = min(K0 + kKZ - 1, g.dlo[2] + g.n[2] - 1);
+        const long long st[3] = {1, g.cb.G[0], (long long)g.cb.G[0] * g.cb.G[1]};
+        const int mst[3] = {1, g.n[0], g.n[0] * g.n[1]};
+        for (int K = K0; K <= K1; ++K) {
+            const int q = cq(g, I, J, K);
+            const int code = cmap[q];
+            const long long c = fidx(g.cb, I, J, K);
+            if (code >= 0) {
+                if (!fonly) Rc[c] = mean8(rf, fr[code], 2 * I, 2 * J, 2 * K);
+                continue;
+            }
+            double rv = Fc[c];
+            if (!fonly) {
+                const int mask = -1 - code;
+                const double UI = Uc[c];
+                const int X[3] = {I, J, K};
+                double gr[6];
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int side = 0; side < 2; ++side) {
+                        const int nbd = X[d] + (side ? 1 : -1);
+                        double v;
+                        if ((mask >> (2 * d + side)) & 1) {
+                            // the 4 fine cells of the covered neighbour against the face
+                            int nb[3] = {X[0], X[1], X[2]};
+                            nb[d] = nbd;
+                            const FBox B = fu[cmap[q + (side ? mst[d] : -mst[d])]];
+                            const int ta = d == 2 ? 0 : d + 1, tb = d == 0 ? 2 : d - 1;
+                            double a[2][2];
+#pragma unroll
+                            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                                for (int p = 0; p < 2; ++p) {
+                                    int fi[3];
+                                    fi[d] = 2 * nb[d] + (side ? 0 : 1);
+                                    fi[ta] = 2 * nb[ta] + p;
+                                    fi[tb] = 2 * nb[tb] + s;
+                                    const long long o = fidx(B, fi[0], fi[1], fi[2]);
+                                    const long long gs = side ? -1 : 1;
+                                    const long long step = d == 0 ? gs : (d == 1 ? gs * B.G[0] : gs * B.G[0] * B.G[1]);
+                                    a[s][p] = (uf[o] - uf[o + step]) / g.h1;
+                                }
+                            v = ((a[0][0] + a[0][1]) + (a[1][0] + a[1][1])) * 0.25;
+                        } else if (nbd < g.dlo[d] || nbd >= g.dlo[d] + g.n[d]) {
+                            if (!g.per[d]) {
+                                v = (-UI - UI) / g.h0;
+                            } else {
+                                const long long w = (long long)(side ? -(g.n[d] - 1) : (g.n[d] - 1)) * st[d];
+                                v = (Uc[c + w] - UI) / g.h0;
+                            }
+                        } else {
+                            v = (Uc[c + (side ? st[d] : -st[d])] - UI) / g.h0;
+                        }
+                        gr[2 * d + side] = v;
+                    }
+                rv = rv - (((gr[0] + gr[1]) + (gr[2] + gr[3])) + (gr[4] + gr[5])) / g.h0;
+                Rc[c] = rv;
+            }
+            norm_add(rv, mx, s2, bad);
+        }
+    }
+    block_norms(mx, s2, bad, partials + 3 * (long long)(blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// Uc += Ec at the uncovered coarse cells.
+__global__ void __launch_bounds__(kCB) k_coarse_update(CGeo g, const int* __restrict__ cmap, double* __restrict__ Uc,
+                                                       const double* __restrict__ Ec) {
+    const int t = blockIdx.x * kCB + threadIdx.x;
+    if (t >= g.n[0] * g.n[1]) return;
+    const int I = g.dlo[0] + t % g.n[0], J = g.dlo[1] + t / g.n[0];
+    const int K0 = g.dlo[2] + blockIdx.y * kKZ, K1 = min(K0 + kKZ - 1, g.dlo[2] + g.n[2] - 1);
+    for (int K = K0; K <= K1; ++K) {
+        if (cmap[cq(g, I, J, K)] >= 0) continue;
+        const long long c = fidx(g.cb, I, J, K);
+        Uc[c] = Uc[c] + Ec[c];
+    }
+}
+
+// Covered coarse cells := the mean of their 8 children; grid (plane blocks,
+// plane groups, fine box) over each fine box's coarse cells.
+__global__ void __launch_bounds__(kCB) k_coarse_sync(CGeo g, double* __restrict__ Uc, const FBox* __restrict__ fu,
+                                                     const double* __restrict__ uf) {
+    const FBox B = fu[blockIdx.z];
+    const int cx = (B.hi[0] - B.lo[0] + 1) >> 1, cy = (B.hi[1] - B.lo[1] + 1) >> 1, cz = (B.hi[2] - B.lo[2] + 1) >> 1;
+    const int t = blockIdx.x * kCB + threadIdx.x;
+    if (t >= cx * cy) return;
+    const int I = (B.lo[0] >> 1) + t % cx, J = (B.lo[1] >> 1) + t / cx;
+    const int K0 = (B.lo[2] >> 1) + blockIdx.y * kKZ, K1 = min(K0 + kKZ - 1, (B.lo[2] >> 1) + cz - 1);
+    for (int K = K0; K <= K1; ++K) Uc[fidx(g.cb, I, J, K)] = mean8(uf, B, 2 * I, 2 * J, 2 * K);
 }
 
 // ------------------------------------------------------------------ host
+static unsigned cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
 struct Comp {
     bxmg_ctx ctx = nullptr;
     uint64_t cba_id = 0, fba_id = 0;
     double h0 = 0.0;
-    bxmg_boxarray one = nullptr;                              // one box over the coarse domain
+    bxmg_boxarray one = nullptr;                                           // one box over the coarse domain
     bxmg_multifab Uc = nullptr, Fc = nullptr, Rc = nullptr, Ec = nullptr;  // over `one`, 1 ghost
-    bxmg_multifab Rf = nullptr;                               // fine residual (caller's fine boxes)
+    bxmg_multifab Rf = nullptr;                                            // fine residual (caller's fine boxes)
     CGeo geo{};
     DevBuf<int> cmap;
     DevBuf<int4> ghosts;
-    long long nghosts = 0;
-    int nfine = 0, bpb = 1, bpb_gs = 1, nbc = 1;
+    int nghosts = 0;
+    int nfine = 0;
+    dim3 g_fine, g_fine_gs, g_sync, g_coarse;  // launch grids
+    int nparts_fine = 0, nparts = 0;
     DevBuf<double> part, fn;
     double* h_norm = nullptr;  // pinned: the norms read back
     ~Comp() {
@@ -349,25 +366,27 @@ struct Comp {
     }
 };
 
-static unsigned blocks_for(long long n) { return (unsigned)((n + kCB - 1) / kCB); }
-
 // Checks the fine layout against the coarse domain: the fine domain is the
 // coarse one refined by 2 with the same boundaries, every fine box is a union
 // of whole coarse cells and lies 2 coarse cells (4 fine) inside every domain
-// face.  Returns "" or the reason.
+// face; index arithmetic stays in 32 bits.  Returns "" or the reason.
 static std::string layout_error(const bxmg_ba_s* cba, const bxmg_ba_s* fba) {
     for (int d = 0; d < 3; ++d) {
         if (fba->dom.lo[d] != 2 * cba->dom.lo[d] || fba->dom.hi[d] != 2 * cba->dom.hi[d] + 1)
             return "the fine domain must be the coarse domain refined by 2";
         if (fba->per[d] != cba->per[d]) return "the fine and coarse boundaries differ";
     }
+    const Box& D = cba->dom;
+    if ((long long)(D.n(0) + 2) * (D.n(1) + 2) * (D.n(2) + 2) >= (1LL << 31)) return "coarse domain too large";
     if (fba->boxes.size() >= (1u << 24)) return "too many fine boxes";
-    for (const Box& B : fba->boxes)
+    for (const Box& B : fba->boxes) {
         for (int d = 0; d < 3; ++d) {
             if ((B.lo[d] & 1) || !(B.hi[d] & 1)) return "fine boxes must be unions of whole coarse cells";
             if (B.lo[d] < fba->dom.lo[d] + 4 || B.hi[d] > fba->dom.hi[d] - 4)
                 return "fine boxes must lie 2 coarse cells inside the domain";
         }
+        if ((long long)(B.n(0) + 8) * (B.n(1) + 8) * (B.n(2) + 8) >= (1LL << 31)) return "fine box too large";
+    }
     return "";
 }
 
@@ -410,7 +429,7 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
     }
     g.h0 = h0;
     g.h1 = h0 * 0.5;
-    // coverage map
+    // coverage map: covering fine box, or -1 - (mask of covered face neighbours)
     const long long nc = D.cells();
     std::vector<int> cmap((size_t)nc, -1);
     auto cidx = [&](int I, int J, int K) {
@@ -418,14 +437,32 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
     };
     const auto& fb = fba->boxes;
     c->nfine = (int)fb.size();
-    long long maxcells = 1;
+    int maxP = 1, maxPh = 1, maxnz = 1, maxPc = 1, maxnzc = 1;
     for (size_t b = 0; b < fb.size(); ++b) {
         const Box& B = fb[b];
-        maxcells = std::max(maxcells, B.cells());
-        for (int K = B.lo[2] / 2; K <= B.hi[2] / 2; ++K)
-            for (int J = B.lo[1] / 2; J <= B.hi[1] / 2; ++J)
-                for (int I = B.lo[0] / 2; I <= B.hi[0] / 2; ++I) cmap[cidx(I, J, K)] = (int)b;
+        maxP = std::max(maxP, B.n(0) * B.n(1));
+        maxPh = std::max(maxPh, ((B.n(0) + 1) / 2) * B.n(1));
+        maxnz = std::max(maxnz, B.n(2));
+        maxPc = std::max(maxPc, (B.n(0) / 2) * (B.n(1) / 2));
+        maxnzc = std::max(maxnzc, B.n(2) / 2);
+        for (int K = B.lo[2] >> 1; K <= B.hi[2] >> 1; ++K)
+            for (int J = B.lo[1] >> 1; J <= B.hi[1] >> 1; ++J)
+                for (int I = B.lo[0] >> 1; I <= B.hi[0] >> 1; ++I) cmap[cidx(I, J, K)] = (int)b;
     }
+    for (const Box& B : fb)
+        for (int K = B.lo[2] >> 1; K <= B.hi[2] >> 1; ++K)
+            for (int J = B.lo[1] >> 1; J <= B.hi[1] >> 1; ++J)
+                for (int I = B.lo[0] >> 1; I <= B.hi[0] >> 1; ++I)
+                    for (int d = 0; d < 3; ++d)
+                        for (int side = 0; side < 2; ++side) {
+                            // the neighbour N across (d, side) of this covered cell sees it across (d, 1 - side)
+                            int x[3] = {I, J, K};
+                            x[d] += side ? 1 : -1;
+                            int& m = cmap[cidx(x[0], x[1], x[2])];
+                            if (m >= 0) continue;
+                            const int mask = (-1 - m) | (1 << (2 * d + (1 - side)));
+                            m = -1 - mask;
+                        }
     // coarse-fine ghosts: face ghosts of each fine box whose coarse cell no
     // fine box covers (the others are fine cells, filled by FillBoundary)
     std::vector<int4> gl;
@@ -445,16 +482,19 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
                     }
             }
     }
-    c->nghosts = (long long)gl.size();
+    if (gl.size() >= (size_t)(1u << 31) - kCB) throw std::runtime_error("too many coarse-fine ghost cells");
+    c->nghosts = (int)gl.size();
+    const unsigned nf = (unsigned)std::max(1, c->nfine);
+    c->g_fine = dim3(cdiv(maxP, kCB), cdiv(maxnz, kKZ), nf);
+    c->g_fine_gs = dim3(cdiv(maxPh, kCB), cdiv(maxnz, kKZ), nf);
+    c->g_sync = dim3(cdiv(maxPc, kCB), cdiv(maxnzc, kKZ), nf);
+    c->g_coarse = dim3(cdiv((long long)g.n[0] * g.n[1], kCB), cdiv(g.n[2], kKZ), 1);
+    c->nparts_fine = c->nfine ? (int)(c->g_fine.x * c->g_fine.y * c->g_fine.z) : 0;
+    c->nparts = c->nparts_fine + (int)(c->g_coarse.x * c->g_coarse.y);
     const hipStream_t s = ctx->stream;
     c->cmap.upload_async(cmap, s);
     c->ghosts.upload_async(gl, s);
-    c->bpb = (int)std::max(1LL, (maxcells + (long long)kCB * kCellsPerThread - 1) / ((long long)kCB * kCellsPerThread));
-    c->bpb_gs = (int)std::max(1LL, (maxcells / 2 + (long long)kCB * kCellsPerThread - 1) / ((long long)kCB * kCellsPerThread));
-    c->nbc = (int)std::min<long long>(kMaxCoarseBlocks, std::max(1LL, (nc + (long long)kCB * kCellsPerThread - 1) /
-                                                                          ((long long)kCB * kCellsPerThread)));
-    std::vector<double> zero((size_t)3 * ((size_t)c->nfine * c->bpb + c->nbc), 0.0);
-    c->part.upload_async(zero, s);
+    c->part.upload_async(std::vector<double>((size_t)3 * c->nparts, 0.0), s);
     c->fn.upload_async(std::vector<double>(3, 0.0), s);
     HIPCHK(hipHostMalloc((void**)&c->h_norm, 4 * sizeof(double)));
     return c;
@@ -523,21 +563,27 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
         const FBox* fF = rhs_f->d_fboxes.p;
         const FBox* fR = c.Rf->d_fboxes.p;
         const unsigned nfb = (unsigned)c.nfine;
-        double* const part_c = c.part.p + 3 * (size_t)c.nfine * c.bpb;
-        const int nparts = c.nfine * c.bpb + c.nbc;
+        double* const part_c = c.part.p + 3 * (size_t)c.nparts_fine;
+        // k_fine_zero covers the grown boxes of phi_f
+        int maxPG = 1, maxGz = 1;
+        for (const FBox& B : phi_f->fboxes) {
+            maxPG = std::max(maxPG, B.G[0] * B.G[1]);
+            maxGz = std::max(maxGz, B.G[2]);
+        }
+        const dim3 g_zero(comp::cdiv(maxPG, comp::kCB), comp::cdiv(maxGz, comp::kKZ), std::max(1u, nfb));
         auto chk = [](bxmg_status st) {
             if (st != BXMG_OK) throw std::runtime_error(bxmg_last_error());
         };
         // load: coarse rhs into the one-box field, zero start on both levels
         chk(bxmg_parallel_copy(c.Fc, 0, rhs_c, 0, 1, 0, s));
         HIPCHK(hipMemsetAsync(Uc, 0, c.Uc->bytes, s));
-        if (nfb) hipLaunchKernelGGL(comp::k_fine_zero, dim3(nfb * c.bpb), dim3(comp::kCB), 0, s, fu, uf, c.bpb);
+        if (nfb) hipLaunchKernelGGL(comp::k_fine_zero, g_zero, dim3(comp::kCB), 0, s, fu, uf);
         HIPCHK(hipGetLastError());
         auto fill_fine = [&]() {
             if (!nfb) return;
             chk(bxmg_fill_boundary(phi_f, 0, 1, 1, s));
             if (c.nghosts)
-                hipLaunchKernelGGL(comp::k_cf_ghost, dim3(comp::blocks_for(c.nghosts)), dim3(comp::kCB), 0, s,
+                hipLaunchKernelGGL(comp::k_cf_ghost, dim3(comp::cdiv(c.nghosts, comp::kCB)), dim3(comp::kCB), 0, s,
                                    c.ghosts.p, c.nghosts, g, (const double*)Uc, fu, uf);
             HIPCHK(hipGetLastError());
         };
@@ -545,13 +591,13 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
         auto residual = [&](bool fonly, double out[3]) {
             if (!fonly) fill_fine();
             if (nfb)
-                hipLaunchKernelGGL(comp::k_fine_resid, dim3(nfb * c.bpb), dim3(comp::kCB), 0, s, g, fu, fF, fR,
-                                   (const double*)uf, ff, rf, c.bpb, (int)fonly, c.part.p);
-            hipLaunchKernelGGL(comp::k_coarse_resid, dim3(c.nbc), dim3(comp::kCB), 0, s, g, (const int*)c.cmap.p,
+                hipLaunchKernelGGL(comp::k_fine_resid, c.g_fine, dim3(comp::kCB), 0, s, g, fu, fF, fR,
+                                   (const double*)uf, ff, rf, (int)fonly, c.part.p);
+            hipLaunchKernelGGL(comp::k_coarse_resid, c.g_coarse, dim3(comp::kCB), 0, s, g, (const int*)c.cmap.p,
                                (const double*)Uc, (const double*)Fc, Rc, fu, (const double*)uf, fR,
                                (const double*)rf, (int)fonly, part_c);
             HIPCHK(hipGetLastError());
-            HIPCHK(launch_norm_final(s, c.part.p, nparts, c.fn.p));
+            HIPCHK(launch_norm_final(s, c.part.p, c.nparts, c.fn.p));
             HIPCHK(hipMemcpyAsync(c.h_norm, c.fn.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             out[0] = c.h_norm[2] > 0.0 ? (double)NAN : c.h_norm[0];
@@ -563,8 +609,8 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
                 for (int col = 0; col < 2; ++col) {
                     fill_fine();
                     if (nfb)
-                        hipLaunchKernelGGL(comp::k_fine_gs, dim3(nfb * c.bpb_gs), dim3(comp::kCB), 0, s, g, fu, fF, uf,
-                                           ff, col, c.bpb_gs);
+                        hipLaunchKernelGGL(comp::k_fine_gs, c.g_fine_gs, dim3(comp::kCB), 0, s, g, fu, fF, uf, ff,
+                                           col);
                     HIPCHK(hipGetLastError());
                 }
         };
@@ -581,15 +627,15 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
             const bxmg_status st = bxmg_mlmg_solve(ctx, &Pc, c.Ec, c.Rc, nullptr, &ci);
             if (st != BXMG_OK) throw std::runtime_error(bxmg_last_error());
             info->levels = ci.levels + 1;
-            hipLaunchKernelGGL(comp::k_coarse_update, dim3(c.nbc), dim3(comp::kCB), 0, s, g, (const int*)c.cmap.p, Uc,
+            hipLaunchKernelGGL(comp::k_coarse_update, c.g_coarse, dim3(comp::kCB), 0, s, g, (const int*)c.cmap.p, Uc,
                                (const double*)Ec);
             if (nfb)
-                hipLaunchKernelGGL(comp::k_fine_prolong, dim3(nfb * c.bpb), dim3(comp::kCB), 0, s, g, fu, uf,
-                                   (const double*)Ec, c.bpb);
+                hipLaunchKernelGGL(comp::k_fine_prolong, c.g_fine, dim3(comp::kCB), 0, s, g, fu, uf,
+                                   (const double*)Ec);
             HIPCHK(hipGetLastError());
             sweeps(P.nu2);
-            hipLaunchKernelGGL(comp::k_coarse_sync, dim3(c.nbc), dim3(comp::kCB), 0, s, g, (const int*)c.cmap.p, Uc, fu,
-                               (const double*)uf);
+            if (nfb)
+                hipLaunchKernelGGL(comp::k_coarse_sync, c.g_sync, dim3(comp::kCB), 0, s, g, Uc, fu, (const double*)uf);
             HIPCHK(hipGetLastError());
         };
         double fz[3];

@@ -842,8 +842,14 @@ void bxmg_multifab_release(bxmg_multifab mf) {
     const hipStream_t s = mf->ctx->stream;
     if (mf->owned) (void)hipFreeAsync(mf->data, s);
     mf->d_fboxes.release_async(s);
-    for (auto& kv : mf->plans) kv.second->tags.release_async(s);
-    for (auto& kv : mf->pcopy_plans) kv.second->tags.release_async(s);
+    for (auto& kv : mf->plans) {
+        kv.second->tags.release_async(s);
+        kv.second->hints.release_async(s);
+    }
+    for (auto& kv : mf->pcopy_plans) {
+        kv.second->tags.release_async(s);
+        kv.second->hints.release_async(s);
+    }
     ba_release(mf->ba);
     delete mf;
 }
@@ -857,7 +863,7 @@ static bxmg_status run_fill(bxmg_multifab mf, int32_t scomp, int32_t ncomp, int 
         Plan* p = mf_plan(mf, mode, cross, odd);
         hipStream_t s = stream ? (hipStream_t)stream : mf->ctx->stream;
         HIPCHK(launch_fill_fab(s, mf->data, mf->dtype == BXMG_F32, mf->d_fboxes.p, p->tags.p, p->ntags, p->cells, scomp,
-                               ncomp));
+                               ncomp, p->hints.p));
     } catch (HipError& e) {
         return fail(BXMG_EDEVICE, std::string("fill: ") + hipGetErrorString(e.e));
     }
@@ -900,7 +906,7 @@ bxmg_status bxmg_parallel_copy(bxmg_multifab dst, int32_t dcomp, bxmg_multifab s
         const Plan& P = *it->second;
         hipStream_t s = hip_stream ? (hipStream_t)hip_stream : dst->ctx->stream;
         HIPCHK(launch_copy_fab(s, dst->dtype == BXMG_F32, dst->data, dst->d_fboxes.p, src->data, src->d_fboxes.p,
-                               P.tags.p, P.ntags, P.cells, dcomp, scomp, ncomp));
+                               P.tags.p, P.ntags, P.cells, dcomp, scomp, ncomp, P.hints.p));
     } catch (HipError& e) {
         return fail(BXMG_EDEVICE, std::string("parallel_copy: ") + hipGetErrorString(e.e));
     }
@@ -933,7 +939,7 @@ bxmg_status bxmg_fill_boundary_noalloc(bxmg_multifab mf, int32_t scomp, int32_t 
         // has read its list before this copy overwrites it
         HIPCHK(hipMemcpyAsync(mf->ctx->scratch, tags.data(), bytes, hipMemcpyHostToDevice, s));
         HIPCHK(launch_fill_fab(s, mf->data, mf->dtype == BXMG_F32, mf->d_fboxes.p, (const Tag*)mf->ctx->scratch,
-                               (int)tags.size(), it->second.second, scomp, ncomp));
+                               (int)tags.size(), it->second.second, scomp, ncomp, nullptr));
     } catch (HipError& e) {
         return fail(BXMG_EDEVICE, std::string("fill_noalloc: ") + hipGetErrorString(e.e));
     }

@@ -529,12 +529,30 @@ struct DevVec {
     }
 };
 
+// For every block of kBlock region cells, the tag of its first cell; then
+// ntags - 1.  The fill and copy kernels search only between a block's two
+// entries.
+inline std::vector<int> tag_hints(const std::vector<Tag>& t) {
+    std::vector<int> h;
+    if (t.empty()) return h;
+    const long long cells = tag_cells(t);
+    size_t q = 0;
+    for (long long g = 0; g < cells; g += kBlock) {
+        while (q + 1 < t.size() && t[q + 1].prefix <= g) ++q;
+        h.push_back((int)q);
+    }
+    h.push_back((int)t.size() - 1);
+    return h;
+}
+
 struct Plan {
     DevBuf<Tag> tags;
+    DevBuf<int> hints;
     int ntags = 0;
     long long cells = 0;
     void set(const std::vector<Tag>& t, hipStream_t s) {
         tags.upload_async(t, s);
+        hints.upload_async(tag_hints(t), s);
         ntags = (int)t.size();
         cells = tag_cells(t);
     }

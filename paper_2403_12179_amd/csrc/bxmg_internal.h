@@ -184,12 +184,14 @@ constexpr int kHist = 256;
 // active != nullptr: nothing happens while active[0] == 0 (a stopped solve)
 hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* list, long long n,
                           const int* active = nullptr);
+// hints: NULL, or for every block of kBlock region cells the tag of its
+// first cell, then ntags - 1 (tag_hints)
 hipError_t launch_fill_fab(hipStream_t s, void* data, bool f32, const FBox* boxes, const Tag* tags, int ntags,
-                           long long ncells, int comp0, int ncomp);
+                           long long ncells, int comp0, int ncomp, const int* hints);
 // ParallelCopy over region tags (source cell = destination cell + soff)
 hipError_t launch_copy_fab(hipStream_t s, bool f32, void* dst, const FBox* dboxes, const void* src,
                            const FBox* sboxes, const Tag* tags, int ntags, long long ncells, int dcomp, int scomp,
-                           int ncomp);
+                           int ncomp, const int* hints);
 
 // Coefficient modes of the stencil kernels: beta != nullptr -> cell beta of
 // the level (same layout as u); fat != nullptr -> face arrays fat[pid] of the

@@ -30,14 +30,37 @@
 namespace bxmg {
 
 // ----------------------------------------------------------------- helpers
-__device__ __forceinline__ int find_tag(const Tag* __restrict__ t, int n, long long g) {
+// The tag holding region cell g: the last tag whose prefix is <= g.  With
+// hints (the tag of the first cell of every block of kBlock cells, plus
+// ntags - 1 at the end) the search starts from the block's own range.
+__device__ __forceinline__ int find_tag(const Tag* __restrict__ t, int n, long long g,
+                                        const int* __restrict__ hints = nullptr) {
     int lo = 0, hi = n - 1;
+    if (hints) {
+        lo = hints[blockIdx.x];
+        hi = hints[blockIdx.x + 1];
+    }
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
         if (t[mid].prefix <= g) lo = mid;
         else hi = mid - 1;
     }
     return lo;
+}
+
+// Region coordinates of cell loc of tag t (32-bit divisions when they fit).
+__device__ __forceinline__ void tag_xyz(const Tag& t, long long loc, int& x, int& y, int& z) {
+    if (loc < 0x7fffffffLL) {
+        const unsigned l = (unsigned)loc, n0 = (unsigned)t.n[0], n1 = (unsigned)t.n[1];
+        const unsigned q = l / n0;
+        x = (int)(l - q * n0);
+        y = (int)(q % n1);
+        z = (int)(q / n1);
+    } else {
+        x = (int)(loc % t.n[0]);
+        y = (int)((loc / t.n[0]) % t.n[1]);
+        z = (int)(loc / ((long long)t.n[0] * t.n[1]));
+    }
 }
 
 __device__ __forceinline__ long long rb_row(const RBox& b, int c, int j, int k) {
@@ -404,14 +427,12 @@ __global__ void __launch_bounds__(kBlock) k_fill_rb(T* __restrict__ data, const 
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_fill_fab(T* __restrict__ data, const FBox* __restrict__ boxes,
                                                     const Tag* __restrict__ tags, int ntags, long long ncells,
-                                                    int comp0, int ncomp) {
+                                                    int comp0, int ncomp, const int* __restrict__ hints) {
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ncells) return;
-    const Tag t = tags[find_tag(tags, ntags, g)];
-    const long long loc = g - t.prefix;
-    const int x = (int)(loc % t.n[0]);
-    const int y = (int)((loc / t.n[0]) % t.n[1]);
-    const int z = (int)(loc / ((long long)t.n[0] * t.n[1]));
+    const Tag t = tags[find_tag(tags, ntags, g, hints)];
+    int x, y, z;
+    tag_xyz(t, g - t.prefix, x, y, z);
     const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
     const int si = t.sgn[0] * di + t.soff[0], sj = t.sgn[1] * dj + t.soff[1], sk = t.sgn[2] * dk + t.soff[2];
     const FBox sb = boxes[t.sbox], db = boxes[t.dbox];
@@ -430,14 +451,12 @@ template <class T>
 __global__ void __launch_bounds__(kBlock) k_copy_fab(T* __restrict__ dst, const FBox* __restrict__ dboxes,
                                                     const T* __restrict__ src, const FBox* __restrict__ sboxes,
                                                     const Tag* __restrict__ tags, int ntags, long long ncells,
-                                                    int dcomp, int scomp, int ncomp) {
+                                                    int dcomp, int scomp, int ncomp, const int* __restrict__ hints) {
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ncells) return;
-    const Tag t = tags[find_tag(tags, ntags, g)];
-    const long long loc = g - t.prefix;
-    const int x = (int)(loc % t.n[0]);
-    const int y = (int)((loc / t.n[0]) % t.n[1]);
-    const int z = (int)(loc / ((long long)t.n[0] * t.n[1]));
+    const Tag t = tags[find_tag(tags, ntags, g, hints)];
+    int x, y, z;
+    tag_xyz(t, g - t.prefix, x, y, z);
     const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
     const FBox sb = sboxes[t.sbox], db = dboxes[t.dbox];
     const long long s0 = fab_idx(sb, di + t.soff[0], dj + t.soff[1], dk + t.soff[2]), d0 = fab_idx(db, di, dj, dk);
@@ -2265,22 +2284,26 @@ hipError_t launch_fill_rb(hipStream_t s, void* data, bool f32, const GhostCopy* 
 
 hipError_t launch_copy_fab(hipStream_t s, bool f32, void* dst, const FBox* dboxes, const void* src,
                            const FBox* sboxes, const Tag* tags, int ntags, long long ncells, int dcomp, int scomp,
-                           int ncomp) {
+                           int ncomp, const int* hints) {
     if (ncells <= 0) return hipSuccess;
     if (f32)
         hipLaunchKernelGGL(k_copy_fab<float>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (float*)dst, dboxes,
-                           (const float*)src, sboxes, tags, ntags, ncells, dcomp, scomp, ncomp);
+                           (const float*)src, sboxes, tags, ntags, ncells, dcomp, scomp, ncomp, hints);
     else
         hipLaunchKernelGGL(k_copy_fab<double>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (double*)dst, dboxes,
-                           (const double*)src, sboxes, tags, ntags, ncells, dcomp, scomp, ncomp);
+                           (const double*)src, sboxes, tags, ntags, ncells, dcomp, scomp, ncomp, hints);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_fab(hipStream_t s, void* data, bool f32, const FBox* boxes, const Tag* tags, int ntags,
-                           long long ncells, int comp0, int ncomp) {
+                           long long ncells, int comp0, int ncomp, const int* hints) {
     if (ncells <= 0) return hipSuccess;
-    if (f32) hipLaunchKernelGGL(k_fill_fab<float>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (float*)data, boxes, tags, ntags, ncells, comp0, ncomp);
-    else hipLaunchKernelGGL(k_fill_fab<double>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (double*)data, boxes, tags, ntags, ncells, comp0, ncomp);
+    if (f32)
+        hipLaunchKernelGGL(k_fill_fab<float>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (float*)data, boxes, tags, ntags,
+                           ncells, comp0, ncomp, hints);
+    else
+        hipLaunchKernelGGL(k_fill_fab<double>, dim3(nblk(ncells)), dim3(kBlock), 0, s, (double*)data, boxes, tags,
+                           ntags, ncells, comp0, ncomp, hints);
     return hipGetLastError();
 }
 
