@@ -47,7 +47,8 @@ namespace bxmg {
 namespace comp {
 
 constexpr int kCB = 256;  // threads per block
-constexpr int kKZ = 8;    // planes each thread walks
+constexpr int kKZ = 8;    // planes each thread walks (kernels that reduce norms, coarse kernels)
+constexpr int kKZs = 4;   // planes each thread walks in the fine sweeps and the interpolation
 
 // The coarse level: layout of the one-box fields and the domain.
 struct CGeo {
@@ -55,6 +56,7 @@ struct CGeo {
     int dlo[3], n[3];  // coarse domain
     int per[3];
     double h0, h1;
+    double ih0sq;  // 1 / h0^2
 };
 
 // Coverage map entry of a coarse cell: >= 0 the fine box covering it;
@@ -66,6 +68,19 @@ __device__ __forceinline__ int cq(const CGeo& g, int I, int J, int K) {
 
 __device__ __forceinline__ long long fidx(const FBox& b, int i, int j, int k) {
     return b.base + (long long)((i - b.glo[0]) + b.G[0] * ((j - b.glo[1]) + b.G[1] * (k - b.glo[2])));
+}
+
+// Block coordinates with consecutive logical blocks on one XCD: blocks are
+// dispatched round-robin over the 8 XCDs (block p to XCD p % 8), so logical
+// block (p % 8) * (N / 8) + p / 8 gives each XCD one contiguous eighth of the
+// grid (x fastest, then y, then z), and its L2 serves the neighbouring rows
+// and planes its stencils read.
+__device__ __forceinline__ uint3 xcd_block() {
+    const unsigned gx = gridDim.x, gy = gridDim.y, N = gx * gy * gridDim.z;
+    const unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned L = (N & 7) ? p : (p & 7) * (N >> 3) + (p >> 3);
+    const unsigned r = L / gx;
+    return make_uint3(L - r * gx, r % gy, r / gy);
 }
 
 __device__ __forceinline__ void block_norms(double mx, double s2, double bad, double* __restrict__ out3) {
@@ -140,13 +155,14 @@ __global__ void __launch_bounds__(kCB) k_cf_ghost(const int4* __restrict__ list,
 // u = (sum of the 6 neighbours - h1^2 f) / 6 at the cells of that colour.
 __global__ void __launch_bounds__(kCB) k_fine_gs(CGeo g, const FBox* __restrict__ fu, const FBox* __restrict__ ff,
                                                  double* __restrict__ u, const double* __restrict__ f, int colour) {
-    const FBox B = fu[blockIdx.z], F = ff[blockIdx.z];
+    const uint3 bk = xcd_block();
+    const FBox B = fu[bk.z], F = ff[bk.z];
     const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1;
     const int nxh = (nx + 1) >> 1;
-    const int t = blockIdx.x * kCB + threadIdx.x;
+    const int t = bk.x * kCB + threadIdx.x;
     if (t >= nxh * ny) return;
     const int tx = t % nxh, j = B.lo[1] + t / nxh;
-    const int k0 = B.lo[2] + blockIdx.y * kKZ, k1 = min(k0 + kKZ - 1, B.hi[2]);
+    const int k0 = B.lo[2] + bk.y * kKZs, k1 = min(k0 + kKZs - 1, B.hi[2]);
     const long long sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
     const double h2 = g.h1 * g.h1;
     for (int k = k0; k <= k1; ++k) {
@@ -164,13 +180,14 @@ __global__ void __launch_bounds__(kCB) k_fine_resid(CGeo g, const FBox* __restri
                                                     const FBox* __restrict__ fr, const double* __restrict__ u,
                                                     const double* __restrict__ f, double* __restrict__ r, int fonly,
                                                     double* __restrict__ partials) {
-    const FBox B = fu[blockIdx.z], F = ff[blockIdx.z], R = fr[blockIdx.z];
+    const uint3 bk = xcd_block();
+    const FBox B = fu[bk.z], F = ff[bk.z], R = fr[bk.z];
     const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1;
-    const int t = blockIdx.x * kCB + threadIdx.x;
+    const int t = bk.x * kCB + threadIdx.x;
     double mx = 0.0, s2 = 0.0, bad = 0.0;
     if (t < nx * ny) {
         const int i = B.lo[0] + t % nx, j = B.lo[1] + t / nx;
-        const int k0 = B.lo[2] + blockIdx.y * kKZ, k1 = min(k0 + kKZ - 1, B.hi[2]);
+        const int k0 = B.lo[2] + bk.y * kKZ, k1 = min(k0 + kKZ - 1, B.hi[2]);
         const long long sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
         const double ih2 = 1.0 / (g.h1 * g.h1);
         for (int k = k0; k <= k1; ++k) {
@@ -184,19 +201,20 @@ __global__ void __launch_bounds__(kCB) k_fine_resid(CGeo g, const FBox* __restri
             norm_add(rv, mx, s2, bad);
         }
     }
-    const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const int blk = (bk.z * gridDim.y + bk.y) * gridDim.x + bk.x;
     block_norms(mx, s2, bad, partials + 3 * (long long)blk);
 }
 
 // Fine cells += trilinear interpolation of the coarse correction Ec.
 __global__ void __launch_bounds__(kCB) k_fine_prolong(CGeo g, const FBox* __restrict__ fu, double* __restrict__ u,
                                                       const double* __restrict__ Ec) {
-    const FBox B = fu[blockIdx.z];
+    const uint3 bk = xcd_block();
+    const FBox B = fu[bk.z];
     const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1;
-    const int t = blockIdx.x * kCB + threadIdx.x;
+    const int t = bk.x * kCB + threadIdx.x;
     if (t >= nx * ny) return;
     const int i = B.lo[0] + t % nx, j = B.lo[1] + t / nx;
-    const int k0 = B.lo[2] + blockIdx.y * kKZ, k1 = min(k0 + kKZ - 1, B.hi[2]);
+    const int k0 = B.lo[2] + bk.y * kKZs, k1 = min(k0 + kKZs - 1, B.hi[2]);
     const int I = i >> 1, J = j >> 1;
     const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1;
     const long long sy = g.cb.G[0], sz = (long long)g.cb.G[0] * g.cb.G[1];
@@ -215,11 +233,12 @@ __global__ void __launch_bounds__(kCB) k_fine_prolong(CGeo g, const FBox* __rest
 
 // Component 0 of every fine box, valid and ghost cells, := 0.
 __global__ void __launch_bounds__(kCB) k_fine_zero(const FBox* __restrict__ fu, double* __restrict__ u) {
-    const FBox B = fu[blockIdx.z];
+    const uint3 bk = xcd_block();
+    const FBox B = fu[bk.z];
     const int P = B.G[0] * B.G[1];
-    const int t = blockIdx.x * kCB + threadIdx.x;
+    const int t = bk.x * kCB + threadIdx.x;
     if (t >= P) return;
-    for (int k = blockIdx.y * kKZ; k < min(blockIdx.y * kKZ + kKZ, B.G[2]); ++k) u[B.base + (long long)k * P + t] = 0.0;
+    for (int k = bk.y * kKZ; k < min(bk.y * kKZ + kKZ, B.G[2]); ++k) u[B.base + (long long)k * P + t] = 0.0;
 }
 
 // Coarse kernels: grid (plane blocks, plane groups of kKZ) over the domain.
@@ -235,25 +254,38 @@ __global__ void __launch_bounds__(kCB) k_coarse_resid(CGeo g, const int* __restr
                                                       const double* __restrict__ uf, const FBox* __restrict__ fr,
                                                       const double* __restrict__ rf, int fonly,
                                                       double* __restrict__ partials) {
-    const int t = blockIdx.x * kCB + threadIdx.x;
+    const uint3 bk = xcd_block();
+    const int t = bk.x * kCB + threadIdx.x;
     double mx = 0.0, s2 = 0.0, bad = 0.0;
     if (t < g.n[0] * g.n[1]) {
         const int I = g.dlo[0] + t % g.n[0], J = g.dlo[1] + t / g.n[0];
-        const int K0 = g.dlo[2] + blockIdx.y * kKZ, K1 = min(K0 + kKZ - 1, g.dlo[2] + g.n[2] - 1);
+        const int K0 = g.dlo[2] + bk.y * kKZ, K1 = min(K0 + kKZ - 1, g.dlo[2] + g.n[2] - 1);
         const long long st[3] = {1, g.cb.G[0], (long long)g.cb.G[0] * g.cb.G[1]};
         const int mst[3] = {1, g.n[0], g.n[0] * g.n[1]};
         for (int K = K0; K <= K1; ++K) {
             const int q = cq(g, I, J, K);
-            const int code = cmap[q];
             const long long c = fidx(g.cb, I, J, K);
+            // every load of the common case issued before the first branch
+            // (the ghost layer keeps the neighbour loads of boundary cells in
+            // bounds)
+            const int code = cmap[q];
+            double rv = Fc[c];
+            const double UI = Uc[c];
+            const double uxm = Uc[c - 1], uxp = Uc[c + 1], uym = Uc[c - st[1]], uyp = Uc[c + st[1]];
+            const double uzm = Uc[c - st[2]], uzp = Uc[c + st[2]];
             if (code >= 0) {
                 if (!fonly) Rc[c] = mean8(rf, fr[code], 2 * I, 2 * J, 2 * K);
                 continue;
             }
-            double rv = Fc[c];
-            if (!fonly) {
+            const bool inner = code == -1 && I > g.dlo[0] && I < g.dlo[0] + g.n[0] - 1 && J > g.dlo[1] &&
+                               J < g.dlo[1] + g.n[1] - 1 && K > g.dlo[2] && K < g.dlo[2] + g.n[2] - 1;
+            if (!fonly && inner) {
+                // no covered neighbour, no domain face: the 7-point operator
+                rv = rv - ((((uxm - UI) + (uxp - UI)) + ((uym - UI) + (uyp - UI))) + ((uzm - UI) + (uzp - UI))) *
+                              g.ih0sq;
+                Rc[c] = rv;
+            } else if (!fonly) {
                 const int mask = -1 - code;
-                const double UI = Uc[c];
                 const int X[3] = {I, J, K};
                 double gr[6];
 #pragma unroll
@@ -301,16 +333,17 @@ __global__ void __launch_bounds__(kCB) k_coarse_resid(CGeo g, const int* __restr
             norm_add(rv, mx, s2, bad);
         }
     }
-    block_norms(mx, s2, bad, partials + 3 * (long long)(blockIdx.y * gridDim.x + blockIdx.x));
+    block_norms(mx, s2, bad, partials + 3 * (long long)(bk.y * gridDim.x + bk.x));
 }
 
 // Uc += Ec at the uncovered coarse cells.
 __global__ void __launch_bounds__(kCB) k_coarse_update(CGeo g, const int* __restrict__ cmap, double* __restrict__ Uc,
                                                        const double* __restrict__ Ec) {
-    const int t = blockIdx.x * kCB + threadIdx.x;
+    const uint3 bk = xcd_block();
+    const int t = bk.x * kCB + threadIdx.x;
     if (t >= g.n[0] * g.n[1]) return;
     const int I = g.dlo[0] + t % g.n[0], J = g.dlo[1] + t / g.n[0];
-    const int K0 = g.dlo[2] + blockIdx.y * kKZ, K1 = min(K0 + kKZ - 1, g.dlo[2] + g.n[2] - 1);
+    const int K0 = g.dlo[2] + bk.y * kKZ, K1 = min(K0 + kKZ - 1, g.dlo[2] + g.n[2] - 1);
     for (int K = K0; K <= K1; ++K) {
         if (cmap[cq(g, I, J, K)] >= 0) continue;
         const long long c = fidx(g.cb, I, J, K);
@@ -322,12 +355,13 @@ __global__ void __launch_bounds__(kCB) k_coarse_update(CGeo g, const int* __rest
 // plane groups, fine box) over each fine box's coarse cells.
 __global__ void __launch_bounds__(kCB) k_coarse_sync(CGeo g, double* __restrict__ Uc, const FBox* __restrict__ fu,
                                                      const double* __restrict__ uf) {
-    const FBox B = fu[blockIdx.z];
+    const uint3 bk = xcd_block();
+    const FBox B = fu[bk.z];
     const int cx = (B.hi[0] - B.lo[0] + 1) >> 1, cy = (B.hi[1] - B.lo[1] + 1) >> 1, cz = (B.hi[2] - B.lo[2] + 1) >> 1;
-    const int t = blockIdx.x * kCB + threadIdx.x;
+    const int t = bk.x * kCB + threadIdx.x;
     if (t >= cx * cy) return;
     const int I = (B.lo[0] >> 1) + t % cx, J = (B.lo[1] >> 1) + t / cx;
-    const int K0 = (B.lo[2] >> 1) + blockIdx.y * kKZ, K1 = min(K0 + kKZ - 1, (B.lo[2] >> 1) + cz - 1);
+    const int K0 = (B.lo[2] >> 1) + bk.y * kKZ, K1 = min(K0 + kKZ - 1, (B.lo[2] >> 1) + cz - 1);
     for (int K = K0; K <= K1; ++K) Uc[fidx(g.cb, I, J, K)] = mean8(uf, B, 2 * I, 2 * J, 2 * K);
 }
 
@@ -346,7 +380,7 @@ struct Comp {
     DevBuf<int4> ghosts;
     int nghosts = 0;
     int nfine = 0;
-    dim3 g_fine, g_fine_gs, g_sync, g_coarse;  // launch grids
+    dim3 g_fine, g_fine_s, g_fine_gs, g_sync, g_coarse;  // launch grids
     int nparts_fine = 0, nparts = 0;
     DevBuf<double> part, fn;
     double* h_norm = nullptr;  // pinned: the norms read back
@@ -429,6 +463,7 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
     }
     g.h0 = h0;
     g.h1 = h0 * 0.5;
+    g.ih0sq = 1.0 / (h0 * h0);
     // coverage map: covering fine box, or -1 - (mask of covered face neighbours)
     const long long nc = D.cells();
     std::vector<int> cmap((size_t)nc, -1);
@@ -486,7 +521,8 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
     c->nghosts = (int)gl.size();
     const unsigned nf = (unsigned)std::max(1, c->nfine);
     c->g_fine = dim3(cdiv(maxP, kCB), cdiv(maxnz, kKZ), nf);
-    c->g_fine_gs = dim3(cdiv(maxPh, kCB), cdiv(maxnz, kKZ), nf);
+    c->g_fine_s = dim3(cdiv(maxP, kCB), cdiv(maxnz, kKZs), nf);
+    c->g_fine_gs = dim3(cdiv(maxPh, kCB), cdiv(maxnz, kKZs), nf);
     c->g_sync = dim3(cdiv(maxPc, kCB), cdiv(maxnzc, kKZ), nf);
     c->g_coarse = dim3(cdiv((long long)g.n[0] * g.n[1], kCB), cdiv(g.n[2], kKZ), 1);
     c->nparts_fine = c->nfine ? (int)(c->g_fine.x * c->g_fine.y * c->g_fine.z) : 0;
@@ -630,7 +666,7 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
             hipLaunchKernelGGL(comp::k_coarse_update, c.g_coarse, dim3(comp::kCB), 0, s, g, (const int*)c.cmap.p, Uc,
                                (const double*)Ec);
             if (nfb)
-                hipLaunchKernelGGL(comp::k_fine_prolong, c.g_fine, dim3(comp::kCB), 0, s, g, fu, uf,
+                hipLaunchKernelGGL(comp::k_fine_prolong, c.g_fine_s, dim3(comp::kCB), 0, s, g, fu, uf,
                                    (const double*)Ec);
             HIPCHK(hipGetLastError());
             sweeps(P.nu2);
