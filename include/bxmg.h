@@ -279,7 +279,8 @@ bxmg_status bxmg_nodal_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg
  *     ones; rhs_c is read at uncovered cells only.
  *   phi_f, rhs_f: FP64 MultiFabs over the fine BoxArray, whose domain is the
  *     coarse one refined by 2 (lo 2*lo, hi 2*hi+1) with the same boundary
- *     conditions; phi_f needs nghost >= 1 (its ghosts are overwritten).  Every
+ *     conditions; phi_f needs nghost >= 1 (its ghosts may be overwritten;
+ *     fine boxes that tile one rectangle run as one merged box).  Every
  *     fine box must have even lower and odd upper corners (whole coarse
  *     cells) and lie at least 4 fine cells inside every domain face.
  *   params: nu1, nu2 (fine and coarse sweeps), max_cycles, fixed_cycles,

@@ -27,8 +27,11 @@
 // Storage: the coarse level lives in one-box MultiFabs over the domain (the
 // caller's coarse data is ParallelCopy'd in and out), so any coarse cell is
 // one address computation away; a dense int map over the coarse cells holds
-// the fine box that covers each one (-1: uncovered).  The fine level is the
-// caller's MultiFabs; the coarse-fine ghost cells are listed once per layout.
+// the fine box that covers each one, or -1 - (mask of covered face
+// neighbours).  The fine level is the caller's MultiFabs, or, when the fine
+// boxes tile one rectangle, one merged box (ParallelCopy in and out) with no
+// ghosts between boxes; the coarse-fine ghost cells are listed once per
+// layout.
 // Fine boxes must be unions of whole coarse cells (even lower, odd upper
 // corners) and lie at least 2 coarse cells inside the domain, so that every
 // coarse cell a ghost or an interpolation reads is a domain cell.
@@ -374,7 +377,13 @@ struct Comp {
     double h0 = 0.0;
     bxmg_boxarray one = nullptr;                                           // one box over the coarse domain
     bxmg_multifab Uc = nullptr, Fc = nullptr, Rc = nullptr, Ec = nullptr;  // over `one`, 1 ghost
-    bxmg_multifab Rf = nullptr;                                            // fine residual (caller's fine boxes)
+    bxmg_multifab Rf = nullptr;                                            // fine residual
+    // Merged fine level: when the fine boxes tile one rectangle, the fine
+    // level runs as that one box (solution with 1 ghost, right-hand side),
+    // loaded and returned by ParallelCopy; there are then no ghosts between
+    // fine boxes and every ghost is a coarse-fine one.
+    bxmg_boxarray fone = nullptr;
+    bxmg_multifab Uf = nullptr, Ff = nullptr;
     CGeo geo{};
     DevBuf<int> cmap;
     DevBuf<int4> ghosts;
@@ -385,9 +394,10 @@ struct Comp {
     DevBuf<double> part, fn;
     double* h_norm = nullptr;  // pinned: the norms read back
     ~Comp() {
-        for (bxmg_multifab m : {Uc, Fc, Rc, Ec, Rf})
+        for (bxmg_multifab m : {Uc, Fc, Rc, Ec, Rf, Uf, Ff})
             if (m) bxmg_multifab_release(m);
         if (one) bxmg_boxarray_release(one);
+        if (fone) bxmg_boxarray_release(fone);
         const hipStream_t s = ctx ? ctx->stream : nullptr;
         cmap.release_async(s);
         ghosts.release_async(s);
@@ -444,16 +454,38 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
     c->Fc = alloc_mf(ctx, c->one, 1);
     c->Rc = alloc_mf(ctx, c->one, 1);
     c->Ec = alloc_mf(ctx, c->one, 1);
-    // the fine residual over the caller's fine boxes
-    bxmg_boxarray fcopy = nullptr;
-    std::vector<int32_t> fl;
-    for (const Box& B : fba->boxes)
-        for (int v : {B.lo[0], B.lo[1], B.lo[2], B.hi[0], B.hi[1], B.hi[2]}) fl.push_back(v);
-    if (bxmg_define_boxarray_list(fba->dom.lo, fba->dom.hi, fba->bc, (int32_t)fba->boxes.size(), fl.data(), &fcopy) !=
-        BXMG_OK)
-        throw std::runtime_error(bxmg_last_error());
-    c->Rf = alloc_mf(ctx, fcopy, 0);
-    bxmg_boxarray_release(fcopy);  // the MultiFab keeps its reference
+    // the fine level: one merged box when the caller's fine boxes tile a
+    // rectangle (they are disjoint, so equal cell counts mean they tile it)
+    Box U = fba->boxes[0];
+    long long fcells = 0;
+    for (const Box& B : fba->boxes) {
+        fcells += B.cells();
+        for (int d = 0; d < 3; ++d) {
+            U.lo[d] = std::min(U.lo[d], B.lo[d]);
+            U.hi[d] = std::max(U.hi[d], B.hi[d]);
+        }
+    }
+    std::vector<Box> fb;  // the boxes the kernels run over
+    if (fcells == U.cells() && fba->boxes.size() > 1) {
+        const int ul[6] = {U.lo[0], U.lo[1], U.lo[2], U.hi[0], U.hi[1], U.hi[2]};
+        if (bxmg_define_boxarray_list(fba->dom.lo, fba->dom.hi, fba->bc, 1, ul, &c->fone) != BXMG_OK)
+            throw std::runtime_error(bxmg_last_error());
+        c->Uf = alloc_mf(ctx, c->fone, 1);
+        c->Ff = alloc_mf(ctx, c->fone, 0);
+        c->Rf = alloc_mf(ctx, c->fone, 0);
+        fb.push_back(U);
+    } else {
+        bxmg_boxarray fcopy = nullptr;
+        std::vector<int32_t> fl;
+        for (const Box& B : fba->boxes)
+            for (int v : {B.lo[0], B.lo[1], B.lo[2], B.hi[0], B.hi[1], B.hi[2]}) fl.push_back(v);
+        if (bxmg_define_boxarray_list(fba->dom.lo, fba->dom.hi, fba->bc, (int32_t)fba->boxes.size(), fl.data(),
+                                      &fcopy) != BXMG_OK)
+            throw std::runtime_error(bxmg_last_error());
+        c->Rf = alloc_mf(ctx, fcopy, 0);
+        bxmg_boxarray_release(fcopy);  // the MultiFab keeps its reference
+        fb = fba->boxes;
+    }
     CGeo& g = c->geo;
     g.cb = c->Uc->fboxes[0];
     for (int d = 0; d < 3; ++d) {
@@ -470,7 +502,6 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
     auto cidx = [&](int I, int J, int K) {
         return (size_t)(I - D.lo[0]) + (size_t)D.n(0) * ((size_t)(J - D.lo[1]) + (size_t)D.n(1) * (K - D.lo[2]));
     };
-    const auto& fb = fba->boxes;
     c->nfine = (int)fb.size();
     int maxP = 1, maxPh = 1, maxnz = 1, maxPc = 1, maxnzc = 1;
     for (size_t b = 0; b < fb.size(); ++b) {
@@ -592,17 +623,19 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
         double* Fc = (double*)c.Fc->data;
         double* Rc = (double*)c.Rc->data;
         double* Ec = (double*)c.Ec->data;
-        double* uf = (double*)phi_f->data;
-        const double* ff = (const double*)rhs_f->data;
+        const bool merged = c.Uf != nullptr;
+        bxmg_multifab mu = merged ? c.Uf : phi_f, mf = merged ? c.Ff : rhs_f;
+        double* uf = (double*)mu->data;
+        const double* ff = (const double*)mf->data;
         double* rf = (double*)c.Rf->data;
-        const FBox* fu = phi_f->d_fboxes.p;
-        const FBox* fF = rhs_f->d_fboxes.p;
+        const FBox* fu = mu->d_fboxes.p;
+        const FBox* fF = mf->d_fboxes.p;
         const FBox* fR = c.Rf->d_fboxes.p;
         const unsigned nfb = (unsigned)c.nfine;
         double* const part_c = c.part.p + 3 * (size_t)c.nparts_fine;
-        // k_fine_zero covers the grown boxes of phi_f
+        // k_fine_zero covers the grown fine boxes
         int maxPG = 1, maxGz = 1;
-        for (const FBox& B : phi_f->fboxes) {
+        for (const FBox& B : mu->fboxes) {
             maxPG = std::max(maxPG, B.G[0] * B.G[1]);
             maxGz = std::max(maxGz, B.G[2]);
         }
@@ -612,12 +645,13 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
         };
         // load: coarse rhs into the one-box field, zero start on both levels
         chk(bxmg_parallel_copy(c.Fc, 0, rhs_c, 0, 1, 0, s));
+        if (merged) chk(bxmg_parallel_copy(c.Ff, 0, rhs_f, 0, 1, 0, s));
         HIPCHK(hipMemsetAsync(Uc, 0, c.Uc->bytes, s));
         if (nfb) hipLaunchKernelGGL(comp::k_fine_zero, g_zero, dim3(comp::kCB), 0, s, fu, uf);
         HIPCHK(hipGetLastError());
         auto fill_fine = [&]() {
             if (!nfb) return;
-            chk(bxmg_fill_boundary(phi_f, 0, 1, 1, s));
+            if (!merged) chk(bxmg_fill_boundary(phi_f, 0, 1, 1, s));
             if (c.nghosts)
                 hipLaunchKernelGGL(comp::k_cf_ghost, dim3(comp::cdiv(c.nghosts, comp::kCB)), dim3(comp::kCB), 0, s,
                                    c.ghosts.p, c.nghosts, g, (const double*)Uc, fu, uf);
@@ -705,6 +739,7 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
         info->cycles = cyc;
         // the coarse solution (covered cells: the mean of their children) back
         chk(bxmg_parallel_copy(phi_c, 0, c.Uc, 0, 1, 0, s));
+        if (merged) chk(bxmg_parallel_copy(phi_f, 0, c.Uf, 0, 1, 0, s));
         HIPCHK(hipStreamSynchronize(s));
         info->status = status;
         if (status == BXMG_ENOCONV) fail(BXMG_ENOCONV, "composite_solve: max_cycles reached");

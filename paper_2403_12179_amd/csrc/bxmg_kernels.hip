@@ -429,19 +429,28 @@ __global__ void __launch_bounds__(kBlock) k_fill_fab(T* __restrict__ data, const
                                                     const Tag* __restrict__ tags, int ntags, long long ncells,
                                                     int comp0, int ncomp, const int* __restrict__ hints) {
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ncells) return;
-    const Tag t = tags[find_tag(tags, ntags, g, hints)];
-    int x, y, z;
-    tag_xyz(t, g - t.prefix, x, y, z);
-    const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
-    const int si = t.sgn[0] * di + t.soff[0], sj = t.sgn[1] * dj + t.soff[1], sk = t.sgn[2] * dk + t.soff[2];
-    const FBox sb = boxes[t.sbox], db = boxes[t.dbox];
-    const long long s0 = fab_idx(sb, si, sj, sk), d0 = fab_idx(db, di, dj, dk);
-    for (int n = comp0; n < comp0 + ncomp; ++n) {
-        T v = data[s0 + n * sb.cs];
-        if (t.neg) v = -v;
-        data[d0 + n * db.cs] = v;
+    auto cell = [&](const Tag& t) {
+        int x, y, z;
+        tag_xyz(t, g - t.prefix, x, y, z);
+        const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
+        const int si = t.sgn[0] * di + t.soff[0], sj = t.sgn[1] * dj + t.soff[1], sk = t.sgn[2] * dk + t.soff[2];
+        const FBox sb = boxes[t.sbox], db = boxes[t.dbox];
+        const long long s0 = fab_idx(sb, si, sj, sk), d0 = fab_idx(db, di, dj, dk);
+        for (int n = comp0; n < comp0 + ncomp; ++n) {
+            T v = data[s0 + n * sb.cs];
+            if (t.neg) v = -v;
+            data[d0 + n * db.cs] = v;
+        }
+    };
+    // a block inside one region: its tag and boxes are the same for every
+    // lane (scalar loads)
+    if (hints && hints[blockIdx.x] == hints[blockIdx.x + 1]) {
+        const Tag t = tags[hints[blockIdx.x]];
+        if (g < ncells) cell(t);
+        return;
     }
+    if (g >= ncells) return;
+    cell(tags[find_tag(tags, ntags, g, hints)]);
 }
 
 // ParallelCopy: region tags between two MultiFabs (destination box dbox,
@@ -453,14 +462,21 @@ __global__ void __launch_bounds__(kBlock) k_copy_fab(T* __restrict__ dst, const 
                                                     const Tag* __restrict__ tags, int ntags, long long ncells,
                                                     int dcomp, int scomp, int ncomp, const int* __restrict__ hints) {
     const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    auto cell = [&](const Tag& t) {
+        int x, y, z;
+        tag_xyz(t, g - t.prefix, x, y, z);
+        const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
+        const FBox sb = sboxes[t.sbox], db = dboxes[t.dbox];
+        const long long s0 = fab_idx(sb, di + t.soff[0], dj + t.soff[1], dk + t.soff[2]), d0 = fab_idx(db, di, dj, dk);
+        for (int n = 0; n < ncomp; ++n) dst[d0 + (dcomp + n) * db.cs] = src[s0 + (scomp + n) * sb.cs];
+    };
+    if (hints && hints[blockIdx.x] == hints[blockIdx.x + 1]) {
+        const Tag t = tags[hints[blockIdx.x]];
+        if (g < ncells) cell(t);
+        return;
+    }
     if (g >= ncells) return;
-    const Tag t = tags[find_tag(tags, ntags, g, hints)];
-    int x, y, z;
-    tag_xyz(t, g - t.prefix, x, y, z);
-    const int di = t.dlo[0] + x, dj = t.dlo[1] + y, dk = t.dlo[2] + z;
-    const FBox sb = sboxes[t.sbox], db = dboxes[t.dbox];
-    const long long s0 = fab_idx(sb, di + t.soff[0], dj + t.soff[1], dk + t.soff[2]), d0 = fab_idx(db, di, dj, dk);
-    for (int n = 0; n < ncomp; ++n) dst[d0 + (dcomp + n) * db.cs] = src[s0 + (scomp + n) * sb.cs];
+    cell(tags[find_tag(tags, ntags, g, hints)]);
 }
 
 // push_ghosts() on a one-box level addressed through its buffer resource: a
