@@ -692,11 +692,9 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
             double rn[3];
             residual(false, rn);
             // coarse correction: one V-cycle from zero on the composite residual
-            HIPCHK(hipMemsetAsync(Ec, 0, c.Ec->bytes, s));
-            bxmg_solve_info ci;
-            const bxmg_status st = bxmg_mlmg_solve(ctx, &Pc, c.Ec, c.Rc, nullptr, &ci);
-            if (st != BXMG_OK) throw std::runtime_error(bxmg_last_error());
-            info->levels = ci.levels + 1;
+            int nlev = 0;
+            chk(vcycle_from_zero(ctx, Pc, c.Ec, c.Rc, &nlev));
+            info->levels = nlev + 1;
             hipLaunchKernelGGL(comp::k_coarse_update, c.g_coarse, dim3(comp::kCB), 0, s, g, (const int*)c.cmap.p, Uc,
                                (const double*)Ec);
             if (nfb)

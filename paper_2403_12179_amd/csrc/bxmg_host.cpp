@@ -1414,6 +1414,42 @@ static bxmg_status solve_impl(bxmg_ctx ctx, const bxmg_solve_params* params, bxm
     return (bxmg_status)info->status;
 }
 
+}  // extern "C"
+
+// One FP64 V-cycle from a zero guess: phi = V(rhs), no stop test, no norms
+// (the composite solve's coarse correction).
+bxmg_status vcycle_from_zero(bxmg_ctx ctx, const bxmg_solve_params& P, bxmg_multifab phi, bxmg_multifab rhs,
+                             int* levels) {
+    const bxmg_ba_s* ba = phi->ba;
+    bxmg_status st;
+    if ((st = check_solve_mf(phi, ba, "phi")) != BXMG_OK || (st = check_solve_mf(rhs, ba, "rhs")) != BXMG_OK) return st;
+    if (!covers_domain(ba)) return fail(BXMG_EINVAL, "vcycle: the BoxArray must cover its domain");
+    const double h = (P.dx > 0) ? P.dx : 1.0 / ba->dom.n(0);
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        st = BXMG_OK;
+        Hier* H = get_hier(ctx, ba, 0, false, h, &st, ctx->merge != 0, 0.0);
+        if (!H) return st;
+        if (levels) *levels = (int)H->L.size();
+        Run R{H, ctx->stream, P.nu1, P.nu2, P.prolong, P.bottom_rtol};
+        R.prof = &ctx->prof;
+        R.lds_coarse = ctx->lds_coarse != 0;
+        const Level& L0 = *H->L[0];
+        double* u = H->u64[0]->p;
+        HIPCHK(launch_fab_to_rb(R.s, L0.view_grid(), (const double*)rhs->data, rhs->d_fboxes.p, H->f64[0]->p, false));
+        HIPCHK(launch_zero<double>(R.s, u, L0.nelem));  // cells and ghosts: the zero guess's ghosts are zero too
+        vcycle<double>(R, 0);
+        HIPCHK(launch_rb_to_fab(R.s, L0.view_grid(), u, (double*)phi->data, phi->d_fboxes.p));
+        ctx->prof.harvest();
+    } catch (HipError& e) {
+        return fail(BXMG_EDEVICE, std::string("vcycle: ") + e.where + ": " + hipGetErrorString(e.e));
+    }
+    return BXMG_OK;
+}
+
+extern "C" {
+
 bxmg_status bxmg_mlmg_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi, bxmg_multifab rhs,
                             bxmg_multifab beta, bxmg_solve_info* info) {
     return solve_impl(ctx, params, phi, rhs, beta, info, 0.0, nullptr);

@@ -759,3 +759,10 @@ inline bool bottom_fits(const Box& dom) {
     const long long grown = (long long)(dom.n(0) + 2) * (dom.n(1) + 2) * (dom.n(2) + 2);
     return dom.cells() <= kMaxBottomCells && grown <= kBottomGrown;
 }
+
+// One FP64 V-cycle of the Poisson operator from a zero guess, phi = V(rhs)
+// (constant coefficient, no stop test, no norms): the composite solve's
+// coarse correction.  phi and rhs as for bxmg_mlmg_solve; asynchronous on the
+// context's stream; *levels (if not NULL) gets the hierarchy's depth.
+bxmg_status vcycle_from_zero(bxmg_ctx ctx, const bxmg_solve_params& P, bxmg_multifab phi, bxmg_multifab rhs,
+                             int* levels);
