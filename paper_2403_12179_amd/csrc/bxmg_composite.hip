@@ -12,7 +12,7 @@
 //    (with the mixed term) taken at the ghost's offset (s_a, s_b) h0/4,
 //    s = +1 on the upper half of C, -1 on the lower.
 //  * Fine operator: the 7-point one with those ghosts (ghosts between fine
-//    boxes by FillBoundary).
+//    boxes copied from the neighbouring box).
 //  * Coarse operator at an uncovered cell: (sum of the 6 outward gradients)
 //    / h0; across a face against a covered cell the gradient is the mean of
 //    the 4 fine gradients (u_i - g_i) / h1 through it, so the coarse flux is
@@ -28,13 +28,18 @@
 // caller's coarse data is ParallelCopy'd in and out), so any coarse cell is
 // one address computation away; a dense int map over the coarse cells holds
 // the fine box that covers each one, or -1 - (mask of covered face
-// neighbours).  The fine level is the caller's MultiFabs, or, when the fine
-// boxes tile one rectangle, one merged box (ParallelCopy in and out) with no
-// ghosts between boxes; the coarse-fine ghost cells are listed once per
-// layout.
-// Fine boxes must be unions of whole coarse cells (even lower, odd upper
-// corners) and lie at least 2 coarse cells inside the domain, so that every
-// coarse cell a ghost or an interpolation reads is a domain cell.
+// neighbours).  The fine level lives in colour-split storage of its own:
+// every fine box grown by one ghost layer, cell (i, j, k) of colour
+// c = (i + j + k) & 1 in colour block c at row ((k - glo_z) G_y + (j - glo_y))
+// and slot (i - glo_x) >> 1, so a colour sweep streams the other colour,
+// its own right-hand side and its own writes.  When the fine boxes tile one
+// rectangle the fine level is that one box (no ghosts between boxes);
+// otherwise ghosts between fine boxes are copied from a per-layout list.
+// The caller's fine fields are converted in (right-hand side) and out
+// (solution) once per solve; the coarse-fine ghost cells are listed once
+// per layout.  Fine boxes must be unions of whole coarse cells (even lower,
+// odd upper corners) and lie at least 2 coarse cells inside the domain, so
+// that every coarse cell a ghost or an interpolation reads is a domain cell.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -62,9 +67,25 @@ struct CGeo {
     double ih0sq;  // 1 / h0^2
 };
 
+// A fine box in colour-split storage (grown by 1): colour block c of the
+// box starts at base + c * cs; rows of H slots.
+struct FRB {
+    int lo[3], hi[3];  // valid cells
+    int glo[3];        // lo - 1
+    int G[3];          // edges + 2
+    int H;             // slots per colour row, (G_x + 1) / 2
+    int pad;
+    long long base, cs;
+};
+
+__host__ __device__ __forceinline__ long long frb_at(const FRB& b, int i, int j, int k) {
+    const int c = (i + j + k) & 1;
+    return b.base + c * b.cs + (long long)(((k - b.glo[2]) * b.G[1] + (j - b.glo[1])) * b.H + ((i - b.glo[0]) >> 1));
+}
+
 // Coverage map entry of a coarse cell: >= 0 the fine box covering it;
 // otherwise -1 - mask, bit 2 d + side of mask set when the face neighbour
-// across (d, side) is covered.
+// across (d, side) is covered, bit 6 when the cell lies on a domain face.
 __device__ __forceinline__ int cq(const CGeo& g, int I, int J, int K) {
     return (I - g.dlo[0]) + g.n[0] * ((J - g.dlo[1]) + g.n[1] * (K - g.dlo[2]));
 }
@@ -111,23 +132,25 @@ __device__ __forceinline__ void norm_add(double rv, double& mx, double& s2, doub
     s2 = s2 + rv * rv;
 }
 
-__device__ __forceinline__ double mean8(const double* __restrict__ x, const FBox& B, int i, int j, int k) {
-    const long long c = fidx(B, i, j, k), sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
-    return (((x[c] + x[c + 1]) + (x[c + sy] + x[c + sy + 1])) +
-            ((x[c + sz] + x[c + sz + 1]) + (x[c + sz + sy] + x[c + sz + sy + 1]))) * 0.125;
+// mean of the 8 children (2I.., 2J.., 2K..) of a coarse cell
+__device__ __forceinline__ double mean8(const double* __restrict__ x, const FRB& B, int i, int j, int k) {
+    return (((x[frb_at(B, i, j, k)] + x[frb_at(B, i + 1, j, k)]) +
+             (x[frb_at(B, i, j + 1, k)] + x[frb_at(B, i + 1, j + 1, k)])) +
+            ((x[frb_at(B, i, j, k + 1)] + x[frb_at(B, i + 1, j, k + 1)]) +
+             (x[frb_at(B, i, j + 1, k + 1)] + x[frb_at(B, i + 1, j + 1, k + 1)]))) * 0.125;
 }
 
 // Coarse-fine ghosts.  One entry per ghost cell: x = box | d << 24 | side << 26
 // (the ghost lies beyond face (d, side) of its box), y, z, w = its fine index.
 __global__ void __launch_bounds__(kCB) k_cf_ghost(const int4* __restrict__ list, int n, CGeo g,
-                                                  const double* __restrict__ Uc, const FBox* __restrict__ fu,
+                                                  const double* __restrict__ Uc, const FRB* __restrict__ fb,
                                                   double* __restrict__ uf) {
     const int q = blockIdx.x * kCB + threadIdx.x;
     if (q >= n) return;
     const int4 r = list[q];
     const int b = r.x & 0xffffff, d = (r.x >> 24) & 3, side = (r.x >> 26) & 1;
     const int gx[3] = {r.y, r.z, r.w};
-    const FBox B = fu[b];
+    const FRB B = fb[b];
     const int step = side ? -1 : 1;  // from the ghost into its box
     int i1[3] = {gx[0], gx[1], gx[2]}, i2[3] = {gx[0], gx[1], gx[2]};
     i1[d] += step;
@@ -146,115 +169,198 @@ __global__ void __launch_bounds__(kCB) k_cf_ghost(const int4* __restrict__ list,
     const double qb = ((U0p + U0m) - 2.0 * UC) * (1.0 / 32.0);
     const double xab = ((U(1, 1) - U(1, -1)) - (U(-1, 1) - U(-1, -1))) * (1.0 / 64.0) * (sa * sb);
     const double Ut = UC + ((da + db) + (qa + qb)) + xab;
-    const double u1 = uf[fidx(B, i1[0], i1[1], i1[2])], u2 = uf[fidx(B, i2[0], i2[1], i2[2])];
-    uf[fidx(B, gx[0], gx[1], gx[2])] = ((8.0 / 15.0) * Ut + (2.0 / 3.0) * u1) - (1.0 / 5.0) * u2;
+    const double u1 = uf[frb_at(B, i1[0], i1[1], i1[2])], u2 = uf[frb_at(B, i2[0], i2[1], i2[2])];
+    uf[frb_at(B, gx[0], gx[1], gx[2])] = ((8.0 / 15.0) * Ut + (2.0 / 3.0) * u1) - (1.0 / 5.0) * u2;
 }
 
-// Fine-box kernels: grid (plane blocks, plane groups of kKZ, box); a thread
-// takes one (i, j) of its box's planes (or half-row position, for the
-// sweeps) and walks kKZ planes.
+// Fine-box kernels: grid (plane blocks, plane groups, box); a thread takes
+// one slot of a row of its box (the two cells sharing that slot, or the
+// one of the swept colour) and walks the group's planes.
+__device__ __forceinline__ int frb_slots(const FRB& B) { return ((B.hi[0] - B.glo[0]) >> 1) + 1; }
 
 // One colour of red-black Gauss-Seidel on the fine boxes (ghosts current):
 // u = (sum of the 6 neighbours - h1^2 f) / 6 at the cells of that colour.
-__global__ void __launch_bounds__(kCB) k_fine_gs(CGeo g, const FBox* __restrict__ fu, const FBox* __restrict__ ff,
-                                                 double* __restrict__ u, const double* __restrict__ f, int colour) {
+__global__ void __launch_bounds__(kCB) k_fine_gs(CGeo g, const FRB* __restrict__ fb, double* __restrict__ u,
+                                                 const double* __restrict__ f, int colour) {
     const uint3 bk = xcd_block();
-    const FBox B = fu[bk.z], F = ff[bk.z];
-    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1;
-    const int nxh = (nx + 1) >> 1;
+    const FRB B = fb[bk.z];
+    const int ns = frb_slots(B), ny = B.hi[1] - B.lo[1] + 1;
     const int t = bk.x * kCB + threadIdx.x;
-    if (t >= nxh * ny) return;
-    const int tx = t % nxh, j = B.lo[1] + t / nxh;
+    if (t >= ns * ny) return;
+    const int ts = t % ns, j = B.lo[1] + t / ns;
     const int k0 = B.lo[2] + bk.y * kKZs, k1 = min(k0 + kKZs - 1, B.hi[2]);
-    const long long sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
+    const long long sy = B.H, sz = (long long)B.H * B.G[1];
     const double h2 = g.h1 * g.h1;
     for (int k = k0; k <= k1; ++k) {
-        const int i = B.lo[0] + 2 * tx + ((B.lo[0] + j + k + colour) & 1);
-        if (i > B.hi[0]) continue;
-        const long long c = fidx(B, i, j, k);
-        const double su = ((u[c - 1] + u[c + 1]) + (u[c - sy] + u[c + sy])) + (u[c - sz] + u[c + sz]);
-        u[c] = (su - h2 * f[fidx(F, i, j, k)]) / 6.0;
+        const int i = B.glo[0] + 2 * ts + ((colour + B.glo[0] + j + k) & 1);
+        if (i < B.lo[0] || i > B.hi[0]) continue;
+        const long long row = (long long)((k - B.glo[2]) * B.G[1] + (j - B.glo[1])) * B.H;
+        const long long o = B.base + (1 - colour) * B.cs + row;  // other colour, this row
+        const long long c = B.base + colour * B.cs + row + ((i - B.glo[0]) >> 1);
+        const long long m = o + ((i - B.glo[0]) >> 1);
+        const double xm = u[o + ((i - 1 - B.glo[0]) >> 1)], xp = u[o + ((i + 1 - B.glo[0]) >> 1)];
+        const double su = ((xm + xp) + (u[m - sy] + u[m + sy])) + (u[m - sz] + u[m + sz]);
+        u[c] = (su - h2 * f[c]) / 6.0;
     }
+}
+
+// The sum of the 6 neighbours of fine cell (i, j, k).
+__device__ __forceinline__ double nsum(const double* __restrict__ u, const FRB& B, int i, int j, int k) {
+    const int c = (i + j + k) & 1;
+    const long long row = (long long)((k - B.glo[2]) * B.G[1] + (j - B.glo[1])) * B.H;
+    const long long o = B.base + (1 - c) * B.cs + row;
+    const long long m = o + ((i - B.glo[0]) >> 1);
+    const long long sy = B.H, sz = (long long)B.H * B.G[1];
+    const double xm = u[o + ((i - 1 - B.glo[0]) >> 1)], xp = u[o + ((i + 1 - B.glo[0]) >> 1)];
+    return ((xm + xp) + (u[m - sy] + u[m + sy])) + (u[m - sz] + u[m + sz]);
 }
 
 // Fine residual r = f - L u on the valid cells (or the norms of f only),
 // with per-block norms (max, sum of squares, non-finite count).
-__global__ void __launch_bounds__(kCB) k_fine_resid(CGeo g, const FBox* __restrict__ fu, const FBox* __restrict__ ff,
-                                                    const FBox* __restrict__ fr, const double* __restrict__ u,
+__global__ void __launch_bounds__(kCB) k_fine_resid(CGeo g, const FRB* __restrict__ fb, const double* __restrict__ u,
                                                     const double* __restrict__ f, double* __restrict__ r, int fonly,
                                                     double* __restrict__ partials) {
     const uint3 bk = xcd_block();
-    const FBox B = fu[bk.z], F = ff[bk.z], R = fr[bk.z];
-    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1;
+    const FRB B = fb[bk.z];
+    const int ns = frb_slots(B), ny = B.hi[1] - B.lo[1] + 1;
     const int t = bk.x * kCB + threadIdx.x;
     double mx = 0.0, s2 = 0.0, bad = 0.0;
-    if (t < nx * ny) {
-        const int i = B.lo[0] + t % nx, j = B.lo[1] + t / nx;
+    if (t < ns * ny) {
+        const int ts = t % ns, j = B.lo[1] + t / ns;
         const int k0 = B.lo[2] + bk.y * kKZ, k1 = min(k0 + kKZ - 1, B.hi[2]);
-        const long long sy = B.G[0], sz = (long long)B.G[0] * B.G[1];
         const double ih2 = 1.0 / (g.h1 * g.h1);
-        for (int k = k0; k <= k1; ++k) {
-            double rv = f[fidx(F, i, j, k)];
-            if (!fonly) {
-                const long long c = fidx(B, i, j, k);
-                const double su = ((u[c - 1] + u[c + 1]) + (u[c - sy] + u[c + sy])) + (u[c - sz] + u[c + sz]);
-                rv = rv - (su - 6.0 * u[c]) * ih2;
-                r[fidx(R, i, j, k)] = rv;
+        for (int k = k0; k <= k1; ++k)
+            for (int e = 0; e < 2; ++e) {
+                const int i = B.glo[0] + 2 * ts + e;
+                if (i < B.lo[0] || i > B.hi[0]) continue;
+                const long long c = frb_at(B, i, j, k);
+                double rv = f[c];
+                if (!fonly) {
+                    rv = rv - (nsum(u, B, i, j, k) - 6.0 * u[c]) * ih2;
+                    r[c] = rv;
+                }
+                norm_add(rv, mx, s2, bad);
             }
-            norm_add(rv, mx, s2, bad);
-        }
     }
     const int blk = (bk.z * gridDim.y + bk.y) * gridDim.x + bk.x;
     block_norms(mx, s2, bad, partials + 3 * (long long)blk);
 }
 
 // Fine cells += trilinear interpolation of the coarse correction Ec.
-__global__ void __launch_bounds__(kCB) k_fine_prolong(CGeo g, const FBox* __restrict__ fu, double* __restrict__ u,
+__global__ void __launch_bounds__(kCB) k_fine_prolong(CGeo g, const FRB* __restrict__ fb, double* __restrict__ u,
                                                       const double* __restrict__ Ec) {
     const uint3 bk = xcd_block();
-    const FBox B = fu[bk.z];
-    const int nx = B.hi[0] - B.lo[0] + 1, ny = B.hi[1] - B.lo[1] + 1;
+    const FRB B = fb[bk.z];
+    const int ns = frb_slots(B), ny = B.hi[1] - B.lo[1] + 1;
     const int t = bk.x * kCB + threadIdx.x;
-    if (t >= nx * ny) return;
-    const int i = B.lo[0] + t % nx, j = B.lo[1] + t / nx;
+    if (t >= ns * ny) return;
+    const int ts = t % ns, j = B.lo[1] + t / ns;
     const int k0 = B.lo[2] + bk.y * kKZs, k1 = min(k0 + kKZs - 1, B.hi[2]);
-    const int I = i >> 1, J = j >> 1;
-    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1;
+    const int J = j >> 1, sj = (j & 1) ? 1 : -1;
     const long long sy = g.cb.G[0], sz = (long long)g.cb.G[0] * g.cb.G[1];
     for (int k = k0; k <= k1; ++k) {
         const int K = k >> 1, sk = (k & 1) ? 1 : -1;
-        const long long e = fidx(g.cb, I, J, K), ex = si, ey = sj * sy, ez = sk * sz;
-        const double c000 = Ec[e], c100 = Ec[e + ex], c010 = Ec[e + ey], c001 = Ec[e + ez];
-        const double c110 = Ec[e + ex + ey], c101 = Ec[e + ex + ez], c011 = Ec[e + ey + ez];
-        const double c111 = Ec[e + ex + ey + ez];
-        const double v = (((27.0 * c000 + 9.0 * ((c100 + c010) + c001)) + 3.0 * ((c110 + c101) + c011)) + c111) *
-                         (1.0 / 64.0);
-        const long long c = fidx(B, i, j, k);
-        u[c] = u[c] + v;
+        for (int e = 0; e < 2; ++e) {
+            const int i = B.glo[0] + 2 * ts + e;
+            if (i < B.lo[0] || i > B.hi[0]) continue;
+            const int I = i >> 1, si = (i & 1) ? 1 : -1;
+            const long long q = fidx(g.cb, I, J, K), ex = si, ey = sj * sy, ez = sk * sz;
+            const double c000 = Ec[q], c100 = Ec[q + ex], c010 = Ec[q + ey], c001 = Ec[q + ez];
+            const double c110 = Ec[q + ex + ey], c101 = Ec[q + ex + ez], c011 = Ec[q + ey + ez];
+            const double c111 = Ec[q + ex + ey + ez];
+            const double v = (((27.0 * c000 + 9.0 * ((c100 + c010) + c001)) + 3.0 * ((c110 + c101) + c011)) + c111) *
+                             (1.0 / 64.0);
+            const long long c = frb_at(B, i, j, k);
+            u[c] = u[c] + v;
+        }
     }
 }
 
-// Component 0 of every fine box, valid and ghost cells, := 0.
-__global__ void __launch_bounds__(kCB) k_fine_zero(const FBox* __restrict__ fu, double* __restrict__ u) {
+// Caller layout <-> colour-split storage: grid (plane blocks, plane groups,
+// caller box); caller box b lies in storage box map[b].
+template <bool TO_FRB>
+__global__ void __launch_bounds__(kCB) k_fab_frb(const FBox* __restrict__ fab, double* __restrict__ x,
+                                                 const FRB* __restrict__ fb, const int* __restrict__ map,
+                                                 double* __restrict__ y) {
     const uint3 bk = xcd_block();
-    const FBox B = fu[bk.z];
-    const int P = B.G[0] * B.G[1];
+    const FBox A = fab[bk.z];
+    const FRB B = fb[map[bk.z]];
+    const int nx = A.hi[0] - A.lo[0] + 1, ny = A.hi[1] - A.lo[1] + 1;
     const int t = bk.x * kCB + threadIdx.x;
-    if (t >= P) return;
-    for (int k = bk.y * kKZ; k < min(bk.y * kKZ + kKZ, B.G[2]); ++k) u[B.base + (long long)k * P + t] = 0.0;
+    if (t >= nx * ny) return;
+    const int i = A.lo[0] + t % nx, j = A.lo[1] + t / nx;
+    const int k0 = A.lo[2] + bk.y * kKZ, k1 = min(k0 + kKZ - 1, A.hi[2]);
+    for (int k = k0; k <= k1; ++k) {
+        if constexpr (TO_FRB) y[frb_at(B, i, j, k)] = x[fidx(A, i, j, k)];
+        else x[fidx(A, i, j, k)] = y[frb_at(B, i, j, k)];
+    }
 }
 
 // Coarse kernels: grid (plane blocks, plane groups of kKZ) over the domain.
 
-// Composite residual on the coarse level: uncovered cells f - Lc u (norms
-// taken there), covered cells the mean of the fine residuals below them
-// (fonly: the norms of f at the uncovered cells, Rc untouched).  The fine
-// ghosts of the current state must be in place (the flux-matched faces
-// read them).
+// The composite operator at an uncovered coarse cell with a covered face
+// neighbour or on a domain face: (sum of the 6 outward gradients) / h0,
+// a face against a covered cell taking the mean of the 4 fine gradients
+// through it (from the fine ghosts, which must be current).
+__device__ __forceinline__ double coarse_op_special(const CGeo& g, const int* __restrict__ cmap,
+                                                    const double* __restrict__ Uc, const FRB* __restrict__ fb,
+                                                    const double* __restrict__ uf, int I, int J, int K, int mask) {
+    const int q = cq(g, I, J, K);
+    const long long c = fidx(g.cb, I, J, K);
+    const long long st[3] = {1, g.cb.G[0], (long long)g.cb.G[0] * g.cb.G[1]};
+    const int mst[3] = {1, g.n[0], g.n[0] * g.n[1]};
+    const double UI = Uc[c];
+    const int X[3] = {I, J, K};
+    double gr[6];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int nbd = X[d] + (side ? 1 : -1);
+            double v;
+            if ((mask >> (2 * d + side)) & 1) {
+                // the 4 fine cells of the covered neighbour against the face
+                int nb[3] = {X[0], X[1], X[2]};
+                nb[d] = nbd;
+                const FRB B = fb[cmap[q + (side ? mst[d] : -mst[d])]];
+                const int ta = d == 2 ? 0 : d + 1, tb = d == 0 ? 2 : d - 1;
+                double a[2][2];
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        int fi[3];
+                        fi[d] = 2 * nb[d] + (side ? 0 : 1);
+                        fi[ta] = 2 * nb[ta] + p;
+                        fi[tb] = 2 * nb[tb] + s;
+                        int gc[3] = {fi[0], fi[1], fi[2]};
+                        gc[d] += side ? -1 : 1;
+                        a[s][p] = (uf[frb_at(B, fi[0], fi[1], fi[2])] - uf[frb_at(B, gc[0], gc[1], gc[2])]) / g.h1;
+                    }
+                v = ((a[0][0] + a[0][1]) + (a[1][0] + a[1][1])) * 0.25;
+            } else if (nbd < g.dlo[d] || nbd >= g.dlo[d] + g.n[d]) {
+                if (!g.per[d]) {
+                    v = (-UI - UI) / g.h0;
+                } else {
+                    const long long w = (long long)(side ? -(g.n[d] - 1) : (g.n[d] - 1)) * st[d];
+                    v = (Uc[c + w] - UI) / g.h0;
+                }
+            } else {
+                v = (Uc[c + (side ? st[d] : -st[d])] - UI) / g.h0;
+            }
+            gr[2 * d + side] = v;
+        }
+    return (((gr[0] + gr[1]) + (gr[2] + gr[3])) + (gr[4] + gr[5])) / g.h0;
+}
+
+// Composite residual on the coarse level, common cells: covered cells take
+// the mean of the fine residuals below them, uncovered interior cells with
+// no covered neighbour f - (7-point operator) (norms taken there); the other
+// uncovered cells (map entries below -1) are k_coarse_resid_special's.
+// fonly: the norms of f only, Rc untouched.
 __global__ void __launch_bounds__(kCB) k_coarse_resid(CGeo g, const int* __restrict__ cmap,
                                                       const double* __restrict__ Uc, const double* __restrict__ Fc,
-                                                      double* __restrict__ Rc, const FBox* __restrict__ fu,
-                                                      const double* __restrict__ uf, const FBox* __restrict__ fr,
+                                                      double* __restrict__ Rc, const FRB* __restrict__ fb,
                                                       const double* __restrict__ rf, int fonly,
                                                       double* __restrict__ partials) {
     const uint3 bk = xcd_block();
@@ -263,80 +369,53 @@ __global__ void __launch_bounds__(kCB) k_coarse_resid(CGeo g, const int* __restr
     if (t < g.n[0] * g.n[1]) {
         const int I = g.dlo[0] + t % g.n[0], J = g.dlo[1] + t / g.n[0];
         const int K0 = g.dlo[2] + bk.y * kKZ, K1 = min(K0 + kKZ - 1, g.dlo[2] + g.n[2] - 1);
-        const long long st[3] = {1, g.cb.G[0], (long long)g.cb.G[0] * g.cb.G[1]};
-        const int mst[3] = {1, g.n[0], g.n[0] * g.n[1]};
+        const long long sy = g.cb.G[0], sz = (long long)g.cb.G[0] * g.cb.G[1];
         for (int K = K0; K <= K1; ++K) {
-            const int q = cq(g, I, J, K);
+            const int code = cmap[cq(g, I, J, K)];
             const long long c = fidx(g.cb, I, J, K);
-            // every load of the common case issued before the first branch
-            // (the ghost layer keeps the neighbour loads of boundary cells in
-            // bounds)
-            const int code = cmap[q];
-            double rv = Fc[c];
-            const double UI = Uc[c];
-            const double uxm = Uc[c - 1], uxp = Uc[c + 1], uym = Uc[c - st[1]], uyp = Uc[c + st[1]];
-            const double uzm = Uc[c - st[2]], uzp = Uc[c + st[2]];
             if (code >= 0) {
-                if (!fonly) Rc[c] = mean8(rf, fr[code], 2 * I, 2 * J, 2 * K);
+                if (!fonly) Rc[c] = mean8(rf, fb[code], 2 * I, 2 * J, 2 * K);
                 continue;
             }
-            const bool inner = code == -1 && I > g.dlo[0] && I < g.dlo[0] + g.n[0] - 1 && J > g.dlo[1] &&
-                               J < g.dlo[1] + g.n[1] - 1 && K > g.dlo[2] && K < g.dlo[2] + g.n[2] - 1;
-            if (!fonly && inner) {
-                // no covered neighbour, no domain face: the 7-point operator
+            if (code != -1) continue;
+            double rv = Fc[c];
+            if (!fonly) {
+                const double UI = Uc[c];
+                const double uxm = Uc[c - 1], uxp = Uc[c + 1], uym = Uc[c - sy], uyp = Uc[c + sy];
+                const double uzm = Uc[c - sz], uzp = Uc[c + sz];
                 rv = rv - ((((uxm - UI) + (uxp - UI)) + ((uym - UI) + (uyp - UI))) + ((uzm - UI) + (uzp - UI))) *
                               g.ih0sq;
-                Rc[c] = rv;
-            } else if (!fonly) {
-                const int mask = -1 - code;
-                const int X[3] = {I, J, K};
-                double gr[6];
-#pragma unroll
-                for (int d = 0; d < 3; ++d)
-#pragma unroll
-                    for (int side = 0; side < 2; ++side) {
-                        const int nbd = X[d] + (side ? 1 : -1);
-                        double v;
-                        if ((mask >> (2 * d + side)) & 1) {
-                            // the 4 fine cells of the covered neighbour against the face
-                            int nb[3] = {X[0], X[1], X[2]};
-                            nb[d] = nbd;
-                            const FBox B = fu[cmap[q + (side ? mst[d] : -mst[d])]];
-                            const int ta = d == 2 ? 0 : d + 1, tb = d == 0 ? 2 : d - 1;
-                            double a[2][2];
-#pragma unroll
-                            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                                for (int p = 0; p < 2; ++p) {
-                                    int fi[3];
-                                    fi[d] = 2 * nb[d] + (side ? 0 : 1);
-                                    fi[ta] = 2 * nb[ta] + p;
-                                    fi[tb] = 2 * nb[tb] + s;
-                                    const long long o = fidx(B, fi[0], fi[1], fi[2]);
-                                    const long long gs = side ? -1 : 1;
-                                    const long long step = d == 0 ? gs : (d == 1 ? gs * B.G[0] : gs * B.G[0] * B.G[1]);
-                                    a[s][p] = (uf[o] - uf[o + step]) / g.h1;
-                                }
-                            v = ((a[0][0] + a[0][1]) + (a[1][0] + a[1][1])) * 0.25;
-                        } else if (nbd < g.dlo[d] || nbd >= g.dlo[d] + g.n[d]) {
-                            if (!g.per[d]) {
-                                v = (-UI - UI) / g.h0;
-                            } else {
-                                const long long w = (long long)(side ? -(g.n[d] - 1) : (g.n[d] - 1)) * st[d];
-                                v = (Uc[c + w] - UI) / g.h0;
-                            }
-                        } else {
-                            v = (Uc[c + (side ? st[d] : -st[d])] - UI) / g.h0;
-                        }
-                        gr[2 * d + side] = v;
-                    }
-                rv = rv - (((gr[0] + gr[1]) + (gr[2] + gr[3])) + (gr[4] + gr[5])) / g.h0;
                 Rc[c] = rv;
             }
             norm_add(rv, mx, s2, bad);
         }
     }
     block_norms(mx, s2, bad, partials + 3 * (long long)(bk.y * gridDim.x + bk.x));
+}
+
+// Composite residual at the listed uncovered cells that have a covered face
+// neighbour or lie on a domain face (entry: I, J, K, map entry), norms
+// taken there.
+__global__ void __launch_bounds__(kCB) k_coarse_resid_special(CGeo g, const int4* __restrict__ list, int n,
+                                                              const int* __restrict__ cmap,
+                                                              const double* __restrict__ Uc,
+                                                              const double* __restrict__ Fc, double* __restrict__ Rc,
+                                                              const FRB* __restrict__ fb,
+                                                              const double* __restrict__ uf, int fonly,
+                                                              double* __restrict__ partials) {
+    const int q = blockIdx.x * kCB + threadIdx.x;
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    if (q < n) {
+        const int4 e = list[q];
+        const long long c = fidx(g.cb, e.x, e.y, e.z);
+        double rv = Fc[c];
+        if (!fonly) {
+            rv = rv - coarse_op_special(g, cmap, Uc, fb, uf, e.x, e.y, e.z, (-1 - e.w) & 63);
+            Rc[c] = rv;
+        }
+        norm_add(rv, mx, s2, bad);
+    }
+    block_norms(mx, s2, bad, partials + 3 * (long long)blockIdx.x);
 }
 
 // Uc += Ec at the uncovered coarse cells.
@@ -356,10 +435,10 @@ __global__ void __launch_bounds__(kCB) k_coarse_update(CGeo g, const int* __rest
 
 // Covered coarse cells := the mean of their 8 children; grid (plane blocks,
 // plane groups, fine box) over each fine box's coarse cells.
-__global__ void __launch_bounds__(kCB) k_coarse_sync(CGeo g, double* __restrict__ Uc, const FBox* __restrict__ fu,
+__global__ void __launch_bounds__(kCB) k_coarse_sync(CGeo g, double* __restrict__ Uc, const FRB* __restrict__ fb,
                                                      const double* __restrict__ uf) {
     const uint3 bk = xcd_block();
-    const FBox B = fu[bk.z];
+    const FRB B = fb[bk.z];
     const int cx = (B.hi[0] - B.lo[0] + 1) >> 1, cy = (B.hi[1] - B.lo[1] + 1) >> 1, cz = (B.hi[2] - B.lo[2] + 1) >> 1;
     const int t = bk.x * kCB + threadIdx.x;
     if (t >= cx * cy) return;
@@ -377,32 +456,37 @@ struct Comp {
     double h0 = 0.0;
     bxmg_boxarray one = nullptr;                                           // one box over the coarse domain
     bxmg_multifab Uc = nullptr, Fc = nullptr, Rc = nullptr, Ec = nullptr;  // over `one`, 1 ghost
-    bxmg_multifab Rf = nullptr;                                            // fine residual
-    // Merged fine level: when the fine boxes tile one rectangle, the fine
-    // level runs as that one box (solution with 1 ghost, right-hand side),
-    // loaded and returned by ParallelCopy; there are then no ghosts between
-    // fine boxes and every ghost is a coarse-fine one.
-    bxmg_boxarray fone = nullptr;
-    bxmg_multifab Uf = nullptr, Ff = nullptr;
     CGeo geo{};
+    // the fine level in colour-split storage: solution, right-hand side,
+    // residual (one layout), its boxes, and the caller box -> storage box map
+    DevBuf<double> uf, ff, rf;
+    DevBuf<FRB> frb;
+    DevBuf<int> fmap;
+    DevBuf<GhostCopy> fx;  // ghosts between fine boxes
+    long long nfx = 0;
+    long long fslab = 0;  // elements per fine field
     DevBuf<int> cmap;
     DevBuf<int4> ghosts;
     int nghosts = 0;
+    DevBuf<int4> special;  // uncovered coarse cells next to a covered one or on a domain face
+    int nspecial = 0;
     int nfine = 0;
-    dim3 g_fine, g_fine_s, g_fine_gs, g_sync, g_coarse;  // launch grids
+    dim3 g_fine, g_fine_s, g_sync, g_coarse, g_conv;  // launch grids
     int nparts_fine = 0, nparts = 0;
     DevBuf<double> part, fn;
     double* h_norm = nullptr;  // pinned: the norms read back
     ~Comp() {
-        for (bxmg_multifab m : {Uc, Fc, Rc, Ec, Rf, Uf, Ff})
+        for (bxmg_multifab m : {Uc, Fc, Rc, Ec})
             if (m) bxmg_multifab_release(m);
         if (one) bxmg_boxarray_release(one);
-        if (fone) bxmg_boxarray_release(fone);
         const hipStream_t s = ctx ? ctx->stream : nullptr;
+        for (DevBuf<double>* b : {&uf, &ff, &rf, &part, &fn}) b->release_async(s);
+        frb.release_async(s);
+        fmap.release_async(s);
+        fx.release_async(s);
         cmap.release_async(s);
         ghosts.release_async(s);
-        part.release_async(s);
-        fn.release_async(s);
+        special.release_async(s);
         if (h_norm) {
             (void)hipStreamSynchronize(s);
             (void)hipHostFree(h_norm);
@@ -413,7 +497,8 @@ struct Comp {
 // Checks the fine layout against the coarse domain: the fine domain is the
 // coarse one refined by 2 with the same boundaries, every fine box is a union
 // of whole coarse cells and lies 2 coarse cells (4 fine) inside every domain
-// face; index arithmetic stays in 32 bits.  Returns "" or the reason.
+// face; index arithmetic stays in 32 bits (ghost copies address a fine field
+// with 31-bit offsets).  Returns "" or the reason.
 static std::string layout_error(const bxmg_ba_s* cba, const bxmg_ba_s* fba) {
     for (int d = 0; d < 3; ++d) {
         if (fba->dom.lo[d] != 2 * cba->dom.lo[d] || fba->dom.hi[d] != 2 * cba->dom.hi[d] + 1)
@@ -423,14 +508,16 @@ static std::string layout_error(const bxmg_ba_s* cba, const bxmg_ba_s* fba) {
     const Box& D = cba->dom;
     if ((long long)(D.n(0) + 2) * (D.n(1) + 2) * (D.n(2) + 2) >= (1LL << 31)) return "coarse domain too large";
     if (fba->boxes.size() >= (1u << 24)) return "too many fine boxes";
+    long long total = 0;
     for (const Box& B : fba->boxes) {
         for (int d = 0; d < 3; ++d) {
             if ((B.lo[d] & 1) || !(B.hi[d] & 1)) return "fine boxes must be unions of whole coarse cells";
             if (B.lo[d] < fba->dom.lo[d] + 4 || B.hi[d] > fba->dom.hi[d] - 4)
                 return "fine boxes must lie 2 coarse cells inside the domain";
         }
-        if ((long long)(B.n(0) + 8) * (B.n(1) + 8) * (B.n(2) + 8) >= (1LL << 31)) return "fine box too large";
+        total += (long long)(B.n(0) + 3) * (B.n(1) + 2) * (B.n(2) + 2) + 128;
     }
+    if (total >= (1LL << 31) - 1) return "fine level too large";
     return "";
 }
 
@@ -454,38 +541,6 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
     c->Fc = alloc_mf(ctx, c->one, 1);
     c->Rc = alloc_mf(ctx, c->one, 1);
     c->Ec = alloc_mf(ctx, c->one, 1);
-    // the fine level: one merged box when the caller's fine boxes tile a
-    // rectangle (they are disjoint, so equal cell counts mean they tile it)
-    Box U = fba->boxes[0];
-    long long fcells = 0;
-    for (const Box& B : fba->boxes) {
-        fcells += B.cells();
-        for (int d = 0; d < 3; ++d) {
-            U.lo[d] = std::min(U.lo[d], B.lo[d]);
-            U.hi[d] = std::max(U.hi[d], B.hi[d]);
-        }
-    }
-    std::vector<Box> fb;  // the boxes the kernels run over
-    if (fcells == U.cells() && fba->boxes.size() > 1) {
-        const int ul[6] = {U.lo[0], U.lo[1], U.lo[2], U.hi[0], U.hi[1], U.hi[2]};
-        if (bxmg_define_boxarray_list(fba->dom.lo, fba->dom.hi, fba->bc, 1, ul, &c->fone) != BXMG_OK)
-            throw std::runtime_error(bxmg_last_error());
-        c->Uf = alloc_mf(ctx, c->fone, 1);
-        c->Ff = alloc_mf(ctx, c->fone, 0);
-        c->Rf = alloc_mf(ctx, c->fone, 0);
-        fb.push_back(U);
-    } else {
-        bxmg_boxarray fcopy = nullptr;
-        std::vector<int32_t> fl;
-        for (const Box& B : fba->boxes)
-            for (int v : {B.lo[0], B.lo[1], B.lo[2], B.hi[0], B.hi[1], B.hi[2]}) fl.push_back(v);
-        if (bxmg_define_boxarray_list(fba->dom.lo, fba->dom.hi, fba->bc, (int32_t)fba->boxes.size(), fl.data(),
-                                      &fcopy) != BXMG_OK)
-            throw std::runtime_error(bxmg_last_error());
-        c->Rf = alloc_mf(ctx, fcopy, 0);
-        bxmg_boxarray_release(fcopy);  // the MultiFab keeps its reference
-        fb = fba->boxes;
-    }
     CGeo& g = c->geo;
     g.cb = c->Uc->fboxes[0];
     for (int d = 0; d < 3; ++d) {
@@ -496,18 +551,51 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
     g.h0 = h0;
     g.h1 = h0 * 0.5;
     g.ih0sq = 1.0 / (h0 * h0);
+    // the fine boxes the kernels run over: one merged box when the caller's
+    // boxes tile a rectangle (they are disjoint, so equal cell counts mean
+    // they tile it), else the caller's boxes
+    Box U = fba->boxes[0];
+    long long fcells = 0;
+    for (const Box& B : fba->boxes) {
+        fcells += B.cells();
+        for (int d = 0; d < 3; ++d) {
+            U.lo[d] = std::min(U.lo[d], B.lo[d]);
+            U.hi[d] = std::max(U.hi[d], B.hi[d]);
+        }
+    }
+    const bool merged = fcells == U.cells();
+    const std::vector<Box> fb = merged ? std::vector<Box>{U} : fba->boxes;
+    std::vector<int> fmap(fba->boxes.size());
+    for (size_t b = 0; b < fmap.size(); ++b) fmap[b] = merged ? 0 : (int)b;
+    // colour-split storage of the fine boxes
+    std::vector<FRB> frb;
+    long long off = 0;
+    for (const Box& B : fb) {
+        FRB r{};
+        for (int d = 0; d < 3; ++d) {
+            r.lo[d] = B.lo[d];
+            r.hi[d] = B.hi[d];
+            r.glo[d] = B.lo[d] - 1;
+            r.G[d] = B.n(d) + 2;
+        }
+        r.H = (r.G[0] + 1) / 2;
+        r.cs = ((long long)r.H * r.G[1] * r.G[2] + 63) / 64 * 64;
+        r.base = off;
+        off += 2 * r.cs;
+        frb.push_back(r);
+    }
+    c->fslab = off;
+    c->nfine = (int)fb.size();
     // coverage map: covering fine box, or -1 - (mask of covered face neighbours)
     const long long nc = D.cells();
     std::vector<int> cmap((size_t)nc, -1);
     auto cidx = [&](int I, int J, int K) {
         return (size_t)(I - D.lo[0]) + (size_t)D.n(0) * ((size_t)(J - D.lo[1]) + (size_t)D.n(1) * (K - D.lo[2]));
     };
-    c->nfine = (int)fb.size();
-    int maxP = 1, maxPh = 1, maxnz = 1, maxPc = 1, maxnzc = 1;
+    int maxS = 1, maxnz = 1, maxPc = 1, maxnzc = 1;
     for (size_t b = 0; b < fb.size(); ++b) {
         const Box& B = fb[b];
-        maxP = std::max(maxP, B.n(0) * B.n(1));
-        maxPh = std::max(maxPh, ((B.n(0) + 1) / 2) * B.n(1));
+        maxS = std::max(maxS, (((B.hi[0] - (B.lo[0] - 1)) >> 1) + 1) * B.n(1));
         maxnz = std::max(maxnz, B.n(2));
         maxPc = std::max(maxPc, (B.n(0) / 2) * (B.n(1) / 2));
         maxnzc = std::max(maxnzc, B.n(2) / 2);
@@ -521,7 +609,7 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
                 for (int I = B.lo[0] >> 1; I <= B.hi[0] >> 1; ++I)
                     for (int d = 0; d < 3; ++d)
                         for (int side = 0; side < 2; ++side) {
-                            // the neighbour N across (d, side) of this covered cell sees it across (d, 1 - side)
+                            // the neighbour across (d, side) of this covered cell sees it across (d, 1 - side)
                             int x[3] = {I, J, K};
                             x[d] += side ? 1 : -1;
                             int& m = cmap[cidx(x[0], x[1], x[2])];
@@ -529,9 +617,24 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
                             const int mask = (-1 - m) | (1 << (2 * d + (1 - side)));
                             m = -1 - mask;
                         }
-    // coarse-fine ghosts: face ghosts of each fine box whose coarse cell no
-    // fine box covers (the others are fine cells, filled by FillBoundary)
+    // uncovered cells on a domain face are special too (bit 6 of the mask)
+    std::vector<int4> sl;
+    for (int K = D.lo[2]; K <= D.hi[2]; ++K)
+        for (int J = D.lo[1]; J <= D.hi[1]; ++J)
+            for (int I = D.lo[0]; I <= D.hi[0]; ++I) {
+                int& m = cmap[cidx(I, J, K)];
+                if (m >= 0) continue;
+                const bool face = I == D.lo[0] || I == D.hi[0] || J == D.lo[1] || J == D.hi[1] || K == D.lo[2] ||
+                                  K == D.hi[2];
+                if (face) m = -1 - ((-1 - m) | 64);
+                if (m != -1) sl.push_back(make_int4(I, J, K, m));
+            }
+    if (sl.size() >= (size_t)(1u << 31) - kCB) throw std::runtime_error("too many special coarse cells");
+    c->nspecial = (int)sl.size();
+    // face ghosts of each fine box: copies from the fine box that owns the
+    // cell, or coarse-fine ghosts (their coarse cell is not covered)
     std::vector<int4> gl;
+    std::vector<GhostCopy> fx;
     for (size_t b = 0; b < fb.size(); ++b) {
         const Box& B = fb[b];
         for (int d = 0; d < 3; ++d)
@@ -543,23 +646,45 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
                         gx[d] = side ? B.hi[d] + 1 : B.lo[d] - 1;
                         gx[ta] = x;
                         gx[tb] = y;
-                        if (cmap[cidx(gx[0] >> 1, gx[1] >> 1, gx[2] >> 1)] >= 0) continue;
-                        gl.push_back(make_int4((int)b | (d << 24) | (side << 26), gx[0], gx[1], gx[2]));
+                        const int o = cmap[cidx(gx[0] >> 1, gx[1] >> 1, gx[2] >> 1)];
+                        if (o < 0) {
+                            gl.push_back(make_int4((int)b | (d << 24) | (side << 26), gx[0], gx[1], gx[2]));
+                        } else {
+                            GhostCopy p;
+                            p.dst = (uint32_t)frb_at(frb[b], gx[0], gx[1], gx[2]);
+                            p.src = (uint32_t)frb_at(frb[o], gx[0], gx[1], gx[2]);
+                            fx.push_back(p);
+                        }
                     }
             }
     }
     if (gl.size() >= (size_t)(1u << 31) - kCB) throw std::runtime_error("too many coarse-fine ghost cells");
     c->nghosts = (int)gl.size();
-    const unsigned nf = (unsigned)std::max(1, c->nfine);
-    c->g_fine = dim3(cdiv(maxP, kCB), cdiv(maxnz, kKZ), nf);
-    c->g_fine_s = dim3(cdiv(maxP, kCB), cdiv(maxnz, kKZs), nf);
-    c->g_fine_gs = dim3(cdiv(maxPh, kCB), cdiv(maxnz, kKZs), nf);
+    c->nfx = (long long)fx.size();
+    const unsigned nf = (unsigned)c->nfine;
+    c->g_fine = dim3(cdiv(maxS, kCB), cdiv(maxnz, kKZ), nf);
+    c->g_fine_s = dim3(cdiv(maxS, kCB), cdiv(maxnz, kKZs), nf);
     c->g_sync = dim3(cdiv(maxPc, kCB), cdiv(maxnzc, kKZ), nf);
     c->g_coarse = dim3(cdiv((long long)g.n[0] * g.n[1], kCB), cdiv(g.n[2], kKZ), 1);
-    c->nparts_fine = c->nfine ? (int)(c->g_fine.x * c->g_fine.y * c->g_fine.z) : 0;
-    c->nparts = c->nparts_fine + (int)(c->g_coarse.x * c->g_coarse.y);
+    int maxP = 1, maxz = 1;
+    for (const Box& B : fba->boxes) {
+        maxP = std::max(maxP, B.n(0) * B.n(1));
+        maxz = std::max(maxz, B.n(2));
+    }
+    c->g_conv = dim3(cdiv(maxP, kCB), cdiv(maxz, kKZ), (unsigned)fba->boxes.size());
+    c->nparts_fine = (int)(c->g_fine.x * c->g_fine.y * c->g_fine.z);
+    c->nparts = c->nparts_fine + (int)(c->g_coarse.x * c->g_coarse.y) + (int)cdiv(c->nspecial, kCB);
     const hipStream_t s = ctx->stream;
+    for (DevBuf<double>* b : {&c->uf, &c->ff, &c->rf}) {
+        HIPCHK(hipMallocAsync((void**)&b->p, (size_t)c->fslab * sizeof(double), s));
+        b->n = (size_t)c->fslab;
+        HIPCHK(hipMemsetAsync(b->p, 0, (size_t)c->fslab * sizeof(double), s));
+    }
+    c->frb.upload_async(frb, s);
+    c->fmap.upload_async(fmap, s);
+    c->fx.upload_async(fx, s);
     c->cmap.upload_async(cmap, s);
+    c->special.upload_async(sl, s);
     c->ghosts.upload_async(gl, s);
     c->part.upload_async(std::vector<double>((size_t)3 * c->nparts, 0.0), s);
     c->fn.upload_async(std::vector<double>(3, 0.0), s);
@@ -601,7 +726,6 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
     if (check_field_mf(rhs_c, cba, "coarse rhs") != BXMG_OK || check_field_mf(rhs_f, fba, "fine rhs") != BXMG_OK)
         return (bxmg_status)(info->status = BXMG_EINVAL);
     if (!covers_domain(cba)) return bad("the coarse BoxArray must cover its domain");
-    if (phi_f->ng < 1) return bad("the fine solution needs nghost >= 1");
     const std::string le = comp::layout_error(cba, fba);
     if (!le.empty()) return bad(le);
     const double h0 = (P.dx > 0) ? P.dx : 1.0 / cba->dom.n(0);
@@ -623,49 +747,42 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
         double* Fc = (double*)c.Fc->data;
         double* Rc = (double*)c.Rc->data;
         double* Ec = (double*)c.Ec->data;
-        const bool merged = c.Uf != nullptr;
-        bxmg_multifab mu = merged ? c.Uf : phi_f, mf = merged ? c.Ff : rhs_f;
-        double* uf = (double*)mu->data;
-        const double* ff = (const double*)mf->data;
-        double* rf = (double*)c.Rf->data;
-        const FBox* fu = mu->d_fboxes.p;
-        const FBox* fF = mf->d_fboxes.p;
-        const FBox* fR = c.Rf->d_fboxes.p;
-        const unsigned nfb = (unsigned)c.nfine;
+        double* uf = c.uf.p;
+        double* ff = c.ff.p;
+        double* rf = c.rf.p;
+        const comp::FRB* fb = c.frb.p;
         double* const part_c = c.part.p + 3 * (size_t)c.nparts_fine;
-        // k_fine_zero covers the grown fine boxes
-        int maxPG = 1, maxGz = 1;
-        for (const FBox& B : mu->fboxes) {
-            maxPG = std::max(maxPG, B.G[0] * B.G[1]);
-            maxGz = std::max(maxGz, B.G[2]);
-        }
-        const dim3 g_zero(comp::cdiv(maxPG, comp::kCB), comp::cdiv(maxGz, comp::kKZ), std::max(1u, nfb));
+        double* const part_s = part_c + 3 * (size_t)(c.g_coarse.x * c.g_coarse.y);
+        const dim3 B(comp::kCB);
         auto chk = [](bxmg_status st) {
             if (st != BXMG_OK) throw std::runtime_error(bxmg_last_error());
         };
-        // load: coarse rhs into the one-box field, zero start on both levels
+        // load: the coarse rhs into the one-box field, the fine rhs into the
+        // colour-split storage; zero start on both levels
         chk(bxmg_parallel_copy(c.Fc, 0, rhs_c, 0, 1, 0, s));
-        if (merged) chk(bxmg_parallel_copy(c.Ff, 0, rhs_f, 0, 1, 0, s));
-        HIPCHK(hipMemsetAsync(Uc, 0, c.Uc->bytes, s));
-        if (nfb) hipLaunchKernelGGL(comp::k_fine_zero, g_zero, dim3(comp::kCB), 0, s, fu, uf);
+        hipLaunchKernelGGL(comp::k_fab_frb<true>, c.g_conv, B, 0, s, rhs_f->d_fboxes.p, (double*)rhs_f->data, fb,
+                           (const int*)c.fmap.p, ff);
         HIPCHK(hipGetLastError());
+        HIPCHK(hipMemsetAsync(Uc, 0, c.Uc->bytes, s));
+        HIPCHK(hipMemsetAsync(uf, 0, (size_t)c.fslab * sizeof(double), s));
         auto fill_fine = [&]() {
-            if (!nfb) return;
-            if (!merged) chk(bxmg_fill_boundary(phi_f, 0, 1, 1, s));
+            if (c.nfx) HIPCHK(launch_fill_rb(s, uf, false, c.fx.p, c.nfx));
             if (c.nghosts)
-                hipLaunchKernelGGL(comp::k_cf_ghost, dim3(comp::cdiv(c.nghosts, comp::kCB)), dim3(comp::kCB), 0, s,
-                                   c.ghosts.p, c.nghosts, g, (const double*)Uc, fu, uf);
+                hipLaunchKernelGGL(comp::k_cf_ghost, dim3(comp::cdiv(c.nghosts, comp::kCB)), B, 0, s, c.ghosts.p,
+                                   c.nghosts, g, (const double*)Uc, fb, uf);
             HIPCHK(hipGetLastError());
         };
-        // composite residual (fonly: norms of f) into Rf / Rc, norms read back
+        // composite residual (fonly: norms of f) into rf / Rc, norms read back
         auto residual = [&](bool fonly, double out[3]) {
             if (!fonly) fill_fine();
-            if (nfb)
-                hipLaunchKernelGGL(comp::k_fine_resid, c.g_fine, dim3(comp::kCB), 0, s, g, fu, fF, fR,
-                                   (const double*)uf, ff, rf, (int)fonly, c.part.p);
-            hipLaunchKernelGGL(comp::k_coarse_resid, c.g_coarse, dim3(comp::kCB), 0, s, g, (const int*)c.cmap.p,
-                               (const double*)Uc, (const double*)Fc, Rc, fu, (const double*)uf, fR,
-                               (const double*)rf, (int)fonly, part_c);
+            hipLaunchKernelGGL(comp::k_fine_resid, c.g_fine, B, 0, s, g, fb, (const double*)uf, (const double*)ff, rf,
+                               (int)fonly, c.part.p);
+            hipLaunchKernelGGL(comp::k_coarse_resid, c.g_coarse, B, 0, s, g, (const int*)c.cmap.p, (const double*)Uc,
+                               (const double*)Fc, Rc, fb, (const double*)rf, (int)fonly, part_c);
+            if (c.nspecial)
+                hipLaunchKernelGGL(comp::k_coarse_resid_special, dim3(comp::cdiv(c.nspecial, comp::kCB)), B, 0, s, g,
+                                   c.special.p, c.nspecial, (const int*)c.cmap.p, (const double*)Uc,
+                                   (const double*)Fc, Rc, fb, (const double*)uf, (int)fonly, part_s);
             HIPCHK(hipGetLastError());
             HIPCHK(launch_norm_final(s, c.part.p, c.nparts, c.fn.p));
             HIPCHK(hipMemcpyAsync(c.h_norm, c.fn.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -678,9 +795,7 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
             for (int q = 0; q < n; ++q)
                 for (int col = 0; col < 2; ++col) {
                     fill_fine();
-                    if (nfb)
-                        hipLaunchKernelGGL(comp::k_fine_gs, c.g_fine_gs, dim3(comp::kCB), 0, s, g, fu, fF, uf, ff,
-                                           col);
+                    hipLaunchKernelGGL(comp::k_fine_gs, c.g_fine_s, B, 0, s, g, fb, uf, (const double*)ff, col);
                     HIPCHK(hipGetLastError());
                 }
         };
@@ -695,15 +810,12 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
             int nlev = 0;
             chk(vcycle_from_zero(ctx, Pc, c.Ec, c.Rc, &nlev));
             info->levels = nlev + 1;
-            hipLaunchKernelGGL(comp::k_coarse_update, c.g_coarse, dim3(comp::kCB), 0, s, g, (const int*)c.cmap.p, Uc,
+            hipLaunchKernelGGL(comp::k_coarse_update, c.g_coarse, B, 0, s, g, (const int*)c.cmap.p, Uc,
                                (const double*)Ec);
-            if (nfb)
-                hipLaunchKernelGGL(comp::k_fine_prolong, c.g_fine_s, dim3(comp::kCB), 0, s, g, fu, uf,
-                                   (const double*)Ec);
+            hipLaunchKernelGGL(comp::k_fine_prolong, c.g_fine_s, B, 0, s, g, fb, uf, (const double*)Ec);
             HIPCHK(hipGetLastError());
             sweeps(P.nu2);
-            if (nfb)
-                hipLaunchKernelGGL(comp::k_coarse_sync, c.g_sync, dim3(comp::kCB), 0, s, g, Uc, fu, (const double*)uf);
+            hipLaunchKernelGGL(comp::k_coarse_sync, c.g_sync, B, 0, s, g, Uc, fb, (const double*)uf);
             HIPCHK(hipGetLastError());
         };
         double fz[3];
@@ -735,9 +847,12 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
             }
         }
         info->cycles = cyc;
-        // the coarse solution (covered cells: the mean of their children) back
+        // the solutions back: coarse (covered cells: the mean of their
+        // children) and the fine valid cells
         chk(bxmg_parallel_copy(phi_c, 0, c.Uc, 0, 1, 0, s));
-        if (merged) chk(bxmg_parallel_copy(phi_f, 0, c.Uf, 0, 1, 0, s));
+        hipLaunchKernelGGL(comp::k_fab_frb<false>, c.g_conv, B, 0, s, phi_f->d_fboxes.p, (double*)phi_f->data, fb,
+                           (const int*)c.fmap.p, uf);
+        HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s));
         info->status = status;
         if (status == BXMG_ENOCONV) fail(BXMG_ENOCONV, "composite_solve: max_cycles reached");
