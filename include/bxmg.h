@@ -279,8 +279,9 @@ bxmg_status bxmg_nodal_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg
  *     ones; rhs_c is read at uncovered cells only.
  *   phi_f, rhs_f: FP64 MultiFabs over the fine BoxArray, whose domain is the
  *     coarse one refined by 2 (lo 2*lo, hi 2*hi+1) with the same boundary
- *     conditions; phi_f needs nghost >= 1 (its ghosts may be overwritten;
- *     fine boxes that tile one rectangle run as one merged box).  Every
+ *     conditions; any nghost (phi_f's valid cells are written, rhs_f's
+ *     read, ghost cells left alone; fine boxes that tile one rectangle run
+ *     as one merged box in the solver's own storage).  Every
  *     fine box must have even lower and odd upper corners (whole coarse
  *     cells) and lie at least 4 fine cells inside every domain face.
  *   params: nu1, nu2 (fine and coarse sweeps), max_cycles, fixed_cycles,
@@ -290,8 +291,9 @@ bxmg_status bxmg_nodal_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg
  * Component 0 of each field is used.  A fully periodic problem needs a
  * compatible rhs (zero volume-weighted sum over the unknowns) and returns a
  * solution defined up to a constant.  The per-layout state (one-box coarse
- * fields, coverage map, coarse-fine ghost list) is cached on the context for
- * the last layout; composite solves on one context run one at a time.
+ * fields, the fine level's colour-split storage, coverage map, ghost and
+ * boundary-cell lists) is cached on the context for the last layout;
+ * composite solves on one context run one at a time.
  * Synchronous on the context's stream.  Returns info->status: OK, ENOCONV,
  * ENONFINITE, EINVAL (bad arguments or layout), ENOMEM or EDEVICE. */
 bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg_multifab phi_c,

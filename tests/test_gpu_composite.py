@@ -33,15 +33,19 @@ def cov_mask(n, fb):
     return m
 
 
-def gpu_solve(bx, n, per, cb, fb, fc, ff, **params):
+def gpu_solve(bx, n, per, cb, fb, fc, ff, ngf=1, check_ghosts=False, **params):
     bc = tuple(bx.PERIODIC if p else bx.DIRICHLET0 for p in per)
     cba = bx.BoxArray.from_boxes((0, 0, 0), (n - 1,) * 3, cb, bc=bc)
     fba = bx.BoxArray.from_boxes((0, 0, 0), (2 * n - 1,) * 3, fb, bc=bc)
     pc = bx.MultiFab(cba, nghost=1).set_val(np.nan)  # contents on entry are ignored
     rc = bx.MultiFab(cba, nghost=0).from_global(np.asfortranarray(fc))
-    pf = bx.MultiFab(fba, nghost=1).set_val(np.nan)
+    pf = bx.MultiFab(fba, nghost=ngf).set_val(np.nan)
     rf = bx.MultiFab(fba, nghost=2).from_global(np.asfortranarray(ff), ghost=np.nan)
     res = bx.composite_solve(pc, rc, pf, rf, **params)
+    if check_ghosts:  # the fine solution's ghost cells are left alone (NaN), its valid cells written
+        packed = pf.to_packed()
+        valid = sum((hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1) for lo, hi in fb)
+        assert np.isnan(packed).sum() == packed.size - valid
     return pc.to_global(), pf.to_global(), res
 
 
@@ -66,7 +70,7 @@ def test_fixed_cycles_elementwise(bx, orc, n, kind, fmax, cmax):
     fc, ff = rhs(n, fb, 31)
     print("composite fixed cycles", n, kind, len(fb), "fine boxes", flush=True)
     uc_o, uf_o, io = orc.composite_solve(n, (0, 0, 0), cb, fb, fc, ff, fixed_cycles=4)
-    uc_g, uf_g, ig = gpu_solve(bx, n, (0, 0, 0), cb, fb, fc, ff, fixed_cycles=4)
+    uc_g, uf_g, ig = gpu_solve(bx, n, (0, 0, 0), cb, fb, fc, ff, check_ghosts=True, fixed_cycles=4)
     assert ig.status == 0 and ig.cycles == 4 == io["cycles"]
     scale = max(np.abs(uc_o).max(), np.abs(uf_o).max())
     fm = W.fine_mask(n, fb)
@@ -127,14 +131,15 @@ def test_periodic_up_to_constant(bx, orc):
 
 
 def test_repeat_and_relayout(bx, orc):
-    """Cached per-layout state: a second layout, then the first again."""
+    """Cached per-layout state: a second layout, then the first again (and
+    fine solution fields with 0, 2 and 1 ghost layers)."""
     n = 16
-    for kind in ("lshape", "centre", "lshape"):
+    for kind, ngf in (("lshape", 0), ("centre", 2), ("lshape", 1)):
         _, fb = W.composite_layout(n, kind, max_box=8)
         cb = W.chop_boxes(n, 8)
         fc, ff = rhs(n, fb, 61)
         uc_o, uf_o, io = orc.composite_solve(n, (0, 0, 0), cb, fb, fc, ff, fixed_cycles=2)
-        uc_g, uf_g, ig = gpu_solve(bx, n, (0, 0, 0), cb, fb, fc, ff, fixed_cycles=2)
+        uc_g, uf_g, ig = gpu_solve(bx, n, (0, 0, 0), cb, fb, fc, ff, ngf=ngf, fixed_cycles=2)
         scale = max(np.abs(uc_o).max(), np.abs(uf_o).max())
         fm = W.fine_mask(n, fb)
         assert np.abs(uc_g - uc_o).max() <= 1e-9 * scale
