@@ -624,6 +624,46 @@ def cpu_c1():
             "sample": "the whole 32^3 solve incl. setup, 1 thread"}, u
 
 
+def cpu_rows(orc, W, keep):
+    """The oracle, as it stands, beside the heat, nodal and composite rows
+    (one thread each, bounded samples, setup included)."""
+    out = {}
+    model, ncpu = cpu_info()
+    host_s = "host %s, %s logical CPUs" % (model, ncpu)
+    if "heat" in keep:
+        k = keep["heat"]
+        n, dt = k["n"], k["dt"]
+        boxes = orc.chop((0, 0, 0), (n - 1,) * 3, MAX_BOX)
+        t0 = time.perf_counter()
+        orc.heat_step((0, 0, 0), (n - 1,) * 3, (0, 0, 0), boxes, k["u_prev"], dt, source=k["src"], fixed_cycles=2)
+        t = time.perf_counter() - t0
+        out["heat"] = {"value": n ** 3 * 2 / t, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+                       "sample": "one backward-Euler step of the same problem cut to 2 V-cycles, 1 thread, %.1f s; %s"
+                                 % (t, host_s)}
+    if "nodal" in keep:
+        n = keep["nodal"]["n"]
+        t0 = time.perf_counter()
+        orc.nodal_solve((n, n, n), (0, 0, 0), keep["nodal"]["f"], fixed_cycles=2)
+        t = time.perf_counter() - t0
+        out["nodal"] = {"value": n ** 3 * 2 / t, "unit": "node-updates/s", "cores": 1, "kind": "oracle",
+                        "sample": "2 V-cycles of the same 257^3-node problem, 1 thread, %.1f s; %s" % (t, host_s)}
+    if "composite" in keep:
+        n = 128  # the same layout rule at half the size: ~2 s per cycle
+        cb, fb = W.composite_layout(n, "centre", max_box=MAX_BOX)
+        fc = W.uniform_rhs((n, n, n), seed=71)
+        ff = np.zeros((2 * n,) * 3, order="F")
+        lo, hi = n // 2, 3 * n // 2
+        ff[lo:hi, lo:hi, lo:hi] = W.uniform_rhs((n, n, n), seed=72)
+        t0 = time.perf_counter()
+        orc.composite_solve(n, (0, 0, 0), cb, fb, fc, ff, fixed_cycles=2)
+        t = time.perf_counter() - t0
+        unknowns = n ** 3 - (n // 2) ** 3 + n ** 3
+        out["composite"] = {"value": unknowns * 2 / t, "unit": "unknown-updates/s", "cores": 1, "kind": "oracle",
+                            "sample": "2 composite cycles of the 128^3 + 128^3 problem (central half refined), "
+                                      "1 thread, %.1f s; %s" % (t, host_s)}
+    return out
+
+
 def cpu_leg_c3(out_path):
     """Child process: the oracle on the 512^3 variable-coefficient problem
     (host draws of the same recipe, seeds 3 and 33), one thread: setup plus
@@ -938,6 +978,8 @@ def main():
                                         u_ref=None if key == "fp64" else k["u"]["fp64"])
             line["mixed_precision"]["error_vs_oracle"] = chk
             del k
+        for row, cb_row in cpu_rows(orc, W, keep).items():
+            line[row]["cpu_oracle"] = cb_row
         if "heat" in keep:
             k = keep.pop("heat")
             n, dt = k["n"], k["dt"]
