@@ -94,19 +94,6 @@ __device__ __forceinline__ long long fidx(const FBox& b, int i, int j, int k) {
     return b.base + (long long)((i - b.glo[0]) + b.G[0] * ((j - b.glo[1]) + b.G[1] * (k - b.glo[2])));
 }
 
-// Block coordinates with consecutive logical blocks on one XCD: blocks are
-// dispatched round-robin over the 8 XCDs (block p to XCD p % 8), so logical
-// block (p % 8) * (N / 8) + p / 8 gives each XCD one contiguous eighth of the
-// grid (x fastest, then y, then z), and its L2 serves the neighbouring rows
-// and planes its stencils read.
-__device__ __forceinline__ uint3 xcd_block() {
-    const unsigned gx = gridDim.x, gy = gridDim.y, N = gx * gy * gridDim.z;
-    const unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-    const unsigned L = (N & 7) ? p : (p & 7) * (N >> 3) + (p >> 3);
-    const unsigned r = L / gx;
-    return make_uint3(L - r * gx, r % gy, r / gy);
-}
-
 __device__ __forceinline__ void block_norms(double mx, double s2, double bad, double* __restrict__ out3) {
     __shared__ double sh[3 * (kCB / 64)];
     for (int o = 32; o > 0; o >>= 1) {

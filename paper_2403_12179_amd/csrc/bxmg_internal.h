@@ -11,6 +11,19 @@ constexpr int kMaxBottomCells = 4096;  // bottom level: one workgroup, vectors i
 constexpr int kBottomGrown = 6144;     // ... and at most this many cells with its ghost layer
 constexpr int kBlock = 256;            // threads per block of the cell kernels
 
+// Block coordinates with consecutive logical blocks on one XCD: blocks are
+// dispatched round-robin over the 8 XCDs (block p to XCD p % 8), so logical
+// block (p % 8) * (N / 8) + p / 8 gives each XCD one contiguous eighth of the
+// grid (x fastest, then y, then z), and its L2 serves the neighbouring rows
+// and planes its stencils read.
+__device__ __forceinline__ uint3 xcd_block() {
+    const unsigned gx = gridDim.x, gy = gridDim.y, N = gx * gy * gridDim.z;
+    const unsigned p = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned L = (N & 7) ? p : (p & 7) * (N >> 3) + (p >> 3);
+    const unsigned r = L / gx;
+    return make_uint3(L - r * gx, r % gy, r / gy);
+}
+
 // Box of a level in the multigrid hierarchy, colour-split storage ("RB").
 // Cells of colour c = (i+j+k)&1 of the box grown by ng are stored as half
 // rows: element (i,j,k) sits at

@@ -77,21 +77,44 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
 
 constexpr int kNB = 256;
 
-// one colour: thread per colour node of the grid (t along x: i = 2t + parity)
+// Level kernels walk planes: grid (plane blocks, plane groups of kKZ), a
+// thread takes one (x, y) position of its planes; node offsets are 32-bit
+// (levels hold fewer than 2^31 nodes).  Interior nodes read their six
+// neighbours directly; the others go through the wrapped index.
+constexpr int kKZ = 8;
+
+__device__ __forceinline__ int nidx32(const NLev& L, int i, int j, int k) {
+    return i + (L.n[0] + 1) * (j + (L.n[1] + 1) * k);
+}
+
+// no neighbour through a wrap: in a periodic direction node n_d - 1 reads
+// node 0 through the wrapped index (the copy n_d is refreshed only at the
+// end), so it is not interior
+__device__ __forceinline__ bool interior(const NLev& L, int i, int j, int k) {
+    return i > 0 && i < L.n[0] - L.per[0] && j > 0 && j < L.n[1] - L.per[1] && k > 0 && k < L.n[2] - L.per[2];
+}
+
+// one colour: a thread per colour node of a row position (i = 2t + parity)
 __global__ void __launch_bounds__(kNB) k_nd_gs(NLev L, double* __restrict__ u, const double* __restrict__ f,
-                                              int colour) {
-    const int hx = (L.n[0] + 2) / 2;
-    const long long total = (long long)hx * (L.n[1] + 1) * (L.n[2] + 1);
+                                              int colour, int kz) {
+    const uint3 bk = xcd_block();
+    const int hx = (L.n[0] + 2) / 2, ny = L.n[1] + 1;
+    const int t = bk.x * kNB + threadIdx.x;
+    if (t >= hx * ny) return;
+    const int tx = t % hx, j = t / hx;
+    const int k0 = bk.y * kz, k1 = min(k0 + kz - 1, L.n[2]);
+    const int sy = L.n[0] + 1, sz = (L.n[0] + 1) * (L.n[1] + 1);
     const double h2 = L.h * L.h;
-    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-         g += (long long)gridDim.x * blockDim.x) {
-        const int t = (int)(g % hx);
-        const int j = (int)((g / hx) % (L.n[1] + 1));
-        const int k = (int)(g / ((long long)hx * (L.n[1] + 1)));
-        const int i = 2 * t + ((colour - j - k) & 1);
+    for (int k = k0; k <= k1; ++k) {
+        const int i = 2 * tx + ((colour - j - k) & 1);
         if (i > L.n[0] || !unknown(L, i, j, k)) continue;
-        const long long q = nidx(L, i, j, k);
-        u[q] = (nsum(L, u, i, j, k) - h2 * f[q]) / 6.0;
+        const int q = nidx32(L, i, j, k);
+        double su;
+        if (interior(L, i, j, k))
+            su = ((u[q - 1] + u[q + 1]) + (u[q - sy] + u[q + sy])) + (u[q - sz] + u[q + sz]);
+        else
+            su = nsum(L, u, i, j, k);
+        u[q] = (su - h2 * f[q]) / 6.0;
     }
 }
 
@@ -99,24 +122,34 @@ __global__ void __launch_bounds__(kNB) k_nd_gs(NLev L, double* __restrict__ u, c
 // non-finite count) per block
 __global__ void __launch_bounds__(kNB) k_nd_resid(NLev L, const double* __restrict__ u,
                                                  const double* __restrict__ f, double* __restrict__ r,
-                                                 double* __restrict__ partials) {
+                                                 double* __restrict__ partials, int kz) {
     __shared__ double sh[3 * (kNB / 64)];
+    const uint3 bk = xcd_block();
+    const int nx = L.n[0] + 1, ny = L.n[1] + 1;
+    const int t = bk.x * kNB + threadIdx.x;
     const double ih2 = 1.0 / (L.h * L.h);
     double mx = 0.0, s2 = 0.0, bad = 0.0;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < L.size;
-         q += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(q % (L.n[0] + 1));
-        const int j = (int)((q / (L.n[0] + 1)) % (L.n[1] + 1));
-        const int k = (int)(q / ((long long)(L.n[0] + 1) * (L.n[1] + 1)));
-        double rv = 0.0;
-        if (unknown(L, i, j, k)) {
-            rv = f[q] - (nsum(L, u, i, j, k) - 6.0 * u[q]) * ih2;
-            const double a = fabs(rv);
-            if (!(a <= 1.7976931348623157e308)) bad += 1.0;
-            else mx = fmax(mx, a);
-            s2 = s2 + rv * rv;
+    if (t < nx * ny) {
+        const int i = t % nx, j = t / nx;
+        const int k0 = bk.y * kz, k1 = min(k0 + kz - 1, L.n[2]);
+        const int sy = nx, sz = nx * ny;
+        for (int k = k0; k <= k1; ++k) {
+            const int q = nidx32(L, i, j, k);
+            double rv = 0.0;
+            if (unknown(L, i, j, k)) {
+                double su;
+                if (interior(L, i, j, k))
+                    su = ((u[q - 1] + u[q + 1]) + (u[q - sy] + u[q + sy])) + (u[q - sz] + u[q + sz]);
+                else
+                    su = nsum(L, u, i, j, k);
+                rv = f[q] - (su - 6.0 * u[q]) * ih2;
+                const double a = fabs(rv);
+                if (!(a <= 1.7976931348623157e308)) bad += 1.0;
+                else mx = fmax(mx, a);
+                s2 = s2 + rv * rv;
+            }
+            r[q] = rv;
         }
-        r[q] = rv;
     }
     for (int o = 32; o > 0; o >>= 1) {
         mx = fmax(mx, __shfl_xor(mx, o));
@@ -128,9 +161,10 @@ __global__ void __launch_bounds__(kNB) k_nd_resid(NLev L, const double* __restri
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < kNB / 64; ++w) { mx = fmax(mx, sh[3 * w]); s2 = s2 + sh[3 * w + 1]; bad = bad + sh[3 * w + 2]; }
-        partials[3 * blockIdx.x] = mx;
-        partials[3 * blockIdx.x + 1] = s2;
-        partials[3 * blockIdx.x + 2] = bad;
+        const int blk = bk.y * gridDim.x + bk.x;
+        partials[3 * blk] = mx;
+        partials[3 * blk + 1] = s2;
+        partials[3 * blk + 2] = bad;
     }
 }
 
@@ -169,20 +203,23 @@ __global__ void __launch_bounds__(kNB) k_nd_fnorm(NLev L, const double* __restri
 // full weighting onto the coarse unknowns (0 at the other coarse nodes), in
 // the order z, then y, then x offsets; the coarse u is zeroed on the way
 __global__ void __launch_bounds__(kNB) k_nd_restrict(NLev F, const double* __restrict__ r, NLev C,
-                                                    double* __restrict__ fc, double* __restrict__ uc) {
+                                                    double* __restrict__ fc, double* __restrict__ uc, int kz) {
+    const uint3 bk = xcd_block();
+    const int nx = C.n[0] + 1, ny = C.n[1] + 1;
+    const int t = bk.x * kNB + threadIdx.x;
+    if (t >= nx * ny) return;
+    const int I = t % nx, J = t / nx;
+    const int K0 = bk.y * kz, K1 = min(K0 + kz - 1, C.n[2]);
     const double w[3] = {0.25, 0.5, 0.25};
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < C.size;
-         q += (long long)gridDim.x * blockDim.x) {
-        const int I = (int)(q % (C.n[0] + 1));
-        const int J = (int)((q / (C.n[0] + 1)) % (C.n[1] + 1));
-        const int K = (int)(q / ((long long)(C.n[0] + 1) * (C.n[1] + 1)));
+    for (int K = K0; K <= K1; ++K) {
+        const int q = nidx32(C, I, J, K);
         double s = 0.0;
         if (unknown(C, I, J, K)) {
             for (int c = -1; c <= 1; ++c)
                 for (int b = -1; b <= 1; ++b)
                     for (int a = -1; a <= 1; ++a) {
                         const int i = wrap(F, 0, 2 * I + a), j = wrap(F, 1, 2 * J + b), k = wrap(F, 2, 2 * K + c);
-                        s = s + ((w[a + 1] * w[b + 1]) * w[c + 1]) * r[nidx(F, i, j, k)];
+                        s = s + ((w[a + 1] * w[b + 1]) * w[c + 1]) * r[nidx32(F, i, j, k)];
                     }
         }
         fc[q] = s;
@@ -357,6 +394,27 @@ __global__ void __launch_bounds__(kNBot) k_nd_bottom(NLev L, double* __restrict_
 
 inline unsigned nblocks(long long n) { return (unsigned)std::min<long long>((n + kNB - 1) / kNB, 8192); }
 
+// Planes each thread walks on a level: up to kmax, fewer where the level
+// would otherwise give fewer than 2048 blocks.
+inline int plane_depth(const NLev& L, bool half, int kmax) {
+    const long long row = half ? (L.n[0] + 2) / 2 : L.n[0] + 1;
+    const long long gx = (row * (L.n[1] + 1) + kNB - 1) / kNB;
+    const long long kz = (gx * (L.n[2] + 1)) / 2048;
+    return (int)std::max(1LL, std::min<long long>(kmax, kz));
+}
+// grid of the plane-walking kernels over the nodes of a level (half rows
+// for the sweeps), kz planes per thread
+inline dim3 plane_grid(const NLev& L, bool half, int kz) {
+    const long long row = half ? (L.n[0] + 2) / 2 : L.n[0] + 1;
+    return dim3((unsigned)((row * (L.n[1] + 1) + kNB - 1) / kNB), (unsigned)((L.n[2] + 1 + kz - 1) / kz), 1);
+}
+inline int plane_blocks(const NLev& L, int kz) {
+    const dim3 g = plane_grid(L, false, kz);
+    return (int)(g.x * g.y);
+}
+constexpr int kKZr = kKZ;  // residual
+constexpr int kKZt = 2;    // transfers
+
 // The nodal hierarchy of one geometry, cached on the context.
 struct NHier {
     std::vector<NLev> L;
@@ -398,6 +456,7 @@ static NHier* get(bxmg_ctx ctx, const bxmg_ba_s* ba, double h0) {
     }
     const NLev& B = H->L.back();
     if (B.size > 4096 * 8) throw std::runtime_error("nodal: bottom level too large");
+    if (H->L[0].size >= (1LL << 31)) throw std::runtime_error("nodal: more than 2^31 nodes");
     const size_t nl = H->L.size();
     H->u.resize(nl);
     H->f.resize(nl);
@@ -407,7 +466,9 @@ static NHier* get(bxmg_ctx ctx, const bxmg_ba_s* ba, double h0) {
         H->f[q].alloc(H->L[q].size);
         H->r[q].alloc(H->L[q].size);
     }
-    H->part.alloc(3 * 8192);
+    int np = 8192;
+    for (const NLev& l : H->L) np = std::max(np, plane_blocks(l, plane_depth(l, false, kKZr)));
+    H->part.alloc(3 * (size_t)np);
     H->bp.alloc(B.size);
     H->bq.alloc(B.size);
     H->fn.alloc(3);
@@ -425,20 +486,22 @@ static void vcycle(NHier& H, size_t l, hipStream_t s, int nu1, int nu2, double b
         HIPCHK(hipGetLastError());
         return;
     }
-    const unsigned gb = nblocks(((long long)(L.n[0] + 2) / 2) * (L.n[1] + 1) * (L.n[2] + 1));
+    const int kg = plane_depth(L, true, kKZ), kr = plane_depth(L, false, kKZr);
+    const dim3 gb = plane_grid(L, true, kg);
     for (int q = 0; q < nu1; ++q)
         for (int c = 0; c < 2; ++c)
-            hipLaunchKernelGGL(k_nd_gs, dim3(gb), dim3(kNB), 0, s, L, H.u[l].p, H.f[l].p, c);
-    hipLaunchKernelGGL(k_nd_resid, dim3(nblocks(L.size)), dim3(kNB), 0, s, L, H.u[l].p, H.f[l].p, H.r[l].p,
-                       H.part.p);
+            hipLaunchKernelGGL(k_nd_gs, gb, dim3(kNB), 0, s, L, H.u[l].p, H.f[l].p, c, kg);
+    hipLaunchKernelGGL(k_nd_resid, plane_grid(L, false, kr), dim3(kNB), 0, s, L, H.u[l].p, H.f[l].p, H.r[l].p,
+                       H.part.p, kr);
     const NLev& C = H.L[l + 1];
-    hipLaunchKernelGGL(k_nd_restrict, dim3(nblocks(C.size)), dim3(kNB), 0, s, L, H.r[l].p, C, H.f[l + 1].p,
-                       H.u[l + 1].p);
+    const int kc = plane_depth(C, false, kKZt);
+    hipLaunchKernelGGL(k_nd_restrict, plane_grid(C, false, kc), dim3(kNB), 0, s, L, H.r[l].p, C, H.f[l + 1].p,
+                       H.u[l + 1].p, kc);
     vcycle(H, l + 1, s, nu1, nu2, brtol);
     hipLaunchKernelGGL(k_nd_prolong, dim3(nblocks(L.size)), dim3(kNB), 0, s, C, H.u[l + 1].p, L, H.u[l].p);
     for (int q = 0; q < nu2; ++q)
         for (int c = 0; c < 2; ++c)
-            hipLaunchKernelGGL(k_nd_gs, dim3(gb), dim3(kNB), 0, s, L, H.u[l].p, H.f[l].p, c);
+            hipLaunchKernelGGL(k_nd_gs, gb, dim3(kNB), 0, s, L, H.u[l].p, H.f[l].p, c, kg);
     HIPCHK(hipGetLastError());
 }
 
@@ -471,16 +534,17 @@ extern "C" bxmg_status bxmg_nodal_solve(bxmg_ctx ctx, const bxmg_solve_params* p
         HIPCHK(hipMemcpyAsync(H->u[0].p, phi, L0.size * sizeof(double), hipMemcpyDeviceToDevice, s));
         HIPCHK(hipMemcpyAsync(H->f[0].p, rhs, L0.size * sizeof(double), hipMemcpyDeviceToDevice, s));
         const unsigned nb = nodal::nblocks(L0.size);
+        const int kr0 = nodal::plane_depth(L0, false, nodal::kKZr);
         // norms reduced on the device and read back: of f (fonly) or of the
         // residual of the current iterate
         auto norms = [&](bool fonly, double out[3]) {
             if (fonly)
                 hipLaunchKernelGGL(nodal::k_nd_fnorm, dim3(nb), dim3(nodal::kNB), 0, s, L0, H->f[0].p, H->part.p);
             else
-                hipLaunchKernelGGL(nodal::k_nd_resid, dim3(nb), dim3(nodal::kNB), 0, s, L0, H->u[0].p, H->f[0].p,
-                                   H->r[0].p, H->part.p);
+                hipLaunchKernelGGL(nodal::k_nd_resid, nodal::plane_grid(L0, false, kr0), dim3(nodal::kNB), 0, s, L0,
+                                   H->u[0].p, H->f[0].p, H->r[0].p, H->part.p, kr0);
             HIPCHK(hipGetLastError());
-            HIPCHK(launch_norm_final(s, H->part.p, (int)nb, H->fn.p));
+            HIPCHK(launch_norm_final(s, H->part.p, fonly ? (int)nb : nodal::plane_blocks(L0, kr0), H->fn.p));
             HIPCHK(hipMemcpyAsync(ctx->h_norm, H->fn.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             out[0] = ctx->h_norm[2] > 0.0 ? (double)NAN : ctx->h_norm[0];
