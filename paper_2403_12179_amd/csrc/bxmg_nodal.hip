@@ -2,8 +2,12 @@
 // paper Section 2): V-cycles over node-centred data of the whole domain.
 //
 // On a domain of n_d cells of width h per direction the nodes sit at
-// x = i h, i = 0 .. n_d, stored as one F-order array of
-// (n_0+1)(n_1+1)(n_2+1) values per level.  A homogeneous-Dirichlet
+// x = i h, i = 0 .. n_d.  The caller's arrays are F-order over the
+// (n_0+1)(n_1+1)(n_2+1) nodes; every level is held colour-split inside the
+// solver: node (i, j, k) of colour c = (i + j + k) & 1 in colour block c,
+// row k (n_1+1) + j, slot i >> 1 (rows of (n_0+2)/2 slots), so a colour
+// sweep streams the other colour, its own right-hand side and its own
+// writes.  A homogeneous-Dirichlet
 // direction keeps its boundary nodes at 0 (they are not unknowns); in a
 // periodic direction node n_d is node 0: the kernels read neighbours
 // through the wrapped index, and the copies n_d are refreshed only in the
@@ -30,11 +34,24 @@ struct NLev {
     int n[3];    // cells per direction (nodes 0..n)
     int per[3];
     double h;
-    long long size;  // (n0+1)(n1+1)(n2+1)
+    long long size;   // nodes, (n0+1)(n1+1)(n2+1)
+    int H;            // slots per colour row, (n0+2)/2
+    long long cs;     // colour block stride (elements)
+    long long alloc;  // elements of a level array, 2 cs
 };
 
+// offset of node (i, j, k) in the colour-split level array
 __host__ __device__ inline long long nidx(const NLev& L, int i, int j, int k) {
-    return i + (long long)(L.n[0] + 1) * (j + (long long)(L.n[1] + 1) * k);
+    return ((i + j + k) & 1) * L.cs + (long long)((k * (L.n[1] + 1) + j) * L.H + (i >> 1));
+}
+
+// node (i, j, k) of the g-th node in F order (x fastest)
+__device__ __forceinline__ void coords(const NLev& L, long long g, int& i, int& j, int& k) {
+    const int nx = L.n[0] + 1, ny = L.n[1] + 1;
+    const long long r = g / nx;
+    i = (int)(g - r * nx);
+    j = (int)(r % ny);
+    k = (int)(r / ny);
 }
 
 __device__ __forceinline__ bool unknown(const NLev& L, int i, int j, int k) {
@@ -77,14 +94,19 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
 
 constexpr int kNB = 256;
 
-// Level kernels walk planes: grid (plane blocks, plane groups of kKZ), a
-// thread takes one (x, y) position of its planes; node offsets are 32-bit
-// (levels hold fewer than 2^31 nodes).  Interior nodes read their six
-// neighbours directly; the others go through the wrapped index.
+// Level kernels walk planes: grid (plane blocks, plane groups), a thread
+// takes one (x, y) position of its planes.  Interior nodes read their six
+// neighbours directly (x from the other colour's slots (i -+ 1) >> 1, y and z
+// from the other colour's rows at slot i >> 1); the others go through the
+// wrapped index.
 constexpr int kKZ = 8;
 
-__device__ __forceinline__ int nidx32(const NLev& L, int i, int j, int k) {
-    return i + (L.n[0] + 1) * (j + (L.n[1] + 1) * k);
+// the six neighbours of interior node (i, j, k), ((x- + x+) + (y- + y+)) + (z- + z+)
+__device__ __forceinline__ double nsum_in(const NLev& L, const double* __restrict__ u, int i, int j, int k) {
+    const int c = (i + j + k) & 1;
+    const long long o = (1 - c) * L.cs + (long long)((k * (L.n[1] + 1) + j) * L.H);
+    const long long m = o + (i >> 1), sy = L.H, sz = (long long)L.H * (L.n[1] + 1);
+    return ((u[o + ((i - 1) >> 1)] + u[o + ((i + 1) >> 1)]) + (u[m - sy] + u[m + sy])) + (u[m - sz] + u[m + sz]);
 }
 
 // no neighbour through a wrap: in a periodic direction node n_d - 1 reads
@@ -103,17 +125,12 @@ __global__ void __launch_bounds__(kNB) k_nd_gs(NLev L, double* __restrict__ u, c
     if (t >= hx * ny) return;
     const int tx = t % hx, j = t / hx;
     const int k0 = bk.y * kz, k1 = min(k0 + kz - 1, L.n[2]);
-    const int sy = L.n[0] + 1, sz = (L.n[0] + 1) * (L.n[1] + 1);
     const double h2 = L.h * L.h;
     for (int k = k0; k <= k1; ++k) {
         const int i = 2 * tx + ((colour - j - k) & 1);
         if (i > L.n[0] || !unknown(L, i, j, k)) continue;
-        const int q = nidx32(L, i, j, k);
-        double su;
-        if (interior(L, i, j, k))
-            su = ((u[q - 1] + u[q + 1]) + (u[q - sy] + u[q + sy])) + (u[q - sz] + u[q + sz]);
-        else
-            su = nsum(L, u, i, j, k);
+        const long long q = nidx(L, i, j, k);
+        const double su = interior(L, i, j, k) ? nsum_in(L, u, i, j, k) : nsum(L, u, i, j, k);
         u[q] = (su - h2 * f[q]) / 6.0;
     }
 }
@@ -125,23 +142,22 @@ __global__ void __launch_bounds__(kNB) k_nd_resid(NLev L, const double* __restri
                                                  double* __restrict__ partials, int kz) {
     __shared__ double sh[3 * (kNB / 64)];
     const uint3 bk = xcd_block();
-    const int nx = L.n[0] + 1, ny = L.n[1] + 1;
+    const int hx = (L.n[0] + 2) / 2, ny = L.n[1] + 1;
     const int t = bk.x * kNB + threadIdx.x;
     const double ih2 = 1.0 / (L.h * L.h);
     double mx = 0.0, s2 = 0.0, bad = 0.0;
-    if (t < nx * ny) {
-        const int i = t % nx, j = t / nx;
+    if (t < hx * ny) {
+        // a thread per row slot, the node of each colour in it
+        const int tx = t % hx, j = t / hx;
         const int k0 = bk.y * kz, k1 = min(k0 + kz - 1, L.n[2]);
-        const int sy = nx, sz = nx * ny;
-        for (int k = k0; k <= k1; ++k) {
-            const int q = nidx32(L, i, j, k);
+        for (int k = k0; k <= k1; ++k)
+          for (int c = 0; c < 2; ++c) {
+            const int i = 2 * tx + ((c - j - k) & 1);
+            if (i > L.n[0]) continue;
+            const long long q = nidx(L, i, j, k);
             double rv = 0.0;
             if (unknown(L, i, j, k)) {
-                double su;
-                if (interior(L, i, j, k))
-                    su = ((u[q - 1] + u[q + 1]) + (u[q - sy] + u[q + sy])) + (u[q - sz] + u[q + sz]);
-                else
-                    su = nsum(L, u, i, j, k);
+                const double su = interior(L, i, j, k) ? nsum_in(L, u, i, j, k) : nsum(L, u, i, j, k);
                 rv = f[q] - (su - 6.0 * u[q]) * ih2;
                 const double a = fabs(rv);
                 if (!(a <= 1.7976931348623157e308)) bad += 1.0;
@@ -149,7 +165,7 @@ __global__ void __launch_bounds__(kNB) k_nd_resid(NLev L, const double* __restri
                 s2 = s2 + rv * rv;
             }
             r[q] = rv;
-        }
+          }
     }
     for (int o = 32; o > 0; o >>= 1) {
         mx = fmax(mx, __shfl_xor(mx, o));
@@ -173,12 +189,12 @@ __global__ void __launch_bounds__(kNB) k_nd_fnorm(NLev L, const double* __restri
                                                  double* __restrict__ partials) {
     __shared__ double sh[3 * (kNB / 64)];
     double mx = 0.0, s2 = 0.0, bad = 0.0;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < L.size;
-         q += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(q % (L.n[0] + 1));
-        const int j = (int)((q / (L.n[0] + 1)) % (L.n[1] + 1));
-        const int k = (int)(q / ((long long)(L.n[0] + 1) * (L.n[1] + 1)));
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < L.size;
+         g += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        coords(L, g, i, j, k);
         if (!unknown(L, i, j, k)) continue;
+        const long long q = nidx(L, i, j, k);
         const double a = fabs(f[q]);
         if (!(a <= 1.7976931348623157e308)) bad += 1.0;
         else mx = fmax(mx, a);
@@ -212,14 +228,14 @@ __global__ void __launch_bounds__(kNB) k_nd_restrict(NLev F, const double* __res
     const int K0 = bk.y * kz, K1 = min(K0 + kz - 1, C.n[2]);
     const double w[3] = {0.25, 0.5, 0.25};
     for (int K = K0; K <= K1; ++K) {
-        const int q = nidx32(C, I, J, K);
+        const long long q = nidx(C, I, J, K);
         double s = 0.0;
         if (unknown(C, I, J, K)) {
             for (int c = -1; c <= 1; ++c)
                 for (int b = -1; b <= 1; ++b)
                     for (int a = -1; a <= 1; ++a) {
                         const int i = wrap(F, 0, 2 * I + a), j = wrap(F, 1, 2 * J + b), k = wrap(F, 2, 2 * K + c);
-                        s = s + ((w[a + 1] * w[b + 1]) * w[c + 1]) * r[nidx32(F, i, j, k)];
+                        s = s + ((w[a + 1] * w[b + 1]) * w[c + 1]) * r[nidx(F, i, j, k)];
                     }
         }
         fc[q] = s;
@@ -231,12 +247,12 @@ __global__ void __launch_bounds__(kNB) k_nd_restrict(NLev F, const double* __res
 // coarse nodes I + o' (o' <= o), summed z, y, x
 __global__ void __launch_bounds__(kNB) k_nd_prolong(NLev C, const double* __restrict__ e, NLev F,
                                                    double* __restrict__ u) {
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < F.size;
-         q += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(q % (F.n[0] + 1));
-        const int j = (int)((q / (F.n[0] + 1)) % (F.n[1] + 1));
-        const int k = (int)(q / ((long long)(F.n[0] + 1) * (F.n[1] + 1)));
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < F.size;
+         g += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        coords(F, g, i, j, k);
         if (!unknown(F, i, j, k)) continue;
+        const long long q = nidx(F, i, j, k);
         const int I[3] = {i >> 1, j >> 1, k >> 1}, o[3] = {i & 1, j & 1, k & 1};
         double s = 0.0;
         int cnt = 0;
@@ -252,10 +268,11 @@ __global__ void __launch_bounds__(kNB) k_nd_prolong(NLev C, const double* __rest
 
 // the periodic copies n_d take the values of their nodes 0
 __global__ void __launch_bounds__(kNB) k_nd_copies(NLev L, double* __restrict__ u) {
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < L.size;
-         q += (long long)gridDim.x * blockDim.x) {
-        int c[3] = {(int)(q % (L.n[0] + 1)), (int)((q / (L.n[0] + 1)) % (L.n[1] + 1)),
-                    (int)(q / ((long long)(L.n[0] + 1) * (L.n[1] + 1)))};
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < L.size;
+         g += (long long)gridDim.x * blockDim.x) {
+        int c[3];
+        coords(L, g, c[0], c[1], c[2]);
+        const long long q = nidx(L, c[0], c[1], c[2]);
         bool copy = false;
         for (int d = 0; d < 3; ++d)
             if (L.per[d] && c[d] == L.n[d]) { c[d] = 0; copy = true; }
@@ -268,12 +285,11 @@ __global__ void __launch_bounds__(kNB) k_nd_copies(NLev L, double* __restrict__ 
 __global__ void __launch_bounds__(kNB) k_nd_sum(NLev L, const double* __restrict__ u, double* __restrict__ part) {
     __shared__ double sh[2 * (kNB / 64)];
     double s = 0.0, c = 0.0;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < L.size;
-         q += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(q % (L.n[0] + 1));
-        const int j = (int)((q / (L.n[0] + 1)) % (L.n[1] + 1));
-        const int k = (int)(q / ((long long)(L.n[0] + 1) * (L.n[1] + 1)));
-        if (unknown(L, i, j, k)) { s = s + u[q]; c = c + 1.0; }
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < L.size;
+         g += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        coords(L, g, i, j, k);
+        if (unknown(L, i, j, k)) { s = s + u[nidx(L, i, j, k)]; c = c + 1.0; }
     }
     block_sum2(s, c, sh);
     if (threadIdx.x == 0) { part[2 * blockIdx.x] = s; part[2 * blockIdx.x + 1] = c; }
@@ -283,19 +299,21 @@ __global__ void __launch_bounds__(kNB) k_nd_sub(NLev L, double* __restrict__ u, 
     double s = 0.0, c = 0.0;
     for (int b = 0; b < nparts; ++b) { s = s + part[2 * b]; c = c + part[2 * b + 1]; }
     const double m = s / c;
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < L.size;
-         q += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(q % (L.n[0] + 1));
-        const int j = (int)((q / (L.n[0] + 1)) % (L.n[1] + 1));
-        const int k = (int)(q / ((long long)(L.n[0] + 1) * (L.n[1] + 1)));
-        if (unknown(L, i, j, k)) u[q] = u[q] - m;
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < L.size;
+         g += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        coords(L, g, i, j, k);
+        if (unknown(L, i, j, k)) {
+            const long long q = nidx(L, i, j, k);
+            u[q] = u[q] - m;
+        }
     }
 }
 
 // Bottom: FP64 CG on the unknowns in one workgroup, vectors in device
-// memory (levels of a few thousand nodes); fully periodic: right-hand side
-// and solution projected to mean 0.  rtol on the L2 norm, at most 4 N
-// iterations.
+// memory (levels of a few thousand nodes, colour-split like the others);
+// fully periodic: right-hand side and solution projected to mean 0.  rtol
+// on the L2 norm, at most 4 N iterations.
 constexpr int kNBot = 1024;
 __global__ void __launch_bounds__(kNBot) k_nd_bottom(NLev L, double* __restrict__ x, const double* __restrict__ f,
                                                     double* __restrict__ r, double* __restrict__ p,
@@ -305,19 +323,15 @@ __global__ void __launch_bounds__(kNBot) k_nd_bottom(NLev L, double* __restrict_
     const long long N = L.size;
     const bool sing = L.per[0] && L.per[1] && L.per[2];
     const double ih2 = 1.0 / (L.h * L.h);
-    auto coords = [&](long long g, int& i, int& j, int& k) {
-        i = (int)(g % (L.n[0] + 1));
-        j = (int)((g / (L.n[0] + 1)) % (L.n[1] + 1));
-        k = (int)(g / ((long long)(L.n[0] + 1) * (L.n[1] + 1)));
-    };
     // sum over unknowns of a*b (or of a, with b == nullptr), broadcast
     auto dot = [&](const double* a, const double* b, double& cnt) {
         double s = 0.0, c = 0.0;
         for (long long g = threadIdx.x; g < N; g += blockDim.x) {
             int i, j, k;
-            coords(g, i, j, k);
+            coords(L, g, i, j, k);
             if (!unknown(L, i, j, k)) continue;
-            s = s + (b ? a[g] * b[g] : a[g]);
+            const long long o = nidx(L, i, j, k);
+            s = s + (b ? a[o] * b[o] : a[o]);
             c = c + 1.0;
         }
         block_sum2(s, c, sh);
@@ -330,9 +344,10 @@ __global__ void __launch_bounds__(kNBot) k_nd_bottom(NLev L, double* __restrict_
     };
     for (long long g = threadIdx.x; g < N; g += blockDim.x) {
         int i, j, k;
-        coords(g, i, j, k);
-        r[g] = unknown(L, i, j, k) ? f[g] : 0.0;
-        x[g] = 0.0;
+        coords(L, g, i, j, k);
+        const long long o = nidx(L, i, j, k);
+        r[o] = unknown(L, i, j, k) ? f[o] : 0.0;
+        x[o] = 0.0;
     }
     __syncthreads();
     double cnt;
@@ -340,12 +355,20 @@ __global__ void __launch_bounds__(kNBot) k_nd_bottom(NLev L, double* __restrict_
         const double m = dot(r, nullptr, cnt) / cnt;
         for (long long g = threadIdx.x; g < N; g += blockDim.x) {
             int i, j, k;
-            coords(g, i, j, k);
-            if (unknown(L, i, j, k)) r[g] = r[g] - m;
+            coords(L, g, i, j, k);
+            if (unknown(L, i, j, k)) {
+                const long long o = nidx(L, i, j, k);
+                r[o] = r[o] - m;
+            }
         }
         __syncthreads();
     }
-    for (long long g = threadIdx.x; g < N; g += blockDim.x) p[g] = r[g];
+    for (long long g = threadIdx.x; g < N; g += blockDim.x) {
+        int i, j, k;
+        coords(L, g, i, j, k);
+        const long long o = nidx(L, i, j, k);
+        p[o] = r[o];
+    }
     __syncthreads();
     double rs = dot(r, r, cnt);
     const double rs0 = rs;
@@ -355,17 +378,19 @@ __global__ void __launch_bounds__(kNBot) k_nd_bottom(NLev L, double* __restrict_
         while (it < maxit) {
             for (long long g = threadIdx.x; g < N; g += blockDim.x) {
                 int i, j, k;
-                coords(g, i, j, k);
-                q[g] = unknown(L, i, j, k) ? (nsum(L, p, i, j, k) - 6.0 * p[g]) * ih2 : 0.0;
+                coords(L, g, i, j, k);
+                const long long o = nidx(L, i, j, k);
+                q[o] = unknown(L, i, j, k) ? (nsum(L, p, i, j, k) - 6.0 * p[o]) * ih2 : 0.0;
             }
             __syncthreads();
             const double alpha = rs / dot(p, q, cnt);
             for (long long g = threadIdx.x; g < N; g += blockDim.x) {
                 int i, j, k;
-                coords(g, i, j, k);
+                coords(L, g, i, j, k);
                 if (!unknown(L, i, j, k)) continue;
-                x[g] = x[g] + alpha * p[g];
-                r[g] = r[g] - alpha * q[g];
+                const long long o = nidx(L, i, j, k);
+                x[o] = x[o] + alpha * p[o];
+                r[o] = r[o] - alpha * q[o];
             }
             __syncthreads();
             const double rsn = dot(r, r, cnt);
@@ -374,8 +399,11 @@ __global__ void __launch_bounds__(kNBot) k_nd_bottom(NLev L, double* __restrict_
             const double beta = rsn / rs;
             for (long long g = threadIdx.x; g < N; g += blockDim.x) {
                 int i, j, k;
-                coords(g, i, j, k);
-                if (unknown(L, i, j, k)) p[g] = r[g] + beta * p[g];
+                coords(L, g, i, j, k);
+                if (unknown(L, i, j, k)) {
+                    const long long o = nidx(L, i, j, k);
+                    p[o] = r[o] + beta * p[o];
+                }
             }
             __syncthreads();
             rs = rsn;
@@ -384,12 +412,27 @@ __global__ void __launch_bounds__(kNBot) k_nd_bottom(NLev L, double* __restrict_
             const double m = dot(x, nullptr, cnt) / cnt;
             for (long long g = threadIdx.x; g < N; g += blockDim.x) {
                 int i, j, k;
-                coords(g, i, j, k);
-                if (unknown(L, i, j, k)) x[g] = x[g] - m;
+                coords(L, g, i, j, k);
+                if (unknown(L, i, j, k)) {
+                    const long long o = nidx(L, i, j, k);
+                    x[o] = x[o] - m;
+                }
             }
         }
     }
     if (threadIdx.x == 0 && iters) *iters = it;
+}
+
+// Caller F-order node array <-> colour-split level array.
+template <bool TO_SPLIT>
+__global__ void __launch_bounds__(kNB) k_nd_convert(NLev L, double* __restrict__ fo, double* __restrict__ sp) {
+    for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < L.size;
+         g += (long long)gridDim.x * blockDim.x) {
+        int i, j, k;
+        coords(L, g, i, j, k);
+        if constexpr (TO_SPLIT) sp[nidx(L, i, j, k)] = fo[g];
+        else fo[g] = sp[nidx(L, i, j, k)];
+    }
 }
 
 inline unsigned nblocks(long long n) { return (unsigned)std::min<long long>((n + kNB - 1) / kNB, 8192); }
@@ -408,8 +451,8 @@ inline dim3 plane_grid(const NLev& L, bool half, int kz) {
     const long long row = half ? (L.n[0] + 2) / 2 : L.n[0] + 1;
     return dim3((unsigned)((row * (L.n[1] + 1) + kNB - 1) / kNB), (unsigned)((L.n[2] + 1 + kz - 1) / kz), 1);
 }
-inline int plane_blocks(const NLev& L, int kz) {
-    const dim3 g = plane_grid(L, false, kz);
+inline int plane_blocks(const NLev& L, bool half, int kz) {
+    const dim3 g = plane_grid(L, half, kz);
     return (int)(g.x * g.y);
 }
 constexpr int kKZr = kKZ;  // residual
@@ -446,6 +489,9 @@ static NHier* get(bxmg_ctx ctx, const bxmg_ba_s* ba, double h0) {
     l.h = h0;
     for (;;) {
         l.size = (long long)(l.n[0] + 1) * (l.n[1] + 1) * (l.n[2] + 1);
+        l.H = (l.n[0] + 2) / 2;
+        l.cs = ((long long)l.H * (l.n[1] + 1) * (l.n[2] + 1) + 63) / 64 * 64;
+        l.alloc = 2 * l.cs;
         H->L.push_back(l);
         bool more = true;
         for (int d = 0; d < 3; ++d)
@@ -456,21 +502,21 @@ static NHier* get(bxmg_ctx ctx, const bxmg_ba_s* ba, double h0) {
     }
     const NLev& B = H->L.back();
     if (B.size > 4096 * 8) throw std::runtime_error("nodal: bottom level too large");
-    if (H->L[0].size >= (1LL << 31)) throw std::runtime_error("nodal: more than 2^31 nodes");
+    if (H->L[0].alloc >= (1LL << 31)) throw std::runtime_error("nodal: more than 2^31 nodes");
     const size_t nl = H->L.size();
     H->u.resize(nl);
     H->f.resize(nl);
     H->r.resize(nl);
     for (size_t q = 0; q < nl; ++q) {
-        H->u[q].alloc(H->L[q].size);
-        H->f[q].alloc(H->L[q].size);
-        H->r[q].alloc(H->L[q].size);
+        H->u[q].alloc(H->L[q].alloc);
+        H->f[q].alloc(H->L[q].alloc);
+        H->r[q].alloc(H->L[q].alloc);
     }
     int np = 8192;
-    for (const NLev& l : H->L) np = std::max(np, plane_blocks(l, plane_depth(l, false, kKZr)));
+    for (const NLev& l : H->L) np = std::max(np, plane_blocks(l, true, plane_depth(l, true, kKZr)));
     H->part.alloc(3 * (size_t)np);
-    H->bp.alloc(B.size);
-    H->bq.alloc(B.size);
+    H->bp.alloc(B.alloc);
+    H->bq.alloc(B.alloc);
     H->fn.alloc(3);
     H->iters.alloc(1);
     if (C.h.size() >= 4) C.h.erase(C.h.begin());
@@ -486,12 +532,12 @@ static void vcycle(NHier& H, size_t l, hipStream_t s, int nu1, int nu2, double b
         HIPCHK(hipGetLastError());
         return;
     }
-    const int kg = plane_depth(L, true, kKZ), kr = plane_depth(L, false, kKZr);
+    const int kg = plane_depth(L, true, kKZ), kr = plane_depth(L, true, kKZr);
     const dim3 gb = plane_grid(L, true, kg);
     for (int q = 0; q < nu1; ++q)
         for (int c = 0; c < 2; ++c)
             hipLaunchKernelGGL(k_nd_gs, gb, dim3(kNB), 0, s, L, H.u[l].p, H.f[l].p, c, kg);
-    hipLaunchKernelGGL(k_nd_resid, plane_grid(L, false, kr), dim3(kNB), 0, s, L, H.u[l].p, H.f[l].p, H.r[l].p,
+    hipLaunchKernelGGL(k_nd_resid, plane_grid(L, true, kr), dim3(kNB), 0, s, L, H.u[l].p, H.f[l].p, H.r[l].p,
                        H.part.p, kr);
     const NLev& C = H.L[l + 1];
     const int kc = plane_depth(C, false, kKZt);
@@ -531,20 +577,24 @@ extern "C" bxmg_status bxmg_nodal_solve(bxmg_ctx ctx, const bxmg_solve_params* p
         const hipStream_t s = ctx->stream;
         const nodal::NLev& L0 = H->L[0];
         info->levels = (int)H->L.size();
-        HIPCHK(hipMemcpyAsync(H->u[0].p, phi, L0.size * sizeof(double), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(H->f[0].p, rhs, L0.size * sizeof(double), hipMemcpyDeviceToDevice, s));
         const unsigned nb = nodal::nblocks(L0.size);
-        const int kr0 = nodal::plane_depth(L0, false, nodal::kKZr);
+        // the caller's arrays into the colour-split level arrays
+        HIPCHK(hipMemsetAsync(H->u[0].p, 0, L0.alloc * sizeof(double), s));
+        HIPCHK(hipMemsetAsync(H->f[0].p, 0, L0.alloc * sizeof(double), s));
+        hipLaunchKernelGGL(nodal::k_nd_convert<true>, dim3(nb), dim3(nodal::kNB), 0, s, L0, phi, H->u[0].p);
+        hipLaunchKernelGGL(nodal::k_nd_convert<true>, dim3(nb), dim3(nodal::kNB), 0, s, L0, (double*)rhs, H->f[0].p);
+        HIPCHK(hipGetLastError());
+        const int kr0 = nodal::plane_depth(L0, true, nodal::kKZr);
         // norms reduced on the device and read back: of f (fonly) or of the
         // residual of the current iterate
         auto norms = [&](bool fonly, double out[3]) {
             if (fonly)
                 hipLaunchKernelGGL(nodal::k_nd_fnorm, dim3(nb), dim3(nodal::kNB), 0, s, L0, H->f[0].p, H->part.p);
             else
-                hipLaunchKernelGGL(nodal::k_nd_resid, nodal::plane_grid(L0, false, kr0), dim3(nodal::kNB), 0, s, L0,
+                hipLaunchKernelGGL(nodal::k_nd_resid, nodal::plane_grid(L0, true, kr0), dim3(nodal::kNB), 0, s, L0,
                                    H->u[0].p, H->f[0].p, H->r[0].p, H->part.p, kr0);
             HIPCHK(hipGetLastError());
-            HIPCHK(launch_norm_final(s, H->part.p, fonly ? (int)nb : nodal::plane_blocks(L0, kr0), H->fn.p));
+            HIPCHK(launch_norm_final(s, H->part.p, fonly ? (int)nb : nodal::plane_blocks(L0, true, kr0), H->fn.p));
             HIPCHK(hipMemcpyAsync(ctx->h_norm, H->fn.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             out[0] = ctx->h_norm[2] > 0.0 ? (double)NAN : ctx->h_norm[0];
@@ -579,7 +629,7 @@ extern "C" bxmg_status bxmg_nodal_solve(bxmg_ctx ctx, const bxmg_solve_params* p
                 nodal::vcycle(*H, 0, s, P.nu1, P.nu2, P.bottom_rtol);
             }
         } else {
-            HIPCHK(hipMemsetAsync(H->u[0].p, 0, L0.size * sizeof(double), s));  // f == 0: u = 0
+            HIPCHK(hipMemsetAsync(H->u[0].p, 0, L0.alloc * sizeof(double), s));  // f == 0: u = 0
         }
         info->cycles = cyc;
         if (status == 0) {
@@ -591,7 +641,8 @@ extern "C" bxmg_status bxmg_nodal_solve(bxmg_ctx ctx, const bxmg_solve_params* p
             hipLaunchKernelGGL(nodal::k_nd_copies, dim3(nodal::nblocks(L0.size)), dim3(nodal::kNB), 0, s, L0,
                                H->u[0].p);
             HIPCHK(hipGetLastError());
-            HIPCHK(hipMemcpyAsync(phi, H->u[0].p, L0.size * sizeof(double), hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(nodal::k_nd_convert<false>, dim3(nb), dim3(nodal::kNB), 0, s, L0, phi, H->u[0].p);
+            HIPCHK(hipGetLastError());
         }
         HIPCHK(hipStreamSynchronize(s));
         info->status = status;
