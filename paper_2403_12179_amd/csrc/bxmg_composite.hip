@@ -449,12 +449,12 @@ struct Comp {
     DevBuf<double> uf, ff, rf;
     DevBuf<FRB> frb;
     DevBuf<int> fmap;
-    DevBuf<GhostCopy> fx;  // ghosts between fine boxes
-    long long nfx = 0;
+    DevBuf<GhostCopy> fx;  // ghosts between fine boxes, colour-0 ghosts first
+    long long nfx = 0, nfx0 = 0;
     long long fslab = 0;  // elements per fine field
     DevBuf<int> cmap;
-    DevBuf<int4> ghosts;
-    int nghosts = 0;
+    DevBuf<int4> ghosts;  // coarse-fine ghosts, colour-0 ghosts first
+    int nghosts = 0, nghosts0 = 0;
     DevBuf<int4> special;  // uncovered coarse cells next to a covered one or on a domain face
     int nspecial = 0;
     int nfine = 0;
@@ -621,7 +621,7 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
     // face ghosts of each fine box: copies from the fine box that owns the
     // cell, or coarse-fine ghosts (their coarse cell is not covered)
     std::vector<int4> gl;
-    std::vector<GhostCopy> fx;
+    std::vector<GhostCopy> fx[2];  // by the colour of the ghost
     for (size_t b = 0; b < fb.size(); ++b) {
         const Box& B = fb[b];
         for (int d = 0; d < 3; ++d)
@@ -640,14 +640,19 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
                             GhostCopy p;
                             p.dst = (uint32_t)frb_at(frb[b], gx[0], gx[1], gx[2]);
                             p.src = (uint32_t)frb_at(frb[o], gx[0], gx[1], gx[2]);
-                            fx.push_back(p);
+                            fx[(gx[0] + gx[1] + gx[2]) & 1].push_back(p);
                         }
                     }
             }
     }
     if (gl.size() >= (size_t)(1u << 31) - kCB) throw std::runtime_error("too many coarse-fine ghost cells");
+    // colour 0 first: a sweep of colour c reads only the ghosts of colour 1 - c
+    std::stable_partition(gl.begin(), gl.end(), [](const int4& e) { return ((e.y + e.z + e.w) & 1) == 0; });
+    c->nghosts0 = (int)std::count_if(gl.begin(), gl.end(), [](const int4& e) { return ((e.y + e.z + e.w) & 1) == 0; });
+    c->nfx0 = (long long)fx[0].size();
+    fx[0].insert(fx[0].end(), fx[1].begin(), fx[1].end());
     c->nghosts = (int)gl.size();
-    c->nfx = (long long)fx.size();
+    c->nfx = (long long)fx[0].size();
     const unsigned nf = (unsigned)c->nfine;
     c->g_fine = dim3(cdiv(maxS, kCB), cdiv(maxnz, kKZ), nf);
     c->g_fine_s = dim3(cdiv(maxS, kCB), cdiv(maxnz, kKZs), nf);
@@ -669,7 +674,7 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
     }
     c->frb.upload_async(frb, s);
     c->fmap.upload_async(fmap, s);
-    c->fx.upload_async(fx, s);
+    c->fx.upload_async(fx[0], s);
     c->cmap.upload_async(cmap, s);
     c->special.upload_async(sl, s);
     c->ghosts.upload_async(gl, s);
@@ -752,16 +757,20 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemsetAsync(Uc, 0, c.Uc->bytes, s));
         HIPCHK(hipMemsetAsync(uf, 0, (size_t)c.fslab * sizeof(double), s));
-        auto fill_fine = [&]() {
-            if (c.nfx) HIPCHK(launch_fill_rb(s, uf, false, c.fx.p, c.nfx));
-            if (c.nghosts)
-                hipLaunchKernelGGL(comp::k_cf_ghost, dim3(comp::cdiv(c.nghosts, comp::kCB)), B, 0, s, c.ghosts.p,
-                                   c.nghosts, g, (const double*)Uc, fb, uf);
+        // ghosts of the fine level from the current state: all of them
+        // (colours < 0), or those of the given colour only
+        auto fill_fine = [&](int colour) {
+            const long long x0 = colour == 1 ? c.nfx0 : 0, x1 = colour == 0 ? c.nfx0 : c.nfx;
+            const int g0 = colour == 1 ? c.nghosts0 : 0, g1 = colour == 0 ? c.nghosts0 : c.nghosts;
+            if (x1 > x0) HIPCHK(launch_fill_rb(s, uf, false, c.fx.p + x0, x1 - x0));
+            if (g1 > g0)
+                hipLaunchKernelGGL(comp::k_cf_ghost, dim3(comp::cdiv(g1 - g0, comp::kCB)), B, 0, s, c.ghosts.p + g0,
+                                   g1 - g0, g, (const double*)Uc, fb, uf);
             HIPCHK(hipGetLastError());
         };
         // composite residual (fonly: norms of f) into rf / Rc, norms read back
         auto residual = [&](bool fonly, double out[3]) {
-            if (!fonly) fill_fine();
+            if (!fonly) fill_fine(-1);
             hipLaunchKernelGGL(comp::k_fine_resid, c.g_fine, B, 0, s, g, fb, (const double*)uf, (const double*)ff, rf,
                                (int)fonly, c.part.p);
             hipLaunchKernelGGL(comp::k_coarse_resid, c.g_coarse, B, 0, s, g, (const int*)c.cmap.p, (const double*)Uc,
@@ -781,7 +790,7 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
         auto sweeps = [&](int n) {
             for (int q = 0; q < n; ++q)
                 for (int col = 0; col < 2; ++col) {
-                    fill_fine();
+                    fill_fine(1 - col);  // the sweep of colour col reads ghosts of the other colour
                     hipLaunchKernelGGL(comp::k_fine_gs, c.g_fine_s, B, 0, s, g, fb, uf, (const double*)ff, col);
                     HIPCHK(hipGetLastError());
                 }
