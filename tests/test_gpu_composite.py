@@ -60,6 +60,7 @@ CASES = [
     (16, "lshape", 8, 8),
     (32, "centre", 16, 16),
     (32, "centre", 8, 12),   # ragged coarse boxes
+    (32, "holed", 8, 16),    # 63 abutting fine boxes, not merged: ghosts copied between them
 ]
 
 

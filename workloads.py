@@ -124,6 +124,7 @@ def composite_layout(n, kind="centre", max_box=32):
     fine boxes in fine indices (refinement ratio 2).
       centre : the central half of the domain refined ([n/4, 3n/4) coarse
                cells), chopped into fine boxes of edge max_box
+      holed  : the same boxes less the last one (their union is no rectangle)
       lshape : an L of two abutting fine boxes plus a detached one
     Coarse boxes: the domain chopped into boxes of edge min(n, 32)."""
     cb = chop_boxes(n, min(n, 32))
@@ -137,6 +138,16 @@ def composite_layout(n, kind="centre", max_box=32):
                     fb.append(((i, j, k), (min(i + max_box, hi) - 1, min(j + max_box, hi) - 1,
                                            min(k + max_box, hi) - 1)))
         return cb, fb
+    if kind == "holed":  # the central half in boxes of max_box, less its last box: not one rectangle
+        q = n // 4
+        lo, hi = 2 * q, 2 * (n - q)
+        fb = []
+        for k in range(lo, hi, max_box):
+            for j in range(lo, hi, max_box):
+                for i in range(lo, hi, max_box):
+                    fb.append(((i, j, k), (min(i + max_box, hi) - 1, min(j + max_box, hi) - 1,
+                                           min(k + max_box, hi) - 1)))
+        return cb, fb[:-1]
     if kind == "lshape":
         a = n // 4
         return cb, [((2 * a, 2 * a, 2 * a), (4 * a - 1, 4 * a - 1, 4 * a - 1)),
