@@ -59,12 +59,17 @@ constexpr int kKZ = 8;    // planes each thread walks (kernels that reduce norms
 constexpr int kKZs = 4;   // planes each thread walks in the fine sweeps and the interpolation
 
 // The coarse level: layout of the one-box fields and the domain.
+// The coarse level: the one-box layout of its solution and right-hand side
+// (F order, 1 ghost) and of the correction's colour-split level-0 arrays
+// (residual = the V-cycle's right-hand side, correction = its solution).
 struct CGeo {
-    FBox cb;           // every coarse field has this layout (one box, 1 ghost)
+    FBox cb;
     int dlo[3], n[3];  // coarse domain
     int per[3];
     double h0, h1;
     double ih0sq;  // 1 / h0^2
+    int rlo[3], rglo[3], rG[3], rH;  // colour-split layout of the correction arrays
+    long long rbase, rcs;
 };
 
 // A fine box in colour-split storage (grown by 1): colour block c of the
@@ -88,6 +93,12 @@ __host__ __device__ __forceinline__ long long frb_at(const FRB& b, int i, int j,
 // across (d, side) is covered, bit 6 when the cell lies on a domain face.
 __device__ __forceinline__ int cq(const CGeo& g, int I, int J, int K) {
     return (I - g.dlo[0]) + g.n[0] * ((J - g.dlo[1]) + g.n[1] * (K - g.dlo[2]));
+}
+
+// offset of coarse cell (I, J, K) in the correction arrays
+__device__ __forceinline__ long long ridx(const CGeo& g, int I, int J, int K) {
+    return g.rbase + ((I + J + K) & 1) * g.rcs +
+           (long long)(((K - g.rglo[2]) * g.rG[1] + (J - g.rglo[1])) * g.rH + ((I - g.rglo[0]) >> 1));
 }
 
 __device__ __forceinline__ long long fidx(const FBox& b, int i, int j, int k) {
@@ -244,17 +255,16 @@ __global__ void __launch_bounds__(kCB) k_fine_prolong(CGeo g, const FRB* __restr
     const int ts = t % ns, j = B.lo[1] + t / ns;
     const int k0 = B.lo[2] + bk.y * kKZs, k1 = min(k0 + kKZs - 1, B.hi[2]);
     const int J = j >> 1, sj = (j & 1) ? 1 : -1;
-    const long long sy = g.cb.G[0], sz = (long long)g.cb.G[0] * g.cb.G[1];
     for (int k = k0; k <= k1; ++k) {
         const int K = k >> 1, sk = (k & 1) ? 1 : -1;
         for (int e = 0; e < 2; ++e) {
             const int i = B.glo[0] + 2 * ts + e;
             if (i < B.lo[0] || i > B.hi[0]) continue;
             const int I = i >> 1, si = (i & 1) ? 1 : -1;
-            const long long q = fidx(g.cb, I, J, K), ex = si, ey = sj * sy, ez = sk * sz;
-            const double c000 = Ec[q], c100 = Ec[q + ex], c010 = Ec[q + ey], c001 = Ec[q + ez];
-            const double c110 = Ec[q + ex + ey], c101 = Ec[q + ex + ez], c011 = Ec[q + ey + ez];
-            const double c111 = Ec[q + ex + ey + ez];
+            const double c000 = Ec[ridx(g, I, J, K)], c100 = Ec[ridx(g, I + si, J, K)];
+            const double c010 = Ec[ridx(g, I, J + sj, K)], c001 = Ec[ridx(g, I, J, K + sk)];
+            const double c110 = Ec[ridx(g, I + si, J + sj, K)], c101 = Ec[ridx(g, I + si, J, K + sk)];
+            const double c011 = Ec[ridx(g, I, J + sj, K + sk)], c111 = Ec[ridx(g, I + si, J + sj, K + sk)];
             const double v = (((27.0 * c000 + 9.0 * ((c100 + c010) + c001)) + 3.0 * ((c110 + c101) + c011)) + c111) *
                              (1.0 / 64.0);
             const long long c = frb_at(B, i, j, k);
@@ -361,7 +371,7 @@ __global__ void __launch_bounds__(kCB) k_coarse_resid(CGeo g, const int* __restr
             const int code = cmap[cq(g, I, J, K)];
             const long long c = fidx(g.cb, I, J, K);
             if (code >= 0) {
-                if (!fonly) Rc[c] = mean8(rf, fb[code], 2 * I, 2 * J, 2 * K);
+                if (!fonly) Rc[ridx(g, I, J, K)] = mean8(rf, fb[code], 2 * I, 2 * J, 2 * K);
                 continue;
             }
             if (code != -1) continue;
@@ -372,7 +382,7 @@ __global__ void __launch_bounds__(kCB) k_coarse_resid(CGeo g, const int* __restr
                 const double uzm = Uc[c - sz], uzp = Uc[c + sz];
                 rv = rv - ((((uxm - UI) + (uxp - UI)) + ((uym - UI) + (uyp - UI))) + ((uzm - UI) + (uzp - UI))) *
                               g.ih0sq;
-                Rc[c] = rv;
+                Rc[ridx(g, I, J, K)] = rv;
             }
             norm_add(rv, mx, s2, bad);
         }
@@ -398,7 +408,7 @@ __global__ void __launch_bounds__(kCB) k_coarse_resid_special(CGeo g, const int4
         double rv = Fc[c];
         if (!fonly) {
             rv = rv - coarse_op_special(g, cmap, Uc, fb, uf, e.x, e.y, e.z, (-1 - e.w) & 63);
-            Rc[c] = rv;
+            Rc[ridx(g, e.x, e.y, e.z)] = rv;
         }
         norm_add(rv, mx, s2, bad);
     }
@@ -416,7 +426,7 @@ __global__ void __launch_bounds__(kCB) k_coarse_update(CGeo g, const int* __rest
     for (int K = K0; K <= K1; ++K) {
         if (cmap[cq(g, I, J, K)] >= 0) continue;
         const long long c = fidx(g.cb, I, J, K);
-        Uc[c] = Uc[c] + Ec[c];
+        Uc[c] = Uc[c] + Ec[ridx(g, I, J, K)];
     }
 }
 
@@ -442,7 +452,12 @@ struct Comp {
     uint64_t cba_id = 0, fba_id = 0;
     double h0 = 0.0;
     bxmg_boxarray one = nullptr;                                           // one box over the coarse domain
-    bxmg_multifab Uc = nullptr, Fc = nullptr, Rc = nullptr, Ec = nullptr;  // over `one`, 1 ghost
+    bxmg_multifab Uc = nullptr, Fc = nullptr;  // over `one`, 1 ghost
+    // the correction's own multigrid hierarchy over the coarse domain: its
+    // level-0 arrays are the residual (right-hand side) and the correction
+    std::shared_ptr<Hier> hier;
+    double *Rc = nullptr, *Ec = nullptr;
+    int levels = 0;
     CGeo geo{};
     // the fine level in colour-split storage: solution, right-hand side,
     // residual (one layout), its boxes, and the caller box -> storage box map
@@ -463,8 +478,12 @@ struct Comp {
     DevBuf<double> part, fn;
     double* h_norm = nullptr;  // pinned: the norms read back
     ~Comp() {
-        for (bxmg_multifab m : {Uc, Fc, Rc, Ec})
+        for (bxmg_multifab m : {Uc, Fc})
             if (m) bxmg_multifab_release(m);
+        if (hier) {
+            (void)hipStreamSynchronize(ctx ? ctx->stream : nullptr);
+            hier.reset();
+        }
         if (one) bxmg_boxarray_release(one);
         const hipStream_t s = ctx ? ctx->stream : nullptr;
         for (DevBuf<double>* b : {&uf, &ff, &rf, &part, &fn}) b->release_async(s);
@@ -526,9 +545,18 @@ static std::unique_ptr<Comp> build(bxmg_ctx ctx, const bxmg_ba_s* cba, const bxm
         throw std::runtime_error(bxmg_last_error());
     c->Uc = alloc_mf(ctx, c->one, 1);
     c->Fc = alloc_mf(ctx, c->one, 1);
-    c->Rc = alloc_mf(ctx, c->one, 1);
-    c->Ec = alloc_mf(ctx, c->one, 1);
+    c->hier = hier_create(ctx, c->one, h0);
+    RBox rb;
+    hier_level0(c->hier.get(), &c->Ec, &c->Rc, &rb, &c->levels);
     CGeo& g = c->geo;
+    for (int d = 0; d < 3; ++d) {
+        g.rlo[d] = rb.lo[d];
+        g.rglo[d] = rb.glo[d];
+        g.rG[d] = rb.G[d];
+    }
+    g.rH = rb.H;
+    g.rbase = rb.base;
+    g.rcs = rb.cstride;
     g.cb = c->Uc->fboxes[0];
     for (int d = 0; d < 3; ++d) {
         g.dlo[d] = D.lo[d];
@@ -737,8 +765,8 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
         const comp::CGeo& g = c.geo;
         double* Uc = (double*)c.Uc->data;
         double* Fc = (double*)c.Fc->data;
-        double* Rc = (double*)c.Rc->data;
-        double* Ec = (double*)c.Ec->data;
+        double* Rc = c.Rc;
+        double* Ec = c.Ec;
         double* uf = c.uf.p;
         double* ff = c.ff.p;
         double* rf = c.rf.p;
@@ -803,9 +831,8 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
             double rn[3];
             residual(false, rn);
             // coarse correction: one V-cycle from zero on the composite residual
-            int nlev = 0;
-            chk(vcycle_from_zero(ctx, Pc, c.Ec, c.Rc, &nlev));
-            info->levels = nlev + 1;
+            hier_vcycle_from_zero(ctx, c.hier.get(), Pc);
+            info->levels = c.levels + 1;
             hipLaunchKernelGGL(comp::k_coarse_update, c.g_coarse, B, 0, s, g, (const int*)c.cmap.p, Uc,
                                (const double*)Ec);
             hipLaunchKernelGGL(comp::k_fine_prolong, c.g_fine_s, B, 0, s, g, fb, uf, (const double*)Ec);

@@ -1416,36 +1416,34 @@ static bxmg_status solve_impl(bxmg_ctx ctx, const bxmg_solve_params* params, bxm
 
 }  // extern "C"
 
-// One FP64 V-cycle from a zero guess: phi = V(rhs), no stop test, no norms
-// (the composite solve's coarse correction).
-bxmg_status vcycle_from_zero(bxmg_ctx ctx, const bxmg_solve_params& P, bxmg_multifab phi, bxmg_multifab rhs,
-                             int* levels) {
-    const bxmg_ba_s* ba = phi->ba;
-    bxmg_status st;
-    if ((st = check_solve_mf(phi, ba, "phi")) != BXMG_OK || (st = check_solve_mf(rhs, ba, "rhs")) != BXMG_OK) return st;
-    if (!covers_domain(ba)) return fail(BXMG_EINVAL, "vcycle: the BoxArray must cover its domain");
-    const double h = (P.dx > 0) ? P.dx : 1.0 / ba->dom.n(0);
+std::shared_ptr<Hier> hier_create(bxmg_ctx ctx, const bxmg_ba_s* ba, double h) {
+    auto lb = make_hierarchy(ba->dom, ba->boxes);
+    if (!bottom_fits(lb.back().dom)) throw std::runtime_error("bottom level too large");
+    Tuning tune;
+    tune.zc = ctx->zc;
+    tune.zc_planes = ctx->zc_planes;
+    tune.res = ctx->res;
+    tune.ly_cap = ctx->ly_cap;
+    return std::shared_ptr<Hier>(build_hier(ba, 0, false, h, tune, ctx->merge != 0, 0.0).release());
+}
+
+void hier_level0(Hier* H, double** u, double** f, RBox* box, int* levels) {
+    const Level& L0 = *H->L[0];
+    *u = H->u64[0]->p;
+    *f = H->f64[0]->p;
+    *box = L0.rb.at(0);
+    *levels = (int)H->L.size();
+}
+
+void hier_vcycle_from_zero(bxmg_ctx ctx, Hier* H, const bxmg_solve_params& P) {
     std::lock_guard<std::mutex> lock(ctx->mu);
-    try {
-        HIPCHK(hipSetDevice(ctx->device));
-        st = BXMG_OK;
-        Hier* H = get_hier(ctx, ba, 0, false, h, &st, ctx->merge != 0, 0.0);
-        if (!H) return st;
-        if (levels) *levels = (int)H->L.size();
-        Run R{H, ctx->stream, P.nu1, P.nu2, P.prolong, P.bottom_rtol};
-        R.prof = &ctx->prof;
-        R.lds_coarse = ctx->lds_coarse != 0;
-        const Level& L0 = *H->L[0];
-        double* u = H->u64[0]->p;
-        HIPCHK(launch_fab_to_rb(R.s, L0.view_grid(), (const double*)rhs->data, rhs->d_fboxes.p, H->f64[0]->p, false));
-        HIPCHK(launch_zero<double>(R.s, u, L0.nelem));  // cells and ghosts: the zero guess's ghosts are zero too
-        vcycle<double>(R, 0);
-        HIPCHK(launch_rb_to_fab(R.s, L0.view_grid(), u, (double*)phi->data, phi->d_fboxes.p));
-        ctx->prof.harvest();
-    } catch (HipError& e) {
-        return fail(BXMG_EDEVICE, std::string("vcycle: ") + e.where + ": " + hipGetErrorString(e.e));
-    }
-    return BXMG_OK;
+    Run R{H, ctx->stream, P.nu1, P.nu2, P.prolong, P.bottom_rtol};
+    R.prof = &ctx->prof;
+    R.lds_coarse = ctx->lds_coarse != 0;
+    const Level& L0 = *H->L[0];
+    HIPCHK(launch_zero<double>(R.s, H->u64[0]->p, L0.nelem));
+    vcycle<double>(R, 0);
+    ctx->prof.harvest();
 }
 
 extern "C" {

@@ -760,9 +760,14 @@ inline bool bottom_fits(const Box& dom) {
     return dom.cells() <= kMaxBottomCells && grown <= kBottomGrown;
 }
 
-// One FP64 V-cycle of the Poisson operator from a zero guess, phi = V(rhs)
-// (constant coefficient, no stop test, no norms): the composite solve's
-// coarse correction.  phi and rhs as for bxmg_mlmg_solve; asynchronous on the
-// context's stream; *levels (if not NULL) gets the hierarchy's depth.
-bxmg_status vcycle_from_zero(bxmg_ctx ctx, const bxmg_solve_params& P, bxmg_multifab phi, bxmg_multifab rhs,
-                             int* levels);
+// An FP64 constant-coefficient Poisson hierarchy of ba owned by the caller
+// (not in the context's cache); throws std::runtime_error when its bottom
+// level is too large, HipError on device errors.
+std::shared_ptr<Hier> hier_create(bxmg_ctx ctx, const bxmg_ba_s* ba, double h);
+// Its level-0 colour-split arrays (solution, right-hand side), the layout of
+// its single level-0 box, and its depth.
+void hier_level0(Hier* H, double** u, double** f, RBox* box, int* levels);
+// One V-cycle from zero on the level-0 right-hand side as it stands;
+// asynchronous on the context's stream.
+void hier_vcycle_from_zero(bxmg_ctx ctx, Hier* H, const bxmg_solve_params& P);
+
