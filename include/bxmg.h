@@ -291,8 +291,9 @@ bxmg_status bxmg_nodal_solve(bxmg_ctx ctx, const bxmg_solve_params* params, bxmg
  * Component 0 of each field is used.  A fully periodic problem needs a
  * compatible rhs (zero volume-weighted sum over the unknowns) and returns a
  * solution defined up to a constant.  The per-layout state (one-box coarse
- * fields, the fine level's colour-split storage, coverage map, ghost and
- * boundary-cell lists) is cached on the context for the last layout;
+ * fields, the coarse correction's multigrid hierarchy, the fine level's
+ * colour-split storage, coverage map, ghost and boundary-cell lists) is
+ * cached on the context for the last layout;
  * composite solves on one context run one at a time.
  * Synchronous on the context's stream.  Returns info->status: OK, ENOCONV,
  * ENONFINITE, EINVAL (bad arguments or layout), ENOMEM or EDEVICE. */
