@@ -213,10 +213,14 @@ __device__ __forceinline__ double nsum(const double* __restrict__ u, const FRB& 
     return ((xm + xp) + (u[m - sy] + u[m + sy])) + (u[m - sz] + u[m + sz]);
 }
 
-// Fine residual r = f - L u on the valid cells (or the norms of f only),
-// with per-block norms (max, sum of squares, non-finite count).
+// The residual kernels' modes: the norms of f, the norms of the residual,
+// or the norms and the residual stored.
+enum { kNormsF = 0, kNormsR = 1, kStoreR = 2 };
+
+// Fine residual r = f - L u on the valid cells, with per-block norms (max,
+// sum of squares, non-finite count).
 __global__ void __launch_bounds__(kCB) k_fine_resid(CGeo g, const FRB* __restrict__ fb, const double* __restrict__ u,
-                                                    const double* __restrict__ f, double* __restrict__ r, int fonly,
+                                                    const double* __restrict__ f, double* __restrict__ r, int mode,
                                                     double* __restrict__ partials) {
     const uint3 bk = xcd_block();
     const FRB B = fb[bk.z];
@@ -233,9 +237,9 @@ __global__ void __launch_bounds__(kCB) k_fine_resid(CGeo g, const FRB* __restric
                 if (i < B.lo[0] || i > B.hi[0]) continue;
                 const long long c = frb_at(B, i, j, k);
                 double rv = f[c];
-                if (!fonly) {
+                if (mode != kNormsF) {
                     rv = rv - (nsum(u, B, i, j, k) - 6.0 * u[c]) * ih2;
-                    r[c] = rv;
+                    if (mode == kStoreR) r[c] = rv;
                 }
                 norm_add(rv, mx, s2, bad);
             }
@@ -354,11 +358,11 @@ __device__ __forceinline__ double coarse_op_special(const CGeo& g, const int* __
 // the mean of the fine residuals below them, uncovered interior cells with
 // no covered neighbour f - (7-point operator) (norms taken there); the other
 // uncovered cells (map entries below -1) are k_coarse_resid_special's.
-// fonly: the norms of f only, Rc untouched.
+// mode as for k_fine_resid (Rc written only with kStoreR).
 __global__ void __launch_bounds__(kCB) k_coarse_resid(CGeo g, const int* __restrict__ cmap,
                                                       const double* __restrict__ Uc, const double* __restrict__ Fc,
                                                       double* __restrict__ Rc, const FRB* __restrict__ fb,
-                                                      const double* __restrict__ rf, int fonly,
+                                                      const double* __restrict__ rf, int mode,
                                                       double* __restrict__ partials) {
     const uint3 bk = xcd_block();
     const int t = bk.x * kCB + threadIdx.x;
@@ -371,18 +375,18 @@ __global__ void __launch_bounds__(kCB) k_coarse_resid(CGeo g, const int* __restr
             const int code = cmap[cq(g, I, J, K)];
             const long long c = fidx(g.cb, I, J, K);
             if (code >= 0) {
-                if (!fonly) Rc[ridx(g, I, J, K)] = mean8(rf, fb[code], 2 * I, 2 * J, 2 * K);
+                if (mode == kStoreR) Rc[ridx(g, I, J, K)] = mean8(rf, fb[code], 2 * I, 2 * J, 2 * K);
                 continue;
             }
             if (code != -1) continue;
             double rv = Fc[c];
-            if (!fonly) {
+            if (mode != kNormsF) {
                 const double UI = Uc[c];
                 const double uxm = Uc[c - 1], uxp = Uc[c + 1], uym = Uc[c - sy], uyp = Uc[c + sy];
                 const double uzm = Uc[c - sz], uzp = Uc[c + sz];
                 rv = rv - ((((uxm - UI) + (uxp - UI)) + ((uym - UI) + (uyp - UI))) + ((uzm - UI) + (uzp - UI))) *
                               g.ih0sq;
-                Rc[ridx(g, I, J, K)] = rv;
+                if (mode == kStoreR) Rc[ridx(g, I, J, K)] = rv;
             }
             norm_add(rv, mx, s2, bad);
         }
@@ -398,7 +402,7 @@ __global__ void __launch_bounds__(kCB) k_coarse_resid_special(CGeo g, const int4
                                                               const double* __restrict__ Uc,
                                                               const double* __restrict__ Fc, double* __restrict__ Rc,
                                                               const FRB* __restrict__ fb,
-                                                              const double* __restrict__ uf, int fonly,
+                                                              const double* __restrict__ uf, int mode,
                                                               double* __restrict__ partials) {
     const int q = blockIdx.x * kCB + threadIdx.x;
     double mx = 0.0, s2 = 0.0, bad = 0.0;
@@ -406,9 +410,9 @@ __global__ void __launch_bounds__(kCB) k_coarse_resid_special(CGeo g, const int4
         const int4 e = list[q];
         const long long c = fidx(g.cb, e.x, e.y, e.z);
         double rv = Fc[c];
-        if (!fonly) {
+        if (mode != kNormsF) {
             rv = rv - coarse_op_special(g, cmap, Uc, fb, uf, e.x, e.y, e.z, (-1 - e.w) & 63);
-            Rc[ridx(g, e.x, e.y, e.z)] = rv;
+            if (mode == kStoreR) Rc[ridx(g, e.x, e.y, e.z)] = rv;
         }
         norm_add(rv, mx, s2, bad);
     }
@@ -796,18 +800,20 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
                                    g1 - g0, g, (const double*)Uc, fb, uf);
             HIPCHK(hipGetLastError());
         };
-        // composite residual (fonly: norms of f) into rf / Rc, norms read back
-        auto residual = [&](bool fonly, double out[3]) {
-            if (!fonly) fill_fine(-1);
+        // composite residual norms read back (mode: of f, of the residual, or
+        // with the residual stored into rf / Rc)
+        auto residual = [&](int mode, double* out) {
+            if (mode != comp::kNormsF) fill_fine(-1);
             hipLaunchKernelGGL(comp::k_fine_resid, c.g_fine, B, 0, s, g, fb, (const double*)uf, (const double*)ff, rf,
-                               (int)fonly, c.part.p);
+                               mode, c.part.p);
             hipLaunchKernelGGL(comp::k_coarse_resid, c.g_coarse, B, 0, s, g, (const int*)c.cmap.p, (const double*)Uc,
-                               (const double*)Fc, Rc, fb, (const double*)rf, (int)fonly, part_c);
+                               (const double*)Fc, Rc, fb, (const double*)rf, mode, part_c);
             if (c.nspecial)
                 hipLaunchKernelGGL(comp::k_coarse_resid_special, dim3(comp::cdiv(c.nspecial, comp::kCB)), B, 0, s, g,
                                    c.special.p, c.nspecial, (const int*)c.cmap.p, (const double*)Uc,
-                                   (const double*)Fc, Rc, fb, (const double*)uf, (int)fonly, part_s);
+                                   (const double*)Fc, Rc, fb, (const double*)uf, mode, part_s);
             HIPCHK(hipGetLastError());
+            if (!out) return;  // the residual is wanted, not its norms: no wait for the device
             HIPCHK(launch_norm_final(s, c.part.p, c.nparts, c.fn.p));
             HIPCHK(hipMemcpyAsync(c.h_norm, c.fn.p, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
@@ -828,8 +834,7 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
         Pc.dx = h0;
         auto cycle = [&]() {
             sweeps(P.nu1);
-            double rn[3];
-            residual(false, rn);
+            residual(comp::kStoreR, nullptr);  // the correction's right-hand side
             // coarse correction: one V-cycle from zero on the composite residual
             hier_vcycle_from_zero(ctx, c.hier.get(), Pc);
             info->levels = c.levels + 1;
@@ -842,7 +847,7 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
             HIPCHK(hipGetLastError());
         };
         double fz[3];
-        residual(true, fz);
+        residual(comp::kNormsF, fz);
         const double fnorm = fz[0];
         info->f_inf = fnorm;
         int status = 0, cyc = 0;
@@ -851,7 +856,7 @@ extern "C" bxmg_status bxmg_composite_solve(bxmg_ctx ctx, const bxmg_solve_param
         } else if (fnorm > 0.0) {
             for (;; ++cyc) {
                 double rn[3];
-                residual(false, rn);
+                residual(comp::kNormsR, rn);  // the stop test needs the norms only
                 if (cyc < kHist) {
                     info->hist[cyc] = rn[0] / fnorm;
                     info->hist_l2[cyc] = std::sqrt(rn[1]);
