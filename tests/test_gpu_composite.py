@@ -83,6 +83,23 @@ def test_fixed_cycles_elementwise(bx, orc, n, kind, fmax, cmax):
     assert ig.f_inf == pytest.approx(io["f_inf"], rel=1e-15)
 
 
+@pytest.mark.parametrize("per", [(1, 0, 0), (0, 1, 1)])
+def test_mixed_boundaries_elementwise(bx, orc, per):
+    """Periodic in some directions, Dirichlet in the others (non-singular)."""
+    n = 16
+    _, fb = W.composite_layout(n, "lshape")
+    cb = W.chop_boxes(n, 8)
+    fc, ff = rhs(n, fb, 91)
+    uc_o, uf_o, io = orc.composite_solve(n, per, cb, fb, fc, ff, fixed_cycles=3)
+    uc_g, uf_g, ig = gpu_solve(bx, n, per, cb, fb, fc, ff, fixed_cycles=3)
+    assert ig.status == 0 and io["status"] == 0
+    scale = max(np.abs(uc_o).max(), np.abs(uf_o).max())
+    fm = W.fine_mask(n, fb)
+    assert np.abs(uc_g - uc_o).max() <= 1e-9 * scale
+    assert np.abs(uf_g[fm] - uf_o[fm]).max() <= 1e-9 * scale
+    np.testing.assert_allclose(ig.hist, io["hist"], rtol=1e-7)
+
+
 @pytest.mark.parametrize("n,kind,fmax,cmax", CASES[:2])
 def test_converged(bx, orc, n, kind, fmax, cmax):
     _, fb = W.composite_layout(n, kind, max_box=fmax)
