@@ -391,36 +391,43 @@ def section_composite(bx, W, reps=3):
     return out, keep
 
 
-def make_batch_problems(bx, W, nprob=256, seed=4):
+def make_batch_problems(bx, W, nprob=256, seed=4, ctx=None):
     edges = W.batch_edges(nprob, seed)
     probs = []
     for p, e in enumerate(edges):
         ba = bx.BoxArray.chop((0, 0, 0), (e - 1,) * 3, 32, bc=(bx.PERIODIC,) * 3)
         f = W.uniform_rhs_device((e, e, e), 4000 + p, mean_zero=True)
-        probs.append(dict(e=e, ba=ba, f=f, phi=bx.MultiFab(ba).set_val(0.0),
-                          rhs=bx.MultiFab(ba).set_val(0.0).from_tensor(f)))
+        probs.append(dict(e=e, ba=ba, f=f, phi=bx.MultiFab(ba, ctx=ctx).set_val(0.0),
+                          rhs=bx.MultiFab(ba, ctx=ctx).set_val(0.0).from_tensor(f)))
     return probs
 
 
-def section_batched(bx, W, nsample=4):
+def section_batched(bx, W, nsample=4, tune_cache=None):
     """256 periodic problems, edges uniform over {32,48,64,96,128} (seed 4),
     max box 32, f ~ U[-1,1] minus its mean (seed 4000+p): the batch engine
     (FP32 V-cycles inside FP64 refinement, one launch per stage over all
-    problems, hipGraph) vs plain FP64 solves one at a time, both to 1e-10."""
+    problems, hipGraph) vs plain FP64 solves one at a time, both to 1e-10.
+    The batch runs on a context of its own whose launch shape is tuned on
+    this batch (tune_cache False: the default shape, no tuning)."""
     import torch
-    probs = make_batch_problems(bx, W)
+    from paper_2403_12179_amd import tuning
+    ctx = bx.Context(0)
+    probs = make_batch_problems(bx, W, ctx=ctx)
     cells = sum(p["e"] ** 3 for p in probs)
-    ctx = probs[0]["phi"].ctx
     out = {"workload": "batch_256_periodic_edges_32-128_maxbox32_tol1e-10", "problems": len(probs),
            "cells": cells, "boxes": sum(len(p["ba"]) for p in probs)}
-    # warm-up of both paths on a few problems (builds, graph capture)
+    if tune_cache is False:
+        tuned = dict(tuning.DEFAULT_SHAPE, source="default")
+        tuning.apply(ctx, tuned)
+    else:
+        tuned = tuning.tune_batch(ctx, [(p["phi"], p["rhs"], None, TOL) for p in probs], 12 << 30, 512,
+                                  cache=tune_cache, precision=1)
+    out["launch_shape"] = {k: v for k, v in tuned.items() if k != "format"}
+    # warm-up on a few problems (builds, graph capture)
     b = bx.Batch(ctx, 12 << 30, 512, precision=1)
     for p in probs[:4]:
         b.add(p["phi"], p["rhs"], rel_tol=TOL)
     b.run(2)
-    for p in probs[:4]:
-        p["phi"].set_val(0.0)
-        bx.mlmg_solve(p["phi"], p["rhs"], rel_tol=TOL)
     for p in probs:
         p["phi"].set_val(0.0)
     torch.cuda.synchronize()
@@ -444,7 +451,12 @@ def section_batched(bx, W, nsample=4):
     by_q = {ids[i]: r for i, r in done}
     keep = [dict(q=q, e=probs[q]["e"], f=host(probs[q]["f"]), u=probs[q]["phi"].to_global(),
                  cycles=by_q[q].cycles, per=(1, 1, 1), beta=None, tol=TOL) for q in sample]
-    # plain FP64, one problem after another
+    # plain FP64, one problem after another, in the default launch shape
+    tuning.apply(ctx, tuning.DEFAULT_SHAPE)
+    for p in probs[:4]:
+        p["phi"].set_val(0.0)
+        bx.mlmg_solve(p["phi"], p["rhs"], rel_tol=TOL)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     cyc64 = []
     for p in probs:
@@ -809,7 +821,10 @@ def main():
     ap.add_argument("--sections", default="c1,mixed,heat,nodal,composite,batched,serving",
                     help="other rows to measure after the headline (comma list; '' for none)")
     ap.add_argument("--serving-requests", type=int, default=2000)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="default launch shapes, no tuning")
+    ap.add_argument("--tune-cache", metavar="PATH",
+                    help="launch-shape cache file (default: BXMG_TUNE_CACHE or ~/.cache/bxmg/tune.json; "
+                         "'none' to time without a cache)")
     ap.add_argument("--no-headline", action="store_true", help="run only the sections (profiling)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("CSV", "OUT", "COMMAND"),
                     help="write a text summary of a rocprofv3 kernel_stats.csv")
@@ -849,8 +864,15 @@ def main():
 
     import torch
     import paper_2403_12179_amd as bx
+    from paper_2403_12179_amd import tuning
     import workloads as W
 
+    if args.no_autotune:
+        tune_cache = False
+    elif args.tune_cache:
+        tune_cache = False if args.tune_cache == "none" else tuning.TuneCache(args.tune_cache)
+    else:
+        tune_cache = None
     line = {}
     keep = {}
     if not args.no_headline:
@@ -864,7 +886,9 @@ def main():
             tuned = {"planes_per_thread": z, "buffer_addressing": r, "tile_rows_log2_cap": ly, "source": "--knobs"}
         elif not args.no_autotune:
             # the project autotuner picks the launch shapes on this workload
-            tuned = bx.autotune(bx.MultiFab(ba), rhs, cycles=6)
+            # (or takes them from its cache)
+            tuned = tuning.tune_solve(bx.MultiFab(ba), rhs, cache=tune_cache, cycles=6)
+            tuned.pop("format", None)
             z, r, ly = tuned["planes_per_thread"], tuned["buffer_addressing"], tuned["tile_rows_log2_cap"]
         else:
             z, r, ly = 4, 1, 8
@@ -976,7 +1000,7 @@ def main():
         elif name == "composite":
             line["composite"], keep["composite"] = section_composite(bx, W)
         elif name == "batched":
-            line["batched"], keep["batched"], keep["edges"] = section_batched(bx, W)
+            line["batched"], keep["batched"], keep["edges"] = section_batched(bx, W, tune_cache=tune_cache)
         elif name == "serving":
             line["serving"], keep["serving"] = section_serving(bx, W, args.serving_requests)
         else:

@@ -140,6 +140,18 @@ class Context:
         L.check(L.lib().bxmg_ctx_create(int(device), C.c_void_p(stream.cuda_stream), C.byref(h)))
         self._h = h
 
+    def tune(self, param, value):
+        """One launch-shape knob (bxmg_ctx_tune); applies to hierarchies and
+        batch plans built afterwards."""
+        L.check(L.lib().bxmg_ctx_tune(self._h, int(param), int(value)))
+
+    def set_launch_shape(self, planes_per_thread, buffer_addressing, tile_rows_log2_cap):
+        """Knobs 0 and 1 (planes per thread), 2 (32-bit buffer offsets) and 3
+        (log2 of the tile-row cap) together."""
+        for param, value in ((0, planes_per_thread), (1, planes_per_thread), (2, buffer_addressing),
+                             (3, tile_rows_log2_cap)):
+            self.tune(param, value)
+
     def close(self):
         if self._h:
             L.lib().bxmg_ctx_destroy(self._h)
