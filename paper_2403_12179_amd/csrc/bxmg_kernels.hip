@@ -1644,6 +1644,47 @@ __device__ __forceinline__ double bot_reduce(double v, double* sh) {
     return sh[32];
 }
 
+// Face ghost t of the CG's p grid (nx x ny x nz cells grown by one; the
+// 7-point stencil reads face ghosts only): t runs over the 2(ny nz + nx nz +
+// nx ny) face ghosts, x faces first, low side before high.  Returns the
+// ghost's index in the grown grid, the index of the cell it copies and the
+// sign (the periodic image, or odd reflection at a Dirichlet face).  Written
+// without arrays indexed by the direction, which would live in scratch.
+struct BottomGhost {
+    int dst, src;
+    double sgn;
+};
+__device__ __forceinline__ BottomGhost bottom_ghost(int t, int nx, int ny, int nz, bool px, bool py, bool pz) {
+    const int gx = nx + 2, gy = ny + 2;
+    const int nfx = ny * nz, nfy = nx * nz, nfz = nx * ny;
+    int gi, gj, gk, si, sj, sk;
+    bool per;
+    if (t < 2 * nfx) {
+        const int side = t / nfx, tt = t - side * nfx;
+        gj = sj = tt % ny;
+        gk = sk = tt / ny;
+        gi = side ? nx : -1;
+        si = px ? (side ? 0 : nx - 1) : (side ? nx - 1 : 0);
+        per = px;
+    } else if ((t -= 2 * nfx) < 2 * nfy) {
+        const int side = t / nfy, tt = t - side * nfy;
+        gi = si = tt % nx;
+        gk = sk = tt / nx;
+        gj = side ? ny : -1;
+        sj = py ? (side ? 0 : ny - 1) : (side ? ny - 1 : 0);
+        per = py;
+    } else {
+        t -= 2 * nfy;
+        const int side = t / nfz, tt = t - side * nfz;
+        gi = si = tt % nx;
+        gj = sj = tt / nx;
+        gk = side ? nz : -1;
+        sk = pz ? (side ? 0 : nz - 1) : (side ? nz - 1 : 0);
+        per = pz;
+    }
+    return {(gi + 1) + gx * ((gj + 1) + gy * (gk + 1)), (si + 1) + gx * ((sj + 1) + gy * (sk + 1)), per ? 1.0 : -1.0};
+}
+
 // The CG's vectors in LDS: p over the bottom grown by one cell, x, r, q over
 // its N cells, 40 reduction slots (bottom_lds_bytes on the host side).
 struct BottomLds {
@@ -1668,6 +1709,7 @@ __device__ void bottom_cg(T* __restrict__ u, const T* __restrict__ f, const Face
     double* q = S.q;
     double* sh = S.sh;
     const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+    const bool px = G.per[0] != 0, py = G.per[1] != 0, pz = G.per[2] != 0;
     const int N = nx * ny * nz;
     const int gx = nx + 2, gy = ny + 2;
     const double ih2 = 1.0 / (h * h);
@@ -1706,23 +1748,10 @@ __device__ void bottom_cg(T* __restrict__ u, const T* __restrict__ f, const Face
         const int maxit = 4 * N;
         for (it = 0; it < maxit;) {
             // ghosts of p: face ghosts only (7-point stencil)
-            const int nfx = ny * nz, nfy = nx * nz, nfz = nx * ny;
-            for (int t = threadIdx.x; t < 2 * (nfx + nfy + nfz); t += blockDim.x) {
-                int d, side, a, b;
-                int tt = t;
-                if (tt < 2 * nfx) { d = 0; side = tt / nfx; tt %= nfx; a = tt % ny; b = tt / ny; }
-                else if ((tt -= 2 * nfx) < 2 * nfy) { d = 1; side = tt / nfy; tt %= nfy; a = tt % nx; b = tt / nx; }
-                else { tt -= 2 * nfy; d = 2; side = tt / nfz; tt %= nfz; a = tt % nx; b = tt / nx; }
-                int gc[3], sc[3];
-                if (d == 0) { gc[1] = sc[1] = a; gc[2] = sc[2] = b; }
-                else if (d == 1) { gc[0] = sc[0] = a; gc[2] = sc[2] = b; }
-                else { gc[0] = sc[0] = a; gc[1] = sc[1] = b; }
-                const int nd = G.n[d];
-                gc[d] = side ? nd : -1;
-                double sgn = 1.0;
-                if (G.per[d]) sc[d] = side ? 0 : nd - 1;
-                else { sc[d] = side ? nd - 1 : 0; sgn = -1.0; }
-                p[pidx(gc[0], gc[1], gc[2])] = sgn * p[pidx(sc[0], sc[1], sc[2])];
+            const int nghost = 2 * (ny * nz + nx * nz + nx * ny);
+            for (int t = threadIdx.x; t < nghost; t += blockDim.x) {
+                const BottomGhost gh = bottom_ghost(t, nx, ny, nz, px, py, pz);
+                p[gh.dst] = gh.sgn * p[gh.src];
             }
             __syncthreads();
             double pAp = 0.0;
@@ -1817,8 +1846,10 @@ __device__ void bottom_cg_wave(T* __restrict__ u, const T* __restrict__ f, const
     double* p = S.p;
     const int lane = threadIdx.x;
     const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+    const bool px = G.per[0] != 0, py = G.per[1] != 0, pz = G.per[2] != 0;
     const int N = nx * ny * nz;
     const int gx = nx + 2, gy = ny + 2;
+    const int nghost = 2 * (ny * nz + nx * nz + nx * ny);
     const double ih2 = 1.0 / (h * h);
     const bool mine = lane < N;
     const int a = lane % nx, b = (lane / nx) % ny, c = lane / (nx * ny);
@@ -1847,24 +1878,9 @@ __device__ void bottom_cg_wave(T* __restrict__ u, const T* __restrict__ f, const
             // p with its face ghosts in LDS (7-point stencil)
             if (mine) p[pc] = pv;
             wave_lds_sync();
-            const int nfx = ny * nz, nfy = nx * nz, nfz = nx * ny;
-            for (int t = lane; t < 2 * (nfx + nfy + nfz); t += 64) {
-                int d, side, e, g;
-                int tt = t;
-                if (tt < 2 * nfx) { d = 0; side = tt / nfx; tt %= nfx; e = tt % ny; g = tt / ny; }
-                else if ((tt -= 2 * nfx) < 2 * nfy) { d = 1; side = tt / nfy; tt %= nfy; e = tt % nx; g = tt / nx; }
-                else { tt -= 2 * nfy; d = 2; side = tt / nfz; tt %= nfz; e = tt % nx; g = tt / nx; }
-                int gc[3], sc[3];
-                if (d == 0) { gc[1] = sc[1] = e; gc[2] = sc[2] = g; }
-                else if (d == 1) { gc[0] = sc[0] = e; gc[2] = sc[2] = g; }
-                else { gc[0] = sc[0] = e; gc[1] = sc[1] = g; }
-                const int nd = G.n[d];
-                gc[d] = side ? nd : -1;
-                double sgn = 1.0;
-                if (G.per[d]) sc[d] = side ? 0 : nd - 1;
-                else { sc[d] = side ? nd - 1 : 0; sgn = -1.0; }
-                p[(gc[0] + 1) + gx * ((gc[1] + 1) + gy * (gc[2] + 1))] =
-                    sgn * p[(sc[0] + 1) + gx * ((sc[1] + 1) + gy * (sc[2] + 1))];
+            for (int t = lane; t < nghost; t += 64) {
+                const BottomGhost gh = bottom_ghost(t, nx, ny, nz, px, py, pz);
+                p[gh.dst] = gh.sgn * p[gh.src];
             }
             wave_lds_sync();
             double qv = 0.0;
