@@ -202,6 +202,80 @@ def summarize_counters(d):
     print(json.dumps(out, indent=1))
 
 
+# C3 (512^3, cell beta): level-0 kernels whose HBM bytes the counters check,
+# with their algorithmic bytes per fine cell (one colour of a half-sweep
+# writes half the cells; beta is read at every cell once)
+C3_N = 512
+C3_KERNELS = [
+    ("FP64 GS, cell beta (one colour)", "k_gs<double, 1", 20.0),
+    ("FP32 GS, cell beta (one colour)", "k_gs<float, 1", 10.0),
+    ("FP64 residual with the float cast", "k_resid<double, 1, float", 28.0),
+    ("FP64 residual+restriction", "k_resid_restrict<double, 1>", 25.0),
+]
+C3_COUNTERS = os.path.join(ROOT, "profiles", "counters_c3_level0_512c512_varcoef.json")
+
+
+def summarize_counters_c3(d):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the C3 level-0 launches
+    in C3_KERNELS (the largest launches of each) and of the 1 GiB calibration
+    kernel, from the rocprofv3 --pmc databases under d/fetch and d/write;
+    writes the committed summary."""
+    import sqlite3
+
+    def rows(sub, counter):
+        dbs = glob.glob(os.path.join(sub, "**", "*.db"), recursive=True)
+        if not dbs:
+            raise SystemExit("no rocprofv3 database under %s" % sub)
+        out = []
+        for db in dbs:
+            con = sqlite3.connect(db)
+            out += list(con.execute("select dispatch_id, kernel_name, grid_size, value from counters_collection "
+                                    "where counter_name = ?", (counter,)))
+        return out
+
+    def largest(rs, match):
+        vals, grids = {}, {}
+        for disp, name, grid, value in rs:
+            if match in name:
+                vals[disp] = vals.get(disp, 0.0) + float(value)
+                grids[disp] = grid
+        top = max(grids.values(), default=0)
+        return [v for k, v in vals.items() if grids[k] == top]
+
+    cells = float(C3_N) ** 3
+    out = {"workload": "512^3 in 512 boxes of 64^3, cell beta, FP64 / FP32-in-FP64 / PCG solves to 1e-10",
+           "kernel_src_sha": src_sha(),
+           "commands": ["cd /tmp && timeout -s KILL 300 rocprofv3 --pmc %s -d $REPO/%s/%s -o c3 -- python3 "
+                        "$REPO/bench.py --no-headline --sections mixed --no-cpu-baseline --calibrate-copy"
+                        % (c, os.path.relpath(d, ROOT), sub) for c, sub in (("FETCH_SIZE", "fetch"),
+                                                                         ("WRITE_SIZE", "write"))],
+           "kernels": {}}
+    scale = {}
+    data = {}
+    for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        rs = rows(os.path.join(d, sub), counter)
+        cp = largest(rs, "MulFunctor")
+        if not cp:
+            raise SystemExit("no calibration dispatch for %s" % counter)
+        scale[counter] = (COPY_BYTES / 1024.0) / max(cp)
+        data[counter] = rs
+    out["fetch_scale"], out["write_scale"] = scale["FETCH_SIZE"], scale["WRITE_SIZE"]
+    for label, match, bpc in C3_KERNELS:
+        e = {"match": match, "algorithmic_bytes_per_launch": bpc * cells}
+        for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            v = largest(data[counter], match)
+            if not v:
+                raise SystemExit("no dispatches of %s for %s" % (match, counter))
+            e[counter.lower() + "_kib_per_launch"] = sum(v) / len(v)
+            e[counter.lower() + "_launches"] = len(v)
+        e["hbm_bytes_per_launch"] = 1024.0 * (e["fetch_size_kib_per_launch"] * scale["FETCH_SIZE"] +
+                                              e["write_size_kib_per_launch"] * scale["WRITE_SIZE"])
+        e["traffic_over_algorithmic"] = e["hbm_bytes_per_launch"] / e["algorithmic_bytes_per_launch"]
+        out["kernels"][label] = e
+    json.dump(out, open(C3_COUNTERS, "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
 # ------------------------------------------------------------ other rows
 def host(t):
     return np.asfortranarray(t.double().cpu().numpy())
@@ -820,6 +894,18 @@ def summarize_trace(csv_path, out_path, command):
     print("\n".join(lines[:25]))
 
 
+def calibrate_copy():
+    """An elementwise kernel that reads 1 GiB and writes 1 GiB (the scale of
+    the HBM byte counters)."""
+    import torch
+    a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -828,6 +914,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--summarize-counters", metavar="DIR")
+    ap.add_argument("--summarize-counters-c3", metavar="DIR")
     ap.add_argument("--sections", default="c1,mixed,heat,nodal,composite,batched,serving",
                     help="other rows to measure after the headline (comma list; '' for none)")
     ap.add_argument("--serving-requests", type=int, default=2000)
@@ -853,6 +940,9 @@ def main():
         return 0
     if args.summarize_counters:
         summarize_counters(args.summarize_counters)
+        return 0
+    if args.summarize_counters_c3:
+        summarize_counters_c3(args.summarize_counters_c3)
         return 0
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
@@ -931,13 +1021,7 @@ def main():
         if not res.ok:
             raise SystemExit("solve failed: %s" % res)
         if args.calibrate_copy:
-            # an elementwise kernel that reads 1 GiB and writes 1 GiB
-            a = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
-            b = torch.empty_like(a)
-            torch.cuda.synchronize()
-            torch.mul(a, 1.0, out=b)
-            torch.cuda.synchronize()
-            del a, b
+            calibrate_copy()
 
         # the same solve with the 512 boxes kept as boxes (one launch per stage
         # over every box's tiles, ghost exchanges between boxes): the fused
@@ -997,6 +1081,8 @@ def main():
         }
         del phi, rhs
         torch.cuda.empty_cache()
+    if args.no_headline and args.calibrate_copy:
+        calibrate_copy()
     for name in secs:
         print("bench: section %s" % name, file=sys.stderr, flush=True)
         if name == "c1":
