@@ -90,6 +90,7 @@ struct PlanLevel {
     std::vector<Tile> tcol, tdown;  // tiles of the level alone (box = local index)
     int stage_values = 0;           // prolongation: coarse values a colour tile reads (bound)
     DevBuf<GhostCopy> face[2], full;    // indices relative to the problem start
+    DevBuf<GhostCopy> face01;           // level 0: both colours' face ghosts in one list (admission)
     DevBuf<GhostCopy> cface[2], cfull;  // relative to the level start (coarse-cycle levels)
     long long fface[3] = {0, 0, 0};     // face-array offsets (variable coefficient)
 };
@@ -195,6 +196,11 @@ void plan_device(GeoPlan& P, const bxmg_ctx_s* ctx, bool var) {
         if ((int)l < P.cs) {
             v.face[0].upload(f0);
             v.face[1].upload(f1);
+            if (l == 0) {
+                std::vector<GhostCopy> both(f0);
+                both.insert(both.end(), f1.begin(), f1.end());
+                v.face01.upload(both);
+            }
         }
         if (l >= 1 && (int)l <= P.cs) v.full.upload(full);
         if ((int)l >= P.cs) {
@@ -313,7 +319,7 @@ struct bxmg_batch_s {
     DevBuf<double> norms, hist, hist_l2, fn3;
     int* h_active = nullptr;
     BatchSlot* h_st = nullptr;
-    double* h_hist = nullptr;  // 2 * kHist per slot (history, then L2 history)
+    double* h_hist = nullptr;  // the device's hist, then hist_l2 (kHist per slot each)
     std::vector<std::unique_ptr<Problem>> slots;
     std::deque<int> free_slots;
     int64_t next_id = 1;
@@ -709,16 +715,32 @@ void release_problem(bxmg_batch_s* b, int s) {
     b->free_slots.push_back(s);
 }
 
-// Enqueues the conversion of a stopped problem's solution into its phi and
-// the copy of its history (convert == false: phi is left as it was).
+// Enqueues the copy of stopped problems' histories: per problem for a few,
+// else the whole history arrays in two copies (one per array, instead of two
+// per problem).
+constexpr size_t kBulkHistory = 16;
+void copy_histories(bxmg_batch_s* b, const std::vector<int>& stopped) {
+    hipStream_t st = b->stream;
+    const size_t all = (size_t)b->max_slots * kHist;
+    if (stopped.size() > kBulkHistory) {
+        HIPCHK(hipMemcpyAsync(b->h_hist, b->hist.p, all * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(b->h_hist + all, b->hist_l2.p, all * sizeof(double), hipMemcpyDeviceToHost, st));
+        return;
+    }
+    for (int s : stopped) {
+        HIPCHK(hipMemcpyAsync(b->h_hist + (size_t)s * kHist, b->hist.p + (size_t)s * kHist, kHist * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(b->h_hist + all + (size_t)s * kHist, b->hist_l2.p + (size_t)s * kHist,
+                              kHist * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+}
+
+// Enqueues the conversion of a stopped problem's solution into its phi
+// (convert == false: phi is left as it was).
 void retire_enqueue(bxmg_batch_s* b, int s, bool convert) {
     const Problem& p = *b->slots[s];
     const GeoPlan& P = *p.plan;
     hipStream_t st = b->stream;
-    HIPCHK(hipMemcpyAsync(b->h_hist + (size_t)s * 2 * kHist, b->hist.p + (size_t)s * kHist, kHist * sizeof(double),
-                          hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(b->h_hist + (size_t)s * 2 * kHist + kHist, b->hist_l2.p + (size_t)s * kHist,
-                          kHist * sizeof(double), hipMemcpyDeviceToHost, st));
     if (!convert) return;
     const Grid g0 = P.grid0();
     if (b->h_st[s].fnorm == 0.0 && b->h_st[s].status == 0)  // f == 0: the solution is u = 0
@@ -742,10 +764,11 @@ void retire_finish(bxmg_batch_s* b, int s) {
     d.info.levels = (int)p.plan->L.size();
     d.info.nhist = std::min(S.nhist, kHist);
     d.info.f_inf = (S.status == kStatusNonFinite && S.nhist == 0) ? NAN : S.fnorm;
-    const double* h = b->h_hist + (size_t)s * 2 * kHist;
+    const double* h = b->h_hist + (size_t)s * kHist;
+    const double* h2 = b->h_hist + (size_t)b->max_slots * kHist + (size_t)s * kHist;
     for (int k = 0; k < d.info.nhist; ++k) {
         d.info.hist[k] = h[k];
-        d.info.hist_l2[k] = h[kHist + k];
+        d.info.hist_l2[k] = h2[k];
     }
     if (d.info.nhist > 0) {
         d.info.rel_resid_inf = d.info.hist[d.info.nhist - 1];
@@ -922,19 +945,19 @@ bxmg_status bxmg_batch_add(bxmg_batch b, bxmg_multifab phi, bxmg_multifab rhs, b
                 setup_faces<float>(s, q, b->b32.p + base, b->fa32.p);
             }
         }
-        // ghosts of the converted guess (later producers keep them current)
-        HIPCHK(launch_fill_rb(s, u, false, P.L[0].face[0].p, (long long)P.L[0].face[0].n));
-        HIPCHK(launch_fill_rb(s, u, false, P.L[0].face[1].p, (long long)P.L[0].face[1].n));
-        // ||f||_inf and the slot state, decided on the device
-        HIPCHK(launch_norm_final(s, b->scratch.p(), P.nt0, b->fn3.p + 3 * (size_t)slot));
+        // ghosts of the converted guess, both colours in one launch (later
+        // producers keep them current)
+        HIPCHK(launch_fill_rb(s, u, false, P.L[0].face01.p, (long long)P.L[0].face01.n));
+        // ||f||_inf and the slot state, decided on the device: the state goes
+        // in as a launch argument and the norm of f is reduced in the same launch
         BatchSlot S{};
         S.rel_tol = q.rel_tol;
         S.abs_tol = b->P.abs_tol;
         S.max_cycles = b->P.max_cycles;
         S.fixed_cycles = b->P.fixed_cycles;
-        b->h_st[slot] = S;  // pinned: the source of the copy below
-        HIPCHK(hipMemcpyAsync(b->st.p + slot, b->h_st + slot, sizeof S, hipMemcpyHostToDevice, s));
-        HIPCHK(launch_batch_admit(s, b->fn3.p + 3 * (size_t)slot, b->st.p, b->active.p, slot));
+        b->h_st[slot] = S;
+        HIPCHK(launch_batch_admit_norms(s, b->scratch.p(), P.nt0, S, b->fn3.p + 3 * (size_t)slot, b->st.p,
+                                        b->active.p, slot));
     } catch (HipError& e) {
         return fail(e.e == hipErrorOutOfMemory ? BXMG_ENOMEM : BXMG_EDEVICE,
                     std::string("batch_add: ") + e.where + ": " + hipGetErrorString(e.e));
@@ -995,6 +1018,7 @@ static bxmg_status batch_collect(bxmg_batch b, int32_t* nrunning) {
             for (int m = 0; m < b->max_slots; ++m)
                 if (b->slots[m] && !b->h_active[m]) stopped.push_back(m);
             if (!stopped.empty()) {
+                copy_histories(b, stopped);
                 // a right-hand side that was not finite leaves phi untouched
                 for (int m : stopped)
                     retire_enqueue(b, m, !(b->h_st[m].status == kStatusNonFinite && b->h_st[m].nhist == 0));

@@ -327,6 +327,11 @@ hipError_t launch_fill_sets(hipStream_t s, void* data, bool f32, const GhostSet*
 // Admission of one problem: ||f||_inf from fn3 (max, sum, bad) into st[slot],
 // and active[slot] = 1 unless f is zero or not finite.
 hipError_t launch_batch_admit(hipStream_t s, const double* fn3, BatchSlot* st, int* active, int slot);
+// The same decision with the norms of f reduced from n per-tile partials in
+// the same launch (fn3 receives them, as launch_norm_final writes them) and
+// the slot state S passed by value instead of copied to st[slot] beforehand.
+hipError_t launch_batch_admit_norms(hipStream_t s, const double* partials, int n, const BatchSlot& S, double* fn3,
+                                    BatchSlot* st, int* active, int slot);
 // Zero element ranges [start, start + len) of the problems still active.
 struct ZeroRange {
     long long start, len;

@@ -697,10 +697,12 @@ __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ 
 // partials before adding them (the reduction is latency-bound), in a fixed
 // order, so the result does not depend on timing.
 constexpr int kNormThreads = 1024, kNormUnroll = 4;
-__global__ void __launch_bounds__(kNormThreads) k_norm_final(const double* __restrict__ partials, int n,
-                                                            double* __restrict__ out) {
-    __shared__ double sh[3 * (kNormThreads / 64)];
-    double mx = 0.0, s2 = 0.0, bad = 0.0;
+// The reduction of k_norm_final, for a workgroup of kNormThreads.
+__device__ __forceinline__ void norm_reduce(const double* __restrict__ partials, int n, double* sh, double& mx,
+                                            double& s2, double& bad) {
+    mx = 0.0;
+    s2 = 0.0;
+    bad = 0.0;
     for (int q0 = threadIdx.x; q0 < n; q0 += kNormUnroll * kNormThreads) {
         double a[kNormUnroll][3];
 #pragma unroll
@@ -718,6 +720,13 @@ __global__ void __launch_bounds__(kNormThreads) k_norm_final(const double* __res
         }
     }
     block_reduce3(mx, s2, bad, sh);
+}
+
+__global__ void __launch_bounds__(kNormThreads) k_norm_final(const double* __restrict__ partials, int n,
+                                                            double* __restrict__ out) {
+    __shared__ double sh[3 * (kNormThreads / 64)];
+    double mx, s2, bad;
+    norm_reduce(partials, n, sh, mx, s2, bad);
     if (threadIdx.x == 0) { out[0] = mx; out[1] = s2; out[2] = bad; }
 }
 
@@ -2737,6 +2746,38 @@ hipError_t launch_fill_sets(hipStream_t s, void* data, bool f32, const GhostSet*
     const dim3 G((unsigned)std::min<long long>(nblk(max_n), 1024), (unsigned)nsets);
     if (f32) hipLaunchKernelGGL(k_fill_sets<float>, G, dim3(kBlock), 0, s, (float*)data, sets, active);
     else hipLaunchKernelGGL(k_fill_sets<double>, G, dim3(kBlock), 0, s, (double*)data, sets, active);
+    return hipGetLastError();
+}
+
+// Admission in one launch: the norms of f reduced from the per-tile partials
+// (as k_norm_final, into fn3), the slot state S written, then the decision
+// of k_batch_admit.
+__global__ void __launch_bounds__(kNormThreads) k_batch_admit_norms(const double* __restrict__ partials, int n,
+                                                                   BatchSlot S, double* __restrict__ fn3,
+                                                                   BatchSlot* __restrict__ st,
+                                                                   int* __restrict__ active, int slot) {
+    __shared__ double sh[3 * (kNormThreads / 64)];
+    double mx, s2, bad;
+    norm_reduce(partials, n, sh, mx, s2, bad);
+    if (threadIdx.x != 0) return;
+    fn3[0] = mx;
+    fn3[1] = s2;
+    fn3[2] = bad;
+    S.fnorm = mx;
+    int act = 1;
+    if (bad > 0.0) {
+        S.status = kStatusNonFinite;
+        act = 0;
+    } else if (!(mx > 0.0)) {
+        act = 0;  // f == 0: the solution is the initial guess
+    }
+    st[slot] = S;
+    active[slot] = act;
+}
+
+hipError_t launch_batch_admit_norms(hipStream_t s, const double* partials, int n, const BatchSlot& S, double* fn3,
+                                    BatchSlot* st, int* active, int slot) {
+    hipLaunchKernelGGL(k_batch_admit_norms, dim3(1), dim3(kNormThreads), 0, s, partials, n, S, fn3, st, active, slot);
     return hipGetLastError();
 }
 
