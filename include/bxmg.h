@@ -414,10 +414,13 @@ void bxmg_batch_destroy(bxmg_batch b);
  * cells, or level storage beyond 2^31 elements). */
 size_t bxmg_batch_footprint(bxmg_batch b, bxmg_boxarray ba);
 
-/* Admits a problem: enqueues the conversion of phi (initial guess), rhs
- * (and beta) into the arena and the computation of ||rhs||_inf on the
- * batch's stream, without waiting for them (a zero or non-finite rhs
- * retires the problem at the next step).  rel_tol <= 0: the batch's rel_tol.  The MultiFabs (FP64, nghost >= 1,
+/* Admits a problem: takes its slot and arena range now; the conversion of
+ * phi (initial guess), rhs (and beta) into the arena and ||rhs||_inf run at
+ * the next bxmg_batch_step / bxmg_batch_launch, together with every problem
+ * added since the last one, after the work the caller queued on the
+ * context's stream before that call (phi, rhs and beta must keep their
+ * values until then; a zero or non-finite rhs retires the problem at that
+ * step).  rel_tol <= 0: the batch's rel_tol.  The MultiFabs (FP64, nghost >= 1,
  * one BoxArray) must stay alive until the result is polled: phi receives
  * the solution.  BXMG_EBUSY: the footprint does not fit now or every slot
  * is taken (nothing changed); EINVAL: bad arguments or a domain a batch

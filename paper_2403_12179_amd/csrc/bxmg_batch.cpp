@@ -110,6 +110,8 @@ struct GeoPlan {
     DevBuf<RBox> vrb0;
     DevBuf<Tile> t0;
     int nt0 = 0;
+    std::vector<RBox> view0_h;  // host copies: the boxes of grid0() and its tiles
+    std::vector<Tile> t0_h;
     int res0 = 0;
     DevBuf<GhostCopy> full_even0;
     DevBuf<int> cbox0;
@@ -232,12 +234,16 @@ void plan_device(GeoPlan& P, const bxmg_ctx_s* ctx, bool var) {
             v.push_back(r);
         }
         P.vrb0.upload(v);
+        P.view0_h = v;
+    } else {
+        P.view0_h = L0.rb;
     }
     // the problem's own level-0 tiles over the caller's boxes: those over
     // which a lone solve sums the periodic mean (the conversions and the
     // norm of f run over them too)
     const std::vector<Tile> t0 = mean_tiles(colour_extents(P.boxes0)).tiles;
     P.t0.upload(t0);
+    P.t0_h = t0;
     P.nt0 = (int)t0.size();
     if (var) {
         P.full_even0.upload(ghost_list(build_tags(L0.dom, P.per, L0.boxes, 1, false, 2, false), L0.rb, 3));
@@ -270,6 +276,7 @@ struct Problem {
     int64_t id = 0;
     int slot = -1;
     bxmg_multifab phi = nullptr;
+    bxmg_multifab rhs = nullptr, beta = nullptr;  // read at admission
     std::shared_ptr<GeoPlan> plan;
     long long off = 0, foff = 0;  // arena ranges
     double rel_tol = 0;
@@ -333,6 +340,20 @@ struct bxmg_batch_s {
     std::vector<BLevel> lev;
     int lmax = 0;
     DevVec<int> tstart, segslot;
+    // problems added since the last launch, admitted together by its first launches
+    std::vector<int> pending;
+    DevVec<Tile> a_tiles;
+    DevVec<RBox> a_rb;
+    DevVec<ConvSrc> a_src;
+    DevVec<int> a_tstart, a_seg, a_slots;
+    DevVec<GhostSet> a_sets;
+    DevVec<BatchSlot> a_states;
+    DevVec<double> a_part;
+    // the stopped problems of a step, converted back together
+    DevVec<Tile> r_tiles, m_tiles;
+    DevVec<RBox> r_rb, m_rb;
+    DevVec<RetireBox> r_info, m_info;
+    DevVec<int> m_seg;
     int nseg = 0;
     DevVec<double> partials, scratch;
     DevVec<ZeroRange> z0;
@@ -735,21 +756,65 @@ void copy_histories(bxmg_batch_s* b, const std::vector<int>& stopped) {
     }
 }
 
-// Enqueues the conversion of a stopped problem's solution into its phi
-// (convert == false: phi is left as it was).
-void retire_enqueue(bxmg_batch_s* b, int s, bool convert) {
-    const Problem& p = *b->slots[s];
+// Enqueues the conversion of stopped problems' solutions into their phi:
+// the zero solution of a zero right-hand side per problem, then for all of
+// them at once the mean subtraction of the fully periodic ones and the
+// conversion into the caller layout (a few launches for any number).
+void append_retire(const Problem& p, int seg, std::vector<Tile>& tiles, std::vector<RBox>& rbs,
+                   std::vector<RetireBox>& info) {
     const GeoPlan& P = *p.plan;
-    hipStream_t st = b->stream;
-    if (!convert) return;
-    const Grid g0 = P.grid0();
-    if (b->h_st[s].fnorm == 0.0 && b->h_st[s].status == 0)  // f == 0: the solution is u = 0
-        HIPCHK(launch_zero<double>(st, b->u64.p + p.off + P.L[0].off, P.L[0].nelem));
-    if (P.per[0] && P.per[1] && P.per[2]) {
-        b->scratch.reserve(3 * (size_t)P.nt0 + 8);
-        HIPCHK(launch_mean_sub(st, g0, b->u64.p + p.off, b->scratch.p()));
+    const int box0 = (int)rbs.size(), t0 = (int)tiles.size();
+    for (size_t k = 0; k < P.view0_h.size(); ++k) {
+        RBox r = P.view0_h[k];
+        r.base += p.off;
+        rbs.push_back(r);
+        RetireBox R{};
+        R.fab = (double*)p.phi->data;
+        R.f = p.phi->fboxes[k];
+        R.tstart = t0;
+        R.nt = (int)P.t0_h.size();
+        R.seg = seg;
+        info.push_back(R);
     }
-    HIPCHK(launch_rb_to_fab(st, g0, b->u64.p + p.off, (double*)p.phi->data, p.phi->d_fboxes.p));
+    for (Tile t : P.t0_h) {
+        t.box += box0;
+        tiles.push_back(t);
+    }
+}
+
+void retire_convert(bxmg_batch_s* b, const std::vector<int>& conv) {
+    if (conv.empty()) return;
+    hipStream_t st = b->stream;
+    std::vector<Tile> tiles, mtiles;
+    std::vector<RBox> rbs, mrbs;
+    std::vector<RetireBox> info, minfo;
+    std::vector<int> mseg{0};
+    for (int s : conv) {
+        const Problem& p = *b->slots[s];
+        const GeoPlan& P = *p.plan;
+        if (b->h_st[s].fnorm == 0.0 && b->h_st[s].status == 0)  // f == 0: the solution is u = 0
+            HIPCHK(launch_zero<double>(st, b->u64.p + p.off + P.L[0].off, P.L[0].nelem));
+        append_retire(p, 0, tiles, rbs, info);
+        if (P.per[0] && P.per[1] && P.per[2]) {
+            append_retire(p, (int)mseg.size() - 1, mtiles, mrbs, minfo);
+            mseg.push_back((int)mtiles.size());
+        }
+    }
+    if (!mtiles.empty()) {
+        b->m_tiles.assign(mtiles);
+        b->m_rb.assign(mrbs);
+        b->m_info.assign(minfo);
+        b->m_seg.assign(mseg);
+        b->scratch.reserve(3 * (mtiles.size() + mseg.size()) + 8);
+        const Grid mg{b->m_rb.p(), b->m_tiles.p(), (int)mtiles.size(), 0, nullptr, 0, 0};
+        HIPCHK(launch_mean_sub_many(st, mg, b->m_info.p(), b->m_seg.p(), (int)mseg.size() - 1, b->u64.p,
+                                    b->scratch.p()));
+    }
+    b->r_tiles.assign(tiles);
+    b->r_rb.assign(rbs);
+    b->r_info.assign(info);
+    const Grid g{b->r_rb.p(), b->r_tiles.p(), (int)tiles.size(), 0, nullptr, 0, 0};
+    HIPCHK(launch_rb_to_fab_many(st, g, b->u64.p, b->r_info.p()));
 }
 
 // After the stream drained: the result record, then the slot and ranges go back.
@@ -883,7 +948,6 @@ bxmg_status bxmg_batch_add(bxmg_batch b, bxmg_multifab phi, bxmg_multifab rhs, b
     std::lock_guard<std::mutex> lock(b->ctx->mu);
     if (b->inflight) return fail(BXMG_EINVAL, "batch_add: collect the launched cycles first");
     const double h = (b->P.dx > 0) ? b->P.dx : 1.0 / ba->dom.n(0);
-    hipStream_t s = b->stream;
     try {
         HIPCHK(hipSetDevice(b->ctx->device));
         std::string why;
@@ -914,6 +978,8 @@ bxmg_status bxmg_batch_add(bxmg_batch b, bxmg_multifab phi, bxmg_multifab rhs, b
         p->slot = slot;
         p->id = b->next_id++;
         p->phi = phi;
+        p->rhs = rhs;
+        p->beta = beta;
         p->plan = plan;
         p->off = base;
         p->foff = fbase;
@@ -923,46 +989,99 @@ bxmg_status bxmg_batch_add(bxmg_batch b, bxmg_multifab phi, bxmg_multifab rhs, b
         b->h_active[slot] = 1;  // until the device says otherwise
         b->dirty = true;
         *id = b->slots[slot]->id;
-        const Problem& q = *b->slots[slot];
-        // the caller's writes to phi, rhs and beta come first
-        HIPCHK(hipEventRecord(b->caller_ready, b->ctx->stream));
-        HIPCHK(hipStreamWaitEvent(s, b->caller_ready, 0));
-        const Grid g0 = P.grid0();
-        double* u = b->u64.p + base;
-        double* f = b->f64.p + base;
-        HIPCHK(launch_fab_to_rb(s, g0, (const double*)phi->data, phi->d_fboxes.p, u, false));
-        // f, with the norms of f per tile on the way (reduced below)
-        b->scratch.reserve(3 * (size_t)P.nt0 + 8);
-        HIPCHK(launch_fab_to_rb_norm(s, g0, (const double*)rhs->data, rhs->d_fboxes.p, f, b->scratch.p()));
-        if (b->var) {
-            double* bt = b->b64.p + base;
-            HIPCHK(launch_fab_to_rb(s, g0, (const double*)beta->data, beta->d_fboxes.p, bt, false));
-            if (b->prec == 0) {
-                setup_faces<double>(s, q, bt, b->fa64.p);
-            } else {
-                HIPCHK(launch_fill_rb(s, bt, false, P.full_even0.p, (long long)P.full_even0.n));
-                HIPCHK(launch_cast_f32(s, bt + P.L[0].off, b->b32.p + base + P.L[0].off, P.L[0].nelem));
-                setup_faces<float>(s, q, b->b32.p + base, b->fa32.p);
-            }
-        }
-        // ghosts of the converted guess, both colours in one launch (later
-        // producers keep them current)
-        HIPCHK(launch_fill_rb(s, u, false, P.L[0].face01.p, (long long)P.L[0].face01.n));
-        // ||f||_inf and the slot state, decided on the device: the state goes
-        // in as a launch argument and the norm of f is reduced in the same launch
+        // the slot state; conversions and the admission decision run with
+        // the other problems added before the next launch (admit_pending)
         BatchSlot S{};
-        S.rel_tol = q.rel_tol;
+        S.rel_tol = b->slots[slot]->rel_tol;
         S.abs_tol = b->P.abs_tol;
         S.max_cycles = b->P.max_cycles;
         S.fixed_cycles = b->P.fixed_cycles;
         b->h_st[slot] = S;
-        HIPCHK(launch_batch_admit_norms(s, b->scratch.p(), P.nt0, S, b->fn3.p + 3 * (size_t)slot, b->st.p,
-                                        b->active.p, slot));
+        b->pending.push_back(slot);
     } catch (HipError& e) {
         return fail(e.e == hipErrorOutOfMemory ? BXMG_ENOMEM : BXMG_EDEVICE,
                     std::string("batch_add: ") + e.where + ": " + hipGetErrorString(e.e));
     }
     return BXMG_OK;
+}
+
+// Admission of every problem added since the last launch, after the work
+// the caller queued on the context's stream so far: the initial guesses and
+// right-hand sides of all of them in one conversion launch (with the norms of
+// f per tile), their face ghosts in one fill, the norms of f reduced per
+// problem, coefficient setup (variable beta, per problem), and the decision
+// of every slot in one launch.  Six launches for any number of problems
+// (plus the coefficient setup), instead of several per problem.
+void admit_pending(bxmg_batch_s* b, hipStream_t s) {
+    if (b->pending.empty()) return;
+    HIPCHK(hipEventRecord(b->caller_ready, b->ctx->stream));
+    HIPCHK(hipStreamWaitEvent(s, b->caller_ready, 0));
+    std::vector<Tile> tiles;
+    std::vector<RBox> rbs;
+    std::vector<ConvSrc> srcs;
+    std::vector<int> tstart{0}, seg;
+    std::vector<GhostSet> sets;
+    std::vector<BatchSlot> states;
+    long long max_ghosts = 0;
+    for (int slot : b->pending) {
+        const Problem& q = *b->slots[slot];
+        const GeoPlan& P = *q.plan;
+        const int box0 = (int)rbs.size();
+        for (size_t k = 0; k < P.view0_h.size(); ++k) {
+            RBox r = P.view0_h[k];
+            r.base += q.off;
+            rbs.push_back(r);
+            ConvSrc c;
+            c.phi = (const double*)q.phi->data;
+            c.rhs = (const double*)q.rhs->data;
+            c.fphi = q.phi->fboxes[k];
+            c.frhs = q.rhs->fboxes[k];
+            srcs.push_back(c);
+        }
+        for (Tile t : P.t0_h) {
+            t.box += box0;
+            tiles.push_back(t);
+        }
+        tstart.push_back((int)tiles.size());
+        seg.push_back(slot);
+        const DevBuf<GhostCopy>& fl = P.L[0].face01;
+        sets.push_back(GhostSet{fl.p, (long long)fl.n, q.off, slot, 0});
+        max_ghosts = std::max(max_ghosts, (long long)fl.n);
+        states.push_back(b->h_st[slot]);
+    }
+    b->a_tiles.assign(tiles);
+    b->a_rb.assign(rbs);
+    b->a_src.assign(srcs);
+    b->a_tstart.assign(tstart);
+    b->a_seg.assign(seg);
+    b->a_slots.assign(b->pending);
+    b->a_sets.assign(sets);
+    b->a_states.assign(states);
+    b->a_part.reserve(3 * tiles.size() + 8);
+    const Grid g{b->a_rb.p(), b->a_tiles.p(), (int)tiles.size(), 0, nullptr, 0, 0};
+    HIPCHK(launch_admit_convert(s, g, b->a_src.p(), b->u64.p, b->f64.p, b->a_part.p()));
+    // ghosts of the converted guesses (later producers keep them current)
+    HIPCHK(launch_fill_sets(s, b->u64.p, false, b->a_sets.p(), (int)sets.size(), max_ghosts, nullptr));
+    HIPCHK(launch_norm_seg(s, b->a_part.p(), b->a_tstart.p(), b->a_seg.p(), (int)seg.size(), nullptr, b->fn3.p));
+    if (b->var) {
+        for (int slot : b->pending) {
+            const Problem& q = *b->slots[slot];
+            const GeoPlan& P = *q.plan;
+            const Grid g0 = P.grid0();
+            double* bt = b->b64.p + q.off;
+            HIPCHK(launch_fab_to_rb(s, g0, (const double*)q.beta->data, q.beta->d_fboxes.p, bt, false));
+            if (b->prec == 0) {
+                setup_faces<double>(s, q, bt, b->fa64.p);
+            } else {
+                HIPCHK(launch_fill_rb(s, bt, false, P.full_even0.p, (long long)P.full_even0.n));
+                HIPCHK(launch_cast_f32(s, bt + P.L[0].off, b->b32.p + q.off + P.L[0].off, P.L[0].nelem));
+                setup_faces<float>(s, q, b->b32.p + q.off, b->fa32.p);
+            }
+        }
+    }
+    HIPCHK(launch_batch_admit_many(s, b->fn3.p, b->a_states.p(), b->a_slots.p(), (int)b->pending.size(), b->st.p,
+                                   b->active.p));
+    b->pending.clear();
 }
 
 static bxmg_status batch_launch(bxmg_batch b, int32_t ncycles) {
@@ -971,6 +1090,7 @@ static bxmg_status batch_launch(bxmg_batch b, int32_t ncycles) {
     hipStream_t s = b->stream;
     try {
         HIPCHK(hipSetDevice(b->ctx->device));
+        admit_pending(b, s);
         if (b->dirty) {
             rebuild(b);
             b->stable = 0;
@@ -1020,8 +1140,10 @@ static bxmg_status batch_collect(bxmg_batch b, int32_t* nrunning) {
             if (!stopped.empty()) {
                 copy_histories(b, stopped);
                 // a right-hand side that was not finite leaves phi untouched
+                std::vector<int> conv;
                 for (int m : stopped)
-                    retire_enqueue(b, m, !(b->h_st[m].status == kStatusNonFinite && b->h_st[m].nhist == 0));
+                    if (!(b->h_st[m].status == kStatusNonFinite && b->h_st[m].nhist == 0)) conv.push_back(m);
+                retire_convert(b, conv);
                 HIPCHK(hipStreamSynchronize(s));
                 for (int m : stopped) retire_finish(b, m);
                 // retired problems cost only idle blocks; the launch lists are
@@ -1091,6 +1213,13 @@ bxmg_status bxmg_batch_remove(bxmg_batch b, int64_t id) {
     if (b->inflight) return fail(BXMG_EINVAL, "batch_remove: collect the launched cycles first");
     for (int s = 0; s < b->max_slots; ++s)
         if (b->slots[s] && b->slots[s]->id == id) {
+            auto pend = std::find(b->pending.begin(), b->pending.end(), s);
+            if (pend != b->pending.end()) {  // not admitted on the device yet
+                b->pending.erase(pend);
+                release_problem(b, s);
+                b->dirty = true;
+                return BXMG_OK;
+            }
             try {
                 HIPCHK(hipSetDevice(b->ctx->device));
                 HIPCHK(hipStreamSynchronize(b->stream));

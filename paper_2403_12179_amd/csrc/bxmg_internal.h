@@ -276,6 +276,23 @@ hipError_t launch_add_f32(hipStream_t s, const Grid& g, double* u, const float* 
 
 // periodic projection: subtract the mean of the valid cells
 hipError_t launch_mean_sub(hipStream_t s, const Grid& g, double* u, double* scratch);
+// Retirement of many problems at once.  Box q of a launch grid belongs to
+// problem seg (of the launch) whose tiles are [tstart, tstart + nt) of the
+// grid, and writes its solution to fab (FBox f, base relative to fab).
+struct RetireBox {
+    double* fab;
+    FBox f;
+    int tstart, nt, seg, pad;
+};
+// The mean subtraction of launch_mean_sub for every problem of g (bitwise
+// the same: each tile's partial sum sits where a launch over that problem
+// alone puts it, and each problem's partials are reduced as there);
+// seg_tiles[q..q+1] = tile range of problem q (nseg problems); scratch holds
+// 3 per tile of g plus 3 per problem.
+hipError_t launch_mean_sub_many(hipStream_t s, const Grid& g, const RetireBox* info, const int* seg_tiles, int nseg,
+                                double* u, double* scratch);
+// launch_rb_to_fab for every box of g into its own problem's MultiFab.
+hipError_t launch_rb_to_fab_many(hipStream_t s, const Grid& g, const double* rb, const RetireBox* info);
 
 // variable coefficient setup
 template <class T>
@@ -327,6 +344,23 @@ hipError_t launch_fill_sets(hipStream_t s, void* data, bool f32, const GhostSet*
 // Admission of one problem: ||f||_inf from fn3 (max, sum, bad) into st[slot],
 // and active[slot] = 1 unless f is zero or not finite.
 hipError_t launch_batch_admit(hipStream_t s, const double* fn3, BatchSlot* st, int* active, int slot);
+// Admission of n problems in one launch each way: box q of the launch grid g
+// reads the caller's initial guess and right-hand side through src[q]
+// (pointers, and FBoxes whose bases are relative to them) and writes them
+// into level storage u and f through RBox q (bases relative to u and f);
+// partials[3 t] receive the right-hand side's norms of tile t (g's tile
+// order, so each problem's tiles form one range for launch_norm_seg).
+struct ConvSrc {
+    const double* phi;
+    const double* rhs;
+    FBox fphi, frhs;
+};
+hipError_t launch_admit_convert(hipStream_t s, const Grid& g, const ConvSrc* src, double* u, double* f,
+                                double* partials);
+// For q < n: slot = slots[q] takes state states[q] with ||f|| from norms[3 slot]
+// and the decision of launch_batch_admit.
+hipError_t launch_batch_admit_many(hipStream_t s, const double* norms, const BatchSlot* states, const int* slots,
+                                   int n, BatchSlot* st, int* active);
 // The same decision with the norms of f reduced from n per-tile partials in
 // the same launch (fn3 receives them, as launch_norm_final writes them) and
 // the slot state S passed by value instead of copied to st[slot] beforehand.

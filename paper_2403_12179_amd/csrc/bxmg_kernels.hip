@@ -788,6 +788,43 @@ __global__ void __launch_bounds__(kBlock) k_fab_to_rb_norm(Grid g, const double*
     }
 }
 
+// Admission of many problems: the initial guess and the right-hand side of
+// every box of the launch converted into level storage, the right-hand
+// side's norms per tile (k_fab_to_rb and k_fab_to_rb_norm over boxes with
+// their own source arrays).
+__global__ void __launch_bounds__(kBlock) k_admit_convert(Grid g, const ConvSrc* __restrict__ src,
+                                                         double* __restrict__ u, double* __restrict__ f,
+                                                         double* __restrict__ partials) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    double mx = 0.0, s2 = 0.0, bad = 0.0;
+    const int tix = tile_index(g.rev);
+    const Tile tl = g.tiles[tix];
+    const RBox B = g.boxes[tl.box];
+    const ConvSrc S = src[tl.box];
+    const TileThread th = tile_thread(tl);
+    const int j = B.lo[1] + th.y;
+    if (j <= B.hi[1])
+        for (int z = 0; z < (int)tl.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            if (k > B.hi[2]) break;
+            for (int c = 0; c < 2; ++c) {
+                const int i = colour_i(B, th.x, j, k, c);
+                if (i > B.hi[0]) continue;
+                const long long o = rb_idx(B, i, j, k);
+                u[o] = S.phi[fab_idx(S.fphi, i, j, k)];
+                const double v = S.rhs[fab_idx(S.frhs, i, j, k)];
+                f[o] = v;
+                acc_norm(v, mx, s2, bad);
+            }
+        }
+    block_reduce3(mx, s2, bad, sh);
+    if (threadIdx.x == 0) {
+        partials[3 * tix] = mx;
+        partials[3 * tix + 1] = s2;
+        partials[3 * tix + 2] = bad;
+    }
+}
+
 // Heat-step right-hand side: f = -((u * inv_dt) + s) at every valid cell,
 // written into level storage, with its norms (as k_fab_to_rb_norm).
 __global__ void __launch_bounds__(kBlock) k_heat_rhs(Grid g, const double* __restrict__ u,
@@ -1553,6 +1590,70 @@ __global__ void __launch_bounds__(kBlock) k_sum_valid(Grid g, const double* __re
 __global__ void __launch_bounds__(kBlock) k_sub_mean(Grid g, double* __restrict__ u, const double* __restrict__ tot) {
     const double mean = tot[1] / tot[2];
     BXMG_FOR_VALID_CELLS(g, const long long idx = rb_idx(B, i, j, k); u[idx] = u[idx] - mean)
+}
+
+// Block of a launch over n tiles that tile_index sends to tile t (rev = 0):
+// where a launch over one problem's tiles alone puts tile t's partial.
+__device__ __forceinline__ int solo_block(int t, int n) {
+    if ((n & 7) == 0) {
+        const int per = n >> 3;
+        return (t % per) * 8 + t / per;
+    }
+    return t;
+}
+
+// k_sum_valid over many problems' tiles, each tile's partial stored where a
+// launch over its problem alone stores it.
+__global__ void __launch_bounds__(kBlock) k_sum_valid_many(Grid g, const RetireBox* __restrict__ info,
+                                                          const double* __restrict__ u,
+                                                          double* __restrict__ partials) {
+    __shared__ double sh[3 * (kBlock / 64)];
+    double mx = 0.0, s = 0.0, cnt = 0.0;
+    const int tix = tile_index(g.rev);
+    const Tile tl = g.tiles[tix];
+    const RBox B = g.boxes[tl.box];
+    const RetireBox R = info[tl.box];
+    const TileThread th = tile_thread(tl);
+    const int j = B.lo[1] + th.y;
+    if (j <= B.hi[1])
+        for (int z = 0; z < (int)tl.zc; ++z) {
+            const int k = B.lo[2] + th.z0 + z * th.dz;
+            if (k > B.hi[2]) break;
+            for (int c = 0; c < 2; ++c) {
+                const int i = colour_i(B, th.x, j, k, c);
+                if (i > B.hi[0]) continue;
+                s = s + u[rb_idx(B, i, j, k)];
+                cnt += 1.0;
+            }
+        }
+    block_reduce3(mx, s, cnt, sh);
+    if (threadIdx.x == 0) {
+        const int q = R.tstart + solo_block(tix - R.tstart, R.nt);
+        partials[3 * q] = 0.0;
+        partials[3 * q + 1] = s;
+        partials[3 * q + 2] = cnt;
+    }
+}
+
+// k_norm_final per problem: block q reduces partials [seg[q], seg[q+1]).
+__global__ void __launch_bounds__(kNormThreads) k_norm_final_seg(const double* __restrict__ partials,
+                                                                const int* __restrict__ seg, double* __restrict__ out) {
+    __shared__ double sh[3 * (kNormThreads / 64)];
+    const int q = blockIdx.x;
+    double mx, s2, bad;
+    norm_reduce(partials + 3 * (long long)seg[q], seg[q + 1] - seg[q], sh, mx, s2, bad);
+    if (threadIdx.x == 0) { out[3 * q] = mx; out[3 * q + 1] = s2; out[3 * q + 2] = bad; }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sub_mean_many(Grid g, const RetireBox* __restrict__ info,
+                                                         double* __restrict__ u, const double* __restrict__ tot) {
+    BXMG_FOR_VALID_CELLS(g, const double* t3 = tot + 3 * (long long)info[tl.box].seg; const double mean = t3[1] / t3[2];
+                         const long long idx = rb_idx(B, i, j, k); u[idx] = u[idx] - mean)
+}
+
+__global__ void __launch_bounds__(kBlock) k_rb_to_fab_many(Grid g, const double* __restrict__ rb,
+                                                          const RetireBox* __restrict__ info) {
+    BXMG_FOR_VALID_CELLS(g, const RetireBox& R = info[tl.box]; R.fab[fab_idx(R.f, i, j, k)] = rb[rb_idx(B, i, j, k)])
 }
 
 // ------------------------------------------------------ coefficient setup
@@ -2553,6 +2654,22 @@ hipError_t launch_add_f32(hipStream_t s, const Grid& g, double* u, const float* 
     return hipGetLastError();
 }
 
+hipError_t launch_mean_sub_many(hipStream_t s, const Grid& g, const RetireBox* info, const int* seg_tiles, int nseg,
+                                double* u, double* scratch) {
+    if (g.ntiles <= 0 || nseg <= 0) return hipSuccess;
+    double* tot = scratch + 3 * (long long)g.ntiles;
+    hipLaunchKernelGGL(k_sum_valid_many, dim3(g.ntiles), dim3(kBlock), 0, s, g, info, u, scratch);
+    hipLaunchKernelGGL(k_norm_final_seg, dim3(nseg), dim3(kNormThreads), 0, s, scratch, seg_tiles, tot);
+    hipLaunchKernelGGL(k_sub_mean_many, dim3(g.ntiles), dim3(kBlock), 0, s, g, info, u, tot);
+    return hipGetLastError();
+}
+
+hipError_t launch_rb_to_fab_many(hipStream_t s, const Grid& g, const double* rb, const RetireBox* info) {
+    if (g.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rb_to_fab_many, dim3(g.ntiles), dim3(kBlock), 0, s, g, rb, info);
+    return hipGetLastError();
+}
+
 hipError_t launch_mean_sub(hipStream_t s, const Grid& g, double* u, double* scratch) {
     if (g.ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sum_valid, dim3(g.ntiles), dim3(kBlock), 0, s, g, u, scratch);
@@ -2648,7 +2765,7 @@ __global__ void __launch_bounds__(kBlock) k_norm_seg(const double* __restrict__ 
                                                     double* __restrict__ norms) {
     __shared__ double sh[3 * (kBlock / 64)];
     const int q = blockIdx.x, p = seg_slot[q];
-    if (!active[p]) return;
+    if (active && !active[p]) return;
     double mx = 0.0, s2 = 0.0, bad = 0.0;
     for (int t = tstart[q] + (int)threadIdx.x; t < tstart[q + 1]; t += blockDim.x) {
         mx = fmax(mx, partials[3 * t]);
@@ -2778,6 +2895,40 @@ __global__ void __launch_bounds__(kNormThreads) k_batch_admit_norms(const double
 hipError_t launch_batch_admit_norms(hipStream_t s, const double* partials, int n, const BatchSlot& S, double* fn3,
                                     BatchSlot* st, int* active, int slot) {
     hipLaunchKernelGGL(k_batch_admit_norms, dim3(1), dim3(kNormThreads), 0, s, partials, n, S, fn3, st, active, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_admit_convert(hipStream_t s, const Grid& g, const ConvSrc* src, double* u, double* f,
+                                double* partials) {
+    if (g.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_admit_convert, dim3(g.ntiles), dim3(kBlock), 0, s, g, src, u, f, partials);
+    return hipGetLastError();
+}
+
+__global__ void k_batch_admit_many(const double* __restrict__ norms, const BatchSlot* __restrict__ states,
+                                   const int* __restrict__ slots, int n, BatchSlot* __restrict__ st,
+                                   int* __restrict__ active) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int slot = slots[q];
+    const double* fn = norms + 3 * (long long)slot;
+    BatchSlot S = states[q];
+    S.fnorm = fn[0];
+    int act = 1;
+    if (fn[2] > 0.0) {
+        S.status = kStatusNonFinite;
+        act = 0;
+    } else if (!(fn[0] > 0.0)) {
+        act = 0;  // f == 0: the solution is the initial guess
+    }
+    st[slot] = S;
+    active[slot] = act;
+}
+
+hipError_t launch_batch_admit_many(hipStream_t s, const double* norms, const BatchSlot* states, const int* slots,
+                                   int n, BatchSlot* st, int* active) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_admit_many, dim3(nblk(n)), dim3(kBlock), 0, s, norms, states, slots, n, st, active);
     return hipGetLastError();
 }
 
