@@ -183,3 +183,41 @@ def test_status_codes_and_remove(bx):
     with pytest.raises(bx.BxmgError):
         b.add(q["phi"], q["rhs"], q["phi"])  # beta in a constant-coefficient batch
     b.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_grouped_admission_and_retirement(bx, precision):
+    """Problems added together are admitted by one group of launches and the
+    ones that stop together are converted back by one: periodic and Dirichlet
+    problems of several shapes in one group (the periodic means taken for a
+    subset of the group), a zero right-hand side, a problem removed before
+    the step that would admit it, and more problems joining a running batch.
+    Every result is bitwise its lone solve, history included."""
+    shapes = [(32, True, 32), (48, False, 32), (64, True, 16), (32, False, 32), (96, True, 32), (64, False, 32)]
+    probs = [problem(bx, n, per, 8100 + q, mb=mb) for q, (n, per, mb) in enumerate(shapes)]
+    zero = problem(bx, 32, True, 8199)
+    zero["rhs"].set_val(0.0)
+    gone = problem(bx, 48, True, 8198)
+    alone = [solve_alone(bx, p, precision=precision) for p in probs]
+    for p in probs + [zero, gone]:
+        p["phi"].set_val(0.0)
+    b = bx.Batch(probs[0]["phi"].ctx, 512 * MB, 64, precision=precision)
+    ids = {}
+    for q, p in enumerate(probs[:4]):
+        ids[b.add(p["phi"], p["rhs"])] = q
+    idz = b.add(zero["phi"], zero["rhs"])
+    idg = b.add(gone["phi"], gone["rhs"])
+    b.remove(idg)  # before any launch: never admitted
+    b.step(1)
+    for q, p in enumerate(probs[4:], start=4):  # join the running batch
+        ids[b.add(p["phi"], p["rhs"])] = q
+    done = dict(b.run(2))
+    b.close()
+    assert idg not in done and sorted(done) == sorted(list(ids) + [idz])
+    assert done[idz].ok and done[idz].cycles == 0
+    assert np.all(zero["phi"].to_global() == 0.0)
+    for i, q in ids.items():
+        u_alone, r_alone = alone[q]
+        assert done[i].ok and done[i].cycles == r_alone.cycles, q
+        assert done[i].hist == r_alone.hist, q
+        assert np.array_equal(probs[q]["phi"].to_global(), u_alone), q
