@@ -1343,21 +1343,33 @@ __global__ void __launch_bounds__(kBlock) k_prolong_c1s(Grid g, const RBox* __re
             }
             return v;
         };
-        for (int q = t; q < n; q += bs) {
-            if constexpr (SELF) {
-                bool neg = false;
-                const int I = mirror(Ilo + x, 0, neg), Jq = mirror(Jlo + y, 1, neg), K = mirror(Klo + z, 2, neg);
-                const T v = cb[rb_off(C, I, Jq, K)];
-                cs[q] = neg ? -v : v;
-            } else {
-                cs[q] = cb[rb_off(C, Ilo + x, Jlo + y, Klo + z)];
+        // four values per step: their loads leave together
+        for (int q0 = t; q0 < n; q0 += 4 * bs) {
+            T v[4];
+            bool ng[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int q = q0 + m * bs;
+                ng[m] = false;
+                int o = 0;
+                if constexpr (SELF) {
+                    const int I = mirror(Ilo + x, 0, ng[m]), Jq = mirror(Jlo + y, 1, ng[m]), K = mirror(Klo + z, 2, ng[m]);
+                    o = rb_off(C, I, Jq, K);
+                } else {
+                    o = rb_off(C, Ilo + x, Jlo + y, Klo + z);
+                }
+                v[m] = q < n ? cb[o] : T(0);
+                x += sx;
+                y += sy;
+                z += sz;
+                if (x >= nI) { x -= nI; ++y; }
+                if (y >= nJ) { y -= nJ; ++z; }
             }
-            // q + bs: x, y, z stay in [0,nI) x [0,nJ) x [0,..) with one carry each
-            x += sx;
-            y += sy;
-            z += sz;
-            if (x >= nI) { x -= nI; ++y; }
-            if (y >= nJ) { y -= nJ; ++z; }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int q = q0 + m * bs;
+                if (q < n) cs[q] = ng[m] ? -v[m] : v[m];
+            }
         }
     }
     __syncthreads();
@@ -2268,9 +2280,19 @@ __device__ void blk_zero(const LvMem<T, LDS>& u, long long n) {
     __syncthreads();
 }
 
+// four elements per thread and step, loaded before any is stored (a copy
+// from device memory waits for one load's latency per step, not per element)
 template <class T, bool LD, bool LS>
 __device__ void blk_copy(const LvMem<T, LD>& dst, const LvMem<T, LS>& src, long long n) {
-    for (int g = threadIdx.x; g < (int)n; g += blockDim.x) dst.st(g, src.ld(g));
+    const int bs = blockDim.x, ni = (int)n;
+    for (int g0 = threadIdx.x; g0 < ni; g0 += 4 * bs) {
+        T v[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v[m] = g0 + m * bs < ni ? src.ld(g0 + m * bs) : T(0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if (g0 + m * bs < ni) dst.st(g0 + m * bs, v[m]);
+    }
     __syncthreads();
 }
 
