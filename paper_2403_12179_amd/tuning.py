@@ -70,11 +70,16 @@ class TuneCache:
         return self._d.get(key)
 
     def put(self, key, entry):
+        """Stores the entry; returns False (the entry kept in memory only)
+        when the file cannot be written, e.g. a read-only home."""
         self._d = self._load()  # keep what other processes wrote meanwhile
         self._d[key] = dict(entry, format=FORMAT)
         folder = os.path.dirname(os.path.abspath(self.path))
-        os.makedirs(folder, exist_ok=True)
-        fd, tmp = tempfile.mkstemp(prefix=".tune.", dir=folder)
+        try:
+            os.makedirs(folder, exist_ok=True)
+            fd, tmp = tempfile.mkstemp(prefix=".tune.", dir=folder)
+        except OSError:
+            return False
         try:
             with os.fdopen(fd, "w") as fh:
                 json.dump(self._d, fh, indent=1, sort_keys=True)
@@ -83,6 +88,7 @@ class TuneCache:
             if os.path.exists(tmp):
                 os.unlink(tmp)
             raise
+        return True
 
     def __len__(self):
         return len(self._d)

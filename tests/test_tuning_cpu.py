@@ -85,3 +85,11 @@ def test_fingerprint_follows_the_library():
         pytest.skip("library not built")
     fp = tuning.lib_fingerprint()
     assert len(fp) == 12 and int(fp, 16) >= 0
+
+
+def test_unwritable_cache_keeps_entry_in_memory(tmp_path):
+    blocker = tmp_path / "file"
+    blocker.write_text("not a folder")
+    tc = tuning.TuneCache(str(blocker / "sub" / "tune.json"))  # parent is a file: cannot be created
+    assert tc.put("k", dict(tuning.DEFAULT_SHAPE)) is False
+    assert tc.get("k")["planes_per_thread"] == 4
