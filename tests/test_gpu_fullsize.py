@@ -7,7 +7,10 @@ with the benchmark's recipes and seeds):
   oracle's FP64 operator, and agree with each other within the error bound
   of that residual;
 * the batch of 256 periodic problems: every problem reaches 1e-10, a sample
-  is checked with the oracle's operator and is bitwise its lone solve.
+  is checked with the oracle's operator and is bitwise its lone solve;
+* the nodal solve on 257^3 nodes and three heat steps on 256^3 in 512
+  boxes: the oracle's operators recompute the residual of the GPU's
+  solutions (the oracle's own solves at these sizes take minutes).
 """
 import numpy as np
 import pytest
@@ -79,3 +82,55 @@ def test_batch_256_periodic(bx, orc):
         p["phi"].set_val(0.0)
         alone = bx.mlmg_solve(p["phi"], p["rhs"], precision=1)
         assert alone.cycles == done[q].cycles and np.array_equal(p["phi"].to_global(), u), q
+
+
+def test_nodal_257_nodes(bx, orc):
+    """The nodal row at its full size (256^3 cells, 257^3 nodes, Dirichlet,
+    f ~ U[-1,1] drawn on the device with the benchmark's seed 7): the
+    oracle's operator applied to the GPU's solution leaves |f - L u| <=
+    1e-10 |f| at the unknown nodes (up to rounding), as the solve reports."""
+    import torch
+    n = 256
+    ba = bx.BoxArray.chop((0, 0, 0), (n - 1,) * 3, 32, bc=(bx.DIRICHLET0,) * 3)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    rhs = torch.rand((n + 1,) * 3, generator=g, device="cuda", dtype=torch.float64) * 2.0 - 1.0
+    phi = torch.zeros_like(rhs)
+    print("nodal full size: GPU solve", flush=True)
+    res = bx.nodal_solve(ba, phi, rhs, rel_tol=1e-10)
+    assert res.ok and res.rel_resid_inf <= 1e-10 and res.cycles <= 14
+    f = np.asfortranarray(rhs.cpu().numpy().transpose(2, 1, 0))
+    u = np.asfortranarray(phi.cpu().numpy().transpose(2, 1, 0))
+    del rhs, phi
+    print("nodal full size: oracle residual", flush=True)
+    m = np.zeros(f.shape, bool)
+    m[1:-1, 1:-1, 1:-1] = True  # the unknowns: every node off the Dirichlet boundary
+    r = np.where(m, f - orc.nodal_apply((n,) * 3, (0, 0, 0), 1.0 / n, u), 0.0)
+    fnorm = np.max(np.abs(f[m]))
+    assert np.max(np.abs(r)) <= 1.5e-10 * fnorm
+    assert res.rel_resid_inf == pytest.approx(np.max(np.abs(r)) / fnorm, rel=0.2, abs=1e-13)
+
+
+def test_heat_steps_256_in_512_boxes(bx, orc):
+    """The heat row at its full size (256^3 in 512 boxes of 32^3, Dirichlet,
+    dt = 1e-4): after 3 backward-Euler steps from a seeded field, the last
+    step's solution meets 1e-10 by the oracle's Helmholtz operator
+    (alpha = 1/dt) against that step's right-hand side u_prev / dt."""
+    n = 256
+    dt = 1e-4
+    ba = bx.BoxArray.chop((0, 0, 0), (n - 1,) * 3, 32, bc=(bx.DIRICHLET0,) * 3)
+    u0 = W.uniform_rhs((n, n, n), seed=8)
+    u = bx.MultiFab(ba).set_val(0.0).from_global(u0)
+    prev = None
+    res = None
+    print("heat full size: GPU steps", flush=True)
+    for step in range(3):
+        prev = u.to_global()
+        res = bx.heat_step(u, dt, rel_tol=1e-10)
+        assert res.ok, res
+    un = u.to_global()
+    print("heat full size: oracle residual", flush=True)
+    # the step solves (1/dt) u - lap u = u_prev / dt, i.e. lap u - (1/dt) u = -u_prev / dt
+    f = -prev / dt
+    r = f - orc.apply_op((0, 0, 0), (n - 1,) * 3, (0, 0, 0), 1.0 / n, un, alpha=1.0 / dt)
+    assert np.max(np.abs(r)) <= 1.5e-10 * np.max(np.abs(f))
