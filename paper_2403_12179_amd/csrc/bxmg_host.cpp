@@ -130,7 +130,7 @@ struct Hier {
     DevBuf<double> partials;  // 3 per tile of the largest tiled launch, + 3
     DevBuf<double> fnorm;     // 3
     // the solve's stop test on the device (the batch engine's, one slot):
-    // slot state, flags {active, slot index 0, active count}, the history
+    // slot state, flags {active, slot index 0, active count, guess not +0}, the history
     // (kHist of |r|/|f|, then kHist of |r|_2) and the norms of f
     DevBuf<BatchSlot> st;
     DevBuf<int> flags;
@@ -1248,8 +1248,12 @@ static bxmg_status solve_impl(bxmg_ctx ctx, const bxmg_solve_params* params, bxm
         const Level& L0 = *H->L[0];
         double* u = H->u64[0]->p;
         double* f = H->f64[0]->p;
-        // caller layout -> colour-split level 0
-        HIPCHK(launch_fab_to_rb(R.s, L0.view_grid(), (const double*)phi->data, phi->d_fboxes.p, u, false));
+        // caller layout -> colour-split level 0; flags[3] = whether the guess
+        // has a value other than +0.0 (the first residual skips the reads of
+        // an all-zero guess)
+        int* const guess_nz = H->flags.p + 3;
+        HIPCHK(hipMemsetAsync(guess_nz, 0, sizeof(int), R.s));
+        HIPCHK(launch_fab_to_rb_nz(R.s, L0.view_grid(), (const double*)phi->data, phi->d_fboxes.p, u, guess_nz));
         // f, with the norms of f per tile on the way (reduced below)
         if (heat)
             HIPCHK(launch_heat_rhs(R.s, L0.view_grid(), (const double*)phi->data, phi->d_fboxes.p,
@@ -1294,6 +1298,7 @@ static bxmg_status solve_impl(bxmg_ctx ctx, const bxmg_solve_params* params, bxm
         // take the colour-1 residual norms in the V-cycle's last level-0 sweep
         const bool fusable = P.precision == 0 && L0.push && L0.res && P.nu2 > 0;
         double* const norms1 = H->partials.p + 3 * (size_t)L0.ntcol;
+        const int* first_nz = guess_nz;  // for the first residual only
         auto check = [&](bool fused) {  // residual of the current iterate, then the stop test
             if (!L0.push) fill_faces<double>(R, 0, u);
             R.pre(0, kStageResid);
@@ -1303,11 +1308,12 @@ static bxmg_status solve_impl(bxmg_ctx ctx, const bxmg_solve_params* params, bxm
                                                     (double*)nullptr, H->partials.p, true));
             } else if (P.precision == 0) {
                 HIPCHK(launch_resid<double, double>(R.s, R.grid(L0.walk()), u, f, beta ? H->beta64.p : nullptr, nf,
-                                                    (double*)nullptr, H->partials.p));
+                                                    (double*)nullptr, H->partials.p, false, first_nz));
             } else {
                 HIPCHK(launch_resid<double, float>(R.s, R.grid(L0.walk()), u, f, beta ? H->beta64.p : nullptr, nf,
-                                                   H->f32[0]->p, H->partials.p));
+                                                   H->f32[0]->p, H->partials.p, false, first_nz));
             }
+            first_nz = nullptr;
             R.post(0, kStageResid);
             HIPCHK(launch_norm_final(R.s, H->partials.p, (fused ? 2 : 1) * L0.ntcol, H->fnorm.p));
             HIPCHK(launch_batch_check(R.s, H->flags.p + 1, 1, H->fnorm.p, H->st.p, H->flags.p, H->hist.p,

@@ -219,9 +219,13 @@ hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* be
 // mixed-precision cast), partial norms (max|r|, sum r^2, bad count) at
 // 3 * (tile index).  colour0_only (FP64, buffer-addressed, no store): the
 // colour-0 cells only, after a colour-1 sweep that took the others' norms.
+// nonzero (constant coefficient, buffer-addressed): the flag
+// launch_fab_to_rb_nz set; while it is 0 the guess is +0.0 everywhere and
+// the residual is f, taken without reading u (bitwise the same results).
 template <class T, class R>
 hipError_t launch_resid(hipStream_t s, const Grid& g, const T* u, const T* f, const T* beta,
-                        const FaceArrays<T>* fat, R* r, double* partials, bool colour0_only = false);
+                        const FaceArrays<T>* fat, R* r, double* partials, bool colour0_only = false,
+                        const int* nonzero = nullptr);
 hipError_t launch_norm_final(hipStream_t s, const double* partials, int n, double* out3);
 hipError_t launch_field_norm(hipStream_t s, const Grid& g, const double* x, double* partials);
 
@@ -264,6 +268,10 @@ hipError_t launch_cast_f32(hipStream_t s, const double* src, float* dst, long lo
 
 // layout conversions: F-order caller MultiFab (FP64, comp 0) <-> RB level
 hipError_t launch_fab_to_rb(hipStream_t s, const Grid& g, const double* fab, const FBox* fb, void* rb, bool f32);
+// FP64 launch_fab_to_rb that also sets *nonzero to 1 when any converted value
+// is not +0.0 (the caller zeroes it first).
+hipError_t launch_fab_to_rb_nz(hipStream_t s, const Grid& g, const double* fab, const FBox* fb, double* rb,
+                               int* nonzero);
 // launch_fab_to_rb (FP64) and launch_field_norm of the result in one pass
 hipError_t launch_fab_to_rb_norm(hipStream_t s, const Grid& g, const double* fab, const FBox* fb, double* rb,
                                 double* partials);

@@ -363,3 +363,30 @@ def test_history_is_the_residual_of_the_iterate(bx, orc, merge, var, spike):
                 assert (i + j + k) % 2 == 1 and (i in (0, n - 1) or j in (0, n - 1) or k in (0, n - 1))
     finally:
         _tune(bx, phi.ctx, merge=1)
+
+
+@pytest.mark.parametrize("per,precision", [(0, 0), (1, 0), (0, 1)])
+def test_zero_guess_shortcut(bx, orc, per, precision):
+    """A guess that is +0.0 in every cell has residual f, which the first
+    residual takes without reading the guess.  A guess of -0.0 (the same
+    values, other bits) takes the full path: the histories and solutions of
+    the two agree exactly.  A guess that is zero but for one cell also takes
+    the full path: its hist[0] is the oracle operator's residual of it."""
+    n = 64
+    f = W.uniform_rhs((n, n, n), 81, mean_zero=bool(per))
+    ba, phi, rhs, _ = setup(bx, (0, 0, 0), (n - 1,) * 3, 32, (per,) * 3, f)
+    out = []
+    for v in (0.0, -0.0):
+        phi.set_val(v)
+        assert np.all(np.signbit(phi.to_global()) == np.signbit(v))
+        res = bx.mlmg_solve(phi, rhs, fixed_cycles=3, precision=precision)
+        out.append((res.hist, res.hist_l2, phi.to_global()))
+    assert out[0][0] == out[1][0] and out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2])
+    g = np.zeros((n, n, n), order="F")
+    g[n // 2, 5, n - 1] = 0.5
+    phi.set_val(0.0).from_global(g)
+    res = bx.mlmg_solve(phi, rhs, fixed_cycles=1, precision=precision)
+    r = f - orc.apply_op((0, 0, 0), (n - 1,) * 3, (per,) * 3, 1.0 / n, g, None)
+    assert res.hist[0] == pytest.approx(np.abs(r).max() / np.abs(f).max(), rel=1e-14)
+    assert res.hist[0] != pytest.approx(1.0, rel=1e-3)  # the guess moved the residual
