@@ -322,6 +322,9 @@ struct bxmg_batch_s {
     DevBuf<float> u32, f32, b32, fa32;
     // per slot
     DevBuf<int> active, nactive;
+    // per slot: 0 while the problem's iterate is its all-+0.0 guess (the
+    // first residual then skips the reads of u)
+    DevBuf<int> guess_nz;
     DevBuf<BatchSlot> st;
     DevBuf<double> norms, hist, hist_l2, fn3;
     int* h_active = nullptr;
@@ -710,13 +713,13 @@ void enqueue_cycle(bxmg_batch_s* b, hipStream_t s) {
     const double* beta0 = b->var ? b->b64.p : nullptr;
     if (b->prec == 0)
         HIPCHK(launch_resid<double, double>(s, level_grid(b, 0), b->u64.p, b->f64.p, beta0, nullptr, (double*)nullptr,
-                                            b->partials.p()));
+                                            b->partials.p(), false, b->guess_nz.p));
     else
         HIPCHK(launch_resid<double, float>(s, level_grid(b, 0), b->u64.p, b->f64.p, beta0, nullptr, b->f32.p,
-                                           b->partials.p()));
+                                           b->partials.p(), false, b->guess_nz.p));
     HIPCHK(launch_norm_seg(s, b->partials.p(), b->tstart.p(), b->segslot.p(), b->nseg, b->active.p, b->norms.p));
     HIPCHK(launch_batch_check(s, b->d_members.p(), (int)b->members.size(), b->norms.p, b->st.p, b->active.p,
-                              b->hist.p, b->hist_l2.p, b->nactive.p));
+                              b->hist.p, b->hist_l2.p, b->nactive.p, b->guess_nz.p));
     if (b->prec == 0) {
         b_vcycle<double>(b, s);
     } else {
@@ -890,6 +893,7 @@ bxmg_status bxmg_batch_create(bxmg_ctx ctx, size_t hbm_budget_bytes, int32_t max
             else b->fa64.alloc(std::max<long long>(b->fcap, 64));
         }
         b->active.alloc(max_problems);
+        b->guess_nz.alloc(max_problems);
         HIPCHK(hipMemset(b->active.p, 0, max_problems * sizeof(int)));
         b->nactive.alloc(1);
         b->st.alloc(max_problems);
@@ -1036,6 +1040,7 @@ void admit_pending(bxmg_batch_s* b, hipStream_t s) {
             c.rhs = (const double*)q.rhs->data;
             c.fphi = q.phi->fboxes[k];
             c.frhs = q.rhs->fboxes[k];
+            c.slot = slot;
             srcs.push_back(c);
         }
         for (Tile t : P.t0_h) {
@@ -1059,7 +1064,8 @@ void admit_pending(bxmg_batch_s* b, hipStream_t s) {
     b->a_states.assign(states);
     b->a_part.reserve(3 * tiles.size() + 8);
     const Grid g{b->a_rb.p(), b->a_tiles.p(), (int)tiles.size(), 0, nullptr, 0, 0};
-    HIPCHK(launch_admit_convert(s, g, b->a_src.p(), b->u64.p, b->f64.p, b->a_part.p()));
+    HIPCHK(launch_set_slots(s, b->a_slots.p(), (int)b->pending.size(), b->guess_nz.p, 0));
+    HIPCHK(launch_admit_convert(s, g, b->a_src.p(), b->u64.p, b->f64.p, b->a_part.p(), b->guess_nz.p));
     // ghosts of the converted guesses (later producers keep them current)
     HIPCHK(launch_fill_sets(s, b->u64.p, false, b->a_sets.p(), (int)sets.size(), max_ghosts, nullptr));
     HIPCHK(launch_norm_seg(s, b->a_part.p(), b->a_tstart.p(), b->a_seg.p(), (int)seg.size(), nullptr, b->fn3.p));

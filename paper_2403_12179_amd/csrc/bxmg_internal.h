@@ -219,9 +219,10 @@ hipError_t launch_gs(hipStream_t s, const Grid& g, T* u, const T* f, const T* be
 // mixed-precision cast), partial norms (max|r|, sum r^2, bad count) at
 // 3 * (tile index).  colour0_only (FP64, buffer-addressed, no store): the
 // colour-0 cells only, after a colour-1 sweep that took the others' norms.
-// nonzero (constant coefficient, buffer-addressed): the flag
-// launch_fab_to_rb_nz set; while it is 0 the guess is +0.0 everywhere and
-// the residual is f, taken without reading u (bitwise the same results).
+// nonzero (constant coefficient, buffer-addressed): one flag per problem
+// (box pid), set when its guess has a value other than +0.0 or after its
+// first check; while it is 0 the residual is f, taken without reading u
+// (bitwise the same results as the full path).
 template <class T, class R>
 hipError_t launch_resid(hipStream_t s, const Grid& g, const T* u, const T* f, const T* beta,
                         const FaceArrays<T>* fat, R* r, double* partials, bool colour0_only = false,
@@ -337,9 +338,11 @@ constexpr int kStatusNonFinite = -5;  // = BXMG_ENONFINITE
 hipError_t launch_norm_seg(hipStream_t s, const double* partials, const int* tstart, const int* seg_slot, int nseg,
                            const int* active, double* norms);
 // Stop test of every active member slot (see BatchSlot): records the
-// history, retires finished problems, counts the rest into *nactive.
+// history, retires finished problems, counts the rest into *nactive; seen
+// (optional): seen[slot] = 1 for every active slot checked.
 hipError_t launch_batch_check(hipStream_t s, const int* slots, int n, const double* norms, BatchSlot* st,
-                              int* active, double* hist, double* hist_l2, int* nactive);
+                              int* active, double* hist, double* hist_l2, int* nactive,
+                              int* seen = nullptr);
 // Ghost lists of many problems in one launch: set q copies list[0..n) with
 // indices relative to data + off (active slots only).
 struct GhostSet {
@@ -362,9 +365,12 @@ struct ConvSrc {
     const double* phi;
     const double* rhs;
     FBox fphi, frhs;
+    int slot;  // the problem's slot: nonzero[slot] |= (its guess has a value other than +0.0)
 };
 hipError_t launch_admit_convert(hipStream_t s, const Grid& g, const ConvSrc* src, double* u, double* f,
-                                double* partials);
+                                double* partials, int* nonzero);
+// a[slots[q]] = v for q < n
+hipError_t launch_set_slots(hipStream_t s, const int* slots, int n, int* a, int v);
 // For q < n: slot = slots[q] takes state states[q] with ||f|| from norms[3 slot]
 // and the decision of launch_batch_admit.
 hipError_t launch_batch_admit_many(hipStream_t s, const double* norms, const BatchSlot* states, const int* slots,

@@ -638,10 +638,11 @@ __global__ void __launch_bounds__(kBlock) k_resid(Grid g, const T* __restrict__ 
     const long long ne = 2 * B.cstride;
     const BoxRes<T> U(u + B.base, ne), F(f + B.base, ne), Bt((MODE == 1 ? beta : f) + B.base, ne);
     const BoxRes<R> Rr(r ? r + B.base : (R*)nullptr, r ? ne : 0);
-    // a guess that is +0.0 everywhere (constant coefficient): the stencil
-    // sums are exactly +0.0, so the residual is f itself and u need not be
-    // read -- the same values, norms and stores as the full path
-    const bool zero_guess = MODE == 0 && RES && nonzero && nonzero[0] == 0;
+    // a guess that is +0.0 everywhere (constant coefficient; one flag per
+    // problem): the stencil sums are exactly +0.0, so the residual is f
+    // itself and u need not be read -- the same values, norms and stores as
+    // the full path
+    const bool zero_guess = MODE == 0 && RES && nonzero && nonzero[B.pid] == 0;
     if (j <= B.hi[1]) {
         // z+ of one plane is z- of the next when walking planes 2 apart (see k_gs)
         const bool walk2 = th.dz == 2;
@@ -806,9 +807,10 @@ __global__ void __launch_bounds__(kBlock) k_fab_to_rb_norm(Grid g, const double*
 // their own source arrays).
 __global__ void __launch_bounds__(kBlock) k_admit_convert(Grid g, const ConvSrc* __restrict__ src,
                                                          double* __restrict__ u, double* __restrict__ f,
-                                                         double* __restrict__ partials) {
+                                                         double* __restrict__ partials, int* __restrict__ nonzero) {
     __shared__ double sh[3 * (kBlock / 64)];
     double mx = 0.0, s2 = 0.0, bad = 0.0;
+    bool nz = false;
     const int tix = tile_index(g.rev);
     const Tile tl = g.tiles[tix];
     const RBox B = g.boxes[tl.box];
@@ -823,12 +825,15 @@ __global__ void __launch_bounds__(kBlock) k_admit_convert(Grid g, const ConvSrc*
                 const int i = colour_i(B, th.x, j, k, c);
                 if (i > B.hi[0]) continue;
                 const long long o = rb_idx(B, i, j, k);
-                u[o] = S.phi[fab_idx(S.fphi, i, j, k)];
+                const double w = S.phi[fab_idx(S.fphi, i, j, k)];
+                u[o] = w;
+                nz = nz || __double_as_longlong(w) != 0;
                 const double v = S.rhs[fab_idx(S.frhs, i, j, k)];
                 f[o] = v;
                 acc_norm(v, mx, s2, bad);
             }
         }
+    if (__any(nz) && (threadIdx.x & 63) == 0) atomicOr(&nonzero[S.slot], 1);
     block_reduce3(mx, s2, bad, sh);
     if (threadIdx.x == 0) {
         partials[3 * tix] = mx;
@@ -2847,7 +2852,8 @@ __global__ void __launch_bounds__(kBlock) k_norm_seg(const double* __restrict__ 
 __global__ void __launch_bounds__(1024) k_batch_check(const int* __restrict__ slots, int n,
                                                      const double* __restrict__ norms, BatchSlot* __restrict__ st,
                                                      int* __restrict__ active, double* __restrict__ hist,
-                                                     double* __restrict__ hist_l2, int* __restrict__ nactive) {
+                                                     double* __restrict__ hist_l2, int* __restrict__ nactive,
+                                                     int* __restrict__ seen) {
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
@@ -2855,6 +2861,7 @@ __global__ void __launch_bounds__(1024) k_batch_check(const int* __restrict__ sl
     for (int q = threadIdx.x; q < n; q += blockDim.x) {
         const int p = slots[q];
         if (!active[p]) continue;
+        if (seen) seen[p] = 1;  // the iterate after this check is no zero guess
         BatchSlot S = st[p];
         const double rinf = norms[3 * p + 2] > 0.0 ? (double)NAN : norms[3 * p];
         const int c = S.cycles;
@@ -2965,9 +2972,9 @@ hipError_t launch_batch_admit_norms(hipStream_t s, const double* partials, int n
 }
 
 hipError_t launch_admit_convert(hipStream_t s, const Grid& g, const ConvSrc* src, double* u, double* f,
-                                double* partials) {
+                                double* partials, int* nonzero) {
     if (g.ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_admit_convert, dim3(g.ntiles), dim3(kBlock), 0, s, g, src, u, f, partials);
+    hipLaunchKernelGGL(k_admit_convert, dim3(g.ntiles), dim3(kBlock), 0, s, g, src, u, f, partials, nonzero);
     return hipGetLastError();
 }
 
@@ -3011,8 +3018,20 @@ hipError_t launch_norm_seg(hipStream_t s, const double* partials, const int* tst
 }
 
 hipError_t launch_batch_check(hipStream_t s, const int* slots, int n, const double* norms, BatchSlot* st,
-                              int* active, double* hist, double* hist_l2, int* nactive) {
-    hipLaunchKernelGGL(k_batch_check, dim3(1), dim3(1024), 0, s, slots, n, norms, st, active, hist, hist_l2, nactive);
+                              int* active, double* hist, double* hist_l2, int* nactive, int* seen) {
+    hipLaunchKernelGGL(k_batch_check, dim3(1), dim3(1024), 0, s, slots, n, norms, st, active, hist, hist_l2, nactive,
+                       seen);
+    return hipGetLastError();
+}
+
+__global__ void k_set_slots(const int* __restrict__ slots, int n, int* __restrict__ a, int v) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) a[slots[q]] = v;
+}
+
+hipError_t launch_set_slots(hipStream_t s, const int* slots, int n, int* a, int v) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_slots, dim3((n + 255) / 256), dim3(256), 0, s, slots, n, a, v);
     return hipGetLastError();
 }
 

@@ -221,3 +221,39 @@ def test_grouped_admission_and_retirement(bx, precision):
         assert done[i].ok and done[i].cycles == r_alone.cycles, q
         assert done[i].hist == r_alone.hist, q
         assert np.array_equal(probs[q]["phi"].to_global(), u_alone), q
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_zero_guess_flag_per_problem(bx, orc, precision):
+    """A problem's first residual skips the reads of its guess only when that
+    guess is +0.0 in every cell (one flag per slot, cleared at admission).
+    In one batch: a +0.0 guess and a -0.0 guess of the same problem (the
+    second takes the full path) end with the same history and solution, and
+    a guess that is zero but for one cell has the oracle operator's residual
+    of it as hist[0].  A second pass in the reverse order puts each guess in
+    another problem's former slot."""
+    n = 32
+    probs = [problem(bx, n, False, 4100) for _ in range(3)]
+    g = np.zeros((n, n, n), order="F")
+    g[3, n // 2, 7] = 0.25
+    f = probs[0]["f"]
+    r = f - orc.apply_op((0, 0, 0), (n - 1,) * 3, (0, 0, 0), 1.0 / n, g, None)
+    want0 = np.abs(r).max() / np.abs(f).max()
+    b = bx.Batch(probs[0]["phi"].ctx, 512 * MB, 64, precision=precision)
+    try:
+        for order in ([0, 1, 2], [2, 1, 0]):
+            probs[0]["phi"].set_val(0.0)
+            probs[1]["phi"].set_val(-0.0)
+            probs[2]["phi"].set_val(0.0).from_global(g)
+            ids = {}
+            for q in order:
+                pid = b.add(probs[q]["phi"], probs[q]["rhs"], None)
+                assert pid is not None
+                ids[pid] = q
+            out = {ids[i]: res for i, res in b.run(2)}
+            assert sorted(out) == [0, 1, 2] and all(out[q].ok for q in out)
+            assert out[0].hist == out[1].hist
+            assert np.array_equal(probs[0]["phi"].to_global(), probs[1]["phi"].to_global())
+            assert out[2].hist[0] == pytest.approx(want0, rel=1e-14)
+    finally:
+        b.close()
